@@ -1,0 +1,110 @@
+"""Monolithic geometric multigrid V-cycle for the stage system (Sec. 4.1-4.2, 5.1).
+
+TEST INFRASTRUCTURE ONLY (oracle).
+
+Hierarchy from uniform refinement; coarse operators by rediscretisation (assembly of
+the stage system on every level, Sec. 4.1); interpolation I_r (x) P, restriction its
+transpose; additive Vanka relaxation with `pre` and `post` sweeps (Sec. 5.1 uses 2 and
+2); direct solve on the coarsest level (Sec. 4.1 uses a sparse direct solver; here a
+dense LU with partial pivoting).
+
+Readings where the paper is silent:
+  * cycle shape: on each level, pre-sweeps from a zero guess, residual, restrict,
+    recurse, prolongate-and-add without damping, post-sweeps;
+  * pressure nullspace: the coarse LU pins the pressure at vertex 0 of every stage
+    (its row and column replaced by the identity, right-hand side entry 0), and the
+    V-cycle output has each stage's pressure mean removed;
+  * the wind of the Oseen operator is interpolated on each level (evaluated at that
+    level's P2 nodes).
+
+Mixed precision: with dtype=float32 the level operators, patch inverses and
+vectors of the V-cycle are float32 and the coarse solve stays float64, as in the
+FP32-patch variant of the HIP library.
+
+Pinned by tests/test_oracle_multigrid.py: coarse solve residual; two-grid and V-cycle
+contraction; FGMRES-MG solution equal to the dense direct solve; mesh-independent
+iteration counts.
+"""
+from __future__ import annotations
+
+import numpy as np
+import scipy.linalg as sla
+import scipy.sparse as sp
+
+from .fem import TaylorHood
+from .stage import StageSystem
+from .transfer import interpolation_matrices, stage_prolongation
+from .vanka import VankaSmoother, patch_dofs
+
+
+class Hierarchy:
+    def __init__(self, mesh_levels, A, dt, nu, wind=None, omega=0.5, weighted=True, pre=2, post=2,
+                 dtype=np.float64):
+        """mesh_levels: coarse-to-fine sequence of objects with .xyz and .cells.
+        wind: callable (points, t) -> (npts, dim) or None (Stokes)."""
+        self.A = np.asarray(A, dtype=np.float64)
+        self.r = self.A.shape[0]
+        self.pre, self.post = pre, post
+        self.dtype = dtype
+        self.spaces = [TaylorHood(m.xyz, m.cells) for m in mesh_levels]
+        self.systems = []
+        for th in self.spaces:
+            wn = th.interpolate(wind) if wind is not None else None
+            self.systems.append(StageSystem(th, self.A, dt, nu, wn))
+        self.dim = self.spaces[0].dim
+        self.P = [None]
+        for lc in range(len(self.spaces) - 1):
+            Pu, Pp = interpolation_matrices(self.spaces[lc], self.spaces[lc + 1])
+            self.P.append(stage_prolongation(Pu, Pp, self.dim, self.r))
+        self.smoothers = [None]
+        self.Jw = [s.J.astype(dtype) for s in self.systems]
+        self.Pw = [None] + [P.astype(dtype) for P in self.P[1:]]
+        for lev in range(1, len(self.spaces)):
+            pat = patch_dofs(self.spaces[lev], self.r)
+            self.smoothers.append(VankaSmoother(self.systems[lev].J, pat, omega, weighted, dtype))
+        # coarse LU with one pinned pressure per stage
+        s0 = self.systems[0]
+        Jc = s0.J.toarray()
+        self.pinned = [i * s0.ns + s0.th.nvel for i in range(self.r)]
+        for q in self.pinned:
+            Jc[q, :] = 0.0
+            Jc[:, q] = 0.0
+            Jc[q, q] = 1.0
+        self.coarse_lu = sla.lu_factor(Jc)
+        self.coarse_luT = sla.lu_factor(Jc.T.copy())
+
+    @property
+    def finest(self) -> StageSystem:
+        return self.systems[-1]
+
+    def coarse_solve(self, b: np.ndarray, transpose: bool = False) -> np.ndarray:
+        b = np.array(b, dtype=np.float64)
+        b[self.pinned] = 0.0
+        return sla.lu_solve(self.coarse_luT if transpose else self.coarse_lu, b)
+
+    def _cycle(self, lev: int, b: np.ndarray, transpose: bool) -> np.ndarray:
+        if lev == 0:
+            return self.coarse_solve(b, transpose).astype(self.dtype)
+        Jop = self.Jw[lev].T if transpose else self.Jw[lev]
+        sm = self.smoothers[lev]
+        npre, npost = (self.post, self.pre) if transpose else (self.pre, self.post)
+        x = np.zeros_like(b)
+        for _ in range(npre):
+            x = sm.sweep(b, x, Jop, transpose)
+        res = b - Jop @ x
+        bc = self.Pw[lev].T @ res
+        x = x + self.Pw[lev] @ self._cycle(lev - 1, bc, transpose)
+        for _ in range(npost):
+            x = sm.sweep(b, x, Jop, transpose)
+        return x
+
+    def vcycle(self, b: np.ndarray) -> np.ndarray:
+        """z = V b from a zero initial guess, pressure means removed."""
+        z = self._cycle(len(self.spaces) - 1, np.asarray(b).astype(self.dtype), False).astype(np.float64)
+        return self.finest.project_pressure_mean(z)
+
+    def vcycle_transpose(self, b: np.ndarray) -> np.ndarray:
+        """V^T b: the transpose of vcycle as a linear map (projection first, then the
+        V-cycle of J^T with transposed patch solves and swapped sweep counts)."""
+        b = self.finest.project_pressure_mean(np.asarray(b, dtype=np.float64))
+        return self._cycle(len(self.spaces) - 1, b.astype(self.dtype), True).astype(np.float64)

@@ -1,0 +1,87 @@
+"""Pins for oracle/multigrid.py and oracle/fgmres.py."""
+import numpy as np
+import pytest
+
+from oracle.fgmres import fgmres
+from oracle.multigrid import Hierarchy
+from oracle.tableau import tableau
+from oracle.timestep import dense_solver
+from paper_2202_07381_amd import workloads as wl
+
+
+def _setup(n_coarse=4, nlev=3, fam="radauIIA", r=2, dt=1 / 16, nu=1.0, wind=None, dtype=np.float64, weighted=True):
+    A, b, c = tableau(fam, r)
+    H = Hierarchy(wl.square_hierarchy(n_coarse, nlev), A, dt, nu, wind=wind, dtype=dtype, weighted=weighted)
+    S = H.finest
+    f = wl.forcing_2d(1)
+    F = S.rhs([S.th.interpolate(f)] * r, np.zeros(S.th.nvel), np.zeros(S.th.nverts))
+    return H, S, F
+
+
+def test_coarse_solve_exact():
+    H, S, F = _setup(nlev=1)
+    x = H.coarse_solve(F)
+    assert np.linalg.norm(F - S.J @ x) < 1e-13 * np.linalg.norm(F)
+
+
+def test_fgmres_mg_matches_direct_solve():
+    H, S, F = _setup(n_coarse=4, nlev=2)
+    x, info = fgmres(S.apply, H.vcycle, F, np.zeros_like(F), 1e-13, 200, 30, project=S.project_pressure_mean)
+    xd = dense_solver(S)(F)
+    assert info.converged
+    assert np.linalg.norm(x - xd) < 1e-10 * np.linalg.norm(xd)
+
+
+def test_arnoldi_estimate_equals_true_residual():
+    H, S, F = _setup()
+    for maxit in (3, 7):
+        x, info = fgmres(S.apply, H.vcycle, F, np.zeros_like(F), 1e-14, maxit, 30)
+        true = np.linalg.norm(F - S.J @ x)
+        assert abs(true - info.history[-1]) < 1e-12 * info.history[0]
+
+
+def test_weighting_reading():
+    # the literal (unweighted) omega=0.5 sweep is not a useful preconditioner here;
+    # the partition-of-unity weighted one converges fast (reading of the damping).
+    Hw, S, F = _setup()
+    _, iw = fgmres(S.apply, Hw.vcycle, F, np.zeros_like(F), 1e-8, 60, 30)
+    Hu, S2, F2 = _setup(weighted=False)
+    _, iu = fgmres(S2.apply, Hu.vcycle, F2, np.zeros_like(F2), 1e-8, 60, 30)
+    assert iw.converged and iw.iterations <= 15
+    assert not iu.converged
+
+
+@pytest.mark.slow
+def test_mesh_independent_iterations():
+    its = []
+    for nlev in (3, 4, 5):  # 16^2, 32^2, 64^2 with a 4x4 coarsest mesh
+        H, S, F = _setup(nlev=nlev)
+        _, info = fgmres(S.apply, H.vcycle, F, np.zeros_like(F), 1e-8, 100, 30)
+        assert info.converged
+        its.append(info.iterations)
+    assert max(its) / min(its) <= 1.5, its
+
+
+def test_vcycle_transpose_dot_product():
+    H, S, F = _setup(fam="gauss", r=2, wind=wl.wind_2d(3, 16), nu=0.05)
+    rng = np.random.default_rng(5)
+    x, y = rng.standard_normal(S.n), rng.standard_normal(S.n)
+    lhs = H.vcycle(x) @ y
+    rhs = x @ H.vcycle_transpose(y)
+    assert abs(lhs - rhs) < 1e-12 * abs(lhs)
+
+
+def test_oseen_converges():
+    H, S, F = _setup(fam="gauss", r=2, nu=0.01, dt=5e-3, wind=wl.wind_2d(3, 16))
+    assert S.Cs is not None
+    _, info = fgmres(S.apply, H.vcycle, F, np.zeros_like(F), 1e-8, 100, 30)
+    assert info.converged
+
+
+def test_mixed_precision_reaches_fp64_tolerance():
+    H, S, F = _setup(dtype=np.float32)
+    x, info = fgmres(S.apply, H.vcycle, F, np.zeros_like(F), 1e-8, 100, 30, project=S.project_pressure_mean)
+    assert info.converged and info.rel_residual <= 1e-8
+    H64, _, _ = _setup()
+    x64, _ = fgmres(S.apply, H64.vcycle, F, np.zeros_like(F), 1e-8, 100, 30, project=S.project_pressure_mean)
+    assert np.linalg.norm(x - x64) / np.linalg.norm(x64) < 1e-6

@@ -1,0 +1,74 @@
+"""Pins for oracle/vanka.py: Fig. 1 patch shape, patch-size statistics, exactness."""
+import numpy as np
+import pytest
+
+from oracle.fem import TaylorHood
+from oracle.stage import StageSystem
+from oracle.tableau import tableau
+from oracle.vanka import VankaSmoother, multiplicity, patch_dofs
+from paper_2202_07381_amd import workloads as wl
+
+
+def test_interior_patch_is_fig1():
+    # Fig. 1: 19 velocity nodes (x2 components) and one pressure node per stage
+    xyz, cells = wl.square_mesh(8)
+    th = TaylorHood(xyz, cells)
+    v = 4 * 9 + 4
+    pat = patch_dofs(th, 1)[v]
+    assert pat.size == 39
+    assert (pat >= th.nvel).sum() == 1 and pat[-1] == th.nvel + v
+    # the 19 nodes: a 3x3 block of the doubled lattice around v plus 10 more (Fig. 1)
+    nodes = th.free[pat[pat < th.nfree]]
+    lat = np.rint(th.node_xyz[nodes] * 16).astype(int) - 8
+    expect = {(x, y) for x in (-1, 0, 1) for y in (-1, 0, 1)}
+    expect |= {(0, -2), (0, 2), (-2, 0), (2, 0), (2, -2), (1, -2), (2, -1), (-2, 1), (-2, 2), (-1, 2)}
+    assert set(map(tuple, lat)) == expect
+
+
+@pytest.mark.parametrize("n,sum_n,sum_n2", [(16, 9327, 330081), (32, 38607, 1436289)])
+def test_patch_statistics(n, sum_n, sum_n2):
+    # sums of per-stage patch sizes by independent topology counting
+    xyz, cells = wl.square_mesh(n)
+    th = TaylorHood(xyz, cells)
+    sizes = np.array([p.size for p in patch_dofs(th, 1)])
+    assert sizes.sum() == sum_n and (sizes**2).sum() == sum_n2
+    assert set(sizes) == {3, 9, 11, 15, 27, 29, 33, 39}
+
+
+def test_interior_patch_3d():
+    xyz, cells = wl.cube_mesh(4)
+    th = TaylorHood(xyz, cells)
+    v = (2 * 5 + 2) * 5 + 2
+    assert patch_dofs(th, 1)[v].size == 196  # 65 nodes x 3 + 1
+
+
+@pytest.mark.parametrize("r", [1, 2, 3])
+def test_cover_and_multiplicity(r):
+    xyz, cells = wl.square_mesh(6)
+    th = TaylorHood(xyz, cells)
+    pats = patch_dofs(th, r)
+    D = multiplicity(pats, r * th.nstage)
+    assert D.min() >= 1
+    assert D.max() == 7
+    for i in range(r):
+        assert np.all(D[i * th.nstage + th.nvel:(i + 1) * th.nstage] == 1)
+    assert all(p.size == r * (pats[0].size // r) for p in pats[:1])
+
+
+def test_single_patch_exactness():
+    xyz, cells = wl.square_mesh(6)
+    th = TaylorHood(xyz, cells)
+    A, b, c = tableau("radauIIA", 3)
+    S = StageSystem(th, A, 0.05, 1.0)
+    pats = patch_dofs(th, 3)
+    sm = VankaSmoother(S.J, pats, 1.0, weighted=False)
+    rng = np.random.default_rng(3)
+    for v in (0, 17, 24):
+        e = np.zeros(S.n)
+        e[pats[v]] = rng.standard_normal(pats[v].size)
+        Je = S.J @ e
+        inv = [g for g in sm.groups if g[0].shape[1] == pats[v].size][0]
+        row = [i for i in range(inv[0].shape[0]) if np.array_equal(inv[0][i], pats[v])][0]
+        back = np.zeros(S.n)
+        back[pats[v]] = inv[1][row] @ Je[pats[v]]
+        assert np.abs(back - e).max() < 1e-12 * np.abs(e).max()
