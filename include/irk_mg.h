@@ -1,0 +1,206 @@
+/*
+ * irk_mg.h -- C ABI of the MI355X stage-coupled Vanka multigrid library (libirkmg.so).
+ *
+ * The library solves the stage system of a fully implicit Runge--Kutta step for the
+ * Taylor--Hood (P2-P1) discretisation of the time-dependent Stokes equations and of
+ * their Oseen linearisation (Abu-Labdeh, MacLachlan, Farrell, "Monolithic multigrid for
+ * implicit Runge--Kutta discretizations of incompressible fluid flow", Sec. 3.1, the
+ * stage system in Kronecker form):
+ *
+ *     ( I_r (x) [M 0; 0 0] + dt A (x) [K(+C) B; B^T 0] ) k = F,
+ *
+ * preconditioning FGMRES (Sec. 4) with a geometric V-cycle whose relaxation is the
+ * additive vertex-star Vanka sweep coupling all stages (Sec. 4.2) and whose transfers
+ * are I_r (x) P and its transpose (Sec. 4.1).  All arithmetic runs in HIP kernels on a
+ * gfx950 GPU; host code only builds the mesh topology and sparse structures.
+ *
+ * Conventions used by every entry point
+ * -------------------------------------
+ * Numbering.  On a mesh level the P2 nodes are the vertices in input order followed
+ *   by the edges sorted by (smaller vertex index, larger vertex index).  A node is a
+ *   boundary node when it lies on a facet that belongs to exactly one cell; boundary
+ *   velocity values are zero and eliminated.  Free nodes are the others, in ascending
+ *   node order.
+ * Vector layout ("ABI layout"), length r * ns with ns = dim * nfree + nverts: stage
+ *   blocks in stage order (Sec. 3.1 orders the stages consecutively, each stage's
+ *   velocity and pressure together); inside a stage block the velocity components one
+ *   after the other, each over the free nodes, then the pressure at every vertex.
+ * Pressure.  The pressure is determined up to a constant per stage.  Every
+ *   preconditioner application and every solution returned has each stage's
+ *   arithmetic pressure mean removed; the coarsest-level solve pins the pressure of
+ *   vertex 0 of every stage.
+ * Memory.  Host inputs to irk_mg_setup are borrowed (copied during the call).  Vector
+ *   arguments of the other calls are DEVICE pointers owned by the caller, float64,
+ *   contiguous, not aliasing each other unless stated; the handle owns all its device
+ *   memory.  `stream` is a hipStream_t (NULL: the null stream); work is stream-ordered
+ *   and calls return without synchronising unless stated.
+ * Errors.  Calls return IRK_OK (0), a negative error, or a positive warning.  Arguments
+ *   are validated before any device work.  irk_last_error() describes the last failure
+ *   on the calling thread.  A handle is not thread safe; distinct handles are
+ *   independent.
+ */
+#ifndef IRK_MG_H
+#define IRK_MG_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int irk_status;
+enum {
+  IRK_OK = 0,
+  IRK_EINVAL = -1,     /* invalid argument (checked before any device work)       */
+  IRK_ENOMEM = -2,     /* device or host allocation failed                        */
+  IRK_EHIP = -3,       /* a HIP runtime call failed                               */
+  IRK_ESINGULAR = -4,  /* zero pivot in a patch or coarse factorisation           */
+  IRK_ENAN = -5,       /* non-finite value met in a solve                         */
+  IRK_ENOCONV = 1      /* warning: FGMRES hit maxit before reaching rtol          */
+};
+
+/* One level of a nested simplicial mesh hierarchy (Sec. 4.1: uniform refinements of
+ * a coarsest grid).  Levels are passed coarse to fine.  cells[c*(dim+1)+k] is the k-th
+ * vertex of cell c; parent[c] is the cell of the next coarser level that contains
+ * cell c (NULL on level 0).  Every level must be a red refinement of the previous one
+ * (each coarse vertex and edge midpoint is a fine vertex). */
+typedef struct irk_mesh_level {
+  int dim;                /* 2 (triangles) or 3 (tetrahedra)                 */
+  int64_t nverts, ncells;
+  const double* xyz;      /* host, nverts x dim, row-major                    */
+  const int64_t* cells;   /* host, ncells x (dim+1)                           */
+  const int64_t* parent;  /* host, ncells, or NULL on level 0                 */
+} irk_mesh_level;
+
+/* Butcher tableau (Sec. 2, eq. "general RK"): r x r matrix A (row-major), weights b,
+ * nodes c.  1 <= r <= 4.  A must be invertible (fully implicit). */
+typedef struct irk_tableau {
+  int r;
+  const double* A;
+  const double* b;
+  const double* c;
+} irk_tableau;
+
+/* Solver options.  Defaults (irk_mg_default_opts): 2 pre- and 2 post-sweeps (Sec. 5.1),
+ * omega = 0.5, partition-of-unity weighting, FP64. */
+typedef struct irk_mg_opts {
+  int pre, post;     /* Vanka sweeps before / after the coarse correction        */
+  double omega;      /* damping of the additive sweep (Sec. 4.2)                 */
+  int weighting;     /* 0: literal sum over patches; 1: each DOF's correction
+                        divided by the number of patches containing it          */
+  int precision;     /* 0: FP64 V-cycle; 1: FP32 patch factors and FP32 V-cycle
+                        (coarse solve, FGMRES and outer residual stay FP64)      */
+} irk_mg_opts;
+
+/* Per-solve report.  history (host, may be NULL) receives up to history_cap residual
+ * 2-norms: the initial one, then one per iteration. */
+typedef struct irk_solve_info {
+  int iterations;
+  int converged;
+  double rel_residual;     /* ||F - J k|| / ||F - J k0|| recomputed at exit */
+  double* history;
+  int history_cap;
+  double ms_vcycle;        /* GPU time inside the preconditioner (ms)       */
+  double ms_total;         /* GPU time of the whole solve (ms)              */
+} irk_solve_info;
+
+typedef struct irk_mg irk_mg; /* opaque handle */
+
+/* Fill *opt with the defaults listed above. */
+void irk_mg_default_opts(irk_mg_opts* opt);
+
+/* Built-in tableaux (Sec. 5: Gauss, RadauIIA, LobattoIIIC): family 0 = RadauIIA
+ * (r = 1..3), 1 = Gauss (r = 1..3), 2 = LobattoIIIC (r = 2..3).  Writes r*r + 2r
+ * values to A, b, c (host arrays of size >= 16, 4, 4).  Returns IRK_EINVAL for an
+ * unknown (family, r). */
+irk_status irk_tableau_builtin(int family, int r, double* A, double* b, double* c);
+
+/* P2 node coordinates of one mesh level without building a handle (so that nodal data
+ * such as the wind can be evaluated before irk_mg_setup): writes the node count to
+ * *nnodes and, if xyz is not NULL, the coordinates (host, nnodes x dim) in the node
+ * numbering above.  Errors: IRK_EINVAL for null or out-of-range input. */
+irk_status irk_mesh_p2_nodes(const irk_mesh_level* level, int64_t* nnodes, double* xyz);
+
+/* Build the hierarchy for the stage operator with step dt, viscosity nu (K is nu times
+ * the P2 Laplacian, Sec. 3.1-3.2) and optional wind (Oseen convection C(w), Sec. 3.2):
+ * `wind` is host, nnodes_finest x dim nodal P2 values on the finest level (NULL for
+ * Stokes); coarser levels take the values at coincident nodes.  Assembles every level
+ * (rediscretisation, Sec. 4.1), builds the vertex-star patches (Sec. 4.2, Fig. 1),
+ * factorises every patch on the GPU and the coarsest operator, and returns the handle
+ * in *out.  Synchronises `stream` before returning.  Errors: IRK_EINVAL (dims, sizes,
+ * r outside 1..4, non-nested levels, nlevels < 1), IRK_ENOMEM, IRK_EHIP,
+ * IRK_ESINGULAR (a zero pivot in a patch or in the coarse operator). */
+irk_status irk_mg_setup(const irk_mesh_level* levels, int nlevels, const irk_tableau* tab,
+                        double dt, double nu, const double* wind, const irk_mg_opts* opt,
+                        void* stream, irk_mg** out);
+
+/* Release the handle and all its device memory (NULL is ignored). */
+void irk_mg_destroy(irk_mg* h);
+
+/* Number of unknowns r * ns of level `level` (0 = coarsest; -1 = finest), or -1. */
+int64_t irk_mg_ndofs(const irk_mg* h, int level);
+
+/* Level sizes: out[0..4] = nverts, nnodes, nfree, ns (= dim*nfree + nverts), nlevels.
+ * level -1 is the finest. */
+irk_status irk_mg_sizes(const irk_mg* h, int level, int64_t* out);
+
+/* Coordinates of the P2 nodes of a level (host out, nnodes x dim) and the node index of
+ * every free node (host out, nfree; may be NULL). */
+irk_status irk_mg_p2_nodes(const irk_mg* h, int level, double* xyz, int64_t* free_nodes);
+
+/* y = J x (transpose = 0) or y = J^T x (transpose = 1) on the finest level. */
+irk_status irk_mg_apply(irk_mg* h, const double* x, double* y, int transpose, void* stream);
+
+/* z = V r: one V-cycle (Sec. 4.1-4.2, 5.1) from a zero initial guess on the finest
+ * level, pressure means removed.  In FP32 mode r is rounded to FP32 on entry and the
+ * cycle runs in FP32 except for the coarse solve.  r and z may not alias. */
+irk_status irk_mg_vcycle(irk_mg* h, const double* r, double* z, void* stream);
+
+/* z = V^T r: the transpose of irk_mg_vcycle as a linear map (used by adjoint solves). */
+irk_status irk_mg_vcycle_transpose(irk_mg* h, const double* r, double* z, void* stream);
+
+/* Solve J k = F by restarted FGMRES(restart) right-preconditioned with irk_mg_vcycle
+ * (Sec. 4), modified Gram--Schmidt, stopping when the residual estimate is at most
+ * rtol * ||F - J k0|| or after maxit iterations.  k holds k0 on entry and the solution
+ * (pressure means removed) on exit.  Synchronises `stream`.  Returns IRK_ENOCONV when
+ * maxit is reached, IRK_ENAN when a non-finite value appears.  info may be NULL. */
+irk_status irk_fgmres_solve(irk_mg* h, const double* F, double* k, double rtol, int maxit,
+                            int restart, irk_solve_info* info, void* stream);
+
+/* Solve J^T lam = G the same way, preconditioned by irk_mg_vcycle_transpose.  G must
+ * have zero pressure sum in every stage (the left null vectors of J^T). */
+irk_status irk_adjoint_solve(irk_mg* h, const double* G, double* lam, double rtol, int maxit,
+                             int restart, irk_solve_info* info, void* stream);
+
+/* Right-hand side of the stage system (Sec. 3.1): F_i = [M f_i - L u - B p ; -B^T u]
+ * with L = K (+C).  f: device, r x nnodes x dim (stage, node, component) nodal forcing
+ * values at every P2 node of the finest level; state: device, ns values (u as in a
+ * stage block of the ABI layout, then p). */
+irk_status irk_rhs(irk_mg* h, const double* f, const double* state, double* F, void* stream);
+
+/* state += dt * sum_j b_j k_j (the update of Sec. 3.1), state and k as above. */
+irk_status irk_update(irk_mg* h, const double* k, double* state, void* stream);
+
+/* Per-level building blocks, exposed so that each step of the cycle can be checked on
+ * its own.  Vectors use the ABI layout of the level named. */
+/* y = J_l x or J_l^T x on level l. */
+irk_status irk_level_apply(irk_mg* h, int level, int transpose, const double* x, double* y,
+                           void* stream);
+/* One additive Vanka sweep on level l >= 1 (Sec. 4.2): k <- k + omega W sum_v R_v^T
+ * A_v^{-1} R_v (F - J_l k); transpose = 1 gives the transposed sweep for J_l^T. */
+irk_status irk_level_sweep(irk_mg* h, int level, int transpose, const double* F, double* k,
+                           void* stream);
+/* xc = (I_r (x) P_l)^T xf: restriction from level l >= 1 to level l-1 (Sec. 4.1). */
+irk_status irk_level_restrict(irk_mg* h, int level, const double* xf, double* xc, void* stream);
+/* xf += (I_r (x) P_l) xc: prolongation from level l-1 to level l >= 1 (Sec. 4.1). */
+irk_status irk_level_prolong(irk_mg* h, int level, const double* xc, double* xf, void* stream);
+/* x = J_0^{-1} b on the coarsest level with pinned pressures (transpose: J_0^{-T}). */
+irk_status irk_coarse_solve(irk_mg* h, int transpose, const double* b, double* x, void* stream);
+
+/* Description of the last error on the calling thread ("" if none). */
+const char* irk_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* IRK_MG_H */

@@ -1,0 +1,196 @@
+// Internal structures of libirkmg: host-side level data built at setup, the device
+// copies the kernels read, and the launchers the driver calls.
+//
+// Internal vector layout of a level (device only; the ABI layout is converted at the
+// boundary): velocity first, node-major with component and stage innermost,
+//   V[(i * dim + c) * r + s]        i < nfree, c < dim, s < r
+// then pressure, vertex-major with stage innermost,
+//   P[offV + v * r + s]             offV = nfree * dim * r.
+// Every sparse operator reads the dim*r (or r) values of a node as one contiguous
+// chunk, so one CSR traversal serves all stages and components (the Kronecker
+// structure is never expanded).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+namespace irk {
+
+constexpr int kMaxStages = 4;
+
+// ----------------------------------------------------------------- host level data
+struct HostLevel {
+  int dim = 0;
+  int64_t nv = 0, nc = 0, ne = 0, nn = 0, nfree = 0;
+  std::vector<double> xyz;          // nv x dim
+  std::vector<int64_t> cells;       // nc x (dim+1)
+  std::vector<int64_t> edges;       // ne x 2
+  std::vector<int64_t> cell_nodes;  // nc x nloc (vertices, then local edges)
+  std::vector<int32_t> free_of_node, node_of_free;
+  std::vector<int32_t> node_cell_ptr, node_cell;  // node -> cells containing it
+
+  // scalar P2 operators on free x free: mass M, L = nu K (+ C), and L^T on the
+  // same (symmetric) pattern
+  std::vector<int32_t> s_ptr, s_col;
+  std::vector<double> s_M, s_L, s_Lt, s_K1;  // s_K1: Laplacian with nu = 1
+  // weak gradient B (free node x vertex, dim values per entry) and its transpose
+  std::vector<int32_t> b_ptr, b_col;
+  std::vector<double> b_val;
+  std::vector<int32_t> bt_ptr, bt_col;
+  std::vector<double> bt_val;
+  // free-row x all-node mass (forcing term of the right-hand side)
+  std::vector<int32_t> mfa_ptr, mfa_col;
+  std::vector<double> mfa_val;
+
+  // vertex-star patches: free nodes of each patch (ascending) and the CSR entries
+  // that couple them
+  std::vector<int32_t> pn_ptr, pn_node;
+  std::vector<int32_t> pvv_ptr, pvv;  // triples (local a, local b, scalar CSR pos)
+  std::vector<int32_t> pvp;           // per patch node: B CSR pos of (node, vertex)
+
+  // transfers from the next coarser level (fine rows): scalar P2 on free nodes,
+  // P1 on vertices, and their transposes (coarse rows)
+  std::vector<int32_t> pu_ptr, pu_col, put_ptr, put_col;
+  std::vector<double> pu_val, put_val;
+  std::vector<int32_t> pp_ptr, pp_col, ppt_ptr, ppt_col;
+  std::vector<double> pp_val, ppt_val;
+  std::vector<int64_t> coarse_node_to_fine_vertex;  // injection (wind)
+};
+
+// Element reference tensors (integrals over the cell divided by its measure).
+void build_topology(HostLevel& L, int dim, int64_t nv, int64_t nc, const double* xyz,
+                    const int64_t* cells);
+void assemble_level(HostLevel& L, double nu, const std::vector<double>* wind_nodal,
+                    bool with_mfa);
+void build_patches(HostLevel& L);
+// Returns an empty string on success, else a description of the nesting failure.
+std::string build_transfer(const HostLevel& coarse, HostLevel& fine, const int64_t* parent);
+// Dense coarse operator with pinned pressures, inverted by Gauss--Jordan with partial
+// pivoting; returns false on a zero pivot.  inv is column-major N x N, internal layout.
+bool coarse_inverse(const HostLevel& L, int r, const double* A, double dt,
+                    std::vector<double>& inv);
+
+// ---------------------------------------------------------------- device level data
+template <typename T>
+struct DevOps {
+  T* s_M = nullptr;
+  T* s_L = nullptr;
+  T* s_Lt = nullptr;
+  T* b_val = nullptr;
+  T* bt_val = nullptr;
+  T* pu_val = nullptr;
+  T* put_val = nullptr;
+  T* pp_val = nullptr;
+  T* ppt_val = nullptr;
+  T* W = nullptr;  // per internal DOF weight of the additive correction
+};
+
+struct DevLevel {
+  int dim = 0, r = 0;
+  int64_t nv = 0, nfree = 0, N = 0, offV = 0;
+  int32_t *s_ptr = nullptr, *s_col = nullptr;
+  int32_t *b_ptr = nullptr, *b_col = nullptr, *bt_ptr = nullptr, *bt_col = nullptr;
+  int32_t *pu_ptr = nullptr, *pu_col = nullptr, *put_ptr = nullptr, *put_col = nullptr;
+  int32_t *pp_ptr = nullptr, *pp_col = nullptr, *ppt_ptr = nullptr, *ppt_col = nullptr;
+  int32_t *mfa_ptr = nullptr, *mfa_col = nullptr;
+  double* mfa_val = nullptr;
+  double* s_K1 = nullptr;
+  DevOps<double> d64;
+  DevOps<float> d32;
+
+  // patches
+  int64_t npatch = 0;
+  int32_t* p_nloc = nullptr;     // r * (dim * nn + 1)
+  int32_t* p_ld = nullptr;       // leading dimension of the stored inverse
+  int64_t* p_inv_off = nullptr;  // element offset of the inverse
+  int64_t* p_slot_off = nullptr; // offset of the patch's output slots
+  int32_t* p_gidx = nullptr;     // concatenated local -> internal DOF index
+  int32_t* p_nn = nullptr;
+  int32_t* p_vertex = nullptr;
+  int32_t *pvv_ptr = nullptr, *pvv = nullptr, *pvp = nullptr, *pn_ptr = nullptr;
+  int32_t *gat_ptr = nullptr, *gat_slot = nullptr;  // DOF -> its patch slots
+  void* inv = nullptr;                              // double or float inverses
+  int64_t inv_elems = 0, slots = 0;
+  int max_nloc = 0;
+  int32_t* sched = nullptr;  // patch launch order (largest first)
+
+  // work vectors (internal layout) in the working precision
+  void *b = nullptr, *x = nullptr, *res = nullptr, *Y = nullptr;
+};
+
+struct Handle {
+  int dim = 0, r = 0, nlevels = 0, precision = 0;
+  double dt = 0, nu = 0, omega = 0.5;
+  int pre = 2, post = 2, weighting = 1;
+  double A[kMaxStages * kMaxStages] = {0}, At[kMaxStages * kMaxStages] = {0};
+  double b[kMaxStages] = {0}, c[kMaxStages] = {0};
+  std::vector<HostLevel> host;
+  std::vector<DevLevel> dev;
+  double* coarse_inv = nullptr;   // column-major, internal layout
+  double* coarse_invT = nullptr;  // column-major inverse of the transpose
+  double *cb = nullptr, *cx = nullptr;  // FP64 coarse vectors
+  // FGMRES workspace (finest level, internal layout, FP64)
+  int krylov_cap = 0;
+  double *kv = nullptr, *kz = nullptr, *kw = nullptr, *kF = nullptr, *kx = nullptr,
+         *kr = nullptr;
+  double* scal = nullptr;      // device scalars (dot results)
+  double* partials = nullptr;  // reduction partials
+  double* hbuf = nullptr;      // device Hessenberg column
+  std::vector<void*> allocations;
+  hipEvent_t ev0 = nullptr, ev1 = nullptr, ev2 = nullptr, ev3 = nullptr;
+};
+
+// ------------------------------------------------------------------------ launchers
+// All launchers enqueue on `s` and return hipGetLastError().
+namespace k {
+template <typename T>
+hipError_t residual(const DevLevel& L, const DevOps<T>& ops, const double* A, double dt,
+                    const T* F, const T* x, T* y, hipStream_t s);
+template <typename T>
+hipError_t patch_apply(const DevLevel& L, const DevOps<T>& ops, const T* res, T* Y,
+                       int transpose, hipStream_t s);
+template <typename T>
+hipError_t gather_update(const DevLevel& L, const DevOps<T>& ops, const T* Y, T* x, T omega,
+                         int mode, hipStream_t s);
+template <typename T>
+hipError_t restrict_(const DevLevel& fine, const DevLevel& coarse, const DevOps<T>& fops,
+                     const T* xf, T* xc, hipStream_t s);
+template <typename T>
+hipError_t prolong_add(const DevLevel& fine, const DevLevel& coarse, const DevOps<T>& fops,
+                       const T* xc, T* xf, hipStream_t s);
+template <typename T>
+hipError_t patch_factor(const DevLevel& L, const DevOps<T>& ops, const double* A, double dt,
+                        int* d_fail, hipStream_t s);
+hipError_t coarse_gemv(const double* inv, int64_t N, const double* b, double* x,
+                       const int64_t* pins, int npins, hipStream_t s);
+template <typename T>
+hipError_t to_internal(const DevLevel& L, const double* abi, T* x, hipStream_t s);
+template <typename T>
+hipError_t to_abi(const DevLevel& L, const T* x, double* abi, hipStream_t s);
+template <typename S, typename D>
+hipError_t cast(const S* in, D* out, int64_t n, hipStream_t s);
+hipError_t project_pressure(const DevLevel& L, double* x, double* partials, hipStream_t s);
+// deterministic reductions: result written to device scalar *out
+hipError_t dot(const double* a, const double* b, int64_t n, double* partials, double* out,
+               hipStream_t s, int take_sqrt = 0);
+// y += alpha * x with alpha = sign * (*dev_scalar) (or the host value if dev_scalar null)
+hipError_t axpy_dev(double* y, const double* x, int64_t n, const double* dev_scalar,
+                    double sign, hipStream_t s);
+// y = x / (*dev_scalar)
+hipError_t scale_inv_dev(double* y, const double* x, int64_t n, const double* dev_scalar,
+                         hipStream_t s);
+hipError_t axpby(double* y, const double* x, int64_t n, double alpha, double beta,
+                 hipStream_t s);  // y = alpha x + beta y
+hipError_t fill(double* y, int64_t n, double v, hipStream_t s);
+hipError_t fillf(float* y, int64_t n, float v, hipStream_t s);
+hipError_t nonfinite(const double* x, int64_t n, int* flag, hipStream_t s);
+hipError_t rhs(const DevLevel& L, int64_t nnodes, const double* f, const double* state,
+               double* F, hipStream_t s);
+hipError_t update(const DevLevel& L, const double* b, double dt, const double* k,
+                  double* state, hipStream_t s);
+}  // namespace k
+
+}  // namespace irk

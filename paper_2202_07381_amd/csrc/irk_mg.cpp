@@ -1,0 +1,885 @@
+// C ABI of libirkmg (include/irk_mg.h): argument validation, setup orchestration, the
+// multi-launch V-cycle (Sec. 4.1-4.2, 5.1) and the restarted FGMRES driver (Sec. 4).
+// Host code only sequences kernels; all vector arithmetic runs on the GPU.
+#include "../../include/irk_mg.h"
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <numeric>
+#include <string>
+#include <type_traits>
+#include <vector>
+
+#include "irk_internal.h"
+
+using namespace irk;
+
+namespace {
+
+thread_local std::string g_err;
+
+irk_status fail(irk_status code, const std::string& msg) {
+  g_err = msg;
+  return code;
+}
+
+#define HIPCHK(expr)                                                                    \
+  do {                                                                                  \
+    hipError_t e_ = (expr);                                                             \
+    if (e_ != hipSuccess)                                                               \
+      return fail(e_ == hipErrorOutOfMemory ? IRK_ENOMEM : IRK_EHIP,                    \
+                  std::string(#expr) + ": " + hipGetErrorString(e_));                   \
+  } while (0)
+
+#define CHK(expr)                       \
+  do {                                  \
+    irk_status s_ = (expr);             \
+    if (s_ != IRK_OK) return s_;        \
+  } while (0)
+
+template <typename T>
+irk_status dalloc(Handle* h, T** p, size_t n) {
+  *p = nullptr;
+  if (n == 0) n = 1;
+  hipError_t e = hipMalloc((void**)p, n * sizeof(T));
+  if (e != hipSuccess) return fail(IRK_ENOMEM, "hipMalloc of " + std::to_string(n * sizeof(T)) + " bytes failed");
+  h->allocations.push_back(*p);
+  return IRK_OK;
+}
+
+template <typename T, typename S>
+irk_status upload(Handle* h, T** p, const std::vector<S>& v, hipStream_t s) {
+  CHK(dalloc(h, p, v.size()));
+  if (v.empty()) return IRK_OK;
+  std::vector<T> tmp(v.begin(), v.end());
+  HIPCHK(hipMemcpyAsync(*p, tmp.data(), tmp.size() * sizeof(T), hipMemcpyHostToDevice, s));
+  HIPCHK(hipStreamSynchronize(s));
+  return IRK_OK;
+}
+
+template <typename T>
+DevOps<T>& ops_of(DevLevel& L);
+template <>
+DevOps<double>& ops_of<double>(DevLevel& L) { return L.d64; }
+template <>
+DevOps<float>& ops_of<float>(DevLevel& L) { return L.d32; }
+
+template <typename T>
+irk_status upload_ops(Handle* h, HostLevel& H, DevLevel& D, DevOps<T>& o, const std::vector<double>& W,
+                      hipStream_t s) {
+  CHK(upload(h, &o.s_M, H.s_M, s));
+  CHK(upload(h, &o.s_L, H.s_L, s));
+  CHK(upload(h, &o.s_Lt, H.s_Lt, s));
+  CHK(upload(h, &o.b_val, H.b_val, s));
+  CHK(upload(h, &o.bt_val, H.bt_val, s));
+  CHK(upload(h, &o.W, W, s));
+  if (!H.pu_val.empty()) {
+    CHK(upload(h, &o.pu_val, H.pu_val, s));
+    CHK(upload(h, &o.put_val, H.put_val, s));
+    CHK(upload(h, &o.pp_val, H.pp_val, s));
+    CHK(upload(h, &o.ppt_val, H.ppt_val, s));
+  }
+  (void)D;
+  return IRK_OK;
+}
+
+inline hipStream_t S(void* s) { return reinterpret_cast<hipStream_t>(s); }
+
+// ----------------------------------------------------------------------- V-cycle
+template <typename T>
+irk_status smooth(Handle* h, int l, int nsweeps, bool zero_start, bool tr, hipStream_t s) {
+  DevLevel& L = h->dev[l];
+  DevOps<T>& o = ops_of<T>(L);
+  T* b = (T*)L.b;
+  T* x = (T*)L.x;
+  T* res = (T*)L.res;
+  T* Y = (T*)L.Y;
+  const double* A = tr ? h->At : h->A;
+  if (nsweeps == 0) {
+    if (zero_start) {
+      if constexpr (std::is_same<T, double>::value) HIPCHK(k::fill(x, L.N, 0.0, s));
+      else HIPCHK(k::fillf(x, L.N, 0.f, s));
+    }
+    return IRK_OK;
+  }
+  DevOps<T> ot = o;
+  if (tr) ot.s_L = o.s_Lt;
+  for (int it = 0; it < nsweeps; ++it) {
+    const bool first = zero_start && it == 0;
+    const T* r = b;
+    if (!first) {
+      HIPCHK(k::residual<T>(L, ot, A, h->dt, b, x, res, s));
+      r = res;
+    }
+    HIPCHK(k::patch_apply<T>(L, o, r, Y, tr ? 1 : 0, s));
+    const int mode = (tr ? 2 : 0) + (first ? 0 : 1);
+    HIPCHK(k::gather_update<T>(L, o, Y, x, (T)h->omega, mode, s));
+  }
+  return IRK_OK;
+}
+
+template <typename T>
+irk_status vcycle_T(Handle* h, bool tr, hipStream_t s, const int64_t* pins) {
+  const int top = h->nlevels - 1;
+  const int npre = tr ? h->post : h->pre;
+  const int npost = tr ? h->pre : h->post;
+  const double* A = tr ? h->At : h->A;
+  for (int l = top; l >= 1; --l) {
+    DevLevel& L = h->dev[l];
+    DevOps<T> o = ops_of<T>(L);
+    if (tr) o.s_L = o.s_Lt;
+    CHK(smooth<T>(h, l, npre, true, tr, s));
+    HIPCHK(k::residual<T>(L, o, A, h->dt, (const T*)L.b, (const T*)L.x, (T*)L.res, s));
+    HIPCHK(k::restrict_<T>(L, h->dev[l - 1], ops_of<T>(L), (const T*)L.res, (T*)h->dev[l - 1].b, s));
+  }
+  {
+    DevLevel& L = h->dev[0];
+    HIPCHK((k::cast<T, double>((const T*)L.b, h->cb, L.N, s)));
+    HIPCHK(k::coarse_gemv(tr ? h->coarse_invT : h->coarse_inv, L.N, h->cb, h->cx, pins, h->r, s));
+    HIPCHK((k::cast<double, T>(h->cx, (T*)L.x, L.N, s)));
+  }
+  for (int l = 1; l <= top; ++l) {
+    DevLevel& L = h->dev[l];
+    HIPCHK(k::prolong_add<T>(L, h->dev[l - 1], ops_of<T>(L), (const T*)h->dev[l - 1].x, (T*)L.x, s));
+    CHK(smooth<T>(h, l, npost, false, tr, s));
+  }
+  return IRK_OK;
+}
+
+struct HandleExtra {
+  int64_t* pins = nullptr;
+  int* flag = nullptr;
+};
+
+}  // namespace
+
+// Extra device state hung off the handle (pins of the coarse solve, error flags).
+namespace irk {
+struct HandleFull : Handle {
+  HandleExtra ex;
+};
+}  // namespace irk
+
+struct irk_mg : irk::HandleFull {};
+
+namespace {
+
+irk_status precondition(irk_mg* h, const double* v, double* z, bool tr, hipStream_t s) {
+  DevLevel& L = h->dev[h->nlevels - 1];
+  if (tr) {
+    HIPCHK((k::cast<double, double>(v, h->kw, L.N, s)));
+    HIPCHK(k::project_pressure(L, h->kw, h->partials, s));
+    v = h->kw;
+  }
+  if (h->precision == 0) {
+    HIPCHK((k::cast<double, double>(v, (double*)L.b, L.N, s)));
+    CHK(vcycle_T<double>(h, tr, s, h->ex.pins));
+    HIPCHK((k::cast<double, double>((const double*)L.x, z, L.N, s)));
+  } else {
+    HIPCHK((k::cast<double, float>(v, (float*)L.b, L.N, s)));
+    CHK(vcycle_T<float>(h, tr, s, h->ex.pins));
+    HIPCHK((k::cast<float, double>((const float*)L.x, z, L.N, s)));
+  }
+  if (!tr) HIPCHK(k::project_pressure(L, z, h->partials, s));
+  return IRK_OK;
+}
+
+irk_status apply_J(irk_mg* h, const double* x, double* y, bool tr, const double* F, hipStream_t s) {
+  DevLevel& L = h->dev[h->nlevels - 1];
+  DevOps<double> o = L.d64;
+  if (tr) o.s_L = o.s_Lt;
+  HIPCHK(k::residual<double>(L, o, tr ? h->At : h->A, h->dt, F, x, y, s));
+  return IRK_OK;
+}
+
+irk_status ensure_krylov(irk_mg* h, int restart) {
+  if (h->krylov_cap >= restart) return IRK_OK;
+  const int64_t N = h->dev[h->nlevels - 1].N;
+  if (h->kv) {
+    (void)hipFree(h->kv);
+    (void)hipFree(h->kz);
+    h->allocations.erase(std::remove(h->allocations.begin(), h->allocations.end(), (void*)h->kv), h->allocations.end());
+    h->allocations.erase(std::remove(h->allocations.begin(), h->allocations.end(), (void*)h->kz), h->allocations.end());
+    h->kv = h->kz = nullptr;
+  }
+  CHK(dalloc(h, &h->kv, (size_t)(restart + 1) * N));
+  CHK(dalloc(h, &h->kz, (size_t)restart * N));
+  h->krylov_cap = restart;
+  return IRK_OK;
+}
+
+irk_status fgmres(irk_mg* h, const double* F_abi, double* k_abi, double rtol, int maxit, int restart,
+                  irk_solve_info* info, bool tr, hipStream_t s) {
+  if (!F_abi || !k_abi) return fail(IRK_EINVAL, "null vector");
+  if (!(rtol > 0) || maxit < 1 || restart < 1 || restart > 1000)
+    return fail(IRK_EINVAL, "rtol must be > 0, maxit >= 1, 1 <= restart <= 1000");
+  CHK(ensure_krylov(h, restart));
+  DevLevel& L = h->dev[h->nlevels - 1];
+  const int64_t N = L.N;
+  HIPCHK(hipEventRecord(h->ev0, s));
+  HIPCHK(k::to_internal<double>(L, F_abi, h->kF, s));
+  HIPCHK(k::to_internal<double>(L, k_abi, h->kx, s));
+  double* H = nullptr;
+  std::vector<double> Hm((size_t)(restart + 1) * restart), cs(restart), sn(restart), g(restart + 1),
+      y(restart), hcol(restart + 2);
+  auto host_scalar = [&](double* dev, double* out) -> irk_status {
+    HIPCHK(hipMemcpyAsync(out, dev, sizeof(double), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    return IRK_OK;
+  };
+  (void)H;
+  CHK(apply_J(h, h->kx, h->kr, tr, h->kF, s));
+  HIPCHK(k::dot(h->kr, h->kr, N, h->partials, h->scal, s, 1));
+  double beta0;
+  CHK(host_scalar(h->scal, &beta0));
+  int hist_n = 0;
+  auto push_hist = [&](double v) {
+    if (info && info->history && hist_n < info->history_cap) info->history[hist_n++] = v;
+  };
+  push_hist(beta0);
+  if (!std::isfinite(beta0)) return fail(IRK_ENAN, "non-finite initial residual");
+  int its = 0;
+  bool converged = beta0 == 0.0;
+  float ms_v = 0.f;
+  while (!converged && its < maxit) {
+    CHK(apply_J(h, h->kx, h->kr, tr, h->kF, s));
+    HIPCHK(k::dot(h->kr, h->kr, N, h->partials, h->scal, s, 1));
+    double beta;
+    CHK(host_scalar(h->scal, &beta));
+    if (!std::isfinite(beta)) return fail(IRK_ENAN, "non-finite residual");
+    if (beta <= rtol * beta0) {
+      converged = true;
+      break;
+    }
+    HIPCHK(k::axpby(h->kv, h->kr, N, 1.0 / beta, 0.0, s));
+    std::fill(g.begin(), g.end(), 0.0);
+    g[0] = beta;
+    int jend = 0;
+    for (int j = 0; j < restart; ++j) {
+      double* vj = h->kv + (size_t)j * N;
+      double* zj = h->kz + (size_t)j * N;
+      double* vn = h->kv + (size_t)(j + 1) * N;
+      HIPCHK(hipEventRecord(h->ev2, s));
+      CHK(precondition(h, vj, zj, tr, s));
+      HIPCHK(hipEventRecord(h->ev3, s));
+      CHK(apply_J(h, zj, vn, tr, nullptr, s));
+      for (int i = 0; i <= j; ++i) {
+        HIPCHK(k::dot(vn, h->kv + (size_t)i * N, N, h->partials, h->hbuf + i, s, 0));
+        HIPCHK(k::axpy_dev(vn, h->kv + (size_t)i * N, N, h->hbuf + i, -1.0, s));
+      }
+      HIPCHK(k::dot(vn, vn, N, h->partials, h->hbuf + j + 1, s, 1));
+      HIPCHK(k::scale_inv_dev(vn, vn, N, h->hbuf + j + 1, s));
+      HIPCHK(hipMemcpyAsync(hcol.data(), h->hbuf, (j + 2) * sizeof(double), hipMemcpyDeviceToHost, s));
+      HIPCHK(hipStreamSynchronize(s));
+      float ms = 0;
+      HIPCHK(hipEventElapsedTime(&ms, h->ev2, h->ev3));
+      ms_v += ms;
+      for (int i = 0; i <= j + 1; ++i) {
+        if (!std::isfinite(hcol[i])) return fail(IRK_ENAN, "non-finite value in the Arnoldi process");
+        Hm[i * restart + j] = hcol[i];
+      }
+      for (int i = 0; i < j; ++i) {
+        const double t = cs[i] * Hm[i * restart + j] + sn[i] * Hm[(i + 1) * restart + j];
+        Hm[(i + 1) * restart + j] = -sn[i] * Hm[i * restart + j] + cs[i] * Hm[(i + 1) * restart + j];
+        Hm[i * restart + j] = t;
+      }
+      const double den = std::hypot(Hm[j * restart + j], Hm[(j + 1) * restart + j]);
+      cs[j] = Hm[j * restart + j] / den;
+      sn[j] = Hm[(j + 1) * restart + j] / den;
+      Hm[j * restart + j] = den;
+      Hm[(j + 1) * restart + j] = 0.0;
+      g[j + 1] = -sn[j] * g[j];
+      g[j] = cs[j] * g[j];
+      ++its;
+      jend = j + 1;
+      push_hist(std::fabs(g[j + 1]));
+      if (std::fabs(g[j + 1]) <= rtol * beta0 || its >= maxit) break;
+    }
+    for (int i = jend - 1; i >= 0; --i) {
+      double acc = g[i];
+      for (int m = i + 1; m < jend; ++m) acc -= Hm[i * restart + m] * y[m];
+      y[i] = acc / Hm[i * restart + i];
+    }
+    for (int i = 0; i < jend; ++i) HIPCHK(k::axpby(h->kx, h->kz + (size_t)i * N, N, y[i], 1.0, s));
+    if (std::fabs(g[jend]) <= rtol * beta0) converged = true;
+  }
+  HIPCHK(k::project_pressure(L, h->kx, h->partials, s));
+  CHK(apply_J(h, h->kx, h->kr, tr, h->kF, s));
+  HIPCHK(k::dot(h->kr, h->kr, N, h->partials, h->scal, s, 1));
+  double fin;
+  CHK(host_scalar(h->scal, &fin));
+  HIPCHK(k::to_abi<double>(L, h->kx, k_abi, s));
+  HIPCHK(hipEventRecord(h->ev1, s));
+  HIPCHK(hipEventSynchronize(h->ev1));
+  float ms_t = 0;
+  HIPCHK(hipEventElapsedTime(&ms_t, h->ev0, h->ev1));
+  if (info) {
+    info->iterations = its;
+    info->converged = converged ? 1 : 0;
+    info->rel_residual = beta0 > 0 ? fin / beta0 : 0.0;
+    info->ms_vcycle = ms_v;
+    info->ms_total = ms_t;
+  }
+  if (!std::isfinite(fin)) return fail(IRK_ENAN, "non-finite final residual");
+  if (!converged) {
+    g_err = "FGMRES reached maxit";
+    return IRK_ENOCONV;
+  }
+  return IRK_OK;
+}
+
+irk_status check_handle(irk_mg* h) {
+  if (!h) return fail(IRK_EINVAL, "null handle");
+  return IRK_OK;
+}
+
+irk_status check_level(irk_mg* h, int& level) {
+  CHK(check_handle(h));
+  if (level < 0) level = h->nlevels - 1;
+  if (level >= h->nlevels) return fail(IRK_EINVAL, "level out of range");
+  return IRK_OK;
+}
+
+template <typename T>
+irk_status level_sweep_T(irk_mg* h, int level, int transpose, const double* F, double* kv,
+                                hipStream_t s) {
+  DevLevel& L = h->dev[level];
+  HIPCHK(k::to_internal<T>(L, F, (T*)L.b, s));
+  HIPCHK(k::to_internal<T>(L, kv, (T*)L.x, s));
+  CHK(smooth<T>(h, level, 1, false, transpose != 0, s));
+  HIPCHK(k::to_abi<T>(L, (const T*)L.x, kv, s));
+  return IRK_OK;
+}
+
+}  // namespace
+
+// =========================================================================== ABI
+extern "C" {
+
+void irk_mg_default_opts(irk_mg_opts* o) {
+  if (!o) return;
+  o->pre = 2;
+  o->post = 2;
+  o->omega = 0.5;
+  o->weighting = 1;
+  o->precision = 0;
+}
+
+irk_status irk_tableau_builtin(int family, int r, double* A, double* b, double* c) {
+  if (!A || !b || !c) return fail(IRK_EINVAL, "null output");
+  const double s6 = std::sqrt(6.0), s3 = std::sqrt(3.0), s15 = std::sqrt(15.0);
+  std::vector<double> a, bb, cc;
+  if (family == 0 && r == 1) {
+    a = {1.0};
+    bb = {1.0};
+    cc = {1.0};
+  } else if (family == 0 && r == 2) {
+    a = {5.0 / 12, -1.0 / 12, 3.0 / 4, 1.0 / 4};
+    bb = {3.0 / 4, 1.0 / 4};
+    cc = {1.0 / 3, 1.0};
+  } else if (family == 0 && r == 3) {
+    a = {(88 - 7 * s6) / 360,      (296 - 169 * s6) / 1800, (-2 + 3 * s6) / 225,
+         (296 + 169 * s6) / 1800,  (88 + 7 * s6) / 360,     (-2 - 3 * s6) / 225,
+         (16 - s6) / 36,           (16 + s6) / 36,          1.0 / 9};
+    bb = {(16 - s6) / 36, (16 + s6) / 36, 1.0 / 9};
+    cc = {(4 - s6) / 10, (4 + s6) / 10, 1.0};
+  } else if (family == 1 && r == 1) {
+    a = {0.5};
+    bb = {1.0};
+    cc = {0.5};
+  } else if (family == 1 && r == 2) {
+    a = {0.25, 0.25 - s3 / 6, 0.25 + s3 / 6, 0.25};
+    bb = {0.5, 0.5};
+    cc = {0.5 - s3 / 6, 0.5 + s3 / 6};
+  } else if (family == 1 && r == 3) {
+    a = {5.0 / 36,            2.0 / 9 - s15 / 15, 5.0 / 36 - s15 / 30,
+         5.0 / 36 + s15 / 24, 2.0 / 9,            5.0 / 36 - s15 / 24,
+         5.0 / 36 + s15 / 30, 2.0 / 9 + s15 / 15, 5.0 / 36};
+    bb = {5.0 / 18, 4.0 / 9, 5.0 / 18};
+    cc = {0.5 - s15 / 10, 0.5, 0.5 + s15 / 10};
+  } else if (family == 2 && r == 2) {
+    a = {0.5, -0.5, 0.5, 0.5};
+    bb = {0.5, 0.5};
+    cc = {0.0, 1.0};
+  } else if (family == 2 && r == 3) {
+    a = {1.0 / 6, -1.0 / 3, 1.0 / 6, 1.0 / 6, 5.0 / 12, -1.0 / 12, 1.0 / 6, 2.0 / 3, 1.0 / 6};
+    bb = {1.0 / 6, 2.0 / 3, 1.0 / 6};
+    cc = {0.0, 0.5, 1.0};
+  } else {
+    return fail(IRK_EINVAL, "unknown tableau (family, r)");
+  }
+  std::copy(a.begin(), a.end(), A);
+  std::copy(bb.begin(), bb.end(), b);
+  std::copy(cc.begin(), cc.end(), c);
+  return IRK_OK;
+}
+
+const char* irk_last_error(void) { return g_err.c_str(); }
+
+irk_status irk_mesh_p2_nodes(const irk_mesh_level* m, int64_t* nnodes, double* xyz) {
+  if (!m || !nnodes || !m->xyz || !m->cells) return fail(IRK_EINVAL, "null argument");
+  if ((m->dim != 2 && m->dim != 3) || m->nverts < m->dim + 1 || m->ncells < 1)
+    return fail(IRK_EINVAL, "bad mesh sizes");
+  for (int64_t i = 0; i < m->ncells * (m->dim + 1); ++i)
+    if (m->cells[i] < 0 || m->cells[i] >= m->nverts) return fail(IRK_EINVAL, "vertex index out of range");
+  HostLevel H;
+  try {
+    build_topology(H, m->dim, m->nverts, m->ncells, m->xyz, m->cells);
+  } catch (const std::bad_alloc&) {
+    return fail(IRK_ENOMEM, "host allocation failed");
+  }
+  *nnodes = H.nn;
+  if (xyz) {
+    const int d = H.dim;
+    for (int64_t n = 0; n < H.nn; ++n) {
+      if (n < H.nv) {
+        for (int i = 0; i < d; ++i) xyz[n * d + i] = H.xyz[n * d + i];
+      } else {
+        const int64_t a = H.edges[(n - H.nv) * 2], b = H.edges[(n - H.nv) * 2 + 1];
+        for (int i = 0; i < d; ++i) xyz[n * d + i] = 0.5 * (H.xyz[a * d + i] + H.xyz[b * d + i]);
+      }
+    }
+  }
+  return IRK_OK;
+}
+
+void irk_mg_destroy(irk_mg* h) {
+  if (!h) return;
+  for (void* p : h->allocations) (void)hipFree(p);
+  for (hipEvent_t e : {h->ev0, h->ev1, h->ev2, h->ev3})
+    if (e) (void)hipEventDestroy(e);
+  delete h;
+}
+
+static irk_status setup_impl(const irk_mesh_level* lv, int nlevels, const irk_tableau* tab, double dt,
+                             double nu, const double* wind, const irk_mg_opts* opt, hipStream_t s,
+                             irk_mg* h) {
+  const int dim = lv[0].dim;
+  const int r = tab->r;
+  h->dim = dim;
+  h->r = r;
+  h->nlevels = nlevels;
+  h->dt = dt;
+  h->nu = nu;
+  irk_mg_opts o;
+  irk_mg_default_opts(&o);
+  if (opt) o = *opt;
+  h->pre = o.pre;
+  h->post = o.post;
+  h->omega = o.omega;
+  h->weighting = o.weighting;
+  h->precision = o.precision;
+  for (int i = 0; i < r; ++i) {
+    h->b[i] = tab->b[i];
+    h->c[i] = tab->c[i];
+    for (int j = 0; j < r; ++j) {
+      h->A[i * r + j] = tab->A[i * r + j];
+      h->At[i * r + j] = tab->A[j * r + i];
+    }
+  }
+  // ---- host: topology, transfers, assembly, patches
+  h->host.resize(nlevels);
+  for (int l = 0; l < nlevels; ++l)
+    build_topology(h->host[l], dim, lv[l].nverts, lv[l].ncells, lv[l].xyz, lv[l].cells);
+  for (int l = 1; l < nlevels; ++l) {
+    std::string e = build_transfer(h->host[l - 1], h->host[l], lv[l].parent);
+    if (!e.empty()) return fail(IRK_EINVAL, "level " + std::to_string(l) + ": " + e);
+  }
+  std::vector<std::vector<double>> winds(nlevels);
+  if (wind) {
+    const HostLevel& Ft = h->host[nlevels - 1];
+    winds[nlevels - 1].assign(wind, wind + Ft.nn * dim);
+    for (int l = nlevels - 2; l >= 0; --l) {
+      const HostLevel& C = h->host[l];
+      const HostLevel& F = h->host[l + 1];
+      winds[l].resize(C.nn * dim);
+      for (int64_t n = 0; n < C.nn; ++n)
+        for (int i = 0; i < dim; ++i)
+          winds[l][n * dim + i] = winds[l + 1][F.coarse_node_to_fine_vertex[n] * dim + i];
+    }
+    for (double w : winds[nlevels - 1])
+      if (!std::isfinite(w)) return fail(IRK_EINVAL, "non-finite wind value");
+  }
+  for (int l = 0; l < nlevels; ++l) {
+    assemble_level(h->host[l], nu, wind ? &winds[l] : nullptr, l == nlevels - 1);
+    if (l >= 1) build_patches(h->host[l]);
+  }
+  // ---- device
+  const int VEC = h->precision == 0 ? 2 : 4;
+  h->dev.resize(nlevels);
+  for (int l = 0; l < nlevels; ++l) {
+    HostLevel& H = h->host[l];
+    DevLevel& D = h->dev[l];
+    D.dim = dim;
+    D.r = r;
+    D.nv = H.nv;
+    D.nfree = H.nfree;
+    D.offV = H.nfree * dim * r;
+    D.N = D.offV + H.nv * r;
+    CHK(upload(h, &D.s_ptr, H.s_ptr, s));
+    CHK(upload(h, &D.s_col, H.s_col, s));
+    CHK(upload(h, &D.b_ptr, H.b_ptr, s));
+    CHK(upload(h, &D.b_col, H.b_col, s));
+    CHK(upload(h, &D.bt_ptr, H.bt_ptr, s));
+    CHK(upload(h, &D.bt_col, H.bt_col, s));
+    if (l >= 1) {
+      CHK(upload(h, &D.pu_ptr, H.pu_ptr, s));
+      CHK(upload(h, &D.pu_col, H.pu_col, s));
+      CHK(upload(h, &D.put_ptr, H.put_ptr, s));
+      CHK(upload(h, &D.put_col, H.put_col, s));
+      CHK(upload(h, &D.pp_ptr, H.pp_ptr, s));
+      CHK(upload(h, &D.pp_col, H.pp_col, s));
+      CHK(upload(h, &D.ppt_ptr, H.ppt_ptr, s));
+      CHK(upload(h, &D.ppt_col, H.ppt_col, s));
+    }
+    if (l == nlevels - 1) {
+      CHK(upload(h, &D.mfa_ptr, H.mfa_ptr, s));
+      CHK(upload(h, &D.mfa_col, H.mfa_col, s));
+      CHK(upload(h, &D.mfa_val, H.mfa_val, s));
+      CHK(upload(h, &D.s_K1, H.s_K1, s));
+    }
+    // patches: sizes, offsets, local -> internal index, DOF -> slot lists, weights
+    std::vector<double> W(D.N, 1.0);
+    if (l >= 1) {
+      const int64_t np = H.nv;
+      D.npatch = np;
+      std::vector<int32_t> nloc(np), ld(np), nnv(np), gidx, gptr(D.N + 1, 0), gslot;
+      std::vector<int64_t> inv_off(np), slot_off(np);
+      int64_t io = 0, so = 0;
+      int maxn = 0;
+      for (int64_t p = 0; p < np; ++p) {
+        const int nn = H.pn_ptr[p + 1] - H.pn_ptr[p];
+        const int n = r * (dim * nn + 1);
+        nnv[p] = nn;
+        nloc[p] = n;
+        ld[p] = (n + VEC - 1) / VEC * VEC;
+        inv_off[p] = io;
+        slot_off[p] = so;
+        io += (int64_t)ld[p] * n;
+        so += n;
+        maxn = std::max(maxn, n);
+        for (int st = 0; st < r; ++st) {
+          for (int c = 0; c < dim; ++c)
+            for (int a = 0; a < nn; ++a)
+              gidx.push_back((int32_t)(((int64_t)H.pn_node[H.pn_ptr[p] + a] * dim + c) * r + st));
+          gidx.push_back((int32_t)(D.offV + p * r + st));
+        }
+      }
+      D.inv_elems = io;
+      D.slots = so;
+      D.max_nloc = maxn;
+      if (so > INT32_MAX || D.N > INT32_MAX) return fail(IRK_EINVAL, "problem too large for 32-bit patch indices");
+      for (int32_t g : gidx) gptr[g + 1]++;
+      for (int64_t g = 0; g < D.N; ++g) gptr[g + 1] += gptr[g];
+      gslot.resize(so);
+      std::vector<int32_t> fillp(gptr.begin(), gptr.end() - 1);
+      for (int64_t q = 0; q < so; ++q) gslot[fillp[gidx[q]]++] = (int32_t)q;
+      for (int64_t g = 0; g < D.N; ++g) {
+        const int cnt = gptr[g + 1] - gptr[g];
+        if (cnt == 0) return fail(IRK_EINVAL, "a DOF is covered by no patch");
+        W[g] = h->weighting ? 1.0 / cnt : 1.0;
+      }
+      std::vector<int32_t> sched(np);
+      std::iota(sched.begin(), sched.end(), 0);
+      std::stable_sort(sched.begin(), sched.end(), [&](int32_t a, int32_t b) { return nloc[a] > nloc[b]; });
+      CHK(upload(h, &D.p_nloc, nloc, s));
+      CHK(upload(h, &D.p_ld, ld, s));
+      CHK(upload(h, &D.p_nn, nnv, s));
+      CHK(upload(h, &D.p_inv_off, inv_off, s));
+      CHK(upload(h, &D.p_slot_off, slot_off, s));
+      CHK(upload(h, &D.p_gidx, gidx, s));
+      CHK(upload(h, &D.gat_ptr, gptr, s));
+      CHK(upload(h, &D.gat_slot, gslot, s));
+      CHK(upload(h, &D.sched, sched, s));
+      CHK(upload(h, &D.pvv_ptr, H.pvv_ptr, s));
+      CHK(upload(h, &D.pvv, H.pvv, s));
+      CHK(upload(h, &D.pvp, H.pvp, s));
+      CHK(upload(h, &D.pn_ptr, H.pn_ptr, s));
+    }
+    CHK(upload_ops<double>(h, H, D, D.d64, W, s));
+    if (h->precision == 1) CHK(upload_ops<float>(h, H, D, D.d32, W, s));
+    const size_t es = h->precision == 0 ? sizeof(double) : sizeof(float);
+    double* tmp;
+    for (void** buf : {&D.b, &D.x, &D.res}) {
+      CHK(dalloc(h, &tmp, (D.N * es + 7) / 8));
+      *buf = tmp;
+    }
+    if (l >= 1) {
+      CHK(dalloc(h, &tmp, (D.slots * es + 7) / 8));
+      D.Y = tmp;
+      CHK(dalloc(h, &tmp, (D.inv_elems * es + 7) / 8));
+      D.inv = tmp;
+    }
+  }
+  // ---- patch factorisation on the GPU
+  int* dfail;
+  CHK(dalloc(h, &dfail, 1));
+  h->ex.flag = dfail;
+  HIPCHK(hipMemsetAsync(dfail, 0, sizeof(int), s));
+  for (int l = 1; l < nlevels; ++l) {
+    DevLevel& D = h->dev[l];
+    const size_t es = h->precision == 0 ? sizeof(double) : sizeof(float);
+    if ((size_t)D.max_nloc * D.max_nloc * es + D.max_nloc * (es + 4) + 64 > 160 * 1024)
+      return fail(IRK_EINVAL, "patch of " + std::to_string(D.max_nloc) +
+                                  " unknowns exceeds the LDS factorisation limit");
+    if (h->precision == 0) HIPCHK(k::patch_factor<double>(D, D.d64, h->A, dt, dfail, s));
+    else HIPCHK(k::patch_factor<float>(D, D.d32, h->A, dt, dfail, s));
+  }
+  int hfail = 0;
+  HIPCHK(hipMemcpyAsync(&hfail, dfail, sizeof(int), hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  if (hfail) return fail(IRK_ESINGULAR, "zero pivot in a patch factorisation");
+  // ---- coarse inverse (and of the transpose)
+  {
+    std::vector<double> inv, invT;
+    if (!coarse_inverse(h->host[0], r, h->A, dt, inv))
+      return fail(IRK_ESINGULAR, "singular coarse operator");
+    const int64_t N0 = h->dev[0].N;
+    invT.resize(inv.size());
+    for (int64_t i = 0; i < N0; ++i)
+      for (int64_t j = 0; j < N0; ++j) invT[j * N0 + i] = inv[i * N0 + j];
+    CHK(upload(h, &h->coarse_inv, inv, s));
+    CHK(upload(h, &h->coarse_invT, invT, s));
+    CHK(dalloc(h, &h->cb, N0));
+    CHK(dalloc(h, &h->cx, N0));
+    std::vector<int64_t> pins(r);
+    for (int st = 0; st < r; ++st) pins[st] = h->dev[0].offV + st;
+    CHK(upload(h, &h->ex.pins, pins, s));
+  }
+  // ---- Krylov and reduction workspace
+  const int64_t N = h->dev[nlevels - 1].N;
+  CHK(dalloc(h, &h->kw, N));
+  CHK(dalloc(h, &h->kF, N));
+  CHK(dalloc(h, &h->kx, N));
+  CHK(dalloc(h, &h->kr, N));
+  CHK(dalloc(h, &h->scal, 16));
+  CHK(dalloc(h, &h->partials, 1024));
+  CHK(dalloc(h, &h->hbuf, 1024 + 2));
+  for (hipEvent_t* e : {&h->ev0, &h->ev1, &h->ev2, &h->ev3}) HIPCHK(hipEventCreate(e));
+  HIPCHK(hipStreamSynchronize(s));
+  return IRK_OK;
+}
+
+irk_status irk_mg_setup(const irk_mesh_level* lv, int nlevels, const irk_tableau* tab, double dt,
+                        double nu, const double* wind, const irk_mg_opts* opt, void* stream,
+                        irk_mg** out) {
+  if (!out) return fail(IRK_EINVAL, "out is NULL");
+  *out = nullptr;
+  if (!lv || nlevels < 1 || nlevels > 16) return fail(IRK_EINVAL, "need 1..16 mesh levels");
+  if (!tab || tab->r < 1 || tab->r > kMaxStages || !tab->A || !tab->b || !tab->c)
+    return fail(IRK_EINVAL, "tableau must have 1 <= r <= 4 and non-null A, b, c");
+  for (int i = 0; i < tab->r * tab->r; ++i)
+    if (!std::isfinite(tab->A[i])) return fail(IRK_EINVAL, "non-finite tableau entry");
+  if (!(dt > 0) || !std::isfinite(dt)) return fail(IRK_EINVAL, "dt must be positive and finite");
+  if (!(nu > 0) || !std::isfinite(nu)) return fail(IRK_EINVAL, "nu must be positive and finite");
+  if (opt) {
+    if (opt->pre < 0 || opt->post < 0 || opt->pre > 64 || opt->post > 64)
+      return fail(IRK_EINVAL, "sweep counts must be in 0..64");
+    if (!(opt->omega > 0) || !std::isfinite(opt->omega)) return fail(IRK_EINVAL, "omega must be positive");
+    if (opt->weighting != 0 && opt->weighting != 1) return fail(IRK_EINVAL, "weighting must be 0 or 1");
+    if (opt->precision != 0 && opt->precision != 1) return fail(IRK_EINVAL, "precision must be 0 or 1");
+  }
+  const int dim = lv[0].dim;
+  if (dim != 2 && dim != 3) return fail(IRK_EINVAL, "dim must be 2 or 3");
+  for (int l = 0; l < nlevels; ++l) {
+    const irk_mesh_level& m = lv[l];
+    if (m.dim != dim) return fail(IRK_EINVAL, "all levels must have the same dim");
+    if (m.nverts < dim + 1 || m.ncells < 1 || !m.xyz || !m.cells)
+      return fail(IRK_EINVAL, "level " + std::to_string(l) + ": empty mesh or null arrays");
+    if (m.nverts > (1LL << 30) || m.ncells > (1LL << 30)) return fail(IRK_EINVAL, "mesh too large");
+    if (l > 0 && !m.parent) return fail(IRK_EINVAL, "level " + std::to_string(l) + ": parent is NULL");
+    if (l > 0 && m.ncells != lv[l - 1].ncells * (dim == 2 ? 4 : 8))
+      return fail(IRK_EINVAL, "level " + std::to_string(l) + " is not a uniform refinement of level " +
+                                  std::to_string(l - 1));
+    for (int64_t i = 0; i < m.ncells * (dim + 1); ++i)
+      if (m.cells[i] < 0 || m.cells[i] >= m.nverts)
+        return fail(IRK_EINVAL, "level " + std::to_string(l) + ": vertex index out of range");
+    for (int64_t i = 0; i < m.nverts * dim; ++i)
+      if (!std::isfinite(m.xyz[i])) return fail(IRK_EINVAL, "non-finite coordinate");
+    if (l > 0)
+      for (int64_t c = 0; c < m.ncells; ++c)
+        if (m.parent[c] < 0 || m.parent[c] >= lv[l - 1].ncells)
+          return fail(IRK_EINVAL, "level " + std::to_string(l) + ": parent index out of range");
+  }
+  irk_mg* h = new (std::nothrow) irk_mg();
+  if (!h) return fail(IRK_ENOMEM, "handle allocation failed");
+  irk_status st;
+  try {
+    st = setup_impl(lv, nlevels, tab, dt, nu, wind, opt, S(stream), h);
+  } catch (const std::bad_alloc&) {
+    st = fail(IRK_ENOMEM, "host allocation failed during setup");
+  } catch (const std::exception& e) {
+    st = fail(IRK_EINVAL, std::string("setup failed: ") + e.what());
+  }
+  if (st != IRK_OK) {
+    irk_mg_destroy(h);
+    return st;
+  }
+  *out = h;
+  g_err.clear();
+  return IRK_OK;
+}
+
+int64_t irk_mg_ndofs(const irk_mg* h, int level) {
+  if (!h) return -1;
+  if (level < 0) level = h->nlevels - 1;
+  if (level >= h->nlevels) return -1;
+  return h->dev[level].N;
+}
+
+irk_status irk_mg_sizes(const irk_mg* hc, int level, int64_t* out) {
+  irk_mg* h = const_cast<irk_mg*>(hc);
+  CHK(check_level(h, level));
+  if (!out) return fail(IRK_EINVAL, "out is NULL");
+  const HostLevel& H = h->host[level];
+  out[0] = H.nv;
+  out[1] = H.nn;
+  out[2] = H.nfree;
+  out[3] = H.dim * H.nfree + H.nv;
+  out[4] = h->nlevels;
+  return IRK_OK;
+}
+
+irk_status irk_mg_p2_nodes(const irk_mg* hc, int level, double* xyz, int64_t* free_nodes) {
+  irk_mg* h = const_cast<irk_mg*>(hc);
+  CHK(check_level(h, level));
+  const HostLevel& H = h->host[level];
+  const int d = H.dim;
+  if (xyz)
+    for (int64_t n = 0; n < H.nn; ++n) {
+      if (n < H.nv) {
+        for (int i = 0; i < d; ++i) xyz[n * d + i] = H.xyz[n * d + i];
+      } else {
+        const int64_t a = H.edges[(n - H.nv) * 2], b = H.edges[(n - H.nv) * 2 + 1];
+        for (int i = 0; i < d; ++i) xyz[n * d + i] = 0.5 * (H.xyz[a * d + i] + H.xyz[b * d + i]);
+      }
+    }
+  if (free_nodes)
+    for (int64_t i = 0; i < H.nfree; ++i) free_nodes[i] = H.node_of_free[i];
+  return IRK_OK;
+}
+
+irk_status irk_mg_apply(irk_mg* h, const double* x, double* y, int transpose, void* stream) {
+  return irk_level_apply(h, -1, transpose, x, y, stream);
+}
+
+irk_status irk_mg_vcycle(irk_mg* h, const double* r, double* z, void* stream) {
+  CHK(check_handle(h));
+  if (!r || !z) return fail(IRK_EINVAL, "null vector");
+  if (r == z) return fail(IRK_EINVAL, "r and z may not alias");
+  DevLevel& L = h->dev[h->nlevels - 1];
+  hipStream_t s = S(stream);
+  HIPCHK(k::to_internal<double>(L, r, h->kr, s));
+  CHK(precondition(h, h->kr, h->kF, false, s));
+  HIPCHK(k::to_abi<double>(L, h->kF, z, s));
+  return IRK_OK;
+}
+
+irk_status irk_mg_vcycle_transpose(irk_mg* h, const double* r, double* z, void* stream) {
+  CHK(check_handle(h));
+  if (!r || !z) return fail(IRK_EINVAL, "null vector");
+  if (r == z) return fail(IRK_EINVAL, "r and z may not alias");
+  DevLevel& L = h->dev[h->nlevels - 1];
+  hipStream_t s = S(stream);
+  HIPCHK(k::to_internal<double>(L, r, h->kr, s));
+  CHK(precondition(h, h->kr, h->kF, true, s));
+  HIPCHK(k::to_abi<double>(L, h->kF, z, s));
+  return IRK_OK;
+}
+
+irk_status irk_fgmres_solve(irk_mg* h, const double* F, double* k, double rtol, int maxit, int restart,
+                            irk_solve_info* info, void* stream) {
+  CHK(check_handle(h));
+  return fgmres(h, F, k, rtol, maxit, restart, info, false, S(stream));
+}
+
+irk_status irk_adjoint_solve(irk_mg* h, const double* G, double* lam, double rtol, int maxit, int restart,
+                             irk_solve_info* info, void* stream) {
+  CHK(check_handle(h));
+  return fgmres(h, G, lam, rtol, maxit, restart, info, true, S(stream));
+}
+
+irk_status irk_rhs(irk_mg* h, const double* f, const double* state, double* F, void* stream) {
+  CHK(check_handle(h));
+  if (!f || !state || !F) return fail(IRK_EINVAL, "null vector");
+  const int top = h->nlevels - 1;
+  HIPCHK(k::rhs(h->dev[top], h->host[top].nn, f, state, F, S(stream)));
+  return IRK_OK;
+}
+
+irk_status irk_update(irk_mg* h, const double* kv, double* state, void* stream) {
+  CHK(check_handle(h));
+  if (!kv || !state) return fail(IRK_EINVAL, "null vector");
+  HIPCHK(k::update(h->dev[h->nlevels - 1], h->b, h->dt, kv, state, S(stream)));
+  return IRK_OK;
+}
+
+irk_status irk_level_apply(irk_mg* h, int level, int transpose, const double* x, double* y,
+                           void* stream) {
+  CHK(check_level(h, level));
+  if (!x || !y) return fail(IRK_EINVAL, "null vector");
+  if (x == y) return fail(IRK_EINVAL, "x and y may not alias");
+  DevLevel& L = h->dev[level];
+  hipStream_t s = S(stream);
+  double* tmp_in = h->kw;  // finest-level FGMRES scratch, large enough for any level
+  double* tmp_out = h->kr;
+  HIPCHK(k::to_internal<double>(L, x, tmp_in, s));
+  DevOps<double> o = L.d64;
+  if (transpose) o.s_L = o.s_Lt;
+  HIPCHK(k::residual<double>(L, o, transpose ? h->At : h->A, h->dt, nullptr, tmp_in, tmp_out, s));
+  HIPCHK(k::to_abi<double>(L, tmp_out, y, s));
+  return IRK_OK;
+}
+
+irk_status irk_level_sweep(irk_mg* h, int level, int transpose, const double* F, double* kv,
+                           void* stream) {
+  CHK(check_level(h, level));
+  if (level < 1) return fail(IRK_EINVAL, "the coarsest level has no patches");
+  if (!F || !kv) return fail(IRK_EINVAL, "null vector");
+  if (h->precision == 0) return level_sweep_T<double>(h, level, transpose, F, kv, S(stream));
+  return level_sweep_T<float>(h, level, transpose, F, kv, S(stream));
+}
+
+irk_status irk_level_restrict(irk_mg* h, int level, const double* xf, double* xc, void* stream) {
+  CHK(check_level(h, level));
+  if (level < 1) return fail(IRK_EINVAL, "level must be >= 1");
+  if (!xf || !xc) return fail(IRK_EINVAL, "null vector");
+  DevLevel& F = h->dev[level];
+  DevLevel& C = h->dev[level - 1];
+  hipStream_t s = S(stream);
+  HIPCHK(k::to_internal<double>(F, xf, h->kw, s));
+  HIPCHK(k::restrict_<double>(F, C, F.d64, h->kw, h->kr, s));
+  HIPCHK(k::to_abi<double>(C, h->kr, xc, s));
+  return IRK_OK;
+}
+
+irk_status irk_level_prolong(irk_mg* h, int level, const double* xc, double* xf, void* stream) {
+  CHK(check_level(h, level));
+  if (level < 1) return fail(IRK_EINVAL, "level must be >= 1");
+  if (!xf || !xc) return fail(IRK_EINVAL, "null vector");
+  DevLevel& F = h->dev[level];
+  DevLevel& C = h->dev[level - 1];
+  hipStream_t s = S(stream);
+  HIPCHK(k::to_internal<double>(C, xc, h->kw, s));
+  HIPCHK(k::to_internal<double>(F, xf, h->kr, s));
+  HIPCHK(k::prolong_add<double>(F, C, F.d64, h->kw, h->kr, s));
+  HIPCHK(k::to_abi<double>(F, h->kr, xf, s));
+  return IRK_OK;
+}
+
+irk_status irk_coarse_solve(irk_mg* h, int transpose, const double* b, double* x, void* stream) {
+  CHK(check_handle(h));
+  if (!b || !x) return fail(IRK_EINVAL, "null vector");
+  DevLevel& L = h->dev[0];
+  hipStream_t s = S(stream);
+  HIPCHK(k::to_internal<double>(L, b, h->cb, s));
+  HIPCHK(k::coarse_gemv(transpose ? h->coarse_invT : h->coarse_inv, L.N, h->cb, h->cx, h->ex.pins, h->r, s));
+  HIPCHK(k::to_abi<double>(L, h->cx, x, s));
+  return IRK_OK;
+}
+
+}  // extern "C"

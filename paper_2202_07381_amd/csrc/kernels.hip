@@ -1,0 +1,838 @@
+// HIP kernels of libirkmg for gfx950 (CDNA4, 64-wide wavefronts).
+//
+//  residual       r = F - J x (or y = J x) for the Kronecker stage operator
+//                 J = I_r (x) [M 0;0 0] + dt A (x) [L B; B^T 0]   (Sec. 3.1).
+//                 One CSR traversal of the scalar P2 blocks serves all dim*r values
+//                 of a node; the r x r stage mixing is applied once per row.
+//  patch_factor   A_v = R_v J R_v^T assembled in LDS and inverted by Gauss--Jordan with
+//                 partial pivoting (Sec. 4.2 patch solves), stored column-major.
+//  patch_apply    one wavefront per patch: gather R_v res, stream the stored inverse
+//                 column by column (each column one coalesced 16-byte-per-lane load),
+//                 write the local correction to the patch's private output slots.
+//  gather_update  owner gather: every DOF sums its patches' slots in a fixed order and
+//                 applies x += omega W sum (deterministic, no atomics).
+//  restrict_ / prolong_add   I_r (x) P and its transpose (Sec. 4.1), node-chunked CSR.
+//  coarse_gemv    dense coarse solve with the stored inverse.
+//  dot / axpy / ... deterministic fixed-order reductions for FGMRES.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+
+#include "irk_internal.h"
+
+namespace irk {
+namespace k {
+namespace {
+
+constexpr int kBlock = 256;
+constexpr int kReduceBlocks = 512;
+
+inline unsigned blocks_for(int64_t n, int block = kBlock) {
+  int64_t b = (n + block - 1) / block;
+  return (unsigned)std::max<int64_t>(1, b);
+}
+
+template <typename T>
+struct Coef {
+  T v[kMaxStages * kMaxStages];
+};
+
+template <typename T, int R>
+Coef<T> scaled(const double* A, double dt) {
+  Coef<T> c{};
+  for (int i = 0; i < R * R; ++i) c.v[i] = (T)(dt * A[i]);
+  return c;
+}
+
+// ------------------------------------------------------------------------ residual
+template <int D, int R, typename T>
+__global__ __launch_bounds__(kBlock) void k_residual(
+    int64_t nfree, int64_t nv, int64_t offV, const int32_t* __restrict__ s_ptr,
+    const int32_t* __restrict__ s_col, const T* __restrict__ sM, const T* __restrict__ sL,
+    const int32_t* __restrict__ b_ptr, const int32_t* __restrict__ b_col,
+    const T* __restrict__ b_val, const int32_t* __restrict__ bt_ptr,
+    const int32_t* __restrict__ bt_col, const T* __restrict__ bt_val, Coef<T> dtA,
+    const T* __restrict__ F, const T* __restrict__ x, T* __restrict__ y) {
+  const int64_t row = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  constexpr int DR = D * R;
+  if (row < nfree) {
+    T am[DR], al[DR];
+#pragma unroll
+    for (int q = 0; q < DR; ++q) am[q] = al[q] = T(0);
+    const int32_t p0 = s_ptr[row], p1 = s_ptr[row + 1];
+    for (int32_t p = p0; p < p1; ++p) {
+      const int64_t j = s_col[p];
+      const T m = sM[p], l = sL[p];
+      const T* xj = x + j * DR;
+#pragma unroll
+      for (int q = 0; q < DR; ++q) {
+        const T xv = xj[q];
+        am[q] += m * xv;
+        al[q] += l * xv;
+      }
+    }
+    const int32_t q0 = b_ptr[row], q1 = b_ptr[row + 1];
+    for (int32_t p = q0; p < q1; ++p) {
+      const T* xp = x + offV + (int64_t)b_col[p] * R;
+      T pv[R];
+#pragma unroll
+      for (int t = 0; t < R; ++t) pv[t] = xp[t];
+#pragma unroll
+      for (int c = 0; c < D; ++c) {
+        const T bv = b_val[(int64_t)p * D + c];
+#pragma unroll
+        for (int t = 0; t < R; ++t) al[c * R + t] += bv * pv[t];
+      }
+    }
+#pragma unroll
+    for (int c = 0; c < D; ++c)
+#pragma unroll
+      for (int s = 0; s < R; ++s) {
+        T acc = am[c * R + s];
+#pragma unroll
+        for (int t = 0; t < R; ++t) acc += dtA.v[s * R + t] * al[c * R + t];
+        const int64_t o = row * DR + c * R + s;
+        y[o] = F ? F[o] - acc : acc;
+      }
+  } else if (row < nfree + nv) {
+    const int64_t v = row - nfree;
+    T a[R];
+#pragma unroll
+    for (int t = 0; t < R; ++t) a[t] = T(0);
+    const int32_t p0 = bt_ptr[v], p1 = bt_ptr[v + 1];
+    for (int32_t p = p0; p < p1; ++p) {
+      const T* xi = x + (int64_t)bt_col[p] * DR;
+#pragma unroll
+      for (int c = 0; c < D; ++c) {
+        const T bv = bt_val[(int64_t)p * D + c];
+#pragma unroll
+        for (int t = 0; t < R; ++t) a[t] += bv * xi[c * R + t];
+      }
+    }
+#pragma unroll
+    for (int s = 0; s < R; ++s) {
+      T acc = T(0);
+#pragma unroll
+      for (int t = 0; t < R; ++t) acc += dtA.v[s * R + t] * a[t];
+      const int64_t o = offV + v * R + s;
+      y[o] = F ? F[o] - acc : acc;
+    }
+  }
+}
+
+// ------------------------------------------------------------------ patch factorise
+// One workgroup per patch, matrix in dynamic LDS (row-major n x n).
+template <int D, int R, typename T>
+__global__ __launch_bounds__(kBlock) void k_patch_factor(
+    int64_t npatch, const int32_t* __restrict__ pn_ptr, const int32_t* __restrict__ pvv_ptr,
+    const int32_t* __restrict__ pvv, const int32_t* __restrict__ pvp,
+    const int32_t* __restrict__ p_ld, const int64_t* __restrict__ p_inv_off,
+    const T* __restrict__ sM, const T* __restrict__ sL, const T* __restrict__ b_val,
+    Coef<T> dtA, T* __restrict__ inv, int* __restrict__ fail) {
+  extern __shared__ unsigned char smem_raw[];
+  const int64_t p = blockIdx.x;
+  if (p >= npatch) return;
+  const int nn = pn_ptr[p + 1] - pn_ptr[p];
+  const int sb = D * nn + 1;  // per-stage block size
+  const int n = R * sb;
+  T* Am = reinterpret_cast<T*>(smem_raw);
+  T* colk = Am + (size_t)n * n;
+  int* perm = reinterpret_cast<int*>(colk + n);
+  __shared__ int s_piv;
+  __shared__ T s_best;
+  const int tid = threadIdx.x;
+  for (int e = tid; e < n * n; e += blockDim.x) Am[e] = T(0);
+  __syncthreads();
+  // velocity-velocity: delta_st M_ab + dt a_st L_ab on every component
+  const int32_t v0 = pvv_ptr[p], v1 = pvv_ptr[p + 1];
+  for (int32_t e = v0 + tid; e < v1; e += blockDim.x) {
+    const int la = pvv[3 * e], lb = pvv[3 * e + 1], pos = pvv[3 * e + 2];
+    const T m = sM[pos], l = sL[pos];
+    for (int c = 0; c < D; ++c)
+      for (int s = 0; s < R; ++s)
+        for (int t = 0; t < R; ++t)
+          Am[(s * sb + c * nn + la) * n + (t * sb + c * nn + lb)] =
+              (s == t ? m : T(0)) + dtA.v[s * R + t] * l;
+  }
+  // velocity-pressure couplings with the patch vertex: dt a_st B and dt a_st B^T
+  const int32_t n0 = pn_ptr[p];
+  for (int la = tid; la < nn; la += blockDim.x) {
+    const int pos = pvp[n0 + la];
+    if (pos < 0) continue;
+    for (int c = 0; c < D; ++c) {
+      const T bv = b_val[(int64_t)pos * D + c];
+      for (int s = 0; s < R; ++s)
+        for (int t = 0; t < R; ++t) {
+          const T val = dtA.v[s * R + t] * bv;
+          Am[(s * sb + c * nn + la) * n + (t * sb + D * nn)] = val;
+          Am[(s * sb + D * nn) * n + (t * sb + c * nn + la)] = val;
+        }
+    }
+  }
+  __syncthreads();
+  // in-place Gauss--Jordan with partial pivoting (ties -> smallest row index)
+  for (int kk = 0; kk < n; ++kk) {
+    if (tid < 64) {
+      T best = T(-1);
+      int bi = kk;
+      for (int i = kk + tid; i < n; i += 64) {
+        const T a = fabs(Am[i * n + kk]);
+        if (a > best) {
+          best = a;
+          bi = i;
+        }
+      }
+      for (int off = 32; off > 0; off >>= 1) {
+        const T ob = __shfl_xor(best, off, 64);
+        const int oi = __shfl_xor(bi, off, 64);
+        if (ob > best || (ob == best && oi < bi)) {
+          best = ob;
+          bi = oi;
+        }
+      }
+      if (tid == 0) {
+        s_piv = bi;
+        s_best = best;
+        perm[kk] = bi;
+      }
+    }
+    __syncthreads();
+    const int piv = s_piv;
+    if (!(s_best > T(0))) {
+      if (tid == 0) atomicMax(fail, 1);
+      return;  // uniform across the workgroup
+    }
+    if (piv != kk)
+      for (int j = tid; j < n; j += blockDim.x) {
+        const T t = Am[kk * n + j];
+        Am[kk * n + j] = Am[piv * n + j];
+        Am[piv * n + j] = t;
+      }
+    __syncthreads();
+    const T ip = T(1) / Am[kk * n + kk];
+    for (int i = tid; i < n; i += blockDim.x) colk[i] = Am[i * n + kk];
+    __syncthreads();
+    for (int j = tid; j < n; j += blockDim.x) Am[kk * n + j] = (j == kk ? ip : Am[kk * n + j] * ip);
+    __syncthreads();
+    for (int e = tid; e < n * n; e += blockDim.x) {
+      const int i = e / n, j = e - i * n;
+      if (i == kk) continue;
+      const T base = (j == kk) ? T(0) : Am[e];
+      Am[e] = base - colk[i] * Am[kk * n + j];
+    }
+    __syncthreads();
+  }
+  for (int kk = n - 1; kk >= 0; --kk) {
+    const int q = perm[kk];
+    if (q != kk)
+      for (int i = tid; i < n; i += blockDim.x) {
+        const T t = Am[i * n + kk];
+        Am[i * n + kk] = Am[i * n + q];
+        Am[i * n + q] = t;
+      }
+    __syncthreads();
+  }
+  const int ld = p_ld[p];
+  T* out = inv + p_inv_off[p];
+  for (int e = tid; e < n * ld; e += blockDim.x) {
+    const int j = e / ld, i = e - j * ld;
+    out[e] = i < n ? Am[i * n + j] : T(0);
+  }
+}
+
+// ------------------------------------------------------------------- patch apply
+template <typename T>
+struct Vec16;
+template <>
+struct Vec16<double> {
+  using type = double2;
+  static constexpr int n = 2;
+};
+template <>
+struct Vec16<float> {
+  using type = float4;
+  static constexpr int n = 4;
+};
+
+template <typename V, typename T>
+__device__ inline void vload(const T* p, T* out);
+template <>
+__device__ inline void vload<double2, double>(const double* p, double* o) {
+  const double2 v = *reinterpret_cast<const double2*>(p);
+  o[0] = v.x;
+  o[1] = v.y;
+}
+template <>
+__device__ inline void vload<float4, float>(const float* p, float* o) {
+  const float4 v = *reinterpret_cast<const float4*>(p);
+  o[0] = v.x;
+  o[1] = v.y;
+  o[2] = v.z;
+  o[3] = v.w;
+}
+
+constexpr int kWaves = 4;  // wavefronts (patches) per workgroup
+
+// One wavefront per patch.  Lane l owns rows [rb*64*VEC + l*VEC, +VEC) of each row
+// block rb.  Non-transposed: y = Ainv x streams column j with one 16-byte load per
+// lane.  Transposed: y_j = column_j . x, a wave reduction per column.
+template <typename T, int RB, int NMAX>
+__global__ __launch_bounds__(kWaves * 64) void k_patch_apply(
+    int64_t npatch, const int32_t* __restrict__ sched, const int32_t* __restrict__ p_nloc,
+    const int32_t* __restrict__ p_ld, const int64_t* __restrict__ p_inv_off,
+    const int64_t* __restrict__ p_slot_off, const int32_t* __restrict__ gidx,
+    const T* __restrict__ inv, const T* __restrict__ res, const T* __restrict__ W,
+    T* __restrict__ Y, int transpose) {
+  using VT = typename Vec16<T>::type;
+  constexpr int VEC = Vec16<T>::n;
+  __shared__ T xs[kWaves][NMAX];
+  const int lane = threadIdx.x & 63;
+  const int wave = threadIdx.x >> 6;
+  const int64_t idx = (int64_t)blockIdx.x * kWaves + wave;
+  if (idx >= npatch) return;  // whole wavefront exits; no workgroup barrier below
+  const int p = sched[idx];
+  const int n = p_nloc[p];
+  const int ld = p_ld[p];
+  const int64_t so = p_slot_off[p];
+  const T* __restrict__ Ap = inv + p_inv_off[p];
+  for (int i = lane; i < n; i += 64) {
+    const int32_t g = gidx[so + i];
+    xs[wave][i] = W ? res[g] * W[g] : res[g];
+  }
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  if (!transpose) {
+    T acc[RB][VEC];
+#pragma unroll
+    for (int b = 0; b < RB; ++b)
+#pragma unroll
+      for (int v = 0; v < VEC; ++v) acc[b][v] = T(0);
+    int j = 0;
+    for (; j + 4 <= n; j += 4) {
+      T a[4][RB][VEC];
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+#pragma unroll
+        for (int b = 0; b < RB; ++b) {
+          const int r0 = b * 64 * VEC + lane * VEC;
+          if (r0 < n) vload<VT, T>(Ap + (int64_t)(j + u) * ld + r0, a[u][b]);
+          else
+#pragma unroll
+            for (int v = 0; v < VEC; ++v) a[u][b][v] = T(0);
+        }
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const T xj = xs[wave][j + u];
+#pragma unroll
+        for (int b = 0; b < RB; ++b)
+#pragma unroll
+          for (int v = 0; v < VEC; ++v) acc[b][v] += a[u][b][v] * xj;
+      }
+    }
+    for (; j < n; ++j) {
+      const T xj = xs[wave][j];
+#pragma unroll
+      for (int b = 0; b < RB; ++b) {
+        const int r0 = b * 64 * VEC + lane * VEC;
+        if (r0 < n) {
+          T a[VEC];
+          vload<VT, T>(Ap + (int64_t)j * ld + r0, a);
+#pragma unroll
+          for (int v = 0; v < VEC; ++v) acc[b][v] += a[v] * xj;
+        }
+      }
+    }
+#pragma unroll
+    for (int b = 0; b < RB; ++b)
+#pragma unroll
+      for (int v = 0; v < VEC; ++v) {
+        const int row = b * 64 * VEC + lane * VEC + v;
+        if (row < n) Y[so + row] = acc[b][v];
+      }
+  } else {
+    for (int j = 0; j < n; ++j) {
+      T part = T(0);
+#pragma unroll
+      for (int b = 0; b < RB; ++b) {
+        const int r0 = b * 64 * VEC + lane * VEC;
+        if (r0 < n) {
+          T a[VEC];
+          vload<VT, T>(Ap + (int64_t)j * ld + r0, a);
+#pragma unroll
+          for (int v = 0; v < VEC; ++v)
+            if (r0 + v < n) part += a[v] * xs[wave][r0 + v];
+        }
+      }
+#pragma unroll
+      for (int off = 32; off > 0; off >>= 1) part += __shfl_xor(part, off, 64);
+      if (lane == 0) Y[so + j] = part;
+    }
+  }
+}
+
+// ------------------------------------------------------------------ gather update
+// mode 0: x = omega*W*s   1: x += omega*W*s   2: x = omega*s   3: x += omega*s
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_gather_update(int64_t N, const int32_t* __restrict__ gptr,
+                                                          const int32_t* __restrict__ gslot,
+                                                          const T* __restrict__ Y,
+                                                          const T* __restrict__ W, T omega,
+                                                          int mode, T* __restrict__ x) {
+  const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= N) return;
+  T s = T(0);
+  const int32_t q1 = gptr[g + 1];
+  for (int32_t q = gptr[g]; q < q1; ++q) s += Y[gslot[q]];
+  T c = omega * s;
+  if (mode < 2) c *= W[g];
+  x[g] = (mode & 1) ? x[g] + c : c;
+}
+
+// ---------------------------------------------------------------------- transfers
+template <int D, int R, typename T>
+__global__ __launch_bounds__(kBlock) void k_spmv_nodes(
+    int64_t nrow_u, int64_t nrow_p, int64_t out_offV, int64_t in_offV,
+    const int32_t* __restrict__ u_ptr, const int32_t* __restrict__ u_col,
+    const T* __restrict__ u_val, const int32_t* __restrict__ p_ptr,
+    const int32_t* __restrict__ p_col, const T* __restrict__ p_val, const T* __restrict__ in,
+    T* __restrict__ out, int add) {
+  const int64_t row = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  constexpr int DR = D * R;
+  if (row < nrow_u) {
+    T acc[DR];
+#pragma unroll
+    for (int q = 0; q < DR; ++q) acc[q] = T(0);
+    for (int32_t p = u_ptr[row]; p < u_ptr[row + 1]; ++p) {
+      const T w = u_val[p];
+      const T* xi = in + (int64_t)u_col[p] * DR;
+#pragma unroll
+      for (int q = 0; q < DR; ++q) acc[q] += w * xi[q];
+    }
+#pragma unroll
+    for (int q = 0; q < DR; ++q) {
+      const int64_t o = row * DR + q;
+      out[o] = add ? out[o] + acc[q] : acc[q];
+    }
+  } else if (row < nrow_u + nrow_p) {
+    const int64_t v = row - nrow_u;
+    T acc[R];
+#pragma unroll
+    for (int q = 0; q < R; ++q) acc[q] = T(0);
+    for (int32_t p = p_ptr[v]; p < p_ptr[v + 1]; ++p) {
+      const T w = p_val[p];
+      const T* xi = in + in_offV + (int64_t)p_col[p] * R;
+#pragma unroll
+      for (int q = 0; q < R; ++q) acc[q] += w * xi[q];
+    }
+#pragma unroll
+    for (int q = 0; q < R; ++q) {
+      const int64_t o = out_offV + v * R + q;
+      out[o] = add ? out[o] + acc[q] : acc[q];
+    }
+  }
+}
+
+// ------------------------------------------------------------------- coarse solve
+__global__ __launch_bounds__(kBlock) void k_coarse_gemv(const double* __restrict__ inv, int64_t N,
+                                                        const double* __restrict__ b,
+                                                        double* __restrict__ x) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= N) return;
+  double acc = 0;
+  for (int64_t j = 0; j < N; ++j) acc += inv[j * N + i] * b[j];
+  x[i] = acc;
+}
+
+__global__ void k_zero_pins(double* b, const int64_t* pins, int np) {
+  const int i = threadIdx.x;
+  if (i < np) b[pins[i]] = 0.0;
+}
+
+// ------------------------------------------------------------------------ layouts
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_permute(int64_t N, int64_t offV, int64_t nfree,
+                                                    int64_t ns, int D, int R,
+                                                    const double* __restrict__ in,
+                                                    T* __restrict__ out, int to_internal,
+                                                    const T* __restrict__ in_int,
+                                                    double* __restrict__ out_abi) {
+  const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= N) return;
+  int64_t a;
+  if (g < offV) {
+    const int64_t i = g / (D * R), rem = g - i * D * R;
+    const int c = (int)(rem / R), s = (int)(rem - (int64_t)c * R);
+    a = s * ns + c * nfree + i;
+  } else {
+    const int64_t v = (g - offV) / R;
+    const int s = (int)(g - offV - v * R);
+    a = s * ns + D * nfree + v;
+  }
+  if (to_internal) out[g] = (T)in[a];
+  else out_abi[a] = (double)in_int[g];
+}
+
+template <typename S, typename Dt>
+__global__ __launch_bounds__(kBlock) void k_cast(const S* __restrict__ in, Dt* __restrict__ out,
+                                                 int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) out[i] = (Dt)in[i];
+}
+
+// per-stage pressure mean removal: one workgroup per stage, fixed-order reduction
+__global__ __launch_bounds__(1024) void k_project(double* x, int64_t offV, int64_t nv, int R) {
+  __shared__ double red[1024];
+  const int s = blockIdx.x;
+  double acc = 0;
+  for (int64_t v = threadIdx.x; v < nv; v += blockDim.x) acc += x[offV + v * R + s];
+  red[threadIdx.x] = acc;
+  __syncthreads();
+  for (int w = blockDim.x / 2; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+    __syncthreads();
+  }
+  const double mean = red[0] / (double)nv;
+  for (int64_t v = threadIdx.x; v < nv; v += blockDim.x) x[offV + v * R + s] -= mean;
+}
+
+// ------------------------------------------------------------------------- BLAS-1
+__global__ __launch_bounds__(kBlock) void k_dot_partial(const double* __restrict__ a,
+                                                        const double* __restrict__ b, int64_t n,
+                                                        double* __restrict__ partials) {
+  __shared__ double red[kBlock];
+  double acc = 0;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    acc += a[i] * b[i];
+  red[threadIdx.x] = acc;
+  __syncthreads();
+  for (int w = kBlock / 2; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) partials[blockIdx.x] = red[0];
+}
+
+__global__ __launch_bounds__(kBlock) void k_dot_final(const double* __restrict__ partials, int nb,
+                                                      double* __restrict__ out, int take_sqrt) {
+  __shared__ double red[kBlock];
+  double acc = 0;
+  for (int i = threadIdx.x; i < nb; i += blockDim.x) acc += partials[i];
+  red[threadIdx.x] = acc;
+  __syncthreads();
+  for (int w = kBlock / 2; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) *out = take_sqrt ? sqrt(red[0]) : red[0];
+}
+
+__global__ __launch_bounds__(kBlock) void k_axpy_dev(double* __restrict__ y,
+                                                     const double* __restrict__ x, int64_t n,
+                                                     const double* __restrict__ s, double sign,
+                                                     double alpha_host) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const double a = s ? sign * (*s) : alpha_host;
+  y[i] += a * x[i];
+}
+
+__global__ __launch_bounds__(kBlock) void k_scale_inv(double* __restrict__ y,
+                                                      const double* __restrict__ x, int64_t n,
+                                                      const double* __restrict__ s) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) y[i] = x[i] / (*s);
+}
+
+__global__ __launch_bounds__(kBlock) void k_axpby(double* __restrict__ y,
+                                                  const double* __restrict__ x, int64_t n,
+                                                  double a, double b) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) y[i] = a * x[i] + b * y[i];
+}
+
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_fill(T* y, int64_t n, T v) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) y[i] = v;
+}
+
+__global__ __launch_bounds__(kBlock) void k_nonfinite(const double* __restrict__ x, int64_t n,
+                                                      int* flag) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n && !isfinite(x[i])) atomicMax(flag, 1);
+}
+
+// ---------------------------------------------------------------- rhs and update
+// F_i = [M_fa f_i - L u - B p ; -B^T u] in the ABI layout; state = (u, p) stage block.
+__global__ __launch_bounds__(kBlock) void k_rhs(
+    int64_t nfree, int64_t nv, int64_t nnodes, int D, int R, const int32_t* __restrict__ mfa_ptr,
+    const int32_t* __restrict__ mfa_col, const double* __restrict__ mfa_val,
+    const int32_t* __restrict__ s_ptr, const int32_t* __restrict__ s_col,
+    const double* __restrict__ sL, const int32_t* __restrict__ b_ptr,
+    const int32_t* __restrict__ b_col, const double* __restrict__ b_val,
+    const int32_t* __restrict__ bt_ptr, const int32_t* __restrict__ bt_col,
+    const double* __restrict__ bt_val, const double* __restrict__ f,
+    const double* __restrict__ state, double* __restrict__ F) {
+  const int64_t row = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t ns = D * nfree + nv;
+  const double* u = state;
+  const double* pr = state + D * nfree;
+  if (row < nfree) {
+    for (int c = 0; c < D; ++c) {
+      double lu = 0, bp = 0;
+      for (int32_t p = s_ptr[row]; p < s_ptr[row + 1]; ++p) lu += sL[p] * u[c * nfree + s_col[p]];
+      for (int32_t p = b_ptr[row]; p < b_ptr[row + 1]; ++p) bp += b_val[(int64_t)p * D + c] * pr[b_col[p]];
+      for (int s = 0; s < R; ++s) {
+        double mf = 0;
+        for (int32_t p = mfa_ptr[row]; p < mfa_ptr[row + 1]; ++p)
+          mf += mfa_val[p] * f[((int64_t)s * nnodes + mfa_col[p]) * D + c];
+        F[s * ns + c * nfree + row] = mf - lu - bp;
+      }
+    }
+  } else if (row < nfree + nv) {
+    const int64_t v = row - nfree;
+    double acc = 0;
+    for (int32_t p = bt_ptr[v]; p < bt_ptr[v + 1]; ++p)
+      for (int c = 0; c < D; ++c) acc += bt_val[(int64_t)p * D + c] * u[c * nfree + bt_col[p]];
+    for (int s = 0; s < R; ++s) F[s * ns + D * nfree + v] = -acc;
+  }
+}
+
+__global__ __launch_bounds__(kBlock) void k_update(int64_t ns, int R, Coef<double> bdt,
+                                                   const double* __restrict__ kv,
+                                                   double* __restrict__ state) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= ns) return;
+  double acc = state[i];
+  for (int j = 0; j < R; ++j) acc += bdt.v[j] * kv[j * ns + i];
+  state[i] = acc;
+}
+
+}  // namespace
+
+// =========================================================================== launchers
+#define IRK_DISPATCH_DR(D, R, ...)                        \
+  do {                                                     \
+    if ((D) == 2) {                                        \
+      switch (R) {                                         \
+        case 1: { constexpr int DD = 2, RR = 1; __VA_ARGS__; } break; \
+        case 2: { constexpr int DD = 2, RR = 2; __VA_ARGS__; } break; \
+        case 3: { constexpr int DD = 2, RR = 3; __VA_ARGS__; } break; \
+        case 4: { constexpr int DD = 2, RR = 4; __VA_ARGS__; } break; \
+        default: return hipErrorInvalidValue;              \
+      }                                                    \
+    } else {                                               \
+      switch (R) {                                         \
+        case 1: { constexpr int DD = 3, RR = 1; __VA_ARGS__; } break; \
+        case 2: { constexpr int DD = 3, RR = 2; __VA_ARGS__; } break; \
+        case 3: { constexpr int DD = 3, RR = 3; __VA_ARGS__; } break; \
+        case 4: { constexpr int DD = 3, RR = 4; __VA_ARGS__; } break; \
+        default: return hipErrorInvalidValue;              \
+      }                                                    \
+    }                                                      \
+  } while (0)
+
+template <typename T>
+hipError_t residual(const DevLevel& L, const DevOps<T>& ops, const double* A, double dt,
+                    const T* F, const T* x, T* y, hipStream_t s) {
+  const int64_t rows = L.nfree + L.nv;
+  const unsigned g = blocks_for(rows);
+  IRK_DISPATCH_DR(L.dim, L.r, (k_residual<DD, RR, T><<<dim3(g), dim3(kBlock), 0, s>>>(L.nfree, L.nv, L.offV, L.s_ptr, L.s_col, ops.s_M, ops.s_L,
+                                                  L.b_ptr, L.b_col, ops.b_val, L.bt_ptr, L.bt_col,
+                                                  ops.bt_val, scaled<T, RR>(A, dt), F, x, y)));
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t patch_factor(const DevLevel& L, const DevOps<T>& ops, const double* A, double dt,
+                        int* d_fail, hipStream_t s) {
+  const size_t n = (size_t)L.max_nloc;
+  const size_t lds = n * n * sizeof(T) + n * sizeof(T) + n * sizeof(int) + 64;
+  if (lds > 160 * 1024) return hipErrorInvalidConfiguration;
+  IRK_DISPATCH_DR(L.dim, L.r, {
+    auto kern = k_patch_factor<DD, RR, T>;
+    hipError_t e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+    kern<<<dim3((unsigned)L.npatch), dim3(kBlock), lds, s>>>(L.npatch, L.pn_ptr,
+                       L.pvv_ptr, L.pvv, L.pvp, L.p_ld, L.p_inv_off, ops.s_M, ops.s_L, ops.b_val,
+                       scaled<T, RR>(A, dt), reinterpret_cast<T*>(L.inv), d_fail);
+  });
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t patch_apply(const DevLevel& L, const DevOps<T>& ops, const T* res, T* Y,
+                       int transpose, hipStream_t s) {
+  constexpr int VEC = Vec16<T>::n;
+  const unsigned g = blocks_for(L.npatch, kWaves);
+  const T* W = transpose ? ops.W : nullptr;
+  const T* inv = reinterpret_cast<const T*>(L.inv);
+  const int rows_per_block = 64 * VEC;
+  const int rb = (L.max_nloc + rows_per_block - 1) / rows_per_block;
+#define IRK_PA(RBV, NM)                                                                        \
+  k_patch_apply<T, RBV, NM><<<dim3(g), dim3(kWaves * 64), 0, s>>>(L.npatch,  \
+                     L.sched, L.p_nloc, L.p_ld, L.p_inv_off, L.p_slot_off, L.p_gidx, inv, res, \
+                     W, Y, transpose)
+  if (L.max_nloc <= 128) {
+    if (rb == 1) IRK_PA(1, 128); else IRK_PA(2, 128);
+  } else if (L.max_nloc <= 256) {
+    if (rb == 1) IRK_PA(1, 256); else IRK_PA(2, 256);
+  } else if (L.max_nloc <= 512) {
+    if (rb <= 2) IRK_PA(2, 512); else if (rb <= 4) IRK_PA(4, 512); else return hipErrorInvalidValue;
+  } else if (L.max_nloc <= 1024) {
+    if (rb <= 4) IRK_PA(4, 1024); else if (rb <= 8) IRK_PA(8, 1024); else return hipErrorInvalidValue;
+  } else {
+    return hipErrorInvalidValue;
+  }
+#undef IRK_PA
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t gather_update(const DevLevel& L, const DevOps<T>& ops, const T* Y, T* x, T omega,
+                         int mode, hipStream_t s) {
+  k_gather_update<T><<<dim3(blocks_for(L.N)), dim3(kBlock), 0, s>>>(L.N,
+                     L.gat_ptr, L.gat_slot, Y, ops.W, omega, mode, x);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t restrict_(const DevLevel& F, const DevLevel& C, const DevOps<T>& fops, const T* xf,
+                     T* xc, hipStream_t s) {
+  const unsigned g = blocks_for(C.nfree + C.nv);
+  IRK_DISPATCH_DR(F.dim, F.r, (k_spmv_nodes<DD, RR, T><<<dim3(g), dim3(kBlock), 0, s>>>(C.nfree, C.nv, C.offV, F.offV, F.put_ptr, F.put_col,
+                                                  fops.put_val, F.ppt_ptr, F.ppt_col, fops.ppt_val, xf,
+                                                  xc, 0)));
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t prolong_add(const DevLevel& F, const DevLevel& C, const DevOps<T>& fops, const T* xc,
+                       T* xf, hipStream_t s) {
+  const unsigned g = blocks_for(F.nfree + F.nv);
+  IRK_DISPATCH_DR(F.dim, F.r, (k_spmv_nodes<DD, RR, T><<<dim3(g), dim3(kBlock), 0, s>>>(F.nfree, F.nv, F.offV, C.offV, F.pu_ptr, F.pu_col,
+                                                  fops.pu_val, F.pp_ptr, F.pp_col, fops.pp_val, xc,
+                                                  xf, 1)));
+  return hipGetLastError();
+}
+
+hipError_t coarse_gemv(const double* inv, int64_t N, const double* b, double* x,
+                       const int64_t* pins, int npins, hipStream_t s) {
+  if (pins && npins > 0) k_zero_pins<<<dim3(1), dim3(64), 0, s>>>(const_cast<double*>(b), pins, npins);
+  k_coarse_gemv<<<dim3(blocks_for(N)), dim3(kBlock), 0, s>>>(inv, N, b, x);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t to_internal(const DevLevel& L, const double* abi, T* x, hipStream_t s) {
+  const int64_t ns = L.dim * L.nfree + L.nv;
+  k_permute<T><<<dim3(blocks_for(L.N)), dim3(kBlock), 0, s>>>(L.N, L.offV,
+                     L.nfree, ns, L.dim, L.r, abi, x, 1, nullptr, nullptr);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t to_abi(const DevLevel& L, const T* x, double* abi, hipStream_t s) {
+  const int64_t ns = L.dim * L.nfree + L.nv;
+  k_permute<T><<<dim3(blocks_for(L.N)), dim3(kBlock), 0, s>>>(L.N, L.offV,
+                     L.nfree, ns, L.dim, L.r, nullptr, nullptr, 0, x, abi);
+  return hipGetLastError();
+}
+
+template <typename S, typename D>
+hipError_t cast(const S* in, D* out, int64_t n, hipStream_t s) {
+  k_cast<S, D><<<dim3(blocks_for(n)), dim3(kBlock), 0, s>>>(in, out, n);
+  return hipGetLastError();
+}
+
+hipError_t project_pressure(const DevLevel& L, double* x, double*, hipStream_t s) {
+  k_project<<<dim3(L.r), dim3(1024), 0, s>>>(x, L.offV, L.nv, L.r);
+  return hipGetLastError();
+}
+
+hipError_t dot(const double* a, const double* b, int64_t n, double* partials, double* out,
+               hipStream_t s, int take_sqrt) {
+  const int nb = (int)std::min<int64_t>(kReduceBlocks, blocks_for(n));
+  k_dot_partial<<<dim3(nb), dim3(kBlock), 0, s>>>(a, b, n, partials);
+  k_dot_final<<<dim3(1), dim3(kBlock), 0, s>>>(partials, nb, out, take_sqrt);
+  return hipGetLastError();
+}
+
+hipError_t axpy_dev(double* y, const double* x, int64_t n, const double* dev_scalar,
+                    double sign, hipStream_t s) {
+  k_axpy_dev<<<dim3(blocks_for(n)), dim3(kBlock), 0, s>>>(y, x, n, dev_scalar,
+                     sign, sign);
+  return hipGetLastError();
+}
+
+hipError_t scale_inv_dev(double* y, const double* x, int64_t n, const double* dev_scalar,
+                         hipStream_t s) {
+  k_scale_inv<<<dim3(blocks_for(n)), dim3(kBlock), 0, s>>>(y, x, n, dev_scalar);
+  return hipGetLastError();
+}
+
+hipError_t axpby(double* y, const double* x, int64_t n, double a, double b, hipStream_t s) {
+  k_axpby<<<dim3(blocks_for(n)), dim3(kBlock), 0, s>>>(y, x, n, a, b);
+  return hipGetLastError();
+}
+
+hipError_t fill(double* y, int64_t n, double v, hipStream_t s) {
+  k_fill<double><<<dim3(blocks_for(n)), dim3(kBlock), 0, s>>>(y, n, v);
+  return hipGetLastError();
+}
+
+hipError_t fillf(float* y, int64_t n, float v, hipStream_t s) {
+  k_fill<float><<<dim3(blocks_for(n)), dim3(kBlock), 0, s>>>(y, n, v);
+  return hipGetLastError();
+}
+
+hipError_t nonfinite(const double* x, int64_t n, int* flag, hipStream_t s) {
+  k_nonfinite<<<dim3(blocks_for(n)), dim3(kBlock), 0, s>>>(x, n, flag);
+  return hipGetLastError();
+}
+
+hipError_t rhs(const DevLevel& L, int64_t nnodes, const double* f, const double* state,
+                    double* F, hipStream_t s) {
+  k_rhs<<<dim3(blocks_for(L.nfree + L.nv)), dim3(kBlock), 0, s>>>(L.nfree, L.nv,
+                     nnodes, L.dim, L.r, L.mfa_ptr, L.mfa_col, L.mfa_val, L.s_ptr, L.s_col,
+                     L.d64.s_L, L.b_ptr, L.b_col, L.d64.b_val, L.bt_ptr, L.bt_col, L.d64.bt_val, f,
+                     state, F);
+  return hipGetLastError();
+}
+
+hipError_t update(const DevLevel& L, const double* b, double dt, const double* kv, double* state,
+                  hipStream_t s) {
+  Coef<double> c{};
+  for (int j = 0; j < L.r; ++j) c.v[j] = dt * b[j];
+  const int64_t ns = L.dim * L.nfree + L.nv;
+  k_update<<<dim3(blocks_for(ns)), dim3(kBlock), 0, s>>>(ns, L.r, c, kv, state);
+  return hipGetLastError();
+}
+
+// explicit instantiations
+#define IRK_INST(T)                                                                              \
+  template hipError_t residual<T>(const DevLevel&, const DevOps<T>&, const double*, double,     \
+                                  const T*, const T*, T*, hipStream_t);                         \
+  template hipError_t patch_factor<T>(const DevLevel&, const DevOps<T>&, const double*, double, \
+                                      int*, hipStream_t);                                       \
+  template hipError_t patch_apply<T>(const DevLevel&, const DevOps<T>&, const T*, T*, int,      \
+                                     hipStream_t);                                              \
+  template hipError_t gather_update<T>(const DevLevel&, const DevOps<T>&, const T*, T*, T, int, \
+                                       hipStream_t);                                            \
+  template hipError_t restrict_<T>(const DevLevel&, const DevLevel&, const DevOps<T>&, const T*, \
+                                   T*, hipStream_t);                                            \
+  template hipError_t prolong_add<T>(const DevLevel&, const DevLevel&, const DevOps<T>&,        \
+                                     const T*, T*, hipStream_t);                                \
+  template hipError_t to_internal<T>(const DevLevel&, const double*, T*, hipStream_t);         \
+  template hipError_t to_abi<T>(const DevLevel&, const T*, double*, hipStream_t);
+IRK_INST(double)
+IRK_INST(float)
+template hipError_t cast<double, float>(const double*, float*, int64_t, hipStream_t);
+template hipError_t cast<float, double>(const float*, double*, int64_t, hipStream_t);
+template hipError_t cast<double, double>(const double*, double*, int64_t, hipStream_t);
+
+}  // namespace k
+}  // namespace irk

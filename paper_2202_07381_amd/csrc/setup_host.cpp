@@ -1,0 +1,654 @@
+// Host-side setup of libirkmg: mesh topology and P2 numbering, exact element matrices,
+// sparse assembly (rediscretisation on every level, Sec. 4.1), vertex-star patches
+// (Sec. 4.2, Fig. 1), transfer operators from the parent map (Sec. 4.1) and the dense
+// coarse inverse.  Everything here is untimed setup; all solve-time arithmetic runs in
+// the HIP kernels.
+//
+// Element integrals use the exact formula for monomials in barycentric coordinates on a
+// d-simplex T:  int_T lam^a = |T| d! prod(a_k!) / (|a| + d)!.  P2 basis functions are
+// lam_i (2 lam_i - 1) (vertex i) and 4 lam_i lam_j (edge ij), gradients follow from
+// grad lam_k, so the reference tensors below depend on nothing but the dimension.
+#include <algorithm>
+#include <array>
+#include <cmath>
+#include <cstring>
+#include <map>
+#include <numeric>
+#include <stdexcept>
+
+#include "irk_internal.h"
+
+namespace irk {
+namespace {
+
+const int kEdges2[3][2] = {{0, 1}, {0, 2}, {1, 2}};
+const int kEdges3[6][2] = {{0, 1}, {0, 2}, {0, 3}, {1, 2}, {1, 3}, {2, 3}};
+
+inline int nloc_of(int dim) { return dim == 2 ? 6 : 10; }
+inline const int (*edges_of(int dim))[2] { return dim == 2 ? kEdges2 : kEdges3; }
+
+// ------------------------------------------------ polynomials in barycentric coords
+struct Term {
+  double c;
+  std::array<int, 4> e;
+};
+using Poly = std::vector<Term>;
+
+Poly mul(const Poly& a, const Poly& b) {
+  Poly out;
+  for (const Term& x : a)
+    for (const Term& y : b) {
+      Term t;
+      t.c = x.c * y.c;
+      for (int k = 0; k < 4; ++k) t.e[k] = x.e[k] + y.e[k];
+      out.push_back(t);
+    }
+  return out;
+}
+
+Poly dlam(const Poly& p, int k) {  // formal derivative with respect to lam_k
+  Poly out;
+  for (const Term& t : p)
+    if (t.e[k] > 0) {
+      Term u = t;
+      u.c *= t.e[k];
+      u.e[k] -= 1;
+      out.push_back(u);
+    }
+  return out;
+}
+
+double fact(int n) {
+  double f = 1;
+  for (int i = 2; i <= n; ++i) f *= i;
+  return f;
+}
+
+double integrate(const Poly& p, int dim) {  // int_T p / |T|
+  double s = 0;
+  for (const Term& t : p) {
+    int tot = 0;
+    double num = fact(dim);
+    for (int k = 0; k <= dim; ++k) {
+      num *= fact(t.e[k]);
+      tot += t.e[k];
+    }
+    s += t.c * num / fact(tot + dim);
+  }
+  return s;
+}
+
+Poly lam_pow(int i, int pw, double c) {
+  Term t;
+  t.c = c;
+  t.e = {0, 0, 0, 0};
+  t.e[i] = pw;
+  return {t};
+}
+
+Poly basis(int dim, int a) {
+  if (a <= dim) {
+    Poly p = lam_pow(a, 2, 2.0);
+    p.push_back(lam_pow(a, 1, -1.0)[0]);
+    return p;
+  }
+  const int* e = edges_of(dim)[a - dim - 1];
+  Term t;
+  t.c = 4.0;
+  t.e = {0, 0, 0, 0};
+  t.e[e[0]] = 1;
+  t.e[e[1]] = 1;
+  return {t};
+}
+
+struct RefTensors {
+  int dim, nl;
+  std::vector<double> M;  // [a][b]
+  std::vector<double> S;  // [a][b][k][l]  int d_k phi_a d_l phi_b
+  std::vector<double> B;  // [a][q][k]     int lam_q d_k phi_a
+  std::vector<double> C;  // [e][a][b][k]  int phi_e phi_a d_k phi_b
+};
+
+const RefTensors& ref_tensors(int dim) {
+  static RefTensors cache[2];
+  RefTensors& R = cache[dim - 2];
+  if (!R.M.empty()) return R;
+  const int nl = nloc_of(dim), nb = dim + 1;
+  R.dim = dim;
+  R.nl = nl;
+  std::vector<Poly> phi(nl);
+  std::vector<std::vector<Poly>> dphi(nl, std::vector<Poly>(nb));
+  for (int a = 0; a < nl; ++a) {
+    phi[a] = basis(dim, a);
+    for (int k = 0; k < nb; ++k) dphi[a][k] = dlam(phi[a], k);
+  }
+  R.M.resize(nl * nl);
+  R.S.resize(nl * nl * nb * nb);
+  R.B.resize(nl * nb * nb);
+  R.C.resize(nl * nl * nl * nb);
+  for (int a = 0; a < nl; ++a)
+    for (int b = 0; b < nl; ++b) {
+      R.M[a * nl + b] = integrate(mul(phi[a], phi[b]), dim);
+      for (int k = 0; k < nb; ++k)
+        for (int l = 0; l < nb; ++l)
+          R.S[((a * nl + b) * nb + k) * nb + l] = integrate(mul(dphi[a][k], dphi[b][l]), dim);
+    }
+  for (int a = 0; a < nl; ++a)
+    for (int q = 0; q < nb; ++q)
+      for (int k = 0; k < nb; ++k)
+        R.B[(a * nb + q) * nb + k] = integrate(mul(lam_pow(q, 1, 1.0), dphi[a][k]), dim);
+  for (int e = 0; e < nl; ++e)
+    for (int a = 0; a < nl; ++a) {
+      Poly pe = mul(phi[e], phi[a]);
+      for (int b = 0; b < nl; ++b)
+        for (int k = 0; k < nb; ++k)
+          R.C[((e * nl + a) * nl + b) * nb + k] = integrate(mul(pe, dphi[b][k]), dim);
+    }
+  return R;
+}
+
+// gradients of barycentric coordinates and measure of a cell
+void cell_geometry(const HostLevel& L, int64_t c, double* glam /* (dim+1) x dim */,
+                   double* vol) {
+  const int d = L.dim;
+  const int64_t* v = &L.cells[c * (d + 1)];
+  double J[3][3], Ji[3][3];
+  for (int i = 0; i < d; ++i)
+    for (int k = 0; k < d; ++k) J[i][k] = L.xyz[v[k + 1] * d + i] - L.xyz[v[0] * d + i];
+  double det;
+  if (d == 2) {
+    det = J[0][0] * J[1][1] - J[0][1] * J[1][0];
+    Ji[0][0] = J[1][1] / det;
+    Ji[0][1] = -J[0][1] / det;
+    Ji[1][0] = -J[1][0] / det;
+    Ji[1][1] = J[0][0] / det;
+  } else {
+    det = J[0][0] * (J[1][1] * J[2][2] - J[1][2] * J[2][1]) -
+          J[0][1] * (J[1][0] * J[2][2] - J[1][2] * J[2][0]) +
+          J[0][2] * (J[1][0] * J[2][1] - J[1][1] * J[2][0]);
+    Ji[0][0] = (J[1][1] * J[2][2] - J[1][2] * J[2][1]) / det;
+    Ji[0][1] = (J[0][2] * J[2][1] - J[0][1] * J[2][2]) / det;
+    Ji[0][2] = (J[0][1] * J[1][2] - J[0][2] * J[1][1]) / det;
+    Ji[1][0] = (J[1][2] * J[2][0] - J[1][0] * J[2][2]) / det;
+    Ji[1][1] = (J[0][0] * J[2][2] - J[0][2] * J[2][0]) / det;
+    Ji[1][2] = (J[0][2] * J[1][0] - J[0][0] * J[1][2]) / det;
+    Ji[2][0] = (J[1][0] * J[2][1] - J[1][1] * J[2][0]) / det;
+    Ji[2][1] = (J[0][1] * J[2][0] - J[0][0] * J[2][1]) / det;
+    Ji[2][2] = (J[0][0] * J[1][1] - J[0][1] * J[1][0]) / det;
+  }
+  // lam_{k+1} = row k of J^{-1} applied to (x - x0); lam_0 = 1 - sum
+  for (int i = 0; i < d; ++i) glam[0 * d + i] = 0;
+  for (int k = 0; k < d; ++k)
+    for (int i = 0; i < d; ++i) {
+      glam[(k + 1) * d + i] = Ji[k][i];
+      glam[0 * d + i] -= Ji[k][i];
+    }
+  *vol = std::fabs(det) / (d == 2 ? 2.0 : 6.0);
+}
+
+// barycentric coordinates of point x in cell c
+void barycentric(const HostLevel& L, int64_t c, const double* x, double* lam) {
+  const int d = L.dim;
+  double glam[12], vol;
+  cell_geometry(L, c, glam, &vol);
+  const int64_t* v = &L.cells[c * (d + 1)];
+  double s = 0;
+  for (int k = 1; k <= d; ++k) {
+    double acc = 0;
+    for (int i = 0; i < d; ++i) acc += glam[k * d + i] * (x[i] - L.xyz[v[0] * d + i]);
+    lam[k] = acc;
+    s += acc;
+  }
+  lam[0] = 1.0 - s;
+}
+
+void node_coord(const HostLevel& L, int64_t node, double* x) {
+  const int d = L.dim;
+  if (node < L.nv) {
+    for (int i = 0; i < d; ++i) x[i] = L.xyz[node * d + i];
+  } else {
+    const int64_t a = L.edges[(node - L.nv) * 2], b = L.edges[(node - L.nv) * 2 + 1];
+    for (int i = 0; i < d; ++i) x[i] = 0.5 * (L.xyz[a * d + i] + L.xyz[b * d + i]);
+  }
+}
+
+void p2_values(int dim, const double* lam, double* w) {
+  for (int i = 0; i <= dim; ++i) w[i] = lam[i] * (2 * lam[i] - 1);
+  const int(*E)[2] = edges_of(dim);
+  const int ne = dim == 2 ? 3 : 6;
+  for (int e = 0; e < ne; ++e) w[dim + 1 + e] = 4 * lam[E[e][0]] * lam[E[e][1]];
+}
+
+int32_t find_in_row(const std::vector<int32_t>& ptr, const std::vector<int32_t>& col,
+                    int64_t row, int64_t c) {
+  auto b = col.begin() + ptr[row], e = col.begin() + ptr[row + 1];
+  auto it = std::lower_bound(b, e, (int32_t)c);
+  if (it == e || *it != c) return -1;
+  return (int32_t)(it - col.begin());
+}
+
+void csr_from_rows(std::vector<std::vector<int32_t>>& rows, std::vector<int32_t>& ptr,
+                   std::vector<int32_t>& col) {
+  ptr.assign(rows.size() + 1, 0);
+  for (size_t i = 0; i < rows.size(); ++i) ptr[i + 1] = ptr[i] + (int32_t)rows[i].size();
+  col.resize(ptr.back());
+  for (size_t i = 0; i < rows.size(); ++i)
+    std::copy(rows[i].begin(), rows[i].end(), col.begin() + ptr[i]);
+}
+
+void transpose_csr(int64_t nrows, int64_t ncols, const std::vector<int32_t>& ptr,
+                   const std::vector<int32_t>& col, const std::vector<double>& val, int vw,
+                   std::vector<int32_t>& tptr, std::vector<int32_t>& tcol,
+                   std::vector<double>& tval) {
+  tptr.assign(ncols + 1, 0);
+  for (int32_t c : col) tptr[c + 1]++;
+  for (int64_t i = 0; i < ncols; ++i) tptr[i + 1] += tptr[i];
+  tcol.resize(col.size());
+  tval.resize(val.size());
+  std::vector<int32_t> fillp(tptr.begin(), tptr.end() - 1);
+  for (int64_t i = 0; i < nrows; ++i)  // ascending rows -> sorted transposed columns
+    for (int32_t p = ptr[i]; p < ptr[i + 1]; ++p) {
+      int32_t q = fillp[col[p]]++;
+      tcol[q] = (int32_t)i;
+      for (int k = 0; k < vw; ++k) tval[(size_t)q * vw + k] = val[(size_t)p * vw + k];
+    }
+}
+
+}  // namespace
+
+// -------------------------------------------------------------------------- topology
+void build_topology(HostLevel& L, int dim, int64_t nv, int64_t nc, const double* xyz,
+                    const int64_t* cells) {
+  L.dim = dim;
+  L.nv = nv;
+  L.nc = nc;
+  const int nb = dim + 1, nl = nloc_of(dim), nle = nl - nb;
+  L.xyz.assign(xyz, xyz + nv * dim);
+  L.cells.assign(cells, cells + nc * nb);
+  const int(*E)[2] = edges_of(dim);
+  std::vector<int64_t> keys;
+  keys.reserve(nc * nle);
+  for (int64_t c = 0; c < nc; ++c)
+    for (int e = 0; e < nle; ++e) {
+      int64_t a = L.cells[c * nb + E[e][0]], b = L.cells[c * nb + E[e][1]];
+      keys.push_back(std::min(a, b) * nv + std::max(a, b));
+    }
+  std::vector<int64_t> uk(keys);
+  std::sort(uk.begin(), uk.end());
+  uk.erase(std::unique(uk.begin(), uk.end()), uk.end());
+  L.ne = (int64_t)uk.size();
+  L.nn = nv + L.ne;
+  L.edges.resize(L.ne * 2);
+  for (int64_t i = 0; i < L.ne; ++i) {
+    L.edges[2 * i] = uk[i] / nv;
+    L.edges[2 * i + 1] = uk[i] % nv;
+  }
+  L.cell_nodes.resize(nc * nl);
+  for (int64_t c = 0; c < nc; ++c) {
+    for (int k = 0; k < nb; ++k) L.cell_nodes[c * nl + k] = L.cells[c * nb + k];
+    for (int e = 0; e < nle; ++e) {
+      int64_t key = keys[c * nle + e];
+      L.cell_nodes[c * nl + nb + e] =
+          nv + (int64_t)(std::lower_bound(uk.begin(), uk.end(), key) - uk.begin());
+    }
+  }
+  // boundary: facets owned by a single cell
+  std::vector<std::array<int64_t, 3>> fac;
+  fac.reserve(nc * nb);
+  for (int64_t c = 0; c < nc; ++c)
+    for (int skip = 0; skip < nb; ++skip) {
+      std::array<int64_t, 3> f = {-1, -1, -1};
+      int m = 0;
+      for (int k = 0; k < nb; ++k)
+        if (k != skip) f[m++] = L.cells[c * nb + k];
+      std::sort(f.begin(), f.begin() + dim);
+      fac.push_back(f);
+    }
+  std::sort(fac.begin(), fac.end());
+  std::vector<char> bnd(L.nn, 0);
+  for (size_t i = 0; i < fac.size();) {
+    size_t j = i;
+    while (j < fac.size() && fac[j] == fac[i]) ++j;
+    if (j - i == 1) {
+      const auto& f = fac[i];
+      for (int k = 0; k < dim; ++k) bnd[f[k]] = 1;
+      for (int a = 0; a < dim; ++a)
+        for (int b = a + 1; b < dim; ++b) {
+          int64_t key = std::min(f[a], f[b]) * nv + std::max(f[a], f[b]);
+          bnd[nv + (std::lower_bound(uk.begin(), uk.end(), key) - uk.begin())] = 1;
+        }
+    }
+    i = j;
+  }
+  L.free_of_node.assign(L.nn, -1);
+  L.node_of_free.clear();
+  for (int64_t n = 0; n < L.nn; ++n)
+    if (!bnd[n]) {
+      L.free_of_node[n] = (int32_t)L.node_of_free.size();
+      L.node_of_free.push_back((int32_t)n);
+    }
+  L.nfree = (int64_t)L.node_of_free.size();
+  // node -> cells
+  L.node_cell_ptr.assign(L.nn + 1, 0);
+  for (int64_t c = 0; c < nc; ++c)
+    for (int a = 0; a < nl; ++a) L.node_cell_ptr[L.cell_nodes[c * nl + a] + 1]++;
+  for (int64_t n = 0; n < L.nn; ++n) L.node_cell_ptr[n + 1] += L.node_cell_ptr[n];
+  L.node_cell.resize(L.node_cell_ptr.back());
+  std::vector<int32_t> fp(L.node_cell_ptr.begin(), L.node_cell_ptr.end() - 1);
+  for (int64_t c = 0; c < nc; ++c)
+    for (int a = 0; a < nl; ++a) L.node_cell[fp[L.cell_nodes[c * nl + a]]++] = (int32_t)c;
+}
+
+// -------------------------------------------------------------------------- assembly
+void assemble_level(HostLevel& L, double nu, const std::vector<double>* wind, bool with_mfa) {
+  const int d = L.dim, nb = d + 1, nl = nloc_of(d);
+  const RefTensors& R = ref_tensors(d);
+  // patterns from node -> cell adjacency
+  std::vector<std::vector<int32_t>> srows(L.nfree), brows(L.nfree), mrows;
+  if (with_mfa) mrows.resize(L.nfree);
+  for (int64_t i = 0; i < L.nfree; ++i) {
+    const int64_t n = L.node_of_free[i];
+    for (int32_t p = L.node_cell_ptr[n]; p < L.node_cell_ptr[n + 1]; ++p) {
+      const int64_t c = L.node_cell[p];
+      for (int a = 0; a < nl; ++a) {
+        int64_t m = L.cell_nodes[c * nl + a];
+        if (L.free_of_node[m] >= 0) srows[i].push_back(L.free_of_node[m]);
+        if (with_mfa) mrows[i].push_back((int32_t)m);
+      }
+      for (int q = 0; q < nb; ++q) brows[i].push_back((int32_t)L.cells[c * nb + q]);
+    }
+    for (auto* v : {&srows[i], &brows[i]}) {
+      std::sort(v->begin(), v->end());
+      v->erase(std::unique(v->begin(), v->end()), v->end());
+    }
+    if (with_mfa) {
+      std::sort(mrows[i].begin(), mrows[i].end());
+      mrows[i].erase(std::unique(mrows[i].begin(), mrows[i].end()), mrows[i].end());
+    }
+  }
+  csr_from_rows(srows, L.s_ptr, L.s_col);
+  csr_from_rows(brows, L.b_ptr, L.b_col);
+  const size_t snnz = L.s_col.size();
+  L.s_M.assign(snnz, 0.0);
+  L.s_L.assign(snnz, 0.0);
+  L.s_K1.assign(snnz, 0.0);
+  std::vector<double> conv(snnz, 0.0);
+  L.b_val.assign(L.b_col.size() * d, 0.0);
+  if (with_mfa) {
+    csr_from_rows(mrows, L.mfa_ptr, L.mfa_col);
+    L.mfa_val.assign(L.mfa_col.size(), 0.0);
+  }
+  double glam[12], vol;
+  double G[4][4], Me[10][10], Ke[10][10], Ce[10][10], Be[10][4][3];
+  for (int64_t c = 0; c < L.nc; ++c) {
+    cell_geometry(L, c, glam, &vol);
+    for (int k = 0; k < nb; ++k)
+      for (int l = 0; l < nb; ++l) {
+        double s = 0;
+        for (int i = 0; i < d; ++i) s += glam[k * d + i] * glam[l * d + i];
+        G[k][l] = s;
+      }
+    for (int a = 0; a < nl; ++a)
+      for (int b = 0; b < nl; ++b) {
+        Me[a][b] = vol * R.M[a * nl + b];
+        double s = 0;
+        for (int k = 0; k < nb; ++k)
+          for (int l = 0; l < nb; ++l) s += G[k][l] * R.S[((a * nl + b) * nb + k) * nb + l];
+        Ke[a][b] = vol * s;
+        Ce[a][b] = 0;
+      }
+    if (wind) {
+      // C_ab = sum_e sum_k (w_e . grad lam_k) int phi_e phi_a d_k phi_b
+      double wg[10][4];
+      for (int e = 0; e < nl; ++e) {
+        const int64_t node = L.cell_nodes[c * nl + e];
+        for (int k = 0; k < nb; ++k) {
+          double s = 0;
+          for (int i = 0; i < d; ++i) s += (*wind)[node * d + i] * glam[k * d + i];
+          wg[e][k] = s;
+        }
+      }
+      for (int a = 0; a < nl; ++a)
+        for (int b = 0; b < nl; ++b) {
+          double s = 0;
+          for (int e = 0; e < nl; ++e)
+            for (int k = 0; k < nb; ++k) s += wg[e][k] * R.C[((e * nl + a) * nl + b) * nb + k];
+          Ce[a][b] = vol * s;
+        }
+    }
+    for (int a = 0; a < nl; ++a)
+      for (int q = 0; q < nb; ++q)
+        for (int i = 0; i < d; ++i) {
+          double s = 0;
+          for (int k = 0; k < nb; ++k) s += R.B[(a * nb + q) * nb + k] * glam[k * d + i];
+          Be[a][q][i] = -vol * s;  // B_(a,i),q = - int lam_q d_i phi_a
+        }
+    for (int a = 0; a < nl; ++a) {
+      const int64_t na = L.cell_nodes[c * nl + a];
+      const int64_t ia = L.free_of_node[na];
+      if (ia < 0) continue;
+      for (int b = 0; b < nl; ++b) {
+        const int64_t nbn = L.cell_nodes[c * nl + b];
+        if (with_mfa) {
+          int32_t p = find_in_row(L.mfa_ptr, L.mfa_col, ia, nbn);
+          L.mfa_val[p] += Me[a][b];
+        }
+        const int64_t ib = L.free_of_node[nbn];
+        if (ib < 0) continue;
+        int32_t p = find_in_row(L.s_ptr, L.s_col, ia, ib);
+        L.s_M[p] += Me[a][b];
+        L.s_K1[p] += Ke[a][b];
+        conv[p] += Ce[a][b];
+      }
+      for (int q = 0; q < nb; ++q) {
+        int32_t p = find_in_row(L.b_ptr, L.b_col, ia, L.cells[c * nb + q]);
+        for (int i = 0; i < d; ++i) L.b_val[(size_t)p * d + i] += Be[a][q][i];
+      }
+    }
+  }
+  for (size_t p = 0; p < snnz; ++p) L.s_L[p] = nu * L.s_K1[p] + conv[p];
+  // L^T on the same symmetric pattern
+  L.s_Lt.assign(snnz, 0.0);
+  for (int64_t i = 0; i < L.nfree; ++i)
+    for (int32_t p = L.s_ptr[i]; p < L.s_ptr[i + 1]; ++p) {
+      int32_t q = find_in_row(L.s_ptr, L.s_col, L.s_col[p], i);
+      L.s_Lt[p] = L.s_L[q];
+    }
+  transpose_csr(L.nfree, L.nv, L.b_ptr, L.b_col, L.b_val, d, L.bt_ptr, L.bt_col, L.bt_val);
+}
+
+// --------------------------------------------------------------------------- patches
+void build_patches(HostLevel& L) {
+  const int nl = nloc_of(L.dim);
+  L.pn_ptr.assign(L.nv + 1, 0);
+  L.pn_node.clear();
+  L.pvv_ptr.assign(L.nv + 1, 0);
+  L.pvv.clear();
+  L.pvp.clear();
+  std::vector<int32_t> nodes;
+  for (int64_t v = 0; v < L.nv; ++v) {
+    nodes.clear();
+    for (int32_t p = L.node_cell_ptr[v]; p < L.node_cell_ptr[v + 1]; ++p) {
+      const int64_t c = L.node_cell[p];
+      for (int a = 0; a < nl; ++a) {
+        int32_t f = L.free_of_node[L.cell_nodes[c * nl + a]];
+        if (f >= 0) nodes.push_back(f);
+      }
+    }
+    std::sort(nodes.begin(), nodes.end());
+    nodes.erase(std::unique(nodes.begin(), nodes.end()), nodes.end());
+    for (size_t la = 0; la < nodes.size(); ++la) {
+      const int32_t i = nodes[la];
+      for (int32_t p = L.s_ptr[i]; p < L.s_ptr[i + 1]; ++p) {
+        auto it = std::lower_bound(nodes.begin(), nodes.end(), L.s_col[p]);
+        if (it != nodes.end() && *it == L.s_col[p]) {
+          L.pvv.push_back((int32_t)la);
+          L.pvv.push_back((int32_t)(it - nodes.begin()));
+          L.pvv.push_back(p);
+        }
+      }
+      L.pvp.push_back(find_in_row(L.b_ptr, L.b_col, i, v));
+    }
+    L.pn_node.insert(L.pn_node.end(), nodes.begin(), nodes.end());
+    L.pn_ptr[v + 1] = (int32_t)L.pn_node.size();
+    L.pvv_ptr[v + 1] = (int32_t)(L.pvv.size() / 3);
+  }
+}
+
+// ------------------------------------------------------------------------- transfers
+std::string build_transfer(const HostLevel& C, HostLevel& F, const int64_t* parent) {
+  const int d = F.dim, nb = d + 1, nlc = nloc_of(d), nlf = nloc_of(d);
+  std::vector<char> done_u(F.nfree, 0), done_p(F.nv, 0);
+  std::vector<std::vector<std::pair<int32_t, double>>> pu(F.nfree), pp(F.nv);
+  F.coarse_node_to_fine_vertex.assign(C.nn, -1);
+  double x[3], lam[4], w[10];
+  for (int64_t f = 0; f < F.nc; ++f) {
+    const int64_t pc = parent[f];
+    if (pc < 0 || pc >= C.nc) return "parent index out of range";
+    for (int a = 0; a < nlf; ++a) {
+      const int64_t node = F.cell_nodes[f * nlf + a];
+      const bool is_vertex = a < nb;
+      const int64_t fi = F.free_of_node[node];
+      const bool need_u = fi >= 0 && !done_u[fi];
+      const bool need_p = is_vertex && !done_p[node];
+      if (!need_u && !need_p) continue;
+      node_coord(F, node, x);
+      barycentric(C, pc, x, lam);
+      for (int k = 0; k < nb; ++k)
+        if (lam[k] < -1e-9) return "fine node outside its parent cell: levels are not nested";
+      if (need_u) {
+        done_u[fi] = 1;
+        p2_values(d, lam, w);
+        for (int b = 0; b < nlc; ++b) {
+          const int32_t cf = C.free_of_node[C.cell_nodes[pc * nlc + b]];
+          if (cf >= 0 && std::fabs(w[b]) > 1e-12) pu[fi].push_back({cf, w[b]});
+        }
+      }
+      if (need_p) {
+        done_p[node] = 1;
+        for (int k = 0; k < nb; ++k)
+          if (std::fabs(lam[k]) > 1e-12) pp[node].push_back({(int32_t)C.cells[pc * nb + k], lam[k]});
+        // a fine vertex is a coarse vertex or a coarse edge midpoint
+        int ones = 0, halves = 0, kk[2] = {-1, -1};
+        for (int k = 0; k < nb; ++k) {
+          if (std::fabs(lam[k] - 1.0) < 1e-9) kk[ones++] = k;
+          else if (std::fabs(lam[k] - 0.5) < 1e-9 && halves < 2) kk[halves++] = k;
+        }
+        if (ones == 1) {
+          F.coarse_node_to_fine_vertex[C.cells[pc * nb + kk[0]]] = node;
+        } else if (halves == 2) {
+          const int64_t a0 = C.cells[pc * nb + kk[0]], a1 = C.cells[pc * nb + kk[1]];
+          for (int e = 0; e < nlc - nb; ++e) {
+            const int64_t cn = C.cell_nodes[pc * nlc + nb + e];
+            const int64_t ea = C.edges[(cn - C.nv) * 2], eb = C.edges[(cn - C.nv) * 2 + 1];
+            if ((ea == a0 && eb == a1) || (ea == a1 && eb == a0))
+              F.coarse_node_to_fine_vertex[cn] = node;
+          }
+        }
+      }
+    }
+  }
+  for (int64_t i = 0; i < F.nfree; ++i)
+    if (!done_u[i]) return "fine free node not covered by any cell";
+  for (int64_t n = 0; n < C.nn; ++n)
+    if (F.coarse_node_to_fine_vertex[n] < 0)
+      return "coarse node without a coincident fine vertex: levels are not nested";
+  auto to_csr = [](std::vector<std::vector<std::pair<int32_t, double>>>& rows,
+                   std::vector<int32_t>& ptr, std::vector<int32_t>& col,
+                   std::vector<double>& val) {
+    ptr.assign(rows.size() + 1, 0);
+    col.clear();
+    val.clear();
+    for (size_t i = 0; i < rows.size(); ++i) {
+      std::sort(rows[i].begin(), rows[i].end());
+      for (auto& e : rows[i]) {
+        col.push_back(e.first);
+        val.push_back(e.second);
+      }
+      ptr[i + 1] = (int32_t)col.size();
+    }
+  };
+  to_csr(pu, F.pu_ptr, F.pu_col, F.pu_val);
+  to_csr(pp, F.pp_ptr, F.pp_col, F.pp_val);
+  transpose_csr(F.nfree, C.nfree, F.pu_ptr, F.pu_col, F.pu_val, 1, F.put_ptr, F.put_col,
+                F.put_val);
+  transpose_csr(F.nv, C.nv, F.pp_ptr, F.pp_col, F.pp_val, 1, F.ppt_ptr, F.ppt_col, F.ppt_val);
+  return "";
+}
+
+// ---------------------------------------------------------------- coarse inverse
+bool coarse_inverse(const HostLevel& L, int r, const double* A, double dt,
+                    std::vector<double>& inv) {
+  const int d = L.dim;
+  const int64_t offV = L.nfree * d * r;
+  const int64_t N = offV + L.nv * r;
+  std::vector<double> J((size_t)N * N, 0.0);  // row-major
+  auto vel = [&](int64_t i, int c, int s) { return (i * d + c) * r + s; };
+  auto pre = [&](int64_t v, int s) { return offV + v * r + s; };
+  for (int64_t i = 0; i < L.nfree; ++i) {
+    for (int32_t p = L.s_ptr[i]; p < L.s_ptr[i + 1]; ++p) {
+      const int64_t j = L.s_col[p];
+      for (int c = 0; c < d; ++c)
+        for (int s = 0; s < r; ++s)
+          for (int t = 0; t < r; ++t)
+            J[vel(i, c, s) * N + vel(j, c, t)] +=
+                (s == t ? L.s_M[p] : 0.0) + dt * A[s * r + t] * L.s_L[p];
+    }
+    for (int32_t p = L.b_ptr[i]; p < L.b_ptr[i + 1]; ++p) {
+      const int64_t v = L.b_col[p];
+      for (int c = 0; c < d; ++c)
+        for (int s = 0; s < r; ++s)
+          for (int t = 0; t < r; ++t) {
+            const double val = dt * A[s * r + t] * L.b_val[(size_t)p * d + c];
+            J[vel(i, c, s) * N + pre(v, t)] += val;
+            J[pre(v, s) * N + vel(i, c, t)] += val;
+          }
+    }
+  }
+  for (int s = 0; s < r; ++s) {  // pin the pressure of vertex 0 in every stage
+    const int64_t q = pre(0, s);
+    for (int64_t k = 0; k < N; ++k) {
+      J[q * N + k] = 0.0;
+      J[k * N + q] = 0.0;
+    }
+    J[q * N + q] = 1.0;
+  }
+  // in-place Gauss--Jordan with partial pivoting
+  std::vector<int64_t> swp(N);
+  double scale = 0;
+  for (double v : J) scale = std::max(scale, std::fabs(v));
+  for (int64_t k = 0; k < N; ++k) {
+    int64_t piv = k;
+    double best = std::fabs(J[k * N + k]);
+    for (int64_t i = k + 1; i < N; ++i)
+      if (std::fabs(J[i * N + k]) > best) {
+        best = std::fabs(J[i * N + k]);
+        piv = i;
+      }
+    if (!(best > 1e-300) || best < 1e-14 * scale) return false;
+    swp[k] = piv;
+    if (piv != k)
+      for (int64_t j = 0; j < N; ++j) std::swap(J[k * N + j], J[piv * N + j]);
+    const double ip = 1.0 / J[k * N + k];
+    J[k * N + k] = 1.0;
+    for (int64_t j = 0; j < N; ++j) J[k * N + j] *= ip;
+    for (int64_t i = 0; i < N; ++i) {
+      if (i == k) continue;
+      const double f = J[i * N + k];
+      if (f == 0.0) continue;
+      J[i * N + k] = 0.0;
+      double* ri = &J[i * N];
+      const double* rk = &J[k * N];
+      for (int64_t j = 0; j < N; ++j) ri[j] -= f * rk[j];
+    }
+  }
+  for (int64_t k = N - 1; k >= 0; --k)
+    if (swp[k] != k)
+      for (int64_t i = 0; i < N; ++i) std::swap(J[i * N + k], J[i * N + swp[k]]);
+  inv.resize((size_t)N * N);
+  for (int64_t i = 0; i < N; ++i)
+    for (int64_t j = 0; j < N; ++j) inv[j * N + i] = J[i * N + j];  // column-major
+  return true;
+}
+
+}  // namespace irk

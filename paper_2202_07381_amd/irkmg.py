@@ -1,0 +1,254 @@
+"""Thin ctypes binding of libirkmg (include/irk_mg.h).
+
+Argument marshalling only: every step of the method runs in the HIP library.  Names
+follow the C ABI.  Device vectors are torch float64 CUDA tensors; the current torch
+stream is passed to every call.  Importing this module loads ``libirkmg.so`` and fails
+loudly if it has not been built (``__graft_entry__.build()``).
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import re
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libirkmg.so")
+HEADER = os.path.join(os.path.dirname(_HERE), "include", "irk_mg.h")
+
+IRK_OK, IRK_EINVAL, IRK_ENOMEM, IRK_EHIP, IRK_ESINGULAR, IRK_ENAN, IRK_ENOCONV = 0, -1, -2, -3, -4, -5, 1
+FAMILIES = {"radauIIA": 0, "gauss": 1, "lobattoIIIC": 2}
+
+
+class IrkError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"irk status {status}: {msg}")
+        self.status = status
+
+
+class irk_mesh_level(C.Structure):
+    _fields_ = [("dim", C.c_int), ("nverts", C.c_int64), ("ncells", C.c_int64),
+                ("xyz", C.c_void_p), ("cells", C.c_void_p), ("parent", C.c_void_p)]
+
+
+class irk_tableau(C.Structure):
+    _fields_ = [("r", C.c_int), ("A", C.c_void_p), ("b", C.c_void_p), ("c", C.c_void_p)]
+
+
+class irk_mg_opts(C.Structure):
+    _fields_ = [("pre", C.c_int), ("post", C.c_int), ("omega", C.c_double),
+                ("weighting", C.c_int), ("precision", C.c_int)]
+
+
+class irk_solve_info(C.Structure):
+    _fields_ = [("iterations", C.c_int), ("converged", C.c_int), ("rel_residual", C.c_double),
+                ("history", C.POINTER(C.c_double)), ("history_cap", C.c_int),
+                ("ms_vcycle", C.c_double), ("ms_total", C.c_double)]
+
+
+def _load() -> C.CDLL:
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is missing: build it with __graft_entry__.build()")
+    lib = C.CDLL(LIB_PATH)
+    vp, i64, d, i = C.c_void_p, C.c_int64, C.c_double, C.c_int
+    sig = {
+        "irk_mg_default_opts": (None, [vp]),
+        "irk_tableau_builtin": (i, [i, i, vp, vp, vp]),
+        "irk_mesh_p2_nodes": (i, [vp, vp, vp]),
+        "irk_mg_setup": (i, [vp, i, vp, d, d, vp, vp, vp, vp]),
+        "irk_mg_destroy": (None, [vp]),
+        "irk_mg_ndofs": (i64, [vp, i]),
+        "irk_mg_sizes": (i, [vp, i, vp]),
+        "irk_mg_p2_nodes": (i, [vp, i, vp, vp]),
+        "irk_mg_apply": (i, [vp, vp, vp, i, vp]),
+        "irk_mg_vcycle": (i, [vp, vp, vp, vp]),
+        "irk_mg_vcycle_transpose": (i, [vp, vp, vp, vp]),
+        "irk_fgmres_solve": (i, [vp, vp, vp, d, i, i, vp, vp]),
+        "irk_adjoint_solve": (i, [vp, vp, vp, d, i, i, vp, vp]),
+        "irk_rhs": (i, [vp, vp, vp, vp, vp]),
+        "irk_update": (i, [vp, vp, vp, vp]),
+        "irk_level_apply": (i, [vp, i, i, vp, vp, vp]),
+        "irk_level_sweep": (i, [vp, i, i, vp, vp, vp]),
+        "irk_level_restrict": (i, [vp, i, vp, vp, vp]),
+        "irk_level_prolong": (i, [vp, i, vp, vp, vp]),
+        "irk_coarse_solve": (i, [vp, i, vp, vp, vp]),
+        "irk_last_error": (C.c_char_p, []),
+    }
+    for name, (res, args) in sig.items():
+        f = getattr(lib, name)
+        f.restype = res
+        f.argtypes = args
+    return lib
+
+
+lib = _load()
+
+
+def header_functions() -> list[str]:
+    """Names of the functions the public header declares."""
+    txt = open(HEADER).read()
+    return sorted(set(re.findall(r"^\s*(?:irk_status|void|int64_t|const char\*)\s+(irk_\w+)\s*\(", txt, re.M)))
+
+
+def _check(status: int, ok=(IRK_OK,)) -> int:
+    if status not in ok:
+        raise IrkError(status, lib.irk_last_error().decode())
+    return status
+
+
+def irk_tableau_builtin(family: str, r: int):
+    A, b, c = np.zeros(16), np.zeros(4), np.zeros(4)
+    _check(lib.irk_tableau_builtin(FAMILIES[family], r, A.ctypes.data, b.ctypes.data, c.ctypes.data))
+    return A[: r * r].reshape(r, r).copy(), b[:r].copy(), c[:r].copy()
+
+
+def _mesh_struct(level) -> tuple[irk_mesh_level, list]:
+    xyz = np.ascontiguousarray(level.xyz, dtype=np.float64)
+    cells = np.ascontiguousarray(level.cells, dtype=np.int64)
+    keep = [xyz, cells]
+    par = None
+    if getattr(level, "parent", None) is not None:
+        par = np.ascontiguousarray(level.parent, dtype=np.int64)
+        keep.append(par)
+    s = irk_mesh_level(level.dim, xyz.shape[0], cells.shape[0], xyz.ctypes.data, cells.ctypes.data,
+                       par.ctypes.data if par is not None else None)
+    return s, keep
+
+
+def irk_mesh_p2_nodes(level) -> np.ndarray:
+    s, keep = _mesh_struct(level)
+    n = C.c_int64(0)
+    _check(lib.irk_mesh_p2_nodes(C.byref(s), C.byref(n), None))
+    xyz = np.zeros((n.value, level.dim))
+    _check(lib.irk_mesh_p2_nodes(C.byref(s), C.byref(n), xyz.ctypes.data))
+    return xyz
+
+
+def _stream(stream=None) -> int:
+    import torch
+
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return stream.cuda_stream
+
+
+def _dev(t, n: int, name: str) -> int:
+    import torch
+
+    if not isinstance(t, torch.Tensor) or not t.is_cuda or t.dtype != torch.float64 or not t.is_contiguous():
+        raise ValueError(f"{name} must be a contiguous float64 CUDA tensor")
+    if t.numel() != n:
+        raise ValueError(f"{name} has {t.numel()} entries, expected {n}")
+    return t.data_ptr()
+
+
+class IrkMG:
+    """Handle of one hierarchy (irk_mg_setup ... irk_mg_destroy)."""
+
+    def __init__(self, levels, A, b, c, dt: float, nu: float, wind_nodal=None, pre=2, post=2,
+                 omega=0.5, weighting=1, precision=0, stream=None):
+        structs, keep = [], []
+        for lv in levels:
+            s, k = _mesh_struct(lv)
+            structs.append(s)
+            keep += k
+        arr = (irk_mesh_level * len(structs))(*structs)
+        A = np.ascontiguousarray(A, dtype=np.float64)
+        self.A, self.b, self.c = A, np.ascontiguousarray(b, dtype=np.float64), np.ascontiguousarray(c, dtype=np.float64)
+        self.r = len(self.b)
+        tab = irk_tableau(self.r, A.ctypes.data, self.b.ctypes.data, self.c.ctypes.data)
+        opts = irk_mg_opts(pre, post, omega, weighting, precision)
+        w = None
+        if wind_nodal is not None:
+            w = np.ascontiguousarray(wind_nodal, dtype=np.float64)
+        h = C.c_void_p()
+        _check(lib.irk_mg_setup(arr, len(structs), C.byref(tab), dt, nu, w.ctypes.data if w is not None else None,
+                                C.byref(opts), _stream(stream), C.byref(h)))
+        self.h = h
+        self.dt, self.nu, self.precision = dt, nu, precision
+        self.nlevels = len(structs)
+        self.dim = levels[0].dim
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib.irk_mg_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        self.close()
+
+    # ---------------------------------------------------------------- sizes
+    def irk_mg_ndofs(self, level: int = -1) -> int:
+        return int(lib.irk_mg_ndofs(self.h, level))
+
+    def irk_mg_sizes(self, level: int = -1) -> dict:
+        out = np.zeros(5, dtype=np.int64)
+        _check(lib.irk_mg_sizes(self.h, level, out.ctypes.data))
+        return dict(nverts=int(out[0]), nnodes=int(out[1]), nfree=int(out[2]), ns=int(out[3]), nlevels=int(out[4]))
+
+    def irk_mg_p2_nodes(self, level: int = -1):
+        sz = self.irk_mg_sizes(level)
+        xyz = np.zeros((sz["nnodes"], self.dim))
+        free = np.zeros(sz["nfree"], dtype=np.int64)
+        _check(lib.irk_mg_p2_nodes(self.h, level, xyz.ctypes.data, free.ctypes.data))
+        return xyz, free
+
+    # ------------------------------------------------------------- operators
+    def irk_mg_apply(self, x, y, transpose=False, stream=None):
+        n = self.irk_mg_ndofs()
+        _check(lib.irk_mg_apply(self.h, _dev(x, n, "x"), _dev(y, n, "y"), int(transpose), _stream(stream)))
+
+    def irk_mg_vcycle(self, r, z, stream=None):
+        n = self.irk_mg_ndofs()
+        _check(lib.irk_mg_vcycle(self.h, _dev(r, n, "r"), _dev(z, n, "z"), _stream(stream)))
+
+    def irk_mg_vcycle_transpose(self, r, z, stream=None):
+        n = self.irk_mg_ndofs()
+        _check(lib.irk_mg_vcycle_transpose(self.h, _dev(r, n, "r"), _dev(z, n, "z"), _stream(stream)))
+
+    def _solve(self, fn, F, k, rtol, maxit, restart, history_cap, stream):
+        n = self.irk_mg_ndofs()
+        hist = np.zeros(max(1, history_cap))
+        info = irk_solve_info(0, 0, 0.0, hist.ctypes.data_as(C.POINTER(C.c_double)), history_cap, 0.0, 0.0)
+        st = _check(fn(self.h, _dev(F, n, "F"), _dev(k, n, "k"), rtol, maxit, restart, C.byref(info), _stream(stream)),
+                    ok=(IRK_OK, IRK_ENOCONV))
+        its = info.iterations
+        return dict(status=st, iterations=its, converged=bool(info.converged), rel_residual=info.rel_residual,
+                    history=hist[: min(history_cap, its + 1)].copy(), ms_vcycle=info.ms_vcycle, ms_total=info.ms_total)
+
+    def irk_fgmres_solve(self, F, k, rtol=1e-8, maxit=1000, restart=30, history_cap=1024, stream=None):
+        return self._solve(lib.irk_fgmres_solve, F, k, rtol, maxit, restart, history_cap, stream)
+
+    def irk_adjoint_solve(self, G, lam, rtol=1e-8, maxit=1000, restart=30, history_cap=1024, stream=None):
+        return self._solve(lib.irk_adjoint_solve, G, lam, rtol, maxit, restart, history_cap, stream)
+
+    def irk_rhs(self, f_nodal, state, F, stream=None):
+        sz = self.irk_mg_sizes()
+        _check(lib.irk_rhs(self.h, _dev(f_nodal, self.r * sz["nnodes"] * self.dim, "f"), _dev(state, sz["ns"], "state"),
+                           _dev(F, self.irk_mg_ndofs(), "F"), _stream(stream)))
+
+    def irk_update(self, k, state, stream=None):
+        sz = self.irk_mg_sizes()
+        _check(lib.irk_update(self.h, _dev(k, self.irk_mg_ndofs(), "k"), _dev(state, sz["ns"], "state"), _stream(stream)))
+
+    # ------------------------------------------------------------ per level
+    def irk_level_apply(self, level, x, y, transpose=False, stream=None):
+        n = self.irk_mg_ndofs(level)
+        _check(lib.irk_level_apply(self.h, level, int(transpose), _dev(x, n, "x"), _dev(y, n, "y"), _stream(stream)))
+
+    def irk_level_sweep(self, level, F, k, transpose=False, stream=None):
+        n = self.irk_mg_ndofs(level)
+        _check(lib.irk_level_sweep(self.h, level, int(transpose), _dev(F, n, "F"), _dev(k, n, "k"), _stream(stream)))
+
+    def irk_level_restrict(self, level, xf, xc, stream=None):
+        _check(lib.irk_level_restrict(self.h, level, _dev(xf, self.irk_mg_ndofs(level), "xf"),
+                                      _dev(xc, self.irk_mg_ndofs(level - 1), "xc"), _stream(stream)))
+
+    def irk_level_prolong(self, level, xc, xf, stream=None):
+        _check(lib.irk_level_prolong(self.h, level, _dev(xc, self.irk_mg_ndofs(level - 1), "xc"),
+                                     _dev(xf, self.irk_mg_ndofs(level), "xf"), _stream(stream)))
+
+    def irk_coarse_solve(self, b, x, transpose=False, stream=None):
+        n = self.irk_mg_ndofs(0)
+        _check(lib.irk_coarse_solve(self.h, int(transpose), _dev(b, n, "b"), _dev(x, n, "x"), _stream(stream)))

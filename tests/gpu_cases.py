@@ -1,0 +1,93 @@
+"""Shared set-up for GPU parity tests: the same seeded workload handed to the HIP
+library (through the C ABI) and to the CPU oracle."""
+import functools
+import sys
+
+import numpy as np
+
+from oracle.multigrid import Hierarchy
+from oracle.tableau import tableau
+from paper_2202_07381_amd import workloads as wl
+
+CASES = {
+    # name: (dim, n_coarse, nlevels, family, r, dt, nu, wind seed or None)
+    "c1": (2, 4, 3, "radauIIA", 2, 1 / 16, 1.0, None),
+    "r3": (2, 4, 4, "radauIIA", 3, 1e-2, 1.0, None),
+    "oseen": (2, 4, 3, "gauss", 2, 5e-3, 0.01, 3),
+    "be": (2, 2, 3, "radauIIA", 1, 0.05, 0.3, None),
+    "lob3": (2, 2, 3, "lobattoIIIC", 3, 0.02, 1.0, None),
+}
+
+
+def say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def torch_dev():
+    import torch
+
+    return torch.device("cuda:0")
+
+
+def levels_of(case):
+    dim, nc, nl = CASES[case][:3]
+    return wl.square_hierarchy(nc, nl) if dim == 2 else wl.cube_hierarchy(nc, nl)
+
+
+def wind_of(case):
+    dim, nc, nl, fam, r, dt, nu, ws = CASES[case]
+    if ws is None:
+        return None
+    return wl.wind_2d(ws, nc * 2 ** (nl - 1))
+
+
+@functools.lru_cache(maxsize=None)
+def oracle_of(case, dtype=np.float64):
+    dim, nc, nl, fam, r, dt, nu, ws = CASES[case]
+    A, b, c = tableau(fam, r)
+    return Hierarchy(levels_of(case), A, dt, nu, wind=wind_of(case), dtype=dtype)
+
+
+_GPU = {}
+
+
+def gpu_of(case, precision=0):
+    key = (case, precision)
+    if key not in _GPU:
+        from paper_2202_07381_amd import irkmg
+
+        dim, nc, nl, fam, r, dt, nu, ws = CASES[case]
+        lv = levels_of(case)
+        A, b, c = irkmg.irk_tableau_builtin(fam, r)
+        wind = wind_of(case)
+        wn = wind(irkmg.irk_mesh_p2_nodes(lv[-1])) if wind is not None else None
+        say(f"[setup] case={case} precision={precision} N={r * 0}")
+        _GPU[key] = irkmg.IrkMG(lv, A, b, c, dt, nu, wind_nodal=wn, precision=precision)
+        say(f"[setup] done case={case} N={_GPU[key].irk_mg_ndofs()}")
+    return _GPU[key]
+
+
+def to_dev(x):
+    import torch
+
+    return torch.tensor(np.ascontiguousarray(x), dtype=torch.float64, device=torch_dev())
+
+
+def to_host(t):
+    import torch
+
+    torch.cuda.synchronize()
+    return t.cpu().numpy()
+
+
+def relerr(a, b):
+    return float(np.abs(a - b).max() / max(np.abs(b).max(), 1e-300))
+
+
+def forcing_rhs(case):
+    """F of the first step from rest with the seeded 2D forcing (oracle side)."""
+    H = oracle_of(case)
+    S = H.finest
+    f = wl.forcing_2d(1)
+    return S.rhs([S.th.interpolate(f, 0.0)] * S.r, np.zeros(S.th.nvel), np.zeros(S.th.nverts))

@@ -1,0 +1,90 @@
+"""CPU checks of the C-ABI library: it loads, exports every declared symbol, and
+rejects invalid arguments before touching a device."""
+import ctypes as C
+
+import numpy as np
+import pytest
+
+from oracle.fem import TaylorHood
+from oracle.tableau import tableau
+from paper_2202_07381_amd import irkmg
+from paper_2202_07381_amd import workloads as wl
+
+
+def test_exports_every_declared_symbol():
+    names = irkmg.header_functions()
+    assert len(names) >= 20
+    for n in names:
+        assert hasattr(irkmg.lib, n), n
+
+
+@pytest.mark.parametrize("fam,r", [("radauIIA", 1), ("radauIIA", 2), ("radauIIA", 3), ("gauss", 1), ("gauss", 2),
+                                   ("gauss", 3), ("lobattoIIIC", 2), ("lobattoIIIC", 3)])
+def test_builtin_tableaux_match_oracle(fam, r):
+    A, b, c = irkmg.irk_tableau_builtin(fam, r)
+    Ao, bo, co = tableau(fam, r)
+    assert np.abs(A - Ao).max() < 1e-15 and np.abs(b - bo).max() < 1e-15 and np.abs(c - co).max() < 1e-15
+
+
+def test_unknown_tableau_rejected():
+    with pytest.raises(irkmg.IrkError) as e:
+        irkmg.irk_tableau_builtin("lobattoIIIC", 1)
+    assert e.value.status == irkmg.IRK_EINVAL
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_p2_node_numbering_matches_oracle(dim):
+    xyz, cells = wl.square_mesh(5) if dim == 2 else wl.cube_mesh(2)
+    got = irkmg.irk_mesh_p2_nodes(wl.MeshLevel(dim, xyz, cells, None))
+    assert np.array_equal(got, TaylorHood(xyz, cells).node_xyz)
+
+
+def _setup_status(levels, r=2, dt=0.1, nu=1.0, opts=None, nlev=None):
+    structs = []
+    keep = []
+    for lv in levels:
+        s, k = irkmg._mesh_struct(lv)
+        structs.append(s)
+        keep += k
+    arr = (irkmg.irk_mesh_level * max(1, len(structs)))(*structs)
+    A, b, c = np.eye(max(r, 1)) * 0.5, np.ones(max(r, 1)) / max(r, 1), np.ones(max(r, 1))
+    tab = irkmg.irk_tableau(r, A.ctypes.data, b.ctypes.data, c.ctypes.data)
+    h = C.c_void_p()
+    st = irkmg.lib.irk_mg_setup(arr, len(structs) if nlev is None else nlev, C.byref(tab), dt, nu, None,
+                                C.byref(opts) if opts else None, None, C.byref(h))
+    return st, irkmg.lib.irk_last_error().decode()
+
+
+def test_setup_validation_before_device_work():
+    lv = wl.square_hierarchy(2, 2)
+    assert _setup_status(lv, r=5)[0] == irkmg.IRK_EINVAL
+    assert _setup_status(lv, r=0)[0] == irkmg.IRK_EINVAL
+    assert _setup_status(lv, nlev=0)[0] == irkmg.IRK_EINVAL
+    assert _setup_status(lv, dt=-1.0)[0] == irkmg.IRK_EINVAL
+    assert _setup_status(lv, nu=float("nan"))[0] == irkmg.IRK_EINVAL
+    bad = wl.square_hierarchy(2, 2)
+    bad[1].parent = None
+    assert _setup_status(bad)[0] == irkmg.IRK_EINVAL
+    bad = wl.square_hierarchy(2, 2)
+    bad[1].parent = bad[1].parent.copy()
+    bad[1].parent[3] = 10**6
+    st, msg = _setup_status(bad)
+    assert st == irkmg.IRK_EINVAL and "parent" in msg
+    bad = wl.square_hierarchy(2, 2)
+    bad[1].cells = bad[1].cells.copy()
+    bad[1].cells[0, 0] = -4
+    assert _setup_status(bad)[0] == irkmg.IRK_EINVAL
+    # a level that is not a uniform refinement
+    skip = [wl.square_hierarchy(2, 1)[0], wl.square_hierarchy(2, 3)[2]]
+    assert _setup_status(skip)[0] == irkmg.IRK_EINVAL
+    opts = irkmg.irk_mg_opts(2, 2, -0.5, 1, 0)
+    assert _setup_status(lv, opts=opts)[0] == irkmg.IRK_EINVAL
+    opts = irkmg.irk_mg_opts(2, 2, 0.5, 3, 0)
+    assert _setup_status(lv, opts=opts)[0] == irkmg.IRK_EINVAL
+
+
+def test_null_handle_calls_fail_cleanly():
+    assert irkmg.lib.irk_mg_vcycle(None, None, None, None) == irkmg.IRK_EINVAL
+    assert irkmg.lib.irk_fgmres_solve(None, None, None, 1e-8, 10, 30, None, None) == irkmg.IRK_EINVAL
+    assert irkmg.lib.irk_mg_ndofs(None, -1) == -1
+    irkmg.lib.irk_mg_destroy(None)
