@@ -1,10 +1,14 @@
 """GPU parity of every step of the hot path against the CPU oracle, through the C ABI.
 
 Tolerances: single operator applications (residual, transfers) 1e-13 relative to the
-largest entry; patch sweeps, coarse solve and V-cycle 1e-11 (the patch inverses come
-from different elimination orders on the two sides, so they agree to the conditioning
-of the patch matrices times the unit roundoff); FGMRES solutions after equal
-iteration counts 1e-10 relative (the target stated for the method)."""
+largest entry; patch sweeps 1e-11 (the patch inverses come from different elimination
+orders on the two sides, so they agree to the conditioning of the patch matrices
+times the unit roundoff); coarse solve and V-cycle max(1e-11, 4 cond(J_0) eps): the
+library applies an explicit Gauss--Jordan inverse of the pinned coarse operator and
+the oracle an LU solve, two backward-stable solves whose results differ by up to the
+condition number times the unit roundoff (cond(J_0) reaches 1e8 at dt = 1e-2);
+FGMRES solutions after equal iteration counts 1e-10 relative (the target stated for
+the method)."""
 import numpy as np
 import pytest
 
@@ -62,6 +66,15 @@ def test_transfers(case):
         assert relerr(to_host(fine), base + P @ xc) < 1e-13
 
 
+def coarse_tol(H):
+    J = H.systems[0].J.toarray()
+    for q in H.pinned:
+        J[q, :] = 0.0
+        J[:, q] = 0.0
+        J[q, q] = 1.0
+    return max(1e-11, 4 * np.linalg.cond(J) * np.finfo(float).eps)
+
+
 @pytest.mark.parametrize("case", ALL)
 def test_coarse_solve(case):
     g, H = gpu_of(case), oracle_of(case)
@@ -71,7 +84,7 @@ def test_coarse_solve(case):
         say(f"[coarse] case={case} transpose={tr}")
         x = torch.zeros_like(to_dev(b))
         g.irk_coarse_solve(to_dev(b), x, transpose=tr)
-        assert relerr(to_host(x), H.coarse_solve(b, tr)) < 1e-11
+        assert relerr(to_host(x), H.coarse_solve(b, tr)) < coarse_tol(H)
 
 
 @pytest.mark.parametrize("case", ALL)
@@ -81,10 +94,10 @@ def test_vcycle(case):
     say(f"[vcycle] case={case}")
     z = torch.zeros(r.size, dtype=torch.float64, device="cuda")
     g.irk_mg_vcycle(to_dev(r), z)
-    assert relerr(to_host(z), H.vcycle(r)) < 1e-11
+    assert relerr(to_host(z), H.vcycle(r)) < coarse_tol(H)
     say(f"[vcycle^T] case={case}")
     g.irk_mg_vcycle_transpose(to_dev(r), z)
-    assert relerr(to_host(z), H.vcycle_transpose(r)) < 1e-11
+    assert relerr(to_host(z), H.vcycle_transpose(r)) < coarse_tol(H)
 
 
 @pytest.mark.parametrize("case", ALL)
