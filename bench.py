@@ -1,0 +1,240 @@
+#!/usr/bin/env python3
+"""Benchmark of the stage-coupled Vanka multigrid path on one MI355X.
+
+Workload (all inputs seeded and synthetic): 2D Stokes on the 256 x 256 triangulated
+unit square, Taylor--Hood P2-P1 (588,291 unknowns per stage), 3-stage RadauIIA,
+dt = 1e-2, nu = 1, manufactured solution from a 16-mode stream function (seed 2);
+7-level geometric V-cycle (4 x 4 coarsest mesh) with 2 pre- and 2 post-sweeps of
+the additive vertex-star Vanka smoother, omega = 0.5, preconditioning FGMRES(30) to a
+relative residual of 1e-8.
+
+A step is one IRK time step: right-hand side, FGMRES solve from a zero initial guess
+(every V-cycle inside it: residuals, patch solves, transfers, coarse solve), and the
+stage update.  Inputs (forcing at every stage time of every step) are resident in
+device memory before the timed region.  The FP64 path gives the headline value; the
+FP32-patch path (FP32 patch factors and V-cycle inside FP64 FGMRES) is reported
+beside it, with its speedup and its solution difference from the FP64 path.
+
+value = stage-DOF updates per second = (unknowns of the finest level) x (V-cycles
+applied in the timed steps) / (timed wall time), so FGMRES, right-hand-side and
+update work are charged to the V-cycles.
+
+The roofline object is for the dominant kernel, the finest-level patch apply, timed
+with HIP events around each of its launches on its own stream inside the timed
+region; achieved = algorithmic bytes per launch / average launch time.
+The cpu_baseline object times the CPU oracle's V-cycle on a bounded sample (the same
+workload family on the 128 x 128 mesh, 6 levels), single-threaded.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "Vanka V-cycle stage-DOF updates/s + time to 1e-8 rel. residual, FP32 vs FP64"
+HBM_PEAK_GBS = 8000.0
+
+
+def log(msg: str) -> None:
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def run_precision(precision, levels, A, b, c, dt, nu, mms, nodes, steps, warmup, profile):
+    import numpy as np
+    import torch
+
+    from paper_2202_07381_amd import irkmg
+
+    t0 = time.time()
+    g = irkmg.IrkMG(levels, A, b, c, dt, nu, precision=precision)
+    torch.cuda.synchronize()
+    setup_s = time.time() - t0
+    sz = g.irk_mg_sizes()
+    _, free = g.irk_mg_p2_nodes()
+    N = g.irk_mg_ndofs()
+    r = len(b)
+    log(f"precision={precision} setup {setup_s:.2f}s N={N}")
+    u0 = mms.velocity(nodes[free], 0.0)
+    state = torch.tensor(np.concatenate([u0[:, 0], u0[:, 1], np.zeros(sz["nverts"])]), device="cuda")
+    nsteps = warmup + steps
+    fdev = []
+    for n in range(nsteps):
+        fn = np.stack([mms(nodes, (n + ci) * dt) for ci in c])  # (r, nnodes, 2)
+        fdev.append(torch.tensor(fn.ravel(), device="cuda"))
+    F = torch.zeros(N, dtype=torch.float64, device="cuda")
+    k = torch.zeros_like(F)
+    its = []
+
+    def step(n):
+        g.irk_rhs(fdev[n], state, F)
+        k.zero_()
+        info = g.irk_fgmres_solve(F, k, rtol=1e-8, maxit=300, restart=30, history_cap=0)
+        if not info["converged"]:
+            raise RuntimeError(f"FGMRES did not converge at step {n}: {info}")
+        g.irk_update(k, state)
+        return info
+
+    for n in range(warmup):
+        step(n)
+        log(f"precision={precision} warmup step {n} done")
+    torch.cuda.synchronize()
+    if profile:
+        g.irk_mg_profile(True)
+    t0 = time.perf_counter()
+    infos = []
+    for n in range(warmup, nsteps):
+        infos.append(step(n))
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    if profile:
+        g.irk_mg_profile(False)
+    its = [i["iterations"] for i in infos]
+    log(f"precision={precision} timed {steps} steps in {elapsed:.3f}s, iterations {its}")
+    out = dict(
+        N=N, setup_s=setup_s, elapsed_s=elapsed, iterations=its,
+        rel_residual=max(i["rel_residual"] for i in infos),
+        ms_per_step=1000.0 * elapsed / steps,
+        value=N * sum(its) / elapsed,
+        state=state.cpu().numpy(),
+    )
+    if profile:
+        out["stats"] = {kname: g.irk_mg_kernel_stats(kname, -1) for kname in ("patch_apply", "residual", "gather_update")}
+    # V-cycle alone (preconditioner application on a fixed residual)
+    rv = torch.tensor(np.random.default_rng(7).standard_normal(N), device="cuda")
+    z = torch.zeros_like(rv)
+    for _ in range(2):
+        g.irk_mg_vcycle(rv, z)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    nv = 10
+    e0.record()
+    for _ in range(nv):
+        g.irk_mg_vcycle(rv, z)
+    e1.record()
+    torch.cuda.synchronize()
+    out["vcycle_ms"] = e0.elapsed_time(e1) / nv
+    out["vcycle_updates_per_s"] = N / (out["vcycle_ms"] * 1e-3)
+    g.close()
+    return out
+
+
+def cpu_baseline(A, dt, nu):
+    import numpy as np
+    from threadpoolctl import threadpool_limits
+
+    from oracle.multigrid import Hierarchy
+    from paper_2202_07381_amd import workloads as wl
+
+    levels = wl.square_hierarchy(4, 6)  # 128 x 128 sample of the same workload family
+    t0 = time.time()
+    H = Hierarchy(levels, A, dt, nu)
+    log(f"oracle setup (128x128) {time.time() - t0:.1f}s")
+    N = H.finest.n
+    rv = np.random.default_rng(7).standard_normal(N)
+    with threadpool_limits(limits=1):
+        H.vcycle(rv)
+        t0 = time.perf_counter()
+        reps = 2
+        for _ in range(reps):
+            H.vcycle(rv)
+        dtv = (time.perf_counter() - t0) / reps
+    log(f"oracle V-cycle {dtv:.2f}s")
+    return {"value": N / dtv, "unit": "stage-DOF updates/s", "cores": 1, "kind": "oracle",
+            "sample": f"one oracle V-cycle (7-level workload family, here 6 levels on the 128x128 mesh, "
+                      f"{N} unknowns, RadauIIA(3), dt=1e-2, nu=1), mean of {reps} after one warm-up, "
+                      f"single-threaded NumPy/SciPy; setup excluded",
+            "vcycle_s": dtv}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--n", type=int, default=256, help="finest mesh size (power-of-two multiple of 4)")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-fp32", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(the sharding design is described in DESIGN.md); run with --gpus 1.", file=sys.stderr)
+        sys.exit(2)
+    import numpy as np
+    import torch
+
+    from paper_2202_07381_amd import irkmg
+    from paper_2202_07381_amd import workloads as wl
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    nlev = int(round(np.log2(args.n // 4))) + 1
+    levels = wl.square_hierarchy(4, nlev)
+    A, b, c = irkmg.irk_tableau_builtin("radauIIA", 3)
+    dt, nu = 1e-2, 1.0
+    mms = wl.mms_2d(2, nu)
+    nodes = irkmg.irk_mesh_p2_nodes(levels[-1])
+
+    r64 = run_precision(0, levels, A, b, c, dt, nu, mms, nodes, args.steps, args.warmup, profile=True)
+    r32 = None if args.no_fp32 else run_precision(1, levels, A, b, c, dt, nu, mms, nodes, args.steps, args.warmup,
+                                                  profile=True)
+    st = r64["stats"]["patch_apply"]
+    avg_ms = st["ms_total"] / max(1, st["launches"])
+    achieved = st["bytes_per_launch"] / (avg_ms * 1e-3) / 1e9
+    line = {
+        "metric": METRIC,
+        "value": r64["value"],
+        "unit": "stage-DOF updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": r64["ms_per_step"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {
+            "workload": f"2D Stokes {args.n}x{args.n} P2-P1, RadauIIA(3), dt=1e-2, nu=1, MMS seed 2, "
+                        f"{nlev}-level V-cycle 2/2 additive Vanka omega=0.5, FGMRES(30) to 1e-8",
+            "n": args.n, "levels": nlev, "stages": 3, "unknowns": r64["N"],
+        },
+        "time_to_1e-8_ms": r64["ms_per_step"],
+        "iterations_per_step": r64["iterations"],
+        "max_rel_residual": r64["rel_residual"],
+        "vcycle_ms": r64["vcycle_ms"],
+        "vcycle_only_updates_per_s": r64["vcycle_updates_per_s"],
+        "setup_s": r64["setup_s"],
+        "roofline": {
+            "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+            "kernel": "patch_apply (finest level)", "avg_launch_ms": avg_ms, "launches": st["launches"],
+            "bytes_per_launch": st["bytes_per_launch"],
+        },
+        "kernels_finest_level": {k: {"launches": v["launches"], "avg_ms": v["ms_total"] / max(1, v["launches"]),
+                                     "GB/s": v["bytes_per_launch"] / max(1e-12, v["ms_total"] / max(1, v["launches"]) * 1e-3) / 1e9}
+                                 for k, v in r64["stats"].items()},
+    }
+    if r32 is not None:
+        s32 = r32["stats"]["patch_apply"]
+        ms32 = s32["ms_total"] / max(1, s32["launches"])
+        diff = float(np.linalg.norm(r32["state"] - r64["state"]) / np.linalg.norm(r64["state"]))
+        line["fp32_patch"] = {
+            "value": r32["value"], "ms_per_step": r32["ms_per_step"], "iterations_per_step": r32["iterations"],
+            "max_rel_residual": r32["rel_residual"], "vcycle_ms": r32["vcycle_ms"],
+            "vcycle_only_updates_per_s": r32["vcycle_updates_per_s"],
+            "speedup_vs_fp64_step": r64["ms_per_step"] / r32["ms_per_step"],
+            "speedup_vs_fp64_vcycle": r64["vcycle_ms"] / r32["vcycle_ms"],
+            "state_rel_diff_vs_fp64": diff,
+            "patch_apply_GB/s": s32["bytes_per_launch"] / (ms32 * 1e-3) / 1e9,
+        }
+    if not args.no_cpu_baseline:
+        line["cpu_baseline"] = cpu_baseline(A, dt, nu)
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -197,6 +197,27 @@ irk_status irk_level_prolong(irk_mg* h, int level, const double* xc, double* xf,
 /* x = J_0^{-1} b on the coarsest level with pinned pressures (transpose: J_0^{-T}). */
 irk_status irk_coarse_solve(irk_mg* h, int transpose, const double* b, double* x, void* stream);
 
+/* Measurement of the V-cycle kernels.  irk_mg_profile(h, 1) clears the counters and
+ * brackets every later launch of the kernels below with HIP events on the stream it is
+ * launched on; irk_mg_profile(h, 0) stops recording.  irk_mg_kernel_stats waits for
+ * the recorded events and reports, for one kernel on one level (-1: finest), the number
+ * of launches, their summed GPU time and the algorithmic bytes one launch moves:
+ *   kernel 0  patch apply:   stored patch inverses (sum_v n_v^2 values) + one read of
+ *                            the residual (N values) + the local corrections written
+ *                            (sum_v n_v values);
+ *   kernel 1  residual:      scalar P2 blocks (column index + M + L per entry), B and
+ *                            B^T (index + dim values per entry), F and x read, r written;
+ *   kernel 2  gather update: local corrections and their slot indices read, x read and
+ *                            written, weights read.
+ * Values are 8 bytes (FP64 mode) or 4 bytes (FP32 mode), indices 4 bytes. */
+typedef struct irk_kernel_stats {
+  int64_t launches;
+  double ms_total;
+  double bytes_per_launch;
+} irk_kernel_stats;
+irk_status irk_mg_profile(irk_mg* h, int enable);
+irk_status irk_mg_kernel_stats(irk_mg* h, int kernel, int level, irk_kernel_stats* out);
+
 /* Description of the last error on the calling thread ("" if none). */
 const char* irk_last_error(void);
 

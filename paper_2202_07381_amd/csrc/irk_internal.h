@@ -117,6 +117,9 @@ struct DevLevel {
   int max_nloc = 0;
   int32_t* sched = nullptr;  // patch launch order (largest first)
 
+  // algorithmic bytes per launch of patch apply, residual and gather update
+  double alg_bytes[3] = {0, 0, 0};
+
   // work vectors (internal layout) in the working precision
   void *b = nullptr, *x = nullptr, *res = nullptr, *Y = nullptr;
 };
@@ -140,6 +143,14 @@ struct Handle {
   double* partials = nullptr;  // reduction partials
   double* hbuf = nullptr;      // device Hessenberg column
   std::vector<void*> allocations;
+  // measurement mode: event pairs around kernel launches
+  struct ProfEv {
+    hipEvent_t a = nullptr, b = nullptr;
+    int kernel = 0, level = 0;
+  };
+  bool prof = false;
+  std::vector<ProfEv> prof_pool;
+  size_t prof_used = 0;
   hipEvent_t ev0 = nullptr, ev1 = nullptr, ev2 = nullptr, ev3 = nullptr;
 };
 

@@ -89,6 +89,25 @@ irk_status upload_ops(Handle* h, HostLevel& H, DevLevel& D, DevOps<T>& o, const 
 
 inline hipStream_t S(void* s) { return reinterpret_cast<hipStream_t>(s); }
 
+// ------------------------------------------------------------------- measurement
+int prof_begin(Handle* h, int kernel, int level, hipStream_t s) {
+  if (!h->prof) return -1;
+  if (h->prof_used == h->prof_pool.size()) {
+    Handle::ProfEv e;
+    if (hipEventCreate(&e.a) != hipSuccess || hipEventCreate(&e.b) != hipSuccess) return -1;
+    h->prof_pool.push_back(e);
+  }
+  Handle::ProfEv& e = h->prof_pool[h->prof_used];
+  e.kernel = kernel;
+  e.level = level;
+  if (hipEventRecord(e.a, s) != hipSuccess) return -1;
+  return (int)h->prof_used++;
+}
+
+void prof_end(Handle* h, int idx, hipStream_t s) {
+  if (idx >= 0) (void)hipEventRecord(h->prof_pool[idx].b, s);
+}
+
 // ----------------------------------------------------------------------- V-cycle
 template <typename T>
 irk_status smooth(Handle* h, int l, int nsweeps, bool zero_start, bool tr, hipStream_t s) {
@@ -112,12 +131,18 @@ irk_status smooth(Handle* h, int l, int nsweeps, bool zero_start, bool tr, hipSt
     const bool first = zero_start && it == 0;
     const T* r = b;
     if (!first) {
+      const int p0 = prof_begin(h, 1, l, s);
       HIPCHK(k::residual<T>(L, ot, A, h->dt, b, x, res, s));
+      prof_end(h, p0, s);
       r = res;
     }
+    const int p1 = prof_begin(h, 0, l, s);
     HIPCHK(k::patch_apply<T>(L, o, r, Y, tr ? 1 : 0, s));
+    prof_end(h, p1, s);
     const int mode = (tr ? 2 : 0) + (first ? 0 : 1);
+    const int p2 = prof_begin(h, 2, l, s);
     HIPCHK(k::gather_update<T>(L, o, Y, x, (T)h->omega, mode, s));
+    prof_end(h, p2, s);
   }
   return IRK_OK;
 }
@@ -133,7 +158,9 @@ irk_status vcycle_T(Handle* h, bool tr, hipStream_t s, const int64_t* pins) {
     DevOps<T> o = ops_of<T>(L);
     if (tr) o.s_L = o.s_Lt;
     CHK(smooth<T>(h, l, npre, true, tr, s));
+    const int p0 = prof_begin(h, 1, l, s);
     HIPCHK(k::residual<T>(L, o, A, h->dt, (const T*)L.b, (const T*)L.x, (T*)L.res, s));
+    prof_end(h, p0, s);
     HIPCHK(k::restrict_<T>(L, h->dev[l - 1], ops_of<T>(L), (const T*)L.res, (T*)h->dev[l - 1].b, s));
   }
   {
@@ -447,8 +474,37 @@ irk_status irk_mesh_p2_nodes(const irk_mesh_level* m, int64_t* nnodes, double* x
   return IRK_OK;
 }
 
+irk_status irk_mg_profile(irk_mg* h, int enable) {
+  CHK(check_handle(h));
+  h->prof = enable != 0;
+  if (enable) h->prof_used = 0;
+  return IRK_OK;
+}
+
+irk_status irk_mg_kernel_stats(irk_mg* h, int kernel, int level, irk_kernel_stats* out) {
+  CHK(check_level(h, level));
+  if (!out || kernel < 0 || kernel > 2) return fail(IRK_EINVAL, "kernel must be 0, 1 or 2 and out non-NULL");
+  out->launches = 0;
+  out->ms_total = 0;
+  out->bytes_per_launch = h->dev[level].alg_bytes[kernel];
+  for (size_t i = 0; i < h->prof_used; ++i) {
+    Handle::ProfEv& e = h->prof_pool[i];
+    if (e.kernel != kernel || e.level != level) continue;
+    HIPCHK(hipEventSynchronize(e.b));
+    float ms = 0;
+    HIPCHK(hipEventElapsedTime(&ms, e.a, e.b));
+    out->launches++;
+    out->ms_total += ms;
+  }
+  return IRK_OK;
+}
+
 void irk_mg_destroy(irk_mg* h) {
   if (!h) return;
+  for (auto& e : h->prof_pool) {
+    if (e.a) (void)hipEventDestroy(e.a);
+    if (e.b) (void)hipEventDestroy(e.b);
+  }
   for (void* p : h->allocations) (void)hipFree(p);
   for (hipEvent_t e : {h->ev0, h->ev1, h->ev2, h->ev3})
     if (e) (void)hipEventDestroy(e);
@@ -599,6 +655,20 @@ static irk_status setup_impl(const irk_mesh_level* lv, int nlevels, const irk_ta
       CHK(upload(h, &D.pvv, H.pvv, s));
       CHK(upload(h, &D.pvp, H.pvp, s));
       CHK(upload(h, &D.pn_ptr, H.pn_ptr, s));
+    }
+    {
+      const double es = h->precision == 0 ? 8.0 : 4.0;
+      double sum_n = 0, sum_n2 = 0;
+      if (l >= 1)
+        for (int64_t p = 0; p < H.nv; ++p) {
+          const double n = r * (dim * (double)(H.pn_ptr[p + 1] - H.pn_ptr[p]) + 1);
+          sum_n += n;
+          sum_n2 += n * n;
+        }
+      D.alg_bytes[0] = es * (sum_n2 + (double)D.N + sum_n);
+      D.alg_bytes[1] = (double)H.s_col.size() * (4 + 2 * es) +
+                       2.0 * (double)H.b_col.size() * (4 + dim * es) + 3.0 * es * (double)D.N;
+      D.alg_bytes[2] = sum_n * (es + 4) + 3.0 * es * (double)D.N;
     }
     CHK(upload_ops<double>(h, H, D, D.d64, W, s));
     if (h->precision == 1) CHK(upload_ops<float>(h, H, D, D.d32, W, s));

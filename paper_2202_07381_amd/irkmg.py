@@ -47,6 +47,13 @@ class irk_solve_info(C.Structure):
                 ("ms_vcycle", C.c_double), ("ms_total", C.c_double)]
 
 
+class irk_kernel_stats(C.Structure):
+    _fields_ = [("launches", C.c_int64), ("ms_total", C.c_double), ("bytes_per_launch", C.c_double)]
+
+
+KERNELS = {"patch_apply": 0, "residual": 1, "gather_update": 2}
+
+
 def _load() -> C.CDLL:
     if not os.path.exists(LIB_PATH):
         raise RuntimeError(f"{LIB_PATH} is missing: build it with __graft_entry__.build()")
@@ -73,6 +80,8 @@ def _load() -> C.CDLL:
         "irk_level_restrict": (i, [vp, i, vp, vp, vp]),
         "irk_level_prolong": (i, [vp, i, vp, vp, vp]),
         "irk_coarse_solve": (i, [vp, i, vp, vp, vp]),
+        "irk_mg_profile": (i, [vp, i]),
+        "irk_mg_kernel_stats": (i, [vp, i, i, vp]),
         "irk_last_error": (C.c_char_p, []),
     }
     for name, (res, args) in sig.items():
@@ -231,6 +240,15 @@ class IrkMG:
     def irk_update(self, k, state, stream=None):
         sz = self.irk_mg_sizes()
         _check(lib.irk_update(self.h, _dev(k, self.irk_mg_ndofs(), "k"), _dev(state, sz["ns"], "state"), _stream(stream)))
+
+    # ---------------------------------------------------------- measurement
+    def irk_mg_profile(self, enable: bool):
+        _check(lib.irk_mg_profile(self.h, int(enable)))
+
+    def irk_mg_kernel_stats(self, kernel: str, level: int = -1) -> dict:
+        st = irk_kernel_stats()
+        _check(lib.irk_mg_kernel_stats(self.h, KERNELS[kernel], level, C.byref(st)))
+        return dict(launches=int(st.launches), ms_total=float(st.ms_total), bytes_per_launch=float(st.bytes_per_launch))
 
     # ------------------------------------------------------------ per level
     def irk_level_apply(self, level, x, y, transpose=False, stream=None):
