@@ -135,6 +135,7 @@ struct Handle {
   double* coarse_inv = nullptr;   // column-major, internal layout
   double* coarse_invT = nullptr;  // column-major inverse of the transpose
   double *cb = nullptr, *cx = nullptr;  // FP64 coarse vectors
+  double* cpart = nullptr;               // coarse GEMV partial sums
   // FGMRES workspace (finest level, internal layout, FP64)
   int krylov_cap = 0;
   double *kv = nullptr, *kz = nullptr, *kw = nullptr, *kF = nullptr, *kx = nullptr,
@@ -176,7 +177,8 @@ template <typename T>
 hipError_t patch_factor(const DevLevel& L, const DevOps<T>& ops, const double* A, double dt,
                         int* d_fail, hipStream_t s);
 hipError_t coarse_gemv(const double* inv, int64_t N, const double* b, double* x,
-                       const int64_t* pins, int npins, hipStream_t s);
+                       const int64_t* pins, int npins, double* part, hipStream_t s);
+int coarse_split();  // number of partial sums per row used by coarse_gemv
 template <typename T>
 hipError_t to_internal(const DevLevel& L, const double* abi, T* x, hipStream_t s);
 template <typename T>

@@ -166,7 +166,7 @@ irk_status vcycle_T(Handle* h, bool tr, hipStream_t s, const int64_t* pins) {
   {
     DevLevel& L = h->dev[0];
     HIPCHK((k::cast<T, double>((const T*)L.b, h->cb, L.N, s)));
-    HIPCHK(k::coarse_gemv(tr ? h->coarse_invT : h->coarse_inv, L.N, h->cb, h->cx, pins, h->r, s));
+    HIPCHK(k::coarse_gemv(tr ? h->coarse_invT : h->coarse_inv, L.N, h->cb, h->cx, pins, h->r, h->cpart, s));
     HIPCHK((k::cast<double, T>(h->cx, (T*)L.x, L.N, s)));
   }
   for (int l = 1; l <= top; ++l) {
@@ -693,9 +693,9 @@ static irk_status setup_impl(const irk_mesh_level* lv, int nlevels, const irk_ta
   for (int l = 1; l < nlevels; ++l) {
     DevLevel& D = h->dev[l];
     const size_t es = h->precision == 0 ? sizeof(double) : sizeof(float);
-    if ((size_t)D.max_nloc * D.max_nloc * es + D.max_nloc * (es + 4) + 64 > 160 * 1024)
+    if (D.max_nloc > 1024)
       return fail(IRK_EINVAL, "patch of " + std::to_string(D.max_nloc) +
-                                  " unknowns exceeds the LDS factorisation limit");
+                                  " unknowns exceeds the factorisation limit of 1024");
     if (h->precision == 0) HIPCHK(k::patch_factor<double>(D, D.d64, h->A, dt, dfail, s));
     else HIPCHK(k::patch_factor<float>(D, D.d32, h->A, dt, dfail, s));
   }
@@ -716,6 +716,7 @@ static irk_status setup_impl(const irk_mesh_level* lv, int nlevels, const irk_ta
     CHK(upload(h, &h->coarse_invT, invT, s));
     CHK(dalloc(h, &h->cb, N0));
     CHK(dalloc(h, &h->cx, N0));
+    CHK(dalloc(h, &h->cpart, (size_t)N0 * k::coarse_split()));
     std::vector<int64_t> pins(r);
     for (int st = 0; st < r; ++st) pins[st] = h->dev[0].offV + st;
     CHK(upload(h, &h->ex.pins, pins, s));
@@ -947,7 +948,7 @@ irk_status irk_coarse_solve(irk_mg* h, int transpose, const double* b, double* x
   DevLevel& L = h->dev[0];
   hipStream_t s = S(stream);
   HIPCHK(k::to_internal<double>(L, b, h->cb, s));
-  HIPCHK(k::coarse_gemv(transpose ? h->coarse_invT : h->coarse_inv, L.N, h->cb, h->cx, h->ex.pins, h->r, s));
+  HIPCHK(k::coarse_gemv(transpose ? h->coarse_invT : h->coarse_inv, L.N, h->cb, h->cx, h->ex.pins, h->r, h->cpart, s));
   HIPCHK(k::to_abi<double>(L, h->cx, x, s));
   return IRK_OK;
 }

@@ -241,6 +241,185 @@ __global__ __launch_bounds__(kBlock) void k_patch_factor(
   }
 }
 
+// Patches too large for LDS: the matrix is assembled straight into its column-major
+// inverse slot (n x ld) and inverted in place by the same Gauss--Jordan recurrence,
+// blocked: a panel of BW columns is reduced in LDS (pivot search, row swaps, scaling,
+// elimination within the panel), the panel's row swaps are applied to every other
+// column, and the other columns receive the panel's transform as a rank-BW update
+//   A[:, j] <- (A[:, j] with the panel's pivot rows zeroed) + P * A_old[pivot rows, j].
+// Each thread keeps its rows of P in registers during the update.
+constexpr int kGjBw = 16;     // panel width
+constexpr int kGjJt = 64;     // columns per update tile
+constexpr int kGjRows = 4;    // rows per thread (n <= 1024)
+
+template <int D, int R, typename T>
+__global__ __launch_bounds__(kBlock) void k_patch_factor_global(
+    int64_t npatch, const int32_t* __restrict__ pn_ptr, const int32_t* __restrict__ pvv_ptr,
+    const int32_t* __restrict__ pvv, const int32_t* __restrict__ pvp,
+    const int32_t* __restrict__ p_ld, const int64_t* __restrict__ p_inv_off,
+    const T* __restrict__ sM, const T* __restrict__ sL, const T* __restrict__ b_val,
+    Coef<T> dtA, T* __restrict__ inv, int* __restrict__ fail) {
+  extern __shared__ unsigned char smem_raw[];
+  const int64_t p = blockIdx.x;
+  if (p >= npatch) return;
+  const int nn = pn_ptr[p + 1] - pn_ptr[p];
+  const int sb = D * nn + 1;
+  const int n = R * sb;
+  const int ld = p_ld[p];
+  T* __restrict__ Am = inv + p_inv_off[p];  // column-major: Am[j * ld + i]
+  T* P = reinterpret_cast<T*>(smem_raw);    // panel, P[c * n + i]
+  T* colk = P + (size_t)kGjBw * n;
+  T* Ak = colk + n;                          // Ak[c * kGjJt + jj]
+  int* perm = reinterpret_cast<int*>(Ak + kGjBw * kGjJt);
+  __shared__ int s_piv;
+  __shared__ T s_best;
+  const int tid = threadIdx.x;
+  for (int64_t e = tid; e < (int64_t)n * ld; e += blockDim.x) Am[e] = T(0);
+  __syncthreads();
+  const int32_t v0 = pvv_ptr[p], v1 = pvv_ptr[p + 1];
+  for (int32_t e = v0 + tid; e < v1; e += blockDim.x) {
+    const int la = pvv[3 * e], lb = pvv[3 * e + 1], pos = pvv[3 * e + 2];
+    const T m = sM[pos], l = sL[pos];
+    for (int c = 0; c < D; ++c)
+      for (int s = 0; s < R; ++s)
+        for (int t = 0; t < R; ++t)
+          Am[(int64_t)(t * sb + c * nn + lb) * ld + (s * sb + c * nn + la)] =
+              (s == t ? m : T(0)) + dtA.v[s * R + t] * l;
+  }
+  const int32_t n0 = pn_ptr[p];
+  for (int la = tid; la < nn; la += blockDim.x) {
+    const int pos = pvp[n0 + la];
+    if (pos < 0) continue;
+    for (int c = 0; c < D; ++c) {
+      const T bv = b_val[(int64_t)pos * D + c];
+      for (int s = 0; s < R; ++s)
+        for (int t = 0; t < R; ++t) {
+          const T val = dtA.v[s * R + t] * bv;
+          Am[(int64_t)(t * sb + D * nn) * ld + (s * sb + c * nn + la)] = val;
+          Am[(int64_t)(t * sb + c * nn + la) * ld + (s * sb + D * nn)] = val;
+        }
+    }
+  }
+  __syncthreads();
+  for (int kb = 0; kb < n; kb += kGjBw) {
+    const int bw = min(kGjBw, n - kb);
+    for (int e = tid; e < bw * n; e += blockDim.x) {
+      const int c = e / n, i = e - c * n;
+      P[c * n + i] = Am[(int64_t)(kb + c) * ld + i];
+    }
+    __syncthreads();
+    for (int cc = 0; cc < bw; ++cc) {
+      const int c = kb + cc;
+      if (tid < 64) {
+        T best = T(-1);
+        int bi = c;
+        for (int i = c + tid; i < n; i += 64) {
+          const T a = fabs(P[cc * n + i]);
+          if (a > best) {
+            best = a;
+            bi = i;
+          }
+        }
+        for (int off = 32; off > 0; off >>= 1) {
+          const T ob = __shfl_xor(best, off, 64);
+          const int oi = __shfl_xor(bi, off, 64);
+          if (ob > best || (ob == best && oi < bi)) {
+            best = ob;
+            bi = oi;
+          }
+        }
+        if (tid == 0) {
+          s_piv = bi;
+          s_best = best;
+          perm[c] = bi;
+        }
+      }
+      __syncthreads();
+      const int piv = s_piv;
+      if (!(s_best > T(0))) {
+        if (tid == 0) atomicMax(fail, 1);
+        return;  // uniform across the workgroup
+      }
+      if (piv != c && tid < bw) {
+        const T t = P[tid * n + c];
+        P[tid * n + c] = P[tid * n + piv];
+        P[tid * n + piv] = t;
+      }
+      __syncthreads();
+      const T ip = T(1) / P[cc * n + c];
+      for (int i = tid; i < n; i += blockDim.x) colk[i] = P[cc * n + i];
+      __syncthreads();
+      if (tid < bw) P[tid * n + c] = (tid == cc) ? ip : P[tid * n + c] * ip;
+      __syncthreads();
+      for (int e = tid; e < bw * n; e += blockDim.x) {
+        const int q = e / n, i = e - q * n;
+        if (i == c) continue;
+        const T base = (q == cc) ? T(0) : P[q * n + i];
+        P[q * n + i] = base - colk[i] * P[q * n + c];
+      }
+      __syncthreads();
+    }
+    // the panel's row swaps, in order, on every other column
+    for (int cc = 0; cc < bw; ++cc) {
+      const int c = kb + cc, q = perm[c];
+      if (q != c)
+        for (int j = tid; j < n; j += blockDim.x) {
+          if (j >= kb && j < kb + bw) continue;
+          const T t = Am[(int64_t)j * ld + c];
+          Am[(int64_t)j * ld + c] = Am[(int64_t)j * ld + q];
+          Am[(int64_t)j * ld + q] = t;
+        }
+      __syncthreads();
+    }
+    // rank-bw update of the other columns
+    T pr[kGjRows][kGjBw];
+#pragma unroll
+    for (int rr = 0; rr < kGjRows; ++rr) {
+      const int i = tid + rr * kBlock;
+#pragma unroll
+      for (int c = 0; c < kGjBw; ++c) pr[rr][c] = (i < n && c < bw) ? P[c * n + i] : T(0);
+    }
+    for (int j0 = 0; j0 < n; j0 += kGjJt) {
+      const int jt = min(kGjJt, n - j0);
+      for (int e = tid; e < bw * jt; e += blockDim.x) {
+        const int c = e / jt, jj = e - c * jt;
+        Ak[c * kGjJt + jj] = Am[(int64_t)(j0 + jj) * ld + kb + c];
+      }
+      __syncthreads();
+      for (int jj = 0; jj < jt; ++jj) {
+        const int j = j0 + jj;
+        if (j >= kb && j < kb + bw) continue;
+        T* col = Am + (int64_t)j * ld;
+#pragma unroll
+        for (int rr = 0; rr < kGjRows; ++rr) {
+          const int i = tid + rr * kBlock;
+          if (i >= n) continue;
+          T acc = (i >= kb && i < kb + bw) ? T(0) : col[i];
+#pragma unroll
+          for (int c = 0; c < kGjBw; ++c) acc += pr[rr][c] * Ak[c * kGjJt + jj];
+          col[i] = acc;
+        }
+      }
+      __syncthreads();
+    }
+    for (int e = tid; e < bw * n; e += blockDim.x) {
+      const int c = e / n, i = e - c * n;
+      Am[(int64_t)(kb + c) * ld + i] = P[c * n + i];
+    }
+    __syncthreads();
+  }
+  for (int kk = n - 1; kk >= 0; --kk) {
+    const int q = perm[kk];
+    if (q != kk)
+      for (int i = tid; i < n; i += blockDim.x) {
+        const T t = Am[(int64_t)kk * ld + i];
+        Am[(int64_t)kk * ld + i] = Am[(int64_t)q * ld + i];
+        Am[(int64_t)q * ld + i] = t;
+      }
+    __syncthreads();
+  }
+}
+
 // ------------------------------------------------------------------- patch apply
 template <typename T>
 struct Vec16;
@@ -435,13 +614,32 @@ __global__ __launch_bounds__(kBlock) void k_spmv_nodes(
 }
 
 // ------------------------------------------------------------------- coarse solve
-__global__ __launch_bounds__(kBlock) void k_coarse_gemv(const double* __restrict__ inv, int64_t N,
-                                                        const double* __restrict__ b,
-                                                        double* __restrict__ x) {
+// x = inv * b with inv column-major N x N.  Grid (ceil(N/64), kCoarseSplit); each
+// wavefront owns 64 rows and a contiguous range of columns; partial sums are reduced
+// in a fixed order by k_coarse_reduce.
+constexpr int kCoarseSplit = 16;
+
+__global__ __launch_bounds__(kBlock) void k_coarse_gemv_part(const double* __restrict__ inv, int64_t N,
+                                                             const double* __restrict__ b,
+                                                             double* __restrict__ part) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int64_t i = (int64_t)blockIdx.x * 64 + lane;
+  const int nchunk = kCoarseSplit * (kBlock / 64);
+  const int chunk = blockIdx.y * (kBlock / 64) + wave;
+  const int64_t per = (N + nchunk - 1) / nchunk;
+  const int64_t j0 = chunk * per, j1 = min(N, j0 + per);
+  double acc = 0;
+  if (i < N)
+    for (int64_t j = j0; j < j1; ++j) acc += inv[j * N + i] * b[j];
+  if (i < N) part[(int64_t)chunk * N + i] = acc;
+}
+
+__global__ __launch_bounds__(kBlock) void k_coarse_reduce(const double* __restrict__ part, int64_t N,
+                                                          double* __restrict__ x) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= N) return;
   double acc = 0;
-  for (int64_t j = 0; j < N; ++j) acc += inv[j * N + i] * b[j];
+  for (int c = 0; c < kCoarseSplit * (kBlock / 64); ++c) acc += part[(int64_t)c * N + i];
   x[i] = acc;
 }
 
@@ -651,7 +849,21 @@ hipError_t patch_factor(const DevLevel& L, const DevOps<T>& ops, const double* A
                         int* d_fail, hipStream_t s) {
   const size_t n = (size_t)L.max_nloc;
   const size_t lds = n * n * sizeof(T) + n * sizeof(T) + n * sizeof(int) + 64;
-  if (lds > 160 * 1024) return hipErrorInvalidConfiguration;
+  if (lds > 160 * 1024) {
+    if (n > (size_t)kGjRows * kBlock) return hipErrorInvalidConfiguration;
+    const size_t glds = (size_t)kGjBw * n * sizeof(T) + n * sizeof(T) + (size_t)kGjBw * kGjJt * sizeof(T) +
+                        n * sizeof(int) + 64;
+    IRK_DISPATCH_DR(L.dim, L.r, {
+      auto kern = k_patch_factor_global<DD, RR, T>;
+      hipError_t e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)glds);
+      if (e != hipSuccess) return e;
+      kern<<<dim3((unsigned)L.npatch), dim3(kBlock), glds, s>>>(L.npatch, L.pn_ptr, L.pvv_ptr, L.pvv, L.pvp, L.p_ld,
+                                                                L.p_inv_off, ops.s_M, ops.s_L, ops.b_val,
+                                                                scaled<T, RR>(A, dt), reinterpret_cast<T*>(L.inv),
+                                                                d_fail);
+    });
+    return hipGetLastError();
+  }
   IRK_DISPATCH_DR(L.dim, L.r, {
     auto kern = k_patch_factor<DD, RR, T>;
     hipError_t e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
@@ -720,11 +932,14 @@ hipError_t prolong_add(const DevLevel& F, const DevLevel& C, const DevOps<T>& fo
 }
 
 hipError_t coarse_gemv(const double* inv, int64_t N, const double* b, double* x,
-                       const int64_t* pins, int npins, hipStream_t s) {
+                       const int64_t* pins, int npins, double* part, hipStream_t s) {
   if (pins && npins > 0) k_zero_pins<<<dim3(1), dim3(64), 0, s>>>(const_cast<double*>(b), pins, npins);
-  k_coarse_gemv<<<dim3(blocks_for(N)), dim3(kBlock), 0, s>>>(inv, N, b, x);
+  k_coarse_gemv_part<<<dim3((unsigned)((N + 63) / 64), kCoarseSplit), dim3(kBlock), 0, s>>>(inv, N, b, part);
+  k_coarse_reduce<<<dim3(blocks_for(N)), dim3(kBlock), 0, s>>>(part, N, x);
   return hipGetLastError();
 }
+
+int coarse_split() { return kCoarseSplit * (kBlock / 64); }
 
 template <typename T>
 hipError_t to_internal(const DevLevel& L, const double* abi, T* x, hipStream_t s) {

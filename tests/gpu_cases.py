@@ -16,6 +16,8 @@ CASES = {
     "oseen": (2, 4, 3, "gauss", 2, 5e-3, 0.01, 3),
     "be": (2, 2, 3, "radauIIA", 1, 0.05, 0.3, None),
     "lob3": (2, 2, 3, "lobattoIIIC", 3, 0.02, 1.0, None),
+    "3d2": (3, 2, 2, "radauIIA", 2, 1e-2, 1.0, None),
+    "3d3": (3, 2, 3, "radauIIA", 2, 1e-2, 1.0, None),
 }
 
 
@@ -86,8 +88,8 @@ def relerr(a, b):
 
 
 def forcing_rhs(case):
-    """F of the first step from rest with the seeded 2D forcing (oracle side)."""
+    """F of the first step from rest with the seeded forcing (oracle side)."""
     H = oracle_of(case)
     S = H.finest
-    f = wl.forcing_2d(1)
+    f = wl.forcing_2d(1) if S.th.dim == 2 else wl.forcing_3d(5)
     return S.rhs([S.th.interpolate(f, 0.0)] * S.r, np.zeros(S.th.nvel), np.zeros(S.th.nverts))

@@ -153,7 +153,7 @@ def test_rhs_and_update():
     S = H.finest
     rng = np.random.default_rng(18)
     u, p = rng.standard_normal(S.th.nvel), rng.standard_normal(S.th.nverts)
-    fn = [rng.standard_normal((S.th.nnodes, 2)) for _ in range(S.r)]
+    fn = [rng.standard_normal((S.th.nnodes, S.th.dim)) for _ in range(S.r)]
     say("[rhs] case=r3")
     F = torch.zeros(S.n, dtype=torch.float64, device="cuda")
     g.irk_rhs(to_dev(np.stack(fn).ravel()), to_dev(np.concatenate([u, p])), F)
