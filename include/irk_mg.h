@@ -181,6 +181,25 @@ irk_status irk_rhs(irk_mg* h, const double* f, const double* state, double* F, v
 /* state += dt * sum_j b_j k_j (the update of Sec. 3.1), state and k as above. */
 irk_status irk_update(irk_mg* h, const double* k, double* state, void* stream);
 
+/* Adjoint building blocks (transposes of the maps above; used to differentiate a
+ * sequence of IRK steps with respect to the forcing, the viscosity and the state).
+ * irk_rhs_adjoint: the transpose of (f, state) -> F of irk_rhs: given lam (ABI layout),
+ *   gf (device, r x nnodes x dim, overwritten) = M_fa^T lam_i^u per stage and component,
+ *   gstate (device, ns, overwritten) = [-L^T sum_i lam_i^u - B sum_i lam_i^p ;
+ *   -B^T sum_i lam_i^u].
+ * irk_update_adjoint: the transpose of irk_update with respect to k: G_i = dt b_i gstate
+ *   (G in the ABI layout, overwritten).
+ * irk_nu_sensitivity: out (device, one double, overwritten) =
+ *   lam^T (dF/dnu - dJ/dnu k) = -sum_i lam_i^u . (K_1 u) - dt sum_ij a_ij lam_i^u . (K_1 k_j^u),
+ *   K_1 the vector P2 Laplacian with nu = 1 and u the velocity of `state`
+ *   (F and J depend on nu through K = nu K_1; the convection term does not).
+ * irk_mass_apply: out (ns) = [M u ; 0] for a state vector (velocity mass). */
+irk_status irk_rhs_adjoint(irk_mg* h, const double* lam, double* gf, double* gstate, void* stream);
+irk_status irk_update_adjoint(irk_mg* h, const double* gstate, double* G, void* stream);
+irk_status irk_nu_sensitivity(irk_mg* h, const double* lam, const double* k, const double* state,
+                              double* out, void* stream);
+irk_status irk_mass_apply(irk_mg* h, const double* state, double* out, void* stream);
+
 /* Per-level building blocks, exposed so that each step of the cycle can be checked on
  * its own.  Vectors use the ABI layout of the level named. */
 /* y = J_l x or J_l^T x on level l. */

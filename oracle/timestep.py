@@ -35,9 +35,12 @@ def step(S: StageSystem, b: np.ndarray, c: np.ndarray, forcing, t: float, u: np.
     return u_new, p_new, k
 
 
-def dense_solver(S: StageSystem):
-    """Direct solve of J k = F with one pinned pressure per stage, means removed."""
+def dense_solver(S: StageSystem, transpose: bool = False):
+    """Direct solve of J k = F (or J^T k = F) with one pinned pressure per stage,
+    pressure means removed."""
     J = S.J.toarray()
+    if transpose:
+        J = J.T.copy()
     pins = [i * S.ns + S.th.nvel for i in range(S.r)]
     for q in pins:
         J[q, :] = 0.0

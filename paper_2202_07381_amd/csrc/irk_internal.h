@@ -97,6 +97,8 @@ struct DevLevel {
   int32_t *pp_ptr = nullptr, *pp_col = nullptr, *ppt_ptr = nullptr, *ppt_col = nullptr;
   int32_t *mfa_ptr = nullptr, *mfa_col = nullptr;
   double* mfa_val = nullptr;
+  int32_t *mfat_ptr = nullptr, *mfat_col = nullptr;  // M_fa^T (node rows)
+  double* mfat_val = nullptr;
   double* s_K1 = nullptr;
   DevOps<double> d64;
   DevOps<float> d32;
@@ -204,6 +206,13 @@ hipError_t rhs(const DevLevel& L, int64_t nnodes, const double* f, const double*
                double* F, hipStream_t s);
 hipError_t update(const DevLevel& L, const double* b, double dt, const double* k,
                   double* state, hipStream_t s);
+hipError_t rhs_adjoint(const DevLevel& L, int64_t nnodes, const int32_t* mt_ptr, const int32_t* mt_col,
+                       const double* mt_val, const double* lam, double* gf, double* gstate, hipStream_t s);
+hipError_t update_adjoint(const DevLevel& L, const double* b, double dt, const double* gs, double* G,
+                          hipStream_t s);
+hipError_t nu_sensitivity(const DevLevel& L, const double* A, double dt, const double* lam, const double* kv,
+                          const double* state, double* rowsum, double* partials, double* out, hipStream_t s);
+hipError_t mass_apply(const DevLevel& L, const double* st, double* out, hipStream_t s);
 }  // namespace k
 
 }  // namespace irk

@@ -89,6 +89,23 @@ irk_status upload_ops(Handle* h, HostLevel& H, DevLevel& D, DevOps<T>& o, const 
 
 inline hipStream_t S(void* s) { return reinterpret_cast<hipStream_t>(s); }
 
+void transpose_host(int64_t nrows, int64_t ncols, const std::vector<int32_t>& ptr, const std::vector<int32_t>& col,
+                    const std::vector<double>& val, std::vector<int32_t>& tptr, std::vector<int32_t>& tcol,
+                    std::vector<double>& tval) {
+  tptr.assign(ncols + 1, 0);
+  for (int32_t cc : col) tptr[cc + 1]++;
+  for (int64_t i = 0; i < ncols; ++i) tptr[i + 1] += tptr[i];
+  tcol.resize(col.size());
+  tval.resize(val.size());
+  std::vector<int32_t> fp(tptr.begin(), tptr.end() - 1);
+  for (int64_t i = 0; i < nrows; ++i)
+    for (int32_t p = ptr[i]; p < ptr[i + 1]; ++p) {
+      const int32_t q = fp[col[p]]++;
+      tcol[q] = (int32_t)i;
+      tval[q] = val[p];
+    }
+}
+
 // ------------------------------------------------------------------- measurement
 int prof_begin(Handle* h, int kernel, int level, hipStream_t s) {
   if (!h->prof) return -1;
@@ -596,6 +613,14 @@ static irk_status setup_impl(const irk_mesh_level* lv, int nlevels, const irk_ta
       CHK(upload(h, &D.mfa_ptr, H.mfa_ptr, s));
       CHK(upload(h, &D.mfa_col, H.mfa_col, s));
       CHK(upload(h, &D.mfa_val, H.mfa_val, s));
+      {
+        std::vector<int32_t> tp, tc;
+        std::vector<double> tv;
+        transpose_host(H.nfree, H.nn, H.mfa_ptr, H.mfa_col, H.mfa_val, tp, tc, tv);
+        CHK(upload(h, &D.mfat_ptr, tp, s));
+        CHK(upload(h, &D.mfat_col, tc, s));
+        CHK(upload(h, &D.mfat_val, tv, s));
+      }
       CHK(upload(h, &D.s_K1, H.s_K1, s));
     }
     // patches: sizes, offsets, local -> internal index, DOF -> slot lists, weights
@@ -886,6 +911,38 @@ irk_status irk_update(irk_mg* h, const double* kv, double* state, void* stream) 
   CHK(check_handle(h));
   if (!kv || !state) return fail(IRK_EINVAL, "null vector");
   HIPCHK(k::update(h->dev[h->nlevels - 1], h->b, h->dt, kv, state, S(stream)));
+  return IRK_OK;
+}
+
+irk_status irk_rhs_adjoint(irk_mg* h, const double* lam, double* gf, double* gstate, void* stream) {
+  CHK(check_handle(h));
+  if (!lam || !gf || !gstate) return fail(IRK_EINVAL, "null vector");
+  const int top = h->nlevels - 1;
+  DevLevel& L = h->dev[top];
+  HIPCHK(k::rhs_adjoint(L, h->host[top].nn, L.mfat_ptr, L.mfat_col, L.mfat_val, lam, gf, gstate, S(stream)));
+  return IRK_OK;
+}
+
+irk_status irk_update_adjoint(irk_mg* h, const double* gstate, double* G, void* stream) {
+  CHK(check_handle(h));
+  if (!gstate || !G) return fail(IRK_EINVAL, "null vector");
+  HIPCHK(k::update_adjoint(h->dev[h->nlevels - 1], h->b, h->dt, gstate, G, S(stream)));
+  return IRK_OK;
+}
+
+irk_status irk_nu_sensitivity(irk_mg* h, const double* lam, const double* kv, const double* state, double* out,
+                              void* stream) {
+  CHK(check_handle(h));
+  if (!lam || !kv || !state || !out) return fail(IRK_EINVAL, "null vector");
+  DevLevel& L = h->dev[h->nlevels - 1];
+  HIPCHK(k::nu_sensitivity(L, h->A, h->dt, lam, kv, state, h->kw, h->partials, out, S(stream)));
+  return IRK_OK;
+}
+
+irk_status irk_mass_apply(irk_mg* h, const double* state, double* out, void* stream) {
+  CHK(check_handle(h));
+  if (!state || !out) return fail(IRK_EINVAL, "null vector");
+  HIPCHK(k::mass_apply(h->dev[h->nlevels - 1], state, out, S(stream)));
   return IRK_OK;
 }
 

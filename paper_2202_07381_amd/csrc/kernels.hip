@@ -713,6 +713,22 @@ __global__ __launch_bounds__(kBlock) void k_dot_partial(const double* __restrict
   if (threadIdx.x == 0) partials[blockIdx.x] = red[0];
 }
 
+__global__ __launch_bounds__(kBlock) void k_sum_partial(const double* __restrict__ a, int64_t n,
+                                                        double* __restrict__ partials) {
+  __shared__ double red[kBlock];
+  double acc = 0;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    acc += a[i];
+  red[threadIdx.x] = acc;
+  __syncthreads();
+  for (int w = kBlock / 2; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) partials[blockIdx.x] = red[0];
+}
+
 __global__ __launch_bounds__(kBlock) void k_dot_final(const double* __restrict__ partials, int nb,
                                                       double* __restrict__ out, int take_sqrt) {
   __shared__ double red[kBlock];
@@ -807,6 +823,122 @@ __global__ __launch_bounds__(kBlock) void k_update(int64_t ns, int R, Coef<doubl
   double acc = state[i];
   for (int j = 0; j < R; ++j) acc += bdt.v[j] * kv[j * ns + i];
   state[i] = acc;
+}
+
+// ------------------------------------------------------------- adjoint helpers
+// gf[s][node][c] = sum_{rows i with column node} mfa[i,node] lam_s^{u,c}[i], computed by
+// rows of M_fa^T (transposed CSR, node rows).
+__global__ __launch_bounds__(kBlock) void k_rhs_adjoint_f(
+    int64_t nnodes, int64_t nfree, int64_t nv, int D, int R, const int32_t* __restrict__ mt_ptr,
+    const int32_t* __restrict__ mt_col, const double* __restrict__ mt_val,
+    const double* __restrict__ lam, double* __restrict__ gf) {
+  const int64_t node = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (node >= nnodes) return;
+  const int64_t ns = D * nfree + nv;
+  for (int s = 0; s < R; ++s)
+    for (int c = 0; c < D; ++c) {
+      double acc = 0;
+      for (int32_t p = mt_ptr[node]; p < mt_ptr[node + 1]; ++p)
+        acc += mt_val[p] * lam[s * ns + c * nfree + mt_col[p]];
+      gf[((int64_t)s * nnodes + node) * D + c] = acc;
+    }
+}
+
+// gstate = [-L^T su - B sp ; -B^T su], su = sum_i lam_i^u, sp = sum_i lam_i^p
+__global__ __launch_bounds__(kBlock) void k_rhs_adjoint_s(
+    int64_t nfree, int64_t nv, int D, int R, const int32_t* __restrict__ s_ptr,
+    const int32_t* __restrict__ s_col, const double* __restrict__ sLt,
+    const int32_t* __restrict__ b_ptr, const int32_t* __restrict__ b_col,
+    const double* __restrict__ b_val, const int32_t* __restrict__ bt_ptr,
+    const int32_t* __restrict__ bt_col, const double* __restrict__ bt_val,
+    const double* __restrict__ lam, double* __restrict__ gs) {
+  const int64_t row = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t ns = D * nfree + nv;
+  if (row < nfree) {
+    for (int c = 0; c < D; ++c) {
+      double acc = 0;
+      for (int32_t p = s_ptr[row]; p < s_ptr[row + 1]; ++p) {
+        double su = 0;
+        for (int s = 0; s < R; ++s) su += lam[s * ns + c * nfree + s_col[p]];
+        acc -= sLt[p] * su;
+      }
+      for (int32_t p = b_ptr[row]; p < b_ptr[row + 1]; ++p) {
+        double sp = 0;
+        for (int s = 0; s < R; ++s) sp += lam[s * ns + D * nfree + b_col[p]];
+        acc -= b_val[(int64_t)p * D + c] * sp;
+      }
+      gs[c * nfree + row] = acc;
+    }
+  } else if (row < nfree + nv) {
+    const int64_t v = row - nfree;
+    double acc = 0;
+    for (int32_t p = bt_ptr[v]; p < bt_ptr[v + 1]; ++p)
+      for (int c = 0; c < D; ++c) {
+        double su = 0;
+        for (int s = 0; s < R; ++s) su += lam[s * ns + c * nfree + bt_col[p]];
+        acc -= bt_val[(int64_t)p * D + c] * su;
+      }
+    gs[D * nfree + v] = acc;
+  }
+}
+
+__global__ __launch_bounds__(kBlock) void k_update_adjoint(int64_t ns, int R, Coef<double> bdt,
+                                                           const double* __restrict__ gs,
+                                                           double* __restrict__ G) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= ns) return;
+  const double g = gs[i];
+  for (int j = 0; j < R; ++j) G[j * ns + i] = bdt.v[j] * g;
+}
+
+// per free-node-row contribution to lam^T(dF/dnu - dJ/dnu k): one value per row,
+// reduced afterwards in a fixed order.
+__global__ __launch_bounds__(kBlock) void k_nu_rows(int64_t nfree, int64_t nv, int D, int R,
+                                                    Coef<double> dtA,
+                                                    const int32_t* __restrict__ s_ptr,
+                                                    const int32_t* __restrict__ s_col,
+                                                    const double* __restrict__ K1,
+                                                    const double* __restrict__ lam,
+                                                    const double* __restrict__ kv,
+                                                    const double* __restrict__ state,
+                                                    double* __restrict__ rowsum) {
+  const int64_t row = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (row >= nfree) return;
+  const int64_t ns = D * nfree + nv;
+  double tot = 0;
+  for (int c = 0; c < D; ++c) {
+    double ku = 0;
+    double kk[kMaxStages] = {0, 0, 0, 0};
+    for (int32_t p = s_ptr[row]; p < s_ptr[row + 1]; ++p) {
+      const int64_t j = s_col[p];
+      ku += K1[p] * state[c * nfree + j];
+      for (int t = 0; t < R; ++t) kk[t] += K1[p] * kv[t * ns + c * nfree + j];
+    }
+    for (int s = 0; s < R; ++s) {
+      double w = ku;
+      for (int t = 0; t < R; ++t) w += dtA.v[s * R + t] * kk[t];
+      tot -= lam[s * ns + c * nfree + row] * w;
+    }
+  }
+  rowsum[row] = tot;
+}
+
+__global__ __launch_bounds__(kBlock) void k_mass_apply(int64_t nfree, int64_t nv, int D,
+                                                       const int32_t* __restrict__ s_ptr,
+                                                       const int32_t* __restrict__ s_col,
+                                                       const double* __restrict__ sM,
+                                                       const double* __restrict__ st,
+                                                       double* __restrict__ out) {
+  const int64_t row = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (row < nfree) {
+    for (int c = 0; c < D; ++c) {
+      double acc = 0;
+      for (int32_t p = s_ptr[row]; p < s_ptr[row + 1]; ++p) acc += sM[p] * st[c * nfree + s_col[p]];
+      out[c * nfree + row] = acc;
+    }
+  } else if (row < nfree + nv) {
+    out[D * nfree + row - nfree] = 0.0;
+  }
 }
 
 }  // namespace
@@ -1024,6 +1156,43 @@ hipError_t update(const DevLevel& L, const double* b, double dt, const double* k
   for (int j = 0; j < L.r; ++j) c.v[j] = dt * b[j];
   const int64_t ns = L.dim * L.nfree + L.nv;
   k_update<<<dim3(blocks_for(ns)), dim3(kBlock), 0, s>>>(ns, L.r, c, kv, state);
+  return hipGetLastError();
+}
+
+hipError_t rhs_adjoint(const DevLevel& L, int64_t nnodes, const int32_t* mt_ptr, const int32_t* mt_col,
+                       const double* mt_val, const double* lam, double* gf, double* gstate, hipStream_t s) {
+  k_rhs_adjoint_f<<<dim3(blocks_for(nnodes)), dim3(kBlock), 0, s>>>(nnodes, L.nfree, L.nv, L.dim, L.r, mt_ptr,
+                                                                    mt_col, mt_val, lam, gf);
+  k_rhs_adjoint_s<<<dim3(blocks_for(L.nfree + L.nv)), dim3(kBlock), 0, s>>>(
+      L.nfree, L.nv, L.dim, L.r, L.s_ptr, L.s_col, L.d64.s_Lt, L.b_ptr, L.b_col, L.d64.b_val, L.bt_ptr, L.bt_col,
+      L.d64.bt_val, lam, gstate);
+  return hipGetLastError();
+}
+
+hipError_t update_adjoint(const DevLevel& L, const double* b, double dt, const double* gs, double* G,
+                          hipStream_t s) {
+  Coef<double> c{};
+  for (int j = 0; j < L.r; ++j) c.v[j] = dt * b[j];
+  const int64_t ns = L.dim * L.nfree + L.nv;
+  k_update_adjoint<<<dim3(blocks_for(ns)), dim3(kBlock), 0, s>>>(ns, L.r, c, gs, G);
+  return hipGetLastError();
+}
+
+hipError_t nu_sensitivity(const DevLevel& L, const double* A, double dt, const double* lam, const double* kv,
+                          const double* state, double* rowsum, double* partials, double* out, hipStream_t s) {
+  Coef<double> c{};
+  for (int i = 0; i < L.r * L.r; ++i) c.v[i] = dt * A[i];
+  k_nu_rows<<<dim3(blocks_for(L.nfree)), dim3(kBlock), 0, s>>>(L.nfree, L.nv, L.dim, L.r, c, L.s_ptr, L.s_col,
+                                                               L.s_K1, lam, kv, state, rowsum);
+  const int nb = (int)std::min<int64_t>(kReduceBlocks, blocks_for(L.nfree));
+  k_sum_partial<<<dim3(nb), dim3(kBlock), 0, s>>>(rowsum, L.nfree, partials);
+  k_dot_final<<<dim3(1), dim3(kBlock), 0, s>>>(partials, nb, out, 0);
+  return hipGetLastError();
+}
+
+hipError_t mass_apply(const DevLevel& L, const double* st, double* out, hipStream_t s) {
+  k_mass_apply<<<dim3(blocks_for(L.nfree + L.nv)), dim3(kBlock), 0, s>>>(L.nfree, L.nv, L.dim, L.s_ptr, L.s_col,
+                                                                         L.d64.s_M, st, out);
   return hipGetLastError();
 }
 

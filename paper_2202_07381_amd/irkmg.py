@@ -80,6 +80,10 @@ def _load() -> C.CDLL:
         "irk_level_restrict": (i, [vp, i, vp, vp, vp]),
         "irk_level_prolong": (i, [vp, i, vp, vp, vp]),
         "irk_coarse_solve": (i, [vp, i, vp, vp, vp]),
+        "irk_rhs_adjoint": (i, [vp, vp, vp, vp, vp]),
+        "irk_update_adjoint": (i, [vp, vp, vp, vp]),
+        "irk_nu_sensitivity": (i, [vp, vp, vp, vp, vp, vp]),
+        "irk_mass_apply": (i, [vp, vp, vp, vp]),
         "irk_mg_profile": (i, [vp, i]),
         "irk_mg_kernel_stats": (i, [vp, i, i, vp]),
         "irk_last_error": (C.c_char_p, []),
@@ -240,6 +244,28 @@ class IrkMG:
     def irk_update(self, k, state, stream=None):
         sz = self.irk_mg_sizes()
         _check(lib.irk_update(self.h, _dev(k, self.irk_mg_ndofs(), "k"), _dev(state, sz["ns"], "state"), _stream(stream)))
+
+    # -------------------------------------------------------------- adjoint
+    def irk_rhs_adjoint(self, lam, gf, gstate, stream=None):
+        sz = self.irk_mg_sizes()
+        _check(lib.irk_rhs_adjoint(self.h, _dev(lam, self.irk_mg_ndofs(), "lam"),
+                                   _dev(gf, self.r * sz["nnodes"] * self.dim, "gf"), _dev(gstate, sz["ns"], "gstate"),
+                                   _stream(stream)))
+
+    def irk_update_adjoint(self, gstate, G, stream=None):
+        sz = self.irk_mg_sizes()
+        _check(lib.irk_update_adjoint(self.h, _dev(gstate, sz["ns"], "gstate"), _dev(G, self.irk_mg_ndofs(), "G"),
+                                      _stream(stream)))
+
+    def irk_nu_sensitivity(self, lam, k, state, out, stream=None):
+        sz = self.irk_mg_sizes()
+        n = self.irk_mg_ndofs()
+        _check(lib.irk_nu_sensitivity(self.h, _dev(lam, n, "lam"), _dev(k, n, "k"), _dev(state, sz["ns"], "state"),
+                                      _dev(out, 1, "out"), _stream(stream)))
+
+    def irk_mass_apply(self, state, out, stream=None):
+        sz = self.irk_mg_sizes()
+        _check(lib.irk_mass_apply(self.h, _dev(state, sz["ns"], "state"), _dev(out, sz["ns"], "out"), _stream(stream)))
 
     # ---------------------------------------------------------- measurement
     def irk_mg_profile(self, enable: bool):
