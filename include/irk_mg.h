@@ -216,6 +216,40 @@ irk_status irk_level_prolong(irk_mg* h, int level, const double* xc, double* xf,
 /* x = J_0^{-1} b on the coarsest level with pinned pressures (transpose: J_0^{-T}). */
 irk_status irk_coarse_solve(irk_mg* h, int transpose, const double* b, double* x, void* stream);
 
+/* Batched solves in one persistent launch.  irk_batch_create groups n FP64 handles
+ * (distinct, set up independently, of any sizes and stage counts); each call of
+ * irk_batch_fgmres_solve then runs the whole FGMRES solve of every handle -- the same
+ * algorithm as irk_fgmres_solve: layout conversion, residuals, V-cycles, Gram--Schmidt,
+ * Givens updates, solution update and projection -- inside ONE persistent kernel in
+ * which workgroups take work items of any unfinished solve.  F[q] and k[q] are device
+ * vectors of handle q (ABI layout); k[q] is the initial guess on entry.  infos[q]
+ * (may be NULL) gets iterations, convergence and the recomputed relative residual;
+ * latency_ms[q] (may be NULL) the device-clock time from the start of the launch to
+ * the moment solve q finished.  Returns IRK_ENOCONV if some solve reached maxit,
+ * IRK_ENAN on a non-finite value.  restart <= 64.
+ * Schedule (irk_batch_opts): rows_per_item (x256 rows or vector entries per work
+ * item), patches_per_wave (patches one wavefront takes per item; 4 wavefronts per
+ * item), workgroups_per_cu (resident workgroups per compute unit), autotune (1: the
+ * first solve call times 2-iteration trial runs of a grid of schedules, writing to
+ * scratch, and keeps the fastest; irk_batch_get_opts reports the choice).  Every wait
+ * in the kernel is bounded: a workgroup that finds no work for a long time aborts the
+ * launch and the call returns IRK_EHIP. */
+typedef struct irk_batch irk_batch;
+typedef struct irk_batch_opts {
+  int rows_per_item;
+  int patches_per_wave;
+  int workgroups_per_cu;
+  int autotune;
+} irk_batch_opts;
+void irk_batch_default_opts(irk_batch_opts* opt);
+irk_status irk_batch_create(irk_mg* const* solves, int n, const irk_batch_opts* opt, void* stream,
+                            irk_batch** out);
+irk_status irk_batch_fgmres_solve(irk_batch* b, const double* const* F, double* const* k, double rtol,
+                                  int maxit, int restart, irk_solve_info* infos, double* latency_ms,
+                                  void* stream);
+irk_status irk_batch_get_opts(const irk_batch* b, irk_batch_opts* out);
+void irk_batch_destroy(irk_batch* b);
+
 /* Measurement of the V-cycle kernels.  irk_mg_profile(h, 1) clears the counters and
  * brackets every later launch of the kernels below with HIP events on the stream it is
  * launched on; irk_mg_profile(h, 0) stops recording.  irk_mg_kernel_stats waits for

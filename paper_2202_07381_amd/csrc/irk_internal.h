@@ -146,6 +146,8 @@ struct Handle {
   double* partials = nullptr;  // reduction partials
   double* hbuf = nullptr;      // device Hessenberg column
   std::vector<void*> allocations;
+  int64_t* pins = nullptr;  // device: pinned coarse pressure DOFs (one per stage)
+  int* flag = nullptr;      // device: error flag of the factorisation kernels
   // measurement mode: event pairs around kernel launches
   struct ProfEv {
     hipEvent_t a = nullptr, b = nullptr;
@@ -215,4 +217,14 @@ hipError_t nu_sensitivity(const DevLevel& L, const double* A, double dt, const d
 hipError_t mass_apply(const DevLevel& L, const double* st, double* out, hipStream_t s);
 }  // namespace k
 
+}  // namespace irk
+
+// the opaque handle of the C ABI
+struct irk_mg : irk::Handle {};
+
+namespace irk {
+// FGMRES workspace of a handle sized for `restart` (used by the batched solver too)
+int ensure_krylov_ws(irk_mg* h, int restart);
+// message returned by irk_last_error() on the calling thread
+void set_error(const std::string& msg);
 }  // namespace irk

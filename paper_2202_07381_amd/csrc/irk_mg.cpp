@@ -194,23 +194,6 @@ irk_status vcycle_T(Handle* h, bool tr, hipStream_t s, const int64_t* pins) {
   return IRK_OK;
 }
 
-struct HandleExtra {
-  int64_t* pins = nullptr;
-  int* flag = nullptr;
-};
-
-}  // namespace
-
-// Extra device state hung off the handle (pins of the coarse solve, error flags).
-namespace irk {
-struct HandleFull : Handle {
-  HandleExtra ex;
-};
-}  // namespace irk
-
-struct irk_mg : irk::HandleFull {};
-
-namespace {
 
 irk_status precondition(irk_mg* h, const double* v, double* z, bool tr, hipStream_t s) {
   DevLevel& L = h->dev[h->nlevels - 1];
@@ -221,11 +204,11 @@ irk_status precondition(irk_mg* h, const double* v, double* z, bool tr, hipStrea
   }
   if (h->precision == 0) {
     HIPCHK((k::cast<double, double>(v, (double*)L.b, L.N, s)));
-    CHK(vcycle_T<double>(h, tr, s, h->ex.pins));
+    CHK(vcycle_T<double>(h, tr, s, h->pins));
     HIPCHK((k::cast<double, double>((const double*)L.x, z, L.N, s)));
   } else {
     HIPCHK((k::cast<double, float>(v, (float*)L.b, L.N, s)));
-    CHK(vcycle_T<float>(h, tr, s, h->ex.pins));
+    CHK(vcycle_T<float>(h, tr, s, h->pins));
     HIPCHK((k::cast<float, double>((const float*)L.x, z, L.N, s)));
   }
   if (!tr) HIPCHK(k::project_pressure(L, z, h->partials, s));
@@ -400,6 +383,9 @@ irk_status level_sweep_T(irk_mg* h, int level, int transpose, const double* F, d
 }
 
 }  // namespace
+
+int irk::ensure_krylov_ws(irk_mg* h, int restart) { return ensure_krylov(h, restart); }
+void irk::set_error(const std::string& msg) { g_err = msg; }
 
 // =========================================================================== ABI
 extern "C" {
@@ -713,7 +699,7 @@ static irk_status setup_impl(const irk_mesh_level* lv, int nlevels, const irk_ta
   // ---- patch factorisation on the GPU
   int* dfail;
   CHK(dalloc(h, &dfail, 1));
-  h->ex.flag = dfail;
+  h->flag = dfail;
   HIPCHK(hipMemsetAsync(dfail, 0, sizeof(int), s));
   for (int l = 1; l < nlevels; ++l) {
     DevLevel& D = h->dev[l];
@@ -744,7 +730,7 @@ static irk_status setup_impl(const irk_mesh_level* lv, int nlevels, const irk_ta
     CHK(dalloc(h, &h->cpart, (size_t)N0 * k::coarse_split()));
     std::vector<int64_t> pins(r);
     for (int st = 0; st < r; ++st) pins[st] = h->dev[0].offV + st;
-    CHK(upload(h, &h->ex.pins, pins, s));
+    CHK(upload(h, &h->pins, pins, s));
   }
   // ---- Krylov and reduction workspace
   const int64_t N = h->dev[nlevels - 1].N;
@@ -1005,7 +991,7 @@ irk_status irk_coarse_solve(irk_mg* h, int transpose, const double* b, double* x
   DevLevel& L = h->dev[0];
   hipStream_t s = S(stream);
   HIPCHK(k::to_internal<double>(L, b, h->cb, s));
-  HIPCHK(k::coarse_gemv(transpose ? h->coarse_invT : h->coarse_inv, L.N, h->cb, h->cx, h->ex.pins, h->r, h->cpart, s));
+  HIPCHK(k::coarse_gemv(transpose ? h->coarse_invT : h->coarse_inv, L.N, h->cb, h->cx, h->pins, h->r, h->cpart, s));
   HIPCHK(k::to_abi<double>(L, h->cx, x, s));
   return IRK_OK;
 }

@@ -19,6 +19,7 @@
 #include <algorithm>
 #include <cmath>
 
+#include "device_ops.h"
 #include "irk_internal.h"
 
 namespace irk {
@@ -33,10 +34,7 @@ inline unsigned blocks_for(int64_t n, int block = kBlock) {
   return (unsigned)std::max<int64_t>(1, b);
 }
 
-template <typename T>
-struct Coef {
-  T v[kMaxStages * kMaxStages];
-};
+using dev::Coef;
 
 template <typename T, int R>
 Coef<T> scaled(const double* A, double dt) {
@@ -55,70 +53,8 @@ __global__ __launch_bounds__(kBlock) void k_residual(
     const int32_t* __restrict__ bt_col, const T* __restrict__ bt_val, Coef<T> dtA,
     const T* __restrict__ F, const T* __restrict__ x, T* __restrict__ y) {
   const int64_t row = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  constexpr int DR = D * R;
-  if (row < nfree) {
-    T am[DR], al[DR];
-#pragma unroll
-    for (int q = 0; q < DR; ++q) am[q] = al[q] = T(0);
-    const int32_t p0 = s_ptr[row], p1 = s_ptr[row + 1];
-    for (int32_t p = p0; p < p1; ++p) {
-      const int64_t j = s_col[p];
-      const T m = sM[p], l = sL[p];
-      const T* xj = x + j * DR;
-#pragma unroll
-      for (int q = 0; q < DR; ++q) {
-        const T xv = xj[q];
-        am[q] += m * xv;
-        al[q] += l * xv;
-      }
-    }
-    const int32_t q0 = b_ptr[row], q1 = b_ptr[row + 1];
-    for (int32_t p = q0; p < q1; ++p) {
-      const T* xp = x + offV + (int64_t)b_col[p] * R;
-      T pv[R];
-#pragma unroll
-      for (int t = 0; t < R; ++t) pv[t] = xp[t];
-#pragma unroll
-      for (int c = 0; c < D; ++c) {
-        const T bv = b_val[(int64_t)p * D + c];
-#pragma unroll
-        for (int t = 0; t < R; ++t) al[c * R + t] += bv * pv[t];
-      }
-    }
-#pragma unroll
-    for (int c = 0; c < D; ++c)
-#pragma unroll
-      for (int s = 0; s < R; ++s) {
-        T acc = am[c * R + s];
-#pragma unroll
-        for (int t = 0; t < R; ++t) acc += dtA.v[s * R + t] * al[c * R + t];
-        const int64_t o = row * DR + c * R + s;
-        y[o] = F ? F[o] - acc : acc;
-      }
-  } else if (row < nfree + nv) {
-    const int64_t v = row - nfree;
-    T a[R];
-#pragma unroll
-    for (int t = 0; t < R; ++t) a[t] = T(0);
-    const int32_t p0 = bt_ptr[v], p1 = bt_ptr[v + 1];
-    for (int32_t p = p0; p < p1; ++p) {
-      const T* xi = x + (int64_t)bt_col[p] * DR;
-#pragma unroll
-      for (int c = 0; c < D; ++c) {
-        const T bv = bt_val[(int64_t)p * D + c];
-#pragma unroll
-        for (int t = 0; t < R; ++t) a[t] += bv * xi[c * R + t];
-      }
-    }
-#pragma unroll
-    for (int s = 0; s < R; ++s) {
-      T acc = T(0);
-#pragma unroll
-      for (int t = 0; t < R; ++t) acc += dtA.v[s * R + t] * a[t];
-      const int64_t o = offV + v * R + s;
-      y[o] = F ? F[o] - acc : acc;
-    }
-  }
+  dev::residual_row<D, R, T>(row, nfree, nv, offV, s_ptr, s_col, sM, sL, b_ptr, b_col, b_val, bt_ptr, bt_col,
+                             bt_val, dtA, F, x, y);
 }
 
 // ------------------------------------------------------------------ patch factorise
@@ -421,41 +357,9 @@ __global__ __launch_bounds__(kBlock) void k_patch_factor_global(
 }
 
 // ------------------------------------------------------------------- patch apply
-template <typename T>
-struct Vec16;
-template <>
-struct Vec16<double> {
-  using type = double2;
-  static constexpr int n = 2;
-};
-template <>
-struct Vec16<float> {
-  using type = float4;
-  static constexpr int n = 4;
-};
-
-template <typename V, typename T>
-__device__ inline void vload(const T* p, T* out);
-template <>
-__device__ inline void vload<double2, double>(const double* p, double* o) {
-  const double2 v = *reinterpret_cast<const double2*>(p);
-  o[0] = v.x;
-  o[1] = v.y;
-}
-template <>
-__device__ inline void vload<float4, float>(const float* p, float* o) {
-  const float4 v = *reinterpret_cast<const float4*>(p);
-  o[0] = v.x;
-  o[1] = v.y;
-  o[2] = v.z;
-  o[3] = v.w;
-}
-
+using dev::Vec16;
 constexpr int kWaves = 4;  // wavefronts (patches) per workgroup
 
-// One wavefront per patch.  Lane l owns rows [rb*64*VEC + l*VEC, +VEC) of each row
-// block rb.  Non-transposed: y = Ainv x streams column j with one 16-byte load per
-// lane.  Transposed: y_j = column_j . x, a wave reduction per column.
 template <typename T, int RB, int NMAX>
 __global__ __launch_bounds__(kWaves * 64) void k_patch_apply(
     int64_t npatch, const int32_t* __restrict__ sched, const int32_t* __restrict__ p_nloc,
@@ -463,96 +367,16 @@ __global__ __launch_bounds__(kWaves * 64) void k_patch_apply(
     const int64_t* __restrict__ p_slot_off, const int32_t* __restrict__ gidx,
     const T* __restrict__ inv, const T* __restrict__ res, const T* __restrict__ W,
     T* __restrict__ Y, int transpose) {
-  using VT = typename Vec16<T>::type;
-  constexpr int VEC = Vec16<T>::n;
   __shared__ T xs[kWaves][NMAX];
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
   const int64_t idx = (int64_t)blockIdx.x * kWaves + wave;
   if (idx >= npatch) return;  // whole wavefront exits; no workgroup barrier below
-  const int p = sched[idx];
-  const int n = p_nloc[p];
-  const int ld = p_ld[p];
-  const int64_t so = p_slot_off[p];
-  const T* __restrict__ Ap = inv + p_inv_off[p];
-  for (int i = lane; i < n; i += 64) {
-    const int32_t g = gidx[so + i];
-    xs[wave][i] = W ? res[g] * W[g] : res[g];
-  }
-  __builtin_amdgcn_wave_barrier();
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-  if (!transpose) {
-    T acc[RB][VEC];
-#pragma unroll
-    for (int b = 0; b < RB; ++b)
-#pragma unroll
-      for (int v = 0; v < VEC; ++v) acc[b][v] = T(0);
-    int j = 0;
-    for (; j + 4 <= n; j += 4) {
-      T a[4][RB][VEC];
-#pragma unroll
-      for (int u = 0; u < 4; ++u)
-#pragma unroll
-        for (int b = 0; b < RB; ++b) {
-          const int r0 = b * 64 * VEC + lane * VEC;
-          if (r0 < n) vload<VT, T>(Ap + (int64_t)(j + u) * ld + r0, a[u][b]);
-          else
-#pragma unroll
-            for (int v = 0; v < VEC; ++v) a[u][b][v] = T(0);
-        }
-#pragma unroll
-      for (int u = 0; u < 4; ++u) {
-        const T xj = xs[wave][j + u];
-#pragma unroll
-        for (int b = 0; b < RB; ++b)
-#pragma unroll
-          for (int v = 0; v < VEC; ++v) acc[b][v] += a[u][b][v] * xj;
-      }
-    }
-    for (; j < n; ++j) {
-      const T xj = xs[wave][j];
-#pragma unroll
-      for (int b = 0; b < RB; ++b) {
-        const int r0 = b * 64 * VEC + lane * VEC;
-        if (r0 < n) {
-          T a[VEC];
-          vload<VT, T>(Ap + (int64_t)j * ld + r0, a);
-#pragma unroll
-          for (int v = 0; v < VEC; ++v) acc[b][v] += a[v] * xj;
-        }
-      }
-    }
-#pragma unroll
-    for (int b = 0; b < RB; ++b)
-#pragma unroll
-      for (int v = 0; v < VEC; ++v) {
-        const int row = b * 64 * VEC + lane * VEC + v;
-        if (row < n) Y[so + row] = acc[b][v];
-      }
-  } else {
-    for (int j = 0; j < n; ++j) {
-      T part = T(0);
-#pragma unroll
-      for (int b = 0; b < RB; ++b) {
-        const int r0 = b * 64 * VEC + lane * VEC;
-        if (r0 < n) {
-          T a[VEC];
-          vload<VT, T>(Ap + (int64_t)j * ld + r0, a);
-#pragma unroll
-          for (int v = 0; v < VEC; ++v)
-            if (r0 + v < n) part += a[v] * xs[wave][r0 + v];
-        }
-      }
-#pragma unroll
-      for (int off = 32; off > 0; off >>= 1) part += __shfl_xor(part, off, 64);
-      if (lane == 0) Y[so + j] = part;
-    }
-  }
+  dev::patch_apply_one<T, RB>(sched[idx], lane, xs[wave], p_nloc, p_ld, p_inv_off, p_slot_off, gidx, inv, res,
+                              W, Y, transpose);
 }
 
 // ------------------------------------------------------------------ gather update
-// mode 0: x = omega*W*s   1: x += omega*W*s   2: x = omega*s   3: x += omega*s
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_gather_update(int64_t N, const int32_t* __restrict__ gptr,
                                                           const int32_t* __restrict__ gslot,
@@ -561,12 +385,7 @@ __global__ __launch_bounds__(kBlock) void k_gather_update(int64_t N, const int32
                                                           int mode, T* __restrict__ x) {
   const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (g >= N) return;
-  T s = T(0);
-  const int32_t q1 = gptr[g + 1];
-  for (int32_t q = gptr[g]; q < q1; ++q) s += Y[gslot[q]];
-  T c = omega * s;
-  if (mode < 2) c *= W[g];
-  x[g] = (mode & 1) ? x[g] + c : c;
+  dev::gather_one<T>(g, gptr, gslot, Y, W, omega, mode, x);
 }
 
 // ---------------------------------------------------------------------- transfers
@@ -578,39 +397,8 @@ __global__ __launch_bounds__(kBlock) void k_spmv_nodes(
     const int32_t* __restrict__ p_col, const T* __restrict__ p_val, const T* __restrict__ in,
     T* __restrict__ out, int add) {
   const int64_t row = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  constexpr int DR = D * R;
-  if (row < nrow_u) {
-    T acc[DR];
-#pragma unroll
-    for (int q = 0; q < DR; ++q) acc[q] = T(0);
-    for (int32_t p = u_ptr[row]; p < u_ptr[row + 1]; ++p) {
-      const T w = u_val[p];
-      const T* xi = in + (int64_t)u_col[p] * DR;
-#pragma unroll
-      for (int q = 0; q < DR; ++q) acc[q] += w * xi[q];
-    }
-#pragma unroll
-    for (int q = 0; q < DR; ++q) {
-      const int64_t o = row * DR + q;
-      out[o] = add ? out[o] + acc[q] : acc[q];
-    }
-  } else if (row < nrow_u + nrow_p) {
-    const int64_t v = row - nrow_u;
-    T acc[R];
-#pragma unroll
-    for (int q = 0; q < R; ++q) acc[q] = T(0);
-    for (int32_t p = p_ptr[v]; p < p_ptr[v + 1]; ++p) {
-      const T w = p_val[p];
-      const T* xi = in + in_offV + (int64_t)p_col[p] * R;
-#pragma unroll
-      for (int q = 0; q < R; ++q) acc[q] += w * xi[q];
-    }
-#pragma unroll
-    for (int q = 0; q < R; ++q) {
-      const int64_t o = out_offV + v * R + q;
-      out[o] = add ? out[o] + acc[q] : acc[q];
-    }
-  }
+  dev::spmv_nodes_row<D, R, T>(row, nrow_u, nrow_p, out_offV, in_offV, u_ptr, u_col, u_val, p_ptr, p_col, p_val,
+                               in, out, add);
 }
 
 // ------------------------------------------------------------------- coarse solve

@@ -47,6 +47,11 @@ class irk_solve_info(C.Structure):
                 ("ms_vcycle", C.c_double), ("ms_total", C.c_double)]
 
 
+class irk_batch_opts(C.Structure):
+    _fields_ = [("rows_per_item", C.c_int), ("patches_per_wave", C.c_int), ("workgroups_per_cu", C.c_int),
+                ("autotune", C.c_int)]
+
+
 class irk_kernel_stats(C.Structure):
     _fields_ = [("launches", C.c_int64), ("ms_total", C.c_double), ("bytes_per_launch", C.c_double)]
 
@@ -84,6 +89,11 @@ def _load() -> C.CDLL:
         "irk_update_adjoint": (i, [vp, vp, vp, vp]),
         "irk_nu_sensitivity": (i, [vp, vp, vp, vp, vp, vp]),
         "irk_mass_apply": (i, [vp, vp, vp, vp]),
+        "irk_batch_default_opts": (None, [vp]),
+        "irk_batch_create": (i, [vp, i, vp, vp, vp]),
+        "irk_batch_fgmres_solve": (i, [vp, vp, vp, d, i, i, vp, vp, vp]),
+        "irk_batch_get_opts": (i, [vp, vp]),
+        "irk_batch_destroy": (None, [vp]),
         "irk_mg_profile": (i, [vp, i]),
         "irk_mg_kernel_stats": (i, [vp, i, i, vp]),
         "irk_last_error": (C.c_char_p, []),
@@ -296,3 +306,43 @@ class IrkMG:
     def irk_coarse_solve(self, b, x, transpose=False, stream=None):
         n = self.irk_mg_ndofs(0)
         _check(lib.irk_coarse_solve(self.h, int(transpose), _dev(b, n, "b"), _dev(x, n, "x"), _stream(stream)))
+
+
+class IrkBatch:
+    """Batched solves of several handles in one persistent launch (irk_batch_*)."""
+
+    def __init__(self, solvers, rows_per_item=1, patches_per_wave=1, workgroups_per_cu=2, autotune=True, stream=None):
+        self.solvers = list(solvers)
+        arr = (C.c_void_p * len(self.solvers))(*[s.h.value for s in self.solvers])
+        opts = irk_batch_opts(rows_per_item, patches_per_wave, workgroups_per_cu, int(autotune))
+        h = C.c_void_p()
+        _check(lib.irk_batch_create(arr, len(self.solvers), C.byref(opts), _stream(stream), C.byref(h)))
+        self.h = h
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib.irk_batch_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        self.close()
+
+    def irk_batch_get_opts(self) -> dict:
+        o = irk_batch_opts()
+        _check(lib.irk_batch_get_opts(self.h, C.byref(o)))
+        return dict(rows_per_item=o.rows_per_item, patches_per_wave=o.patches_per_wave,
+                    workgroups_per_cu=o.workgroups_per_cu, autotune=o.autotune)
+
+    def irk_batch_fgmres_solve(self, Fs, ks, rtol=1e-8, maxit=1000, restart=30, stream=None):
+        n = len(self.solvers)
+        if len(Fs) != n or len(ks) != n:
+            raise ValueError("one F and one k per solver")
+        Fp = (C.c_void_p * n)(*[_dev(F, s.irk_mg_ndofs(), "F") for F, s in zip(Fs, self.solvers)])
+        kp = (C.c_void_p * n)(*[_dev(k, s.irk_mg_ndofs(), "k") for k, s in zip(ks, self.solvers)])
+        infos = (irk_solve_info * n)()
+        lat = np.zeros(n)
+        st = _check(lib.irk_batch_fgmres_solve(self.h, Fp, kp, rtol, maxit, restart, infos, lat.ctypes.data,
+                                               _stream(stream)), ok=(IRK_OK, IRK_ENOCONV))
+        out = [dict(iterations=i.iterations, converged=bool(i.converged), rel_residual=i.rel_residual,
+                    latency_ms=float(l)) for i, l in zip(infos, lat)]
+        return st, out, float(infos[0].ms_total)

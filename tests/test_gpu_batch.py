@@ -1,0 +1,58 @@
+"""Batched solves in one persistent launch: every solve of the batch against the
+oracle's FGMRES (equal iteration counts, solutions within 1e-10 relative)."""
+import numpy as np
+import pytest
+
+from gpu_cases import forcing_rhs, gpu_of, oracle_of, relerr, say, to_dev, to_host
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+BATCH = ["c1", "r3", "oseen", "be", "lob3", "3d3"]
+
+
+@pytest.mark.parametrize("autotune", [False, True])
+def test_batch_matches_oracle(autotune):
+    from oracle.fgmres import fgmres
+    from paper_2202_07381_amd import irkmg
+
+    gs = [gpu_of(c) for c in BATCH]
+    Fs = [forcing_rhs(c) for c in BATCH]
+    say(f"[batch] create autotune={autotune} n={len(gs)}")
+    b = irkmg.IrkBatch(gs, autotune=autotune)
+    ks = [torch.zeros(F.size, dtype=torch.float64, device="cuda") for F in Fs]
+    say("[batch] solve")
+    st, infos, ms = b.irk_batch_fgmres_solve([to_dev(F) for F in Fs], ks, rtol=1e-8, maxit=200, restart=30)
+    say(f"[batch] done status={st} ms={ms:.2f} opts={b.irk_batch_get_opts()}")
+    assert st == irkmg.IRK_OK
+    for c, F, k, info in zip(BATCH, Fs, ks, infos):
+        H = oracle_of(c)
+        S = H.finest
+        xo, io = fgmres(S.apply, H.vcycle, F, np.zeros_like(F), 1e-8, 200, 30, project=S.project_pressure_mean)
+        say(f"[batch] case={c} its={info['iterations']} oracle={io.iterations} lat={info['latency_ms']:.3f}ms")
+        assert info["converged"] and info["iterations"] == io.iterations
+        assert info["rel_residual"] <= 1e-8
+        assert relerr(to_host(k), xo) < 1e-10
+    b.close()
+
+
+def test_batch_maxit_and_restart():
+    from paper_2202_07381_amd import irkmg
+
+    gs = [gpu_of(c) for c in ("c1", "be")]
+    Fs = [forcing_rhs(c) for c in ("c1", "be")]
+    b = irkmg.IrkBatch(gs, autotune=False)
+    ks = [torch.zeros(F.size, dtype=torch.float64, device="cuda") for F in Fs]
+    say("[batch] maxit=2")
+    st, infos, _ = b.irk_batch_fgmres_solve([to_dev(F) for F in Fs], ks, rtol=1e-12, maxit=2, restart=30)
+    assert st == irkmg.IRK_ENOCONV and all(i["iterations"] == 2 for i in infos)
+    # restart 4 with the individual solver as reference (same algorithm)
+    say("[batch] restart=4")
+    ks = [torch.zeros(F.size, dtype=torch.float64, device="cuda") for F in Fs]
+    st, infos, _ = b.irk_batch_fgmres_solve([to_dev(F) for F in Fs], ks, rtol=1e-9, maxit=100, restart=4)
+    for g, F, k, info in zip(gs, Fs, ks, infos):
+        kk = torch.zeros_like(k)
+        ref = g.irk_fgmres_solve(to_dev(F), kk, rtol=1e-9, maxit=100, restart=4)
+        assert info["iterations"] == ref["iterations"]
+        assert relerr(to_host(k), to_host(kk)) < 1e-11
+    b.close()
