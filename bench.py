@@ -151,6 +151,86 @@ def cpu_baseline(A, dt, nu):
             "vcycle_s": dtv}
 
 
+def run_batch(count, log_every=8):
+    """Uneven batch of independent solves: one persistent launch versus the same
+    solves one after another with the one-launch-per-step path."""
+    import numpy as np
+    import torch
+
+    from paper_2202_07381_amd import irkmg
+    from paper_2202_07381_amd import workloads as wl
+
+    specs = wl.batch_specs(4, count)
+    handles, Fs = [], []
+    t0 = time.time()
+    for j, sp in enumerate(specs):
+        levels = wl.square_hierarchy(4, int(round(np.log2(sp.n // 4))) + 1)
+        A, b, c = irkmg.irk_tableau_builtin("radauIIA", sp.r)
+        g = irkmg.IrkMG(levels, A, b, c, sp.dt, sp.nu)
+        nodes = irkmg.irk_mesh_p2_nodes(levels[-1])
+        f = wl.forcing_2d(sp.forcing_seed)
+        fn = np.stack([f(nodes)] * sp.r)
+        sz = g.irk_mg_sizes()
+        F = torch.zeros(g.irk_mg_ndofs(), dtype=torch.float64, device="cuda")
+        g.irk_rhs(torch.tensor(fn.ravel(), device="cuda"), torch.zeros(sz["ns"], dtype=torch.float64, device="cuda"), F)
+        handles.append(g)
+        Fs.append(F)
+        if (j + 1) % log_every == 0:
+            log(f"batch setup {j + 1}/{count} ({time.time() - t0:.1f}s)")
+    torch.cuda.synchronize()
+    total_unknowns = sum(g.irk_mg_ndofs() for g in handles)
+    # one after another
+    ks = [torch.zeros_like(F) for F in Fs]
+    for g, F, k in zip(handles[:2], Fs[:2], ks[:2]):
+        g.irk_fgmres_solve(F, k, rtol=1e-8, maxit=300)
+    torch.cuda.synchronize()
+    seq_lat, seq_its = [], []
+    t0 = time.perf_counter()
+    for g, F, k in zip(handles, Fs, ks):
+        k.zero_()
+        info = g.irk_fgmres_solve(F, k, rtol=1e-8, maxit=300, history_cap=0)
+        seq_its.append(info["iterations"])
+        seq_lat.append((time.perf_counter() - t0) * 1e3)
+    torch.cuda.synchronize()
+    seq_s = time.perf_counter() - t0
+    log(f"sequential {seq_s * 1e3:.1f} ms")
+    # batched
+    bt = irkmg.IrkBatch(handles, autotune=True)
+    kb = [torch.zeros_like(F) for F in Fs]
+    st, infos, _ = bt.irk_batch_fgmres_solve(Fs, kb, rtol=1e-8, maxit=300, restart=30)  # includes autotuning
+    for k in kb:
+        k.zero_()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    st, infos, ms = bt.irk_batch_fgmres_solve(Fs, kb, rtol=1e-8, maxit=300, restart=30)
+    torch.cuda.synchronize()
+    bat_s = time.perf_counter() - t0
+    log(f"batched {bat_s * 1e3:.1f} ms, schedule {bt.irk_batch_get_opts()}")
+    lat = np.array([i["latency_ms"] for i in infos])
+    diff = max(float((kb[q] - ks[q]).norm() / ks[q].norm()) for q in range(count))
+    its = [i["iterations"] for i in infos]
+    vcycles = sum(its)
+    line = {
+        "metric": METRIC + " (batched workload)",
+        "value": sum(g.irk_mg_ndofs() * i for g, i in zip(handles, its)) / bat_s,
+        "unit": "stage-DOF updates/s",
+        "n_gpus": 1, "steps": 1, "warmup": 1, "ms_per_step": bat_s * 1e3, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": f"{count} independent 2D Stokes IRK solves, n in {{32,64,128,256}}, RadauIIA r in {{2,3}}, "
+                               f"nu log-uniform [1e-2,1], dt=1e-2, seeds 4 / 4000+j, FGMRES(30) to 1e-8, one persistent launch",
+                   "solves": count, "unknowns_total": total_unknowns},
+        "status": st, "all_converged": all(i["converged"] for i in infos),
+        "iterations_total": vcycles, "latency_ms_p50": float(np.percentile(lat, 50)),
+        "latency_ms_p99": float(np.percentile(lat, 99)), "latency_ms_max": float(lat.max()),
+        "sequential_ms": seq_s * 1e3, "speedup_vs_sequential": seq_s / bat_s,
+        "sequential_latency_ms_p50": float(np.percentile(seq_lat, 50)),
+        "sequential_latency_ms_p99": float(np.percentile(seq_lat, 99)),
+        "max_rel_diff_vs_sequential": diff, "schedule": bt.irk_batch_get_opts(),
+        "iterations_match_sequential": its == seq_its,
+    }
+    print(json.dumps(line), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -159,6 +239,9 @@ def main():
     ap.add_argument("--n", type=int, default=256, help="finest mesh size (power-of-two multiple of 4)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp32", action="store_true")
+    ap.add_argument("--workload", default="stokes256", choices=["stokes256", "batch64"],
+                    help="stokes256: the headline line; batch64: the uneven batched workload")
+    ap.add_argument("--batch-count", type=int, default=64)
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -171,6 +254,9 @@ def main():
     from paper_2202_07381_amd import workloads as wl
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
+    if args.workload == "batch64":
+        run_batch(args.batch_count)
+        return
     nlev = int(round(np.log2(args.n // 4))) + 1
     levels = wl.square_hierarchy(4, nlev)
     A, b, c = irkmg.irk_tableau_builtin("radauIIA", 3)

@@ -19,6 +19,8 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <string>
 #include <vector>
@@ -34,16 +36,16 @@ constexpr int kBlock = 256;
 constexpr int kWaves = kBlock / 64;
 constexpr int kMaxLevels = 12;
 constexpr int kMaxRestart = 64;
-constexpr int kNmax = 1024;
+constexpr int kNmax = 512;
 constexpr int kCoarseChunks = 64;  // column chunks of the coarse GEMV (16 items x 4 waves)
 
-enum Phase : int {
-  PH_LOAD = 0, PH_R0, PH_N0, PH_RES, PH_NRM, PH_V0, PH_VC_IN,
-  PH_SM_RES, PH_SM_PATCH, PH_SM_GATHER, PH_ZERO, PH_DN_RES, PH_DN_RESTRICT,
-  PH_CO_IN, PH_CO_MV, PH_CO_RED, PH_UP_PROLONG, PH_VC_OUT,
-  PH_PJ_SUM, PH_PJ_SUB, PH_AP, PH_DOT, PH_AXPY, PH_WNRM, PH_VSCALE, PH_XUPD,
-  PH_FR, PH_FN, PH_STORE, PH_DONE
-};
+// states of a solve
+constexpr int PH_LOAD = 0, PH_R0 = 1, PH_N0 = 2, PH_RES = 3, PH_NRM = 4, PH_V0 = 5, PH_VC_IN = 6,
+              PH_SM_RES = 7, PH_SM_PATCH = 8, PH_SM_GATHER = 9, PH_ZERO = 10, PH_DN_RES = 11,
+              PH_DN_RESTRICT = 12, PH_CO_IN = 13, PH_CO_MV = 14, PH_CO_RED = 15, PH_UP_PROLONG = 16,
+              PH_VC_OUT = 17, PH_PJ_SUM = 18, PH_PJ_SUB = 19, PH_AP = 20, PH_DOT = 21, PH_AXPY = 22,
+              PH_WNRM = 23, PH_VSCALE = 24, PH_XUPD = 25, PH_FR = 26, PH_FN = 27, PH_STORE = 28,
+              PH_DONE = 29;
 
 struct BLevel {
   int64_t nfree, nv, N, offV, npatch;
@@ -83,6 +85,7 @@ struct BState {
   double H[(kMaxRestart + 1) * kMaxRestart], cs[kMaxRestart], sn[kMaxRestart], g[kMaxRestart + 1],
       y[kMaxRestart];
   unsigned long long t_end;
+  int ntrans, last_phase;
 };
 
 // the part of a solve's state that a work item reads (copied to LDS per item)
@@ -104,14 +107,21 @@ struct Tun {
   int elems;  // vector entries per item / 256
 };
 
+// state fields are read with device-scope atomic loads so that no cache level can
+// serve a value older than the last release
+template <typename T>
+__device__ __forceinline__ T ald(const T* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
 // ------------------------------------------------------------------ item counts
 __host__ __device__ inline int cdiv(int64_t a, int64_t b) { return (int)((a + b - 1) / b); }
 
-__device__ int items_of_raw(const BSolve& S, const BState& st, int phase, const Tun& t);
-__device__ int items_of(const BSolve& S, const BState& st, int phase, const Tun& t) {
+__host__ __device__ int items_of_raw(const BSolve& S, const BState& st, int phase, const Tun& t);
+__host__ __device__ int items_of(const BSolve& S, const BState& st, int phase, const Tun& t) {
   return max(1, items_of_raw(S, st, phase, t));
 }
-__device__ int items_of_raw(const BSolve& S, const BState& st, int phase, const Tun& t) {
+__host__ __device__ int items_of_raw(const BSolve& S, const BState& st, int phase, const Tun& t) {
   const BLevel& F = S.lv[S.nlevels - 1];
   const int64_t er = (int64_t)kBlock * t.elems, rr = (int64_t)kBlock * t.rows;
   switch (phase) {
@@ -192,8 +202,7 @@ __device__ void patches(const BLevel& L, double* xs, const double* in, int64_t p
     switch (L.rb) {
       case 1: dev::patch_apply_one<double, 1>(p, lane, xs, L.p_nloc, L.p_ld, L.p_inv_off, L.p_slot_off, L.p_gidx, L.inv, in, nullptr, L.Y, 0); break;
       case 2: dev::patch_apply_one<double, 2>(p, lane, xs, L.p_nloc, L.p_ld, L.p_inv_off, L.p_slot_off, L.p_gidx, L.inv, in, nullptr, L.Y, 0); break;
-      case 4: dev::patch_apply_one<double, 4>(p, lane, xs, L.p_nloc, L.p_ld, L.p_inv_off, L.p_slot_off, L.p_gidx, L.inv, in, nullptr, L.Y, 0); break;
-      default: dev::patch_apply_one<double, 8>(p, lane, xs, L.p_nloc, L.p_ld, L.p_inv_off, L.p_slot_off, L.p_gidx, L.inv, in, nullptr, L.Y, 0); break;
+      default: dev::patch_apply_one<double, 4>(p, lane, xs, L.p_nloc, L.p_ld, L.p_inv_off, L.p_slot_off, L.p_gidx, L.inv, in, nullptr, L.Y, 0); break;
     }
   }
 }
@@ -353,24 +362,27 @@ __device__ void exec_item(const BSolve& S, const BCur& st, const BState* gst, in
       break;
     }
     case PH_AXPY: {
-      const double hij = gst->H[st.i * kMaxRestart + st.j];
+      const double hij = ald(&gst->H[st.i * kMaxRestart + st.j]);
       const double* vi = S.V + (int64_t)st.i * N;
       for (int64_t g = e0 + tid; g < e1; g += kBlock) S.w[g] -= hij * vi[g];
       break;
     }
     case PH_VSCALE: {
-      const double hn = gst->H[(st.j + 1) * kMaxRestart + st.j];
+      const double hn = ald(&gst->H[(st.j + 1) * kMaxRestart + st.j]);
       double* vn = S.V + (int64_t)(st.j + 1) * N;
       for (int64_t g = e0 + tid; g < e1; g += kBlock) vn[g] = S.w[g] / hn;
       break;
     }
-    case PH_XUPD:
+    case PH_XUPD: {
+      double yv[kMaxRestart];
+      for (int q = 0; q < st.jend; ++q) yv[q] = ald(&gst->y[q]);
       for (int64_t g = e0 + tid; g < e1; g += kBlock) {
         double acc = S.x[g];
-        for (int q = 0; q < st.jend; ++q) acc += gst->y[q] * S.Z[(int64_t)q * N + g];
+        for (int q = 0; q < st.jend; ++q) acc += yv[q] * S.Z[(int64_t)q * N + g];
         S.x[g] = acc;
       }
       break;
+    }
     case PH_STORE:
       for (int64_t g = e0 + tid; g < e1; g += kBlock)
         S.k_abi[abi_index(g, Fl.offV, Fl.nfree, S.ns, D, R)] = S.x[g];
@@ -381,6 +393,7 @@ __device__ void exec_item(const BSolve& S, const BCur& st, const BState* gst, in
 }
 
 // ------------------------------------------------------------- state transitions
+__host__ __device__ inline bool finite(double v) { return v == v && v - v == 0.0; }
 // Reductions of the finished state (all threads), in item order.
 __device__ double reduce_partials(const BSolve& S, int n, int stride, int off, double* red) {
   double acc = 0;
@@ -389,20 +402,24 @@ __device__ double reduce_partials(const BSolve& S, int n, int stride, int off, d
 }
 
 // smoothing on level l: set the first sweep's phase
-__device__ void start_smooth(BState& st, int l, int nsweeps, int zero_start) {
+__host__ __device__ void end_smooth(const BSolve& S, BState& st);
+
+// smoothing on level l: set the first sweep's state; with no sweeps go on directly
+__host__ __device__ void start_smooth(const BSolve& S, BState& st, int l, int nsweeps, int zero_start) {
   st.level = l;
   st.sweep = 0;
   st.first = zero_start;
-  if (nsweeps == 0) {
-    st.phase = zero_start ? PH_ZERO : -1;  // -1: go straight to the end of smoothing
+  if (nsweeps > 0) {
+    if (zero_start) st.phase = PH_SM_PATCH;
+    else st.phase = PH_SM_RES;
+  } else if (zero_start) {
+    st.phase = PH_ZERO;
   } else {
-    st.phase = zero_start ? PH_SM_PATCH : PH_SM_RES;
+    end_smooth(S, st);
   }
 }
 
-__device__ void end_smooth(const BSolve& S, BState& st);
-
-__device__ void after_coarse(const BSolve& S, BState& st) {
+__host__ __device__ void after_coarse(const BSolve& S, BState& st) {
   if (S.nlevels == 1) {
     st.phase = PH_VC_OUT;
     return;
@@ -412,7 +429,7 @@ __device__ void after_coarse(const BSolve& S, BState& st) {
   st.phase = PH_UP_PROLONG;
 }
 
-__device__ void end_smooth(const BSolve& S, BState& st) {
+__host__ __device__ void end_smooth(const BSolve& S, BState& st) {
   const int top = S.nlevels - 1;
   if (st.leg == 0) {
     st.phase = PH_DN_RES;
@@ -425,7 +442,7 @@ __device__ void end_smooth(const BSolve& S, BState& st) {
 }
 
 // decide the next state (thread 0, after the reductions of the finished one)
-__device__ void advance(const BSolve& S, BState& st, double red_val, const double* means, Ctl* ctl) {
+__host__ __device__ void advance(const BSolve& S, BState& st, double red_val, const double* means, Ctl* ctl) {
   const int top = S.nlevels - 1;
   const int m = S.restart;
   switch (st.phase) {
@@ -434,14 +451,14 @@ __device__ void advance(const BSolve& S, BState& st, double red_val, const doubl
     case PH_N0:
       st.beta0 = sqrt(red_val);
       st.its = 0;
-      if (!isfinite(st.beta0)) { st.status = IRK_ENAN; st.phase = PH_DONE; break; }
+      if (!finite(st.beta0)) { st.status = IRK_ENAN; st.phase = PH_DONE; break; }
       if (st.beta0 == 0.0) { st.converged = 1; st.pj_final = 1; st.phase = PH_PJ_SUM; break; }
       st.phase = PH_RES;
       break;
     case PH_RES: st.phase = PH_NRM; break;
     case PH_NRM:
       st.beta = sqrt(red_val);
-      if (!isfinite(st.beta)) { st.status = IRK_ENAN; st.phase = PH_DONE; break; }
+      if (!finite(st.beta)) { st.status = IRK_ENAN; st.phase = PH_DONE; break; }
       if (st.beta <= S.rtol * st.beta0) { st.converged = 1; st.pj_final = 1; st.phase = PH_PJ_SUM; break; }
       for (int q = 0; q <= m; ++q) st.g[q] = 0.0;
       st.g[0] = st.beta;
@@ -452,8 +469,7 @@ __device__ void advance(const BSolve& S, BState& st, double red_val, const doubl
     case PH_VC_IN:
       st.leg = 0;
       if (top == 0) { st.phase = PH_CO_IN; break; }
-      start_smooth(st, top, S.pre, 1);
-      if (st.phase == -1) end_smooth(S, st);
+      start_smooth(S, st, top, S.pre, 1);
       break;
     case PH_ZERO:
       end_smooth(S, st);
@@ -474,16 +490,14 @@ __device__ void advance(const BSolve& S, BState& st, double red_val, const doubl
         st.level = 0;
         st.phase = PH_CO_IN;
       } else {
-        start_smooth(st, st.level - 1, S.pre, 1);
-        if (st.phase == -1) end_smooth(S, st);
+        start_smooth(S, st, st.level - 1, S.pre, 1);
       }
       break;
     case PH_CO_IN: st.phase = PH_CO_MV; break;
     case PH_CO_MV: st.phase = PH_CO_RED; break;
     case PH_CO_RED: after_coarse(S, st); break;
     case PH_UP_PROLONG:
-      start_smooth(st, st.level, S.post, 0);
-      if (st.phase == -1) end_smooth(S, st);
+      start_smooth(S, st, st.level, S.post, 0);
       break;
     case PH_VC_OUT: st.pj_final = 0; st.phase = PH_PJ_SUM; break;
     case PH_PJ_SUM:
@@ -510,7 +524,7 @@ __device__ void advance(const BSolve& S, BState& st, double red_val, const doubl
       const int j = st.j;
       double* H = st.H;
       for (int q = 0; q <= j + 1; ++q)
-        if (!isfinite(H[q * kMaxRestart + j])) { st.status = IRK_ENAN; st.phase = PH_DONE; return; }
+        if (!finite(H[q * kMaxRestart + j])) { st.status = IRK_ENAN; st.phase = PH_DONE; return; }
       for (int q = 0; q < j; ++q) {
         const double a = H[q * kMaxRestart + j], b = H[(q + 1) * kMaxRestart + j];
         H[q * kMaxRestart + j] = st.cs[q] * a + st.sn[q] * b;
@@ -552,7 +566,7 @@ __device__ void advance(const BSolve& S, BState& st, double red_val, const doubl
     case PH_FR: st.phase = PH_FN; break;
     case PH_FN:
       st.final_rel = st.beta0 > 0 ? sqrt(red_val) / st.beta0 : 0.0;
-      if (!isfinite(st.final_rel)) st.status = IRK_ENAN;
+      if (!finite(st.final_rel)) st.status = IRK_ENAN;
       st.phase = PH_STORE;
       break;
     case PH_STORE:
@@ -565,11 +579,11 @@ __device__ void advance(const BSolve& S, BState& st, double red_val, const doubl
   (void)ctl;
 }
 
-__global__ __launch_bounds__(kBlock) void k_batch(const BSolve* __restrict__ Sv, BState* Stv, Ctl* ctl,
+__global__ __launch_bounds__(kBlock, 2) void k_batch(const BSolve* __restrict__ Sv, BState* Stv, Ctl* ctl,
                                                   int nsolves, Tun tun) {
   __shared__ double xs[kWaves * kNmax];
   __shared__ double red[kBlock];
-  __shared__ int s_item, s_ok, s_last, s_exit, s_solve;
+  __shared__ int s_item, s_ok, s_last, s_exit, s_solve, s_epoch, s_viol;
   __shared__ BCur s_st;  // snapshot of the solve's state for the item being executed
   __shared__ double s_means[kMaxStages];
   const int tid = threadIdx.x;
@@ -597,6 +611,7 @@ __global__ __launch_bounds__(kBlock) void k_batch(const BSolve* __restrict__ Sv,
             s_ok = 1;
             s_item = item;
             s_solve = cursor;
+            s_epoch = e;
           }
         }
       }
@@ -613,25 +628,30 @@ __global__ __launch_bounds__(kBlock) void k_batch(const BSolve* __restrict__ Sv,
       continue;
     }
     idle = 0;
-    __threadfence();  // acquire: the state and the data of earlier states are visible
+    __threadfence();  // acquire (device scope): data released by earlier states is visible
     const BSolve& S = Sv[s_solve];
     BState* st = &Stv[s_solve];
     // snapshot of the state (stable while this item is outstanding)
     if (tid == 0) {
-      s_st.phase = st->phase;
-      s_st.n_items = st->n_items;
-      s_st.level = st->level;
-      s_st.first = st->first;
-      s_st.j = st->j;
-      s_st.i = st->i;
-      s_st.jend = st->jend;
-      s_st.pj_final = st->pj_final;
-      s_st.beta = st->beta;
-      for (int q = 0; q < kMaxStages; ++q) s_st.mean[q] = st->mean[q];
+      s_viol = (ald(&st->epoch) != s_epoch) ? 1 : 0;
+      s_st.phase = ald(&st->phase);
+      s_st.n_items = ald(&st->n_items);
+      s_st.level = ald(&st->level);
+      s_st.first = ald(&st->first);
+      s_st.j = ald(&st->j);
+      s_st.i = ald(&st->i);
+      s_st.jend = ald(&st->jend);
+      s_st.pj_final = ald(&st->pj_final);
+      s_st.beta = ald(&st->beta);
+      for (int q = 0; q < kMaxStages; ++q) s_st.mean[q] = ald(&st->mean[q]);
     }
     __syncthreads();
+    if (s_viol) {
+      if (tid == 0) __hip_atomic_store(&ctl->abort, 2, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+      break;
+    }
     exec_item(S, s_st, st, s_item, tun, xs, red);
-    __threadfence();
+    __threadfence();  // release (device scope) of this item's results
     __syncthreads();
     if (tid == 0) {
       const int d = __hip_atomic_fetch_add(&st->done, 1, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
@@ -639,7 +659,7 @@ __global__ __launch_bounds__(kBlock) void k_batch(const BSolve* __restrict__ Sv,
     }
     __syncthreads();
     if (s_last) {
-      __threadfence();
+      __threadfence();  // acquire every other item's results
       // reductions of the finished state, then the transition
       double rv = 0.0;
       const int ph = s_st.phase;
@@ -653,6 +673,9 @@ __global__ __launch_bounds__(kBlock) void k_batch(const BSolve* __restrict__ Sv,
       __syncthreads();
       if (tid == 0) {
         BState& w = *st;
+        if (w.epoch != s_epoch || w.phase != s_st.phase) s_viol |= 2;
+        w.ntrans += 1;
+        w.last_phase = w.phase;
         advance(S, w, rv, s_means, ctl);
         const int nph = w.phase;
         w.n_items = (nph == PH_DONE) ? 0 : items_of(S, w, nph, tun);
@@ -665,6 +688,10 @@ __global__ __launch_bounds__(kBlock) void k_batch(const BSolve* __restrict__ Sv,
         if (nph == PH_DONE) __hip_atomic_fetch_add(&ctl->finished, 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
       }
       __syncthreads();
+      if (s_viol) {
+        if (tid == 0) __hip_atomic_store(&ctl->abort, 3, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+        break;
+      }
     }
   }
 }
@@ -716,7 +743,7 @@ BLevel level_view(const DevLevel& L) {
   v.N = L.N;
   v.offV = L.offV;
   v.npatch = L.npatch;
-  v.rb = L.max_nloc <= 128 ? 1 : L.max_nloc <= 256 ? 2 : L.max_nloc <= 512 ? 4 : 8;
+  v.rb = L.max_nloc <= 128 ? 1 : L.max_nloc <= 256 ? 2 : 4;
   v.s_ptr = L.s_ptr; v.s_col = L.s_col; v.b_ptr = L.b_ptr; v.b_col = L.b_col; v.bt_ptr = L.bt_ptr; v.bt_col = L.bt_col;
   v.sM = L.d64.s_M; v.sL = L.d64.s_L; v.b_val = L.d64.b_val; v.bt_val = L.d64.bt_val; v.W = L.d64.W;
   v.pu_ptr = L.pu_ptr; v.pu_col = L.pu_col; v.put_ptr = L.put_ptr; v.put_col = L.put_col;
@@ -779,7 +806,7 @@ irk_status run(irk_batch* b, const double* const* F, double* const* k, bool tria
     hSt[q].n_items = host_items_first(hS[q], tun);
   }
   Ctl c{};
-  c.max_idle = 20000000LL;
+  c.max_idle = 2000000LL;
   BHIP(hipMemcpyAsync(b->dS, hS.data(), n * sizeof(BSolve), hipMemcpyHostToDevice, s));
   BHIP(hipMemcpyAsync(b->dSt, hSt.data(), n * sizeof(BState), hipMemcpyHostToDevice, s));
   BHIP(hipMemcpyAsync(b->dctl, &c, sizeof(Ctl), hipMemcpyHostToDevice, s));
@@ -798,7 +825,8 @@ irk_status run(irk_batch* b, const double* const* F, double* const* k, bool tria
   (void)hipEventDestroy(e1);
   if (ms_out) *ms_out = ms;
   BHIP(hipMemcpy(&c, b->dctl, sizeof(Ctl), hipMemcpyDeviceToHost));
-  if (c.abort) return bfail(IRK_EHIP, "batched solver aborted: a workgroup found no work for too long");
+  if (c.abort == 1) return bfail(IRK_EHIP, "batched solver aborted: a workgroup found no work for too long");
+  if (c.abort) return bfail(IRK_EHIP, "batched solver aborted: work-queue protocol violation " + std::to_string(c.abort));
   if (states_out) {
     states_out->resize(n);
     BHIP(hipMemcpy(states_out->data(), b->dSt, n * sizeof(BState), hipMemcpyDeviceToHost));
@@ -908,6 +936,8 @@ irk_status irk_batch_fgmres_solve(irk_batch* b, const double* const* F, double* 
           b->opts.patches_per_wave = ppw;
           float ms = 0;
           irk_status st = run(b, F, k, true, rtol, 2, restart, s, &ms, nullptr, nullptr);
+          if (std::getenv("IRK_BATCH_DEBUG"))
+            fprintf(stderr, "autotune wg %d rows %d ppw %d: %.3f ms (status %d)\n", wg, rows, ppw, ms, st);
           if (st != IRK_OK) return st;
           if (ms < best) {
             best = ms;
@@ -923,6 +953,11 @@ irk_status irk_batch_fgmres_solve(irk_batch* b, const double* const* F, double* 
   irk_status st = run(b, F, k, false, rtol, maxit, restart, s, &ms, &states, &t0);
   if (st != IRK_OK) return st;
   irk_status ret = IRK_OK;
+  if (std::getenv("IRK_BATCH_DEBUG"))
+    for (int q = 0; q < n; ++q)
+      fprintf(stderr, "batch solve %d: ntrans %d last_phase %d its %d conv %d status %d beta0 %g beta %g rel %g size %zu\n", q,
+              states[q].ntrans, states[q].last_phase, states[q].its, states[q].converged, states[q].status,
+              states[q].beta0, states[q].beta, states[q].final_rel, sizeof(BState));
   for (int q = 0; q < n; ++q) {
     const BState& x = states[q];
     if (infos) {

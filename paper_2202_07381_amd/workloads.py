@@ -289,3 +289,26 @@ class ConstantField:
 def random_vector(n: int, seed: int) -> np.ndarray:
     """N(0,1) draws from PCG64(seed), used as residuals and initial guesses."""
     return np.random.default_rng(seed).standard_normal(n)
+
+
+@dataclass
+class BatchSolveSpec:
+    n: int        # finest mesh is n x n (levels from a 4 x 4 coarsest mesh)
+    r: int        # RadauIIA stages
+    nu: float
+    dt: float
+    forcing_seed: int
+
+
+def batch_specs(seed: int = 4, count: int = 64, dt: float = 1e-2) -> list[BatchSolveSpec]:
+    """Uneven batch: n ~ U{32, 64, 128, 256}, r ~ U{2, 3}, nu = 10^U(-2, 0), drawn in
+    that order per solve from PCG64(seed); solve j uses the 2D forcing with seed
+    4000 + j."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for j in range(count):
+        n = int(rng.choice([32, 64, 128, 256]))
+        r = int(rng.integers(2, 4))
+        nu = float(10.0 ** rng.uniform(-2.0, 0.0))
+        out.append(BatchSolveSpec(n, r, nu, dt, 4000 + j))
+    return out

@@ -24,6 +24,8 @@ def test_batch_matches_oracle(autotune):
     say("[batch] solve")
     st, infos, ms = b.irk_batch_fgmres_solve([to_dev(F) for F in Fs], ks, rtol=1e-8, maxit=200, restart=30)
     say(f"[batch] done status={st} ms={ms:.2f} opts={b.irk_batch_get_opts()}")
+    for c, info in zip(BATCH, infos):
+        say(f"[batch] case={c} {info}")
     assert st == irkmg.IRK_OK
     for c, F, k, info in zip(BATCH, Fs, ks, infos):
         H = oracle_of(c)
@@ -56,3 +58,26 @@ def test_batch_maxit_and_restart():
         assert info["iterations"] == ref["iterations"]
         assert relerr(to_host(k), to_host(kk)) < 1e-11
     b.close()
+
+
+def test_batch_bitwise_repeatable():
+    """Work items may run on any workgroup in any order; every result must still be
+    bitwise identical from one launch to the next (reductions are in item order)."""
+    from paper_2202_07381_amd import irkmg
+
+    gs = [gpu_of(c) for c in BATCH]
+    Fs = [to_dev(forcing_rhs(c)) for c in BATCH]
+    for wg in (1, 2):
+        b = irkmg.IrkBatch(gs, workgroups_per_cu=wg, autotune=False)
+        ref = None
+        for rep in range(5):
+            say(f"[batch-repeat] workgroups_per_cu={wg} rep={rep}")
+            ks = [torch.zeros_like(F) for F in Fs]
+            st, infos, _ = b.irk_batch_fgmres_solve(Fs, ks, rtol=1e-8, maxit=200, restart=30)
+            assert st == irkmg.IRK_OK
+            out = [to_host(k) for k in ks]
+            if ref is None:
+                ref = out
+            else:
+                assert all(np.array_equal(a, c) for a, c in zip(out, ref))
+        b.close()
