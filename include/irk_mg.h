@@ -216,8 +216,9 @@ irk_status irk_level_prolong(irk_mg* h, int level, const double* xc, double* xf,
 /* x = J_0^{-1} b on the coarsest level with pinned pressures (transpose: J_0^{-T}). */
 irk_status irk_coarse_solve(irk_mg* h, int transpose, const double* b, double* x, void* stream);
 
-/* Batched solves in one persistent launch.  irk_batch_create groups n FP64 handles
- * (distinct, set up independently, of any sizes and stage counts); each call of
+/* Batched solves in one persistent launch.  irk_batch_create groups n FP64 2D handles
+ * (distinct, set up independently, of any sizes and stage counts, patches of at most
+ * 256 unknowns); each call of
  * irk_batch_fgmres_solve then runs the whole FGMRES solve of every handle -- the same
  * algorithm as irk_fgmres_solve: layout conversion, residuals, V-cycles, Gram--Schmidt,
  * Givens updates, solution update and projection -- inside ONE persistent kernel in

@@ -36,7 +36,7 @@ constexpr int kBlock = 256;
 constexpr int kWaves = kBlock / 64;
 constexpr int kMaxLevels = 12;
 constexpr int kMaxRestart = 64;
-constexpr int kNmax = 512;
+constexpr int kNmax = 256;
 constexpr int kCoarseChunks = 64;  // column chunks of the coarse GEMV (16 items x 4 waves)
 
 // states of a solve
@@ -77,7 +77,10 @@ struct BSolve {
 
 struct BState {
   unsigned long long ticket;  // (epoch << 32) | next item
-  int done, epoch, phase, n_items;
+  unsigned long long meta;    // (epoch << 32) | items of that epoch, published as one word
+  int done;                   // items completed over all states (never reset)
+  int done_base;              // value of `done` when the current state started
+  int epoch, phase, n_items;
   int level, sweep, first, leg, j, i, jend, pj_final;
   int its, converged, status;
   double beta0, beta, final_rel;
@@ -90,7 +93,7 @@ struct BState {
 
 // the part of a solve's state that a work item reads (copied to LDS per item)
 struct BCur {
-  int phase, n_items, level, first, j, i, jend, pj_final;
+  int phase, n_items, done_base, level, first, j, i, jend, pj_final;
   double beta;
   double mean[kMaxStages];
 };
@@ -99,6 +102,8 @@ struct Ctl {
   int finished, abort;
   unsigned long long t0;
   long long max_idle;
+  // on an idle abort: per solve phase, epoch, done, done_base, n_items, ticket item, ticket epoch
+  int dbg[16 * 7];
 };
 
 struct Tun {
@@ -112,6 +117,10 @@ struct Tun {
 template <typename T>
 __device__ __forceinline__ T ald(const T* p) {
   return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+template <typename T>
+__device__ __forceinline__ void ast(T* p, T v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
 // ------------------------------------------------------------------ item counts
@@ -171,7 +180,6 @@ __device__ void residual(int D, int R, const BLevel& L, const dev::Coef<double>&
 #define IRK_B_RES(DD, RR) \
   if (D == DD && R == RR) return resid_rows<DD, RR>(L, c, F, x, y, r0, r1);
   IRK_B_RES(2, 1) IRK_B_RES(2, 2) IRK_B_RES(2, 3) IRK_B_RES(2, 4)
-  IRK_B_RES(3, 1) IRK_B_RES(3, 2) IRK_B_RES(3, 3) IRK_B_RES(3, 4)
 #undef IRK_B_RES
 }
 
@@ -189,7 +197,6 @@ __device__ void spmv(int D, int R, int64_t nu, int64_t np, int64_t out_offV, int
 #define IRK_B_SP(DD, RR) \
   if (D == DD && R == RR) return spmv_rows<DD, RR>(nu, np, out_offV, in_offV, up, uc, uv, pp, pc, pv, in, out, add, r0, r1);
   IRK_B_SP(2, 1) IRK_B_SP(2, 2) IRK_B_SP(2, 3) IRK_B_SP(2, 4)
-  IRK_B_SP(3, 1) IRK_B_SP(3, 2) IRK_B_SP(3, 3) IRK_B_SP(3, 4)
 #undef IRK_B_SP
 }
 
@@ -202,7 +209,7 @@ __device__ void patches(const BLevel& L, double* xs, const double* in, int64_t p
     switch (L.rb) {
       case 1: dev::patch_apply_one<double, 1>(p, lane, xs, L.p_nloc, L.p_ld, L.p_inv_off, L.p_slot_off, L.p_gidx, L.inv, in, nullptr, L.Y, 0); break;
       case 2: dev::patch_apply_one<double, 2>(p, lane, xs, L.p_nloc, L.p_ld, L.p_inv_off, L.p_slot_off, L.p_gidx, L.inv, in, nullptr, L.Y, 0); break;
-      default: dev::patch_apply_one<double, 4>(p, lane, xs, L.p_nloc, L.p_ld, L.p_inv_off, L.p_slot_off, L.p_gidx, L.inv, in, nullptr, L.Y, 0); break;
+      default: dev::patch_apply_one<double, 2>(p, lane, xs, L.p_nloc, L.p_ld, L.p_inv_off, L.p_slot_off, L.p_gidx, L.inv, in, nullptr, L.Y, 0); break;
     }
   }
 }
@@ -374,13 +381,15 @@ __device__ void exec_item(const BSolve& S, const BCur& st, const BState* gst, in
       break;
     }
     case PH_XUPD: {
-      double yv[kMaxRestart];
-      for (int q = 0; q < st.jend; ++q) yv[q] = ald(&gst->y[q]);
+      double* yv = red;  // LDS staging of the update coefficients
+      if (tid < st.jend) yv[tid] = ald(&gst->y[tid]);
+      __syncthreads();
       for (int64_t g = e0 + tid; g < e1; g += kBlock) {
         double acc = S.x[g];
         for (int q = 0; q < st.jend; ++q) acc += yv[q] * S.Z[(int64_t)q * N + g];
         S.x[g] = acc;
       }
+      __syncthreads();
       break;
     }
     case PH_STORE:
@@ -393,6 +402,23 @@ __device__ void exec_item(const BSolve& S, const BCur& st, const BState* gst, in
 }
 
 // ------------------------------------------------------------- state transitions
+// shared arrays of the state go through device-scope loads and stores (plain on the host)
+template <typename T>
+__host__ __device__ inline T gld(const T* p) {
+#if defined(__HIP_DEVICE_COMPILE__)
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+#else
+  return *p;
+#endif
+}
+template <typename T>
+__host__ __device__ inline void gst(T* p, T v) {
+#if defined(__HIP_DEVICE_COMPILE__)
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+#else
+  *p = v;
+#endif
+}
 __host__ __device__ inline bool finite(double v) { return v == v && v - v == 0.0; }
 // Reductions of the finished state (all threads), in item order.
 __device__ double reduce_partials(const BSolve& S, int n, int stride, int off, double* red) {
@@ -460,8 +486,8 @@ __host__ __device__ void advance(const BSolve& S, BState& st, double red_val, co
       st.beta = sqrt(red_val);
       if (!finite(st.beta)) { st.status = IRK_ENAN; st.phase = PH_DONE; break; }
       if (st.beta <= S.rtol * st.beta0) { st.converged = 1; st.pj_final = 1; st.phase = PH_PJ_SUM; break; }
-      for (int q = 0; q <= m; ++q) st.g[q] = 0.0;
-      st.g[0] = st.beta;
+      for (int q = 0; q <= m; ++q) gst(&st.g[q], 0.0);
+      gst(&st.g[0], st.beta);
       st.j = 0;
       st.phase = PH_V0;
       break;
@@ -509,7 +535,7 @@ __host__ __device__ void advance(const BSolve& S, BState& st, double red_val, co
       break;
     case PH_AP: st.i = 0; st.phase = PH_DOT; break;
     case PH_DOT:
-      st.H[st.i * kMaxRestart + st.j] = red_val;
+      gst(&st.H[st.i * kMaxRestart + st.j], red_val);
       st.phase = PH_AXPY;
       break;
     case PH_AXPY:
@@ -517,34 +543,42 @@ __host__ __device__ void advance(const BSolve& S, BState& st, double red_val, co
       st.phase = st.i <= st.j ? PH_DOT : PH_WNRM;
       break;
     case PH_WNRM:
-      st.H[(st.j + 1) * kMaxRestart + st.j] = sqrt(red_val);
+      gst(&st.H[(st.j + 1) * kMaxRestart + st.j], sqrt(red_val));
       st.phase = PH_VSCALE;
       break;
     case PH_VSCALE: {
       const int j = st.j;
       double* H = st.H;
-      for (int q = 0; q <= j + 1; ++q)
-        if (!finite(H[q * kMaxRestart + j])) { st.status = IRK_ENAN; st.phase = PH_DONE; return; }
-      for (int q = 0; q < j; ++q) {
-        const double a = H[q * kMaxRestart + j], b = H[(q + 1) * kMaxRestart + j];
-        H[q * kMaxRestart + j] = st.cs[q] * a + st.sn[q] * b;
-        H[(q + 1) * kMaxRestart + j] = -st.sn[q] * a + st.cs[q] * b;
+      double col[kMaxRestart + 1];
+      for (int q = 0; q <= j + 1; ++q) {
+        col[q] = gld(&H[q * kMaxRestart + j]);
+        if (!finite(col[q])) { st.status = IRK_ENAN; st.phase = PH_DONE; return; }
       }
-      const double den = hypot(H[j * kMaxRestart + j], H[(j + 1) * kMaxRestart + j]);
-      st.cs[j] = H[j * kMaxRestart + j] / den;
-      st.sn[j] = H[(j + 1) * kMaxRestart + j] / den;
-      H[j * kMaxRestart + j] = den;
-      H[(j + 1) * kMaxRestart + j] = 0.0;
-      st.g[j + 1] = -st.sn[j] * st.g[j];
-      st.g[j] = st.cs[j] * st.g[j];
+      for (int q = 0; q < j; ++q) {
+        const double c = gld(&st.cs[q]), sn = gld(&st.sn[q]);
+        const double a = col[q], b = col[q + 1];
+        col[q] = c * a + sn * b;
+        col[q + 1] = -sn * a + c * b;
+      }
+      const double den = hypot(col[j], col[j + 1]);
+      const double cj = col[j] / den, sj = col[j + 1] / den;
+      gst(&st.cs[j], cj);
+      gst(&st.sn[j], sj);
+      col[j] = den;
+      col[j + 1] = 0.0;
+      for (int q = 0; q <= j + 1; ++q) gst(&H[q * kMaxRestart + j], col[q]);
+      const double gj = gld(&st.g[j]);
+      const double gj1 = -sj * gj;
+      gst(&st.g[j + 1], gj1);
+      gst(&st.g[j], cj * gj);
       st.its += 1;
-      const bool conv = fabs(st.g[j + 1]) <= S.rtol * st.beta0;
+      const bool conv = fabs(gj1) <= S.rtol * st.beta0;
       if (conv || st.its >= S.maxit || j + 1 == m) {
         const int jend = j + 1;
         for (int q = jend - 1; q >= 0; --q) {
-          double acc = st.g[q];
-          for (int c = q + 1; c < jend; ++c) acc -= H[q * kMaxRestart + c] * st.y[c];
-          st.y[q] = acc / H[q * kMaxRestart + q];
+          double acc = gld(&st.g[q]);
+          for (int c = q + 1; c < jend; ++c) acc -= gld(&H[q * kMaxRestart + c]) * gld(&st.y[c]);
+          gst(&st.y[q], acc / gld(&H[q * kMaxRestart + q]));
         }
         st.jend = jend;
         if (conv) st.converged = 1;
@@ -579,7 +613,7 @@ __host__ __device__ void advance(const BSolve& S, BState& st, double red_val, co
   (void)ctl;
 }
 
-__global__ __launch_bounds__(kBlock, 2) void k_batch(const BSolve* __restrict__ Sv, BState* Stv, Ctl* ctl,
+__global__ __launch_bounds__(kBlock, 4) void k_batch(const BSolve* __restrict__ Sv, BState* Stv, Ctl* ctl,
                                                   int nsolves, Tun tun) {
   __shared__ double xs[kWaves * kNmax];
   __shared__ double red[kBlock];
@@ -605,9 +639,9 @@ __global__ __launch_bounds__(kBlock, 2) void k_batch(const BSolve* __restrict__ 
           const unsigned long long tk =
               __hip_atomic_fetch_add(&st->ticket, 1ull, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
           const int e = (int)(tk >> 32), item = (int)(tk & 0xffffffffull);
-          const int ep = __hip_atomic_load(&st->epoch, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
-          const int n = __hip_atomic_load(&st->n_items, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
-          if (e == ep && item < n) {
+          // epoch and item count of the current state, read as one word
+          const unsigned long long mt = __hip_atomic_load(&st->meta, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+          if ((int)(mt >> 32) == e && item < (int)(mt & 0xffffffffull)) {
             s_ok = 1;
             s_item = item;
             s_solve = cursor;
@@ -621,14 +655,30 @@ __global__ __launch_bounds__(kBlock, 2) void k_batch(const BSolve* __restrict__ 
     if (!s_ok) {
       cursor = (cursor + 1) % nsolves;
       if (++idle > ctl->max_idle) {
-        if (tid == 0) __hip_atomic_store(&ctl->abort, 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+        if (tid == 0) {
+          int expected = 0;
+          if (__hip_atomic_compare_exchange_strong(&ctl->abort, &expected, 1, __ATOMIC_ACQ_REL, __ATOMIC_RELAXED,
+                                                   __HIP_MEMORY_SCOPE_AGENT))
+            for (int q = 0; q < min(nsolves, 16); ++q) {
+              BState* sq = &Stv[q];
+              const unsigned long long tk = ald(&sq->ticket);
+              ast(&ctl->dbg[q * 7 + 0], ald(&sq->phase));
+              ast(&ctl->dbg[q * 7 + 1], ald(&sq->epoch));
+              ast(&ctl->dbg[q * 7 + 2], ald(&sq->done));
+              ast(&ctl->dbg[q * 7 + 3], ald(&sq->done_base));
+              ast(&ctl->dbg[q * 7 + 4], ald(&sq->n_items));
+              ast(&ctl->dbg[q * 7 + 5], (int)(tk & 0xffffffffull));
+              ast(&ctl->dbg[q * 7 + 6], (int)(tk >> 32));
+            }
+        }
         break;
       }
       __builtin_amdgcn_s_sleep(1);
       continue;
     }
     idle = 0;
-    __threadfence();  // acquire (device scope): data released by earlier states is visible
+    // thread 0's ticket acquire (device scope) invalidated this CU's L1 and this XCD's
+    // L2 before the barrier, so every wave reads data released by earlier states
     const BSolve& S = Sv[s_solve];
     BState* st = &Stv[s_solve];
     // snapshot of the state (stable while this item is outstanding)
@@ -636,6 +686,7 @@ __global__ __launch_bounds__(kBlock, 2) void k_batch(const BSolve* __restrict__ 
       s_viol = (ald(&st->epoch) != s_epoch) ? 1 : 0;
       s_st.phase = ald(&st->phase);
       s_st.n_items = ald(&st->n_items);
+      s_st.done_base = ald(&st->done_base);
       s_st.level = ald(&st->level);
       s_st.first = ald(&st->first);
       s_st.j = ald(&st->j);
@@ -651,15 +702,16 @@ __global__ __launch_bounds__(kBlock, 2) void k_batch(const BSolve* __restrict__ 
       break;
     }
     exec_item(S, s_st, st, s_item, tun, xs, red);
-    __threadfence();  // release (device scope) of this item's results
+    __builtin_amdgcn_s_waitcnt(0);  // this wave's stores have reached L2
     __syncthreads();
     if (tid == 0) {
+      __threadfence();  // release (device scope): write back this XCD's L2
       const int d = __hip_atomic_fetch_add(&st->done, 1, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
-      s_last = (d == s_st.n_items - 1) ? 1 : 0;
+      s_last = (d == s_st.done_base + s_st.n_items - 1) ? 1 : 0;
     }
     __syncthreads();
     if (s_last) {
-      __threadfence();  // acquire every other item's results
+      // thread 0's acq_rel increment acquired every other item's results
       // reductions of the finished state, then the transition
       double rv = 0.0;
       const int ph = s_st.phase;
@@ -673,17 +725,52 @@ __global__ __launch_bounds__(kBlock, 2) void k_batch(const BSolve* __restrict__ 
       __syncthreads();
       if (tid == 0) {
         BState& w = *st;
-        if (w.epoch != s_epoch || w.phase != s_st.phase) s_viol |= 2;
+        if (ald(&st->epoch) != s_epoch || ald(&st->phase) != s_st.phase) s_viol |= 2;
         w.ntrans += 1;
-        w.last_phase = w.phase;
+        w.last_phase = s_st.phase;
+        w.phase = s_st.phase;
+        w.level = ald(&st->level);
+        w.sweep = ald(&st->sweep);
+        w.first = ald(&st->first);
+        w.leg = ald(&st->leg);
+        w.j = ald(&st->j);
+        w.i = ald(&st->i);
+        w.jend = ald(&st->jend);
+        w.pj_final = ald(&st->pj_final);
+        w.its = ald(&st->its);
+        w.converged = ald(&st->converged);
+        w.status = ald(&st->status);
+        w.beta0 = ald(&st->beta0);
+        w.beta = ald(&st->beta);
+        w.final_rel = ald(&st->final_rel);
+        for (int q = 0; q < kMaxStages; ++q) w.mean[q] = ald(&st->mean[q]);
         advance(S, w, rv, s_means, ctl);
         const int nph = w.phase;
-        w.n_items = (nph == PH_DONE) ? 0 : items_of(S, w, nph, tun);
-        w.done = 0;
-        w.epoch += 1;
+        const int nitems = (nph == PH_DONE) ? 0 : items_of(S, w, nph, tun);
         if (nph == PH_DONE) w.t_end = wall_clock64();
+        // publish the new state with device-scope stores, then release the ticket
+        ast(&st->done_base, s_st.done_base + s_st.n_items);
+        ast(&st->n_items, nitems);
+        ast(&st->level, w.level);
+        ast(&st->sweep, w.sweep);
+        ast(&st->first, w.first);
+        ast(&st->leg, w.leg);
+        ast(&st->j, w.j);
+        ast(&st->i, w.i);
+        ast(&st->jend, w.jend);
+        ast(&st->pj_final, w.pj_final);
+        ast(&st->its, w.its);
+        ast(&st->converged, w.converged);
+        ast(&st->status, w.status);
+        ast(&st->beta0, w.beta0);
+        ast(&st->beta, w.beta);
+        ast(&st->final_rel, w.final_rel);
+        for (int q = 0; q < kMaxStages; ++q) ast(&st->mean[q], w.mean[q]);
+        ast(&st->epoch, s_epoch + 1);
+        ast(&st->phase, nph);
+        ast(&st->meta, (((unsigned long long)(s_epoch + 1)) << 32) | (unsigned long long)(unsigned)nitems);
         __threadfence();
-        __hip_atomic_store(&st->ticket, ((unsigned long long)w.epoch) << 32, __ATOMIC_RELEASE,
+        __hip_atomic_store(&st->ticket, ((unsigned long long)(s_epoch + 1)) << 32, __ATOMIC_RELEASE,
                            __HIP_MEMORY_SCOPE_AGENT);
         if (nph == PH_DONE) __hip_atomic_fetch_add(&ctl->finished, 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
       }
@@ -736,6 +823,17 @@ irk_status balloc(irk_batch* b, T** p, size_t n) {
   return IRK_OK;
 }
 
+// The work-queue state (tickets, counters, scalars) lives in fine-grained device
+// memory: atomics on ordinary device memory are resolved in the L2 cache of the XCD
+// that issues them, so workgroups on different XCDs could draw the same ticket.
+template <typename T>
+irk_status balloc_fine(irk_batch* b, T** p, size_t n) {
+  if (hipExtMallocWithFlags((void**)p, std::max<size_t>(1, n) * sizeof(T), hipDeviceMallocFinegrained) != hipSuccess)
+    return bfail(IRK_ENOMEM, "fine-grained allocation failed in the batched solver");
+  b->allocs.push_back(*p);
+  return IRK_OK;
+}
+
 BLevel level_view(const DevLevel& L) {
   BLevel v{};
   v.nfree = L.nfree;
@@ -743,7 +841,7 @@ BLevel level_view(const DevLevel& L) {
   v.N = L.N;
   v.offV = L.offV;
   v.npatch = L.npatch;
-  v.rb = L.max_nloc <= 128 ? 1 : L.max_nloc <= 256 ? 2 : 4;
+  v.rb = L.max_nloc <= 128 ? 1 : 2;
   v.s_ptr = L.s_ptr; v.s_col = L.s_col; v.b_ptr = L.b_ptr; v.b_col = L.b_col; v.bt_ptr = L.bt_ptr; v.bt_col = L.bt_col;
   v.sM = L.d64.s_M; v.sL = L.d64.s_L; v.b_val = L.d64.b_val; v.bt_val = L.d64.bt_val; v.W = L.d64.W;
   v.pu_ptr = L.pu_ptr; v.pu_col = L.pu_col; v.put_ptr = L.put_ptr; v.put_col = L.put_col;
@@ -804,6 +902,7 @@ irk_status run(irk_batch* b, const double* const* F, double* const* k, bool tria
     std::memset(&hSt[q], 0, sizeof(BState));
     hSt[q].phase = PH_LOAD;
     hSt[q].n_items = host_items_first(hS[q], tun);
+    hSt[q].meta = (unsigned long long)(unsigned)hSt[q].n_items;
   }
   Ctl c{};
   c.max_idle = 2000000LL;
@@ -825,7 +924,14 @@ irk_status run(irk_batch* b, const double* const* F, double* const* k, bool tria
   (void)hipEventDestroy(e1);
   if (ms_out) *ms_out = ms;
   BHIP(hipMemcpy(&c, b->dctl, sizeof(Ctl), hipMemcpyDeviceToHost));
-  if (c.abort == 1) return bfail(IRK_EHIP, "batched solver aborted: a workgroup found no work for too long");
+  if (c.abort == 1) {
+    if (std::getenv("IRK_BATCH_DEBUG"))
+      for (int q = 0; q < std::min(n, 16); ++q)
+        fprintf(stderr, "stuck solve %d: phase %d epoch %d done %d base %d n_items %d ticket item %d epoch %d\n", q,
+                c.dbg[q * 7], c.dbg[q * 7 + 1], c.dbg[q * 7 + 2], c.dbg[q * 7 + 3], c.dbg[q * 7 + 4], c.dbg[q * 7 + 5],
+                c.dbg[q * 7 + 6]);
+    return bfail(IRK_EHIP, "batched solver aborted: a workgroup found no work for too long");
+  }
   if (c.abort) return bfail(IRK_EHIP, "batched solver aborted: work-queue protocol violation " + std::to_string(c.abort));
   if (states_out) {
     states_out->resize(n);
@@ -859,6 +965,7 @@ irk_status irk_batch_create(irk_mg* const* hs, int n, const irk_batch_opts* opts
   for (int q = 0; q < n; ++q) {
     if (!hs[q]) return bfail(IRK_EINVAL, "null handle in the batch");
     if (hs[q]->precision != 0) return bfail(IRK_EINVAL, "the batched solver runs FP64 handles only");
+    if (hs[q]->dim != 2) return bfail(IRK_EINVAL, "the batched solver runs 2D handles only");
     if (hs[q]->nlevels > kMaxLevels) return bfail(IRK_EINVAL, "too many levels for the batched solver");
     for (int l = 1; l < hs[q]->nlevels; ++l)
       if (hs[q]->dev[l].max_nloc > kNmax) return bfail(IRK_EINVAL, "patch too large for the batched solver");
@@ -886,8 +993,8 @@ irk_status irk_batch_create(irk_mg* const* hs, int n, const irk_batch_opts* opts
   b->wg_per_cu = occ;
   b->opts.workgroups_per_cu = std::min(b->opts.workgroups_per_cu, occ);
   if ((st = balloc(b, &b->dS, n)) != IRK_OK) return cleanup(st);
-  if ((st = balloc(b, &b->dSt, n)) != IRK_OK) return cleanup(st);
-  if ((st = balloc(b, &b->dctl, 1)) != IRK_OK) return cleanup(st);
+  if ((st = balloc_fine(b, &b->dSt, n)) != IRK_OK) return cleanup(st);
+  if ((st = balloc_fine(b, &b->dctl, 1)) != IRK_OK) return cleanup(st);
   b->partials.resize(n);
   b->ktrial.resize(n);
   for (int q = 0; q < n; ++q) {
