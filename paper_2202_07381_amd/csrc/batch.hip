@@ -32,7 +32,7 @@
 namespace irk {
 namespace batch {
 
-constexpr int kBlock = 256;
+constexpr int kBlock = 1024;
 constexpr int kWaves = kBlock / 64;
 constexpr int kMaxLevels = 12;
 constexpr int kMaxRestart = 64;
@@ -207,7 +207,7 @@ __device__ void patches(const BLevel& L, double* xs, const double* in, int64_t p
     if (idx >= L.npatch) break;
     const int p = L.sched[idx];
     switch (L.rb) {
-      case 1: dev::patch_apply_one<double, 1>(p, lane, xs, L.p_nloc, L.p_ld, L.p_inv_off, L.p_slot_off, L.p_gidx, L.inv, in, nullptr, L.Y, 0); break;
+      case 1: dev::patch_apply_one<double, 1, 8>(p, lane, xs, L.p_nloc, L.p_ld, L.p_inv_off, L.p_slot_off, L.p_gidx, L.inv, in, nullptr, L.Y, 0); break;
       case 2: dev::patch_apply_one<double, 2>(p, lane, xs, L.p_nloc, L.p_ld, L.p_inv_off, L.p_slot_off, L.p_gidx, L.inv, in, nullptr, L.Y, 0); break;
       default: dev::patch_apply_one<double, 2>(p, lane, xs, L.p_nloc, L.p_ld, L.p_inv_off, L.p_slot_off, L.p_gidx, L.inv, in, nullptr, L.Y, 0); break;
     }
@@ -613,7 +613,7 @@ __host__ __device__ void advance(const BSolve& S, BState& st, double red_val, co
   (void)ctl;
 }
 
-__global__ __launch_bounds__(kBlock, 4) void k_batch(const BSolve* __restrict__ Sv, BState* Stv, Ctl* ctl,
+__global__ __launch_bounds__(kBlock, 1) void k_batch(const BSolve* __restrict__ Sv, BState* Stv, Ctl* ctl,
                                                   int nsolves, Tun tun) {
   __shared__ double xs[kWaves * kNmax];
   __shared__ double red[kBlock];

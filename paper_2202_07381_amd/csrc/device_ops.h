@@ -127,7 +127,7 @@ __device__ inline void vload<float4, float>(const float* p, float* o) {
 // [rb*64*VEC + l*VEC, +VEC) of row block rb.  Non-transposed: y = Ainv x streams
 // column j with one 16-byte load per lane; transposed: y_j = column_j . x with a wave
 // reduction per column.  xs is this wavefront's LDS staging area (>= n values).
-template <typename T, int RB>
+template <typename T, int RB, int UNROLL = 4>
 __device__ __forceinline__ void patch_apply_one(
     int p, int lane, T* xs, const int32_t* __restrict__ p_nloc, const int32_t* __restrict__ p_ld,
     const int64_t* __restrict__ p_inv_off, const int64_t* __restrict__ p_slot_off,
@@ -153,10 +153,10 @@ __device__ __forceinline__ void patch_apply_one(
 #pragma unroll
       for (int v = 0; v < VEC; ++v) acc[b][v] = T(0);
     int j = 0;
-    for (; j + 4 <= n; j += 4) {
-      T a[4][RB][VEC];
+    for (; j + UNROLL <= n; j += UNROLL) {
+      T a[UNROLL][RB][VEC];
 #pragma unroll
-      for (int u = 0; u < 4; ++u)
+      for (int u = 0; u < UNROLL; ++u)
 #pragma unroll
         for (int b = 0; b < RB; ++b) {
           const int r0 = b * 64 * VEC + lane * VEC;
@@ -166,7 +166,7 @@ __device__ __forceinline__ void patch_apply_one(
             for (int v = 0; v < VEC; ++v) a[u][b][v] = T(0);
         }
 #pragma unroll
-      for (int u = 0; u < 4; ++u) {
+      for (int u = 0; u < UNROLL; ++u) {
         const T xj = xs[j + u];
 #pragma unroll
         for (int b = 0; b < RB; ++b)
