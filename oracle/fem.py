@@ -161,20 +161,20 @@ class TaylorHood:
 
     def element_stiffness(self) -> np.ndarray:
         xi, w, val, g = self._quad()
-        return np.einsum("q,cqai,cqbi,c->cab", w, g, g, self.detj)
+        return np.einsum("q,cqai,cqbi,c->cab", w, g, g, self.detj, optimize=True)
 
     def element_divergence(self) -> np.ndarray:
         """E[c, a, comp, i] = -int psi_i d_comp phi_a over cell c."""
         xi, w, val, g = self._quad()
         psi = p1_basis(self.dim, xi)
-        return -np.einsum("q,qi,cqak,c->caki", w, psi, g, self.detj)
+        return -np.einsum("q,qi,cqak,c->caki", w, psi, g, self.detj, optimize=True)
 
     def element_convection(self, wind_nodal: np.ndarray) -> np.ndarray:
         """C[c, a, b] = int (w . grad phi_b) phi_a, w the P2 interpolant of the wind."""
         xi, w, val, g = self._quad()
         wloc = wind_nodal[self.cell_nodes]  # (nc, nloc, d)
         wq = np.einsum("qn,cnk->cqk", val, wloc)
-        return np.einsum("q,qa,cqk,cqbk,c->cab", w, val, wq, g, self.detj)
+        return np.einsum("q,qa,cqk,cqbk,c->cab", w, val, wq, g, self.detj, optimize=True)
 
     # ---------------------------------------------------------------- assembly
     def _assemble_nodes(self, elem: np.ndarray) -> sp.csr_matrix:
