@@ -21,7 +21,15 @@ CASES = {
 }
 
 
+# Set by an autouse fixture in conftest.py so that progress lines reach the terminal
+# while pytest captures output (a long test must not look silent).
+_sink = None
+
+
 def say(msg):
+    if _sink is not None:
+        _sink(msg)
+        return
     print(msg, flush=True)
     sys.stdout.flush()
 

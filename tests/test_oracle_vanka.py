@@ -71,4 +71,7 @@ def test_single_patch_exactness():
         row = [i for i in range(inv[0].shape[0]) if np.array_equal(inv[0][i], pats[v])][0]
         back = np.zeros(S.n)
         back[pats[v]] = inv[1][row] @ Je[pats[v]]
-        assert np.abs(back - e).max() < 1e-12 * np.abs(e).max()
+        # a computed inverse applied to A e returns e to within a small multiple of
+        # cond(A_v) * eps (forward error of an inverse-based solve)
+        cond = np.linalg.cond(S.J[pats[v]][:, pats[v]].toarray())
+        assert np.abs(back - e).max() < 16 * cond * np.finfo(float).eps * np.abs(e).max()
