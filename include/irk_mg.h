@@ -82,7 +82,7 @@ typedef struct irk_tableau {
 } irk_tableau;
 
 /* Solver options.  Defaults (irk_mg_default_opts): 2 pre- and 2 post-sweeps (Sec. 5.1),
- * omega = 0.5, partition-of-unity weighting, FP64. */
+ * omega = 0.5, partition-of-unity weighting, FP64, automatic patch form. */
 typedef struct irk_mg_opts {
   int pre, post;     /* Vanka sweeps before / after the coarse correction        */
   double omega;      /* damping of the additive sweep (Sec. 4.2)                 */
@@ -90,6 +90,15 @@ typedef struct irk_mg_opts {
                         divided by the number of patches containing it          */
   int precision;     /* 0: FP64 V-cycle; 1: FP32 patch factors and FP32 V-cycle
                         (coarse solve, FGMRES and outer residual stay FP64)      */
+  int patch_form;    /* how the exact inverse of each stage-coupled patch matrix
+                        I (x) M_v + dt A (x) S_v is stored (the operator applied
+                        is the same in every form):
+                        0: dense (r n_s)^2 inverse;
+                        1: factored through A = W T W^{-1} (irk_stage_basis):
+                           r n_s^2 stored values, IRK_EINVAL from setup if A has
+                           no well-conditioned real block diagonalisation;
+                        2: automatic: 1 when r >= 2 and the decomposition
+                           exists, else 0                                       */
 } irk_mg_opts;
 
 /* Per-solve report.  history (host, may be NULL) receives up to history_cap residual
@@ -133,6 +142,18 @@ irk_status irk_mesh_p2_nodes(const irk_mesh_level* level, int64_t* nnodes, doubl
 irk_status irk_mg_setup(const irk_mesh_level* levels, int nlevels, const irk_tableau* tab,
                         double dt, double nu, const double* wind, const irk_mg_opts* opt,
                         void* stream, irk_mg** out);
+
+/* Patch form a handle uses (0 dense, 1 factored; see irk_mg_opts), or -1 for NULL. */
+int irk_mg_patch_form(const irk_mg* h);
+
+/* Real block diagonalisation of a Butcher matrix, A = W T W^{-1}, as used by the
+ * factored patch form: T is block diagonal with 1x1 blocks (real eigenvalues,
+ * ascending) followed by 2x2 blocks [[a, b], [-b, a]] (pairs a +- ib, b > 0, ascending
+ * a); the columns of W are the real eigenvectors and the real and imaginary parts of
+ * the pairs' eigenvectors.  A, W, Winv, T: host, r x r row-major (outputs may be NULL).
+ * Errors: IRK_EINVAL for r outside 1..4, null A, repeated or defective eigenvalues,
+ * cond(W) > 1e6 or a failed reconstruction check. */
+irk_status irk_stage_basis(int r, const double* A, double* W, double* Winv, double* T);
 
 /* Release the handle and all its device memory (NULL is ignored). */
 void irk_mg_destroy(irk_mg* h);

@@ -49,7 +49,9 @@ constexpr int PH_LOAD = 0, PH_R0 = 1, PH_N0 = 2, PH_RES = 3, PH_NRM = 4, PH_V0 =
 
 struct BLevel {
   int64_t nfree, nv, N, offV, npatch;
-  int rb;  // row blocks of the patch apply (ceil(max patch / 128))
+  int rb;     // row blocks of the patch apply (ceil(max stored column / 128))
+  int pform;  // patch form: 0 dense inverse, 1 factored through the stage eigenbasis
+  irk::StageBasis<double> sb;
   const int32_t *s_ptr, *s_col, *b_ptr, *b_col, *bt_ptr, *bt_col;
   const double *sM, *sL, *b_val, *bt_val, *W;
   const int32_t *pu_ptr, *pu_col, *put_ptr, *put_col, *pp_ptr, *pp_col, *ppt_ptr, *ppt_col;
@@ -200,12 +202,21 @@ __device__ void spmv(int D, int R, int64_t nu, int64_t np, int64_t out_offV, int
 #undef IRK_B_SP
 }
 
-__device__ void patches(const BLevel& L, double* xs, const double* in, int64_t p0, int ppw) {
+__device__ void patches(const BLevel& L, double* xs, double* xt, const double* in, int64_t p0, int ppw) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   for (int q = 0; q < ppw; ++q) {
     const int64_t idx = p0 + (int64_t)wave * ppw + q;
     if (idx >= L.npatch) break;
     const int p = L.sched[idx];
+    if (L.pform == 1) {
+      if (L.rb == 1)
+        dev::patch_apply_eig_one<double, 1, 8>(p, lane, xs, xt, L.sb, L.p_nloc, L.p_ld, L.p_inv_off, L.p_slot_off,
+                                               L.p_gidx, L.inv, in, nullptr, L.Y, 0);
+      else
+        dev::patch_apply_eig_one<double, 2, 4>(p, lane, xs, xt, L.sb, L.p_nloc, L.p_ld, L.p_inv_off, L.p_slot_off,
+                                               L.p_gidx, L.inv, in, nullptr, L.Y, 0);
+      continue;
+    }
     switch (L.rb) {
       case 1: dev::patch_apply_one<double, 1, 8>(p, lane, xs, L.p_nloc, L.p_ld, L.p_inv_off, L.p_slot_off, L.p_gidx, L.inv, in, nullptr, L.Y, 0); break;
       case 2: dev::patch_apply_one<double, 2>(p, lane, xs, L.p_nloc, L.p_ld, L.p_inv_off, L.p_slot_off, L.p_gidx, L.inv, in, nullptr, L.Y, 0); break;
@@ -240,7 +251,7 @@ __device__ double block_sum(double v, double* red) {
 
 // ------------------------------------------------------------------ one work item
 __device__ void exec_item(const BSolve& S, const BCur& st, const BState* gst, int item, const Tun& t, double* xs,
-                          double* red) {
+                          double* xt, double* red) {
   const int D = S.dim, R = S.r, top = S.nlevels - 1;
   const BLevel& Fl = S.lv[top];
   const int64_t N = Fl.N;
@@ -288,7 +299,8 @@ __device__ void exec_item(const BSolve& S, const BCur& st, const BState* gst, in
     case PH_SM_PATCH: {
       const BLevel& L = S.lv[st.level];
       const int wave = tid >> 6;
-      patches(L, xs + wave * kNmax, st.first ? L.b : L.res, (int64_t)item * kWaves * t.ppw, t.ppw);
+      patches(L, xs + wave * kNmax, xt + wave * kNmax, st.first ? L.b : L.res, (int64_t)item * kWaves * t.ppw,
+              t.ppw);
       break;
     }
     case PH_SM_GATHER: {
@@ -616,6 +628,7 @@ __host__ __device__ void advance(const BSolve& S, BState& st, double red_val, co
 __global__ __launch_bounds__(kBlock, 1) void k_batch(const BSolve* __restrict__ Sv, BState* Stv, Ctl* ctl,
                                                   int nsolves, Tun tun) {
   __shared__ double xs[kWaves * kNmax];
+  __shared__ double xt[kWaves * kNmax];
   __shared__ double red[kBlock];
   __shared__ int s_item, s_ok, s_last, s_exit, s_solve, s_epoch, s_viol;
   __shared__ BCur s_st;  // snapshot of the solve's state for the item being executed
@@ -701,7 +714,7 @@ __global__ __launch_bounds__(kBlock, 1) void k_batch(const BSolve* __restrict__ 
       if (tid == 0) __hip_atomic_store(&ctl->abort, 2, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
       break;
     }
-    exec_item(S, s_st, st, s_item, tun, xs, red);
+    exec_item(S, s_st, st, s_item, tun, xs, xt, red);
     __builtin_amdgcn_s_waitcnt(0);  // this wave's stores have reached L2
     __syncthreads();
     if (tid == 0) {
@@ -841,7 +854,9 @@ BLevel level_view(const DevLevel& L) {
   v.N = L.N;
   v.offV = L.offV;
   v.npatch = L.npatch;
-  v.rb = L.max_nloc <= 128 ? 1 : 2;
+  v.pform = L.pform;
+  v.rb = L.pform == 1 ? (L.max_ld <= 128 ? 1 : 2) : (L.max_nloc <= 128 ? 1 : 2);
+  v.sb = L.sb64;
   v.s_ptr = L.s_ptr; v.s_col = L.s_col; v.b_ptr = L.b_ptr; v.b_col = L.b_col; v.bt_ptr = L.bt_ptr; v.bt_col = L.bt_col;
   v.sM = L.d64.s_M; v.sL = L.d64.s_L; v.b_val = L.d64.b_val; v.bt_val = L.d64.bt_val; v.W = L.d64.W;
   v.pu_ptr = L.pu_ptr; v.pu_col = L.pu_col; v.put_ptr = L.put_ptr; v.put_col = L.put_col;
@@ -968,7 +983,8 @@ irk_status irk_batch_create(irk_mg* const* hs, int n, const irk_batch_opts* opts
     if (hs[q]->dim != 2) return bfail(IRK_EINVAL, "the batched solver runs 2D handles only");
     if (hs[q]->nlevels > kMaxLevels) return bfail(IRK_EINVAL, "too many levels for the batched solver");
     for (int l = 1; l < hs[q]->nlevels; ++l)
-      if (hs[q]->dev[l].max_nloc > kNmax) return bfail(IRK_EINVAL, "patch too large for the batched solver");
+      if (hs[q]->dev[l].max_nloc > kNmax || hs[q]->dev[l].max_ld > 2 * 128)
+        return bfail(IRK_EINVAL, "patch too large for the batched solver");
     for (int p = 0; p < q; ++p)
       if (hs[p] == hs[q]) return bfail(IRK_EINVAL, "a handle appears twice in the batch");
   }

@@ -217,6 +217,204 @@ __device__ __forceinline__ void patch_apply_one(
   __builtin_amdgcn_wave_barrier();
 }
 
+// Factored patch inverse (stage eigenbasis).  The stage-coupled patch matrix is
+// I (x) M_v + dt A (x) S_v (Sec. 3 restricted to the patch of Sec. 4.2); with
+// A = W T W^{-1} its inverse is (W (x) I) blockdiag_k(B_k^{-1}) (W^{-1} (x) I), where
+// B_k = I (x) M_v + dt T_k (x) S_v.  Storage per patch: n_s columns of ld values; in a
+// column the blocks follow each other, a real block as n_s values, a pair as n_s
+// complex values (re, im).  For a pair, B_k^{-1} = [[P, -Q], [Q, P]] and the stored
+// complex entry is P + iQ, so applying it is the complex product (P + iQ)(x1 + i x2).
+//
+// One wavefront per patch: gather x (LDS xs), transform to the eigenbasis (LDS xt),
+// sweep the n_s columns (lane l owns VEC consecutive stored rows of every column, as in
+// the dense form, and its chunk lies in one block), transform back and store the n
+// local corrections.  Transposed (adjoint): x -> (W^T (x) I) x, B_k^{-T}, which for a
+// pair is the conjugate transpose of P + iQ, and -> (W^{-T} (x) I); one wave reduction
+// per column and block.
+template <typename T>
+__device__ __forceinline__ int eig_chunk_block(const irk::StageBasis<T>& sb, int ns, int row0, int* off) {
+  constexpr int VEC = Vec16<T>::n;
+  int base = 0;
+  for (int b = 0; b < sb.nblk; ++b) {
+    const int rows = irk::eig_block_rows(sb.type[b], ns, VEC);
+    if (row0 < base + rows) {
+      *off = row0 - base;
+      return b;
+    }
+    base += rows;
+  }
+  return -1;
+}
+
+template <typename T, int RB, int UNROLL = 8>
+__device__ __forceinline__ void patch_apply_eig_one(
+    int p, int lane, T* xs, T* xt, const irk::StageBasis<T>& sb, const int32_t* __restrict__ p_nloc,
+    const int32_t* __restrict__ p_ld, const int64_t* __restrict__ p_inv_off,
+    const int64_t* __restrict__ p_slot_off, const int32_t* __restrict__ gidx, const T* __restrict__ inv,
+    const T* __restrict__ res, const T* __restrict__ W, T* __restrict__ Y, int transpose) {
+  using VT = typename Vec16<T>::type;
+  constexpr int VEC = Vec16<T>::n;
+  const int n = p_nloc[p];
+  const int r = sb.r;
+  const int ns = n / r;
+  const int lc = p_ld[p];
+  const int64_t so = p_slot_off[p];
+  const T* __restrict__ Ap = inv + p_inv_off[p];
+  for (int i = lane; i < n; i += 64) {
+    const int32_t g = gidx[so + i];
+    xs[i] = W ? res[g] * W[g] : res[g];
+  }
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  // to the eigenbasis: xt[k ns + q] = sum_s Tin(k, s) xs[s ns + q]
+  for (int e = lane; e < n; e += 64) {
+    const int k = e / ns, q = e - k * ns;
+    T acc = T(0);
+    for (int s = 0; s < r; ++s) acc += (transpose ? sb.W[s * r + k] : sb.Winv[k * r + s]) * xs[s * ns + q];
+    xt[e] = acc;
+  }
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  // this lane's chunks: block, offset inside the block, inputs (u, v) per column
+  int blk[RB], off[RB], iu[RB], iv[RB];
+#pragma unroll
+  for (int b = 0; b < RB; ++b) {
+    const int row0 = b * 64 * VEC + lane * VEC;
+    off[b] = 0;
+    blk[b] = row0 < lc ? eig_chunk_block(sb, ns, row0, &off[b]) : -1;
+    iu[b] = blk[b] >= 0 ? sb.st0[blk[b]] * ns : 0;
+    iv[b] = (blk[b] >= 0 && sb.type[blk[b]] == 2) ? iu[b] + ns : -1;
+  }
+  if (!transpose) {
+    T acc[RB][VEC];
+#pragma unroll
+    for (int b = 0; b < RB; ++b)
+#pragma unroll
+      for (int v = 0; v < VEC; ++v) acc[b][v] = T(0);
+    int j = 0;
+    for (; j + UNROLL <= ns; j += UNROLL) {
+      T a[UNROLL][RB][VEC];
+#pragma unroll
+      for (int u = 0; u < UNROLL; ++u)
+#pragma unroll
+        for (int b = 0; b < RB; ++b) {
+          if (blk[b] >= 0) vload<VT, T>(Ap + (int64_t)(j + u) * lc + b * 64 * VEC + lane * VEC, a[u][b]);
+          else
+#pragma unroll
+            for (int v = 0; v < VEC; ++v) a[u][b][v] = T(0);
+        }
+#pragma unroll
+      for (int u = 0; u < UNROLL; ++u)
+#pragma unroll
+        for (int b = 0; b < RB; ++b) {
+          const T xu = xt[iu[b] + j + u];
+          const T xv = iv[b] >= 0 ? xt[iv[b] + j + u] : T(0);
+#pragma unroll
+          for (int m = 0; m < VEC / 2; ++m) {
+            acc[b][2 * m] += a[u][b][2 * m] * xu - a[u][b][2 * m + 1] * xv;
+            acc[b][2 * m + 1] += a[u][b][2 * m + 1] * xu + a[u][b][2 * m] * xv;
+          }
+        }
+    }
+    for (; j < ns; ++j)
+#pragma unroll
+      for (int b = 0; b < RB; ++b) {
+        if (blk[b] < 0) continue;
+        T a[VEC];
+        vload<VT, T>(Ap + (int64_t)j * lc + b * 64 * VEC + lane * VEC, a);
+        const T xu = xt[iu[b] + j];
+        const T xv = iv[b] >= 0 ? xt[iv[b] + j] : T(0);
+#pragma unroll
+        for (int m = 0; m < VEC / 2; ++m) {
+          acc[b][2 * m] += a[2 * m] * xu - a[2 * m + 1] * xv;
+          acc[b][2 * m + 1] += a[2 * m + 1] * xu + a[2 * m] * xv;
+        }
+      }
+    // block results into xs (xs is no longer read): real rows off..off+VEC-1, or complex
+    // rows off/2 .. off/2+VEC/2-1 with re -> stage st0, im -> stage st0+1
+#pragma unroll
+    for (int b = 0; b < RB; ++b) {
+      if (blk[b] < 0) continue;
+      if (iv[b] < 0) {
+#pragma unroll
+        for (int v = 0; v < VEC; ++v)
+          if (off[b] + v < ns) xs[iu[b] + off[b] + v] = acc[b][v];
+      } else {
+#pragma unroll
+        for (int m = 0; m < VEC / 2; ++m) {
+          const int c = off[b] / 2 + m;
+          if (c < ns) {
+            xs[iu[b] + c] = acc[b][2 * m];
+            xs[iv[b] + c] = acc[b][2 * m + 1];
+          }
+        }
+      }
+    }
+  } else {
+    for (int j = 0; j < ns; ++j) {
+      T pr[kMaxStages], pi[kMaxStages];
+#pragma unroll
+      for (int q = 0; q < kMaxStages; ++q) pr[q] = pi[q] = T(0);
+#pragma unroll
+      for (int b = 0; b < RB; ++b) {
+        if (blk[b] < 0) continue;
+        T a[VEC];
+        vload<VT, T>(Ap + (int64_t)j * lc + b * 64 * VEC + lane * VEC, a);
+        T sr = T(0), si = T(0);
+        if (iv[b] < 0) {
+#pragma unroll
+          for (int v = 0; v < VEC; ++v)
+            if (off[b] + v < ns) sr += a[v] * xt[iu[b] + off[b] + v];
+        } else {
+#pragma unroll
+          for (int m = 0; m < VEC / 2; ++m) {
+            const int c = off[b] / 2 + m;
+            if (c < ns) {
+              const T zr = xt[iu[b] + c], zi = xt[iv[b] + c];
+              sr += a[2 * m] * zr + a[2 * m + 1] * zi;
+              si += a[2 * m] * zi - a[2 * m + 1] * zr;
+            }
+          }
+        }
+#pragma unroll
+        for (int q = 0; q < kMaxStages; ++q)
+          if (blk[b] == q) {
+            pr[q] += sr;
+            pi[q] += si;
+          }
+      }
+#pragma unroll
+      for (int q = 0; q < kMaxStages; ++q) {
+        if (q >= sb.nblk) break;
+        T vr = pr[q], vi = pi[q];
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) {
+          vr += __shfl_xor(vr, o, 64);
+          vi += __shfl_xor(vi, o, 64);
+        }
+        if (lane == 0) {
+          xs[sb.st0[q] * ns + j] = vr;
+          if (sb.type[q] == 2) xs[(sb.st0[q] + 1) * ns + j] = vi;
+        }
+      }
+    }
+  }
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  // back to the stages: forward W, transposed W^{-T}
+  for (int e = lane; e < n; e += 64) {
+    const int s = e / ns, q = e - s * ns;
+    T acc = T(0);
+    for (int k = 0; k < r; ++k) acc += (transpose ? sb.Winv[k * r + s] : sb.W[s * r + k]) * xs[k * ns + q];
+    Y[so + e] = acc;
+  }
+  // xs and xt are reused by this wavefront's next patch
+  __builtin_amdgcn_wave_barrier();
+}
+
 // Owner gather of one DOF.  mode 0: x = omega*W*s   1: x += omega*W*s
 //                           2: x = omega*s     3: x += omega*s
 template <typename T>

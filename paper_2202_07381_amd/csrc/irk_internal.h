@@ -73,6 +73,44 @@ std::string build_transfer(const HostLevel& coarse, HostLevel& fine, const int64
 bool coarse_inverse(const HostLevel& L, int r, const double* A, double dt,
                     std::vector<double>& inv);
 
+// ------------------------------------------------------------- stage eigenbasis
+// Real block diagonalisation A = W T W^{-1} of the Butcher matrix.  T is block diagonal
+// with 1x1 blocks (real eigenvalues) and 2x2 blocks [[a, b], [-b, a]] (pairs a +- ib,
+// b > 0).  Since every stage-coupled patch matrix has the Kronecker form
+// I (x) M_v + dt A (x) S_v (the stage operator of Sec. 3 restricted to one patch), its
+// inverse is (W (x) I) blockdiag_k (I (x) M_v + dt T_k (x) S_v)^{-1} (W^{-1} (x) I):
+// the same operator, stored as r blocks of n_s^2 values instead of (r n_s)^2.
+struct StageEig {
+  int r = 0, nblk = 0;
+  int type[kMaxStages] = {0};  // stages spanned by the block: 1 (real) or 2 (pair)
+  int st0[kMaxStages] = {0};   // first transformed stage of the block
+  double Tb[kMaxStages][4] = {{0}};  // the block of T, row-major type x type
+  double W[kMaxStages * kMaxStages] = {0};
+  double Winv[kMaxStages * kMaxStages] = {0};  // row-major r x r
+  double cond = 0;   // ||W||_inf ||W^{-1}||_inf
+  double recon = 0;  // max |W T W^{-1} - A|
+};
+// Returns false (with the reason in *why) when A has no well-conditioned real block
+// diagonalisation (repeated or defective eigenvalues, cond(W) > 1e6).
+bool stage_eigenbasis(const double* A, int r, StageEig& out, std::string* why);
+
+// Stored values per column of one eigen-block of a factored patch inverse: a real block
+// keeps its n_s entries, a pair keeps n_s complex entries (re, im interleaved); both
+// padded to whole 16-byte vectors of `vec` elements.
+__host__ __device__ inline int eig_block_rows(int type, int ns, int vec) {
+  return type == 1 ? (ns + vec - 1) / vec * vec : 2 * ((ns + vec / 2 - 1) / (vec / 2) * (vec / 2));
+}
+
+// The basis as the patch kernels read it (by value, in the working precision).
+template <typename T>
+struct StageBasis {
+  int r = 0, nblk = 0;
+  int type[kMaxStages] = {0};
+  int st0[kMaxStages] = {0};
+  T W[kMaxStages * kMaxStages] = {0};
+  T Winv[kMaxStages * kMaxStages] = {0};
+};
+
 // ---------------------------------------------------------------- device level data
 template <typename T>
 struct DevOps {
@@ -118,6 +156,13 @@ struct DevLevel {
   int64_t inv_elems = 0, slots = 0;
   int max_nloc = 0;
   int32_t* sched = nullptr;  // patch launch order (largest first)
+  // patch form: 0 = dense inverse of the stage-coupled patch matrix (column-major,
+  // n x ld); 1 = factored through the stage eigenbasis: n_s columns of ld = sum over
+  // blocks of eig_block_rows values each (p_ld holds that column length)
+  int pform = 0;
+  int max_ld = 0;
+  StageBasis<double> sb64;
+  StageBasis<float> sb32;
 
   // algorithmic bytes per launch of patch apply, residual and gather update
   double alg_bytes[3] = {0, 0, 0};
@@ -130,6 +175,8 @@ struct Handle {
   int dim = 0, r = 0, nlevels = 0, precision = 0;
   double dt = 0, nu = 0, omega = 0.5;
   int pre = 2, post = 2, weighting = 1;
+  int patch_form = 0;  // form in use: 0 dense, 1 stage eigenbasis
+  StageEig eig;
   double A[kMaxStages * kMaxStages] = {0}, At[kMaxStages * kMaxStages] = {0};
   double b[kMaxStages] = {0}, c[kMaxStages] = {0};
   std::vector<HostLevel> host;
@@ -177,9 +224,20 @@ hipError_t restrict_(const DevLevel& fine, const DevLevel& coarse, const DevOps<
 template <typename T>
 hipError_t prolong_add(const DevLevel& fine, const DevLevel& coarse, const DevOps<T>& fops,
                        const T* xc, T* xf, hipStream_t s);
+// Factorise (invert) patches [p0, p1) with an R-stage coefficient matrix coef
+// (I (x) M_v + dt coef (x) S_v; R = r and coef = A for the dense form, R = 1 or 2 and
+// coef = a block of T for one eigen-block); inverse of patch p written column-major
+// (n x ld[p]) at out + off[p] - off0.  nmax: the largest n in the range.
 template <typename T>
-hipError_t patch_factor(const DevLevel& L, const DevOps<T>& ops, const double* A, double dt,
-                        int* d_fail, hipStream_t s);
+hipError_t patch_factor_range(const DevLevel& L, const DevOps<T>& ops, int R, const double* coef,
+                              double dt, const int32_t* ld, const int64_t* off, T* out, int64_t p0,
+                              int64_t p1, int64_t off0, int nmax, int* d_fail, hipStream_t s);
+// Copy eigen-block b of patches [p0, p1) from dense inverses (layout of
+// patch_factor_range with tmp_ld / tmp_off / off0) into the factored layout of L.inv.
+template <typename T>
+hipError_t eig_extract(const DevLevel& L, const StageBasis<T>& sb, int b, const int32_t* tmp_ld,
+                       const int64_t* tmp_off, int64_t off0, const T* tmp, int64_t p0, int64_t p1,
+                       hipStream_t s);
 hipError_t coarse_gemv(const double* inv, int64_t N, const double* b, double* x,
                        const int64_t* pins, int npins, double* part, hipStream_t s);
 int coarse_split();  // number of partial sums per row used by coarse_gemv

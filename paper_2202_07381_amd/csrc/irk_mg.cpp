@@ -397,6 +397,7 @@ void irk_mg_default_opts(irk_mg_opts* o) {
   o->omega = 0.5;
   o->weighting = 1;
   o->precision = 0;
+  o->patch_form = 2;
 }
 
 irk_status irk_tableau_builtin(int family, int r, double* A, double* b, double* c) {
@@ -514,6 +515,90 @@ void irk_mg_destroy(irk_mg* h) {
   delete h;
 }
 
+}  // extern "C"
+
+template <typename T>
+const irk::StageBasis<T>& basis(const DevLevel& D);
+template <>
+const irk::StageBasis<double>& basis<double>(const DevLevel& D) { return D.sb64; }
+template <>
+const irk::StageBasis<float>& basis<float>(const DevLevel& D) { return D.sb32; }
+
+// Factorise every patch of level l.  Dense form: one launch over all patches.  Factored
+// form: for each eigen-block, the (1- or 2-stage) block matrix of a chunk of patches is
+// inverted into a temporary buffer by the same kernels and copied into the factored
+// layout; chunks keep the temporary under 2 GiB.
+template <typename T>
+static irk_status factor_level(irk_mg* h, int l, const DevOps<T>& ops, double dt, int* dfail, hipStream_t s) {
+  DevLevel& D = h->dev[l];
+  const HostLevel& H = h->host[l];
+  const int r = h->r, dim = h->dim;
+  if (D.pform == 0) {
+    HIPCHK(k::patch_factor_range<T>(D, ops, r, h->A, dt, D.p_ld, D.p_inv_off, reinterpret_cast<T*>(D.inv), 0,
+                                    D.npatch, 0, D.max_nloc, dfail, s));
+    return IRK_OK;
+  }
+  const irk::StageEig& E = h->eig;
+  const int VEC = 16 / (int)sizeof(T);
+  const int64_t np = D.npatch;
+  int max_ns = 0;
+  for (int64_t p = 0; p < np; ++p) max_ns = std::max(max_ns, dim * (H.pn_ptr[p + 1] - H.pn_ptr[p]) + 1);
+  const int64_t budget = ((int64_t)2 << 30) / (int64_t)sizeof(T);
+  for (int b = 0; b < E.nblk; ++b) {
+    const int m = E.type[b];
+    std::vector<int32_t> tld(np);
+    std::vector<int64_t> toff(np + 1, 0);
+    for (int64_t p = 0; p < np; ++p) {
+      const int n = m * (dim * (H.pn_ptr[p + 1] - H.pn_ptr[p]) + 1);
+      tld[p] = (n + VEC - 1) / VEC * VEC;
+      toff[p + 1] = toff[p] + (int64_t)tld[p] * n;
+    }
+    int32_t* d_tld = nullptr;
+    int64_t* d_toff = nullptr;
+    T* tmp = nullptr;
+    int64_t chunk_max = 0;
+    {
+      int64_t p0 = 0;
+      while (p0 < np) {
+        int64_t p1 = p0 + 1;
+        while (p1 < np && toff[p1 + 1] - toff[p0] <= budget) ++p1;
+        chunk_max = std::max(chunk_max, toff[p1] - toff[p0]);
+        p0 = p1;
+      }
+    }
+    auto release = [&]() {
+      hipStreamSynchronize(s);
+      if (d_tld) hipFree(d_tld);
+      if (d_toff) hipFree(d_toff);
+      if (tmp) hipFree(tmp);
+    };
+    if (hipMalloc(&d_tld, np * sizeof(int32_t)) != hipSuccess ||
+        hipMalloc(&d_toff, (np + 1) * sizeof(int64_t)) != hipSuccess ||
+        hipMalloc(&tmp, (size_t)chunk_max * sizeof(T)) != hipSuccess) {
+      release();
+      return fail(IRK_ENOMEM, "device allocation of the factorisation workspace failed");
+    }
+    hipError_t e = hipMemcpyAsync(d_tld, tld.data(), np * sizeof(int32_t), hipMemcpyHostToDevice, s);
+    if (e == hipSuccess)
+      e = hipMemcpyAsync(d_toff, toff.data(), (np + 1) * sizeof(int64_t), hipMemcpyHostToDevice, s);
+    double coef[4];
+    for (int i = 0; i < m * m; ++i) coef[i] = E.Tb[b][i];
+    int64_t p0 = 0;
+    while (e == hipSuccess && p0 < np) {
+      int64_t p1 = p0 + 1;
+      while (p1 < np && toff[p1 + 1] - toff[p0] <= budget) ++p1;
+      e = k::patch_factor_range<T>(D, ops, m, coef, dt, d_tld, d_toff, tmp, p0, p1, toff[p0], m * max_ns, dfail, s);
+      if (e == hipSuccess) e = k::eig_extract<T>(D, basis<T>(D), b, d_tld, d_toff, toff[p0], tmp, p0, p1, s);
+      p0 = p1;
+    }
+    release();
+    if (e != hipSuccess) return fail(IRK_EHIP, std::string("patch factorisation: ") + hipGetErrorString(e));
+  }
+  return IRK_OK;
+}
+
+extern "C" {
+
 static irk_status setup_impl(const irk_mesh_level* lv, int nlevels, const irk_tableau* tab, double dt,
                              double nu, const double* wind, const irk_mg_opts* opt, hipStream_t s,
                              irk_mg* h) {
@@ -539,6 +624,14 @@ static irk_status setup_impl(const irk_mesh_level* lv, int nlevels, const irk_ta
       h->A[i * r + j] = tab->A[i * r + j];
       h->At[i * r + j] = tab->A[j * r + i];
     }
+  }
+  {
+    std::string why;
+    irk::StageEig eig;
+    const bool ok = o.patch_form != 0 && irk::stage_eigenbasis(h->A, r, eig, &why);
+    if (o.patch_form == 1 && !ok) return fail(IRK_EINVAL, "factored patch form unavailable: " + why);
+    h->patch_form = ok && (o.patch_form == 1 || r >= 2) ? 1 : 0;
+    if (h->patch_form) h->eig = eig;
   }
   // ---- host: topology, transfers, assembly, patches
   h->host.resize(nlevels);
@@ -617,18 +710,29 @@ static irk_status setup_impl(const irk_mesh_level* lv, int nlevels, const irk_ta
       std::vector<int32_t> nloc(np), ld(np), nnv(np), gidx, gptr(D.N + 1, 0), gslot;
       std::vector<int64_t> inv_off(np), slot_off(np);
       int64_t io = 0, so = 0;
-      int maxn = 0;
+      int maxn = 0, maxld = 0;
+      D.pform = h->patch_form;
       for (int64_t p = 0; p < np; ++p) {
         const int nn = H.pn_ptr[p + 1] - H.pn_ptr[p];
-        const int n = r * (dim * nn + 1);
+        const int ns = dim * nn + 1;
+        const int n = r * ns;
         nnv[p] = nn;
         nloc[p] = n;
-        ld[p] = (n + VEC - 1) / VEC * VEC;
         inv_off[p] = io;
         slot_off[p] = so;
-        io += (int64_t)ld[p] * n;
+        if (D.pform == 1) {
+          // factored: ns columns, each the concatenation of the eigen-blocks' rows
+          int lc = 0;
+          for (int b = 0; b < h->eig.nblk; ++b) lc += irk::eig_block_rows(h->eig.type[b], ns, VEC);
+          ld[p] = lc;
+          io += (int64_t)lc * ns;
+        } else {
+          ld[p] = (n + VEC - 1) / VEC * VEC;
+          io += (int64_t)ld[p] * n;
+        }
         so += n;
         maxn = std::max(maxn, n);
+        maxld = std::max(maxld, ld[p]);
         for (int st = 0; st < r; ++st) {
           for (int c = 0; c < dim; ++c)
             for (int a = 0; a < nn; ++a)
@@ -639,6 +743,32 @@ static irk_status setup_impl(const irk_mesh_level* lv, int nlevels, const irk_ta
       D.inv_elems = io;
       D.slots = so;
       D.max_nloc = maxn;
+      D.max_ld = maxld;
+      if (D.pform == 1) {
+        const irk::StageEig& E = h->eig;
+        for (auto* sbp : {&D.sb64}) {
+          sbp->r = r;
+          sbp->nblk = E.nblk;
+          for (int b = 0; b < E.nblk; ++b) {
+            sbp->type[b] = E.type[b];
+            sbp->st0[b] = E.st0[b];
+          }
+          for (int i = 0; i < r * r; ++i) {
+            sbp->W[i] = E.W[i];
+            sbp->Winv[i] = E.Winv[i];
+          }
+        }
+        D.sb32.r = r;
+        D.sb32.nblk = E.nblk;
+        for (int b = 0; b < E.nblk; ++b) {
+          D.sb32.type[b] = E.type[b];
+          D.sb32.st0[b] = E.st0[b];
+        }
+        for (int i = 0; i < r * r; ++i) {
+          D.sb32.W[i] = (float)E.W[i];
+          D.sb32.Winv[i] = (float)E.Winv[i];
+        }
+      }
       if (so > INT32_MAX || D.N > INT32_MAX) return fail(IRK_EINVAL, "problem too large for 32-bit patch indices");
       for (int32_t g : gidx) gptr[g + 1]++;
       for (int64_t g = 0; g < D.N; ++g) gptr[g + 1] += gptr[g];
@@ -672,9 +802,10 @@ static irk_status setup_impl(const irk_mesh_level* lv, int nlevels, const irk_ta
       double sum_n = 0, sum_n2 = 0;
       if (l >= 1)
         for (int64_t p = 0; p < H.nv; ++p) {
-          const double n = r * (dim * (double)(H.pn_ptr[p + 1] - H.pn_ptr[p]) + 1);
-          sum_n += n;
-          sum_n2 += n * n;
+          const double ns = dim * (double)(H.pn_ptr[p + 1] - H.pn_ptr[p]) + 1;
+          sum_n += r * ns;
+          // stored values read per application: (r ns)^2 dense, r ns^2 factored
+          sum_n2 += h->patch_form == 1 ? r * ns * ns : r * r * ns * ns;
         }
       D.alg_bytes[0] = es * (sum_n2 + (double)D.N + sum_n);
       D.alg_bytes[1] = (double)H.s_col.size() * (4 + 2 * es) +
@@ -707,8 +838,8 @@ static irk_status setup_impl(const irk_mesh_level* lv, int nlevels, const irk_ta
     if (D.max_nloc > 1024)
       return fail(IRK_EINVAL, "patch of " + std::to_string(D.max_nloc) +
                                   " unknowns exceeds the factorisation limit of 1024");
-    if (h->precision == 0) HIPCHK(k::patch_factor<double>(D, D.d64, h->A, dt, dfail, s));
-    else HIPCHK(k::patch_factor<float>(D, D.d32, h->A, dt, dfail, s));
+    if (h->precision == 0) CHK(factor_level<double>(h, l, D.d64, dt, dfail, s));
+    else CHK(factor_level<float>(h, l, D.d32, dt, dfail, s));
   }
   int hfail = 0;
   HIPCHK(hipMemcpyAsync(&hfail, dfail, sizeof(int), hipMemcpyDeviceToHost, s));
@@ -764,6 +895,7 @@ irk_status irk_mg_setup(const irk_mesh_level* lv, int nlevels, const irk_tableau
     if (!(opt->omega > 0) || !std::isfinite(opt->omega)) return fail(IRK_EINVAL, "omega must be positive");
     if (opt->weighting != 0 && opt->weighting != 1) return fail(IRK_EINVAL, "weighting must be 0 or 1");
     if (opt->precision != 0 && opt->precision != 1) return fail(IRK_EINVAL, "precision must be 0 or 1");
+    if (opt->patch_form < 0 || opt->patch_form > 2) return fail(IRK_EINVAL, "patch_form must be 0, 1 or 2");
   }
   const int dim = lv[0].dim;
   if (dim != 2 && dim != 3) return fail(IRK_EINVAL, "dim must be 2 or 3");
@@ -803,6 +935,24 @@ irk_status irk_mg_setup(const irk_mesh_level* lv, int nlevels, const irk_tableau
   }
   *out = h;
   g_err.clear();
+  return IRK_OK;
+}
+
+int irk_mg_patch_form(const irk_mg* h) { return h ? h->patch_form : -1; }
+
+irk_status irk_stage_basis(int r, const double* A, double* W, double* Winv, double* T) {
+  if (r < 1 || r > irk::kMaxStages || !A) return fail(IRK_EINVAL, "need 1 <= r <= 4 and a non-null A");
+  irk::StageEig E;
+  std::string why;
+  if (!irk::stage_eigenbasis(A, r, E, &why)) return fail(IRK_EINVAL, why);
+  if (W) std::memcpy(W, E.W, sizeof(double) * r * r);
+  if (Winv) std::memcpy(Winv, E.Winv, sizeof(double) * r * r);
+  if (T) {
+    for (int i = 0; i < r * r; ++i) T[i] = 0.0;
+    for (int b = 0; b < E.nblk; ++b)
+      for (int i = 0; i < E.type[b]; ++i)
+        for (int j = 0; j < E.type[b]; ++j) T[(E.st0[b] + i) * r + E.st0[b] + j] = E.Tb[b][i * E.type[b] + j];
+  }
   return IRK_OK;
 }
 

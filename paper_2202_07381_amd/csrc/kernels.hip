@@ -43,6 +43,13 @@ Coef<T> scaled(const double* A, double dt) {
   return c;
 }
 
+template <typename T>
+const StageBasis<T>& basis_of(const DevLevel& L);
+template <>
+const StageBasis<double>& basis_of<double>(const DevLevel& L) { return L.sb64; }
+template <>
+const StageBasis<float>& basis_of<float>(const DevLevel& L) { return L.sb32; }
+
 // ------------------------------------------------------------------------ residual
 template <int D, int R, typename T>
 __global__ __launch_bounds__(kBlock) void k_residual(
@@ -65,9 +72,9 @@ __global__ __launch_bounds__(kBlock) void k_patch_factor(
     const int32_t* __restrict__ pvv, const int32_t* __restrict__ pvp,
     const int32_t* __restrict__ p_ld, const int64_t* __restrict__ p_inv_off,
     const T* __restrict__ sM, const T* __restrict__ sL, const T* __restrict__ b_val,
-    Coef<T> dtA, T* __restrict__ inv, int* __restrict__ fail) {
+    Coef<T> dtA, T* __restrict__ inv, int* __restrict__ fail, int64_t p0, int64_t off0) {
   extern __shared__ unsigned char smem_raw[];
-  const int64_t p = blockIdx.x;
+  const int64_t p = p0 + blockIdx.x;
   if (p >= npatch) return;
   const int nn = pn_ptr[p + 1] - pn_ptr[p];
   const int sb = D * nn + 1;  // per-stage block size
@@ -170,7 +177,7 @@ __global__ __launch_bounds__(kBlock) void k_patch_factor(
     __syncthreads();
   }
   const int ld = p_ld[p];
-  T* out = inv + p_inv_off[p];
+  T* out = inv + (p_inv_off[p] - off0);
   for (int e = tid; e < n * ld; e += blockDim.x) {
     const int j = e / ld, i = e - j * ld;
     out[e] = i < n ? Am[i * n + j] : T(0);
@@ -194,15 +201,15 @@ __global__ __launch_bounds__(kBlock) void k_patch_factor_global(
     const int32_t* __restrict__ pvv, const int32_t* __restrict__ pvp,
     const int32_t* __restrict__ p_ld, const int64_t* __restrict__ p_inv_off,
     const T* __restrict__ sM, const T* __restrict__ sL, const T* __restrict__ b_val,
-    Coef<T> dtA, T* __restrict__ inv, int* __restrict__ fail) {
+    Coef<T> dtA, T* __restrict__ inv, int* __restrict__ fail, int64_t p0, int64_t off0) {
   extern __shared__ unsigned char smem_raw[];
-  const int64_t p = blockIdx.x;
+  const int64_t p = p0 + blockIdx.x;
   if (p >= npatch) return;
   const int nn = pn_ptr[p + 1] - pn_ptr[p];
   const int sb = D * nn + 1;
   const int n = R * sb;
   const int ld = p_ld[p];
-  T* __restrict__ Am = inv + p_inv_off[p];  // column-major: Am[j * ld + i]
+  T* __restrict__ Am = inv + (p_inv_off[p] - off0);  // column-major: Am[j * ld + i]
   T* P = reinterpret_cast<T*>(smem_raw);    // panel, P[c * n + i]
   T* colk = P + (size_t)kGjBw * n;
   T* Ak = colk + n;                          // Ak[c * kGjJt + jj]
@@ -374,6 +381,60 @@ __global__ __launch_bounds__(kWaves * 64) void k_patch_apply(
   if (idx >= npatch) return;  // whole wavefront exits; no workgroup barrier below
   dev::patch_apply_one<T, RB>(sched[idx], lane, xs[wave], p_nloc, p_ld, p_inv_off, p_slot_off, gidx, inv, res,
                               W, Y, transpose);
+}
+
+// Copy eigen-block b of every patch in [p0, p1) from its dense inverse (column-major
+// m n_s x ldt at tmp + tmp_off[p] - off0, m = 1 or 2 stages) into the factored layout:
+// n_s columns of lc = p_ld[p] values, the block's rows starting at its row offset.  A
+// pair keeps the first n_s columns of [[P, -Q], [Q, P]] as complex entries P + iQ.
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_eig_extract(
+    int64_t p0, int64_t p1, int r, int b, irk::StageBasis<T> sb, const int32_t* __restrict__ p_nloc,
+    const int32_t* __restrict__ p_ld, const int64_t* __restrict__ p_inv_off,
+    const int32_t* __restrict__ tmp_ld, const int64_t* __restrict__ tmp_off, int64_t off0,
+    const T* __restrict__ tmp, T* __restrict__ inv) {
+  constexpr int VEC = Vec16<T>::n;
+  const int64_t p = p0 + blockIdx.x;
+  if (p >= p1) return;
+  const int ns = p_nloc[p] / r;
+  const int lc = p_ld[p];
+  int rowoff = 0;
+  for (int q = 0; q < b; ++q) rowoff += irk::eig_block_rows(sb.type[q], ns, VEC);
+  const int rows = irk::eig_block_rows(sb.type[b], ns, VEC);
+  const int ldt = tmp_ld[p];
+  const T* __restrict__ Z = tmp + (tmp_off[p] - off0);
+  T* __restrict__ out = inv + p_inv_off[p] + rowoff;
+  const bool pair = sb.type[b] == 2;
+  for (int e = threadIdx.x; e < ns * rows; e += blockDim.x) {
+    const int j = e / rows, i = e - j * rows;
+    T v = T(0);
+    if (!pair) {
+      if (i < ns) v = Z[(int64_t)j * ldt + i];
+    } else {
+      const int c = i >> 1;
+      if (c < ns) v = Z[(int64_t)j * ldt + ((i & 1) ? ns + c : c)];
+    }
+    out[(int64_t)j * lc + i] = v;
+  }
+}
+
+template <typename T, int RB, int NMAX>
+__global__ __launch_bounds__(kWaves * 64) void k_patch_apply_eig(
+    int64_t npatch, irk::StageBasis<T> sb, const int32_t* __restrict__ sched,
+    const int32_t* __restrict__ p_nloc, const int32_t* __restrict__ p_ld,
+    const int64_t* __restrict__ p_inv_off, const int64_t* __restrict__ p_slot_off,
+    const int32_t* __restrict__ gidx, const T* __restrict__ inv, const T* __restrict__ res,
+    const T* __restrict__ W, T* __restrict__ Y, int transpose) {
+  __shared__ T xs[kWaves][NMAX];
+  __shared__ T xt[kWaves][NMAX];
+  const int lane = threadIdx.x & 63;
+  const int wave = threadIdx.x >> 6;
+  const int64_t idx = (int64_t)blockIdx.x * kWaves + wave;
+  if (idx >= npatch) return;  // whole wavefront exits; no workgroup barrier below
+  // columns in flight per lane: fewer for the wide (3D) patches to bound registers
+  constexpr int UNROLL = RB >= 4 ? 2 : (RB == 2 ? 4 : 8);
+  dev::patch_apply_eig_one<T, RB, UNROLL>(sched[idx], lane, xs[wave], xt[wave], sb, p_nloc, p_ld, p_inv_off,
+                                          p_slot_off, gidx, inv, res, W, Y, transpose);
 }
 
 // ------------------------------------------------------------------ gather update
@@ -765,33 +826,44 @@ hipError_t residual(const DevLevel& L, const DevOps<T>& ops, const double* A, do
 }
 
 template <typename T>
-hipError_t patch_factor(const DevLevel& L, const DevOps<T>& ops, const double* A, double dt,
-                        int* d_fail, hipStream_t s) {
-  const size_t n = (size_t)L.max_nloc;
+hipError_t patch_factor_range(const DevLevel& L, const DevOps<T>& ops, int R, const double* coef, double dt,
+                              const int32_t* ld, const int64_t* off, T* out, int64_t p0, int64_t p1,
+                              int64_t off0, int nmax, int* d_fail, hipStream_t s) {
+  if (p1 <= p0) return hipSuccess;
+  const unsigned g = (unsigned)(p1 - p0);
+  const size_t n = (size_t)nmax;
   const size_t lds = n * n * sizeof(T) + n * sizeof(T) + n * sizeof(int) + 64;
   if (lds > 160 * 1024) {
     if (n > (size_t)kGjRows * kBlock) return hipErrorInvalidConfiguration;
     const size_t glds = (size_t)kGjBw * n * sizeof(T) + n * sizeof(T) + (size_t)kGjBw * kGjJt * sizeof(T) +
                         n * sizeof(int) + 64;
-    IRK_DISPATCH_DR(L.dim, L.r, {
+    IRK_DISPATCH_DR(L.dim, R, {
       auto kern = k_patch_factor_global<DD, RR, T>;
       hipError_t e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)glds);
       if (e != hipSuccess) return e;
-      kern<<<dim3((unsigned)L.npatch), dim3(kBlock), glds, s>>>(L.npatch, L.pn_ptr, L.pvv_ptr, L.pvv, L.pvp, L.p_ld,
-                                                                L.p_inv_off, ops.s_M, ops.s_L, ops.b_val,
-                                                                scaled<T, RR>(A, dt), reinterpret_cast<T*>(L.inv),
-                                                                d_fail);
+      kern<<<dim3(g), dim3(kBlock), glds, s>>>(p1, L.pn_ptr, L.pvv_ptr, L.pvv, L.pvp, ld, off, ops.s_M, ops.s_L,
+                                               ops.b_val, scaled<T, RR>(coef, dt), out, d_fail, p0, off0);
     });
     return hipGetLastError();
   }
-  IRK_DISPATCH_DR(L.dim, L.r, {
+  IRK_DISPATCH_DR(L.dim, R, {
     auto kern = k_patch_factor<DD, RR, T>;
     hipError_t e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
-    kern<<<dim3((unsigned)L.npatch), dim3(kBlock), lds, s>>>(L.npatch, L.pn_ptr,
-                       L.pvv_ptr, L.pvv, L.pvp, L.p_ld, L.p_inv_off, ops.s_M, ops.s_L, ops.b_val,
-                       scaled<T, RR>(A, dt), reinterpret_cast<T*>(L.inv), d_fail);
+    kern<<<dim3(g), dim3(kBlock), lds, s>>>(p1, L.pn_ptr, L.pvv_ptr, L.pvv, L.pvp, ld, off, ops.s_M, ops.s_L,
+                                            ops.b_val, scaled<T, RR>(coef, dt), out, d_fail, p0, off0);
   });
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t eig_extract(const DevLevel& L, const StageBasis<T>& sb, int b, const int32_t* tmp_ld,
+                       const int64_t* tmp_off, int64_t off0, const T* tmp, int64_t p0, int64_t p1,
+                       hipStream_t s) {
+  if (p1 <= p0) return hipSuccess;
+  k_eig_extract<T><<<dim3((unsigned)(p1 - p0)), dim3(kBlock), 0, s>>>(p0, p1, L.r, b, sb, L.p_nloc, L.p_ld,
+                                                                     L.p_inv_off, tmp_ld, tmp_off, off0, tmp,
+                                                                     reinterpret_cast<T*>(L.inv));
   return hipGetLastError();
 }
 
@@ -803,6 +875,23 @@ hipError_t patch_apply(const DevLevel& L, const DevOps<T>& ops, const T* res, T*
   const T* W = transpose ? ops.W : nullptr;
   const T* inv = reinterpret_cast<const T*>(L.inv);
   const int rows_per_block = 64 * VEC;
+  if (L.pform == 1) {
+    const StageBasis<T>& sb = basis_of<T>(L);
+    const int rbe = (L.max_ld + rows_per_block - 1) / rows_per_block;
+#define IRK_PAE(RBV, NM)                                                                            \
+  k_patch_apply_eig<T, RBV, NM><<<dim3(g), dim3(kWaves * 64), 0, s>>>(L.npatch, sb, L.sched, L.p_nloc, \
+                                                                   L.p_ld, L.p_inv_off, L.p_slot_off,  \
+                                                                   L.p_gidx, inv, res, W, Y, transpose)
+    if (L.max_nloc <= 128 && rbe <= 1) IRK_PAE(1, 128);
+    else if (L.max_nloc <= 256 && rbe <= 2) IRK_PAE(2, 256);
+    else if (L.max_nloc <= 512 && rbe <= 2) IRK_PAE(2, 512);
+    else if (L.max_nloc <= 512 && rbe <= 4) IRK_PAE(4, 512);
+    else if (L.max_nloc <= 1024 && rbe <= 4) IRK_PAE(4, 1024);
+    else if (L.max_nloc <= 1024 && rbe <= 8) IRK_PAE(8, 1024);
+    else return hipErrorInvalidValue;
+#undef IRK_PAE
+    return hipGetLastError();
+  }
   const int rb = (L.max_nloc + rows_per_block - 1) / rows_per_block;
 #define IRK_PA(RBV, NM)                                                                        \
   k_patch_apply<T, RBV, NM><<<dim3(g), dim3(kWaves * 64), 0, s>>>(L.npatch,  \
@@ -988,8 +1077,12 @@ hipError_t mass_apply(const DevLevel& L, const double* st, double* out, hipStrea
 #define IRK_INST(T)                                                                              \
   template hipError_t residual<T>(const DevLevel&, const DevOps<T>&, const double*, double,     \
                                   const T*, const T*, T*, hipStream_t);                         \
-  template hipError_t patch_factor<T>(const DevLevel&, const DevOps<T>&, const double*, double, \
-                                      int*, hipStream_t);                                       \
+  template hipError_t patch_factor_range<T>(const DevLevel&, const DevOps<T>&, int, const double*, \
+                                            double, const int32_t*, const int64_t*, T*, int64_t,   \
+                                            int64_t, int64_t, int, int*, hipStream_t);             \
+  template hipError_t eig_extract<T>(const DevLevel&, const StageBasis<T>&, int, const int32_t*,  \
+                                     const int64_t*, int64_t, const T*, int64_t, int64_t,          \
+                                     hipStream_t);                                                 \
   template hipError_t patch_apply<T>(const DevLevel&, const DevOps<T>&, const T*, T*, int,      \
                                      hipStream_t);                                              \
   template hipError_t gather_update<T>(const DevLevel&, const DevOps<T>&, const T*, T*, T, int, \

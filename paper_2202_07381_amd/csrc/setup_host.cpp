@@ -10,6 +10,7 @@
 // grad lam_k, so the reference tensors below depend on nothing but the dimension.
 #include <algorithm>
 #include <array>
+#include <complex>
 #include <cmath>
 #include <cstring>
 #include <map>
@@ -651,4 +652,204 @@ bool coarse_inverse(const HostLevel& L, int r, const double* A, double dt,
   return true;
 }
 
+}  // namespace irk
+
+// ------------------------------------------------------------- stage eigenbasis
+namespace irk {
+namespace {
+using cplx = std::complex<double>;
+
+// Solve B x = y for a small complex matrix (Gaussian elimination, partial pivoting);
+// false on an exactly zero pivot.
+bool csolve(int r, std::vector<cplx> B, std::vector<cplx>& y) {
+  for (int k = 0; k < r; ++k) {
+    int piv = k;
+    for (int i = k + 1; i < r; ++i)
+      if (std::abs(B[i * r + k]) > std::abs(B[piv * r + k])) piv = i;
+    if (std::abs(B[piv * r + k]) == 0.0) return false;
+    if (piv != k) {
+      for (int j = 0; j < r; ++j) std::swap(B[k * r + j], B[piv * r + j]);
+      std::swap(y[k], y[piv]);
+    }
+    for (int i = k + 1; i < r; ++i) {
+      const cplx f = B[i * r + k] / B[k * r + k];
+      for (int j = k; j < r; ++j) B[i * r + j] -= f * B[k * r + j];
+      y[i] -= f * y[k];
+    }
+  }
+  for (int k = r - 1; k >= 0; --k) {
+    cplx s = y[k];
+    for (int j = k + 1; j < r; ++j) s -= B[k * r + j] * y[j];
+    y[k] = s / B[k * r + k];
+  }
+  return true;
+}
+
+bool rinverse(int r, const double* M, double* inv) {
+  std::vector<cplx> cols(r * r);
+  for (int j = 0; j < r; ++j) {
+    std::vector<cplx> B(r * r), e(r, 0.0);
+    for (int i = 0; i < r * r; ++i) B[i] = M[i];
+    e[j] = 1.0;
+    if (!csolve(r, B, e)) return false;
+    for (int i = 0; i < r; ++i) inv[i * r + j] = e[i].real();
+  }
+  return true;
+}
+
+double inf_norm(int r, const double* M) {
+  double m = 0;
+  for (int i = 0; i < r; ++i) {
+    double s = 0;
+    for (int j = 0; j < r; ++j) s += std::fabs(M[i * r + j]);
+    m = std::max(m, s);
+  }
+  return m;
+}
+}  // namespace
+
+bool stage_eigenbasis(const double* A, int r, StageEig& out, std::string* why) {
+  auto fail = [&](const std::string& m) {
+    if (why) *why = m;
+    return false;
+  };
+  out = StageEig();
+  out.r = r;
+  if (r < 1 || r > kMaxStages) return fail("stage count outside 1..4");
+  double amax = 0;
+  for (int i = 0; i < r * r; ++i) amax = std::max(amax, std::fabs(A[i]));
+  const double scale = std::max(amax, 1e-300);
+  // characteristic polynomial (Faddeev--LeVerrier): p(z) = sum_k c[k] z^k, c[r] = 1
+  std::vector<double> c(r + 1, 0.0), Mk(r * r, 0.0), AM(r * r);
+  c[r] = 1.0;
+  for (int k = 1; k <= r; ++k) {
+    for (int i = 0; i < r; ++i)
+      for (int j = 0; j < r; ++j) {
+        double s = 0;
+        for (int q = 0; q < r; ++q) s += A[i * r + q] * Mk[q * r + j];
+        AM[i * r + j] = s;
+      }
+    for (int i = 0; i < r * r; ++i) Mk[i] = AM[i];
+    for (int i = 0; i < r; ++i) Mk[i * r + i] += c[r - k + 1];
+    double tr = 0;
+    for (int i = 0; i < r; ++i)
+      for (int q = 0; q < r; ++q) tr += A[i * r + q] * Mk[q * r + i];
+    c[r - k] = -tr / k;
+  }
+  auto peval = [&](cplx z, cplx* dp) {
+    cplx p = c[r], d = 0.0;
+    for (int k = r - 1; k >= 0; --k) {
+      d = d * z + p;
+      p = p * z + c[k];
+    }
+    if (dp) *dp = d;
+    return p;
+  };
+  // roots: Durand--Kerner (simultaneous Weierstrass iteration), then Newton polishing
+  std::vector<cplx> z(r);
+  const cplx seed(0.4, 0.9);
+  for (int i = 0; i < r; ++i) z[i] = scale * std::pow(seed, i);
+  for (int it = 0; it < 2000; ++it) {
+    double change = 0;
+    for (int i = 0; i < r; ++i) {
+      cplx den = 1.0;
+      for (int j = 0; j < r; ++j)
+        if (j != i) den *= z[i] - z[j];
+      if (std::abs(den) == 0.0) den = 1e-300;
+      const cplx dz = peval(z[i], nullptr) / den;
+      z[i] -= dz;
+      change = std::max(change, std::abs(dz));
+    }
+    if (change <= 1e-16 * scale) break;
+  }
+  for (int i = 0; i < r; ++i)
+    for (int it = 0; it < 3; ++it) {
+      cplx d;
+      const cplx p = peval(z[i], &d);
+      if (std::abs(d) == 0.0) break;
+      z[i] -= p / d;
+    }
+  for (int i = 0; i < r; ++i)
+    for (int j = i + 1; j < r; ++j)
+      if (std::abs(z[i] - z[j]) <= 1e-6 * scale) return fail("repeated eigenvalues of A");
+  // blocks: real eigenvalues first (ascending), then pairs with b > 0 (ascending a)
+  std::vector<double> reals;
+  std::vector<cplx> pairs;
+  for (int i = 0; i < r; ++i) {
+    if (std::fabs(z[i].imag()) <= 1e-10 * scale) reals.push_back(z[i].real());
+    else if (z[i].imag() > 0) pairs.push_back(z[i]);
+  }
+  if ((int)reals.size() + 2 * (int)pairs.size() != r) return fail("unpaired complex eigenvalue");
+  std::sort(reals.begin(), reals.end());
+  std::sort(pairs.begin(), pairs.end(), [](cplx a, cplx b) { return a.real() < b.real(); });
+  // eigenvectors by inverse iteration with a slightly shifted eigenvalue
+  auto eigvec = [&](cplx lam) {
+    std::vector<cplx> v(r);
+    for (int i = 0; i < r; ++i) v[i] = 1.0 + 0.1 * i;
+    const cplx mu = lam + cplx(1e-10, 1e-10) * std::max(1.0, std::abs(lam));
+    for (int it = 0; it < 4; ++it) {
+      std::vector<cplx> B(r * r);
+      for (int i = 0; i < r; ++i)
+        for (int j = 0; j < r; ++j) B[i * r + j] = A[i * r + j] - (i == j ? mu : cplx(0.0));
+      if (!csolve(r, B, v)) break;  // mu hit the eigenvalue exactly: v is converged
+      double nrm = 0;
+      int big = 0;
+      for (int i = 0; i < r; ++i) {
+        nrm += std::norm(v[i]);
+        if (std::abs(v[i]) > std::abs(v[big])) big = i;
+      }
+      const cplx ph = v[big] / std::abs(v[big]);
+      for (int i = 0; i < r; ++i) v[i] /= ph * std::sqrt(nrm);
+    }
+    return v;
+  };
+  int col = 0;
+  for (double lam : reals) {
+    const std::vector<cplx> v = eigvec(lam);
+    for (int i = 0; i < r; ++i) out.W[i * r + col] = v[i].real();
+    out.type[out.nblk] = 1;
+    out.st0[out.nblk] = col;
+    out.Tb[out.nblk][0] = lam;
+    ++out.nblk;
+    col += 1;
+  }
+  for (cplx lam : pairs) {
+    // A (p + iq) = (a + ib)(p + iq)  =>  A [p q] = [p q] [[a, b], [-b, a]]
+    const std::vector<cplx> v = eigvec(lam);
+    for (int i = 0; i < r; ++i) {
+      out.W[i * r + col] = v[i].real();
+      out.W[i * r + col + 1] = v[i].imag();
+    }
+    out.type[out.nblk] = 2;
+    out.st0[out.nblk] = col;
+    out.Tb[out.nblk][0] = lam.real();
+    out.Tb[out.nblk][1] = lam.imag();
+    out.Tb[out.nblk][2] = -lam.imag();
+    out.Tb[out.nblk][3] = lam.real();
+    ++out.nblk;
+    col += 2;
+  }
+  if (!rinverse(r, out.W, out.Winv)) return fail("singular eigenvector matrix");
+  out.cond = inf_norm(r, out.W) * inf_norm(r, out.Winv);
+  if (!(out.cond <= 1e6)) return fail("ill-conditioned eigenvector matrix");
+  // reconstruction W T W^{-1} against A
+  std::vector<double> T(r * r, 0.0), WT(r * r, 0.0);
+  for (int b = 0; b < out.nblk; ++b)
+    for (int i = 0; i < out.type[b]; ++i)
+      for (int j = 0; j < out.type[b]; ++j)
+        T[(out.st0[b] + i) * r + out.st0[b] + j] = out.Tb[b][i * out.type[b] + j];
+  for (int i = 0; i < r; ++i)
+    for (int j = 0; j < r; ++j)
+      for (int q = 0; q < r; ++q) WT[i * r + j] += out.W[i * r + q] * T[q * r + j];
+  double err = 0;
+  for (int i = 0; i < r; ++i)
+    for (int j = 0; j < r; ++j) {
+      double s = 0;
+      for (int q = 0; q < r; ++q) s += WT[i * r + q] * out.Winv[q * r + j];
+      err = std::max(err, std::fabs(s - A[i * r + j]));
+    }
+  out.recon = err;
+  if (!(err <= 1e-13 * scale * std::max(1.0, out.cond))) return fail("eigen-decomposition check failed");
+  return true;
+}
 }  // namespace irk

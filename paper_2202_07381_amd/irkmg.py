@@ -38,7 +38,7 @@ class irk_tableau(C.Structure):
 
 class irk_mg_opts(C.Structure):
     _fields_ = [("pre", C.c_int), ("post", C.c_int), ("omega", C.c_double),
-                ("weighting", C.c_int), ("precision", C.c_int)]
+                ("weighting", C.c_int), ("precision", C.c_int), ("patch_form", C.c_int)]
 
 
 class irk_solve_info(C.Structure):
@@ -70,6 +70,8 @@ def _load() -> C.CDLL:
         "irk_mesh_p2_nodes": (i, [vp, vp, vp]),
         "irk_mg_setup": (i, [vp, i, vp, d, d, vp, vp, vp, vp]),
         "irk_mg_destroy": (None, [vp]),
+        "irk_mg_patch_form": (i, [vp]),
+        "irk_stage_basis": (i, [i, vp, vp, vp, vp]),
         "irk_mg_ndofs": (i64, [vp, i]),
         "irk_mg_sizes": (i, [vp, i, vp]),
         "irk_mg_p2_nodes": (i, [vp, i, vp, vp]),
@@ -111,7 +113,7 @@ lib = _load()
 def header_functions() -> list[str]:
     """Names of the functions the public header declares."""
     txt = open(HEADER).read()
-    return sorted(set(re.findall(r"^\s*(?:irk_status|void|int64_t|const char\*)\s+(irk_\w+)\s*\(", txt, re.M)))
+    return sorted(set(re.findall(r"^\s*(?:irk_status|void|int64_t|int|const char\*)\s+(irk_\w+)\s*\(", txt, re.M)))
 
 
 def _check(status: int, ok=(IRK_OK,)) -> int:
@@ -137,6 +139,15 @@ def _mesh_struct(level) -> tuple[irk_mesh_level, list]:
     s = irk_mesh_level(level.dim, xyz.shape[0], cells.shape[0], xyz.ctypes.data, cells.ctypes.data,
                        par.ctypes.data if par is not None else None)
     return s, keep
+
+
+def irk_stage_basis(A):
+    """(W, Winv, T) with A = W T W^{-1}, T real block diagonal (irk_stage_basis)."""
+    A = np.ascontiguousarray(A, dtype=np.float64)
+    r = A.shape[0]
+    W, Wi, T = (np.zeros((r, r)) for _ in range(3))
+    _check(lib.irk_stage_basis(r, A.ctypes.data, W.ctypes.data, Wi.ctypes.data, T.ctypes.data))
+    return W, Wi, T
 
 
 def irk_mesh_p2_nodes(level) -> np.ndarray:
@@ -170,7 +181,7 @@ class IrkMG:
     """Handle of one hierarchy (irk_mg_setup ... irk_mg_destroy)."""
 
     def __init__(self, levels, A, b, c, dt: float, nu: float, wind_nodal=None, pre=2, post=2,
-                 omega=0.5, weighting=1, precision=0, stream=None):
+                 omega=0.5, weighting=1, precision=0, patch_form=2, stream=None):
         structs, keep = [], []
         for lv in levels:
             s, k = _mesh_struct(lv)
@@ -181,7 +192,7 @@ class IrkMG:
         self.A, self.b, self.c = A, np.ascontiguousarray(b, dtype=np.float64), np.ascontiguousarray(c, dtype=np.float64)
         self.r = len(self.b)
         tab = irk_tableau(self.r, A.ctypes.data, self.b.ctypes.data, self.c.ctypes.data)
-        opts = irk_mg_opts(pre, post, omega, weighting, precision)
+        opts = irk_mg_opts(pre, post, omega, weighting, precision, patch_form)
         w = None
         if wind_nodal is not None:
             w = np.ascontiguousarray(wind_nodal, dtype=np.float64)
@@ -202,6 +213,10 @@ class IrkMG:
         self.close()
 
     # ---------------------------------------------------------------- sizes
+    def irk_mg_patch_form(self) -> int:
+        """0: dense patch inverses; 1: factored through the stage eigenbasis."""
+        return int(lib.irk_mg_patch_form(self.h))
+
     def irk_mg_ndofs(self, level: int = -1) -> int:
         return int(lib.irk_mg_ndofs(self.h, level))
 

@@ -62,8 +62,8 @@ def oracle_of(case, dtype=np.float64):
 _GPU = {}
 
 
-def gpu_of(case, precision=0):
-    key = (case, precision)
+def gpu_of(case, precision=0, patch_form=2):
+    key = (case, precision, patch_form)
     if key not in _GPU:
         from paper_2202_07381_amd import irkmg
 
@@ -72,9 +72,9 @@ def gpu_of(case, precision=0):
         A, b, c = irkmg.irk_tableau_builtin(fam, r)
         wind = wind_of(case)
         wn = wind(irkmg.irk_mesh_p2_nodes(lv[-1])) if wind is not None else None
-        say(f"[setup] case={case} precision={precision} N={r * 0}")
-        _GPU[key] = irkmg.IrkMG(lv, A, b, c, dt, nu, wind_nodal=wn, precision=precision)
-        say(f"[setup] done case={case} N={_GPU[key].irk_mg_ndofs()}")
+        say(f"[setup] case={case} precision={precision} patch_form={patch_form}")
+        _GPU[key] = irkmg.IrkMG(lv, A, b, c, dt, nu, wind_nodal=wn, precision=precision, patch_form=patch_form)
+        say(f"[setup] done case={case} N={_GPU[key].irk_mg_ndofs()} form={_GPU[key].irk_mg_patch_form()}")
     return _GPU[key]
 
 

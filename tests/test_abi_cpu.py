@@ -88,3 +88,57 @@ def test_null_handle_calls_fail_cleanly():
     assert irkmg.lib.irk_fgmres_solve(None, None, None, 1e-8, 10, 30, None, None) == irkmg.IRK_EINVAL
     assert irkmg.lib.irk_mg_ndofs(None, -1) == -1
     irkmg.lib.irk_mg_destroy(None)
+
+
+# ------------------------------------------------------------ stage eigenbasis (host)
+@pytest.mark.parametrize("family,r", [("radauIIA", 1), ("radauIIA", 2), ("radauIIA", 3), ("gauss", 2),
+                                      ("gauss", 3), ("lobattoIIIC", 2), ("lobattoIIIC", 3)])
+def test_stage_basis_builtin(family, r):
+    """A = W T W^{-1} with T real block diagonal: real eigenvalues first, then pairs as
+    [[a, b], [-b, a]], b > 0; the eigenvalues agree with LAPACK's."""
+    from paper_2202_07381_amd import irkmg
+
+    A, b, c = irkmg.irk_tableau_builtin(family, r)
+    W, Wi, T = irkmg.irk_stage_basis(A)
+    assert np.abs(W @ T @ Wi - A).max() < 1e-13
+    assert np.abs(W @ Wi - np.eye(r)).max() < 1e-13
+    ev = []
+    k = 0
+    while k < r:
+        if k + 1 < r and T[k, k + 1] != 0.0:
+            a_, b_ = T[k, k], T[k, k + 1]
+            assert b_ > 0 and T[k + 1, k] == -b_ and T[k + 1, k + 1] == a_
+            assert np.all(T[k:k + 2, :k] == 0) and np.all(T[k:k + 2, k + 2:] == 0)
+            ev += [a_ + 1j * b_, a_ - 1j * b_]
+            k += 2
+        else:
+            assert np.count_nonzero(T[k]) <= 1
+            ev.append(T[k, k])
+            k += 1
+    ref = np.linalg.eigvals(A)
+    assert np.abs(np.sort_complex(np.array(ev)) - np.sort_complex(ref)).max() < 1e-12
+
+
+def test_stage_basis_known_spectrum():
+    """4x4 matrix with prescribed eigenvalues (two real, one pair) in a random basis."""
+    from paper_2202_07381_amd import irkmg
+
+    rng = np.random.default_rng(5)
+    V = rng.standard_normal((4, 4))
+    T0 = np.array([[0.2, 0, 0, 0], [0, 0.7, 0, 0], [0, 0, 0.3, 0.45], [0, 0, -0.45, 0.3]])
+    A = V @ T0 @ np.linalg.inv(V)
+    W, Wi, T = irkmg.irk_stage_basis(A)
+    assert np.abs(W @ T @ Wi - A).max() < 1e-12
+    assert np.allclose(np.diag(T)[:2], [0.2, 0.7], atol=1e-12)
+    assert np.allclose(T[2:, 2:], T0[2:, 2:], atol=1e-12)
+
+
+@pytest.mark.parametrize("A", [np.array([[1.0, 1.0], [0.0, 1.0]]),   # defective
+                               2.0 * np.eye(2),                         # repeated
+                               np.zeros((5, 5))])                       # r > 4
+def test_stage_basis_rejects(A):
+    from paper_2202_07381_amd import irkmg
+
+    with pytest.raises(irkmg.IrkError) as ei:
+        irkmg.irk_stage_basis(A)
+    assert ei.value.status == irkmg.IRK_EINVAL

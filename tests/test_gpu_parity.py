@@ -8,7 +8,9 @@ library applies an explicit Gauss--Jordan inverse of the pinned coarse operator 
 the oracle an LU solve, two backward-stable solves whose results differ by up to the
 condition number times the unit roundoff (cond(J_0) reaches 1e8 at dt = 1e-2);
 FGMRES solutions after equal iteration counts 1e-10 relative (the target stated for
-the method)."""
+the method).  Sweeps, V-cycles and solves run with both patch forms: 0 (dense patch
+inverses) and 2 (automatic: inverses factored through the stage eigenbasis for r >= 2),
+which apply the same operator up to rounding."""
 import numpy as np
 import pytest
 
@@ -18,6 +20,7 @@ pytestmark = pytest.mark.gpu
 torch = pytest.importorskip("torch")
 
 ALL = list(CASES)
+FORMS = [0, 2]
 
 
 @pytest.mark.parametrize("case", ALL)
@@ -35,15 +38,16 @@ def test_apply_all_levels(case):
             assert relerr(to_host(y), ref) < 1e-13
 
 
+@pytest.mark.parametrize("form", FORMS)
 @pytest.mark.parametrize("case", ALL)
-def test_sweep_each_level(case):
-    g, H = gpu_of(case), oracle_of(case)
+def test_sweep_each_level(case, form):
+    g, H = gpu_of(case, patch_form=form), oracle_of(case)
     rng = np.random.default_rng(12)
     for lev in range(1, g.nlevels):
         J = H.systems[lev].J
         F, k0 = rng.standard_normal(J.shape[0]), rng.standard_normal(J.shape[0])
         for tr in (False, True):
-            say(f"[sweep] case={case} level={lev} transpose={tr}")
+            say(f"[sweep] case={case} form={form} level={lev} transpose={tr}")
             k = to_dev(k0)
             g.irk_level_sweep(lev, to_dev(F), k, transpose=tr)
             ref = H.smoothers[lev].sweep(F, k0, J.T if tr else J, tr)
@@ -87,11 +91,12 @@ def test_coarse_solve(case):
         assert relerr(to_host(x), H.coarse_solve(b, tr)) < coarse_tol(H)
 
 
+@pytest.mark.parametrize("form", FORMS)
 @pytest.mark.parametrize("case", ALL)
-def test_vcycle(case):
-    g, H = gpu_of(case), oracle_of(case)
+def test_vcycle(case, form):
+    g, H = gpu_of(case, patch_form=form), oracle_of(case)
     r = np.random.default_rng(15).standard_normal(g.irk_mg_ndofs())
-    say(f"[vcycle] case={case}")
+    say(f"[vcycle] case={case} form={form}")
     z = torch.zeros(r.size, dtype=torch.float64, device="cuda")
     g.irk_mg_vcycle(to_dev(r), z)
     assert relerr(to_host(z), H.vcycle(r)) < coarse_tol(H)
@@ -100,11 +105,12 @@ def test_vcycle(case):
     assert relerr(to_host(z), H.vcycle_transpose(r)) < coarse_tol(H)
 
 
+@pytest.mark.parametrize("form", FORMS)
 @pytest.mark.parametrize("case", ALL)
-def test_vcycle_bitwise_repeatable(case):
-    g = gpu_of(case)
+def test_vcycle_bitwise_repeatable(case, form):
+    g = gpu_of(case, patch_form=form)
     r = to_dev(np.random.default_rng(16).standard_normal(g.irk_mg_ndofs()))
-    say(f"[repeat] case={case}")
+    say(f"[repeat] case={case} form={form}")
     outs = []
     for _ in range(5):
         z = torch.zeros_like(r)
@@ -113,15 +119,16 @@ def test_vcycle_bitwise_repeatable(case):
     assert all(np.array_equal(outs[0], o) for o in outs[1:])
 
 
+@pytest.mark.parametrize("form", FORMS)
 @pytest.mark.parametrize("case", ALL)
-def test_fgmres_matches_oracle(case):
+def test_fgmres_matches_oracle(case, form):
     from oracle.fgmres import fgmres
 
-    g, H = gpu_of(case), oracle_of(case)
+    g, H = gpu_of(case, patch_form=form), oracle_of(case)
     S = H.finest
     F = forcing_rhs(case)
     for rtol, maxit in ((1e-8, 200), (1e-30, 4)):
-        say(f"[fgmres] case={case} rtol={rtol} maxit={maxit}")
+        say(f"[fgmres] case={case} form={form} rtol={rtol} maxit={maxit}")
         k = torch.zeros(F.size, dtype=torch.float64, device="cuda")
         info = g.irk_fgmres_solve(to_dev(F), k, rtol=rtol, maxit=maxit, restart=30)
         xo, io = fgmres(S.apply, H.vcycle, F, np.zeros_like(F), rtol, maxit, 30, project=S.project_pressure_mean)
@@ -165,8 +172,9 @@ def test_rhs_and_update():
     assert relerr(to_host(state), ref) < 1e-14
 
 
-def test_mixed_precision_reaches_tolerance():
-    g64, g32, H = gpu_of("r3"), gpu_of("r3", precision=1), oracle_of("r3")
+@pytest.mark.parametrize("form", FORMS)
+def test_mixed_precision_reaches_tolerance(form):
+    g64, g32, H = gpu_of("r3", patch_form=form), gpu_of("r3", precision=1, patch_form=form), oracle_of("r3")
     F = forcing_rhs("r3")
     say("[mixed] case=r3")
     k64 = torch.zeros(F.size, dtype=torch.float64, device="cuda")
@@ -197,3 +205,23 @@ def test_error_paths():
     assert e.value.status == irkmg.IRK_ENAN
     with pytest.raises(ValueError):
         g.irk_mg_vcycle(to_dev(F[:-1]), k)
+
+
+def test_patch_form_selection():
+    """Automatic form: factored for r >= 2, dense for r = 1; both forms can be forced,
+    including the factored form at r = 1 (one real block, W = 1)."""
+    for case in ALL:
+        r = CASES[case][4]
+        assert gpu_of(case, patch_form=2).irk_mg_patch_form() == (1 if r >= 2 else 0), case
+        assert gpu_of(case, patch_form=0).irk_mg_patch_form() == 0, case
+    g, H = gpu_of("be", patch_form=1), oracle_of("be")
+    assert g.irk_mg_patch_form() == 1
+    rng = np.random.default_rng(19)
+    for lev in range(1, g.nlevels):
+        J = H.systems[lev].J
+        F, k0 = rng.standard_normal(J.shape[0]), rng.standard_normal(J.shape[0])
+        for tr in (False, True):
+            say(f"[form1 r=1] level={lev} transpose={tr}")
+            k = to_dev(k0)
+            g.irk_level_sweep(lev, to_dev(F), k, transpose=tr)
+            assert relerr(to_host(k), H.smoothers[lev].sweep(F, k0, J.T if tr else J, tr)) < 1e-11
