@@ -51,6 +51,7 @@ struct BLevel {
   int64_t nfree, nv, N, offV, npatch;
   int rb;     // row blocks of the patch apply (ceil(max stored column / 128))
   int pform;  // patch form: 0 dense inverse, 1 factored through the stage eigenbasis
+  int dim, r;
   irk::StageBasis<double> sb;
   const int32_t *s_ptr, *s_col, *b_ptr, *b_col, *bt_ptr, *bt_col;
   const double *sM, *sL, *b_val, *bt_val, *W;
@@ -211,16 +212,16 @@ __device__ void patches(const BLevel& L, double* xs, double* xt, const double* i
     if (L.pform == 1) {
       if (L.rb == 1)
         dev::patch_apply_eig_one<double, 1, 8>(p, lane, xs, xt, L.sb, L.p_nloc, L.p_ld, L.p_inv_off, L.p_slot_off,
-                                               L.p_gidx, L.inv, in, nullptr, L.Y, 0);
+                                               L.p_gidx, L.inv, in, nullptr, L.Y, 0, L.dim);
       else
         dev::patch_apply_eig_one<double, 2, 4>(p, lane, xs, xt, L.sb, L.p_nloc, L.p_ld, L.p_inv_off, L.p_slot_off,
-                                               L.p_gidx, L.inv, in, nullptr, L.Y, 0);
+                                               L.p_gidx, L.inv, in, nullptr, L.Y, 0, L.dim);
       continue;
     }
     switch (L.rb) {
-      case 1: dev::patch_apply_one<double, 1, 8>(p, lane, xs, L.p_nloc, L.p_ld, L.p_inv_off, L.p_slot_off, L.p_gidx, L.inv, in, nullptr, L.Y, 0); break;
-      case 2: dev::patch_apply_one<double, 2>(p, lane, xs, L.p_nloc, L.p_ld, L.p_inv_off, L.p_slot_off, L.p_gidx, L.inv, in, nullptr, L.Y, 0); break;
-      default: dev::patch_apply_one<double, 2>(p, lane, xs, L.p_nloc, L.p_ld, L.p_inv_off, L.p_slot_off, L.p_gidx, L.inv, in, nullptr, L.Y, 0); break;
+      case 1: dev::patch_apply_one<double, 1, 8>(p, lane, xs, L.p_nloc, L.p_ld, L.p_inv_off, L.p_slot_off, L.p_gidx, L.inv, in, nullptr, L.Y, 0, L.dim, L.r); break;
+      case 2: dev::patch_apply_one<double, 2>(p, lane, xs, L.p_nloc, L.p_ld, L.p_inv_off, L.p_slot_off, L.p_gidx, L.inv, in, nullptr, L.Y, 0, L.dim, L.r); break;
+      default: dev::patch_apply_one<double, 2>(p, lane, xs, L.p_nloc, L.p_ld, L.p_inv_off, L.p_slot_off, L.p_gidx, L.inv, in, nullptr, L.Y, 0, L.dim, L.r); break;
     }
   }
 }
@@ -855,6 +856,8 @@ BLevel level_view(const DevLevel& L) {
   v.offV = L.offV;
   v.npatch = L.npatch;
   v.pform = L.pform;
+  v.dim = L.dim;
+  v.r = L.r;
   v.rb = L.pform == 1 ? (L.max_ld <= 128 ? 1 : 2) : (L.max_nloc <= 128 ? 1 : 2);
   v.sb = L.sb64;
   v.s_ptr = L.s_ptr; v.s_col = L.s_col; v.b_ptr = L.b_ptr; v.b_col = L.b_col; v.bt_ptr = L.bt_ptr; v.bt_col = L.bt_col;

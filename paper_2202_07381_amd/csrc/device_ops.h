@@ -123,6 +123,20 @@ __device__ inline void vload<float4, float>(const float* p, float* o) {
   o[3] = v.w;
 }
 
+// Output slot of local index e of a patch (stage-major: e = s ns + q with q = c nn + a
+// for velocity component c of patch node a, q = D nn for the pressure) in the patch's
+// node-major output order ((a D + c) R + s, pressure nn D R + s), so that the D R values
+// of one node, which the gather reads together, are contiguous.
+__device__ __forceinline__ int node_major_slot(int e, int ns, int D, int R) {
+  const int s = e / ns, q = e - s * ns;
+  const int nn = (ns - 1) / D;
+  if (q < D * nn) {
+    const int c = q / nn, a = q - c * nn;
+    return (a * D + c) * R + s;
+  }
+  return nn * D * R + s;
+}
+
 // One wavefront applies the stored inverse of patch p.  Lane l owns rows
 // [rb*64*VEC + l*VEC, +VEC) of row block rb.  Non-transposed: y = Ainv x streams
 // column j with one 16-byte load per lane; transposed: y_j = column_j . x with a wave
@@ -132,10 +146,11 @@ __device__ __forceinline__ void patch_apply_one(
     int p, int lane, T* xs, const int32_t* __restrict__ p_nloc, const int32_t* __restrict__ p_ld,
     const int64_t* __restrict__ p_inv_off, const int64_t* __restrict__ p_slot_off,
     const int32_t* __restrict__ gidx, const T* __restrict__ inv, const T* __restrict__ res,
-    const T* __restrict__ W, T* __restrict__ Y, int transpose) {
+    const T* __restrict__ W, T* __restrict__ Y, int transpose, int D, int R) {
   using VT = typename Vec16<T>::type;
   constexpr int VEC = Vec16<T>::n;
   const int n = p_nloc[p];
+  const int ns = n / R;
   const int ld = p_ld[p];
   const int64_t so = p_slot_off[p];
   const T* __restrict__ Ap = inv + p_inv_off[p];
@@ -192,7 +207,7 @@ __device__ __forceinline__ void patch_apply_one(
 #pragma unroll
       for (int v = 0; v < VEC; ++v) {
         const int row = b * 64 * VEC + lane * VEC + v;
-        if (row < n) Y[so + row] = acc[b][v];
+        if (row < n) Y[so + node_major_slot(row, ns, D, R)] = acc[b][v];
       }
   } else {
     for (int j = 0; j < n; ++j) {
@@ -210,7 +225,7 @@ __device__ __forceinline__ void patch_apply_one(
       }
 #pragma unroll
       for (int off = 32; off > 0; off >>= 1) part += __shfl_xor(part, off, 64);
-      if (lane == 0) Y[so + j] = part;
+      if (lane == 0) Y[so + node_major_slot(j, ns, D, R)] = part;
     }
   }
   // xs is reused by this wavefront's next patch
@@ -251,7 +266,7 @@ __device__ __forceinline__ void patch_apply_eig_one(
     int p, int lane, T* xs, T* xt, const irk::StageBasis<T>& sb, const int32_t* __restrict__ p_nloc,
     const int32_t* __restrict__ p_ld, const int64_t* __restrict__ p_inv_off,
     const int64_t* __restrict__ p_slot_off, const int32_t* __restrict__ gidx, const T* __restrict__ inv,
-    const T* __restrict__ res, const T* __restrict__ W, T* __restrict__ Y, int transpose) {
+    const T* __restrict__ res, const T* __restrict__ W, T* __restrict__ Y, int transpose, int D) {
   using VT = typename Vec16<T>::type;
   constexpr int VEC = Vec16<T>::n;
   const int n = p_nloc[p];
@@ -409,7 +424,7 @@ __device__ __forceinline__ void patch_apply_eig_one(
     const int s = e / ns, q = e - s * ns;
     T acc = T(0);
     for (int k = 0; k < r; ++k) acc += (transpose ? sb.Winv[k * r + s] : sb.W[s * r + k]) * xs[k * ns + q];
-    Y[so + e] = acc;
+    Y[so + node_major_slot(e, ns, D, r)] = acc;
   }
   // xs and xt are reused by this wavefront's next patch
   __builtin_amdgcn_wave_barrier();
@@ -425,6 +440,31 @@ __device__ __forceinline__ void gather_one(int64_t g, const int32_t* __restrict_
   T s = T(0);
   const int32_t q1 = gptr[g + 1];
   for (int32_t q = gptr[g]; q < q1; ++q) s += Y[gslot[q]];
+  T c = omega * s;
+  if (mode < 2) c *= W[g];
+  x[g] = (mode & 1) ? x[g] + c : c;
+}
+
+// Owner gather of one DOF from the sliced slot lists (entry k of DOF g of slice sl at
+// off[sl] + 64 k + lane; padding entries point at a slot that always holds zero).
+template <typename T>
+__device__ __forceinline__ void gather_sell_one(int64_t g, int64_t sl, int lane, const int32_t* __restrict__ g_off,
+                                                const int32_t* __restrict__ g_w, const int32_t* __restrict__ g_slot,
+                                                const T* __restrict__ Y, const T* __restrict__ W, T omega, int mode,
+                                                T* __restrict__ x, int64_t N) {
+  const int w = g_w[sl];
+  const int64_t e0 = g_off[sl] + lane;
+  T s = T(0);
+  int k = 0;
+  for (; k + 4 <= w; k += 4) {
+    int32_t q[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) q[u] = g_slot[e0 + (int64_t)(k + u) * 64];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) s += Y[q[u]];
+  }
+  for (; k < w; ++k) s += Y[g_slot[e0 + (int64_t)k * 64]];
+  if (g >= N) return;
   T c = omega * s;
   if (mode < 2) c *= W[g];
   x[g] = (mode & 1) ? x[g] + c : c;

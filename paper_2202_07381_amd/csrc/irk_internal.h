@@ -21,6 +21,20 @@ namespace irk {
 
 constexpr int kMaxStages = 4;
 
+// Sliced copy of a CSR operator for the residual kernel: rows in slices of 64, each slice
+// padded to its longest row, entries of a slice stored column-major (entry k of the 64
+// rows contiguous) so that a wavefront reads its rows' k-th entries in one coalesced
+// access.  src[e] is the CSR position of sliced entry e, or -1 for padding (column 0,
+// value 0).
+struct Sell {
+  int64_t nslices = 0;
+  std::vector<int32_t> off, w, col;  // entry offset and width of each slice, columns
+  std::vector<int64_t> src;
+};
+Sell build_sell(int64_t nrows, const std::vector<int32_t>& ptr, const std::vector<int32_t>& col);
+// Values of a CSR value array (k values per entry) in the sliced order.
+std::vector<double> sell_values(const Sell& S, const std::vector<double>& v, int k);
+
 // ----------------------------------------------------------------- host level data
 struct HostLevel {
   int dim = 0;
@@ -58,6 +72,10 @@ struct HostLevel {
   std::vector<int32_t> pp_ptr, pp_col, ppt_ptr, ppt_col;
   std::vector<double> pp_val, ppt_val;
   std::vector<int64_t> coarse_node_to_fine_vertex;  // injection (wind)
+
+  // sliced copies for the residual: velocity rows x free nodes (M, L, L^T), velocity
+  // rows x vertices (B), vertex rows x free nodes (B^T)
+  Sell sell_s, sell_b, sell_bt;
 };
 
 // Element reference tensors (integrals over the cell divided by its measure).
@@ -124,6 +142,8 @@ struct DevOps {
   T* pp_val = nullptr;
   T* ppt_val = nullptr;
   T* W = nullptr;  // per internal DOF weight of the additive correction
+  // values of the sliced operators (residual kernel)
+  T *u_M = nullptr, *u_L = nullptr, *u_Lt = nullptr, *u_B = nullptr, *p_Bt = nullptr;
 };
 
 struct DevLevel {
@@ -140,6 +160,11 @@ struct DevLevel {
   double* s_K1 = nullptr;
   DevOps<double> d64;
   DevOps<float> d32;
+  // sliced operator indices (see Sell): velocity slices, then vertex slices
+  int64_t nsl_u = 0, nsl_p = 0;
+  int32_t *su_off = nullptr, *su_w = nullptr, *su_col = nullptr;
+  int32_t *sb_off = nullptr, *sb_w = nullptr, *sb_col = nullptr;
+  int32_t *sp_off = nullptr, *sp_w = nullptr, *sp_col = nullptr;
 
   // patches
   int64_t npatch = 0;
@@ -152,6 +177,9 @@ struct DevLevel {
   int32_t* p_vertex = nullptr;
   int32_t *pvv_ptr = nullptr, *pvv = nullptr, *pvp = nullptr, *pn_ptr = nullptr;
   int32_t *gat_ptr = nullptr, *gat_slot = nullptr;  // DOF -> its patch slots
+  // the same lists sliced (Sell layout; padding -> slot `slots`, which stays zero)
+  int64_t nsl_g = 0;
+  int32_t *g_off = nullptr, *g_w = nullptr, *g_slot = nullptr;
   void* inv = nullptr;                              // double or float inverses
   int64_t inv_elems = 0, slots = 0;
   int max_nloc = 0;

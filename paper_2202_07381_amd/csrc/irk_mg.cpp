@@ -77,6 +77,11 @@ irk_status upload_ops(Handle* h, HostLevel& H, DevLevel& D, DevOps<T>& o, const 
   CHK(upload(h, &o.b_val, H.b_val, s));
   CHK(upload(h, &o.bt_val, H.bt_val, s));
   CHK(upload(h, &o.W, W, s));
+  CHK(upload(h, &o.u_M, irk::sell_values(H.sell_s, H.s_M, 1), s));
+  CHK(upload(h, &o.u_L, irk::sell_values(H.sell_s, H.s_L, 1), s));
+  CHK(upload(h, &o.u_Lt, irk::sell_values(H.sell_s, H.s_Lt, 1), s));
+  CHK(upload(h, &o.u_B, irk::sell_values(H.sell_b, H.b_val, H.dim), s));
+  CHK(upload(h, &o.p_Bt, irk::sell_values(H.sell_bt, H.bt_val, H.dim), s));
   if (!H.pu_val.empty()) {
     CHK(upload(h, &o.pu_val, H.pu_val, s));
     CHK(upload(h, &o.put_val, H.put_val, s));
@@ -143,7 +148,10 @@ irk_status smooth(Handle* h, int l, int nsweeps, bool zero_start, bool tr, hipSt
     return IRK_OK;
   }
   DevOps<T> ot = o;
-  if (tr) ot.s_L = o.s_Lt;
+  if (tr) {
+    ot.s_L = o.s_Lt;
+    ot.u_L = o.u_Lt;
+  }
   for (int it = 0; it < nsweeps; ++it) {
     const bool first = zero_start && it == 0;
     const T* r = b;
@@ -173,7 +181,10 @@ irk_status vcycle_T(Handle* h, bool tr, hipStream_t s, const int64_t* pins) {
   for (int l = top; l >= 1; --l) {
     DevLevel& L = h->dev[l];
     DevOps<T> o = ops_of<T>(L);
-    if (tr) o.s_L = o.s_Lt;
+    if (tr) {
+      o.s_L = o.s_Lt;
+      o.u_L = o.u_Lt;
+    }
     CHK(smooth<T>(h, l, npre, true, tr, s));
     const int p0 = prof_begin(h, 1, l, s);
     HIPCHK(k::residual<T>(L, o, A, h->dt, (const T*)L.b, (const T*)L.x, (T*)L.res, s));
@@ -218,7 +229,10 @@ irk_status precondition(irk_mg* h, const double* v, double* z, bool tr, hipStrea
 irk_status apply_J(irk_mg* h, const double* x, double* y, bool tr, const double* F, hipStream_t s) {
   DevLevel& L = h->dev[h->nlevels - 1];
   DevOps<double> o = L.d64;
-  if (tr) o.s_L = o.s_Lt;
+  if (tr) {
+    o.s_L = o.s_Lt;
+    o.u_L = o.u_Lt;
+  }
   HIPCHK(k::residual<double>(L, o, tr ? h->At : h->A, h->dt, F, x, y, s));
   return IRK_OK;
 }
@@ -659,6 +673,10 @@ static irk_status setup_impl(const irk_mesh_level* lv, int nlevels, const irk_ta
   for (int l = 0; l < nlevels; ++l) {
     assemble_level(h->host[l], nu, wind ? &winds[l] : nullptr, l == nlevels - 1);
     if (l >= 1) build_patches(h->host[l]);
+    HostLevel& H = h->host[l];
+    H.sell_s = irk::build_sell(H.nfree, H.s_ptr, H.s_col);
+    H.sell_b = irk::build_sell(H.nfree, H.b_ptr, H.b_col);
+    H.sell_bt = irk::build_sell(H.nv, H.bt_ptr, H.bt_col);
   }
   // ---- device
   const int VEC = h->precision == 0 ? 2 : 4;
@@ -678,6 +696,17 @@ static irk_status setup_impl(const irk_mesh_level* lv, int nlevels, const irk_ta
     CHK(upload(h, &D.b_col, H.b_col, s));
     CHK(upload(h, &D.bt_ptr, H.bt_ptr, s));
     CHK(upload(h, &D.bt_col, H.bt_col, s));
+    D.nsl_u = H.sell_s.nslices;
+    D.nsl_p = H.sell_bt.nslices;
+    CHK(upload(h, &D.su_off, H.sell_s.off, s));
+    CHK(upload(h, &D.su_w, H.sell_s.w, s));
+    CHK(upload(h, &D.su_col, H.sell_s.col, s));
+    CHK(upload(h, &D.sb_off, H.sell_b.off, s));
+    CHK(upload(h, &D.sb_w, H.sell_b.w, s));
+    CHK(upload(h, &D.sb_col, H.sell_b.col, s));
+    CHK(upload(h, &D.sp_off, H.sell_bt.off, s));
+    CHK(upload(h, &D.sp_w, H.sell_bt.w, s));
+    CHK(upload(h, &D.sp_col, H.sell_bt.col, s));
     if (l >= 1) {
       CHK(upload(h, &D.pu_ptr, H.pu_ptr, s));
       CHK(upload(h, &D.pu_col, H.pu_col, s));
@@ -774,7 +803,26 @@ static irk_status setup_impl(const irk_mesh_level* lv, int nlevels, const irk_ta
       for (int64_t g = 0; g < D.N; ++g) gptr[g + 1] += gptr[g];
       gslot.resize(so);
       std::vector<int32_t> fillp(gptr.begin(), gptr.end() - 1);
-      for (int64_t q = 0; q < so; ++q) gslot[fillp[gidx[q]]++] = (int32_t)q;
+      // patch outputs are stored node-major within each patch (the patch kernels write
+      // local index e to slot slot_off + node_major_slot(e)); the lists name those slots
+      for (int64_t p = 0; p < np; ++p) {
+        const int n = nloc[p], ns = n / r, nn = nnv[p];
+        for (int e = 0; e < n; ++e) {
+          const int st = e / ns, q = e - st * ns;
+          const int slot = q < dim * nn ? ((q % nn) * dim + q / nn) * r + st : nn * dim * r + st;
+          const int64_t g = gidx[slot_off[p] + e];
+          gslot[fillp[g]++] = (int32_t)(slot_off[p] + slot);
+        }
+      }
+      {
+        irk::Sell G = irk::build_sell(D.N, gptr, gslot);
+        for (size_t e = 0; e < G.col.size(); ++e)
+          if (G.src[e] < 0) G.col[e] = (int32_t)so;  // the zero slot
+        D.nsl_g = G.nslices;
+        CHK(upload(h, &D.g_off, G.off, s));
+        CHK(upload(h, &D.g_w, G.w, s));
+        CHK(upload(h, &D.g_slot, G.col, s));
+      }
       for (int64_t g = 0; g < D.N; ++g) {
         const int cnt = gptr[g + 1] - gptr[g];
         if (cnt == 0) return fail(IRK_EINVAL, "a DOF is covered by no patch");
@@ -821,7 +869,10 @@ static irk_status setup_impl(const irk_mesh_level* lv, int nlevels, const irk_ta
       *buf = tmp;
     }
     if (l >= 1) {
-      CHK(dalloc(h, &tmp, (D.slots * es + 7) / 8));
+      // one extra slot at the end, zeroed here and never written: the sliced gather's
+      // padding entries point at it
+      CHK(dalloc(h, &tmp, ((D.slots + 1) * es + 7) / 8));
+      HIPCHK(hipMemsetAsync(tmp, 0, (D.slots + 1) * es, s));
       D.Y = tmp;
       CHK(dalloc(h, &tmp, (D.inv_elems * es + 7) / 8));
       D.inv = tmp;
@@ -1093,7 +1144,10 @@ irk_status irk_level_apply(irk_mg* h, int level, int transpose, const double* x,
   double* tmp_out = h->kr;
   HIPCHK(k::to_internal<double>(L, x, tmp_in, s));
   DevOps<double> o = L.d64;
-  if (transpose) o.s_L = o.s_Lt;
+  if (transpose) {
+    o.s_L = o.s_Lt;
+    o.u_L = o.u_Lt;
+  }
   HIPCHK(k::residual<double>(L, o, transpose ? h->At : h->A, h->dt, nullptr, tmp_in, tmp_out, s));
   HIPCHK(k::to_abi<double>(L, tmp_out, y, s));
   return IRK_OK;

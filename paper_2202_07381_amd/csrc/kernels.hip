@@ -64,6 +64,146 @@ __global__ __launch_bounds__(kBlock) void k_residual(
                              bt_val, dtA, F, x, y);
 }
 
+// Same residual from the sliced operator copies: one wavefront per slice of 64 rows
+// (velocity slices first, then vertex slices), lane = row, entries of the slice read
+// column-major (coalesced indices and values), 4 entries' gathers in flight per lane.
+constexpr int kSellUnroll = 4;
+
+template <int D, int R, typename T>
+__global__ __launch_bounds__(256) void k_residual_sell(
+    int64_t nfree, int64_t nv, int64_t offV, int64_t nsu, int64_t nsp, const int32_t* __restrict__ su_off,
+    const int32_t* __restrict__ su_w, const int32_t* __restrict__ su_col, const T* __restrict__ uM,
+    const T* __restrict__ uL, const int32_t* __restrict__ sb_off, const int32_t* __restrict__ sb_w,
+    const int32_t* __restrict__ sb_col, const T* __restrict__ uB, const int32_t* __restrict__ sp_off,
+    const int32_t* __restrict__ sp_w, const int32_t* __restrict__ sp_col, const T* __restrict__ pBt,
+    Coef<T> dtA, const T* __restrict__ F, const T* __restrict__ x, T* __restrict__ y) {
+  constexpr int DR = D * R;
+  const int lane = threadIdx.x & 63;
+  const int64_t sl = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (sl < nsu) {
+    const int64_t row = sl * 64 + lane;
+    T am[DR], al[DR];
+#pragma unroll
+    for (int q = 0; q < DR; ++q) am[q] = al[q] = T(0);
+    {
+      const int w = su_w[sl];
+      const int64_t e0 = su_off[sl] + lane;
+      int k = 0;
+      for (; k + kSellUnroll <= w; k += kSellUnroll) {
+        int32_t j[kSellUnroll];
+        T m[kSellUnroll], l[kSellUnroll], xv[kSellUnroll][DR];
+#pragma unroll
+        for (int u = 0; u < kSellUnroll; ++u) {
+          const int64_t e = e0 + (int64_t)(k + u) * 64;
+          j[u] = su_col[e];
+          m[u] = uM[e];
+          l[u] = uL[e];
+        }
+#pragma unroll
+        for (int u = 0; u < kSellUnroll; ++u)
+#pragma unroll
+          for (int q = 0; q < DR; ++q) xv[u][q] = x[(int64_t)j[u] * DR + q];
+#pragma unroll
+        for (int u = 0; u < kSellUnroll; ++u)
+#pragma unroll
+          for (int q = 0; q < DR; ++q) {
+            am[q] += m[u] * xv[u][q];
+            al[q] += l[u] * xv[u][q];
+          }
+      }
+      for (; k < w; ++k) {
+        const int64_t e = e0 + (int64_t)k * 64;
+        const int64_t jj = su_col[e];
+        const T mm = uM[e], ll = uL[e];
+#pragma unroll
+        for (int q = 0; q < DR; ++q) {
+          const T v = x[jj * DR + q];
+          am[q] += mm * v;
+          al[q] += ll * v;
+        }
+      }
+    }
+    {
+      const int w = sb_w[sl];
+      const int64_t e0 = sb_off[sl] + lane;
+      for (int k = 0; k < w; ++k) {
+        const int64_t e = e0 + (int64_t)k * 64;
+        const T* xp = x + offV + (int64_t)sb_col[e] * R;
+        T pv[R];
+#pragma unroll
+        for (int t = 0; t < R; ++t) pv[t] = xp[t];
+#pragma unroll
+        for (int c = 0; c < D; ++c) {
+          const T bv = uB[e * D + c];
+#pragma unroll
+          for (int t = 0; t < R; ++t) al[c * R + t] += bv * pv[t];
+        }
+      }
+    }
+    if (row < nfree) {
+#pragma unroll
+      for (int c = 0; c < D; ++c)
+#pragma unroll
+        for (int s = 0; s < R; ++s) {
+          T acc = am[c * R + s];
+#pragma unroll
+          for (int t = 0; t < R; ++t) acc += dtA.v[s * R + t] * al[c * R + t];
+          const int64_t o = row * DR + c * R + s;
+          y[o] = F ? F[o] - acc : acc;
+        }
+    }
+  } else if (sl < nsu + nsp) {
+    const int64_t ps = sl - nsu;
+    const int64_t v = ps * 64 + lane;
+    T a[R];
+#pragma unroll
+    for (int t = 0; t < R; ++t) a[t] = T(0);
+    const int w = sp_w[ps];
+    const int64_t e0 = sp_off[ps] + lane;
+    int k = 0;
+    for (; k + kSellUnroll <= w; k += kSellUnroll) {
+      int32_t j[kSellUnroll];
+      T xv[kSellUnroll][DR];
+#pragma unroll
+      for (int u = 0; u < kSellUnroll; ++u) j[u] = sp_col[e0 + (int64_t)(k + u) * 64];
+#pragma unroll
+      for (int u = 0; u < kSellUnroll; ++u)
+#pragma unroll
+        for (int q = 0; q < DR; ++q) xv[u][q] = x[(int64_t)j[u] * DR + q];
+#pragma unroll
+      for (int u = 0; u < kSellUnroll; ++u) {
+        const int64_t e = e0 + (int64_t)(k + u) * 64;
+#pragma unroll
+        for (int c = 0; c < D; ++c) {
+          const T bv = pBt[e * D + c];
+#pragma unroll
+          for (int t = 0; t < R; ++t) a[t] += bv * xv[u][c * R + t];
+        }
+      }
+    }
+    for (; k < w; ++k) {
+      const int64_t e = e0 + (int64_t)k * 64;
+      const T* xi = x + (int64_t)sp_col[e] * DR;
+#pragma unroll
+      for (int c = 0; c < D; ++c) {
+        const T bv = pBt[e * D + c];
+#pragma unroll
+        for (int t = 0; t < R; ++t) a[t] += bv * xi[c * R + t];
+      }
+    }
+    if (v < nv) {
+#pragma unroll
+      for (int s = 0; s < R; ++s) {
+        T acc = T(0);
+#pragma unroll
+        for (int t = 0; t < R; ++t) acc += dtA.v[s * R + t] * a[t];
+        const int64_t o = offV + v * R + s;
+        y[o] = F ? F[o] - acc : acc;
+      }
+    }
+  }
+}
+
 // ------------------------------------------------------------------ patch factorise
 // One workgroup per patch, matrix in dynamic LDS (row-major n x n).
 template <int D, int R, typename T>
@@ -373,14 +513,14 @@ __global__ __launch_bounds__(kWaves * 64) void k_patch_apply(
     const int32_t* __restrict__ p_ld, const int64_t* __restrict__ p_inv_off,
     const int64_t* __restrict__ p_slot_off, const int32_t* __restrict__ gidx,
     const T* __restrict__ inv, const T* __restrict__ res, const T* __restrict__ W,
-    T* __restrict__ Y, int transpose) {
+    T* __restrict__ Y, int transpose, int D, int R) {
   __shared__ T xs[kWaves][NMAX];
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
   const int64_t idx = (int64_t)blockIdx.x * kWaves + wave;
   if (idx >= npatch) return;  // whole wavefront exits; no workgroup barrier below
   dev::patch_apply_one<T, RB>(sched[idx], lane, xs[wave], p_nloc, p_ld, p_inv_off, p_slot_off, gidx, inv, res,
-                              W, Y, transpose);
+                              W, Y, transpose, D, R);
 }
 
 // Copy eigen-block b of every patch in [p0, p1) from its dense inverse (column-major
@@ -424,7 +564,7 @@ __global__ __launch_bounds__(kWaves * 64) void k_patch_apply_eig(
     const int32_t* __restrict__ p_nloc, const int32_t* __restrict__ p_ld,
     const int64_t* __restrict__ p_inv_off, const int64_t* __restrict__ p_slot_off,
     const int32_t* __restrict__ gidx, const T* __restrict__ inv, const T* __restrict__ res,
-    const T* __restrict__ W, T* __restrict__ Y, int transpose) {
+    const T* __restrict__ W, T* __restrict__ Y, int transpose, int D) {
   __shared__ T xs[kWaves][NMAX];
   __shared__ T xt[kWaves][NMAX];
   const int lane = threadIdx.x & 63;
@@ -434,19 +574,21 @@ __global__ __launch_bounds__(kWaves * 64) void k_patch_apply_eig(
   // columns in flight per lane: fewer for the wide (3D) patches to bound registers
   constexpr int UNROLL = RB >= 4 ? 2 : (RB == 2 ? 4 : 8);
   dev::patch_apply_eig_one<T, RB, UNROLL>(sched[idx], lane, xs[wave], xt[wave], sb, p_nloc, p_ld, p_inv_off,
-                                          p_slot_off, gidx, inv, res, W, Y, transpose);
+                                          p_slot_off, gidx, inv, res, W, Y, transpose, D);
 }
 
 // ------------------------------------------------------------------ gather update
 template <typename T>
-__global__ __launch_bounds__(kBlock) void k_gather_update(int64_t N, const int32_t* __restrict__ gptr,
-                                                          const int32_t* __restrict__ gslot,
+__global__ __launch_bounds__(kBlock) void k_gather_update(int64_t N, int64_t nsl, const int32_t* __restrict__ g_off,
+                                                          const int32_t* __restrict__ g_w,
+                                                          const int32_t* __restrict__ g_slot,
                                                           const T* __restrict__ Y,
                                                           const T* __restrict__ W, T omega,
                                                           int mode, T* __restrict__ x) {
-  const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (g >= N) return;
-  dev::gather_one<T>(g, gptr, gslot, Y, W, omega, mode, x);
+  const int lane = threadIdx.x & 63;
+  const int64_t sl = (int64_t)blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6);
+  if (sl >= nsl) return;
+  dev::gather_sell_one<T>(sl * 64 + lane, sl, lane, g_off, g_w, g_slot, Y, W, omega, mode, x, N);
 }
 
 // ---------------------------------------------------------------------- transfers
@@ -817,11 +959,12 @@ __global__ __launch_bounds__(kBlock) void k_mass_apply(int64_t nfree, int64_t nv
 template <typename T>
 hipError_t residual(const DevLevel& L, const DevOps<T>& ops, const double* A, double dt,
                     const T* F, const T* x, T* y, hipStream_t s) {
-  const int64_t rows = L.nfree + L.nv;
-  const unsigned g = blocks_for(rows);
-  IRK_DISPATCH_DR(L.dim, L.r, (k_residual<DD, RR, T><<<dim3(g), dim3(kBlock), 0, s>>>(L.nfree, L.nv, L.offV, L.s_ptr, L.s_col, ops.s_M, ops.s_L,
-                                                  L.b_ptr, L.b_col, ops.b_val, L.bt_ptr, L.bt_col,
-                                                  ops.bt_val, scaled<T, RR>(A, dt), F, x, y)));
+  const int64_t nsl = L.nsl_u + L.nsl_p;
+  const unsigned g = (unsigned)((nsl + 3) / 4);
+  IRK_DISPATCH_DR(L.dim, L.r, (k_residual_sell<DD, RR, T><<<dim3(g), dim3(256), 0, s>>>(
+                                  L.nfree, L.nv, L.offV, L.nsl_u, L.nsl_p, L.su_off, L.su_w, L.su_col, ops.u_M,
+                                  ops.u_L, L.sb_off, L.sb_w, L.sb_col, ops.u_B, L.sp_off, L.sp_w, L.sp_col,
+                                  ops.p_Bt, scaled<T, RR>(A, dt), F, x, y)));
   return hipGetLastError();
 }
 
@@ -881,7 +1024,7 @@ hipError_t patch_apply(const DevLevel& L, const DevOps<T>& ops, const T* res, T*
 #define IRK_PAE(RBV, NM)                                                                            \
   k_patch_apply_eig<T, RBV, NM><<<dim3(g), dim3(kWaves * 64), 0, s>>>(L.npatch, sb, L.sched, L.p_nloc, \
                                                                    L.p_ld, L.p_inv_off, L.p_slot_off,  \
-                                                                   L.p_gidx, inv, res, W, Y, transpose)
+                                                                   L.p_gidx, inv, res, W, Y, transpose, L.dim)
     if (L.max_nloc <= 128 && rbe <= 1) IRK_PAE(1, 128);
     else if (L.max_nloc <= 256 && rbe <= 2) IRK_PAE(2, 256);
     else if (L.max_nloc <= 512 && rbe <= 2) IRK_PAE(2, 512);
@@ -896,7 +1039,7 @@ hipError_t patch_apply(const DevLevel& L, const DevOps<T>& ops, const T* res, T*
 #define IRK_PA(RBV, NM)                                                                        \
   k_patch_apply<T, RBV, NM><<<dim3(g), dim3(kWaves * 64), 0, s>>>(L.npatch,  \
                      L.sched, L.p_nloc, L.p_ld, L.p_inv_off, L.p_slot_off, L.p_gidx, inv, res, \
-                     W, Y, transpose)
+                     W, Y, transpose, L.dim, L.r)
   if (L.max_nloc <= 128) {
     if (rb == 1) IRK_PA(1, 128); else IRK_PA(2, 128);
   } else if (L.max_nloc <= 256) {
@@ -915,8 +1058,8 @@ hipError_t patch_apply(const DevLevel& L, const DevOps<T>& ops, const T* res, T*
 template <typename T>
 hipError_t gather_update(const DevLevel& L, const DevOps<T>& ops, const T* Y, T* x, T omega,
                          int mode, hipStream_t s) {
-  k_gather_update<T><<<dim3(blocks_for(L.N)), dim3(kBlock), 0, s>>>(L.N,
-                     L.gat_ptr, L.gat_slot, Y, ops.W, omega, mode, x);
+  k_gather_update<T><<<dim3(blocks_for(L.nsl_g, kBlock / 64)), dim3(kBlock), 0, s>>>(
+      L.N, L.nsl_g, L.g_off, L.g_w, L.g_slot, Y, ops.W, omega, mode, x);
   return hipGetLastError();
 }
 

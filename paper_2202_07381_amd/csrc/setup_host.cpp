@@ -10,6 +10,7 @@
 // grad lam_k, so the reference tensors below depend on nothing but the dimension.
 #include <algorithm>
 #include <array>
+#include <climits>
 #include <complex>
 #include <cmath>
 #include <cstring>
@@ -851,5 +852,46 @@ bool stage_eigenbasis(const double* A, int r, StageEig& out, std::string* why) {
   out.recon = err;
   if (!(err <= 1e-13 * scale * std::max(1.0, out.cond))) return fail("eigen-decomposition check failed");
   return true;
+}
+}  // namespace irk
+
+// ---------------------------------------------------------------- sliced operators
+namespace irk {
+Sell build_sell(int64_t nrows, const std::vector<int32_t>& ptr, const std::vector<int32_t>& col) {
+  Sell S;
+  S.nslices = (nrows + 63) / 64;
+  S.off.resize(S.nslices + 1);
+  S.w.resize(S.nslices);
+  int64_t total = 0;
+  for (int64_t sl = 0; sl < S.nslices; ++sl) {
+    int w = 0;
+    for (int64_t row = sl * 64; row < std::min(nrows, sl * 64 + 64); ++row) w = std::max(w, ptr[row + 1] - ptr[row]);
+    S.w[sl] = w;
+    S.off[sl] = (int32_t)total;
+    total += (int64_t)w * 64;
+    if (total > INT32_MAX) throw std::runtime_error("operator too large for 32-bit sliced offsets");
+  }
+  S.off[S.nslices] = (int32_t)total;
+  S.col.assign(total, 0);
+  S.src.assign(total, -1);
+  for (int64_t sl = 0; sl < S.nslices; ++sl)
+    for (int lane = 0; lane < 64; ++lane) {
+      const int64_t row = sl * 64 + lane;
+      if (row >= nrows) continue;
+      for (int32_t p = ptr[row]; p < ptr[row + 1]; ++p) {
+        const int64_t e = S.off[sl] + (int64_t)(p - ptr[row]) * 64 + lane;
+        S.col[e] = col[p];
+        S.src[e] = p;
+      }
+    }
+  return S;
+}
+
+std::vector<double> sell_values(const Sell& S, const std::vector<double>& v, int k) {
+  std::vector<double> out(S.src.size() * k, 0.0);
+  for (size_t e = 0; e < S.src.size(); ++e)
+    if (S.src[e] >= 0)
+      for (int c = 0; c < k; ++c) out[e * k + c] = v[S.src[e] * k + c];
+  return out;
 }
 }  // namespace irk
