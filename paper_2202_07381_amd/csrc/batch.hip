@@ -211,10 +211,10 @@ __device__ void patches(const BLevel& L, double* xs, double* xt, const double* i
     const int p = L.sched[idx];
     if (L.pform == 1) {
       if (L.rb == 1)
-        dev::patch_apply_eig_one<double, 1, 8>(p, lane, xs, xt, L.sb, L.p_nloc, L.p_ld, L.p_inv_off, L.p_slot_off,
+        dev::patch_apply_eig_one<double, 1, 4, 1>(p, lane, xs, xt, L.sb, L.p_nloc, L.p_ld, L.p_inv_off, L.p_slot_off,
                                                L.p_gidx, L.inv, in, nullptr, L.Y, 0, L.dim);
       else
-        dev::patch_apply_eig_one<double, 2, 4>(p, lane, xs, xt, L.sb, L.p_nloc, L.p_ld, L.p_inv_off, L.p_slot_off,
+        dev::patch_apply_eig_one<double, 2, 4, 1>(p, lane, xs, xt, L.sb, L.p_nloc, L.p_ld, L.p_inv_off, L.p_slot_off,
                                                L.p_gidx, L.inv, in, nullptr, L.Y, 0, L.dim);
       continue;
     }

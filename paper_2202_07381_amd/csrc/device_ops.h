@@ -123,6 +123,32 @@ __device__ inline void vload<float4, float>(const float* p, float* o) {
   o[3] = v.w;
 }
 
+// 16-byte load that bypasses cache retention (the patch factors are streamed once per
+// application and would only evict the gathered vectors)
+template <typename T>
+__device__ inline void vload_nt(const T* p, T* out);
+template <>
+__device__ inline void vload_nt<double>(const double* p, double* o) {
+  typedef double d2 __attribute__((ext_vector_type(2)));
+  const d2 v = __builtin_nontemporal_load(reinterpret_cast<const d2*>(p));
+  o[0] = v.x;
+  o[1] = v.y;
+}
+template <>
+__device__ inline void vload_nt<float>(const float* p, float* o) {
+  typedef float f4 __attribute__((ext_vector_type(4)));
+  const f4 v = __builtin_nontemporal_load(reinterpret_cast<const f4*>(p));
+  o[0] = v.x;
+  o[1] = v.y;
+  o[2] = v.z;
+  o[3] = v.w;
+}
+template <typename T, int NT>
+__device__ __forceinline__ void vload_s(const T* p, T* o) {
+  if constexpr (NT) vload_nt<T>(p, o);
+  else vload<typename Vec16<T>::type, T>(p, o);
+}
+
 // Output slot of local index e of a patch (stage-major: e = s ns + q with q = c nn + a
 // for velocity component c of patch node a, q = D nn for the pressure) in the patch's
 // node-major output order ((a D + c) R + s, pressure nn D R + s), so that the D R values
@@ -141,7 +167,7 @@ __device__ __forceinline__ int node_major_slot(int e, int ns, int D, int R) {
 // [rb*64*VEC + l*VEC, +VEC) of row block rb.  Non-transposed: y = Ainv x streams
 // column j with one 16-byte load per lane; transposed: y_j = column_j . x with a wave
 // reduction per column.  xs is this wavefront's LDS staging area (>= n values).
-template <typename T, int RB, int UNROLL = 4>
+template <typename T, int RB, int UNROLL = 4, int NT = 1>
 __device__ __forceinline__ void patch_apply_one(
     int p, int lane, T* xs, const int32_t* __restrict__ p_nloc, const int32_t* __restrict__ p_ld,
     const int64_t* __restrict__ p_inv_off, const int64_t* __restrict__ p_slot_off,
@@ -175,7 +201,7 @@ __device__ __forceinline__ void patch_apply_one(
 #pragma unroll
         for (int b = 0; b < RB; ++b) {
           const int r0 = b * 64 * VEC + lane * VEC;
-          if (r0 < n) vload<VT, T>(Ap + (int64_t)(j + u) * ld + r0, a[u][b]);
+          if (r0 < n) vload_s<T, NT>(Ap + (int64_t)(j + u) * ld + r0, a[u][b]);
           else
 #pragma unroll
             for (int v = 0; v < VEC; ++v) a[u][b][v] = T(0);
@@ -196,7 +222,7 @@ __device__ __forceinline__ void patch_apply_one(
         const int r0 = b * 64 * VEC + lane * VEC;
         if (r0 < n) {
           T a[VEC];
-          vload<VT, T>(Ap + (int64_t)j * ld + r0, a);
+          vload_s<T, NT>(Ap + (int64_t)j * ld + r0, a);
 #pragma unroll
           for (int v = 0; v < VEC; ++v) acc[b][v] += a[v] * xj;
         }
@@ -261,7 +287,7 @@ __device__ __forceinline__ int eig_chunk_block(const irk::StageBasis<T>& sb, int
   return -1;
 }
 
-template <typename T, int RB, int UNROLL = 8>
+template <typename T, int RB, int UNROLL = 8, int NT = 0>
 __device__ __forceinline__ void patch_apply_eig_one(
     int p, int lane, T* xs, T* xt, const irk::StageBasis<T>& sb, const int32_t* __restrict__ p_nloc,
     const int32_t* __restrict__ p_ld, const int64_t* __restrict__ p_inv_off,
@@ -315,7 +341,7 @@ __device__ __forceinline__ void patch_apply_eig_one(
       for (int u = 0; u < UNROLL; ++u)
 #pragma unroll
         for (int b = 0; b < RB; ++b) {
-          if (blk[b] >= 0) vload<VT, T>(Ap + (int64_t)(j + u) * lc + b * 64 * VEC + lane * VEC, a[u][b]);
+          if (blk[b] >= 0) vload_s<T, NT>(Ap + (int64_t)(j + u) * lc + b * 64 * VEC + lane * VEC, a[u][b]);
           else
 #pragma unroll
             for (int v = 0; v < VEC; ++v) a[u][b][v] = T(0);
@@ -338,7 +364,7 @@ __device__ __forceinline__ void patch_apply_eig_one(
       for (int b = 0; b < RB; ++b) {
         if (blk[b] < 0) continue;
         T a[VEC];
-        vload<VT, T>(Ap + (int64_t)j * lc + b * 64 * VEC + lane * VEC, a);
+        vload_s<T, NT>(Ap + (int64_t)j * lc + b * 64 * VEC + lane * VEC, a);
         const T xu = xt[iu[b] + j];
         const T xv = iv[b] >= 0 ? xt[iv[b] + j] : T(0);
 #pragma unroll

@@ -46,7 +46,9 @@ irk_status dalloc(Handle* h, T** p, size_t n) {
   *p = nullptr;
   if (n == 0) n = 1;
   hipError_t e = hipMalloc((void**)p, n * sizeof(T));
-  if (e != hipSuccess) return fail(IRK_ENOMEM, "hipMalloc of " + std::to_string(n * sizeof(T)) + " bytes failed");
+  if (e != hipSuccess)
+    return fail(e == hipErrorOutOfMemory ? IRK_ENOMEM : IRK_EHIP,
+                "hipMalloc of " + std::to_string(n * sizeof(T)) + " bytes failed: " + hipGetErrorName(e));
   h->allocations.push_back(*p);
   return IRK_OK;
 }

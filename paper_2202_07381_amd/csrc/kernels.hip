@@ -558,23 +558,21 @@ __global__ __launch_bounds__(kBlock) void k_eig_extract(
   }
 }
 
-template <typename T, int RB, int NMAX>
-__global__ __launch_bounds__(kWaves * 64) void k_patch_apply_eig(
+template <typename T, int RB, int NMAX, int UNROLL, int NT, int WAVES, int WPE = 1>
+__global__ __launch_bounds__(WAVES * 64) __attribute__((amdgpu_waves_per_eu(WPE))) void k_patch_apply_eig(
     int64_t npatch, irk::StageBasis<T> sb, const int32_t* __restrict__ sched,
     const int32_t* __restrict__ p_nloc, const int32_t* __restrict__ p_ld,
     const int64_t* __restrict__ p_inv_off, const int64_t* __restrict__ p_slot_off,
     const int32_t* __restrict__ gidx, const T* __restrict__ inv, const T* __restrict__ res,
     const T* __restrict__ W, T* __restrict__ Y, int transpose, int D) {
-  __shared__ T xs[kWaves][NMAX];
-  __shared__ T xt[kWaves][NMAX];
+  __shared__ T xs[WAVES][NMAX];
+  __shared__ T xt[WAVES][NMAX];
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
-  const int64_t idx = (int64_t)blockIdx.x * kWaves + wave;
+  const int64_t idx = (int64_t)blockIdx.x * WAVES + wave;
   if (idx >= npatch) return;  // whole wavefront exits; no workgroup barrier below
-  // columns in flight per lane: fewer for the wide (3D) patches to bound registers
-  constexpr int UNROLL = RB >= 4 ? 2 : (RB == 2 ? 4 : 8);
-  dev::patch_apply_eig_one<T, RB, UNROLL>(sched[idx], lane, xs[wave], xt[wave], sb, p_nloc, p_ld, p_inv_off,
-                                          p_slot_off, gidx, inv, res, W, Y, transpose, D);
+  dev::patch_apply_eig_one<T, RB, UNROLL, NT>(sched[idx], lane, xs[wave], xt[wave], sb, p_nloc, p_ld, p_inv_off,
+                                              p_slot_off, gidx, inv, res, W, Y, transpose, D);
 }
 
 // ------------------------------------------------------------------ gather update
@@ -1021,16 +1019,18 @@ hipError_t patch_apply(const DevLevel& L, const DevOps<T>& ops, const T* res, T*
   if (L.pform == 1) {
     const StageBasis<T>& sb = basis_of<T>(L);
     const int rbe = (L.max_ld + rows_per_block - 1) / rows_per_block;
-#define IRK_PAE(RBV, NM)                                                                            \
-  k_patch_apply_eig<T, RBV, NM><<<dim3(g), dim3(kWaves * 64), 0, s>>>(L.npatch, sb, L.sched, L.p_nloc, \
-                                                                   L.p_ld, L.p_inv_off, L.p_slot_off,  \
-                                                                   L.p_gidx, inv, res, W, Y, transpose, L.dim)
-    if (L.max_nloc <= 128 && rbe <= 1) IRK_PAE(1, 128);
-    else if (L.max_nloc <= 256 && rbe <= 2) IRK_PAE(2, 256);
-    else if (L.max_nloc <= 512 && rbe <= 2) IRK_PAE(2, 512);
-    else if (L.max_nloc <= 512 && rbe <= 4) IRK_PAE(4, 512);
-    else if (L.max_nloc <= 1024 && rbe <= 4) IRK_PAE(4, 1024);
-    else if (L.max_nloc <= 1024 && rbe <= 8) IRK_PAE(8, 1024);
+#define IRK_PAE(RBV, NM, U, NT, WV, ...)                                                              \
+  k_patch_apply_eig<T, RBV, NM, U, NT, WV, ##__VA_ARGS__><<<dim3(blocks_for(L.npatch, WV)), dim3(WV * 64), 0, s>>>( \
+      L.npatch, sb, L.sched, L.p_nloc, L.p_ld, L.p_inv_off, L.p_slot_off, L.p_gidx, inv, res, W, Y,  \
+      transpose, L.dim)
+    // 4 columns in flight per lane with non-temporal loads: at 62 VGPRs the 2D kernel
+    // runs 8 waves per SIMD; deeper unrolling lowered occupancy and measured slower
+    if (L.max_nloc <= 128 && rbe <= 1) IRK_PAE(1, 128, 4, 1, 4);
+    else if (L.max_nloc <= 256 && rbe <= 2) IRK_PAE(2, 256, 4, 1, 4);
+    else if (L.max_nloc <= 512 && rbe <= 2) IRK_PAE(2, 512, 4, 1, 4);
+    else if (L.max_nloc <= 512 && rbe <= 4) IRK_PAE(4, 512, 2, 1, 4);
+    else if (L.max_nloc <= 1024 && rbe <= 4) IRK_PAE(4, 1024, 2, 1, 4);
+    else if (L.max_nloc <= 1024 && rbe <= 8) IRK_PAE(8, 1024, 2, 1, 4);
     else return hipErrorInvalidValue;
 #undef IRK_PAE
     return hipGetLastError();

@@ -13,6 +13,14 @@ import re
 
 import numpy as np
 
+# torch is imported before libirkmg.so is loaded: torch ships its own HIP runtime under
+# the same soname (libamdhip64.so.7) but links it by another name, so loading
+# libirkmg.so first (which resolves ROCm's copy) would put two HIP and HSA runtimes in
+# one process and leave the GPU unusable (hipErrorNoDevice).  Loaded in this order, the
+# library binds to the runtime torch already holds and both share its device pointers
+# and streams.
+import torch  # noqa: F401,E402
+
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libirkmg.so")
 HEADER = os.path.join(os.path.dirname(_HERE), "include", "irk_mg.h")
