@@ -151,6 +151,88 @@ def cpu_baseline(A, dt, nu):
             "vcycle_s": dtv}
 
 
+# ------------------------------------------------------------ HBM traffic (PMC)
+TRAFFIC_RECORD = os.path.join(ROOT, "profiles", "patch_apply_traffic_stokes256_radau3.md")
+KERNEL_SOURCES = [os.path.join(ROOT, "paper_2202_07381_amd", "csrc", f) for f in ("device_ops.h", "kernels.hip")]
+CALIB_ELEMS = 1 << 27  # doubles per calibration copy (1 GiB read + 1 GiB written)
+
+
+def kernel_source_hash() -> str:
+    import hashlib
+
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        h.update(open(f, "rb").read())
+    return h.hexdigest()[:16]
+
+
+def calibration_copies():
+    """Plain elementwise copies of known size for scaling the FETCH/WRITE counters."""
+    import torch
+
+    src = torch.ones(CALIB_ELEMS, dtype=torch.float64, device="cuda")
+    dst = torch.empty_like(src)
+    for _ in range(3):
+        torch.neg(src, out=dst)
+    torch.cuda.synchronize()
+    log(f"calibration copies done: 3 x {CALIB_ELEMS * 8} bytes read and written")
+
+
+def _pmc_rows(d, counter):
+    import csv
+    import glob
+
+    out = {}
+    for f in glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True):
+        for r in csv.DictReader(open(f)):
+            if r.get("Counter_Name") != counter:
+                continue
+            key = (r["Kernel_Name"], int(r.get("Grid_Size") or 0))
+            out.setdefault(key, []).append(float(r["Counter_Value"]))
+    return out
+
+
+def summarize_pmc(fetch_dir, write_dir):
+    """Per-launch HBM bytes of the finest-level patch apply from two rocprofv3 --pmc
+    runs (FETCH_SIZE, WRITE_SIZE; KiB per dispatch), each scaled by what the same
+    counter reads for the calibration copies (CALIB_ELEMS doubles in and out)."""
+    res = {}
+    for name, d, counter in (("fetch", fetch_dir, "FETCH_SIZE"), ("write", write_dir, "WRITE_SIZE")):
+        rows = _pmc_rows(d, counter)
+        cal = [v for (k, g), vals in rows.items() if "neg_kernel" in k for v in vals]
+        pa = {(k, g): vals for (k, g), vals in rows.items() if "k_patch_apply_eig<double, 1, 128" in k}
+        if not cal or not pa:
+            raise SystemExit(f"{counter}: calibration or patch-apply dispatches missing in {d}")
+        ideal_kib = CALIB_ELEMS * 8 / 1024.0
+        scale = ideal_kib / (sum(cal) / len(cal))
+        key = max(pa, key=lambda kg: kg[1])  # finest level: largest grid
+        vals = pa[key]
+        res[name] = dict(counter=counter, calib_measured_kib=sum(cal) / len(cal), calib_ideal_kib=ideal_kib,
+                         scale=scale, dispatches=len(vals), grid=key[1],
+                         raw_kib_per_launch=sum(vals) / len(vals),
+                         bytes_per_launch=scale * 1024.0 * sum(vals) / len(vals))
+    rec = {"kernel_source_sha256_16": kernel_source_hash(), "kernel": "k_patch_apply_eig<double, 1, 128> finest level",
+           "traffic_bytes_per_launch": res["fetch"]["bytes_per_launch"] + res["write"]["bytes_per_launch"],
+           "fetch": res["fetch"], "write": res["write"]}
+    print("traffic-record: " + json.dumps(rec))
+
+
+def stored_traffic():
+    """Calibrated HBM bytes per finest-level patch-apply launch from the committed PMC
+    summary, or None when the kernel sources changed since the counters were taken."""
+    try:
+        for line in open(TRAFFIC_RECORD):
+            if line.startswith("traffic-record: "):
+                rec = json.loads(line[len("traffic-record: "):])
+                if rec.get("kernel_source_sha256_16") == kernel_source_hash():
+                    return rec["traffic_bytes_per_launch"]
+                log("kernel sources changed since the PMC counters were taken: traffic = null")
+                return None
+    except OSError:
+        pass
+    return None
+
+
 def run_batch(count, log_every=8):
     """Uneven batch of independent solves: one persistent launch versus the same
     solves one after another with the one-launch-per-step path."""
@@ -242,10 +324,17 @@ def main():
     ap.add_argument("--workload", default="stokes256", choices=["stokes256", "batch64"],
                     help="stokes256: the headline line; batch64: the uneven batched workload")
     ap.add_argument("--batch-count", type=int, default=64)
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="also run plain copies of known size (for scaling PMC byte counters)")
+    ap.add_argument("--summarize-pmc", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
+                    help="print the traffic record from two rocprofv3 --pmc output directories and exit")
     args = ap.parse_args()
+    if args.summarize_pmc:
+        summarize_pmc(*args.summarize_pmc)
+        return
     if args.gpus != 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path "
-              "(the sharding design is described in DESIGN.md); run with --gpus 1.", file=sys.stderr)
+        print("bench.py measures one GPU: the library has no multi-GPU path "
+              "(one process per GPU, sharded by subdomain, is the design); run with --gpus 1.", file=sys.stderr)
         sys.exit(2)
     import numpy as np
     import torch
@@ -296,7 +385,7 @@ def main():
         "setup_s": r64["setup_s"],
         "roofline": {
             "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+            "frac": achieved / HBM_PEAK_GBS, "traffic": stored_traffic(),
             "kernel": "patch_apply (finest level)", "avg_launch_ms": avg_ms, "launches": st["launches"],
             "bytes_per_launch": st["bytes_per_launch"],
         },
@@ -317,6 +406,8 @@ def main():
             "state_rel_diff_vs_fp64": diff,
             "patch_apply_GB/s": s32["bytes_per_launch"] / (ms32 * 1e-3) / 1e9,
         }
+    if args.calibrate_copy:
+        calibration_copies()
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(A, dt, nu)
     print(json.dumps(line), flush=True)
