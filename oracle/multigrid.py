@@ -4,9 +4,9 @@ TEST INFRASTRUCTURE ONLY (oracle).
 
 Hierarchy from uniform refinement; coarse operators by rediscretisation (assembly of
 the stage system on every level, Sec. 4.1); interpolation I_r (x) P, restriction its
-transpose; additive Vanka relaxation with `pre` and `post` sweeps (Sec. 5.1 uses 2 and
-2); direct solve on the coarsest level (Sec. 4.1 uses a sparse direct solver; here a
-dense LU with partial pivoting).
+transpose; additive Vanka relaxation with `pre` and `post` sweeps or Chebyshev
+steps (Sec. 5.1 uses 2 and 2); direct solve on the coarsest level (Sec. 4.1 uses a
+sparse direct solver; here a dense LU with partial pivoting).
 
 Readings where the paper is silent:
   * cycle shape: on each level, pre-sweeps from a zero guess, residual, restrict,
@@ -39,12 +39,17 @@ from .vanka import VankaSmoother, patch_dofs
 
 class Hierarchy:
     def __init__(self, mesh_levels, A, dt, nu, wind=None, omega=0.5, weighted=True, pre=2, post=2,
-                 dtype=np.float64):
+                 dtype=np.float64, smoother="sweep", interval=(2.0, 8.0)):
         """mesh_levels: coarse-to-fine sequence of objects with .xyz and .cells.
-        wind: callable (points, t) -> (npts, dim) or None (Stokes)."""
+        wind: callable (points, t) -> (npts, dim) or None (Stokes).
+        smoother: "sweep" (damped additive sweeps, omega and weighting) or "chebyshev"
+        (Chebyshev relaxation on `interval` with the additive operator, Sec. 5.1)."""
         self.A = np.asarray(A, dtype=np.float64)
         self.r = self.A.shape[0]
         self.pre, self.post = pre, post
+        if smoother not in ("sweep", "chebyshev"):
+            raise ValueError("smoother must be 'sweep' or 'chebyshev'")
+        self.smoother, self.interval = smoother, (float(interval[0]), float(interval[1]))
         self.dtype = dtype
         self.spaces = [TaylorHood(m.xyz, m.cells) for m in mesh_levels]
         self.systems = []
@@ -89,12 +94,16 @@ class Hierarchy:
         sm = self.smoothers[lev]
         npre, npost = (self.post, self.pre) if transpose else (self.pre, self.post)
         x = np.zeros_like(b)
-        for _ in range(npre):
-            x = sm.sweep(b, x, Jop, transpose)
+        x = self._relax(sm, b, x, Jop, npre, transpose)
         res = b - Jop @ x
         bc = self.Pw[lev].T @ res
         x = x + self.Pw[lev] @ self._cycle(lev - 1, bc, transpose)
-        for _ in range(npost):
+        return self._relax(sm, b, x, Jop, npost, transpose)
+
+    def _relax(self, sm, b, x, Jop, steps, transpose):
+        if self.smoother == "chebyshev":
+            return sm.chebyshev(b, x, Jop, steps, *self.interval, transpose) if steps > 0 else x
+        for _ in range(steps):
             x = sm.sweep(b, x, Jop, transpose)
         return x
 

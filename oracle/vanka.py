@@ -15,9 +15,22 @@ DOF (a partition of unity), because the undamped operator has eigenvalues up to 
 overlap count (about 7 in 2D) and omega = 0.5 alone then amplifies the top modes.
 The transposed sweep (for adjoint solves) uses omega * sum_v R_v^T A_v^{-T} R_v W.
 
+Chebyshev relaxation (Sec. 5.1): the paper accelerates the undamped additive operator
+S = sum_v R_v^T A_v^{-1} R_v with Chebyshev polynomials of the first kind on a fixed
+interval [lo, hi] of the spectrum of S J ([2, 8] for its 2D Stokes runs).  The steps
+follow the classical Chebyshev semi-iteration: with theta = (hi + lo)/2,
+delta = (hi - lo)/2, sigma = theta/delta and r_j = F - J k_j,
+    d_0 = S r_0 / theta,                 rho_0 = 1/sigma,
+    rho_j = 1/(2 sigma - rho_{j-1}),     d_j = rho_j rho_{j-1} d_{j-1} + (2 rho_j/delta) S r_j,
+    k_{j+1} = k_j + d_j,
+so that after m steps the error is T_m((theta - S J)/delta) / T_m(theta/delta) times
+the initial error (T_m the Chebyshev polynomial of the first kind).  The transposed
+relaxation (adjoint) is the same recurrence with J^T and S^T.
+
 Pinned by tests/test_oracle_vanka.py against: Fig. 1's patch (19 velocity nodes and
 one pressure node for an interior vertex); the DOF cover; single-patch exactness
-(R_v^T A_v^{-1} R_v J e = e for e supported on S_v); multiplicity bounds.
+(R_v^T A_v^{-1} R_v J e = e for e supported on S_v); multiplicity bounds; the
+Chebyshev error polynomial in closed form on a diagonal operator.
 """
 from __future__ import annotations
 
@@ -84,6 +97,20 @@ class VankaSmoother:
             np.add.at(out, idx, np.einsum(sub, inv, loc))
         return out
 
+    def apply_S(self, res: np.ndarray, transpose: bool = False) -> np.ndarray:
+        """The (weighted) additive operator W sum_v R_v^T A_v^{-1} R_v, or its transpose."""
+        W = self.W.astype(self.dtype)
+        if transpose:
+            return self.patch_sum(W * res, transpose=True)
+        return W * self.patch_sum(res)
+
+    def chebyshev(self, F: np.ndarray, k: np.ndarray, Jop, steps: int, lo: float, hi: float,
+                  transpose: bool = False) -> np.ndarray:
+        """Chebyshev relaxation (Sec. 5.1) on [lo, hi] with the additive operator; Jop is
+        J (or J^T for the transposed relaxation) in the working precision."""
+        return chebyshev_iteration(lambda x: Jop @ x, lambda r: self.apply_S(r, transpose), F, k, steps, lo, hi,
+                                   self.dtype)
+
     def sweep(self, F: np.ndarray, k: np.ndarray, Jop, transpose: bool = False) -> np.ndarray:
         """One additive sweep on k, returning the new k.  Jop is the level operator in
         the working precision (J itself, or J^T for the transposed smoother)."""
@@ -92,3 +119,24 @@ class VankaSmoother:
         if transpose:
             return k + self.dtype(self.omega) * self.patch_sum(W * res, transpose=True)
         return k + self.dtype(self.omega) * (W * self.patch_sum(res))
+
+
+def chebyshev_iteration(apply_J, apply_S, F, k, steps: int, lo: float, hi: float, dtype=np.float64):
+    """`steps` Chebyshev-accelerated steps for J k = F preconditioned by S, for the
+    spectrum interval [lo, hi] of S J (recurrence in the module docstring)."""
+    theta, delta = 0.5 * (hi + lo), 0.5 * (hi - lo)
+    sigma = theta / delta
+    k = np.array(k, dtype=dtype)
+    d = None
+    rho = None
+    for j in range(steps):
+        z = apply_S(np.asarray(F, dtype=dtype) - apply_J(k))
+        if j == 0:
+            rho = 1.0 / sigma
+            d = dtype(1.0 / theta) * z
+        else:
+            rho_new = 1.0 / (2.0 * sigma - rho)
+            d = dtype(rho_new * rho) * d + dtype(2.0 * rho_new / delta) * z
+            rho = rho_new
+        k = k + d
+    return k

@@ -85,3 +85,51 @@ def test_mixed_precision_reaches_fp64_tolerance():
     H64, _, _ = _setup()
     x64, _ = fgmres(S.apply, H64.vcycle, F, np.zeros_like(F), 1e-8, 100, 30, project=S.project_pressure_mean)
     assert np.linalg.norm(x - x64) / np.linalg.norm(x64) < 1e-6
+
+
+# ------------------------------------------------------------ Chebyshev relaxation
+def test_chebyshev_interval_reading():
+    """The paper's interval [2, 8] follows its own [lambda/4, lambda] rule with lambda the
+    largest eigenvalue of S J, S the undamped additive operator (Sec. 5.1): on the 8x8
+    mesh the spectrum's largest real part is just below 8 and the smallest is the
+    pressure null space's 0."""
+    A, b, c = tableau("radauIIA", 2)
+    H = Hierarchy(wl.square_hierarchy(4, 2), A, 1.0 / 32, 1.0, weighted=False, smoother="chebyshev")
+    J = H.systems[1].J.toarray()
+    SJ = np.column_stack([H.smoothers[1].apply_S(J[:, i]) for i in range(J.shape[0])])
+    ev = np.linalg.eigvals(SJ)
+    assert 7.0 < ev.real.max() < 8.0
+    assert abs(ev.real.min()) < 1e-10
+
+
+@pytest.mark.slow
+def test_chebyshev_mg_mesh_independent():
+    """FGMRES with the Chebyshev-relaxed V-cycle ([2, 8], 2/2 steps, unweighted operator)
+    converges in a mesh-independent number of iterations (Sec. 5.1)."""
+    its = []
+    for nl in (3, 4):
+        A, b, c = tableau("radauIIA", 3)
+        lv = wl.square_hierarchy(4, nl)
+        H = Hierarchy(lv, A, 0.5 / (4 * 2 ** (nl - 1)), 1.0, weighted=False, smoother="chebyshev")
+        S = H.finest
+        f = wl.forcing_2d(1)
+        F = S.rhs([S.th.interpolate(f, 0.0)] * S.r, np.zeros(S.th.nvel), np.zeros(S.th.nverts))
+        x, info = fgmres(S.apply, H.vcycle, F, np.zeros_like(F), 1e-8, 100, 30, project=S.project_pressure_mean)
+        assert info.converged
+        assert np.linalg.norm(F - S.apply(x)) <= 1e-8 * np.linalg.norm(F) * 1.0001
+        its.append(info.iterations)
+    assert max(its) <= 14 and abs(its[0] - its[1]) <= 2
+
+
+def test_chebyshev_vcycle_transpose_dot_product():
+    """The transposed Chebyshev-relaxed V-cycle is the transpose of the V-cycle as a
+    linear map (the adjoint's relaxation is Chebyshev with J^T and S^T)."""
+    A, b, c = tableau("gauss", 2)
+    H = Hierarchy(wl.square_hierarchy(4, 3), A, 5e-3, 0.05, wind=wl.wind_2d(3, 16), weighted=False,
+                  smoother="chebyshev")
+    S = H.finest
+    rng = np.random.default_rng(6)
+    x, y = rng.standard_normal(S.n), rng.standard_normal(S.n)
+    lhs = H.vcycle(x) @ y
+    rhs = x @ H.vcycle_transpose(y)
+    assert abs(lhs - rhs) < 1e-12 * abs(lhs)

@@ -75,3 +75,35 @@ def test_single_patch_exactness():
         # cond(A_v) * eps (forward error of an inverse-based solve)
         cond = np.linalg.cond(S.J[pats[v]][:, pats[v]].toarray())
         assert np.abs(back - e).max() < 16 * cond * np.finfo(float).eps * np.abs(e).max()
+
+
+# ------------------------------------------------------------ Chebyshev relaxation
+def _cheb_T(m, x):
+    """Chebyshev polynomial of the first kind in closed form."""
+    x = np.asarray(x, dtype=float)
+    inside = np.abs(x) <= 1
+    out = np.empty_like(x)
+    out[inside] = np.cos(m * np.arccos(x[inside]))
+    xo = x[~inside]
+    out[~inside] = np.sign(xo) ** m * np.cosh(m * np.arccosh(np.abs(xo)))
+    return out
+
+
+@pytest.mark.parametrize("steps", [1, 2, 3, 5])
+def test_chebyshev_error_polynomial(steps):
+    """On a diagonal S J the error after m steps is T_m((theta - s l)/delta) / T_m(theta/delta)
+    times the initial error, for eigenvalues inside and outside [lo, hi] (Sec. 5.1's
+    relaxation, Chebyshev polynomials of the first kind)."""
+    from oracle.vanka import chebyshev_iteration
+
+    lo, hi = 2.0, 8.0
+    lam = np.array([0.3, 1.0, 2.0, 3.7, 5.0, 6.5, 8.0, 9.5, 12.0])
+    s = np.array([1.0, 0.5, 2.0, 1.0, 0.25, 1.5, 1.0, 0.5, 2.0])
+    sl = s * lam
+    e0 = np.random.default_rng(7).standard_normal(lam.size)
+    xstar = np.random.default_rng(8).standard_normal(lam.size)
+    F = lam * xstar
+    k = chebyshev_iteration(lambda x: lam * x, lambda r: s * r, F, xstar - e0, steps, lo, hi)
+    theta, delta = 0.5 * (hi + lo), 0.5 * (hi - lo)
+    expect = _cheb_T(steps, (theta - sl) / delta) / _cheb_T(steps, np.array([theta / delta]))[0]
+    assert np.allclose((xstar - k) / e0, expect, rtol=1e-12, atol=1e-13)
