@@ -82,7 +82,8 @@ typedef struct irk_tableau {
 } irk_tableau;
 
 /* Solver options.  Defaults (irk_mg_default_opts): 2 pre- and 2 post-sweeps (Sec. 5.1),
- * omega = 0.5, partition-of-unity weighting, FP64, automatic patch form. */
+ * omega = 0.5, partition-of-unity weighting, FP64, automatic patch form, damped
+ * sweeps (Chebyshev interval preset to the paper's [2, 8]). */
 typedef struct irk_mg_opts {
   int pre, post;     /* Vanka sweeps before / after the coarse correction        */
   double omega;      /* damping of the additive sweep (Sec. 4.2)                 */
@@ -99,6 +100,13 @@ typedef struct irk_mg_opts {
                            no well-conditioned real block diagonalisation;
                         2: automatic: 1 when r >= 2 and the decomposition
                            exists, else 0                                       */
+  int smoother;      /* relaxation: 0 = `pre`/`post` damped additive sweeps
+                        k += omega W S r; 1 = `pre`/`post` steps of the Chebyshev
+                        semi-iteration (Sec. 5.1) accelerating W S, S the additive
+                        Vanka operator, for the spectrum interval [cheb_lo,
+                        cheb_hi] of W S J (omega unused; the paper's runs use the
+                        unweighted operator, weighting = 0, on [2, 8])          */
+  double cheb_lo, cheb_hi; /* 0 < cheb_lo < cheb_hi, else IRK_EINVAL            */
 } irk_mg_opts;
 
 /* Per-solve report.  history (host, may be NULL) receives up to history_cap residual

@@ -983,6 +983,7 @@ irk_status irk_batch_create(irk_mg* const* hs, int n, const irk_batch_opts* opts
   for (int q = 0; q < n; ++q) {
     if (!hs[q]) return bfail(IRK_EINVAL, "null handle in the batch");
     if (hs[q]->precision != 0) return bfail(IRK_EINVAL, "the batched solver runs FP64 handles only");
+    if (hs[q]->smoother != 0) return bfail(IRK_EINVAL, "the batched solver runs the damped-sweep smoother only");
     if (hs[q]->dim != 2) return bfail(IRK_EINVAL, "the batched solver runs 2D handles only");
     if (hs[q]->nlevels > kMaxLevels) return bfail(IRK_EINVAL, "too many levels for the batched solver");
     for (int l = 1; l < hs[q]->nlevels; ++l)

@@ -496,6 +496,34 @@ __device__ __forceinline__ void gather_sell_one(int64_t g, int64_t sl, int lane,
   x[g] = (mode & 1) ? x[g] + c : c;
 }
 
+// Chebyshev step of the relaxation for one DOF: with s the sum of its slots,
+// d = c1 d + c2 (W s) (W null: weights already applied to the patch inputs; d not read
+// when first), then x = d (xzero) or x + d.
+template <typename T>
+__device__ __forceinline__ void gather_cheb_one(int64_t g, int64_t sl, int lane, const int32_t* __restrict__ g_off,
+                                                const int32_t* __restrict__ g_w, const int32_t* __restrict__ g_slot,
+                                                const T* __restrict__ Y, const T* __restrict__ W, T c1, T c2,
+                                                int first, int xzero, T* __restrict__ d, T* __restrict__ x,
+                                                int64_t N) {
+  const int w = g_w[sl];
+  const int64_t e0 = g_off[sl] + lane;
+  T s = T(0);
+  int k = 0;
+  for (; k + 4 <= w; k += 4) {
+    int32_t q[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) q[u] = g_slot[e0 + (int64_t)(k + u) * 64];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) s += Y[q[u]];
+  }
+  for (; k < w; ++k) s += Y[g_slot[e0 + (int64_t)k * 64]];
+  if (g >= N) return;
+  const T z = W ? W[g] * s : s;
+  const T dn = first ? c2 * z : c1 * d[g] + c2 * z;
+  d[g] = dn;
+  x[g] = xzero ? dn : x[g] + dn;
+}
+
 // One row of a node-chunked CSR product (restriction / prolongation).
 template <int D, int R, typename T>
 __device__ __forceinline__ void spmv_nodes_row(

@@ -197,6 +197,7 @@ struct DevLevel {
 
   // work vectors (internal layout) in the working precision
   void *b = nullptr, *x = nullptr, *res = nullptr, *Y = nullptr;
+  void* dch = nullptr;  // Chebyshev direction vector
 };
 
 struct Handle {
@@ -204,6 +205,8 @@ struct Handle {
   double dt = 0, nu = 0, omega = 0.5;
   int pre = 2, post = 2, weighting = 1;
   int patch_form = 0;  // form in use: 0 dense, 1 stage eigenbasis
+  int smoother = 0;    // 0 damped sweeps, 1 Chebyshev on [cheb_lo, cheb_hi]
+  double cheb_lo = 2.0, cheb_hi = 8.0;
   StageEig eig;
   double A[kMaxStages * kMaxStages] = {0}, At[kMaxStages * kMaxStages] = {0};
   double b[kMaxStages] = {0}, c[kMaxStages] = {0};
@@ -246,6 +249,11 @@ hipError_t patch_apply(const DevLevel& L, const DevOps<T>& ops, const T* res, T*
 template <typename T>
 hipError_t gather_update(const DevLevel& L, const DevOps<T>& ops, const T* Y, T* x, T omega,
                          int mode, hipStream_t s);
+// Chebyshev step: d = c1 d + c2 W sum(slots) (d not read when first; W omitted when
+// transpose), x = d (xzero) or x + d.
+template <typename T>
+hipError_t gather_cheb(const DevLevel& L, const DevOps<T>& ops, const T* Y, T c1, T c2, int first, int xzero,
+                       int transpose, T* d, T* x, hipStream_t s);
 template <typename T>
 hipError_t restrict_(const DevLevel& fine, const DevLevel& coarse, const DevOps<T>& fops,
                      const T* xf, T* xc, hipStream_t s);

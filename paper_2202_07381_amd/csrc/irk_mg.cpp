@@ -154,6 +154,41 @@ irk_status smooth(Handle* h, int l, int nsweeps, bool zero_start, bool tr, hipSt
     ot.s_L = o.s_Lt;
     ot.u_L = o.u_Lt;
   }
+  if (h->smoother == 1) {
+    // Chebyshev relaxation (Sec. 5.1) on [cheb_lo, cheb_hi]: theta, delta, sigma and the
+    // rho recurrence of the Chebyshev semi-iteration, coefficients formed in FP64
+    const double theta = 0.5 * (h->cheb_hi + h->cheb_lo), delta = 0.5 * (h->cheb_hi - h->cheb_lo);
+    const double sigma = theta / delta;
+    double rho = 0.0;
+    T* d = (T*)L.dch;
+    for (int it = 0; it < nsweeps; ++it) {
+      const bool xzero = zero_start && it == 0;
+      const T* r = b;
+      if (!xzero) {
+        const int p0 = prof_begin(h, 1, l, s);
+        HIPCHK(k::residual<T>(L, ot, A, h->dt, b, x, res, s));
+        prof_end(h, p0, s);
+        r = res;
+      }
+      const int p1 = prof_begin(h, 0, l, s);
+      HIPCHK(k::patch_apply<T>(L, o, r, Y, tr ? 1 : 0, s));
+      prof_end(h, p1, s);
+      double c1 = 0.0, c2;
+      if (it == 0) {
+        rho = 1.0 / sigma;
+        c2 = 1.0 / theta;
+      } else {
+        const double rn = 1.0 / (2.0 * sigma - rho);
+        c1 = rn * rho;
+        c2 = 2.0 * rn / delta;
+        rho = rn;
+      }
+      const int p2 = prof_begin(h, 2, l, s);
+      HIPCHK(k::gather_cheb<T>(L, o, Y, (T)c1, (T)c2, it == 0 ? 1 : 0, xzero ? 1 : 0, tr ? 1 : 0, d, x, s));
+      prof_end(h, p2, s);
+    }
+    return IRK_OK;
+  }
   for (int it = 0; it < nsweeps; ++it) {
     const bool first = zero_start && it == 0;
     const T* r = b;
@@ -414,6 +449,9 @@ void irk_mg_default_opts(irk_mg_opts* o) {
   o->weighting = 1;
   o->precision = 0;
   o->patch_form = 2;
+  o->smoother = 0;
+  o->cheb_lo = 2.0;
+  o->cheb_hi = 8.0;
 }
 
 irk_status irk_tableau_builtin(int family, int r, double* A, double* b, double* c) {
@@ -633,6 +671,9 @@ static irk_status setup_impl(const irk_mesh_level* lv, int nlevels, const irk_ta
   h->omega = o.omega;
   h->weighting = o.weighting;
   h->precision = o.precision;
+  h->smoother = o.smoother;
+  h->cheb_lo = o.cheb_lo;
+  h->cheb_hi = o.cheb_hi;
   for (int i = 0; i < r; ++i) {
     h->b[i] = tab->b[i];
     h->c[i] = tab->c[i];
@@ -876,6 +917,10 @@ static irk_status setup_impl(const irk_mesh_level* lv, int nlevels, const irk_ta
       CHK(dalloc(h, &tmp, ((D.slots + 1) * es + 7) / 8));
       HIPCHK(hipMemsetAsync(tmp, 0, (D.slots + 1) * es, s));
       D.Y = tmp;
+      if (h->smoother == 1) {
+        CHK(dalloc(h, &tmp, (D.N * es + 7) / 8));
+        D.dch = tmp;
+      }
       CHK(dalloc(h, &tmp, (D.inv_elems * es + 7) / 8));
       D.inv = tmp;
     }
@@ -949,6 +994,9 @@ irk_status irk_mg_setup(const irk_mesh_level* lv, int nlevels, const irk_tableau
     if (opt->weighting != 0 && opt->weighting != 1) return fail(IRK_EINVAL, "weighting must be 0 or 1");
     if (opt->precision != 0 && opt->precision != 1) return fail(IRK_EINVAL, "precision must be 0 or 1");
     if (opt->patch_form < 0 || opt->patch_form > 2) return fail(IRK_EINVAL, "patch_form must be 0, 1 or 2");
+    if (opt->smoother != 0 && opt->smoother != 1) return fail(IRK_EINVAL, "smoother must be 0 or 1");
+    if (opt->smoother == 1 && !(opt->cheb_lo > 0 && opt->cheb_hi > opt->cheb_lo && std::isfinite(opt->cheb_hi)))
+      return fail(IRK_EINVAL, "Chebyshev interval must satisfy 0 < cheb_lo < cheb_hi < inf");
   }
   const int dim = lv[0].dim;
   if (dim != 2 && dim != 3) return fail(IRK_EINVAL, "dim must be 2 or 3");

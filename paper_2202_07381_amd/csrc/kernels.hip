@@ -589,6 +589,18 @@ __global__ __launch_bounds__(kBlock) void k_gather_update(int64_t N, int64_t nsl
   dev::gather_sell_one<T>(sl * 64 + lane, sl, lane, g_off, g_w, g_slot, Y, W, omega, mode, x, N);
 }
 
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_gather_cheb(int64_t N, int64_t nsl, const int32_t* __restrict__ g_off,
+                                                        const int32_t* __restrict__ g_w,
+                                                        const int32_t* __restrict__ g_slot, const T* __restrict__ Y,
+                                                        const T* __restrict__ W, T c1, T c2, int first, int xzero,
+                                                        T* __restrict__ d, T* __restrict__ x) {
+  const int lane = threadIdx.x & 63;
+  const int64_t sl = (int64_t)blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6);
+  if (sl >= nsl) return;
+  dev::gather_cheb_one<T>(sl * 64 + lane, sl, lane, g_off, g_w, g_slot, Y, W, c1, c2, first, xzero, d, x, N);
+}
+
 // ---------------------------------------------------------------------- transfers
 template <int D, int R, typename T>
 __global__ __launch_bounds__(kBlock) void k_spmv_nodes(
@@ -1064,6 +1076,14 @@ hipError_t gather_update(const DevLevel& L, const DevOps<T>& ops, const T* Y, T*
 }
 
 template <typename T>
+hipError_t gather_cheb(const DevLevel& L, const DevOps<T>& ops, const T* Y, T c1, T c2, int first, int xzero,
+                       int transpose, T* d, T* x, hipStream_t s) {
+  k_gather_cheb<T><<<dim3(blocks_for(L.nsl_g, kBlock / 64)), dim3(kBlock), 0, s>>>(
+      L.N, L.nsl_g, L.g_off, L.g_w, L.g_slot, Y, transpose ? nullptr : ops.W, c1, c2, first, xzero, d, x);
+  return hipGetLastError();
+}
+
+template <typename T>
 hipError_t restrict_(const DevLevel& F, const DevLevel& C, const DevOps<T>& fops, const T* xf,
                      T* xc, hipStream_t s) {
   const unsigned g = blocks_for(C.nfree + C.nv);
@@ -1228,6 +1248,8 @@ hipError_t mass_apply(const DevLevel& L, const double* st, double* out, hipStrea
                                      hipStream_t);                                                 \
   template hipError_t patch_apply<T>(const DevLevel&, const DevOps<T>&, const T*, T*, int,      \
                                      hipStream_t);                                              \
+  template hipError_t gather_cheb<T>(const DevLevel&, const DevOps<T>&, const T*, T, T, int, int, int, T*, \
+                                     T*, hipStream_t);                                                  \
   template hipError_t gather_update<T>(const DevLevel&, const DevOps<T>&, const T*, T*, T, int, \
                                        hipStream_t);                                            \
   template hipError_t restrict_<T>(const DevLevel&, const DevLevel&, const DevOps<T>&, const T*, \

@@ -46,7 +46,8 @@ class irk_tableau(C.Structure):
 
 class irk_mg_opts(C.Structure):
     _fields_ = [("pre", C.c_int), ("post", C.c_int), ("omega", C.c_double),
-                ("weighting", C.c_int), ("precision", C.c_int), ("patch_form", C.c_int)]
+                ("weighting", C.c_int), ("precision", C.c_int), ("patch_form", C.c_int),
+                ("smoother", C.c_int), ("cheb_lo", C.c_double), ("cheb_hi", C.c_double)]
 
 
 class irk_solve_info(C.Structure):
@@ -189,7 +190,8 @@ class IrkMG:
     """Handle of one hierarchy (irk_mg_setup ... irk_mg_destroy)."""
 
     def __init__(self, levels, A, b, c, dt: float, nu: float, wind_nodal=None, pre=2, post=2,
-                 omega=0.5, weighting=1, precision=0, patch_form=2, stream=None):
+                 omega=0.5, weighting=1, precision=0, patch_form=2, smoother=0, interval=(2.0, 8.0),
+                 stream=None):
         structs, keep = [], []
         for lv in levels:
             s, k = _mesh_struct(lv)
@@ -200,7 +202,7 @@ class IrkMG:
         self.A, self.b, self.c = A, np.ascontiguousarray(b, dtype=np.float64), np.ascontiguousarray(c, dtype=np.float64)
         self.r = len(self.b)
         tab = irk_tableau(self.r, A.ctypes.data, self.b.ctypes.data, self.c.ctypes.data)
-        opts = irk_mg_opts(pre, post, omega, weighting, precision, patch_form)
+        opts = irk_mg_opts(pre, post, omega, weighting, precision, patch_form, smoother, interval[0], interval[1])
         w = None
         if wind_nodal is not None:
             w = np.ascontiguousarray(wind_nodal, dtype=np.float64)

@@ -53,17 +53,22 @@ def wind_of(case):
 
 
 @functools.lru_cache(maxsize=None)
-def oracle_of(case, dtype=np.float64):
+def oracle_of(case, dtype=np.float64, smoother="sweep"):
+    """Oracle hierarchy; smoother "chebyshev" is the paper's relaxation (unweighted
+    additive operator, interval [2, 8])."""
     dim, nc, nl, fam, r, dt, nu, ws = CASES[case]
     A, b, c = tableau(fam, r)
+    if smoother == "chebyshev":
+        return Hierarchy(levels_of(case), A, dt, nu, wind=wind_of(case), dtype=dtype, weighted=False,
+                         smoother="chebyshev", interval=(2.0, 8.0))
     return Hierarchy(levels_of(case), A, dt, nu, wind=wind_of(case), dtype=dtype)
 
 
 _GPU = {}
 
 
-def gpu_of(case, precision=0, patch_form=2):
-    key = (case, precision, patch_form)
+def gpu_of(case, precision=0, patch_form=2, smoother=0):
+    key = (case, precision, patch_form, smoother)
     if key not in _GPU:
         from paper_2202_07381_amd import irkmg
 
@@ -72,8 +77,10 @@ def gpu_of(case, precision=0, patch_form=2):
         A, b, c = irkmg.irk_tableau_builtin(fam, r)
         wind = wind_of(case)
         wn = wind(irkmg.irk_mesh_p2_nodes(lv[-1])) if wind is not None else None
-        say(f"[setup] case={case} precision={precision} patch_form={patch_form}")
-        _GPU[key] = irkmg.IrkMG(lv, A, b, c, dt, nu, wind_nodal=wn, precision=precision, patch_form=patch_form)
+        say(f"[setup] case={case} precision={precision} patch_form={patch_form} smoother={smoother}")
+        extra = dict(smoother=1, weighting=0, interval=(2.0, 8.0)) if smoother == 1 else {}
+        _GPU[key] = irkmg.IrkMG(lv, A, b, c, dt, nu, wind_nodal=wn, precision=precision, patch_form=patch_form,
+                                **extra)
         say(f"[setup] done case={case} N={_GPU[key].irk_mg_ndofs()} form={_GPU[key].irk_mg_patch_form()}")
     return _GPU[key]
 
