@@ -19,9 +19,19 @@ every velocity boundary node eliminated, J has the null vectors e_i (x) (0, 1_p)
 The reading used throughout: remove each stage's arithmetic pressure mean after every
 preconditioner application and from the final solution.
 
+Prescribed (non-zero) boundary velocities g(t): the paper does not say how they enter
+the stages; the reading here takes the DAE view of Sec. 3.1 and requires every stage
+value to equal the data at its stage time, U_{i,b} = g(t^n + c_i dt) = G_i.  The
+boundary stage derivatives are then k_b = (dt A)^{-1} (G - 1 (x) g(t^n)), and the
+boundary couplings move to the right-hand side: velocity rows get
+-M_fb k_{i,b} - K_fb G_i, divergence rows get -B_b^T G_i (rhs_dirichlet).  The state
+keeps only free velocities; its boundary values are g at the current time.
+
 Pinned by tests/test_oracle_stage.py against: the stage equations written out stage
 by stage as in Sec. 3.1 (a double loop over a_ij) for J and F; the null vectors; a
-dense direct solve.
+dense direct solve; for boundary data, a steady P2-P1 Stokes solution (F vanishes) and
+a solution linear in time (the exact stage derivatives solve J k = F for every
+tableau).
 """
 from __future__ import annotations
 
@@ -40,6 +50,7 @@ class StageSystem:
         self.r = self.A.shape[0]
         self.dt = float(dt)
         self.nu = float(nu)
+        self._wind = wind_nodal
         d = th.dim
         M, K, C, Mfa = th.scalar_matrices(nu, wind_nodal)
         self.Ms, self.Ks, self.Cs, self.Ms_free_all = M, K, C, Mfa
@@ -98,3 +109,34 @@ class StageSystem:
         for i in range(self.r):
             Z[i * self.ns + self.th.nvel:(i + 1) * self.ns, i] = 1.0
         return Z
+
+
+    # ------------------------------------------------------- boundary data terms
+    def _boundary_blocks(self):
+        if getattr(self, "_bnd", None) is None:
+            th = self.th
+            f = th.free
+            bnd = np.setdiff1d(np.arange(th.nnodes), f)
+            Mfull = th.scalar_mass_full()
+            Lfull = self.nu * th._assemble_nodes(th.element_stiffness())
+            if self.Cs is not None:
+                Lfull = Lfull + th._assemble_nodes(th.element_convection(self._wind))
+            Bc = th.divergence_full()
+            self._bnd = (bnd, Mfull[f][:, bnd].tocsr(), Lfull[f][:, bnd].tocsr(),
+                         [B[bnd].T.tocsr() for B in Bc])
+        return self._bnd
+
+    def rhs_dirichlet(self, g_n: np.ndarray, g_stages: list[np.ndarray]) -> np.ndarray:
+        """Terms the boundary data add to F (reading in the module docstring).
+        g_n: (nnodes, dim) data at t^n; g_stages: r arrays (nnodes, dim) at t^n + c_i dt;
+        only boundary-node values are used."""
+        th = self.th
+        bnd, Mfb, Lfb, Btb = self._boundary_blocks()
+        G = np.stack([np.asarray(g)[bnd] for g in g_stages])  # (r, nb, dim)
+        kb = np.einsum("ij,jbc->ibc", np.linalg.inv(self.dt * self.A), G - np.asarray(g_n)[bnd][None])
+        blocks = []
+        for i in range(self.r):
+            vel = np.concatenate([-(Mfb @ kb[i, :, c]) - (Lfb @ G[i, :, c]) for c in range(th.dim)])
+            pre = -sum(Btb[c] @ G[i, :, c] for c in range(th.dim))
+            blocks.append(np.concatenate([vel, pre]))
+        return np.concatenate(blocks)

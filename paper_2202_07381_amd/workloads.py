@@ -85,6 +85,66 @@ def square_hierarchy(n_coarse: int, nlevels: int) -> list[MeshLevel]:
     return levels
 
 
+def crossed_mesh(n: int) -> tuple[np.ndarray, np.ndarray]:
+    """n x n quads of the unit square, each cut into four triangles by a vertex at its
+    centre (the "crossed" mesh of Sec. 5.1).
+
+    Corner vertex (i, j) has index j*(n+1) + i; the centre of quad (i, j) has index
+    (n+1)**2 + j*n + i.  Quad (i, j) gives cells 4*(j*n+i) + 0..3: bottom, right, top,
+    left, each listed counter-clockwise with the centre last.
+    """
+    ii, jj = np.meshgrid(np.arange(n + 1), np.arange(n + 1), indexing="xy")
+    corners = np.stack([ii.ravel() / n, jj.ravel() / n], axis=1)
+    qi, qj = np.meshgrid(np.arange(n), np.arange(n), indexing="xy")
+    centres = np.stack([(qi.ravel() + 0.5) / n, (qj.ravel() + 0.5) / n], axis=1)
+    xyz = np.concatenate([corners, centres]).astype(np.float64)
+    v00 = (qj * (n + 1) + qi).ravel()
+    v10, v01 = v00 + 1, v00 + (n + 1)
+    v11 = v01 + 1
+    c = (n + 1) ** 2 + (qj * n + qi).ravel()
+    cells = np.empty((4 * n * n, 3), dtype=np.int64)
+    cells[0::4] = np.stack([v00, v10, c], axis=1)
+    cells[1::4] = np.stack([v10, v11, c], axis=1)
+    cells[2::4] = np.stack([v11, v01, c], axis=1)
+    cells[3::4] = np.stack([v01, v00, c], axis=1)
+    return xyz, cells
+
+
+def red_refine(xyz: np.ndarray, cells: np.ndarray) -> tuple[np.ndarray, np.ndarray, np.ndarray]:
+    """Uniform (red) refinement of a triangle mesh: every cell [a, b, c] becomes
+    [a, m_ab, m_ca], [m_ab, b, m_bc], [m_ca, m_bc, c], [m_ab, m_bc, m_ca] (children
+    4*cell + 0..3, orientation kept).  Coarse vertices keep their indices; edge midpoints
+    follow in the order of the sorted edge list.  Returns (xyz, cells, parent)."""
+    nv = xyz.shape[0]
+    e = np.concatenate([cells[:, [0, 1]], cells[:, [1, 2]], cells[:, [2, 0]]])
+    key = np.sort(e, axis=1)
+    code = key[:, 0] * nv + key[:, 1]
+    uniq, inv = np.unique(code, return_inverse=True)
+    a, b = uniq // nv, uniq % nv
+    mid = 0.5 * (xyz[a] + xyz[b])
+    nc = cells.shape[0]
+    m_ab, m_bc, m_ca = (nv + inv[:nc]), (nv + inv[nc:2 * nc]), (nv + inv[2 * nc:])
+    c0, c1, c2 = cells[:, 0], cells[:, 1], cells[:, 2]
+    fine = np.empty((4 * nc, 3), dtype=np.int64)
+    fine[0::4] = np.stack([c0, m_ab, m_ca], axis=1)
+    fine[1::4] = np.stack([m_ab, c1, m_bc], axis=1)
+    fine[2::4] = np.stack([m_ca, m_bc, c2], axis=1)
+    fine[3::4] = np.stack([m_ab, m_bc, m_ca], axis=1)
+    parent = np.repeat(np.arange(nc, dtype=np.int64), 4)
+    return np.concatenate([xyz, mid]), fine, parent
+
+
+def crossed_hierarchy(n_coarse: int, nlevels: int) -> list[MeshLevel]:
+    """The crossed n_coarse x n_coarse mesh and nlevels-1 uniform refinements of it
+    (Sec. 5.1 uses n_coarse = 8 and refinement levels l = 5, 6, 7)."""
+    xyz, cells = crossed_mesh(n_coarse)
+    levels = [MeshLevel(2, xyz, cells, None)]
+    for _ in range(nlevels - 1):
+        xyz, cells, parent = red_refine(xyz, cells)
+        levels.append(MeshLevel(2, xyz, cells, parent))
+    return levels
+
+
 # ----------------------------------------------------------------------------- 3D
 _KUHN_PERMS = list(itertools.permutations(range(3)))
 

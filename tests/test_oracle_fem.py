@@ -114,3 +114,44 @@ def test_nested_parent_maps():
                 xi = np.linalg.solve(Jm, (f.xyz[f.cells[:, v]] - x0)[..., None])[..., 0]
                 lam = np.hstack([1 - xi.sum(1, keepdims=True), xi])
                 assert lam.min() > -1e-12
+
+
+# ------------------------------------------------------------------ crossed mesh
+def _crossed_counts(n):
+    V = (n + 1) ** 2 + n * n            # corners + quad centres
+    E = 2 * n * (n + 1) + 4 * n * n     # quad sides + four spokes per quad
+    return V, E
+
+
+@pytest.mark.parametrize("n", [2, 3, 5])
+def test_crossed_mesh_counts(n):
+    """Crossed quads (Sec. 5.1): vertex, P2 node and per-stage DOF counts equal the
+    closed forms; every cell positively oriented; the cells tile the unit square."""
+    xyz, cells = wl.crossed_mesh(n)
+    th = TaylorHood(xyz, cells)
+    V, E = _crossed_counts(n)
+    assert th.nverts == V and th.nnodes == V + E and cells.shape[0] == 4 * n * n
+    assert 2 * th.nnodes + th.nverts == 3 * V + 2 * E
+    p = xyz[cells]
+    area = 0.5 * ((p[:, 1, 0] - p[:, 0, 0]) * (p[:, 2, 1] - p[:, 0, 1])
+                  - (p[:, 2, 0] - p[:, 0, 0]) * (p[:, 1, 1] - p[:, 0, 1]))
+    assert area.min() > 0 and abs(area.sum() - 1.0) < 1e-14
+
+
+def test_crossed_hierarchy_nesting_and_paper_size():
+    """Red refinement of the crossed 8x8 mesh: children inside their parents, counts of
+    the crossed mesh at 8 * 2^l, and 1,182,211 DOFs per stage (Dirichlet included) at
+    l = 5, the paper's "about 1.1 million" (Sec. 5.1)."""
+    lv = wl.crossed_hierarchy(8, 3)
+    for l in range(1, 3):
+        f, c = lv[l], lv[l - 1]
+        cen = f.xyz[f.cells].mean(axis=1)
+        P = c.xyz[c.cells[f.parent]]  # (nc, 3, 2)
+        T = np.stack([P[:, 1] - P[:, 0], P[:, 2] - P[:, 0]], axis=2)
+        lam = np.linalg.solve(T, (cen - P[:, 0])[..., None])[..., 0]
+        assert lam.min() > 0 and (lam.sum(axis=1)).max() < 1
+        V, E = _crossed_counts(8 * 2 ** l)
+        th = TaylorHood(f.xyz, f.cells)
+        assert th.nverts == V and th.nnodes == V + E
+    V, E = _crossed_counts(8 * 2 ** 5)
+    assert 3 * V + 2 * E == 1182211
