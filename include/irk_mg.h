@@ -207,6 +207,20 @@ irk_status irk_adjoint_solve(irk_mg* h, const double* G, double* lam, double rto
  * stage block of the ABI layout, then p). */
 irk_status irk_rhs(irk_mg* h, const double* f, const double* state, double* F, void* stream);
 
+/* Add the terms of prescribed (non-zero) boundary velocities to a right-hand side F
+ * built by irk_rhs (Sec. 3.1 with Dirichlet data g(t); the paper does not say how the
+ * data enter the stages: here every stage value equals the data at its stage time,
+ * U_{i,b} = g(t_n + c_i dt), so the boundary stage derivatives are
+ * k_b = (dt A)^{-1} (G - 1 (x) g(t_n)) and
+ *   velocity rows:   F_i -= M_fb k_{i,b} + L_fb G_i,
+ *   divergence rows: F_i -= B_b^T G_i.)
+ * g_n: device, nnodes x dim (finest-level node numbering, values at t_n); g_stages:
+ * device, r x nnodes x dim (values at t_n + c_i dt); only boundary nodes are read.
+ * F: device, ndofs, ABI layout, updated in place.  The state passed to irk_rhs and
+ * irk_update keeps free velocities only; the boundary values are g at that time.
+ * Errors: IRK_EINVAL (null pointers, singular A), IRK_EHIP. */
+irk_status irk_rhs_dirichlet(irk_mg* h, const double* g_n, const double* g_stages, double* F, void* stream);
+
 /* state += dt * sum_j b_j k_j (the update of Sec. 3.1), state and k as above. */
 irk_status irk_update(irk_mg* h, const double* k, double* state, void* stream);
 

@@ -58,6 +58,10 @@ struct HostLevel {
   // free-row x all-node mass (forcing term of the right-hand side)
   std::vector<int32_t> mfa_ptr, mfa_col;
   std::vector<double> mfa_val;
+  // prescribed boundary velocities (finest level): free rows x boundary nodes (M and L
+  // values) and vertex rows x boundary nodes (B^T, dim values per entry)
+  std::vector<int32_t> fb_ptr, fb_col, vb_ptr, vb_col;
+  std::vector<double> fb_m, fb_l, vb_val;
 
   // vertex-star patches: free nodes of each patch (ascending) and the CSR entries
   // that couple them
@@ -158,6 +162,9 @@ struct DevLevel {
   int32_t *mfat_ptr = nullptr, *mfat_col = nullptr;  // M_fa^T (node rows)
   double* mfat_val = nullptr;
   double* s_K1 = nullptr;
+  int32_t *fb_ptr = nullptr, *fb_col = nullptr, *vb_ptr = nullptr, *vb_col = nullptr;
+  double *fb_m = nullptr, *fb_l = nullptr, *vb_val = nullptr;
+  int64_t nnodes = 0;
   DevOps<double> d64;
   DevOps<float> d32;
   // sliced operator indices (see Sell): velocity slices, then vertex slices
@@ -210,6 +217,8 @@ struct Handle {
   StageEig eig;
   double A[kMaxStages * kMaxStages] = {0}, At[kMaxStages * kMaxStages] = {0};
   double b[kMaxStages] = {0}, c[kMaxStages] = {0};
+  double Ainv_dt[kMaxStages * kMaxStages] = {0};  // (dt A)^{-1}, row-major
+  bool A_invertible = false;
   std::vector<HostLevel> host;
   std::vector<DevLevel> dev;
   double* coarse_inv = nullptr;   // column-major, internal layout
@@ -254,6 +263,11 @@ hipError_t gather_update(const DevLevel& L, const DevOps<T>& ops, const T* Y, T*
 template <typename T>
 hipError_t gather_cheb(const DevLevel& L, const DevOps<T>& ops, const T* Y, T c1, T c2, int first, int xzero,
                        int transpose, T* d, T* x, hipStream_t s);
+// F += terms of prescribed boundary velocities (finest level, ABI layout): velocity
+// rows -M_fb k_{i,b} - L_fb G_i with k_b = (dt A)^{-1}(G - 1 (x) g_n), divergence rows
+// -B_b^T G_i; g_n (nnodes x dim) and g_st (r x nnodes x dim) are node arrays.
+hipError_t rhs_dirichlet(const DevLevel& L, const double* Ainv_dt, const double* g_n, const double* g_st,
+                         double* F, hipStream_t s);
 template <typename T>
 hipError_t restrict_(const DevLevel& fine, const DevLevel& coarse, const DevOps<T>& fops,
                      const T* xf, T* xc, hipStream_t s);

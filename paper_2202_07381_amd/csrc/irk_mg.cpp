@@ -683,6 +683,35 @@ static irk_status setup_impl(const irk_mesh_level* lv, int nlevels, const irk_ta
     }
   }
   {
+    // (dt A)^{-1} for the boundary stage derivatives (Gauss--Jordan, partial pivoting)
+    const int n = r;
+    double M[kMaxStages][2 * kMaxStages];
+    for (int i = 0; i < n; ++i)
+      for (int j = 0; j < 2 * n; ++j) M[i][j] = j < n ? dt * h->A[i * n + j] : (j - n == i ? 1.0 : 0.0);
+    bool ok = true;
+    for (int k = 0; k < n && ok; ++k) {
+      int piv = k;
+      for (int i = k + 1; i < n; ++i)
+        if (std::fabs(M[i][k]) > std::fabs(M[piv][k])) piv = i;
+      if (!(std::fabs(M[piv][k]) > 0)) {
+        ok = false;
+        break;
+      }
+      for (int j = 0; j < 2 * n; ++j) std::swap(M[k][j], M[piv][j]);
+      const double ip = 1.0 / M[k][k];
+      for (int j = 0; j < 2 * n; ++j) M[k][j] *= ip;
+      for (int i = 0; i < n; ++i)
+        if (i != k) {
+          const double f = M[i][k];
+          for (int j = 0; j < 2 * n; ++j) M[i][j] -= f * M[k][j];
+        }
+    }
+    h->A_invertible = ok;
+    if (ok)
+      for (int i = 0; i < n; ++i)
+        for (int j = 0; j < n; ++j) h->Ainv_dt[i * n + j] = M[i][n + j];
+  }
+  {
     std::string why;
     irk::StageEig eig;
     const bool ok = o.patch_form != 0 && irk::stage_eigenbasis(h->A, r, eig, &why);
@@ -773,6 +802,14 @@ static irk_status setup_impl(const irk_mesh_level* lv, int nlevels, const irk_ta
         CHK(upload(h, &D.mfat_val, tv, s));
       }
       CHK(upload(h, &D.s_K1, H.s_K1, s));
+      CHK(upload(h, &D.fb_ptr, H.fb_ptr, s));
+      CHK(upload(h, &D.fb_col, H.fb_col, s));
+      CHK(upload(h, &D.fb_m, H.fb_m, s));
+      CHK(upload(h, &D.fb_l, H.fb_l, s));
+      CHK(upload(h, &D.vb_ptr, H.vb_ptr, s));
+      CHK(upload(h, &D.vb_col, H.vb_col, s));
+      CHK(upload(h, &D.vb_val, H.vb_val, s));
+      D.nnodes = H.nn;
     }
     // patches: sizes, offsets, local -> internal index, DOF -> slot lists, weights
     std::vector<double> W(D.N, 1.0);
@@ -1040,6 +1077,15 @@ irk_status irk_mg_setup(const irk_mesh_level* lv, int nlevels, const irk_tableau
 }
 
 int irk_mg_patch_form(const irk_mg* h) { return h ? h->patch_form : -1; }
+
+irk_status irk_rhs_dirichlet(irk_mg* h, const double* g_n, const double* g_stages, double* F, void* stream) {
+  CHK(check_handle(h));
+  if (!g_n || !g_stages || !F) return fail(IRK_EINVAL, "null vector");
+  if (!h->A_invertible) return fail(IRK_EINVAL, "boundary stage derivatives need an invertible A");
+  const DevLevel& L = h->dev[h->nlevels - 1];
+  HIPCHK(k::rhs_dirichlet(L, h->Ainv_dt, g_n, g_stages, F, S(stream)));
+  return IRK_OK;
+}
 
 irk_status irk_stage_basis(int r, const double* A, double* W, double* Winv, double* T) {
   if (r < 1 || r > irk::kMaxStages || !A) return fail(IRK_EINVAL, "need 1 <= r <= 4 and a non-null A");

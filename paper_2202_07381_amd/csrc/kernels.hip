@@ -816,6 +816,52 @@ __global__ __launch_bounds__(kBlock) void k_rhs(
   }
 }
 
+// F += the terms of prescribed boundary velocities (ABI layout).  Velocity row f, stage
+// i, component c: -sum_b (M_fb k_{i,b,c} + L_fb G_{i,b,c}) with
+// k_{i,b,c} = sum_j (dt A)^{-1}_ij (G_{j,b,c} - g_{n,b,c}); vertex row v, stage i:
+// -sum_b sum_c B^T_{v,(b,c)} G_{i,b,c}.
+__global__ __launch_bounds__(kBlock) void k_rhs_dirichlet(
+    int64_t nfree, int64_t nv, int64_t nnodes, int D, int R, const int32_t* __restrict__ fb_ptr,
+    const int32_t* __restrict__ fb_col, const double* __restrict__ fb_m, const double* __restrict__ fb_l,
+    const int32_t* __restrict__ vb_ptr, const int32_t* __restrict__ vb_col, const double* __restrict__ vb_val,
+    Coef<double> ainv, const double* __restrict__ gn, const double* __restrict__ gst, double* __restrict__ F) {
+  const int64_t row = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t ns = D * nfree + nv;
+  if (row < nfree) {
+    double acc[kMaxStages][3];
+    for (int i = 0; i < R; ++i)
+      for (int c = 0; c < D; ++c) acc[i][c] = 0.0;
+    for (int32_t p = fb_ptr[row]; p < fb_ptr[row + 1]; ++p) {
+      const int64_t b = fb_col[p];
+      const double m = fb_m[p], l = fb_l[p];
+      for (int c = 0; c < D; ++c) {
+        const double g0 = gn[b * D + c];
+        double G[kMaxStages];
+        for (int j = 0; j < R; ++j) G[j] = gst[((int64_t)j * nnodes + b) * D + c];
+        for (int i = 0; i < R; ++i) {
+          double kb = 0.0;
+          for (int j = 0; j < R; ++j) kb += ainv.v[i * R + j] * (G[j] - g0);
+          acc[i][c] += m * kb + l * G[i];
+        }
+      }
+    }
+    for (int i = 0; i < R; ++i)
+      for (int c = 0; c < D; ++c) F[i * ns + c * nfree + row] -= acc[i][c];
+  } else if (row < nfree + nv) {
+    const int64_t v = row - nfree;
+    double acc[kMaxStages];
+    for (int i = 0; i < R; ++i) acc[i] = 0.0;
+    for (int32_t p = vb_ptr[v]; p < vb_ptr[v + 1]; ++p) {
+      const int64_t b = vb_col[p];
+      for (int c = 0; c < D; ++c) {
+        const double bv = vb_val[(int64_t)p * D + c];
+        for (int i = 0; i < R; ++i) acc[i] += bv * gst[((int64_t)i * nnodes + b) * D + c];
+      }
+    }
+    for (int i = 0; i < R; ++i) F[i * ns + D * nfree + v] -= acc[i];
+  }
+}
+
 __global__ __launch_bounds__(kBlock) void k_update(int64_t ns, int R, Coef<double> bdt,
                                                    const double* __restrict__ kv,
                                                    double* __restrict__ state) {
@@ -1187,6 +1233,16 @@ hipError_t rhs(const DevLevel& L, int64_t nnodes, const double* f, const double*
                      nnodes, L.dim, L.r, L.mfa_ptr, L.mfa_col, L.mfa_val, L.s_ptr, L.s_col,
                      L.d64.s_L, L.b_ptr, L.b_col, L.d64.b_val, L.bt_ptr, L.bt_col, L.d64.bt_val, f,
                      state, F);
+  return hipGetLastError();
+}
+
+hipError_t rhs_dirichlet(const DevLevel& L, const double* Ainv_dt, const double* g_n, const double* g_st,
+                         double* F, hipStream_t s) {
+  Coef<double> c{};
+  for (int i = 0; i < L.r * L.r; ++i) c.v[i] = Ainv_dt[i];
+  k_rhs_dirichlet<<<dim3(blocks_for(L.nfree + L.nv)), dim3(kBlock), 0, s>>>(
+      L.nfree, L.nv, L.nnodes, L.dim, L.r, L.fb_ptr, L.fb_col, L.fb_m, L.fb_l, L.vb_ptr, L.vb_col, L.vb_val, c, g_n,
+      g_st, F);
   return hipGetLastError();
 }
 

@@ -376,9 +376,17 @@ void assemble_level(HostLevel& L, double nu, const std::vector<double>* wind, bo
   L.s_K1.assign(snnz, 0.0);
   std::vector<double> conv(snnz, 0.0);
   L.b_val.assign(L.b_col.size() * d, 0.0);
+  std::vector<std::array<double, 5>> bnd_trip;  // (vertex, node, B values) of boundary rows
   if (with_mfa) {
     csr_from_rows(mrows, L.mfa_ptr, L.mfa_col);
     L.mfa_val.assign(L.mfa_col.size(), 0.0);
+    std::vector<std::vector<int32_t>> fbrows(L.nfree);
+    for (int64_t i = 0; i < L.nfree; ++i)
+      for (int32_t m : mrows[i])
+        if (L.free_of_node[m] < 0) fbrows[i].push_back(m);
+    csr_from_rows(fbrows, L.fb_ptr, L.fb_col);
+    L.fb_m.assign(L.fb_col.size(), 0.0);
+    L.fb_l.assign(L.fb_col.size(), 0.0);
   }
   double glam[12], vol;
   double G[4][4], Me[10][10], Ke[10][10], Ce[10][10], Be[10][4][3];
@@ -428,12 +436,25 @@ void assemble_level(HostLevel& L, double nu, const std::vector<double>* wind, bo
     for (int a = 0; a < nl; ++a) {
       const int64_t na = L.cell_nodes[c * nl + a];
       const int64_t ia = L.free_of_node[na];
-      if (ia < 0) continue;
+      if (ia < 0) {
+        if (with_mfa)
+          for (int q = 0; q < nb; ++q) {
+            std::array<double, 5> t{(double)L.cells[c * nb + q], (double)na, 0, 0, 0};
+            for (int i = 0; i < d; ++i) t[2 + i] = Be[a][q][i];
+            bnd_trip.push_back(t);
+          }
+        continue;
+      }
       for (int b = 0; b < nl; ++b) {
         const int64_t nbn = L.cell_nodes[c * nl + b];
         if (with_mfa) {
           int32_t p = find_in_row(L.mfa_ptr, L.mfa_col, ia, nbn);
           L.mfa_val[p] += Me[a][b];
+          if (L.free_of_node[nbn] < 0) {
+            int32_t q = find_in_row(L.fb_ptr, L.fb_col, ia, nbn);
+            L.fb_m[q] += Me[a][b];
+            L.fb_l[q] += nu * Ke[a][b] + Ce[a][b];
+          }
         }
         const int64_t ib = L.free_of_node[nbn];
         if (ib < 0) continue;
@@ -457,6 +478,27 @@ void assemble_level(HostLevel& L, double nu, const std::vector<double>* wind, bo
       L.s_Lt[p] = L.s_L[q];
     }
   transpose_csr(L.nfree, L.nv, L.b_ptr, L.b_col, L.b_val, d, L.bt_ptr, L.bt_col, L.bt_val);
+  if (with_mfa) {
+    // vertex rows x boundary nodes of B^T (the divergence of prescribed velocities)
+    std::sort(bnd_trip.begin(), bnd_trip.end(), [](const std::array<double, 5>& x, const std::array<double, 5>& y) {
+      return x[0] < y[0] || (x[0] == y[0] && x[1] < y[1]);
+    });
+    L.vb_ptr.assign(L.nv + 1, 0);
+    L.vb_col.clear();
+    L.vb_val.clear();
+    for (size_t t = 0; t < bnd_trip.size(); ++t) {
+      const int64_t v = (int64_t)bnd_trip[t][0];
+      const int32_t node = (int32_t)bnd_trip[t][1];
+      if (!L.vb_col.empty() && t > 0 && (int64_t)bnd_trip[t - 1][0] == v && L.vb_col.back() == node) {
+        for (int i = 0; i < d; ++i) L.vb_val[L.vb_val.size() - d + i] += bnd_trip[t][2 + i];
+        continue;
+      }
+      L.vb_col.push_back(node);
+      for (int i = 0; i < d; ++i) L.vb_val.push_back(bnd_trip[t][2 + i]);
+      L.vb_ptr[v + 1]++;
+    }
+    for (int64_t v = 0; v < L.nv; ++v) L.vb_ptr[v + 1] += L.vb_ptr[v];
+  }
 }
 
 // --------------------------------------------------------------------------- patches

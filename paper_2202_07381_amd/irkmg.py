@@ -91,6 +91,7 @@ def _load() -> C.CDLL:
         "irk_adjoint_solve": (i, [vp, vp, vp, d, i, i, vp, vp]),
         "irk_rhs": (i, [vp, vp, vp, vp, vp]),
         "irk_update": (i, [vp, vp, vp, vp]),
+        "irk_rhs_dirichlet": (i, [vp, vp, vp, vp, vp]),
         "irk_level_apply": (i, [vp, i, i, vp, vp, vp]),
         "irk_level_sweep": (i, [vp, i, i, vp, vp, vp]),
         "irk_level_restrict": (i, [vp, i, vp, vp, vp]),
@@ -275,6 +276,12 @@ class IrkMG:
         sz = self.irk_mg_sizes()
         _check(lib.irk_rhs(self.h, _dev(f_nodal, self.r * sz["nnodes"] * self.dim, "f"), _dev(state, sz["ns"], "state"),
                            _dev(F, self.irk_mg_ndofs(), "F"), _stream(stream)))
+
+    def irk_rhs_dirichlet(self, g_n, g_stages, F, stream=None):
+        sz = self.irk_mg_sizes()
+        nn = sz["nnodes"] * self.dim
+        _check(lib.irk_rhs_dirichlet(self.h, _dev(g_n, nn, "g_n"), _dev(g_stages, self.r * nn, "g_stages"),
+                                     _dev(F, self.irk_mg_ndofs(), "F"), _stream(stream)))
 
     def irk_update(self, k, state, stream=None):
         sz = self.irk_mg_sizes()

@@ -18,7 +18,11 @@ CASES = {
     "lob3": (2, 2, 3, "lobattoIIIC", 3, 0.02, 1.0, None),
     "3d2": (3, 2, 2, "radauIIA", 2, 1e-2, 1.0, None),
     "3d3": (3, 2, 3, "radauIIA", 2, 1e-2, 1.0, None),
+    "cross": (2, 2, 3, "radauIIA", 3, 1 / 64, 1.0, None),
 }
+# cases on the crossed mesh of Sec. 5.1 (four triangles per quad) instead of the
+# diagonal split
+CROSSED = {"cross"}
 
 
 # Set by an autouse fixture in conftest.py so that progress lines reach the terminal
@@ -42,6 +46,8 @@ def torch_dev():
 
 def levels_of(case):
     dim, nc, nl = CASES[case][:3]
+    if case in CROSSED:
+        return wl.crossed_hierarchy(nc, nl)
     return wl.square_hierarchy(nc, nl) if dim == 2 else wl.cube_hierarchy(nc, nl)
 
 

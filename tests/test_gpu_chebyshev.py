@@ -13,7 +13,7 @@ from test_gpu_parity import coarse_tol
 pytestmark = pytest.mark.gpu
 torch = pytest.importorskip("torch")
 
-CHEB_CASES = ["c1", "r3", "oseen", "lob3", "3d2"]
+CHEB_CASES = ["c1", "r3", "oseen", "lob3", "3d2", "cross"]
 
 
 @pytest.mark.parametrize("form", [0, 2])

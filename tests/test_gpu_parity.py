@@ -172,6 +172,26 @@ def test_rhs_and_update():
     assert relerr(to_host(state), ref) < 1e-14
 
 
+@pytest.mark.parametrize("case", ["r3", "cross"])
+def test_rhs_dirichlet(case):
+    """Boundary-data terms of the right-hand side (irk_rhs + irk_rhs_dirichlet) against
+    the oracle on random node data: 1e-13 of the largest entry."""
+    g, H = gpu_of(case), oracle_of(case)
+    S = H.finest
+    th = S.th
+    rng = np.random.default_rng(21)
+    u, p = rng.standard_normal(th.nvel), rng.standard_normal(th.nverts)
+    fn = [rng.standard_normal((th.nnodes, th.dim)) for _ in range(S.r)]
+    gn = rng.standard_normal((th.nnodes, th.dim))
+    gst = [rng.standard_normal((th.nnodes, th.dim)) for _ in range(S.r)]
+    say(f"[rhs dirichlet] case={case}")
+    F = torch.zeros(S.n, dtype=torch.float64, device="cuda")
+    g.irk_rhs(to_dev(np.stack(fn).ravel()), to_dev(np.concatenate([u, p])), F)
+    g.irk_rhs_dirichlet(to_dev(gn.ravel()), to_dev(np.stack(gst).ravel()), F)
+    ref = S.rhs(fn, u, p) + S.rhs_dirichlet(gn, gst)
+    assert relerr(to_host(F), ref) < 1e-13
+
+
 @pytest.mark.parametrize("form", FORMS)
 def test_mixed_precision_reaches_tolerance(form):
     g64, g32, H = gpu_of("r3", patch_form=form), gpu_of("r3", precision=1, patch_form=form), oracle_of("r3")
