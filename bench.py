@@ -233,6 +233,145 @@ def stored_traffic():
     return None
 
 
+# ------------------------------------------------ mirror of the paper's 2D Stokes table
+# Iterations per time step reported in Table 1 (2D Stokes, crossed 8x8 mesh refined l
+# times, dt = 0.5/2^(l+3), Chebyshev [2, 8] with 2/2 steps): {(r, l): its/step}.
+PAPER_T1_RADAU_ITS = {(2, 5): 8.70, (2, 6): 10.99, (2, 7): 14.22, (3, 5): 9.32, (3, 6): 12.40, (3, 7): 13.91}
+
+
+def p2p1_errors(level, vel, p, exact):
+    """L2 error of a P2 velocity field (nodal values at every node, numbering of the
+    library: vertices, then edges sorted by (smaller, larger) vertex) against `exact`,
+    by 25-point collapsed Gauss quadrature per cell; and the L2 norm of the P1 pressure
+    after removing its integral mean (the exact pressure is zero)."""
+    import numpy as np
+
+    xyz, cells = level.xyz, level.cells
+    nv = xyz.shape[0]
+    pairs = [(0, 1), (1, 2), (0, 2)]
+    keys = np.concatenate([np.sort(cells[:, [a, b]], axis=1) for a, b in pairs])
+    code = keys[:, 0] * nv + keys[:, 1]
+    _, inv = np.unique(code, return_inverse=True)
+    edge_node = nv + inv.reshape(3, -1).T  # (nc, 3) nodes of edges 01, 12, 02
+    gx, gw = np.polynomial.legendre.leggauss(5)
+    gx, gw = 0.5 * (gx + 1.0), 0.5 * gw
+    s_, t_ = np.meshgrid(gx, gx, indexing="ij")
+    w2 = np.outer(gw, gw)
+    l1 = s_ * (1.0 - t_)  # collapsed (Duffy) map to the reference triangle
+    l2 = s_ * t_
+    w = (w2 * s_).ravel()
+    l1, l2 = l1.ravel(), l2.ravel()
+    l0 = 1.0 - l1 - l2
+    lam = np.stack([l0, l1, l2], axis=1)  # (nq, 3)
+    phi_v = lam * (2.0 * lam - 1.0)
+    phi_e = np.stack([4 * l0 * l1, 4 * l1 * l2, 4 * l0 * l2], axis=1)
+    P = xyz[cells]  # (nc, 3, 2)
+    det = np.abs((P[:, 1, 0] - P[:, 0, 0]) * (P[:, 2, 1] - P[:, 0, 1])
+                 - (P[:, 2, 0] - P[:, 0, 0]) * (P[:, 1, 1] - P[:, 0, 1]))
+    xq = np.einsum("qk,ckd->cqd", lam, P)
+    uh = np.einsum("qk,ckd->cqd", phi_v, vel[cells]) + np.einsum("qk,ckd->cqd", phi_e, vel[edge_node])
+    ue = exact(xq.reshape(-1, 2)).reshape(uh.shape)
+    vel_err = np.sqrt(np.einsum("q,cqd,c->", w, (uh - ue) ** 2, det))
+    area = 0.5 * det
+    pc = p[cells]
+    mean = np.sum(area * pc.sum(axis=1) / 3.0) / area.sum()
+    pc = pc - mean
+    p_err = np.sqrt(np.sum(area / 12.0 * (np.sum(pc ** 2, axis=1) + np.sum(pc, axis=1) ** 2)))
+    return float(vel_err), float(p_err)
+
+
+def run_t1(ell, r, precision=0, max_steps=None, log_every=32, fixed_rtol=None):
+    """The paper's 2D Stokes experiment (Sec. 5.1, Table 1): exact solution
+    u = (sin(pi x) cos(pi y), -cos(pi x) sin(pi y)) e^{-2 pi^2 t}, p = 0 (so f = 0 and the
+    boundary data drive the flow), nu = 1, RadauIIA(r), FGMRES with the Chebyshev-relaxed
+    V-cycle, stopping at an absolute residual below 1e-2 N^-3 or a relative 1e-8."""
+    import math
+
+    import numpy as np
+    import torch
+
+    from paper_2202_07381_amd import irkmg
+    from paper_2202_07381_amd import workloads as wl
+
+    levels = wl.crossed_hierarchy(8, ell + 1)
+    A, b, c = irkmg.irk_tableau_builtin("radauIIA", r)
+    nsteps = 2 ** (ell + 3)
+    dt = 0.5 / nsteps
+    t0 = time.time()
+    g = irkmg.IrkMG(levels, A, b, c, dt, 1.0, weighting=0, precision=precision, smoother=1, interval=(2.0, 8.0))
+    torch.cuda.synchronize()
+    setup_s = time.time() - t0
+    nodes, free = g.irk_mg_p2_nodes()
+    sz = g.irk_mg_sizes()
+    N = g.irk_mg_ndofs()
+    log(f"t1 l={ell} r={r} precision={precision} setup {setup_s:.1f}s unknowns {N} ({N // r} per stage)")
+
+    def shape(x):  # spatial factor of the exact velocity
+        return np.stack([np.sin(np.pi * x[:, 0]) * np.cos(np.pi * x[:, 1]),
+                         -np.cos(np.pi * x[:, 0]) * np.sin(np.pi * x[:, 1])], axis=1)
+
+    u0 = shape(nodes)
+    g0 = torch.tensor(u0.ravel(), device="cuda")
+    decay = lambda t: math.exp(-2.0 * math.pi ** 2 * t)
+    uf = u0[free]
+    state = torch.tensor(np.concatenate([uf[:, 0], uf[:, 1], np.zeros(sz["nverts"])]), device="cuda")
+    fzero = torch.zeros(r * sz["nnodes"] * 2, dtype=torch.float64, device="cuda")
+    gst = torch.empty(r * sz["nnodes"] * 2, dtype=torch.float64, device="cuda")
+    gn = torch.empty_like(g0)
+    F = torch.zeros(N, dtype=torch.float64, device="cuda")
+    k = torch.zeros_like(F)
+    atol = 1e-2 * float(nsteps) ** -3
+    steps = nsteps if max_steps is None else min(nsteps, max_steps)
+    its = []
+    torch.cuda.synchronize()
+    tstart = time.perf_counter()
+    for n in range(steps):
+        tn = n * dt
+        gn.copy_(g0).mul_(decay(tn))
+        for i in range(r):
+            gst[i * g0.numel():(i + 1) * g0.numel()].copy_(g0).mul_(decay(tn + float(c[i]) * dt))
+        g.irk_rhs(fzero, state, F)
+        g.irk_rhs_dirichlet(gn, gst, F)
+        normF = float(torch.linalg.vector_norm(F))
+        rtol = max(1e-8, atol / normF) if normF > 0 else 1e-8
+        if fixed_rtol is not None:
+            rtol = fixed_rtol
+        k.zero_()
+        info = g.irk_fgmres_solve(F, k, rtol=rtol, maxit=300, restart=30, history_cap=0)
+        if not info["converged"]:
+            raise RuntimeError(f"t1 step {n} did not converge: {info}")
+        g.irk_update(k, state)
+        its.append(info["iterations"])
+        if (n + 1) % log_every == 0:
+            log(f"t1 step {n + 1}/{steps}: mean its {sum(its) / len(its):.2f}")
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - tstart
+    T = steps * dt
+    st = state.cpu().numpy()
+    nf = sz["nfree"]
+    vel = u0 * decay(T)  # boundary nodes keep the exact data
+    vel[free, 0], vel[free, 1] = st[:nf], st[nf:2 * nf]
+    vel_err, p_err = p2p1_errors(levels[-1], vel, st[2 * nf:], lambda x: shape(x) * decay(T))
+    vel_err /= math.sqrt(0.5) * decay(T)  # exact L2 norm of u(T)
+    mean_its = sum(its) / len(its)
+    g.close()
+    return {
+        "metric": "paper 2D Stokes table mirror: FGMRES iterations per time step, time, t/K (Sec. 5.1, Table 1)",
+        "value": mean_its, "unit": "iterations per step", "higher_is_better": False,
+        "n_gpus": 1, "steps": steps, "dtype": "f64" if precision == 0 else "f64 (FP32 patches)",
+        "data": "synthetic (the paper's exact solution)",
+        "config": {"workload": f"2D Stokes, crossed 8x8 refined l={ell} times, RadauIIA({r}), dt=0.5/2^{ell + 3}, "
+                               f"Chebyshev [2,8] 2/2, unweighted additive Vanka, "
+                               + (f"stop at {fixed_rtol:g} rel" if fixed_rtol is not None
+                                  else "stop at 1e-2 N^-3 abs or 1e-8 rel"),
+                   "l": ell, "stages": r, "unknowns": N, "dofs_per_stage": N // r, "time_steps_total": nsteps},
+        "iterations_per_step_mean": mean_its, "iterations_min_max": [min(its), max(its)],
+        "paper_iterations_per_step": PAPER_T1_RADAU_ITS.get((r, ell)),
+        "time_s": elapsed, "setup_s": setup_s, "t_per_krylov_it_ms": 1e3 * elapsed / sum(its),
+        "final_time": T, "velocity_rel_l2_error": vel_err, "pressure_l2_error": p_err,
+    }
+
+
 def run_batch(count, log_every=8):
     """Uneven batch of independent solves: one persistent launch versus the same
     solves one after another with the one-launch-per-step path."""
@@ -321,9 +460,15 @@ def main():
     ap.add_argument("--n", type=int, default=256, help="finest mesh size (power-of-two multiple of 4)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp32", action="store_true")
-    ap.add_argument("--workload", default="stokes256", choices=["stokes256", "batch64"],
+    ap.add_argument("--workload", default="stokes256", choices=["stokes256", "batch64", "t1"],
                     help="stokes256: the headline line; batch64: the uneven batched workload")
     ap.add_argument("--batch-count", type=int, default=64)
+    ap.add_argument("--t1-level", type=int, default=5, help="t1: refinement level l of the crossed 8x8 mesh")
+    ap.add_argument("--t1-stages", type=int, default=2, choices=[2, 3], help="t1: RadauIIA stages")
+    ap.add_argument("--t1-max-steps", type=int, default=None, help="t1: stop after this many time steps")
+    ap.add_argument("--t1-fp32", action="store_true", help="t1: FP32 patch factors")
+    ap.add_argument("--t1-rtol", type=float, default=None,
+                    help="t1: fixed relative tolerance instead of the paper's stopping rule")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run plain copies of known size (for scaling PMC byte counters)")
     ap.add_argument("--summarize-pmc", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
@@ -345,6 +490,10 @@ def main():
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     if args.workload == "batch64":
         run_batch(args.batch_count)
+        return
+    if args.workload == "t1":
+        print(json.dumps(run_t1(args.t1_level, args.t1_stages, 1 if args.t1_fp32 else 0, args.t1_max_steps,
+                                fixed_rtol=args.t1_rtol)), flush=True)
         return
     nlev = int(round(np.log2(args.n // 4))) + 1
     levels = wl.square_hierarchy(4, nlev)

@@ -19,8 +19,8 @@
  * Numbering.  On a mesh level the P2 nodes are the vertices in input order followed
  *   by the edges sorted by (smaller vertex index, larger vertex index).  A node is a
  *   boundary node when it lies on a facet that belongs to exactly one cell; boundary
- *   velocity values are zero and eliminated.  Free nodes are the others, in ascending
- *   node order.
+ *   velocity values are eliminated: zero, unless irk_rhs_dirichlet adds prescribed
+ *   data.  Free nodes are the others, in ascending node order.
  * Vector layout ("ABI layout"), length r * ns with ns = dim * nfree + nverts: stage
  *   blocks in stage order (Sec. 3.1 orders the stages consecutively, each stage's
  *   velocity and pressure together); inside a stage block the velocity components one
