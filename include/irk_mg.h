@@ -294,14 +294,16 @@ irk_status irk_batch_fgmres_solve(irk_batch* b, const double* const* F, double* 
 irk_status irk_batch_get_opts(const irk_batch* b, irk_batch_opts* out);
 void irk_batch_destroy(irk_batch* b);
 
-/* Measurement of the V-cycle kernels.  irk_mg_profile(h, 1) clears the counters and
- * brackets every later launch of the kernels below with HIP events on the stream it is
- * launched on; irk_mg_profile(h, 0) stops recording.  irk_mg_kernel_stats waits for
- * the recorded events and reports, for one kernel on one level (-1: finest), the number
+/* Measurement of the V-cycle kernels.  irk_mg_profile(h, mode) with mode 1..3 clears
+ * the counters and brackets later launches with HIP events on the stream they are
+ * launched on: mode 1 only the finest level's patch apply (least intrusive), mode 2
+ * every kernel below on the finest level, mode 3 on every level; irk_mg_profile(h, 0)
+ * stops recording (IRK_EINVAL for other modes).  irk_mg_kernel_stats waits for the
+ * recorded events and reports, for one kernel on one level (-1: finest), the number
  * of launches, their summed GPU time and the algorithmic bytes one launch moves:
- *   kernel 0  patch apply:   stored patch inverses (sum_v n_v^2 values) + one read of
- *                            the residual (N values) + the local corrections written
- *                            (sum_v n_v values);
+ *   kernel 0  patch apply:   stored patch factors (sum_v n_v^2 values dense,
+ *                            sum_v r n_s^2 factored) + one read of the residual
+ *                            (N values) + the local corrections written (sum_v n_v);
  *   kernel 1  residual:      scalar P2 blocks (column index + M + L per entry), B and
  *                            B^T (index + dim values per entry), F and x read, r written;
  *   kernel 2  gather update: local corrections and their slot indices read, x read and

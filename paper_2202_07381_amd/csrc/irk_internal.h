@@ -241,6 +241,7 @@ struct Handle {
     int kernel = 0, level = 0;
   };
   bool prof = false;
+  int prof_mode = 3;
   std::vector<ProfEv> prof_pool;
   size_t prof_used = 0;
   hipEvent_t ev0 = nullptr, ev1 = nullptr, ev2 = nullptr, ev3 = nullptr;

@@ -116,6 +116,9 @@ void transpose_host(int64_t nrows, int64_t ncols, const std::vector<int32_t>& pt
 // ------------------------------------------------------------------- measurement
 int prof_begin(Handle* h, int kernel, int level, hipStream_t s) {
   if (!h->prof) return -1;
+  // mode 1: finest-level patch apply only; 2: every kernel of the finest level; 3: all
+  if (h->prof_mode < 3 && level != h->nlevels - 1) return -1;
+  if (h->prof_mode == 1 && kernel != 0) return -1;
   if (h->prof_used == h->prof_pool.size()) {
     Handle::ProfEv e;
     if (hipEventCreate(&e.a) != hipSuccess || hipEventCreate(&e.b) != hipSuccess) return -1;
@@ -534,8 +537,12 @@ irk_status irk_mesh_p2_nodes(const irk_mesh_level* m, int64_t* nnodes, double* x
 
 irk_status irk_mg_profile(irk_mg* h, int enable) {
   CHK(check_handle(h));
+  if (enable < 0 || enable > 3) return fail(IRK_EINVAL, "profile mode must be 0..3");
   h->prof = enable != 0;
-  if (enable) h->prof_used = 0;
+  if (enable) {
+    h->prof_mode = enable;
+    h->prof_used = 0;
+  }
   return IRK_OK;
 }
 

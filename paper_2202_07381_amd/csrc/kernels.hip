@@ -680,20 +680,43 @@ __global__ __launch_bounds__(kBlock) void k_cast(const S* __restrict__ in, Dt* _
   if (i < n) out[i] = (Dt)in[i];
 }
 
-// per-stage pressure mean removal: one workgroup per stage, fixed-order reduction
-__global__ __launch_bounds__(1024) void k_project(double* x, int64_t offV, int64_t nv, int R) {
-  __shared__ double red[1024];
-  const int s = blockIdx.x;
-  double acc = 0;
-  for (int64_t v = threadIdx.x; v < nv; v += blockDim.x) acc += x[offV + v * R + s];
-  red[threadIdx.x] = acc;
+// per-stage pressure mean removal in two passes with a fixed reduction order: partial
+// sums of every stage over vertex chunks (grid-stride, one workgroup per chunk set),
+// then every workgroup of the apply pass sums the partials in the same order and
+// subtracts the means
+constexpr int kProjBlocks = 256;
+
+__global__ __launch_bounds__(kBlock) void k_project_partial(const double* __restrict__ x, int64_t offV,
+                                                            int64_t nv, int R, double* __restrict__ partials) {
+  __shared__ double red[kMaxStages][kBlock];
+  double acc[kMaxStages] = {0, 0, 0, 0};
+  for (int64_t v = (int64_t)blockIdx.x * kBlock + threadIdx.x; v < nv; v += (int64_t)gridDim.x * kBlock)
+    for (int s = 0; s < R; ++s) acc[s] += x[offV + v * R + s];
+  for (int s = 0; s < R; ++s) red[s][threadIdx.x] = acc[s];
   __syncthreads();
-  for (int w = blockDim.x / 2; w > 0; w >>= 1) {
-    if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+  for (int w = kBlock / 2; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w)
+      for (int s = 0; s < R; ++s) red[s][threadIdx.x] += red[s][threadIdx.x + w];
     __syncthreads();
   }
-  const double mean = red[0] / (double)nv;
-  for (int64_t v = threadIdx.x; v < nv; v += blockDim.x) x[offV + v * R + s] -= mean;
+  if (threadIdx.x == 0)
+    for (int s = 0; s < R; ++s) partials[s * gridDim.x + blockIdx.x] = red[s][0];
+}
+
+__global__ __launch_bounds__(kBlock) void k_project_apply(double* __restrict__ x, int64_t offV, int64_t nv, int R,
+                                                          const double* __restrict__ partials, int nb) {
+  __shared__ double red[kMaxStages][kBlock];
+  for (int s = 0; s < R; ++s) red[s][threadIdx.x] = (int)threadIdx.x < nb ? partials[s * nb + threadIdx.x] : 0.0;
+  __syncthreads();
+  for (int w = kBlock / 2; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w)
+      for (int s = 0; s < R; ++s) red[s][threadIdx.x] += red[s][threadIdx.x + w];
+    __syncthreads();
+  }
+  double mean[kMaxStages];
+  for (int s = 0; s < R; ++s) mean[s] = red[s][0] / (double)nv;
+  for (int64_t e = (int64_t)blockIdx.x * kBlock + threadIdx.x; e < nv * R; e += (int64_t)gridDim.x * kBlock)
+    x[offV + e] -= mean[e % R];
 }
 
 // ------------------------------------------------------------------------- BLAS-1
@@ -1181,8 +1204,12 @@ hipError_t cast(const S* in, D* out, int64_t n, hipStream_t s) {
   return hipGetLastError();
 }
 
-hipError_t project_pressure(const DevLevel& L, double* x, double*, hipStream_t s) {
-  k_project<<<dim3(L.r), dim3(1024), 0, s>>>(x, L.offV, L.nv, L.r);
+hipError_t project_pressure(const DevLevel& L, double* x, double* partials, hipStream_t s) {
+  static_assert(kProjBlocks <= kBlock && kProjBlocks * kMaxStages <= 1024, "partials buffer holds 1024 values");
+  const int nb = (int)std::min<int64_t>(kProjBlocks, blocks_for(L.nv));
+  k_project_partial<<<dim3(nb), dim3(kBlock), 0, s>>>(x, L.offV, L.nv, L.r, partials);
+  const unsigned ga = (unsigned)std::min<int64_t>(1024, blocks_for(L.nv * L.r));
+  k_project_apply<<<dim3(ga), dim3(kBlock), 0, s>>>(x, L.offV, L.nv, L.r, partials, nb);
   return hipGetLastError();
 }
 

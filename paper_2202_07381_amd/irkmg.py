@@ -310,8 +310,9 @@ class IrkMG:
         _check(lib.irk_mass_apply(self.h, _dev(state, sz["ns"], "state"), _dev(out, sz["ns"], "out"), _stream(stream)))
 
     # ---------------------------------------------------------- measurement
-    def irk_mg_profile(self, enable: bool):
-        _check(lib.irk_mg_profile(self.h, int(enable)))
+    def irk_mg_profile(self, mode):
+        """0 (or False) off; 1 (or True) finest-level patch apply; 2 finest-level kernels; 3 all."""
+        _check(lib.irk_mg_profile(self.h, int(mode)))
 
     def irk_mg_kernel_stats(self, kernel: str, level: int = -1) -> dict:
         st = irk_kernel_stats()
