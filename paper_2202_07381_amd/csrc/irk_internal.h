@@ -302,6 +302,11 @@ hipError_t project_pressure(const DevLevel& L, double* x, double* partials, hipS
 // deterministic reductions: result written to device scalar *out
 hipError_t dot(const double* a, const double* b, int64_t n, double* partials, double* out,
                hipStream_t s, int take_sqrt = 0);
+// Arnoldi orthogonalisation of w against the j+1 basis vectors V (n apart) by modified
+// Gram--Schmidt, then normalisation: hcol[0..j] = projections, hcol[j+1] = norm (device);
+// partials: 1024-value workspace.
+hipError_t mgs_arnoldi(double* w, const double* V, int64_t n, int j, double* partials, double* hcol,
+                       hipStream_t s);
 // y += alpha * x with alpha = sign * (*dev_scalar) (or the host value if dev_scalar null)
 hipError_t axpy_dev(double* y, const double* x, int64_t n, const double* dev_scalar,
                     double sign, hipStream_t s);

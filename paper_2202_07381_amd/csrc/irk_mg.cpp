@@ -348,12 +348,7 @@ irk_status fgmres(irk_mg* h, const double* F_abi, double* k_abi, double rtol, in
       CHK(precondition(h, vj, zj, tr, s));
       HIPCHK(hipEventRecord(h->ev3, s));
       CHK(apply_J(h, zj, vn, tr, nullptr, s));
-      for (int i = 0; i <= j; ++i) {
-        HIPCHK(k::dot(vn, h->kv + (size_t)i * N, N, h->partials, h->hbuf + i, s, 0));
-        HIPCHK(k::axpy_dev(vn, h->kv + (size_t)i * N, N, h->hbuf + i, -1.0, s));
-      }
-      HIPCHK(k::dot(vn, vn, N, h->partials, h->hbuf + j + 1, s, 1));
-      HIPCHK(k::scale_inv_dev(vn, vn, N, h->hbuf + j + 1, s));
+      HIPCHK(k::mgs_arnoldi(vn, h->kv, N, j, h->partials, h->hbuf, s));
       HIPCHK(hipMemcpyAsync(hcol.data(), h->hbuf, (j + 2) * sizeof(double), hipMemcpyDeviceToHost, s));
       HIPCHK(hipStreamSynchronize(s));
       float ms = 0;

@@ -767,6 +767,58 @@ __global__ __launch_bounds__(kBlock) void k_dot_final(const double* __restrict__
   if (threadIdx.x == 0) *out = take_sqrt ? sqrt(red[0]) : red[0];
 }
 
+// ---- Arnoldi step by modified Gram--Schmidt, one launch per projection: launch i
+// finishes the inner product h_i = <w, v_i> from the previous launch's partial sums
+// (same order as k_dot_final), applies w -= h_i v_i, and forms the partial sums of the
+// next inner product <w, v_{i+1}> (or <w, w> after the last projection) with the
+// grid-stride decomposition of k_dot_partial, so the values equal the unfused sequence.
+__device__ double block_reduce_partials(const double* __restrict__ partials, int nb, double* red) {
+  double acc = 0;
+  for (int i = threadIdx.x; i < nb; i += blockDim.x) acc += partials[i];
+  red[threadIdx.x] = acc;
+  __syncthreads();
+  for (int w = kBlock / 2; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+    __syncthreads();
+  }
+  const double r = red[0];
+  __syncthreads();
+  return r;
+}
+
+__global__ __launch_bounds__(kBlock) void k_mgs_step(double* __restrict__ w, const double* __restrict__ vi,
+                                                     const double* vnext, int64_t n, const double* __restrict__ pin,
+                                                     int nb, double* __restrict__ pout, double* __restrict__ hout) {
+  __shared__ double red[kBlock];
+  const double h = block_reduce_partials(pin, nb, red);
+  if (blockIdx.x == 0 && threadIdx.x == 0) *hout = h;
+  const double a = -1.0 * h;
+  double acc = 0;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x) {
+    double y = w[e];
+    y += a * vi[e];
+    w[e] = y;
+    acc += y * (vnext ? vnext[e] : y);
+  }
+  red[threadIdx.x] = acc;
+  __syncthreads();
+  for (int s2 = kBlock / 2; s2 > 0; s2 >>= 1) {
+    if ((int)threadIdx.x < s2) red[threadIdx.x] += red[threadIdx.x + s2];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) pout[blockIdx.x] = red[0];
+}
+
+__global__ __launch_bounds__(kBlock) void k_mgs_normalize(double* __restrict__ w, int64_t n,
+                                                          const double* __restrict__ pin, int nb,
+                                                          double* __restrict__ hout) {
+  __shared__ double red[kBlock];
+  const double nrm = sqrt(block_reduce_partials(pin, nb, red));
+  if (blockIdx.x == 0 && threadIdx.x == 0) *hout = nrm;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x)
+    w[e] = w[e] / nrm;
+}
+
 __global__ __launch_bounds__(kBlock) void k_axpy_dev(double* __restrict__ y,
                                                      const double* __restrict__ x, int64_t n,
                                                      const double* __restrict__ s, double sign,
@@ -1218,6 +1270,22 @@ hipError_t dot(const double* a, const double* b, int64_t n, double* partials, do
   const int nb = (int)std::min<int64_t>(kReduceBlocks, blocks_for(n));
   k_dot_partial<<<dim3(nb), dim3(kBlock), 0, s>>>(a, b, n, partials);
   k_dot_final<<<dim3(1), dim3(kBlock), 0, s>>>(partials, nb, out, take_sqrt);
+  return hipGetLastError();
+}
+
+hipError_t mgs_arnoldi(double* w, const double* V, int64_t n, int j, double* partials, double* hcol,
+                       hipStream_t s) {
+  const int nb = (int)std::min<int64_t>(kReduceBlocks, blocks_for(n));
+  static_assert(2 * kReduceBlocks <= 1024, "two partial-sum buffers in the 1024-value workspace");
+  double* pa = partials;
+  double* pb = partials + kReduceBlocks;
+  k_dot_partial<<<dim3(nb), dim3(kBlock), 0, s>>>(w, V, n, pa);
+  for (int i = 0; i <= j; ++i) {
+    const double* vnext = i < j ? V + (size_t)(i + 1) * n : nullptr;
+    k_mgs_step<<<dim3(nb), dim3(kBlock), 0, s>>>(w, V + (size_t)i * n, vnext, n, pa, nb, pb, hcol + i);
+    std::swap(pa, pb);
+  }
+  k_mgs_normalize<<<dim3(nb), dim3(kBlock), 0, s>>>(w, n, pa, nb, hcol + j + 1);
   return hipGetLastError();
 }
 
