@@ -88,6 +88,12 @@ __global__ __launch_bounds__(256) void k_residual_sell(
     {
       const int w = su_w[sl];
       const int64_t e0 = su_off[sl] + lane;
+      // software pipelined: the next round's column indices are fetched while this
+      // round's gathers are in flight
+      int32_t jn[kSellUnroll];
+      if (kSellUnroll <= w)
+#pragma unroll
+        for (int u = 0; u < kSellUnroll; ++u) jn[u] = su_col[e0 + (int64_t)u * 64];
       int k = 0;
       for (; k + kSellUnroll <= w; k += kSellUnroll) {
         int32_t j[kSellUnroll];
@@ -95,7 +101,7 @@ __global__ __launch_bounds__(256) void k_residual_sell(
 #pragma unroll
         for (int u = 0; u < kSellUnroll; ++u) {
           const int64_t e = e0 + (int64_t)(k + u) * 64;
-          j[u] = su_col[e];
+          j[u] = jn[u];
           m[u] = uM[e];
           l[u] = uL[e];
         }
@@ -103,6 +109,9 @@ __global__ __launch_bounds__(256) void k_residual_sell(
         for (int u = 0; u < kSellUnroll; ++u)
 #pragma unroll
           for (int q = 0; q < DR; ++q) xv[u][q] = x[(int64_t)j[u] * DR + q];
+        if (k + 2 * kSellUnroll <= w)
+#pragma unroll
+          for (int u = 0; u < kSellUnroll; ++u) jn[u] = su_col[e0 + (int64_t)(k + kSellUnroll + u) * 64];
 #pragma unroll
         for (int u = 0; u < kSellUnroll; ++u)
 #pragma unroll
@@ -126,7 +135,35 @@ __global__ __launch_bounds__(256) void k_residual_sell(
     {
       const int w = sb_w[sl];
       const int64_t e0 = sb_off[sl] + lane;
-      for (int k = 0; k < w; ++k) {
+      int32_t jn[kSellUnroll];
+      if (kSellUnroll <= w)
+#pragma unroll
+        for (int u = 0; u < kSellUnroll; ++u) jn[u] = sb_col[e0 + (int64_t)u * 64];
+      int k = 0;
+      for (; k + kSellUnroll <= w; k += kSellUnroll) {
+        int32_t j[kSellUnroll];
+        T pv[kSellUnroll][R], bv[kSellUnroll][D];
+#pragma unroll
+        for (int u = 0; u < kSellUnroll; ++u) j[u] = jn[u];
+        if (k + 2 * kSellUnroll <= w)
+#pragma unroll
+          for (int u = 0; u < kSellUnroll; ++u) jn[u] = sb_col[e0 + (int64_t)(k + kSellUnroll + u) * 64];
+#pragma unroll
+        for (int u = 0; u < kSellUnroll; ++u) {
+          const int64_t e = e0 + (int64_t)(k + u) * 64;
+#pragma unroll
+          for (int t = 0; t < R; ++t) pv[u][t] = x[offV + (int64_t)j[u] * R + t];
+#pragma unroll
+          for (int c = 0; c < D; ++c) bv[u][c] = uB[e * D + c];
+        }
+#pragma unroll
+        for (int u = 0; u < kSellUnroll; ++u)
+#pragma unroll
+          for (int c = 0; c < D; ++c)
+#pragma unroll
+            for (int t = 0; t < R; ++t) al[c * R + t] += bv[u][c] * pv[u][t];
+      }
+      for (; k < w; ++k) {
         const int64_t e = e0 + (int64_t)k * 64;
         const T* xp = x + offV + (int64_t)sb_col[e] * R;
         T pv[R];
@@ -160,16 +197,23 @@ __global__ __launch_bounds__(256) void k_residual_sell(
     for (int t = 0; t < R; ++t) a[t] = T(0);
     const int w = sp_w[ps];
     const int64_t e0 = sp_off[ps] + lane;
+    int32_t jn[kSellUnroll];
+    if (kSellUnroll <= w)
+#pragma unroll
+      for (int u = 0; u < kSellUnroll; ++u) jn[u] = sp_col[e0 + (int64_t)u * 64];
     int k = 0;
     for (; k + kSellUnroll <= w; k += kSellUnroll) {
       int32_t j[kSellUnroll];
       T xv[kSellUnroll][DR];
 #pragma unroll
-      for (int u = 0; u < kSellUnroll; ++u) j[u] = sp_col[e0 + (int64_t)(k + u) * 64];
+      for (int u = 0; u < kSellUnroll; ++u) j[u] = jn[u];
 #pragma unroll
       for (int u = 0; u < kSellUnroll; ++u)
 #pragma unroll
         for (int q = 0; q < DR; ++q) xv[u][q] = x[(int64_t)j[u] * DR + q];
+      if (k + 2 * kSellUnroll <= w)
+#pragma unroll
+        for (int u = 0; u < kSellUnroll; ++u) jn[u] = sp_col[e0 + (int64_t)(k + kSellUnroll + u) * 64];
 #pragma unroll
       for (int u = 0; u < kSellUnroll; ++u) {
         const int64_t e = e0 + (int64_t)(k + u) * 64;
