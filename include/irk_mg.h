@@ -284,6 +284,13 @@ typedef struct irk_batch_opts {
   int patches_per_wave;
   int workgroups_per_cu;
   int autotune;
+  int mode;     /* 0: one persistent launch; 1: concurrent streams: `streams` host
+                   threads, each with its own HIP stream, take whole solves (largest
+                   first) and run irk_fgmres_solve on them (any handle: FP32, 3D,
+                   Chebyshev; the persistent kernel needs FP64 2D damped-sweep handles
+                   with patches of <= 256 unknowns, else mode 1 is used) */
+  int streams;  /* 1..16; 1 is the one-by-one baseline.  Autotuning times streams
+                   1, 2, 4, 8 and the persistent tiles and keeps the fastest */
 } irk_batch_opts;
 void irk_batch_default_opts(irk_batch_opts* opt);
 irk_status irk_batch_create(irk_mg* const* solves, int n, const irk_batch_opts* opt, void* stream,

@@ -21,8 +21,12 @@
 #include <cmath>
 #include <cstdio>
 #include <cstdlib>
+#include <atomic>
+#include <chrono>
 #include <cstring>
+#include <numeric>
 #include <string>
+#include <thread>
 #include <vector>
 
 #include "../../include/irk_mg.h"
@@ -813,8 +817,10 @@ struct irk_batch {
   std::vector<void*> allocs;
   irk_batch_opts opts{};
   bool tuned = false;
-  int wg_per_cu = 0, cus = 0;
+  bool persistent_ok = true;  // every handle fits the persistent kernel
+  int wg_per_cu = 0, cus = 0, device = 0;
   double wall_khz = 100000.0;
+  std::vector<hipStream_t> streams;  // concurrent-streams schedule
 };
 
 namespace {
@@ -960,6 +966,69 @@ irk_status run(irk_batch* b, const double* const* F, double* const* k, bool tria
 }
 }  // namespace
 
+namespace {
+// Concurrent-streams schedule: `streams` host threads, each with its own HIP stream,
+// take whole solves (largest first) from a shared counter and run the launch-per-step
+// FGMRES-MG solver on them.  Outputs go to k (or to scratch for trial runs).
+irk_status run_streams(irk_batch* b, const double* const* F, double* const* k, bool trial, double rtol, int maxit,
+                       int restart, hipStream_t s, float* ms_out, irk_solve_info* infos, double* latency_ms) {
+  const int n = (int)b->hs.size();
+  const int S = std::max(1, std::min(b->opts.streams, (int)b->streams.size()));
+  BHIP(hipStreamSynchronize(s));  // inputs produced on the caller's stream are ready
+  std::vector<int> order(n);
+  std::iota(order.begin(), order.end(), 0);
+  std::stable_sort(order.begin(), order.end(), [&](int a, int c) {
+    return b->hs[a]->dev[b->hs[a]->nlevels - 1].N > b->hs[c]->dev[b->hs[c]->nlevels - 1].N;
+  });
+  std::atomic<int> next{0};
+  std::vector<irk_status> status(n, IRK_OK);
+  std::vector<std::string> errs(n);
+  std::vector<irk_solve_info> res(n);
+  std::vector<double> lat(n, 0.0);
+  const auto t0 = std::chrono::steady_clock::now();
+  auto worker = [&](int w) {
+    (void)hipSetDevice(b->device);
+    for (;;) {
+      const int i = next.fetch_add(1);
+      if (i >= n) break;
+      const int q = order[i];
+      irk_solve_info info{};
+      double* out = trial ? b->ktrial[q] : k[q];
+      if (trial) (void)hipMemcpyAsync(out, k[q], sizeof(double) * b->hs[q]->dev[b->hs[q]->nlevels - 1].N,
+                                       hipMemcpyDeviceToDevice, b->streams[w]);
+      status[q] = irk_fgmres_solve(b->hs[q], F[q], out, rtol, maxit, restart, &info, b->streams[w]);
+      if (status[q] != IRK_OK) errs[q] = irk_last_error();
+      res[q] = info;
+      lat[q] = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    }
+  };
+  std::vector<std::thread> pool;
+  for (int w = 0; w < S; ++w) pool.emplace_back(worker, w);
+  for (auto& t : pool) t.join();
+  *ms_out = (float)std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+  irk_status ret = IRK_OK;
+  for (int q = 0; q < n; ++q) {
+    if (infos && !trial) {
+      infos[q].iterations = res[q].iterations;
+      infos[q].converged = res[q].converged;
+      infos[q].rel_residual = res[q].rel_residual;
+      infos[q].ms_vcycle = res[q].ms_vcycle;
+      infos[q].ms_total = res[q].ms_total;
+    }
+    if (latency_ms && !trial) latency_ms[q] = lat[q];
+    const irk_status st = status[q];
+    if (st == IRK_OK || (st == IRK_ENOCONV && trial)) continue;
+    if (st == IRK_ENOCONV) {
+      if (ret == IRK_OK) ret = IRK_ENOCONV;
+      continue;
+    }
+    return bfail(st, "batched solve " + std::to_string(q) + ": " + errs[q]);
+  }
+  if (ret == IRK_ENOCONV) irk::set_error("a batched solve reached maxit");
+  return ret;
+}
+}  // namespace
+
 extern "C" {
 
 void irk_batch_default_opts(irk_batch_opts* o) {
@@ -968,6 +1037,8 @@ void irk_batch_default_opts(irk_batch_opts* o) {
   o->patches_per_wave = 1;
   o->workgroups_per_cu = 2;
   o->autotune = 1;
+  o->mode = 0;
+  o->streams = 4;
 }
 
 irk_status irk_batch_create(irk_mg* const* hs, int n, const irk_batch_opts* opts, void* stream, irk_batch** out) {
@@ -980,22 +1051,33 @@ irk_status irk_batch_create(irk_mg* const* hs, int n, const irk_batch_opts* opts
   if (o.rows_per_item < 1 || o.rows_per_item > 64 || o.patches_per_wave < 1 || o.patches_per_wave > 64 ||
       o.workgroups_per_cu < 1 || o.workgroups_per_cu > 8)
     return bfail(IRK_EINVAL, "rows_per_item and patches_per_wave in 1..64, workgroups_per_cu in 1..8");
+  if ((o.mode != 0 && o.mode != 1) || o.streams < 1 || o.streams > 16)
+    return bfail(IRK_EINVAL, "mode must be 0 or 1 and streams in 1..16");
+  // the persistent kernel runs FP64 2D handles with the damped-sweep smoother and
+  // patches of at most 256 unknowns; the concurrent-streams schedule runs any handle
+  bool persistent_ok = true;
+  std::string why;
   for (int q = 0; q < n; ++q) {
     if (!hs[q]) return bfail(IRK_EINVAL, "null handle in the batch");
-    if (hs[q]->precision != 0) return bfail(IRK_EINVAL, "the batched solver runs FP64 handles only");
-    if (hs[q]->smoother != 0) return bfail(IRK_EINVAL, "the batched solver runs the damped-sweep smoother only");
-    if (hs[q]->dim != 2) return bfail(IRK_EINVAL, "the batched solver runs 2D handles only");
-    if (hs[q]->nlevels > kMaxLevels) return bfail(IRK_EINVAL, "too many levels for the batched solver");
-    for (int l = 1; l < hs[q]->nlevels; ++l)
-      if (hs[q]->dev[l].max_nloc > kNmax || hs[q]->dev[l].max_ld > 2 * 128)
-        return bfail(IRK_EINVAL, "patch too large for the batched solver");
     for (int p = 0; p < q; ++p)
       if (hs[p] == hs[q]) return bfail(IRK_EINVAL, "a handle appears twice in the batch");
+    if (hs[q]->precision != 0) why = "the persistent kernel runs FP64 handles only";
+    else if (hs[q]->smoother != 0) why = "the persistent kernel runs the damped-sweep smoother only";
+    else if (hs[q]->dim != 2) why = "the persistent kernel runs 2D handles only";
+    else if (hs[q]->nlevels > kMaxLevels) why = "too many levels for the persistent kernel";
+    else
+      for (int l = 1; l < hs[q]->nlevels; ++l)
+        if (hs[q]->dev[l].max_nloc > kNmax || hs[q]->dev[l].max_ld > 2 * 128)
+          why = "patch too large for the persistent kernel";
+    if (!why.empty()) persistent_ok = false;
   }
+  if (!persistent_ok && o.mode == 0 && !o.autotune) return bfail(IRK_EINVAL, why);
+  if (!persistent_ok) o.mode = 1;
   irk_batch* b = new (std::nothrow) irk_batch();
   if (!b) return bfail(IRK_ENOMEM, "allocation failed");
   b->hs.assign(hs, hs + n);
   b->opts = o;
+  b->persistent_ok = persistent_ok;
   int dev = 0;
   irk_status st = IRK_OK;
   auto cleanup = [&](irk_status code) {
@@ -1005,6 +1087,15 @@ irk_status irk_batch_create(irk_mg* const* hs, int n, const irk_batch_opts* opts
   };
   if (hipGetDevice(&dev) != hipSuccess || hipDeviceGetAttribute(&b->cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
     return cleanup(bfail(IRK_EHIP, "device query failed"));
+  b->device = dev;
+  for (int i = 0; i < 16; ++i) {
+    hipStream_t st_i;
+    if (hipStreamCreate(&st_i) != hipSuccess) {
+      for (hipStream_t x : b->streams) (void)hipStreamDestroy(x);
+      return cleanup(bfail(IRK_EHIP, "stream creation failed"));
+    }
+    b->streams.push_back(st_i);
+  }
   int khz = 0;
   if (hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev) == hipSuccess && khz > 0) b->wall_khz = khz;
   int occ = 0;
@@ -1030,6 +1121,7 @@ irk_status irk_batch_create(irk_mg* const* hs, int n, const irk_batch_opts* opts
 
 void irk_batch_destroy(irk_batch* b) {
   if (!b) return;
+  for (hipStream_t x : b->streams) (void)hipStreamDestroy(x);
   for (void* p : b->allocs) (void)hipFree(p);
   delete b;
 }
@@ -1051,12 +1143,27 @@ irk_status irk_batch_fgmres_solve(irk_batch* b, const double* const* F, double* 
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
   if (b->opts.autotune && !b->tuned) {
     // time short trial runs (2 iterations per solve, outputs to scratch) over the
-    // schedule space and keep the fastest
+    // schedule space (concurrent streams, then the persistent kernel's tiles) and keep
+    // the fastest; one stream is the one-by-one baseline
     float best = 1e30f;
     irk_batch_opts bo = b->opts;
+    for (int S : {1, 2, 4, 8}) {
+      b->opts.mode = 1;
+      b->opts.streams = S;
+      float ms = 0;
+      irk_status st = run_streams(b, F, k, true, rtol, 2, restart, s, &ms, nullptr, nullptr);
+      if (std::getenv("IRK_BATCH_DEBUG")) fprintf(stderr, "autotune streams %d: %.3f ms (status %d)\n", S, ms, st);
+      if (st != IRK_OK) return st;
+      if (ms < best) {
+        best = ms;
+        bo = b->opts;
+      }
+    }
+    b->opts.mode = 0;
     for (int wg : {1, 2, 4})
       for (int rows : {1, 2, 4})
         for (int ppw : {1, 2, 4}) {
+          if (!b->persistent_ok) continue;
           if (wg > b->wg_per_cu) continue;
           b->opts.workgroups_per_cu = wg;
           b->opts.rows_per_item = rows;
@@ -1073,6 +1180,10 @@ irk_status irk_batch_fgmres_solve(irk_batch* b, const double* const* F, double* 
         }
     b->opts = bo;
     b->tuned = true;
+  }
+  if (b->opts.mode == 1) {
+    float ms = 0;
+    return run_streams(b, F, k, false, rtol, maxit, restart, s, &ms, infos, latency_ms);
   }
   std::vector<BState> states;
   unsigned long long t0 = 0;

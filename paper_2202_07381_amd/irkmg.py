@@ -58,7 +58,7 @@ class irk_solve_info(C.Structure):
 
 class irk_batch_opts(C.Structure):
     _fields_ = [("rows_per_item", C.c_int), ("patches_per_wave", C.c_int), ("workgroups_per_cu", C.c_int),
-                ("autotune", C.c_int)]
+                ("autotune", C.c_int), ("mode", C.c_int), ("streams", C.c_int)]
 
 
 class irk_kernel_stats(C.Structure):
@@ -342,12 +342,14 @@ class IrkMG:
 
 
 class IrkBatch:
-    """Batched solves of several handles in one persistent launch (irk_batch_*)."""
+    """Batched solves of several handles (irk_batch_*): one persistent launch (mode 0)
+    or concurrent streams (mode 1); autotuning picks the faster schedule."""
 
-    def __init__(self, solvers, rows_per_item=1, patches_per_wave=1, workgroups_per_cu=2, autotune=True, stream=None):
+    def __init__(self, solvers, rows_per_item=1, patches_per_wave=1, workgroups_per_cu=2, autotune=True, mode=0,
+                 streams=4, stream=None):
         self.solvers = list(solvers)
         arr = (C.c_void_p * len(self.solvers))(*[s.h.value for s in self.solvers])
-        opts = irk_batch_opts(rows_per_item, patches_per_wave, workgroups_per_cu, int(autotune))
+        opts = irk_batch_opts(rows_per_item, patches_per_wave, workgroups_per_cu, int(autotune), mode, streams)
         h = C.c_void_p()
         _check(lib.irk_batch_create(arr, len(self.solvers), C.byref(opts), _stream(stream), C.byref(h)))
         self.h = h
@@ -364,7 +366,7 @@ class IrkBatch:
         o = irk_batch_opts()
         _check(lib.irk_batch_get_opts(self.h, C.byref(o)))
         return dict(rows_per_item=o.rows_per_item, patches_per_wave=o.patches_per_wave,
-                    workgroups_per_cu=o.workgroups_per_cu, autotune=o.autotune)
+                    workgroups_per_cu=o.workgroups_per_cu, autotune=o.autotune, mode=o.mode, streams=o.streams)
 
     def irk_batch_fgmres_solve(self, Fs, ks, rtol=1e-8, maxit=1000, restart=30, stream=None):
         n = len(self.solvers)

@@ -81,3 +81,32 @@ def test_batch_bitwise_repeatable():
             else:
                 assert all(np.array_equal(a, c) for a, c in zip(out, ref))
         b.close()
+
+
+def test_batch_streams_mode_matches_one_by_one():
+    """Concurrent-streams schedule on handles the persistent kernel does not run (FP32
+    patches, Chebyshev relaxation, 3D) beside ordinary ones: every solution equals the
+    one-by-one solve bitwise (the same deterministic kernels on another stream); with
+    autotuning such a batch is scheduled on streams."""
+    from paper_2202_07381_amd import irkmg
+
+    cases = [("r3", dict(precision=1)), ("c1", dict(smoother=1)), ("3d2", {}), ("oseen", {}), ("lob3", {})]
+    gs = [gpu_of(c, **kw) for c, kw in cases]
+    Fs = [to_dev(forcing_rhs(c)) for c, _ in cases]
+    ref = []
+    for g, F in zip(gs, Fs):
+        k = torch.zeros_like(F)
+        info = g.irk_fgmres_solve(F, k, rtol=1e-8, maxit=200, restart=30)
+        ref.append((to_host(k), info["iterations"]))
+    for autotune in (False, True):
+        say(f"[batch streams] autotune={autotune}")
+        b = irkmg.IrkBatch(gs, autotune=autotune, mode=1, streams=3)
+        ks = [torch.zeros_like(F) for F in Fs]
+        st, infos, _ = b.irk_batch_fgmres_solve(Fs, ks, rtol=1e-8, maxit=200, restart=30)
+        assert st == irkmg.IRK_OK and b.irk_batch_get_opts()["mode"] == 1
+        for (kr, itr), k, info in zip(ref, ks, infos):
+            assert info["converged"] and info["iterations"] == itr
+            assert np.array_equal(to_host(k), kr)
+        b.close()
+    with pytest.raises(irkmg.IrkError):
+        irkmg.IrkBatch(gs, autotune=False, mode=0)
