@@ -90,10 +90,10 @@ void assemble_level(HostLevel& L, double nu, const std::vector<double>* wind_nod
 void build_patches(HostLevel& L);
 // Returns an empty string on success, else a description of the nesting failure.
 std::string build_transfer(const HostLevel& coarse, HostLevel& fine, const int64_t* parent);
-// Dense coarse operator with pinned pressures, inverted by Gauss--Jordan with partial
-// pivoting; returns false on a zero pivot.  inv is column-major N x N, internal layout.
-bool coarse_inverse(const HostLevel& L, int r, const double* A, double dt,
-                    std::vector<double>& inv);
+// Dense coarse operator (row-major N x N, internal layout) with the pressure of vertex 0
+// pinned in every stage; *max_abs = its largest entry in magnitude.
+void coarse_matrix(const HostLevel& L, int r, const double* A, double dt, std::vector<double>& J,
+                   double* max_abs);
 
 // ------------------------------------------------------------- stage eigenbasis
 // Real block diagonalisation A = W T W^{-1} of the Butcher matrix.  T is block diagonal
@@ -289,6 +289,12 @@ template <typename T>
 hipError_t eig_extract(const DevLevel& L, const StageBasis<T>& sb, int b, const int32_t* tmp_ld,
                        const int64_t* tmp_off, int64_t off0, const T* tmp, int64_t p0, int64_t p1,
                        hipStream_t s);
+// In-place inverse of a dense row-major N x N matrix on the device by Gauss--Jordan with
+// partial pivoting (ties to the smaller row); a pivot below tol sets *fail.  colk:
+// N-value workspace, swp: N-entry workspace.
+hipError_t dense_inverse(double* J, int64_t N, double tol, double* colk, int64_t* swp, int* fail, hipStream_t s);
+// out (N x N) = transpose of in (N x N)
+hipError_t transpose(const double* in, double* out, int64_t N, hipStream_t s);
 hipError_t coarse_gemv(const double* inv, int64_t N, const double* b, double* x,
                        const int64_t* pins, int npins, double* part, hipStream_t s);
 int coarse_split();  // number of partial sums per row used by coarse_gemv

@@ -982,17 +982,29 @@ static irk_status setup_impl(const irk_mesh_level* lv, int nlevels, const irk_ta
   HIPCHK(hipMemcpyAsync(&hfail, dfail, sizeof(int), hipMemcpyDeviceToHost, s));
   HIPCHK(hipStreamSynchronize(s));
   if (hfail) return fail(IRK_ESINGULAR, "zero pivot in a patch factorisation");
-  // ---- coarse inverse (and of the transpose)
+  // ---- coarse inverse (and of the transpose): dense operator assembled on the host,
+  // inverted on the GPU in place (row-major result = column-major inverse of the
+  // transpose), transposed for the column-major inverse
   {
-    std::vector<double> inv, invT;
-    if (!coarse_inverse(h->host[0], r, h->A, dt, inv))
-      return fail(IRK_ESINGULAR, "singular coarse operator");
+    std::vector<double> Jc;
+    double scale = 0;
+    coarse_matrix(h->host[0], r, h->A, dt, Jc, &scale);
     const int64_t N0 = h->dev[0].N;
-    invT.resize(inv.size());
-    for (int64_t i = 0; i < N0; ++i)
-      for (int64_t j = 0; j < N0; ++j) invT[j * N0 + i] = inv[i * N0 + j];
-    CHK(upload(h, &h->coarse_inv, inv, s));
-    CHK(upload(h, &h->coarse_invT, invT, s));
+    CHK(upload(h, &h->coarse_invT, Jc, s));
+    Jc.clear();
+    Jc.shrink_to_fit();
+    double* colk;
+    int64_t* swp;
+    CHK(dalloc(h, &colk, (size_t)N0));
+    CHK(dalloc(h, &swp, (size_t)N0));
+    HIPCHK(hipMemsetAsync(dfail, 0, sizeof(int), s));
+    HIPCHK(k::dense_inverse(h->coarse_invT, N0, std::max(1e-300, 1e-14 * scale), colk, swp, dfail, s));
+    int cfail = 0;
+    HIPCHK(hipMemcpyAsync(&cfail, dfail, sizeof(int), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    if (cfail) return fail(IRK_ESINGULAR, "singular coarse operator");
+    CHK(dalloc(h, &h->coarse_inv, (size_t)N0 * N0));
+    HIPCHK(k::transpose(h->coarse_invT, h->coarse_inv, N0, s));
     CHK(dalloc(h, &h->cb, N0));
     CHK(dalloc(h, &h->cx, N0));
     CHK(dalloc(h, &h->cpart, (size_t)N0 * k::coarse_split()));

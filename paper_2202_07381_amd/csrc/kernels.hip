@@ -658,6 +658,95 @@ __global__ __launch_bounds__(kBlock) void k_spmv_nodes(
                                in, out, add);
 }
 
+// ------------------------------------------------------- coarse operator inverse
+// Gauss--Jordan step k, part 1 (one workgroup): the largest |J[i][k]|, i >= k (ties to
+// the smaller row), becomes the pivot row; rows k and piv are swapped, column k is
+// saved, and row k is scaled so that it holds the inverse's pivot row.
+__global__ __launch_bounds__(1024) void k_gj_pivot(double* __restrict__ J, int64_t N, int64_t k, double tol,
+                                                   double* __restrict__ colk, int64_t* __restrict__ swp,
+                                                   int* __restrict__ fail) {
+  __shared__ double sb[1024];
+  __shared__ int64_t si[1024];
+  const int tid = threadIdx.x;
+  double best = -1.0;
+  int64_t bi = k;
+  for (int64_t i = k + tid; i < N; i += blockDim.x) {
+    const double a = fabs(J[i * N + k]);
+    if (a > best) {
+      best = a;
+      bi = i;
+    }
+  }
+  sb[tid] = best;
+  si[tid] = bi;
+  __syncthreads();
+  for (int w = blockDim.x / 2; w > 0; w >>= 1) {
+    if (tid < w && (sb[tid + w] > sb[tid] || (sb[tid + w] == sb[tid] && si[tid + w] < si[tid]))) {
+      sb[tid] = sb[tid + w];
+      si[tid] = si[tid + w];
+    }
+    __syncthreads();
+  }
+  const int64_t piv = si[0];
+  if (!(sb[0] > tol)) {
+    if (tid == 0) atomicMax(fail, 1);
+    return;  // uniform: every later step is void and the caller reports the failure
+  }
+  if (piv != k)
+    for (int64_t j = tid; j < N; j += blockDim.x) {
+      const double t = J[k * N + j];
+      J[k * N + j] = J[piv * N + j];
+      J[piv * N + j] = t;
+    }
+  __syncthreads();
+  const double ip = 1.0 / J[k * N + k];
+  for (int64_t i = tid; i < N; i += blockDim.x) colk[i] = i == k ? 0.0 : J[i * N + k];
+  __syncthreads();
+  for (int64_t j = tid; j < N; j += blockDim.x) J[k * N + j] = (j == k ? 1.0 : J[k * N + j]) * ip;
+  if (tid == 0) swp[k] = piv;
+}
+
+// part 2: every other row i loses colk[i] times the scaled pivot row (column k starts
+// from zero); rows with a zero multiplier are left as they are
+__global__ __launch_bounds__(kBlock) void k_gj_update(double* __restrict__ J, int64_t N, int64_t k,
+                                                      const double* __restrict__ colk, const int* __restrict__ fail) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= N * N || *fail) return;
+  const int64_t i = e / N, j = e - i * N;
+  const double f = colk[i];
+  if (i == k || f == 0.0) return;
+  const double base = j == k ? 0.0 : J[e];
+  J[e] = base - f * J[k * N + j];
+}
+
+// the recorded row swaps undone as column swaps, last first (one workgroup)
+__global__ __launch_bounds__(1024) void k_gj_unswap(double* __restrict__ J, int64_t N,
+                                                    const int64_t* __restrict__ swp, const int* __restrict__ fail) {
+  if (*fail) return;
+  for (int64_t k = N - 1; k >= 0; --k) {
+    const int64_t q = swp[k];
+    if (q != k)
+      for (int64_t i = threadIdx.x; i < N; i += blockDim.x) {
+        const double t = J[i * N + k];
+        J[i * N + k] = J[i * N + q];
+        J[i * N + q] = t;
+      }
+    __syncthreads();
+  }
+}
+
+__global__ __launch_bounds__(kBlock) void k_transpose(const double* __restrict__ in, double* __restrict__ out,
+                                                      int64_t N) {
+  __shared__ double tile[32][33];
+  const int64_t bx = blockIdx.x * 32, by = blockIdx.y * 32;
+  const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;  // 32 x 8 threads
+  for (int yy = ty; yy < 32; yy += 8)
+    if (by + yy < N && bx + tx < N) tile[yy][tx] = in[(by + yy) * N + bx + tx];
+  __syncthreads();
+  for (int yy = ty; yy < 32; yy += 8)
+    if (bx + yy < N && by + tx < N) out[(bx + yy) * N + by + tx] = tile[tx][yy];
+}
+
 // ------------------------------------------------------------------- coarse solve
 // x = inv * b with inv column-major N x N.  Grid (ceil(N/64), kCoarseSplit); each
 // wavefront owns 64 rows and a contiguous range of columns; partial sums are reduced
@@ -1265,6 +1354,22 @@ hipError_t prolong_add(const DevLevel& F, const DevLevel& C, const DevOps<T>& fo
   IRK_DISPATCH_DR(F.dim, F.r, (k_spmv_nodes<DD, RR, T><<<dim3(g), dim3(kBlock), 0, s>>>(F.nfree, F.nv, F.offV, C.offV, F.pu_ptr, F.pu_col,
                                                   fops.pu_val, F.pp_ptr, F.pp_col, fops.pp_val, xc,
                                                   xf, 1)));
+  return hipGetLastError();
+}
+
+hipError_t dense_inverse(double* J, int64_t N, double tol, double* colk, int64_t* swp, int* fail, hipStream_t s) {
+  const unsigned gu = (unsigned)((N * N + kBlock - 1) / kBlock);
+  for (int64_t k = 0; k < N; ++k) {
+    k_gj_pivot<<<dim3(1), dim3(1024), 0, s>>>(J, N, k, tol, colk, swp, fail);
+    k_gj_update<<<dim3(gu), dim3(kBlock), 0, s>>>(J, N, k, colk, fail);
+  }
+  k_gj_unswap<<<dim3(1), dim3(1024), 0, s>>>(J, N, swp, fail);
+  return hipGetLastError();
+}
+
+hipError_t transpose(const double* in, double* out, int64_t N, hipStream_t s) {
+  const unsigned g = (unsigned)((N + 31) / 32);
+  k_transpose<<<dim3(g, g), dim3(256), 0, s>>>(in, out, N);
   return hipGetLastError();
 }
 

@@ -621,12 +621,12 @@ std::string build_transfer(const HostLevel& C, HostLevel& F, const int64_t* pare
 }
 
 // ---------------------------------------------------------------- coarse inverse
-bool coarse_inverse(const HostLevel& L, int r, const double* A, double dt,
-                    std::vector<double>& inv) {
+void coarse_matrix(const HostLevel& L, int r, const double* A, double dt, std::vector<double>& J,
+                   double* max_abs) {
   const int d = L.dim;
   const int64_t offV = L.nfree * d * r;
   const int64_t N = offV + L.nv * r;
-  std::vector<double> J((size_t)N * N, 0.0);  // row-major
+  J.assign((size_t)N * N, 0.0);  // row-major
   auto vel = [&](int64_t i, int c, int s) { return (i * d + c) * r + s; };
   auto pre = [&](int64_t v, int s) { return offV + v * r + s; };
   for (int64_t i = 0; i < L.nfree; ++i) {
@@ -657,42 +657,9 @@ bool coarse_inverse(const HostLevel& L, int r, const double* A, double dt,
     }
     J[q * N + q] = 1.0;
   }
-  // in-place Gauss--Jordan with partial pivoting
-  std::vector<int64_t> swp(N);
   double scale = 0;
   for (double v : J) scale = std::max(scale, std::fabs(v));
-  for (int64_t k = 0; k < N; ++k) {
-    int64_t piv = k;
-    double best = std::fabs(J[k * N + k]);
-    for (int64_t i = k + 1; i < N; ++i)
-      if (std::fabs(J[i * N + k]) > best) {
-        best = std::fabs(J[i * N + k]);
-        piv = i;
-      }
-    if (!(best > 1e-300) || best < 1e-14 * scale) return false;
-    swp[k] = piv;
-    if (piv != k)
-      for (int64_t j = 0; j < N; ++j) std::swap(J[k * N + j], J[piv * N + j]);
-    const double ip = 1.0 / J[k * N + k];
-    J[k * N + k] = 1.0;
-    for (int64_t j = 0; j < N; ++j) J[k * N + j] *= ip;
-    for (int64_t i = 0; i < N; ++i) {
-      if (i == k) continue;
-      const double f = J[i * N + k];
-      if (f == 0.0) continue;
-      J[i * N + k] = 0.0;
-      double* ri = &J[i * N];
-      const double* rk = &J[k * N];
-      for (int64_t j = 0; j < N; ++j) ri[j] -= f * rk[j];
-    }
-  }
-  for (int64_t k = N - 1; k >= 0; --k)
-    if (swp[k] != k)
-      for (int64_t i = 0; i < N; ++i) std::swap(J[i * N + k], J[i * N + swp[k]]);
-  inv.resize((size_t)N * N);
-  for (int64_t i = 0; i < N; ++i)
-    for (int64_t j = 0; j < N; ++j) inv[j * N + i] = J[i * N + j];  // column-major
-  return true;
+  *max_abs = scale;
 }
 
 }  // namespace irk
