@@ -283,6 +283,12 @@ template <typename T>
 hipError_t patch_factor_range(const DevLevel& L, const DevOps<T>& ops, int R, const double* coef,
                               double dt, const int32_t* ld, const int64_t* off, T* out, int64_t p0,
                               int64_t p1, int64_t off0, int nmax, int* d_fail, hipStream_t s);
+// Complex eigenvalue pair block b (a + ib): invert C = M_v + dt (a - ib) S_v per patch in
+// LDS and write (Re, Im) of C^{-1} into the factored layout; zr = dt a, zi = -dt b.
+// hipErrorInvalidConfiguration when the n_s x n_s complex matrix does not fit in LDS.
+template <typename T>
+hipError_t patch_factor_cplx(const DevLevel& L, const DevOps<T>& ops, double zr, double zi, int b, int nmax,
+                             int* d_fail, hipStream_t s);
 // Copy eigen-block b of patches [p0, p1) from dense inverses (layout of
 // patch_factor_range with tmp_ld / tmp_off / off0) into the factored layout of L.inv.
 template <typename T>

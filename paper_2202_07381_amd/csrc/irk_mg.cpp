@@ -602,6 +602,11 @@ static irk_status factor_level(irk_mg* h, int l, const DevOps<T>& ops, double dt
   const int64_t budget = ((int64_t)2 << 30) / (int64_t)sizeof(T);
   for (int b = 0; b < E.nblk; ++b) {
     const int m = E.type[b];
+    if (m == 2 && 2.0 * max_ns * max_ns * sizeof(T) + 2.0 * max_ns * sizeof(T) + max_ns * 4.0 + 64 <= 160 * 1024) {
+      // complex pair small enough for LDS: inverted as the n_s x n_s complex matrix
+      HIPCHK(k::patch_factor_cplx<T>(D, ops, dt * E.Tb[b][0], -dt * E.Tb[b][1], b, max_ns, dfail, s));
+      continue;
+    }
     std::vector<int32_t> tld(np);
     std::vector<int64_t> toff(np + 1, 0);
     for (int64_t p = 0; p < np; ++p) {

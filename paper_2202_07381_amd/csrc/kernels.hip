@@ -567,6 +567,153 @@ __global__ __launch_bounds__(kWaves * 64) void k_patch_apply(
                               W, Y, transpose, D, R);
 }
 
+// A complex eigenvalue pair's block I (x) M_v + dt [[a, b], [-b, a]] (x) S_v is the real
+// form of the complex matrix C = M_v + dt (a - ib) S_v, and its inverse's first block
+// column is (Re C^{-1}; Im C^{-1}).  So the pair block is inverted as the n_s x n_s complex
+// matrix: half the flops and a quarter of the LDS of the real 2 n_s block.  One workgroup
+// per patch, complex Gauss--Jordan with partial pivoting on |z|^2 (ties to the smaller
+// row) in LDS, result written straight into the factored layout as (re, im) pairs.
+template <int D, typename T>
+__global__ __launch_bounds__(kBlock) void k_patch_factor_cplx(
+    int64_t npatch, const int32_t* __restrict__ pn_ptr, const int32_t* __restrict__ pvv_ptr,
+    const int32_t* __restrict__ pvv, const int32_t* __restrict__ pvp, const T* __restrict__ sM,
+    const T* __restrict__ sL, const T* __restrict__ b_val, T zr, T zi, int blk, irk::StageBasis<T> sb,
+    const int32_t* __restrict__ p_ld, const int64_t* __restrict__ p_inv_off, T* __restrict__ inv,
+    int* __restrict__ fail) {
+  constexpr int VEC = Vec16<T>::n;
+  extern __shared__ unsigned char smem_raw[];
+  const int64_t p = blockIdx.x;
+  if (p >= npatch) return;
+  const int nn = pn_ptr[p + 1] - pn_ptr[p];
+  const int n = D * nn + 1;
+  T* Ar = reinterpret_cast<T*>(smem_raw);  // real parts, row-major n x n
+  T* Ai = Ar + (size_t)n * n;              // imaginary parts
+  T* cr = Ai + (size_t)n * n;              // saved pivot column
+  T* ci = cr + n;
+  int* perm = reinterpret_cast<int*>(ci + n);
+  __shared__ int s_piv;
+  __shared__ T s_best;
+  const int tid = threadIdx.x;
+  for (int e = tid; e < n * n; e += blockDim.x) Ar[e] = Ai[e] = T(0);
+  __syncthreads();
+  const int32_t v0 = pvv_ptr[p], v1 = pvv_ptr[p + 1];
+  for (int32_t e = v0 + tid; e < v1; e += blockDim.x) {
+    const int la = pvv[3 * e], lb = pvv[3 * e + 1], pos = pvv[3 * e + 2];
+    const T m = sM[pos], l = sL[pos];
+    for (int c = 0; c < D; ++c) {
+      Ar[(c * nn + la) * n + (c * nn + lb)] = m + zr * l;
+      Ai[(c * nn + la) * n + (c * nn + lb)] = zi * l;
+    }
+  }
+  const int32_t n0 = pn_ptr[p];
+  for (int la = tid; la < nn; la += blockDim.x) {
+    const int pos = pvp[n0 + la];
+    if (pos < 0) continue;
+    for (int c = 0; c < D; ++c) {
+      const T bv = b_val[(int64_t)pos * D + c];
+      Ar[(c * nn + la) * n + D * nn] = zr * bv;
+      Ai[(c * nn + la) * n + D * nn] = zi * bv;
+      Ar[(D * nn) * n + (c * nn + la)] = zr * bv;
+      Ai[(D * nn) * n + (c * nn + la)] = zi * bv;
+    }
+  }
+  __syncthreads();
+  for (int kk = 0; kk < n; ++kk) {
+    if (tid < 64) {
+      T best = T(-1);
+      int bi = kk;
+      for (int i = kk + tid; i < n; i += 64) {
+        const T a2 = Ar[i * n + kk] * Ar[i * n + kk] + Ai[i * n + kk] * Ai[i * n + kk];
+        if (a2 > best) {
+          best = a2;
+          bi = i;
+        }
+      }
+      for (int off = 32; off > 0; off >>= 1) {
+        const T ob = __shfl_xor(best, off, 64);
+        const int oi = __shfl_xor(bi, off, 64);
+        if (ob > best || (ob == best && oi < bi)) {
+          best = ob;
+          bi = oi;
+        }
+      }
+      if (tid == 0) {
+        s_piv = bi;
+        s_best = best;
+        perm[kk] = bi;
+      }
+    }
+    __syncthreads();
+    const int piv = s_piv;
+    if (!(s_best > T(0))) {
+      if (tid == 0) atomicMax(fail, 1);
+      return;  // uniform across the workgroup
+    }
+    if (piv != kk)
+      for (int j = tid; j < n; j += blockDim.x) {
+        T t = Ar[kk * n + j];
+        Ar[kk * n + j] = Ar[piv * n + j];
+        Ar[piv * n + j] = t;
+        t = Ai[kk * n + j];
+        Ai[kk * n + j] = Ai[piv * n + j];
+        Ai[piv * n + j] = t;
+      }
+    __syncthreads();
+    // 1 / pivot
+    const T pr = Ar[kk * n + kk], pim = Ai[kk * n + kk];
+    const T den = pr * pr + pim * pim;
+    const T ipr = pr / den, ipi = -pim / den;
+    for (int i = tid; i < n; i += blockDim.x) {
+      cr[i] = Ar[i * n + kk];
+      ci[i] = Ai[i * n + kk];
+    }
+    __syncthreads();
+    for (int j = tid; j < n; j += blockDim.x) {
+      const T xr = j == kk ? T(1) : Ar[kk * n + j];
+      const T xi = j == kk ? T(0) : Ai[kk * n + j];
+      Ar[kk * n + j] = xr * ipr - xi * ipi;
+      Ai[kk * n + j] = xr * ipi + xi * ipr;
+    }
+    __syncthreads();
+    for (int e = tid; e < n * n; e += blockDim.x) {
+      const int i = e / n, j = e - i * n;
+      if (i == kk) continue;
+      const T br = (j == kk) ? T(0) : Ar[e];
+      const T bi2 = (j == kk) ? T(0) : Ai[e];
+      const T ur = Ar[kk * n + j], ui = Ai[kk * n + j];
+      Ar[e] = br - (cr[i] * ur - ci[i] * ui);
+      Ai[e] = bi2 - (cr[i] * ui + ci[i] * ur);
+    }
+    __syncthreads();
+  }
+  for (int kk = n - 1; kk >= 0; --kk) {
+    const int q = perm[kk];
+    if (q != kk)
+      for (int i = tid; i < n; i += blockDim.x) {
+        T t = Ar[i * n + kk];
+        Ar[i * n + kk] = Ar[i * n + q];
+        Ar[i * n + q] = t;
+        t = Ai[i * n + kk];
+        Ai[i * n + kk] = Ai[i * n + q];
+        Ai[i * n + q] = t;
+      }
+    __syncthreads();
+  }
+  // factored layout: column j of the patch, the block's rows at its row offset
+  const int lc = p_ld[p];
+  int rowoff = 0;
+  for (int q = 0; q < blk; ++q) rowoff += irk::eig_block_rows(sb.type[q], n, VEC);
+  const int rows = irk::eig_block_rows(2, n, VEC);
+  T* __restrict__ out = inv + p_inv_off[p] + rowoff;
+  for (int e = tid; e < n * rows; e += blockDim.x) {
+    const int j = e / rows, i = e - j * rows;
+    const int c = i >> 1;
+    T v = T(0);
+    if (c < n) v = (i & 1) ? Ai[c * n + j] : Ar[c * n + j];
+    out[(int64_t)j * lc + i] = v;
+  }
+}
+
 // Copy eigen-block b of every patch in [p0, p1) from its dense inverse (column-major
 // m n_s x ldt at tmp + tmp_off[p] - off0, m = 1 or 2 stages) into the factored layout:
 // n_s columns of lc = p_ld[p] values, the block's rows starting at its row offset.  A
@@ -1264,6 +1411,31 @@ hipError_t patch_factor_range(const DevLevel& L, const DevOps<T>& ops, int R, co
 }
 
 template <typename T>
+hipError_t patch_factor_cplx(const DevLevel& L, const DevOps<T>& ops, double zr, double zi, int b, int nmax,
+                             int* d_fail, hipStream_t s) {
+  const size_t n = (size_t)nmax;
+  const size_t lds = 2 * n * n * sizeof(T) + 2 * n * sizeof(T) + n * sizeof(int) + 64;
+  if (lds > 160 * 1024) return hipErrorInvalidConfiguration;
+  const StageBasis<T>& sb = basis_of<T>(L);
+  if (L.dim == 2) {
+    auto kern = k_patch_factor_cplx<2, T>;
+    hipError_t e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+    kern<<<dim3((unsigned)L.npatch), dim3(kBlock), lds, s>>>(L.npatch, L.pn_ptr, L.pvv_ptr, L.pvv, L.pvp, ops.s_M,
+                                                          ops.s_L, ops.b_val, (T)zr, (T)zi, b, sb, L.p_ld,
+                                                          L.p_inv_off, reinterpret_cast<T*>(L.inv), d_fail);
+  } else {
+    auto kern = k_patch_factor_cplx<3, T>;
+    hipError_t e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+    kern<<<dim3((unsigned)L.npatch), dim3(kBlock), lds, s>>>(L.npatch, L.pn_ptr, L.pvv_ptr, L.pvv, L.pvp, ops.s_M,
+                                                          ops.s_L, ops.b_val, (T)zr, (T)zi, b, sb, L.p_ld,
+                                                          L.p_inv_off, reinterpret_cast<T*>(L.inv), d_fail);
+  }
+  return hipGetLastError();
+}
+
+template <typename T>
 hipError_t eig_extract(const DevLevel& L, const StageBasis<T>& sb, int b, const int32_t* tmp_ld,
                        const int64_t* tmp_off, int64_t off0, const T* tmp, int64_t p0, int64_t p1,
                        hipStream_t s) {
@@ -1543,6 +1715,8 @@ hipError_t mass_apply(const DevLevel& L, const double* st, double* out, hipStrea
   template hipError_t patch_factor_range<T>(const DevLevel&, const DevOps<T>&, int, const double*, \
                                             double, const int32_t*, const int64_t*, T*, int64_t,   \
                                             int64_t, int64_t, int, int*, hipStream_t);             \
+  template hipError_t patch_factor_cplx<T>(const DevLevel&, const DevOps<T>&, double, double, int, int, \
+                                           int*, hipStream_t);                                        \
   template hipError_t eig_extract<T>(const DevLevel&, const StageBasis<T>&, int, const int32_t*,  \
                                      const int64_t*, int64_t, const T*, int64_t, int64_t,          \
                                      hipStream_t);                                                 \

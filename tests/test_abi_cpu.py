@@ -142,3 +142,22 @@ def test_stage_basis_rejects(A):
     with pytest.raises(irkmg.IrkError) as ei:
         irkmg.irk_stage_basis(A)
     assert ei.value.status == irkmg.IRK_EINVAL
+
+
+def test_stage_basis_gauss4():
+    """The 4-stage Gauss collocation tableau (built from Gauss--Legendre nodes) has two
+    complex eigenvalue pairs; the decomposition reproduces A and LAPACK's spectrum."""
+    from paper_2202_07381_amd import irkmg
+
+    x, _ = np.polynomial.legendre.leggauss(4)
+    c = 0.5 * (x + 1.0)
+    V = np.vander(c, 4, increasing=True)
+    m = np.arange(1, 5)
+    A = (c[:, None] ** m[None, :] / m[None, :]) @ np.linalg.inv(V)
+    assert np.allclose(A.sum(axis=1), c, atol=1e-14)
+    W, Wi, T = irkmg.irk_stage_basis(A)
+    assert np.abs(W @ T @ Wi - A).max() < 1e-13
+    assert T[0, 1] > 0 and T[2, 3] > 0  # two pairs
+    ev = np.concatenate([[T[0, 0] + 1j * T[0, 1], T[0, 0] - 1j * T[0, 1]],
+                         [T[2, 2] + 1j * T[2, 3], T[2, 2] - 1j * T[2, 3]]])
+    assert np.abs(np.sort_complex(ev) - np.sort_complex(np.linalg.eigvals(A))).max() < 1e-12

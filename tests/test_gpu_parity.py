@@ -245,3 +245,87 @@ def test_patch_form_selection():
             k = to_dev(k0)
             g.irk_level_sweep(lev, to_dev(F), k, transpose=tr)
             assert relerr(to_host(k), H.smoothers[lev].sweep(F, k0, J.T if tr else J, tr)) < 1e-11
+
+
+# ------------------------------------------------------------- edge cases
+def _gauss_collocation(r):
+    """r-stage Gauss collocation tableau from the Gauss--Legendre nodes: a_ij = int_0^{c_i}
+    l_j(t) dt and b_j = int_0^1 l_j(t) dt for the Lagrange basis l_j on the nodes."""
+    x, _ = np.polynomial.legendre.leggauss(r)
+    c = 0.5 * (x + 1.0)
+    V = np.vander(c, r, increasing=True)  # V[i, m] = c_i^m
+    Vinv = np.linalg.inv(V)               # l_j(t) = sum_m Vinv[m, j] t^m
+    m = np.arange(1, r + 1)
+    A = (c[:, None] ** m[None, :] / m[None, :]) @ Vinv
+    b = (1.0 / m) @ Vinv
+    return A, b, c
+
+
+def _custom_case(A, b, c, dt, nlev=3):
+    from oracle.multigrid import Hierarchy
+    from paper_2202_07381_amd import irkmg
+    from paper_2202_07381_amd import workloads as wl
+
+    lv = wl.square_hierarchy(4, nlev)
+    H = Hierarchy(lv, A, dt, 1.0)
+    return lv, H
+
+
+@pytest.mark.parametrize("kind", ["gauss4", "sdirk2"])
+def test_custom_tableaux(kind):
+    """r = 4 (two complex eigenvalue pairs, the largest stage count) and a defective A (a
+    2-stage SDIRK, repeated eigenvalue): automatic patch form factored resp. dense, the
+    factored form rejected for the defective A; V-cycle and FGMRES against the oracle."""
+    from oracle.fgmres import fgmres
+    from paper_2202_07381_amd import irkmg
+    from paper_2202_07381_amd import workloads as wl
+
+    if kind == "gauss4":
+        A, b, c = _gauss_collocation(4)
+        form_expected = 1
+    else:
+        g_ = 1.0 - 1.0 / np.sqrt(2.0)
+        A = np.array([[g_, 0.0], [1.0 - g_, g_]])
+        b, c = A[-1].copy(), A.sum(axis=1)
+        form_expected = 0
+        with pytest.raises(irkmg.IrkError):
+            irkmg.IrkMG(wl.square_hierarchy(4, 2), A, b, c, 1 / 32, 1.0, patch_form=1)
+    lv, H = _custom_case(A, b, c, 1 / 32)
+    say(f"[custom] {kind} setup")
+    g = irkmg.IrkMG(lv, A, b, c, 1 / 32, 1.0)
+    assert g.irk_mg_patch_form() == form_expected
+    S = H.finest
+    r = np.random.default_rng(41).standard_normal(S.n)
+    z = torch.zeros(S.n, dtype=torch.float64, device="cuda")
+    g.irk_mg_vcycle(to_dev(r), z)
+    assert relerr(to_host(z), H.vcycle(r)) < coarse_tol(H)
+    f = wl.forcing_2d(1)
+    F = S.rhs([S.th.interpolate(f, 0.0)] * S.r, np.zeros(S.th.nvel), np.zeros(S.th.nverts))
+    k = torch.zeros(S.n, dtype=torch.float64, device="cuda")
+    info = g.irk_fgmres_solve(to_dev(F), k, rtol=1e-8, maxit=200)
+    xo, io = fgmres(S.apply, H.vcycle, F, np.zeros_like(F), 1e-8, 200, 30, project=S.project_pressure_mean)
+    say(f"[custom] {kind} its={info['iterations']} oracle={io.iterations}")
+    assert info["converged"] and info["iterations"] == io.iterations
+    assert relerr(to_host(k), xo) < 1e-10
+    g.close()
+
+
+def test_single_level_hierarchy():
+    """One level: the V-cycle is the coarse direct solve, so FGMRES converges in one
+    iteration and matches the oracle's solve."""
+    from oracle.fgmres import fgmres
+    from paper_2202_07381_amd import irkmg
+
+    lv, H = _custom_case(*irkmg.irk_tableau_builtin("radauIIA", 2), 1 / 16, nlev=1)
+    A, b, c = irkmg.irk_tableau_builtin("radauIIA", 2)
+    g = irkmg.IrkMG(lv, A, b, c, 1 / 16, 1.0)
+    S = H.finest
+    # a consistent right-hand side (the divergence rows of J k sum to zero per stage)
+    F = S.J @ np.random.default_rng(42).standard_normal(S.n)
+    k = torch.zeros(S.n, dtype=torch.float64, device="cuda")
+    say("[single level] solve")
+    info = g.irk_fgmres_solve(to_dev(F), k, rtol=1e-10, maxit=20)
+    xo, io = fgmres(S.apply, H.vcycle, F, np.zeros_like(F), 1e-10, 20, 30, project=S.project_pressure_mean)
+    assert info["converged"] and info["iterations"] == io.iterations <= 2
+    assert relerr(to_host(k), xo) < coarse_tol(H)
+    g.close()
