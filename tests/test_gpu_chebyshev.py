@@ -74,3 +74,22 @@ def test_chebyshev_options_rejected():
     with pytest.raises(irkmg.IrkError) as e:
         irkmg.IrkBatch([g], autotune=False)
     assert e.value.status == irkmg.IRK_EINVAL
+
+
+@pytest.mark.parametrize("case", ["c1", "oseen", "cross"])
+def test_chebyshev_adjoint_solve_matches_oracle(case):
+    """The transposed system J^T lam = G (the adjoint solve) preconditioned by the
+    transposed Chebyshev V-cycle: equal iteration counts and solutions to 1e-10."""
+    from oracle.fgmres import fgmres
+
+    g, H = gpu_of(case, smoother=1), oracle_of(case, smoother="chebyshev")
+    S = H.finest
+    G = S.J.T @ np.random.default_rng(34).standard_normal(S.n)  # consistent right-hand side
+    for rtol, maxit in ((1e-8, 200), (1e-30, 5)):
+        say(f"[cheb adjoint] case={case} rtol={rtol}")
+        lam = torch.zeros(S.n, dtype=torch.float64, device="cuda")
+        info = g.irk_adjoint_solve(to_dev(G), lam, rtol=rtol, maxit=maxit)
+        xo, io = fgmres(S.apply_transpose, H.vcycle_transpose, G, np.zeros_like(G), rtol, maxit, 30,
+                        project=S.project_pressure_mean)
+        assert info["iterations"] == io.iterations
+        assert relerr(to_host(lam), xo) < 1e-10

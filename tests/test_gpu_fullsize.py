@@ -9,6 +9,13 @@
   * 512 x 512 Oseen, Gauss(2), nu = 0.01, dt = 5e-3, unit-speed wind (4,712,454
     unknowns), FP32 patches inside FP64 FGMRES: residual of the GPU solution
     recomputed with the oracle's scalar blocks, stage by stage (<= 1e-8).
+  * The 2D Stokes experiment of Sec. 5.1 at l = 5: crossed 8 x 8 mesh refined 5 times,
+    RadauIIA(3), dt = 0.5 / 256, nu = 1, Chebyshev relaxation, boundary data from the
+    exact solution (3,534,345 unknowns): P2 node coordinates equal the oracle's; F of
+    the first step (irk_rhs + irk_rhs_dirichlet) against the oracle's per row (64 eps
+    times the sum of the moduli of the row's terms, the (dt A)^{-1} term scaled by
+    cond(A)); the solution of that step, at the stopping rule of the experiment, has
+    the oracle operator's residual within the rule.
   * 32^3 Stokes, RadauIIA(2), dt = 1e-2, 4 steps (1,572,156 unknowns): gradient of the
     tracking loss with respect to the 27 forcing coefficients (one random direction)
     and nu against central finite differences with h = 1e-6 (<= 1e-6 relative).
@@ -154,6 +161,76 @@ def test_oseen512_fullsize():
     res = np.linalg.norm(Fh - Jk) / np.linalg.norm(Fh)
     say(f"[full512] oracle-residual={res:.2e}")
     assert res <= 1e-8
+    g.close()
+
+
+def test_t1_crossed_l5_fullsize():
+    from oracle.fem import TaylorHood
+    from oracle.stage import StageSystem
+    from oracle.tableau import tableau
+    from paper_2202_07381_amd import irkmg
+    from paper_2202_07381_amd import workloads as wl
+
+    levels = wl.crossed_hierarchy(8, 6)
+    A, b, c = irkmg.irk_tableau_builtin("radauIIA", 3)
+    nsteps = 256
+    dt = 0.5 / nsteps
+    say("[t1-l5] setup FP64, Chebyshev")
+    g = irkmg.IrkMG(levels, A, b, c, dt, 1.0, weighting=0, smoother=1, interval=(2.0, 8.0))
+    N = g.irk_mg_ndofs()
+    assert N == 3 * 1178115  # free velocities and all pressures; 1,182,211 per stage with the boundary
+    say("[t1-l5] oracle stage system")
+    th = TaylorHood(levels[-1].xyz, levels[-1].cells)
+    Ao = tableau("radauIIA", 3)[0]
+    S = StageSystem(th, Ao, dt, 1.0)
+    assert S.n == N
+    nodes, free = g.irk_mg_p2_nodes()
+    assert np.max(np.abs(nodes - th.node_xyz)) <= 1e-15 and np.array_equal(free, th.free)
+
+    def exact(x, t):
+        e = np.exp(-2.0 * np.pi ** 2 * t)
+        return e * np.stack([np.sin(np.pi * x[:, 0]) * np.cos(np.pi * x[:, 1]),
+                             -np.cos(np.pi * x[:, 0]) * np.sin(np.pi * x[:, 1])], axis=1)
+
+    gn = th.interpolate(exact, 0.0)
+    gst = [th.interpolate(exact, ci * dt) for ci in c]
+    u0 = th.free_velocity(gn)
+    p0 = np.zeros(th.nverts)
+    f0 = [np.zeros((th.nnodes, 2))] * 3
+    Fg = torch.zeros(N, dtype=torch.float64, device="cuda")
+    g.irk_rhs(to_dev(np.stack(f0).ravel()), to_dev(np.concatenate([u0, p0])), Fg)
+    g.irk_rhs_dirichlet(to_dev(gn.ravel()), to_dev(np.stack(gst).ravel()), Fg)
+    say("[t1-l5] oracle right-hand side")
+    F = S.rhs(f0, u0, p0) + S.rhs_dirichlet(gn, gst)
+    # per-row rounding bound: eps times the sum of the moduli of each row's terms; the
+    # boundary stage derivatives (dt A)^{-1} (G - g^n) carry cond(A) more
+    bnd, Mfb, Lfb, Btb = S._boundary_blocks()
+    G = np.stack([x[bnd] for x in gst])
+    Ainv = np.linalg.inv(dt * Ao)
+    kb = np.einsum("ij,jbc->ibc", np.abs(Ainv), np.abs(G - gn[bnd][None]))
+    condA = np.linalg.cond(Ao)
+    vel0 = abs(S.Lv) @ np.abs(u0)
+    pre0 = abs(S.B.T) @ np.abs(u0)
+    bound = []
+    for i in range(3):
+        vel = vel0 + np.concatenate([condA * (abs(Mfb) @ kb[i, :, cc]) + abs(Lfb) @ np.abs(G[i, :, cc])
+                                     for cc in range(2)])
+        pre = pre0 + sum(abs(Btb[cc]) @ np.abs(G[i, :, cc]) for cc in range(2))
+        bound.append(np.concatenate([vel, pre]))
+    bound = np.concatenate(bound)
+    Fh = to_host(Fg)
+    dev = np.abs(Fh - F)
+    say(f"[t1-l5] |F| = {np.linalg.norm(F):.3e}, max deviation / bound = {np.max(dev / np.maximum(bound, 1e-300)):.2e}")
+    assert np.all(dev <= 64 * np.finfo(float).eps * bound)
+    # the experiment's stopping rule: absolute 1e-2 N_t^-3 or relative 1e-8
+    rtol = max(1e-8, 1e-2 * nsteps ** -3.0 / np.linalg.norm(Fh))
+    k = torch.zeros(N, dtype=torch.float64, device="cuda")
+    say(f"[t1-l5] solve rtol={rtol:.3e}")
+    info = g.irk_fgmres_solve(Fg, k, rtol=rtol, maxit=300, restart=30)
+    assert info["converged"]
+    res = np.linalg.norm(Fh - S.J @ to_host(k)) / np.linalg.norm(Fh)
+    say(f"[t1-l5] its={info['iterations']} oracle-residual={res:.3e}")
+    assert res <= rtol * (1 + 1e-6)
     g.close()
 
 
