@@ -98,8 +98,15 @@ typedef struct irk_mg_opts {
                         1: factored through A = W T W^{-1} (irk_stage_basis):
                            r n_s^2 stored values, IRK_EINVAL from setup if A has
                            no well-conditioned real block diagonalisation;
-                        2: automatic: 1 when r >= 2 and the decomposition
-                           exists, else 0                                       */
+                        2: automatic: 3 for Stokes (wind NULL), else 1, when
+                           r >= 2 and the decomposition exists; else 0;
+                        3: symmetric factored (Stokes only, wind NULL): every
+                           block M_v + dt T_k S_v is then real or complex
+                           symmetric, and each block inverse is kept by its
+                           n_s/2 + 1 wrapped diagonals, r n_s (n_s/2 + 1)
+                           stored values; used on levels whose patches have at
+                           most 64 unknowns per stage (form 1 on the others
+                           under 2; IRK_EINVAL from setup under 3)              */
   int smoother;      /* relaxation: 0 = `pre`/`post` damped additive sweeps
                         k += omega W S r; 1 = `pre`/`post` steps of the Chebyshev
                         semi-iteration (Sec. 5.1) accelerating W S, S the additive
@@ -151,7 +158,8 @@ irk_status irk_mg_setup(const irk_mesh_level* levels, int nlevels, const irk_tab
                         double dt, double nu, const double* wind, const irk_mg_opts* opt,
                         void* stream, irk_mg** out);
 
-/* Patch form a handle uses (0 dense, 1 factored; see irk_mg_opts), or -1 for NULL. */
+/* Patch form of the finest level (0 dense, 1 factored, 3 symmetric factored; see
+ * irk_mg_opts), or -1 for NULL. */
 int irk_mg_patch_form(const irk_mg* h);
 
 /* Real block diagonalisation of a Butcher matrix, A = W T W^{-1}, as used by the

@@ -54,7 +54,7 @@ constexpr int PH_LOAD = 0, PH_R0 = 1, PH_N0 = 2, PH_RES = 3, PH_NRM = 4, PH_V0 =
 struct BLevel {
   int64_t nfree, nv, N, offV, npatch;
   int rb;     // row blocks of the patch apply (ceil(max stored column / 128))
-  int pform;  // patch form: 0 dense inverse, 1 factored through the stage eigenbasis
+  int pform;  // patch form: 0 dense inverse, 1 factored through the stage eigenbasis, 3 symmetric factored
   int dim, r;
   irk::StageBasis<double> sb;
   const int32_t *s_ptr, *s_col, *b_ptr, *b_col, *bt_ptr, *bt_col;
@@ -213,6 +213,11 @@ __device__ void patches(const BLevel& L, double* xs, double* xt, const double* i
     const int64_t idx = p0 + (int64_t)wave * ppw + q;
     if (idx >= L.npatch) break;
     const int p = L.sched[idx];
+    if (L.pform == 3) {
+      dev::patch_apply_sym_one<double, 4, 1>(p, lane, xs, xt, L.sb, L.p_nloc, L.p_inv_off, L.p_slot_off, L.p_gidx,
+                                             L.inv, in, nullptr, L.Y, 0, L.dim);
+      continue;
+    }
     if (L.pform == 1) {
       if (L.rb == 1)
         dev::patch_apply_eig_one<double, 1, 4, 1>(p, lane, xs, xt, L.sb, L.p_nloc, L.p_ld, L.p_inv_off, L.p_slot_off,

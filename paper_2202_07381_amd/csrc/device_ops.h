@@ -258,6 +258,51 @@ __device__ __forceinline__ void patch_apply_one(
   __builtin_amdgcn_wave_barrier();
 }
 
+// Gather of the (optionally weighted) patch residual into xs and its transform to the
+// stage eigenbasis into xt: xt[k ns + q] = sum_s Tin(k, s) xs[s ns + q] with Tin = W^{-1}
+// (forward) or W^T (transposed).
+template <typename T>
+__device__ __forceinline__ void eig_in(int lane, int n, int ns, int64_t so, T* xs, T* xt,
+                                       const irk::StageBasis<T>& sb, const int32_t* __restrict__ gidx,
+                                       const T* __restrict__ res, const T* __restrict__ W, int transpose) {
+  const int r = sb.r;
+  for (int i = lane; i < n; i += 64) {
+    const int32_t g = gidx[so + i];
+    xs[i] = W ? res[g] * W[g] : res[g];
+  }
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  for (int e = lane; e < n; e += 64) {
+    const int k = e / ns, q = e - k * ns;
+    T acc = T(0);
+    for (int s = 0; s < r; ++s) acc += (transpose ? sb.W[s * r + k] : sb.Winv[k * r + s]) * xs[s * ns + q];
+    xt[e] = acc;
+  }
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Back-transform of the block results in xs (forward W, transposed W^{-T}) and store of
+// the n local corrections in the patch's node-major slots.
+template <typename T>
+__device__ __forceinline__ void eig_out(int lane, int n, int ns, int64_t so, const T* xs,
+                                        const irk::StageBasis<T>& sb, T* __restrict__ Y, int transpose, int D) {
+  const int r = sb.r;
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  for (int e = lane; e < n; e += 64) {
+    const int s = e / ns, q = e - s * ns;
+    T acc = T(0);
+    for (int k = 0; k < r; ++k) acc += (transpose ? sb.Winv[k * r + s] : sb.W[s * r + k]) * xs[k * ns + q];
+    Y[so + node_major_slot(e, ns, D, r)] = acc;
+  }
+  // xs and xt are reused by this wavefront's next patch
+  __builtin_amdgcn_wave_barrier();
+}
+
 // Factored patch inverse (stage eigenbasis).  The stage-coupled patch matrix is
 // I (x) M_v + dt A (x) S_v (Sec. 3 restricted to the patch of Sec. 4.2); with
 // A = W T W^{-1} its inverse is (W (x) I) blockdiag_k(B_k^{-1}) (W^{-1} (x) I), where
@@ -301,23 +346,7 @@ __device__ __forceinline__ void patch_apply_eig_one(
   const int lc = p_ld[p];
   const int64_t so = p_slot_off[p];
   const T* __restrict__ Ap = inv + p_inv_off[p];
-  for (int i = lane; i < n; i += 64) {
-    const int32_t g = gidx[so + i];
-    xs[i] = W ? res[g] * W[g] : res[g];
-  }
-  __builtin_amdgcn_wave_barrier();
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-  // to the eigenbasis: xt[k ns + q] = sum_s Tin(k, s) xs[s ns + q]
-  for (int e = lane; e < n; e += 64) {
-    const int k = e / ns, q = e - k * ns;
-    T acc = T(0);
-    for (int s = 0; s < r; ++s) acc += (transpose ? sb.W[s * r + k] : sb.Winv[k * r + s]) * xs[s * ns + q];
-    xt[e] = acc;
-  }
-  __builtin_amdgcn_wave_barrier();
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  eig_in<T>(lane, n, ns, so, xs, xt, sb, gidx, res, W, transpose);
   // this lane's chunks: block, offset inside the block, inputs (u, v) per column
   int blk[RB], off[RB], iu[RB], iv[RB];
 #pragma unroll
@@ -442,18 +471,108 @@ __device__ __forceinline__ void patch_apply_eig_one(
       }
     }
   }
-  __builtin_amdgcn_wave_barrier();
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-  // back to the stages: forward W, transposed W^{-T}
-  for (int e = lane; e < n; e += 64) {
-    const int s = e / ns, q = e - s * ns;
-    T acc = T(0);
-    for (int k = 0; k < r; ++k) acc += (transpose ? sb.Winv[k * r + s] : sb.W[s * r + k]) * xs[k * ns + q];
-    Y[so + node_major_slot(e, ns, D, r)] = acc;
+  eig_out<T>(lane, n, ns, so, xs, sb, Y, transpose, D);
+}
+
+// Symmetric factored patch inverse.  For a symmetric spatial operator (Stokes: K
+// symmetric and the divergence coupling B, B^T) every eigen-block I (x) M_v + dt T_k (x)
+// S_v is symmetric (real eigenvalue) or complex symmetric (pair), and so is its inverse,
+// which is therefore stored by its wrapped diagonals s = 0 .. n_s/2 (layout with
+// sym_block_values): about half the values of the factored form.  One wavefront per
+// patch, lane i owns row i of every block (n_s <= 64); each stored entry is read once
+// from memory and used for both Z(i, i+s) and Z(i+s, i).  Transposed apply: real blocks
+// are unchanged, a pair's conjugate transpose is its conjugate.  Gather and eigenbasis
+// transforms as in the factored form.
+template <typename T, int U = 4, int NT = 1>
+__device__ __forceinline__ void patch_apply_sym_one(
+    int p, int lane, T* xs, T* xt, const irk::StageBasis<T>& sb, const int32_t* __restrict__ p_nloc,
+    const int64_t* __restrict__ p_inv_off, const int64_t* __restrict__ p_slot_off,
+    const int32_t* __restrict__ gidx, const T* __restrict__ inv, const T* __restrict__ res,
+    const T* __restrict__ W, T* __restrict__ Y, int transpose, int D) {
+  constexpr int VEC = Vec16<T>::n;
+  const int n = p_nloc[p];
+  const int ns = n / sb.r;
+  const int64_t so = p_slot_off[p];
+  const T* __restrict__ Ap = inv + p_inv_off[p];
+  eig_in<T>(lane, n, ns, so, xs, xt, sb, gidx, res, W, transpose);
+  const int nb = ns - irk::sym_diags(ns);  // diagonals also used backwards: 1 .. nb
+  // lanes past n_s repeat lane 0's loads and arithmetic; no lane reads their results
+  const int i = lane < ns ? lane : 0;
+  const T cs = transpose ? T(-1) : T(1);
+  const int64_t step = (int64_t)ns * VEC;
+  int64_t boff = 0;
+  for (int b = 0; b < sb.nblk; ++b) {
+    const int type = sb.type[b];
+    const int ng = irk::sym_words(type, ns, VEC);
+    const T* __restrict__ Dp = Ap + boff + (int64_t)i * VEC;
+    boff += irk::sym_block_values(type, ns, VEC);
+    const T* xu = xt + sb.st0[b] * ns;
+    // diagonal s: forward entry Z(i, i+s) x_{i+s}; for 1 <= s <= nb also Z(i-s, i)
+    // x_{i-s}, the product lane i-s forms from its own row value and hands over
+    int sd = 0, jf = i, jb = i;  // jf = (i + sd) mod n_s, jb = (i - sd) mod n_s
+    if (type == 1) {
+      constexpr int G = VEC;
+      const T xi = xu[i];
+      T acc = T(0);
+      for (int g = 0; g < ng; g += U) {
+        T a[U][VEC];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+          if (g + u < ng) vload_s<T, NT>(Dp + (g + u) * step, a[u]);
+          else
+#pragma unroll
+            for (int v = 0; v < VEC; ++v) a[u][v] = T(0);
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+#pragma unroll
+          for (int k = 0; k < G; ++k) {
+            acc += a[u][k] * xu[jf];
+            if (sd >= 1 && sd <= nb) acc += __shfl(a[u][k] * xi, jb, 64);  // wave-uniform test
+            ++sd;
+            jf = jf + 1 == ns ? 0 : jf + 1;
+            jb = jb == 0 ? ns - 1 : jb - 1;
+          }
+      }
+      if (lane < ns) xs[sb.st0[b] * ns + i] = acc;
+    } else {
+      constexpr int G = VEC / 2;
+      const T* xv = xu + ns;
+      const T xir = xu[i], xii = xv[i];
+      T ar = T(0), ai = T(0);
+      for (int g = 0; g < ng; g += U) {
+        T a[U][VEC];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+          if (g + u < ng) vload_s<T, NT>(Dp + (g + u) * step, a[u]);
+          else
+#pragma unroll
+            for (int v = 0; v < VEC; ++v) a[u][v] = T(0);
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+#pragma unroll
+          for (int k = 0; k < G; ++k) {
+            const T dr = a[u][2 * k], di = cs * a[u][2 * k + 1];
+            const T zr = xu[jf], zi = xv[jf];
+            ar += dr * zr - di * zi;
+            ai += dr * zi + di * zr;
+            if (sd >= 1 && sd <= nb) {  // wave-uniform test
+              ar += __shfl(dr * xir - di * xii, jb, 64);
+              ai += __shfl(dr * xii + di * xir, jb, 64);
+            }
+            ++sd;
+            jf = jf + 1 == ns ? 0 : jf + 1;
+            jb = jb == 0 ? ns - 1 : jb - 1;
+          }
+      }
+      if (lane < ns) {
+        xs[sb.st0[b] * ns + i] = ar;
+        xs[(sb.st0[b] + 1) * ns + i] = ai;
+      }
+    }
   }
-  // xs and xt are reused by this wavefront's next patch
-  __builtin_amdgcn_wave_barrier();
+  eig_out<T>(lane, n, ns, so, xs, sb, Y, transpose, D);
 }
 
 // Owner gather of one DOF.  mode 0: x = omega*W*s   1: x += omega*W*s

@@ -123,6 +123,23 @@ __host__ __device__ inline int eig_block_rows(int type, int ns, int vec) {
   return type == 1 ? (ns + vec - 1) / vec * vec : 2 * ((ns + vec / 2 - 1) / (vec / 2) * (vec / 2));
 }
 
+// Symmetric factored form (a symmetric spatial operator, Stokes): each block inverse Z
+// (n_s x n_s, real or complex symmetric) is kept as its wrapped diagonals
+// Z(i, (i + s) mod n_s), s = 0 .. n_s/2, which hold every entry at least once.  Word
+// (g, i), 16 bytes, holds row i's entries on the G = sym_group consecutive diagonals
+// g*G .. g*G+G-1 (a pair entry as re, im); diagonals past n_s/2 are zero.  Word (g, i)
+// sits at value offset (g * n_s + i) * vec, so one 16-byte load per lane reads word g
+// of every row.
+__host__ __device__ inline int sym_diags(int ns) { return ns / 2 + 1; }
+__host__ __device__ inline int sym_group(int type, int vec) { return type == 1 ? vec : vec / 2; }
+__host__ __device__ inline int sym_words(int type, int ns, int vec) {
+  const int G = sym_group(type, vec);
+  return (sym_diags(ns) + G - 1) / G;
+}
+__host__ __device__ inline int64_t sym_block_values(int type, int ns, int vec) {
+  return (int64_t)sym_words(type, ns, vec) * ns * vec;
+}
+
 // The basis as the patch kernels read it (by value, in the working precision).
 template <typename T>
 struct StageBasis {
@@ -194,8 +211,13 @@ struct DevLevel {
   // patch form: 0 = dense inverse of the stage-coupled patch matrix (column-major,
   // n x ld); 1 = factored through the stage eigenbasis: n_s columns of ld = sum over
   // blocks of eig_block_rows values each (p_ld holds that column length)
+  // 3 = symmetric factored (Stokes, n_s <= 64): each block inverse kept by its wrapped
+  // diagonals (sym_block_values); factorised in the form-1 layout, whose offsets
+  // p_full_off and size full_elems are kept for that step
   int pform = 0;
   int max_ld = 0;
+  int64_t* p_full_off = nullptr;
+  int64_t full_elems = 0;
   StageBasis<double> sb64;
   StageBasis<float> sb32;
 
@@ -211,7 +233,8 @@ struct Handle {
   int dim = 0, r = 0, nlevels = 0, precision = 0;
   double dt = 0, nu = 0, omega = 0.5;
   int pre = 2, post = 2, weighting = 1;
-  int patch_form = 0;  // form in use: 0 dense, 1 stage eigenbasis
+  int patch_form = 0;  // form in use: 0 dense, 1 stage eigenbasis, 3 symmetric eigenbasis
+  int patch_form_req = 2;  // the requested form (2 = automatic)
   int smoother = 0;    // 0 damped sweeps, 1 Chebyshev on [cheb_lo, cheb_hi]
   double cheb_lo = 2.0, cheb_hi = 8.0;
   StageEig eig;
@@ -291,6 +314,8 @@ hipError_t patch_factor_cplx(const DevLevel& L, const DevOps<T>& ops, double zr,
                              int* d_fail, hipStream_t s);
 // Copy eigen-block b of patches [p0, p1) from dense inverses (layout of
 // patch_factor_range with tmp_ld / tmp_off / off0) into the factored layout of L.inv.
+template <typename T>
+hipError_t pack_sym(const DevLevel& L, const int64_t* full_off, const T* full, hipStream_t s);
 template <typename T>
 hipError_t eig_extract(const DevLevel& L, const StageBasis<T>& sb, int b, const int32_t* tmp_ld,
                        const int64_t* tmp_off, int64_t off0, const T* tmp, int64_t p0, int64_t p1,

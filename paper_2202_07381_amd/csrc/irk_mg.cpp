@@ -594,6 +594,27 @@ static irk_status factor_level(irk_mg* h, int l, const DevOps<T>& ops, double dt
                                     D.npatch, 0, D.max_nloc, dfail, s));
     return IRK_OK;
   }
+  if (D.pform == 3) {
+    // factorise in the factored layout (temporary), then keep the wrapped diagonals
+    T* full = nullptr;
+    hipError_t e = hipMalloc(&full, (size_t)std::max<int64_t>(D.full_elems, 1) * sizeof(T));
+    if (e != hipSuccess) return fail(IRK_ENOMEM, "device allocation of the factorisation workspace failed");
+    void* sym = D.inv;
+    int64_t* sym_off = D.p_inv_off;
+    D.inv = full;
+    D.p_inv_off = D.p_full_off;
+    D.pform = 1;
+    const irk_status st = factor_level<T>(h, l, ops, dt, dfail, s);
+    D.pform = 3;
+    D.inv = sym;
+    D.p_inv_off = sym_off;
+    if (st == IRK_OK) e = k::pack_sym<T>(D, D.p_full_off, full, s);
+    hipStreamSynchronize(s);
+    hipFree(full);
+    if (st != IRK_OK) return st;
+    if (e != hipSuccess) return fail(IRK_EHIP, std::string("symmetric patch form: ") + hipGetErrorString(e));
+    return IRK_OK;
+  }
   const irk::StageEig& E = h->eig;
   const int VEC = 16 / (int)sizeof(T);
   const int64_t np = D.npatch;
@@ -722,8 +743,15 @@ static irk_status setup_impl(const irk_mesh_level* lv, int nlevels, const irk_ta
     std::string why;
     irk::StageEig eig;
     const bool ok = o.patch_form != 0 && irk::stage_eigenbasis(h->A, r, eig, &why);
-    if (o.patch_form == 1 && !ok) return fail(IRK_EINVAL, "factored patch form unavailable: " + why);
-    h->patch_form = ok && (o.patch_form == 1 || r >= 2) ? 1 : 0;
+    if ((o.patch_form == 1 || o.patch_form == 3) && !ok)
+      return fail(IRK_EINVAL, "factored patch form unavailable: " + why);
+    if (o.patch_form == 3 && wind)
+      return fail(IRK_EINVAL, "the symmetric patch form needs a symmetric spatial operator (no wind)");
+    int form = ok && (o.patch_form == 1 || o.patch_form == 3 || r >= 2) ? 1 : 0;
+    // a symmetric spatial operator (Stokes) makes every eigen-block inverse symmetric
+    if (form == 1 && !wind && o.patch_form != 1) form = 3;
+    h->patch_form = form;
+    h->patch_form_req = o.patch_form;
     if (h->patch_form) h->eig = eig;
   }
   // ---- host: topology, transfers, assembly, patches
@@ -825,9 +853,19 @@ static irk_status setup_impl(const irk_mesh_level* lv, int nlevels, const irk_ta
       D.npatch = np;
       std::vector<int32_t> nloc(np), ld(np), nnv(np), gidx, gptr(D.N + 1, 0), gslot;
       std::vector<int64_t> inv_off(np), slot_off(np);
-      int64_t io = 0, so = 0;
+      std::vector<int64_t> sym_off(np);
+      int64_t io = 0, so = 0, sio = 0;
       int maxn = 0, maxld = 0;
       D.pform = h->patch_form;
+      if (D.pform == 3) {
+        int maxns = 0;
+        for (int64_t p = 0; p < np; ++p) maxns = std::max(maxns, dim * (H.pn_ptr[p + 1] - H.pn_ptr[p]) + 1);
+        if (maxns > 64) {
+          if (h->patch_form_req == 3)
+            return fail(IRK_EINVAL, "the symmetric patch form needs patches of at most 64 unknowns per stage");
+          D.pform = 1;
+        }
+      }
       for (int64_t p = 0; p < np; ++p) {
         const int nn = H.pn_ptr[p + 1] - H.pn_ptr[p];
         const int ns = dim * nn + 1;
@@ -836,12 +874,14 @@ static irk_status setup_impl(const irk_mesh_level* lv, int nlevels, const irk_ta
         nloc[p] = n;
         inv_off[p] = io;
         slot_off[p] = so;
-        if (D.pform == 1) {
+        if (D.pform == 1 || D.pform == 3) {
           // factored: ns columns, each the concatenation of the eigen-blocks' rows
           int lc = 0;
           for (int b = 0; b < h->eig.nblk; ++b) lc += irk::eig_block_rows(h->eig.type[b], ns, VEC);
           ld[p] = lc;
           io += (int64_t)lc * ns;
+          sym_off[p] = sio;
+          for (int b = 0; b < h->eig.nblk; ++b) sio += irk::sym_block_values(h->eig.type[b], ns, VEC);
         } else {
           ld[p] = (n + VEC - 1) / VEC * VEC;
           io += (int64_t)ld[p] * n;
@@ -856,11 +896,12 @@ static irk_status setup_impl(const irk_mesh_level* lv, int nlevels, const irk_ta
           gidx.push_back((int32_t)(D.offV + p * r + st));
         }
       }
-      D.inv_elems = io;
+      D.inv_elems = D.pform == 3 ? sio : io;
+      D.full_elems = io;
       D.slots = so;
       D.max_nloc = maxn;
       D.max_ld = maxld;
-      if (D.pform == 1) {
+      if (D.pform == 1 || D.pform == 3) {
         const irk::StageEig& E = h->eig;
         for (auto* sbp : {&D.sb64}) {
           sbp->r = r;
@@ -921,7 +962,8 @@ static irk_status setup_impl(const irk_mesh_level* lv, int nlevels, const irk_ta
       CHK(upload(h, &D.p_nloc, nloc, s));
       CHK(upload(h, &D.p_ld, ld, s));
       CHK(upload(h, &D.p_nn, nnv, s));
-      CHK(upload(h, &D.p_inv_off, inv_off, s));
+      CHK(upload(h, &D.p_inv_off, D.pform == 3 ? sym_off : inv_off, s));
+      if (D.pform == 3) CHK(upload(h, &D.p_full_off, inv_off, s));
       CHK(upload(h, &D.p_slot_off, slot_off, s));
       CHK(upload(h, &D.p_gidx, gidx, s));
       CHK(upload(h, &D.gat_ptr, gptr, s));
@@ -939,8 +981,10 @@ static irk_status setup_impl(const irk_mesh_level* lv, int nlevels, const irk_ta
         for (int64_t p = 0; p < H.nv; ++p) {
           const double ns = dim * (double)(H.pn_ptr[p + 1] - H.pn_ptr[p]) + 1;
           sum_n += r * ns;
-          // stored values read per application: (r ns)^2 dense, r ns^2 factored
-          sum_n2 += h->patch_form == 1 ? r * ns * ns : r * r * ns * ns;
+          // stored values read per application: (r ns)^2 dense, r ns^2 factored,
+          // r ns (ns/2 + 1) symmetric factored
+          sum_n2 += D.pform == 3 ? r * ns * (double)irk::sym_diags((int)ns)
+                                 : (D.pform == 1 ? r * ns * ns : r * r * ns * ns);
         }
       D.alg_bytes[0] = es * (sum_n2 + (double)D.N + sum_n);
       D.alg_bytes[1] = (double)H.s_col.size() * (4 + 2 * es) +
@@ -1049,7 +1093,7 @@ irk_status irk_mg_setup(const irk_mesh_level* lv, int nlevels, const irk_tableau
     if (!(opt->omega > 0) || !std::isfinite(opt->omega)) return fail(IRK_EINVAL, "omega must be positive");
     if (opt->weighting != 0 && opt->weighting != 1) return fail(IRK_EINVAL, "weighting must be 0 or 1");
     if (opt->precision != 0 && opt->precision != 1) return fail(IRK_EINVAL, "precision must be 0 or 1");
-    if (opt->patch_form < 0 || opt->patch_form > 2) return fail(IRK_EINVAL, "patch_form must be 0, 1 or 2");
+    if (opt->patch_form < 0 || opt->patch_form > 3) return fail(IRK_EINVAL, "patch_form must be 0, 1, 2 or 3");
     if (opt->smoother != 0 && opt->smoother != 1) return fail(IRK_EINVAL, "smoother must be 0 or 1");
     if (opt->smoother == 1 && !(opt->cheb_lo > 0 && opt->cheb_hi > opt->cheb_lo && std::isfinite(opt->cheb_hi)))
       return fail(IRK_EINVAL, "Chebyshev interval must satisfy 0 < cheb_lo < cheb_hi < inf");
@@ -1095,7 +1139,10 @@ irk_status irk_mg_setup(const irk_mesh_level* lv, int nlevels, const irk_tableau
   return IRK_OK;
 }
 
-int irk_mg_patch_form(const irk_mg* h) { return h ? h->patch_form : -1; }
+int irk_mg_patch_form(const irk_mg* h) {
+  if (!h) return -1;
+  return h->nlevels >= 2 ? h->dev[h->nlevels - 1].pform : h->patch_form;
+}
 
 irk_status irk_rhs_dirichlet(irk_mg* h, const double* g_n, const double* g_stages, double* F, void* stream) {
   CHK(check_handle(h));

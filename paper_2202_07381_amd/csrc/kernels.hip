@@ -766,6 +766,66 @@ __global__ __launch_bounds__(WAVES * 64) __attribute__((amdgpu_waves_per_eu(WPE)
                                               p_slot_off, gidx, inv, res, W, Y, transpose, D);
 }
 
+template <typename T, int NMAX, int UNROLL, int WAVES>
+__global__ __launch_bounds__(WAVES * 64) void k_patch_apply_sym(
+    int64_t npatch, irk::StageBasis<T> sb, const int32_t* __restrict__ sched,
+    const int32_t* __restrict__ p_nloc, const int64_t* __restrict__ p_inv_off,
+    const int64_t* __restrict__ p_slot_off, const int32_t* __restrict__ gidx, const T* __restrict__ inv,
+    const T* __restrict__ res, const T* __restrict__ W, T* __restrict__ Y, int transpose, int D) {
+  __shared__ T xs[WAVES][NMAX];
+  __shared__ T xt[WAVES][NMAX];
+  const int lane = threadIdx.x & 63;
+  const int wave = threadIdx.x >> 6;
+  const int64_t idx = (int64_t)blockIdx.x * WAVES + wave;
+  if (idx >= npatch) return;  // whole wavefront exits; no workgroup barrier below
+  dev::patch_apply_sym_one<T, UNROLL, 1>(sched[idx], lane, xs[wave], xt[wave], sb, p_nloc, p_inv_off, p_slot_off,
+                                         gidx, inv, res, W, Y, transpose, D);
+}
+
+// Symmetric factored form from the factored form (one workgroup per patch): the wrapped
+// diagonals of every block inverse, each entry the mean of Z(i, j) and Z(j, i), which
+// agree up to the rounding of the factorisation.  Factored layout: column j of block b
+// holds Z(i, j) at base_b + i (real) or base_b + 2 i + {0, 1} (pair, re and im).
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_pack_sym(int64_t np, irk::StageBasis<T> sb,
+                                                     const int32_t* __restrict__ p_nloc,
+                                                     const int32_t* __restrict__ p_ld,
+                                                     const int64_t* __restrict__ full_off,
+                                                     const int64_t* __restrict__ sym_off,
+                                                     const T* __restrict__ full, T* __restrict__ out) {
+  constexpr int VEC = Vec16<T>::n;
+  const int64_t p = blockIdx.x;
+  if (p >= np) return;
+  const int ns = p_nloc[p] / sb.r, lc = p_ld[p];
+  const int h = irk::sym_diags(ns);
+  const T* __restrict__ F = full + full_off[p];
+  T* __restrict__ O = out + sym_off[p];
+  int base = 0;
+  int64_t boff = 0;
+  for (int b = 0; b < sb.nblk; ++b) {
+    const int type = sb.type[b];
+    const int G = irk::sym_group(type, VEC);
+    const int64_t cnt = irk::sym_block_values(type, ns, VEC);
+    for (int64_t e = threadIdx.x; e < cnt; e += blockDim.x) {
+      const int v = (int)(e % VEC);
+      const int64_t wi = e / VEC;
+      const int i = (int)(wi % ns), g = (int)(wi / ns);
+      const int k = v / type, comp = v - k * type;
+      const int sd = g * G + k;
+      T val = T(0);
+      if (sd < h) {
+        const int j = (i + sd) % ns;
+        const T zij = F[(int64_t)j * lc + base + type * i + comp];
+        const T zji = F[(int64_t)i * lc + base + type * j + comp];
+        val = T(0.5) * (zij + zji);
+      }
+      O[boff + e] = val;
+    }
+    base += irk::eig_block_rows(type, ns, VEC);
+    boff += cnt;
+  }
+}
+
 // ------------------------------------------------------------------ gather update
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_gather_update(int64_t N, int64_t nsl, const int32_t* __restrict__ g_off,
@@ -1447,6 +1507,15 @@ hipError_t eig_extract(const DevLevel& L, const StageBasis<T>& sb, int b, const 
 }
 
 template <typename T>
+hipError_t pack_sym(const DevLevel& L, const int64_t* full_off, const T* full, hipStream_t s) {
+  if (L.npatch <= 0) return hipSuccess;
+  k_pack_sym<T><<<dim3((unsigned)L.npatch), dim3(kBlock), 0, s>>>(L.npatch, basis_of<T>(L), L.p_nloc, L.p_ld,
+                                                                  full_off, L.p_inv_off, full,
+                                                                  reinterpret_cast<T*>(L.inv));
+  return hipGetLastError();
+}
+
+template <typename T>
 hipError_t patch_apply(const DevLevel& L, const DevOps<T>& ops, const T* res, T* Y,
                        int transpose, hipStream_t s) {
   constexpr int VEC = Vec16<T>::n;
@@ -1454,6 +1523,18 @@ hipError_t patch_apply(const DevLevel& L, const DevOps<T>& ops, const T* res, T*
   const T* W = transpose ? ops.W : nullptr;
   const T* inv = reinterpret_cast<const T*>(L.inv);
   const int rows_per_block = 64 * VEC;
+  if (L.pform == 3) {
+    const StageBasis<T>& sb = basis_of<T>(L);
+    if (L.max_nloc > 256 || L.max_nloc / L.r > 64) return hipErrorInvalidValue;
+#define IRK_PAS(NM, U, WV)                                                                               \
+  k_patch_apply_sym<T, NM, U, WV><<<dim3(blocks_for(L.npatch, WV)), dim3(WV * 64), 0, s>>>(           \
+      L.npatch, sb, L.sched, L.p_nloc, L.p_inv_off, L.p_slot_off, L.p_gidx, inv, res, W, Y, transpose, \
+      L.dim)
+    if (L.max_nloc <= 128) IRK_PAS(128, 4, 4);
+    else IRK_PAS(256, 4, 4);
+#undef IRK_PAS
+    return hipGetLastError();
+  }
   if (L.pform == 1) {
     const StageBasis<T>& sb = basis_of<T>(L);
     const int rbe = (L.max_ld + rows_per_block - 1) / rows_per_block;
@@ -1722,6 +1803,7 @@ hipError_t mass_apply(const DevLevel& L, const double* st, double* out, hipStrea
                                      hipStream_t);                                                 \
   template hipError_t patch_apply<T>(const DevLevel&, const DevOps<T>&, const T*, T*, int,      \
                                      hipStream_t);                                              \
+  template hipError_t pack_sym<T>(const DevLevel&, const int64_t*, const T*, hipStream_t);      \
   template hipError_t gather_cheb<T>(const DevLevel&, const DevOps<T>&, const T*, T, T, int, int, int, T*, \
                                      T*, hipStream_t);                                                  \
   template hipError_t gather_update<T>(const DevLevel&, const DevOps<T>&, const T*, T*, T, int, \

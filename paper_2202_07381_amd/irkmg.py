@@ -225,7 +225,8 @@ class IrkMG:
 
     # ---------------------------------------------------------------- sizes
     def irk_mg_patch_form(self) -> int:
-        """0: dense patch inverses; 1: factored through the stage eigenbasis."""
+        """0: dense patch inverses; 1: factored through the stage eigenbasis; 3: symmetric
+        factored (wrapped diagonals of each block inverse, Stokes)."""
         return int(lib.irk_mg_patch_form(self.h))
 
     def irk_mg_ndofs(self, level: int = -1) -> int:

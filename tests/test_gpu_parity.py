@@ -8,19 +8,21 @@ library applies an explicit Gauss--Jordan inverse of the pinned coarse operator 
 the oracle an LU solve, two backward-stable solves whose results differ by up to the
 condition number times the unit roundoff (cond(J_0) reaches 1e8 at dt = 1e-2);
 FGMRES solutions after equal iteration counts 1e-10 relative (the target stated for
-the method).  Sweeps, V-cycles and solves run with both patch forms: 0 (dense patch
-inverses) and 2 (automatic: inverses factored through the stage eigenbasis for r >= 2),
-which apply the same operator up to rounding."""
+the method).  Sweeps, V-cycles and solves run with the patch forms 0 (dense patch
+inverses), 1 (inverses factored through the stage eigenbasis) and 2 (automatic: for
+r >= 2 the symmetric factored form, wrapped diagonals of each block inverse, on the
+Stokes cases with at most 64 unknowns per stage and patch, else form 1), which apply
+the same operator up to rounding."""
 import numpy as np
 import pytest
 
-from gpu_cases import CASES, forcing_rhs, gpu_of, oracle_of, relerr, say, to_dev, to_host
+from gpu_cases import CASES, forcing_rhs, gpu_of, levels_of, oracle_of, relerr, say, to_dev, to_host, wind_of
 
 pytestmark = pytest.mark.gpu
 torch = pytest.importorskip("torch")
 
 ALL = list(CASES)
-FORMS = [0, 2]
+FORMS = [0, 1, 2]
 
 
 @pytest.mark.parametrize("case", ALL)
@@ -228,23 +230,39 @@ def test_error_paths():
 
 
 def test_patch_form_selection():
-    """Automatic form: factored for r >= 2, dense for r = 1; both forms can be forced,
-    including the factored form at r = 1 (one real block, W = 1)."""
+    """Automatic form: for r >= 2 symmetric factored on 2D Stokes, factored for Oseen
+    (a non-symmetric operator) and in 3D (patches above 64 unknowns per stage), dense for
+    r = 1; every form can be forced where it applies, including the factored and the
+    symmetric factored forms at r = 1 (one real block, W = 1); forcing the symmetric form
+    with a wind or with larger patches is refused."""
+    from paper_2202_07381_amd import irkmg
+
     for case in ALL:
-        r = CASES[case][4]
-        assert gpu_of(case, patch_form=2).irk_mg_patch_form() == (1 if r >= 2 else 0), case
+        dim, r, ws = CASES[case][0], CASES[case][4], CASES[case][7]
+        want = 0 if r < 2 else (1 if ws is not None or dim == 3 else 3)
+        assert gpu_of(case, patch_form=2).irk_mg_patch_form() == want, case
         assert gpu_of(case, patch_form=0).irk_mg_patch_form() == 0, case
-    g, H = gpu_of("be", patch_form=1), oracle_of("be")
-    assert g.irk_mg_patch_form() == 1
     rng = np.random.default_rng(19)
-    for lev in range(1, g.nlevels):
-        J = H.systems[lev].J
-        F, k0 = rng.standard_normal(J.shape[0]), rng.standard_normal(J.shape[0])
-        for tr in (False, True):
-            say(f"[form1 r=1] level={lev} transpose={tr}")
-            k = to_dev(k0)
-            g.irk_level_sweep(lev, to_dev(F), k, transpose=tr)
-            assert relerr(to_host(k), H.smoothers[lev].sweep(F, k0, J.T if tr else J, tr)) < 1e-11
+    for form in (1, 3):
+        g, H = gpu_of("be", patch_form=form), oracle_of("be")
+        assert g.irk_mg_patch_form() == form
+        for lev in range(1, g.nlevels):
+            J = H.systems[lev].J
+            F, k0 = rng.standard_normal(J.shape[0]), rng.standard_normal(J.shape[0])
+            for tr in (False, True):
+                say(f"[form{form} r=1] level={lev} transpose={tr}")
+                k = to_dev(k0)
+                g.irk_level_sweep(lev, to_dev(F), k, transpose=tr)
+                assert relerr(to_host(k), H.smoothers[lev].sweep(F, k0, J.T if tr else J, tr)) < 1e-11
+    for case in ("oseen", "3d2"):
+        dim, nc, nl, fam, r, dt, nu, ws = CASES[case]
+        A, b, c = irkmg.irk_tableau_builtin(fam, r)
+        lv = levels_of(case)
+        w = wind_of(case)
+        wind = w(irkmg.irk_mesh_p2_nodes(lv[-1])) if w is not None else None
+        with pytest.raises(irkmg.IrkError) as e:
+            irkmg.IrkMG(lv, A, b, c, dt, nu, wind_nodal=wind, patch_form=3)
+        assert e.value.status == irkmg.IRK_EINVAL, case
 
 
 # ------------------------------------------------------------- edge cases
@@ -274,15 +292,16 @@ def _custom_case(A, b, c, dt, nlev=3):
 @pytest.mark.parametrize("kind", ["gauss4", "sdirk2"])
 def test_custom_tableaux(kind):
     """r = 4 (two complex eigenvalue pairs, the largest stage count) and a defective A (a
-    2-stage SDIRK, repeated eigenvalue): automatic patch form factored resp. dense, the
-    factored form rejected for the defective A; V-cycle and FGMRES against the oracle."""
+    2-stage SDIRK, repeated eigenvalue): automatic patch form symmetric factored (a Stokes
+    case) resp. dense, the factored form rejected for the defective A; V-cycle and FGMRES
+    against the oracle."""
     from oracle.fgmres import fgmres
     from paper_2202_07381_amd import irkmg
     from paper_2202_07381_amd import workloads as wl
 
     if kind == "gauss4":
         A, b, c = _gauss_collocation(4)
-        form_expected = 1
+        form_expected = 3
     else:
         g_ = 1.0 - 1.0 / np.sqrt(2.0)
         A = np.array([[g_, 0.0], [1.0 - g_, g_]])
