@@ -214,7 +214,7 @@ __device__ void patches(const BLevel& L, double* xs, double* xt, const double* i
     if (idx >= L.npatch) break;
     const int p = L.sched[idx];
     if (L.pform == 3) {
-      dev::patch_apply_sym_one<double, 4, 1>(p, lane, xs, xt, L.sb, L.p_nloc, L.p_inv_off, L.p_slot_off, L.p_gidx,
+      dev::patch_apply_sym_one<double, 4, 1, 0>(p, lane, xs, xt, L.sb, L.p_nloc, L.p_inv_off, L.p_slot_off, L.p_gidx,
                                              L.inv, in, nullptr, L.Y, 0, L.dim);
       continue;
     }
@@ -309,7 +309,7 @@ __device__ void exec_item(const BSolve& S, const BCur& st, const BState* gst, in
     case PH_SM_PATCH: {
       const BLevel& L = S.lv[st.level];
       const int wave = tid >> 6;
-      patches(L, xs + wave * kNmax, xt + wave * kNmax, st.first ? L.b : L.res, (int64_t)item * kWaves * t.ppw,
+      patches(L, xs + wave * kNmax, xt + wave * 2 * kNmax, st.first ? L.b : L.res, (int64_t)item * kWaves * t.ppw,
               t.ppw);
       break;
     }
@@ -638,7 +638,7 @@ __host__ __device__ void advance(const BSolve& S, BState& st, double red_val, co
 __global__ __launch_bounds__(kBlock, 1) void k_batch(const BSolve* __restrict__ Sv, BState* Stv, Ctl* ctl,
                                                   int nsolves, Tun tun) {
   __shared__ double xs[kWaves * kNmax];
-  __shared__ double xt[kWaves * kNmax];
+  __shared__ double xt[kWaves * 2 * kNmax];  // doubled copies for the symmetric form
   __shared__ double red[kBlock];
   __shared__ int s_item, s_ok, s_last, s_exit, s_solve, s_epoch, s_viol;
   __shared__ BCur s_st;  // snapshot of the solve's state for the item being executed

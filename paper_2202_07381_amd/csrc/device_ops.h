@@ -260,8 +260,9 @@ __device__ __forceinline__ void patch_apply_one(
 
 // Gather of the (optionally weighted) patch residual into xs and its transform to the
 // stage eigenbasis into xt: xt[k ns + q] = sum_s Tin(k, s) xs[s ns + q] with Tin = W^{-1}
-// (forward) or W^T (transposed).
-template <typename T>
+// (forward) or W^T (transposed).  DUP: each transformed stage stored twice in a row,
+// xt[k 2ns + q] = xt[k 2ns + ns + q], so that x[(q + s) mod ns] = xt[k 2ns + q + s].
+template <typename T, bool DUP = false>
 __device__ __forceinline__ void eig_in(int lane, int n, int ns, int64_t so, T* xs, T* xt,
                                        const irk::StageBasis<T>& sb, const int32_t* __restrict__ gidx,
                                        const T* __restrict__ res, const T* __restrict__ W, int transpose) {
@@ -277,7 +278,12 @@ __device__ __forceinline__ void eig_in(int lane, int n, int ns, int64_t so, T* x
     const int k = e / ns, q = e - k * ns;
     T acc = T(0);
     for (int s = 0; s < r; ++s) acc += (transpose ? sb.W[s * r + k] : sb.Winv[k * r + s]) * xs[s * ns + q];
-    xt[e] = acc;
+    if constexpr (DUP) {
+      xt[k * 2 * ns + q] = acc;
+      xt[k * 2 * ns + ns + q] = acc;
+    } else {
+      xt[e] = acc;
+    }
   }
   __builtin_amdgcn_wave_barrier();
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
@@ -483,7 +489,58 @@ __device__ __forceinline__ void patch_apply_eig_one(
 // from memory and used for both Z(i, i+s) and Z(i+s, i).  Transposed apply: real blocks
 // are unchanged, a pair's conjugate transpose is its conjugate.  Gather and eigenbasis
 // transforms as in the factored form.
-template <typename T, int U = 4, int NT = 1>
+// Work of one stored word (16 bytes of lane i's row) of a symmetric block, whose
+// diagonals s0, s0-1, ..., s0-G+1 (descending) it holds.  Forward entries
+// Z(i, i+s) x_{i+s}, x read from the doubled copy xu (xu[i + s] = x_{(i+s) mod n_s}).
+// Transposed entries Z(i-s, i) x_{i-s}, 1 <= s <= nb, by a Horner scheme over the
+// descending diagonals: t <- rot(t) + Z(i, i+s) x_i with rot taking lane i-1's value
+// (lane n_s-1's for lane 0), so that after the diagonal s = 0 lane i holds
+// sum_s Z(i-s, i) x_{i-s}.  Real blocks use (ar, tr); pairs (ar, ai, tr, ti) with
+// x = (xu, xv) and cs = -1 for the conjugate.
+template <typename T>
+__device__ __forceinline__ void sym_word(const T* a, int type, int s0, int i, int nb, int src, const T* xu,
+                                         const T* xv, T xir, T xii, T cs, T& ar, T& ai, T& tr, T& ti) {
+  constexpr int VEC = Vec16<T>::n;
+  if (type == 1) {
+#pragma unroll
+    for (int k = 0; k < VEC; ++k) {
+      const int sd = s0 - k;
+      ar += a[k] * xu[i + sd];
+      tr = __shfl(tr, src, 64);
+      if (sd >= 1 && sd <= nb) tr += a[k] * xir;  // wave-uniform test
+    }
+  } else {
+#pragma unroll
+    for (int k = 0; k < VEC / 2; ++k) {
+      const int sd = s0 - k;
+      const T dr = a[2 * k], di = cs * a[2 * k + 1];
+      const T zr = xu[i + sd], zi = xv[i + sd];
+      ar += dr * zr - di * zi;
+      ai += dr * zi + di * zr;
+      tr = __shfl(tr, src, 64);
+      ti = __shfl(ti, src, 64);
+      if (sd >= 1 && sd <= nb) {  // wave-uniform test
+        tr += dr * xir - di * xii;
+        ti += dr * xii + di * xir;
+      }
+    }
+  }
+}
+
+// Symmetric factored patch inverse.  For a symmetric spatial operator (Stokes: K
+// symmetric and the divergence coupling B, B^T) every eigen-block I (x) M_v + dt T_k (x)
+// S_v is symmetric (real eigenvalue) or complex symmetric (pair), and so is its inverse,
+// which is therefore stored by its wrapped diagonals s = 0 .. n_s/2 (layout with
+// sym_block_values): about half the values of the factored form.  One wavefront per
+// patch, lane i owns row i of every block (n_s <= 64); each stored entry is read once
+// from memory and used for both Z(i, i+s) and Z(i+s, i).  Transposed apply: real blocks
+// are unchanged, a pair's conjugate transpose is its conjugate.  Gather and eigenbasis
+// transforms as in the factored form (xt doubled, 2n values).
+//
+// The blocks of a patch follow each other, so its words form one sequence, word w of
+// row i at ((w n_s) + i) vec, read U words at a time; with PF the next U words are in
+// flight while the current ones are used (the first U before the gather).
+template <typename T, int U = 4, int NT = 1, int PF = 0>
 __device__ __forceinline__ void patch_apply_sym_one(
     int p, int lane, T* xs, T* xt, const irk::StageBasis<T>& sb, const int32_t* __restrict__ p_nloc,
     const int64_t* __restrict__ p_inv_off, const int64_t* __restrict__ p_slot_off,
@@ -493,83 +550,69 @@ __device__ __forceinline__ void patch_apply_sym_one(
   const int n = p_nloc[p];
   const int ns = n / sb.r;
   const int64_t so = p_slot_off[p];
-  const T* __restrict__ Ap = inv + p_inv_off[p];
-  eig_in<T>(lane, n, ns, so, xs, xt, sb, gidx, res, W, transpose);
-  const int nb = ns - irk::sym_diags(ns);  // diagonals also used backwards: 1 .. nb
   // lanes past n_s repeat lane 0's loads and arithmetic; no lane reads their results
   const int i = lane < ns ? lane : 0;
-  const T cs = transpose ? T(-1) : T(1);
+  const int src = i == 0 ? ns - 1 : i - 1;  // rot: lane i takes lane i-1 (mod n_s)
+  const T* __restrict__ Dp = inv + p_inv_off[p] + (int64_t)i * VEC;
   const int64_t step = (int64_t)ns * VEC;
-  int64_t boff = 0;
-  for (int b = 0; b < sb.nblk; ++b) {
-    const int type = sb.type[b];
-    const int ng = irk::sym_words(type, ns, VEC);
-    const T* __restrict__ Dp = Ap + boff + (int64_t)i * VEC;
-    boff += irk::sym_block_values(type, ns, VEC);
-    const T* xu = xt + sb.st0[b] * ns;
-    // diagonal s: forward entry Z(i, i+s) x_{i+s}; for 1 <= s <= nb also Z(i-s, i)
-    // x_{i-s}, the product lane i-s forms from its own row value and hands over
-    int sd = 0, jf = i, jb = i;  // jf = (i + sd) mod n_s, jb = (i - sd) mod n_s
-    if (type == 1) {
-      constexpr int G = VEC;
-      const T xi = xu[i];
-      T acc = T(0);
-      for (int g = 0; g < ng; g += U) {
-        T a[U][VEC];
+  int NG = 0;
+  for (int b = 0; b < sb.nblk; ++b) NG += irk::sym_words(sb.type[b], ns, VEC);
+  T a[U][VEC];
+  if constexpr (PF) {
 #pragma unroll
-        for (int u = 0; u < U; ++u) {
-          if (g + u < ng) vload_s<T, NT>(Dp + (g + u) * step, a[u]);
-          else
+    for (int u = 0; u < U; ++u)
+      if (u < NG) vload_s<T, NT>(Dp + u * step, a[u]);
+  }
+  eig_in<T, true>(lane, n, ns, so, xs, xt, sb, gidx, res, W, transpose);
+  const int nb = ns - irk::sym_diags(ns);  // diagonals also used transposed: 1 .. nb
+  const T cs = transpose ? T(-1) : T(1);
+  // current block: type, words done / total, top diagonal, x, accumulators
+  int b = 0, type = sb.type[0], ng = irk::sym_words(type, ns, VEC), wb = 0;
+  int G = type == 1 ? VEC : VEC / 2;
+  int top = ng * G - 1;
+  const T* xu = xt + sb.st0[0] * 2 * ns;
+  const T* xv = xu + 2 * ns;
+  T xir = xu[i], xii = type == 2 ? xv[i] : T(0);
+  T ar = T(0), ai = T(0), tr = T(0), ti = T(0);
+  for (int w0 = 0; w0 < NG; w0 += U) {
+    T nx[U][VEC];
+    if constexpr (PF) {
 #pragma unroll
-            for (int v = 0; v < VEC; ++v) a[u][v] = T(0);
-        }
-#pragma unroll
-        for (int u = 0; u < U; ++u)
-#pragma unroll
-          for (int k = 0; k < G; ++k) {
-            acc += a[u][k] * xu[jf];
-            if (sd >= 1 && sd <= nb) acc += __shfl(a[u][k] * xi, jb, 64);  // wave-uniform test
-            ++sd;
-            jf = jf + 1 == ns ? 0 : jf + 1;
-            jb = jb == 0 ? ns - 1 : jb - 1;
-          }
-      }
-      if (lane < ns) xs[sb.st0[b] * ns + i] = acc;
+      for (int u = 0; u < U; ++u)
+        if (w0 + U + u < NG) vload_s<T, NT>(Dp + (w0 + U + u) * step, nx[u]);
     } else {
-      constexpr int G = VEC / 2;
-      const T* xv = xu + ns;
-      const T xir = xu[i], xii = xv[i];
-      T ar = T(0), ai = T(0);
-      for (int g = 0; g < ng; g += U) {
-        T a[U][VEC];
 #pragma unroll
-        for (int u = 0; u < U; ++u) {
-          if (g + u < ng) vload_s<T, NT>(Dp + (g + u) * step, a[u]);
-          else
+      for (int u = 0; u < U; ++u)
+        if (w0 + u < NG) vload_s<T, NT>(Dp + (w0 + u) * step, a[u]);
+    }
 #pragma unroll
-            for (int v = 0; v < VEC; ++v) a[u][v] = T(0);
+    for (int u = 0; u < U; ++u) {
+      if (w0 + u >= NG) break;
+      sym_word<T>(a[u], type, top - wb * G, i, nb, src, xu, xv, xir, xii, cs, ar, ai, tr, ti);
+      if (++wb == ng) {  // block done: store its rows, move to the next block
+        if (lane < ns) {
+          xs[sb.st0[b] * ns + i] = ar + tr;
+          if (type == 2) xs[(sb.st0[b] + 1) * ns + i] = ai + ti;
         }
-#pragma unroll
-        for (int u = 0; u < U; ++u)
-#pragma unroll
-          for (int k = 0; k < G; ++k) {
-            const T dr = a[u][2 * k], di = cs * a[u][2 * k + 1];
-            const T zr = xu[jf], zi = xv[jf];
-            ar += dr * zr - di * zi;
-            ai += dr * zi + di * zr;
-            if (sd >= 1 && sd <= nb) {  // wave-uniform test
-              ar += __shfl(dr * xir - di * xii, jb, 64);
-              ai += __shfl(dr * xii + di * xir, jb, 64);
-            }
-            ++sd;
-            jf = jf + 1 == ns ? 0 : jf + 1;
-            jb = jb == 0 ? ns - 1 : jb - 1;
-          }
+        if (++b < sb.nblk) {
+          type = sb.type[b];
+          ng = irk::sym_words(type, ns, VEC);
+          wb = 0;
+          G = type == 1 ? VEC : VEC / 2;
+          top = ng * G - 1;
+          xu = xt + sb.st0[b] * 2 * ns;
+          xv = xu + 2 * ns;
+          xir = xu[i];
+          xii = type == 2 ? xv[i] : T(0);
+          ar = ai = tr = ti = T(0);
+        }
       }
-      if (lane < ns) {
-        xs[sb.st0[b] * ns + i] = ar;
-        xs[(sb.st0[b] + 1) * ns + i] = ai;
-      }
+    }
+    if constexpr (PF) {
+#pragma unroll
+      for (int u = 0; u < U; ++u)
+#pragma unroll
+        for (int v = 0; v < VEC; ++v) a[u][v] = nx[u][v];
     }
   }
   eig_out<T>(lane, n, ns, so, xs, sb, Y, transpose, D);
@@ -652,11 +695,31 @@ __device__ __forceinline__ void spmv_nodes_row(
     const int32_t* __restrict__ p_col, const T* __restrict__ p_val, const T* __restrict__ in,
     T* __restrict__ out, int add) {
   constexpr int DR = D * R;
+  constexpr int UN = 4;  // entries whose gathers are in flight together
   if (row < nrow_u) {
     T acc[DR];
 #pragma unroll
     for (int q = 0; q < DR; ++q) acc[q] = T(0);
-    for (int32_t p = u_ptr[row]; p < u_ptr[row + 1]; ++p) {
+    const int32_t p1 = u_ptr[row + 1];
+    int32_t p = u_ptr[row];
+    for (; p + UN <= p1; p += UN) {
+      int32_t c[UN];
+      T w[UN], xv[UN][DR];
+#pragma unroll
+      for (int u = 0; u < UN; ++u) {
+        c[u] = u_col[p + u];
+        w[u] = u_val[p + u];
+      }
+#pragma unroll
+      for (int u = 0; u < UN; ++u)
+#pragma unroll
+        for (int q = 0; q < DR; ++q) xv[u][q] = in[(int64_t)c[u] * DR + q];
+#pragma unroll
+      for (int u = 0; u < UN; ++u)
+#pragma unroll
+        for (int q = 0; q < DR; ++q) acc[q] += w[u] * xv[u][q];
+    }
+    for (; p < p1; ++p) {
       const T w = u_val[p];
       const T* xi = in + (int64_t)u_col[p] * DR;
 #pragma unroll
@@ -672,7 +735,26 @@ __device__ __forceinline__ void spmv_nodes_row(
     T acc[R];
 #pragma unroll
     for (int q = 0; q < R; ++q) acc[q] = T(0);
-    for (int32_t p = p_ptr[v]; p < p_ptr[v + 1]; ++p) {
+    const int32_t p1 = p_ptr[v + 1];
+    int32_t p = p_ptr[v];
+    for (; p + UN <= p1; p += UN) {
+      int32_t c[UN];
+      T w[UN], xv[UN][R];
+#pragma unroll
+      for (int u = 0; u < UN; ++u) {
+        c[u] = p_col[p + u];
+        w[u] = p_val[p + u];
+      }
+#pragma unroll
+      for (int u = 0; u < UN; ++u)
+#pragma unroll
+        for (int q = 0; q < R; ++q) xv[u][q] = in[in_offV + (int64_t)c[u] * R + q];
+#pragma unroll
+      for (int u = 0; u < UN; ++u)
+#pragma unroll
+        for (int q = 0; q < R; ++q) acc[q] += w[u] * xv[u][q];
+    }
+    for (; p < p1; ++p) {
       const T w = p_val[p];
       const T* xi = in + in_offV + (int64_t)p_col[p] * R;
 #pragma unroll

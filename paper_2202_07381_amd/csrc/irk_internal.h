@@ -125,11 +125,12 @@ __host__ __device__ inline int eig_block_rows(int type, int ns, int vec) {
 
 // Symmetric factored form (a symmetric spatial operator, Stokes): each block inverse Z
 // (n_s x n_s, real or complex symmetric) is kept as its wrapped diagonals
-// Z(i, (i + s) mod n_s), s = 0 .. n_s/2, which hold every entry at least once.  Word
-// (g, i), 16 bytes, holds row i's entries on the G = sym_group consecutive diagonals
-// g*G .. g*G+G-1 (a pair entry as re, im); diagonals past n_s/2 are zero.  Word (g, i)
-// sits at value offset (g * n_s + i) * vec, so one 16-byte load per lane reads word g
-// of every row.
+// Z(i, (i + s) mod n_s), s = 0 .. n_s/2, which hold every entry at least once, in
+// descending order: with G = sym_group and ng = sym_words diagonals per word and words
+// per row, word (g, i), 16 bytes, holds row i's entries on the diagonals
+// s = ng G - 1 - g G - k, k = 0 .. G-1 (a pair entry as re, im); diagonals past n_s/2
+// are zero.  Word (g, i) sits at value offset (g * n_s + i) * vec, so one 16-byte load
+// per lane reads word g of every row.
 __host__ __device__ inline int sym_diags(int ns) { return ns / 2 + 1; }
 __host__ __device__ inline int sym_group(int type, int vec) { return type == 1 ? vec : vec / 2; }
 __host__ __device__ inline int sym_words(int type, int ns, int vec) {

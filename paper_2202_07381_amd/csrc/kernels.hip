@@ -50,6 +50,12 @@ const StageBasis<double>& basis_of<double>(const DevLevel& L) { return L.sb64; }
 template <>
 const StageBasis<float>& basis_of<float>(const DevLevel& L) { return L.sb32; }
 
+// Launches of at most this many wavefronts are resident on the chip at once (256 CUs,
+// 4 SIMDs, 2 waves each at the lowest occupancy of these kernels): their time is the
+// latency of one wavefront's dependent loads, so they keep more loads in flight per
+// lane at the cost of occupancy.
+constexpr int64_t kSmallWaves = 2048;
+
 // ------------------------------------------------------------------------ residual
 template <int D, int R, typename T>
 __global__ __launch_bounds__(kBlock) void k_residual(
@@ -66,10 +72,10 @@ __global__ __launch_bounds__(kBlock) void k_residual(
 
 // Same residual from the sliced operator copies: one wavefront per slice of 64 rows
 // (velocity slices first, then vertex slices), lane = row, entries of the slice read
-// column-major (coalesced indices and values), 4 entries' gathers in flight per lane.
-constexpr int kSellUnroll = 4;
-
-template <int D, int R, typename T>
+// column-major (coalesced indices and values), kSellUnroll entries' gathers in flight
+// per lane: 4 where many slices share the chip, 8 on small levels, which are latency
+// bound (every slice resident at once).
+template <int D, int R, typename T, int kSellUnroll>
 __global__ __launch_bounds__(256) void k_residual_sell(
     int64_t nfree, int64_t nv, int64_t offV, int64_t nsu, int64_t nsp, const int32_t* __restrict__ su_off,
     const int32_t* __restrict__ su_w, const int32_t* __restrict__ su_col, const T* __restrict__ uM,
@@ -766,25 +772,25 @@ __global__ __launch_bounds__(WAVES * 64) __attribute__((amdgpu_waves_per_eu(WPE)
                                               p_slot_off, gidx, inv, res, W, Y, transpose, D);
 }
 
-template <typename T, int NMAX, int UNROLL, int WAVES>
+template <typename T, int NMAX, int UNROLL, int PF, int WAVES>
 __global__ __launch_bounds__(WAVES * 64) void k_patch_apply_sym(
     int64_t npatch, irk::StageBasis<T> sb, const int32_t* __restrict__ sched,
     const int32_t* __restrict__ p_nloc, const int64_t* __restrict__ p_inv_off,
     const int64_t* __restrict__ p_slot_off, const int32_t* __restrict__ gidx, const T* __restrict__ inv,
     const T* __restrict__ res, const T* __restrict__ W, T* __restrict__ Y, int transpose, int D) {
   __shared__ T xs[WAVES][NMAX];
-  __shared__ T xt[WAVES][NMAX];
+  __shared__ T xt[WAVES][2 * NMAX];
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
   const int64_t idx = (int64_t)blockIdx.x * WAVES + wave;
   if (idx >= npatch) return;  // whole wavefront exits; no workgroup barrier below
-  dev::patch_apply_sym_one<T, UNROLL, 1>(sched[idx], lane, xs[wave], xt[wave], sb, p_nloc, p_inv_off, p_slot_off,
-                                         gidx, inv, res, W, Y, transpose, D);
+  dev::patch_apply_sym_one<T, UNROLL, 1, PF>(sched[idx], lane, xs[wave], xt[wave], sb, p_nloc, p_inv_off,
+                                             p_slot_off, gidx, inv, res, W, Y, transpose, D);
 }
 
 // Symmetric factored form from the factored form (one workgroup per patch): the wrapped
-// diagonals of every block inverse, each entry the mean of Z(i, j) and Z(j, i), which
-// agree up to the rounding of the factorisation.  Factored layout: column j of block b
+// diagonals of every block inverse in descending order, each entry the mean of Z(i, j)
+// and Z(j, i), which agree up to the rounding of the factorisation.  Factored layout: column j of block b
 // holds Z(i, j) at base_b + i (real) or base_b + 2 i + {0, 1} (pair, re and im).
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_pack_sym(int64_t np, irk::StageBasis<T> sb,
@@ -811,7 +817,7 @@ __global__ __launch_bounds__(kBlock) void k_pack_sym(int64_t np, irk::StageBasis
       const int64_t wi = e / VEC;
       const int i = (int)(wi % ns), g = (int)(wi / ns);
       const int k = v / type, comp = v - k * type;
-      const int sd = g * G + k;
+      const int sd = (int)(cnt / ((int64_t)ns * VEC)) * G - 1 - g * G - k;  // descending diagonals
       T val = T(0);
       if (sd < h) {
         const int j = (i + sd) % ns;
@@ -1432,10 +1438,17 @@ hipError_t residual(const DevLevel& L, const DevOps<T>& ops, const double* A, do
                     const T* F, const T* x, T* y, hipStream_t s) {
   const int64_t nsl = L.nsl_u + L.nsl_p;
   const unsigned g = (unsigned)((nsl + 3) / 4);
-  IRK_DISPATCH_DR(L.dim, L.r, (k_residual_sell<DD, RR, T><<<dim3(g), dim3(256), 0, s>>>(
-                                  L.nfree, L.nv, L.offV, L.nsl_u, L.nsl_p, L.su_off, L.su_w, L.su_col, ops.u_M,
-                                  ops.u_L, L.sb_off, L.sb_w, L.sb_col, ops.u_B, L.sp_off, L.sp_w, L.sp_col,
-                                  ops.p_Bt, scaled<T, RR>(A, dt), F, x, y)));
+  if (nsl <= kSmallWaves) {
+    IRK_DISPATCH_DR(L.dim, L.r, (k_residual_sell<DD, RR, T, 8><<<dim3(g), dim3(256), 0, s>>>(
+                                    L.nfree, L.nv, L.offV, L.nsl_u, L.nsl_p, L.su_off, L.su_w, L.su_col, ops.u_M,
+                                    ops.u_L, L.sb_off, L.sb_w, L.sb_col, ops.u_B, L.sp_off, L.sp_w, L.sp_col,
+                                    ops.p_Bt, scaled<T, RR>(A, dt), F, x, y)));
+  } else {
+    IRK_DISPATCH_DR(L.dim, L.r, (k_residual_sell<DD, RR, T, 4><<<dim3(g), dim3(256), 0, s>>>(
+                                    L.nfree, L.nv, L.offV, L.nsl_u, L.nsl_p, L.su_off, L.su_w, L.su_col, ops.u_M,
+                                    ops.u_L, L.sb_off, L.sb_w, L.sb_col, ops.u_B, L.sp_off, L.sp_w, L.sp_col,
+                                    ops.p_Bt, scaled<T, RR>(A, dt), F, x, y)));
+  }
   return hipGetLastError();
 }
 
@@ -1526,12 +1539,14 @@ hipError_t patch_apply(const DevLevel& L, const DevOps<T>& ops, const T* res, T*
   if (L.pform == 3) {
     const StageBasis<T>& sb = basis_of<T>(L);
     if (L.max_nloc > 256 || L.max_nloc / L.r > 64) return hipErrorInvalidValue;
-#define IRK_PAS(NM, U, WV)                                                                               \
-  k_patch_apply_sym<T, NM, U, WV><<<dim3(blocks_for(L.npatch, WV)), dim3(WV * 64), 0, s>>>(           \
+#define IRK_PAS(NM, U, PF, WV)                                                                           \
+  k_patch_apply_sym<T, NM, U, PF, WV><<<dim3(blocks_for(L.npatch, WV)), dim3(WV * 64), 0, s>>>(       \
       L.npatch, sb, L.sched, L.p_nloc, L.p_inv_off, L.p_slot_off, L.p_gidx, inv, res, W, Y, transpose, \
       L.dim)
-    if (L.max_nloc <= 128) IRK_PAS(128, 4, 4);
-    else IRK_PAS(256, 4, 4);
+    // one wavefront per workgroup, two 16-byte words per lane in flight: measured best
+    // on both the bandwidth-bound fine levels and the latency-bound coarse ones
+    if (L.max_nloc <= 128) IRK_PAS(128, 2, 0, 1);
+    else IRK_PAS(256, 2, 0, 1);
 #undef IRK_PAS
     return hipGetLastError();
   }
