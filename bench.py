@@ -202,6 +202,9 @@ def _pmc_rows(d, counter):
     return out
 
 
+PATCH_KERNELS = ("k_patch_apply_sym<double, 128", "k_patch_apply_eig<double, 1, 128")
+
+
 def summarize_pmc(fetch_dir, write_dir):
     """Per-launch HBM bytes of the finest-level patch apply from two rocprofv3 --pmc
     runs (FETCH_SIZE, WRITE_SIZE; KiB per dispatch), each scaled by what the same
@@ -210,7 +213,12 @@ def summarize_pmc(fetch_dir, write_dir):
     for name, d, counter in (("fetch", fetch_dir, "FETCH_SIZE"), ("write", write_dir, "WRITE_SIZE")):
         rows = _pmc_rows(d, counter)
         cal = [v for (k, g), vals in rows.items() if "neg_kernel" in k for v in vals]
-        pa = {(k, g): vals for (k, g), vals in rows.items() if "k_patch_apply_eig<double, 1, 128" in k}
+        pa = {}
+        for tag in PATCH_KERNELS:  # the form the bench workload uses (symmetric for Stokes)
+            pa = {(k, g): vals for (k, g), vals in rows.items() if tag in k}
+            if pa:
+                res["kernel"] = tag
+                break
         if not cal or not pa:
             raise SystemExit(f"{counter}: calibration or patch-apply dispatches missing in {d}")
         ideal_kib = CALIB_ELEMS * 8 / 1024.0
@@ -221,7 +229,7 @@ def summarize_pmc(fetch_dir, write_dir):
                          scale=scale, dispatches=len(vals), grid=key[1],
                          raw_kib_per_launch=sum(vals) / len(vals),
                          bytes_per_launch=scale * 1024.0 * sum(vals) / len(vals))
-    rec = {"kernel_source_sha256_16": kernel_source_hash(), "kernel": "k_patch_apply_eig<double, 1, 128> finest level",
+    rec = {"kernel_source_sha256_16": kernel_source_hash(), "kernel": res.pop("kernel") + "> finest level",
            "traffic_bytes_per_launch": res["fetch"]["bytes_per_launch"] + res["write"]["bytes_per_launch"],
            "fetch": res["fetch"], "write": res["write"]}
     print("traffic-record: " + json.dumps(rec))

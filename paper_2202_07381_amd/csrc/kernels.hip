@@ -50,11 +50,11 @@ const StageBasis<double>& basis_of<double>(const DevLevel& L) { return L.sb64; }
 template <>
 const StageBasis<float>& basis_of<float>(const DevLevel& L) { return L.sb32; }
 
-// Launches of at most this many wavefronts are resident on the chip at once (256 CUs,
-// 4 SIMDs, 2 waves each at the lowest occupancy of these kernels): their time is the
-// latency of one wavefront's dependent loads, so they keep more loads in flight per
-// lane at the cost of occupancy.
-constexpr int64_t kSmallWaves = 2048;
+// Patch counts up to kSmallPatches mark the small levels (64 x 64 and below on the
+// 256 x 256 hierarchy): their stored factors fit the last-level cache, so the patch
+// kernels read them with ordinary loads there and with non-temporal loads on the
+// large levels, whose factors stream through once per application.
+constexpr int64_t kSmallPatches = 8192;
 
 // ------------------------------------------------------------------------ residual
 template <int D, int R, typename T>
@@ -73,8 +73,7 @@ __global__ __launch_bounds__(kBlock) void k_residual(
 // Same residual from the sliced operator copies: one wavefront per slice of 64 rows
 // (velocity slices first, then vertex slices), lane = row, entries of the slice read
 // column-major (coalesced indices and values), kSellUnroll entries' gathers in flight
-// per lane: 4 where many slices share the chip, 8 on small levels, which are latency
-// bound (every slice resident at once).
+// per lane (4: more lowered occupancy and measured slower on every level).
 template <int D, int R, typename T, int kSellUnroll>
 __global__ __launch_bounds__(256) void k_residual_sell(
     int64_t nfree, int64_t nv, int64_t offV, int64_t nsu, int64_t nsp, const int32_t* __restrict__ su_off,
@@ -772,7 +771,7 @@ __global__ __launch_bounds__(WAVES * 64) __attribute__((amdgpu_waves_per_eu(WPE)
                                               p_slot_off, gidx, inv, res, W, Y, transpose, D);
 }
 
-template <typename T, int NMAX, int UNROLL, int PF, int WAVES>
+template <typename T, int NMAX, int UNROLL, int PF, int WAVES, int NT = 1>
 __global__ __launch_bounds__(WAVES * 64) void k_patch_apply_sym(
     int64_t npatch, irk::StageBasis<T> sb, const int32_t* __restrict__ sched,
     const int32_t* __restrict__ p_nloc, const int64_t* __restrict__ p_inv_off,
@@ -784,7 +783,7 @@ __global__ __launch_bounds__(WAVES * 64) void k_patch_apply_sym(
   const int wave = threadIdx.x >> 6;
   const int64_t idx = (int64_t)blockIdx.x * WAVES + wave;
   if (idx >= npatch) return;  // whole wavefront exits; no workgroup barrier below
-  dev::patch_apply_sym_one<T, UNROLL, 1, PF>(sched[idx], lane, xs[wave], xt[wave], sb, p_nloc, p_inv_off,
+  dev::patch_apply_sym_one<T, UNROLL, NT, PF>(sched[idx], lane, xs[wave], xt[wave], sb, p_nloc, p_inv_off,
                                              p_slot_off, gidx, inv, res, W, Y, transpose, D);
 }
 
@@ -1438,17 +1437,10 @@ hipError_t residual(const DevLevel& L, const DevOps<T>& ops, const double* A, do
                     const T* F, const T* x, T* y, hipStream_t s) {
   const int64_t nsl = L.nsl_u + L.nsl_p;
   const unsigned g = (unsigned)((nsl + 3) / 4);
-  if (nsl <= kSmallWaves) {
-    IRK_DISPATCH_DR(L.dim, L.r, (k_residual_sell<DD, RR, T, 8><<<dim3(g), dim3(256), 0, s>>>(
-                                    L.nfree, L.nv, L.offV, L.nsl_u, L.nsl_p, L.su_off, L.su_w, L.su_col, ops.u_M,
-                                    ops.u_L, L.sb_off, L.sb_w, L.sb_col, ops.u_B, L.sp_off, L.sp_w, L.sp_col,
-                                    ops.p_Bt, scaled<T, RR>(A, dt), F, x, y)));
-  } else {
-    IRK_DISPATCH_DR(L.dim, L.r, (k_residual_sell<DD, RR, T, 4><<<dim3(g), dim3(256), 0, s>>>(
-                                    L.nfree, L.nv, L.offV, L.nsl_u, L.nsl_p, L.su_off, L.su_w, L.su_col, ops.u_M,
-                                    ops.u_L, L.sb_off, L.sb_w, L.sb_col, ops.u_B, L.sp_off, L.sp_w, L.sp_col,
-                                    ops.p_Bt, scaled<T, RR>(A, dt), F, x, y)));
-  }
+  IRK_DISPATCH_DR(L.dim, L.r, (k_residual_sell<DD, RR, T, 4><<<dim3(g), dim3(256), 0, s>>>(
+                                  L.nfree, L.nv, L.offV, L.nsl_u, L.nsl_p, L.su_off, L.su_w, L.su_col, ops.u_M,
+                                  ops.u_L, L.sb_off, L.sb_w, L.sb_col, ops.u_B, L.sp_off, L.sp_w, L.sp_col,
+                                  ops.p_Bt, scaled<T, RR>(A, dt), F, x, y)));
   return hipGetLastError();
 }
 
@@ -1539,14 +1531,21 @@ hipError_t patch_apply(const DevLevel& L, const DevOps<T>& ops, const T* res, T*
   if (L.pform == 3) {
     const StageBasis<T>& sb = basis_of<T>(L);
     if (L.max_nloc > 256 || L.max_nloc / L.r > 64) return hipErrorInvalidValue;
-#define IRK_PAS(NM, U, PF, WV)                                                                           \
-  k_patch_apply_sym<T, NM, U, PF, WV><<<dim3(blocks_for(L.npatch, WV)), dim3(WV * 64), 0, s>>>(       \
+#define IRK_PAS(NM, U, PF, WV, ...)                                                                      \
+  k_patch_apply_sym<T, NM, U, PF, WV, ##__VA_ARGS__><<<dim3(blocks_for(L.npatch, WV)), dim3(WV * 64), 0, s>>>(       \
       L.npatch, sb, L.sched, L.p_nloc, L.p_inv_off, L.p_slot_off, L.p_gidx, inv, res, W, Y, transpose, \
       L.dim)
     // one wavefront per workgroup, two 16-byte words per lane in flight: measured best
     // on both the bandwidth-bound fine levels and the latency-bound coarse ones
-    if (L.max_nloc <= 128) IRK_PAS(128, 2, 0, 1);
-    else IRK_PAS(256, 2, 0, 1);
+    // one wavefront per workgroup, two 16-byte words per lane in flight; non-temporal
+    // loads where the factors stream from memory once per application, ordinary loads
+    // on the small levels, whose factors the last-level cache keeps between applications
+    const bool small = L.npatch <= kSmallPatches;
+    if (L.max_nloc <= 128) {
+      if (small) IRK_PAS(128, 2, 0, 1, 0);
+      else IRK_PAS(128, 2, 0, 1, 1);
+    } else if (small) IRK_PAS(256, 2, 0, 1, 0);
+    else IRK_PAS(256, 2, 0, 1, 1);
 #undef IRK_PAS
     return hipGetLastError();
   }
@@ -1559,7 +1558,9 @@ hipError_t patch_apply(const DevLevel& L, const DevOps<T>& ops, const T* res, T*
       transpose, L.dim)
     // 4 columns in flight per lane with non-temporal loads: at 62 VGPRs the 2D kernel
     // runs 8 waves per SIMD; deeper unrolling lowered occupancy and measured slower
-    if (L.max_nloc <= 128 && rbe <= 1) IRK_PAE(1, 128, 4, 1, 4);
+    const bool small = L.npatch <= kSmallPatches;
+    if (small && L.max_nloc <= 128 && rbe <= 1) IRK_PAE(1, 128, 4, 0, 4);
+    else if (L.max_nloc <= 128 && rbe <= 1) IRK_PAE(1, 128, 4, 1, 4);
     else if (L.max_nloc <= 256 && rbe <= 2) IRK_PAE(2, 256, 4, 1, 4);
     else if (L.max_nloc <= 512 && rbe <= 2) IRK_PAE(2, 512, 4, 1, 4);
     else if (L.max_nloc <= 512 && rbe <= 4) IRK_PAE(4, 512, 2, 1, 4);
