@@ -4,8 +4,9 @@ TEST INFRASTRUCTURE ONLY (oracle).
 
 Hierarchy from uniform refinement; coarse operators by rediscretisation (assembly of
 the stage system on every level, Sec. 4.1); interpolation I_r (x) P, restriction its
-transpose; additive Vanka relaxation with `pre` and `post` sweeps or Chebyshev
-steps (Sec. 5.1 uses 2 and 2); direct solve on the coarsest level (Sec. 4.1 uses a
+transpose; additive Vanka relaxation with `pre` and `post` sweeps, Chebyshev
+steps (Sec. 5.1 uses 2 and 2) or GMRES steps (Sec. 5.4 uses 3 and 3); direct solve
+on the coarsest level (Sec. 4.1 uses a
 sparse direct solver; here a dense LU with partial pivoting).
 
 Readings where the paper is silent:
@@ -42,13 +43,15 @@ class Hierarchy:
                  dtype=np.float64, smoother="sweep", interval=(2.0, 8.0)):
         """mesh_levels: coarse-to-fine sequence of objects with .xyz and .cells.
         wind: callable (points, t) -> (npts, dim) or None (Stokes).
-        smoother: "sweep" (damped additive sweeps, omega and weighting) or "chebyshev"
-        (Chebyshev relaxation on `interval` with the additive operator, Sec. 5.1)."""
+        smoother: "sweep" (damped additive sweeps, omega and weighting), "chebyshev"
+        (Chebyshev relaxation on `interval` with the additive operator, Sec. 5.1) or
+        "gmres" (`pre`/`post` steps of GMRES preconditioned by the additive operator,
+        Sec. 4.2, 5.4)."""
         self.A = np.asarray(A, dtype=np.float64)
         self.r = self.A.shape[0]
         self.pre, self.post = pre, post
-        if smoother not in ("sweep", "chebyshev"):
-            raise ValueError("smoother must be 'sweep' or 'chebyshev'")
+        if smoother not in ("sweep", "chebyshev", "gmres"):
+            raise ValueError("smoother must be 'sweep', 'chebyshev' or 'gmres'")
         self.smoother, self.interval = smoother, (float(interval[0]), float(interval[1]))
         self.dtype = dtype
         self.spaces = [TaylorHood(m.xyz, m.cells) for m in mesh_levels]
@@ -103,6 +106,8 @@ class Hierarchy:
     def _relax(self, sm, b, x, Jop, steps, transpose):
         if self.smoother == "chebyshev":
             return sm.chebyshev(b, x, Jop, steps, *self.interval, transpose) if steps > 0 else x
+        if self.smoother == "gmres":
+            return sm.gmres(b, x, Jop, steps, transpose) if steps > 0 else x
         for _ in range(steps):
             x = sm.sweep(b, x, Jop, transpose)
         return x

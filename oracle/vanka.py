@@ -27,10 +27,26 @@ so that after m steps the error is T_m((theta - S J)/delta) / T_m(theta/delta) t
 the initial error (T_m the Chebyshev polynomial of the first kind).  The transposed
 relaxation (adjoint) is the same recurrence with J^T and S^T.
 
+GMRES relaxation (Sec. 4.2: several steps of a Vanka-preconditioned GMRES iteration as
+the relaxation; Sec. 5.4 uses 3 such pre- and post-steps for its convective problem).
+The paper leaves the GMRES variant open; the reading here is one cycle of m steps of
+left-preconditioned GMRES on J k = F with the additive operator S, from the current k:
+with r_0 = F - J k and beta = ||S r_0||, v_0 = S r_0 / beta and for j < m the Arnoldi
+step w = S J v_j, h_ij = <w, v_i> for i <= j against the unmodified w (classical
+Gram--Schmidt), w -= sum_i h_ij v_i, h_{j+1,j} = ||w||, v_{j+1} = w / h_{j+1,j};
+then y minimises ||beta e_1 - H y|| over the (m+1) x m Hessenberg H and
+k <- k + sum_j y_j v_j.  A zero h_{j+1,j} (the Krylov space is invariant) ends the
+cycle with the j+1 steps taken; beta = 0 leaves k unchanged.  The result depends
+nonlinearly on F, so the V-cycle is a nonlinear preconditioner and the outer
+iteration must be flexible (Sec. 4.1).  The transposed relaxation uses J^T and S^T.
+
 Pinned by tests/test_oracle_vanka.py against: Fig. 1's patch (19 velocity nodes and
 one pressure node for an interior vertex); the DOF cover; single-patch exactness
 (R_v^T A_v^{-1} R_v J e = e for e supported on S_v); multiplicity bounds; the
-Chebyshev error polynomial in closed form on a diagonal operator.
+Chebyshev error polynomial in closed form on a diagonal operator; the GMRES relaxation
+against the minimal-residual step in closed form (m = 1), against a least-squares
+solve over the power basis of the Krylov space (m = 3), and against the exact solution
+when m reaches the dimension.
 """
 from __future__ import annotations
 
@@ -111,6 +127,11 @@ class VankaSmoother:
         return chebyshev_iteration(lambda x: Jop @ x, lambda r: self.apply_S(r, transpose), F, k, steps, lo, hi,
                                    self.dtype)
 
+    def gmres(self, F: np.ndarray, k: np.ndarray, Jop, steps: int, transpose: bool = False) -> np.ndarray:
+        """GMRES relaxation (module docstring) with the additive operator; Jop is J (or
+        J^T for the transposed relaxation) in the working precision."""
+        return gmres_relaxation(lambda x: Jop @ x, lambda r: self.apply_S(r, transpose), F, k, steps, self.dtype)
+
     def sweep(self, F: np.ndarray, k: np.ndarray, Jop, transpose: bool = False) -> np.ndarray:
         """One additive sweep on k, returning the new k.  Jop is the level operator in
         the working precision (J itself, or J^T for the transposed smoother)."""
@@ -139,4 +160,35 @@ def chebyshev_iteration(apply_J, apply_S, F, k, steps: int, lo: float, hi: float
             d = dtype(rho_new * rho) * d + dtype(2.0 * rho_new / delta) * z
             rho = rho_new
         k = k + d
+    return k
+
+
+def gmres_relaxation(apply_J, apply_S, F, k, steps: int, dtype=np.float64):
+    """One cycle of `steps` left-preconditioned GMRES steps for J k = F from k
+    (Arnoldi with classical Gram--Schmidt, Hessenberg least squares; module docstring).
+    Vectors are kept in `dtype`, inner products and the small problem in float64."""
+    k = np.array(k, dtype=dtype)
+    z = apply_S(np.asarray(F, dtype=dtype) - apply_J(k))
+    beta = float(np.linalg.norm(z.astype(np.float64)))
+    if steps <= 0 or beta == 0.0:
+        return k
+    V = [(z / dtype(beta)).astype(dtype)]
+    H = np.zeros((steps + 1, steps))
+    m = steps
+    for j in range(steps):
+        w = apply_S(apply_J(V[j]))
+        h = np.array([float(np.dot(V[i].astype(np.float64), w.astype(np.float64))) for i in range(j + 1)])
+        for i in range(j + 1):
+            w = w - dtype(h[i]) * V[i]
+        H[:j + 1, j] = h
+        H[j + 1, j] = float(np.linalg.norm(w.astype(np.float64)))
+        if H[j + 1, j] == 0.0:
+            m = j + 1
+            break
+        V.append((w / dtype(H[j + 1, j])).astype(dtype))
+    e1 = np.zeros(m + 1)
+    e1[0] = beta
+    y = np.linalg.lstsq(H[:m + 1, :m], e1, rcond=None)[0]
+    for j in range(m):
+        k = k + dtype(y[j]) * V[j]
     return k

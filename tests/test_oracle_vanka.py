@@ -107,3 +107,63 @@ def test_chebyshev_error_polynomial(steps):
     theta, delta = 0.5 * (hi + lo), 0.5 * (hi - lo)
     expect = _cheb_T(steps, (theta - sl) / delta) / _cheb_T(steps, np.array([theta / delta]))[0]
     assert np.allclose((xstar - k) / e0, expect, rtol=1e-12, atol=1e-13)
+
+
+# ------------------------------------------------------------ GMRES relaxation
+def _vanka_case():
+    xyz, cells = wl.square_mesh(4)
+    th = TaylorHood(xyz, cells)
+    A, b, c = tableau("radauIIA", 2)
+    S = StageSystem(th, A, 0.05, 1.0)
+    sm = VankaSmoother(S.J, patch_dofs(th, 2), 1.0, weighted=True)
+    rng = np.random.default_rng(41)
+    return S, sm, rng.standard_normal(S.n), rng.standard_normal(S.n)
+
+
+def test_gmres_relaxation_one_step_is_minimal_residual():
+    """m = 1: with z = S r_0 and q = S J z, the step minimising ||S (F - J (k + a z))|| has
+    a = <q, z> / <q, q> (the one-dimensional least-squares problem in closed form)."""
+    S, sm, F, k0 = _vanka_case()
+    for tr in (False, True):
+        J = S.J.T if tr else S.J
+        z = sm.apply_S(F - J @ k0, tr)
+        q = sm.apply_S(J @ z, tr)
+        expect = k0 + (q @ z) / (q @ q) * z
+        got = sm.gmres(F, k0, J, 1, tr)
+        assert np.linalg.norm(got - expect) <= 1e-12 * np.linalg.norm(expect)
+
+
+def test_gmres_relaxation_matches_krylov_least_squares():
+    """m = 3 against a least-squares solve over the power basis z, Mz, M^2 z (M = S J) of
+    the Krylov space: the GMRES iterate is k + K c with c minimising ||z - M K c||; and
+    the preconditioned residual norm does not grow with m."""
+    S, sm, F, k0 = _vanka_case()
+    J = S.J
+    M = lambda x: sm.apply_S(J @ x)
+    z = sm.apply_S(F - J @ k0)
+    K = np.stack([z, M(z), M(M(z))], axis=1)
+    MK = np.stack([M(K[:, i]) for i in range(3)], axis=1)
+    c = np.linalg.lstsq(MK, z, rcond=None)[0]
+    expect = k0 + K @ c
+    got = sm.gmres(F, k0, J, 3)
+    assert np.linalg.norm(got - expect) <= 1e-9 * np.linalg.norm(expect)
+    norms = [np.linalg.norm(sm.apply_S(F - J @ sm.gmres(F, k0, J, m))) for m in range(0, 5)]
+    assert all(norms[i + 1] <= norms[i] * (1 + 1e-12) for i in range(4))
+
+
+def test_gmres_relaxation_full_dimension_is_exact():
+    """With as many steps as unknowns GMRES solves S J k = S F exactly (nonsingular S), and
+    an invariant Krylov space (S J = I) ends the cycle early with the exact solution."""
+    from oracle.vanka import gmres_relaxation
+
+    rng = np.random.default_rng(43)
+    n = 7
+    J = rng.standard_normal((n, n)) + 4 * np.eye(n)
+    Sm = rng.standard_normal((n, n)) + 3 * np.eye(n)
+    F, k0 = rng.standard_normal(n), rng.standard_normal(n)
+    got = gmres_relaxation(lambda x: J @ x, lambda r: Sm @ r, F, k0, n)
+    assert np.allclose(got, np.linalg.solve(J, F), rtol=1e-9, atol=1e-10)
+    Jinv = np.linalg.inv(J)
+    got = gmres_relaxation(lambda x: J @ x, lambda r: Jinv @ r, F, k0, 3)
+    assert np.allclose(got, np.linalg.solve(J, F), rtol=1e-12, atol=1e-12)
+    assert np.array_equal(gmres_relaxation(lambda x: J @ x, lambda r: Sm @ r, J @ k0, k0, 3), k0)
