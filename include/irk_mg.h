@@ -112,7 +112,12 @@ typedef struct irk_mg_opts {
                         semi-iteration (Sec. 5.1) accelerating W S, S the additive
                         Vanka operator, for the spectrum interval [cheb_lo,
                         cheb_hi] of W S J (omega unused; the paper's runs use the
-                        unweighted operator, weighting = 0, on [2, 8])          */
+                        unweighted operator, weighting = 0, on [2, 8]);
+                        2 = one cycle of `pre`/`post` (at most 8) steps of GMRES
+                        left-preconditioned by W S (Sec. 4.2, 5.4), from the
+                        current iterate, classical Gram--Schmidt: a nonlinear
+                        relaxation, so the V-cycle is a nonlinear preconditioner
+                        (the solvers here are flexible); omega unused          */
   double cheb_lo, cheb_hi; /* 0 < cheb_lo < cheb_hi, else IRK_EINVAL            */
 } irk_mg_opts;
 
@@ -193,7 +198,9 @@ irk_status irk_mg_apply(irk_mg* h, const double* x, double* y, int transpose, vo
  * cycle runs in FP32 except for the coarse solve.  r and z may not alias. */
 irk_status irk_mg_vcycle(irk_mg* h, const double* r, double* z, void* stream);
 
-/* z = V^T r: the transpose of irk_mg_vcycle as a linear map (used by adjoint solves). */
+/* z = V^T r: the transpose of irk_mg_vcycle as a linear map (used by adjoint solves).
+ * With the GMRES relaxation (smoother 2) the V-cycle is not linear; this is then the
+ * same cycle for J^T with the transposed patch solves and relaxations. */
 irk_status irk_mg_vcycle_transpose(irk_mg* h, const double* r, double* z, void* stream);
 
 /* Solve J k = F by restarted FGMRES(restart) right-preconditioned with irk_mg_vcycle
@@ -257,7 +264,9 @@ irk_status irk_mass_apply(irk_mg* h, const double* state, double* out, void* str
 irk_status irk_level_apply(irk_mg* h, int level, int transpose, const double* x, double* y,
                            void* stream);
 /* One additive Vanka sweep on level l >= 1 (Sec. 4.2): k <- k + omega W sum_v R_v^T
- * A_v^{-1} R_v (F - J_l k); transpose = 1 gives the transposed sweep for J_l^T. */
+ * A_v^{-1} R_v (F - J_l k); transpose = 1 gives the transposed sweep for J_l^T.  With
+ * smoother 1 it is one Chebyshev step, with smoother 2 one GMRES step (the relaxation
+ * the handle uses, with one step). */
 irk_status irk_level_sweep(irk_mg* h, int level, int transpose, const double* F, double* k,
                            void* stream);
 /* xc = (I_r (x) P_l)^T xf: restriction from level l >= 1 to level l-1 (Sec. 4.1). */

@@ -20,6 +20,8 @@
 namespace irk {
 
 constexpr int kMaxStages = 4;
+// most GMRES relaxation steps per cycle (smoother 2)
+constexpr int kMaxGr = 8;
 
 // Sliced copy of a CSR operator for the residual kernel: rows in slices of 64, each slice
 // padded to its longest row, entries of a slice stored column-major (entry k of the 64
@@ -228,6 +230,7 @@ struct DevLevel {
   // work vectors (internal layout) in the working precision
   void *b = nullptr, *x = nullptr, *res = nullptr, *Y = nullptr;
   void* dch = nullptr;  // Chebyshev direction vector
+  void* grv = nullptr;  // GMRES relaxation basis: (steps + 1) vectors of N
 };
 
 struct Handle {
@@ -255,6 +258,8 @@ struct Handle {
          *kr = nullptr;
   double* scal = nullptr;      // device scalars (dot results)
   double* partials = nullptr;  // reduction partials
+  double* gr = nullptr;        // GMRES relaxation: Hessenberg, norms, coefficients
+  double* grpart = nullptr;    // GMRES relaxation: per-block partial sums
   double* hbuf = nullptr;      // device Hessenberg column
   std::vector<void*> allocations;
   int64_t* pins = nullptr;  // device: pinned coarse pressure DOFs (one per stage)
@@ -337,6 +342,22 @@ hipError_t to_abi(const DevLevel& L, const T* x, double* abi, hipStream_t s);
 template <typename S, typename D>
 hipError_t cast(const S* in, D* out, int64_t n, hipStream_t s);
 hipError_t project_pressure(const DevLevel& L, double* x, double* partials, hipStream_t s);
+// GMRES relaxation pieces (smoother 2).  `gr` holds H column-major with leading
+// dimension kMaxGr + 1, then the norm slots (kGrNorm + i) and the coefficients
+// (kGrY + j); `part` holds kGrBlocks partial sums per vector.
+constexpr int kGrH = 0, kGrNorm = (kMaxGr + 1) * kMaxGr, kGrY = kGrNorm + kMaxGr + 2,
+              kGrSize = kGrY + kMaxGr, kGrBlocks = 256;
+template <typename T>
+hipError_t gr_dots(const T* V, int64_t ldv, int nv, const T* w, int64_t n, double* part, double* out,
+                   hipStream_t s);
+template <typename T>
+hipError_t gr_orth_norm(T* w, const T* V, int64_t ldv, int j, int64_t n, const double* h, double* part,
+                        double* nrm, hipStream_t s);
+template <typename T>
+hipError_t gr_scale(T* v, int64_t n, const double* d, hipStream_t s);
+hipError_t gr_solve(double* gr, int m, hipStream_t s);
+template <typename T>
+hipError_t gr_update(T* x, const T* V, int64_t ldv, int m, int64_t n, const double* y, int assign, hipStream_t s);
 // deterministic reductions: result written to device scalar *out
 hipError_t dot(const double* a, const double* b, int64_t n, double* partials, double* out,
                hipStream_t s, int take_sqrt = 0);

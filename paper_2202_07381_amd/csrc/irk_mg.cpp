@@ -157,6 +157,52 @@ irk_status smooth(Handle* h, int l, int nsweeps, bool zero_start, bool tr, hipSt
     ot.s_L = o.s_Lt;
     ot.u_L = o.u_Lt;
   }
+  if (h->smoother == 2) {
+    // GMRES relaxation (Sec. 4.2, 5.4): one cycle of nsweeps left-preconditioned GMRES
+    // steps with the additive operator from the current x (zero when zero_start),
+    // classical Gram--Schmidt, least squares on the device
+    const int m = nsweeps;
+    T* V = (T*)L.grv;
+    const int64_t N = L.N;
+    double* gr = h->gr;
+    const int mode = tr ? 2 : 0;  // assign W S r (forward) or S (W r) (transposed)
+    const T* r = b;
+    if (!zero_start) {
+      const int p0 = prof_begin(h, 1, l, s);
+      HIPCHK(k::residual<T>(L, ot, A, h->dt, b, x, res, s));
+      prof_end(h, p0, s);
+      r = res;
+    }
+    int p1 = prof_begin(h, 0, l, s);
+    HIPCHK(k::patch_apply<T>(L, o, r, Y, tr ? 1 : 0, s));
+    prof_end(h, p1, s);
+    int p2 = prof_begin(h, 2, l, s);
+    HIPCHK(k::gather_update<T>(L, o, Y, V, (T)1, mode, s));
+    prof_end(h, p2, s);
+    // beta = ||v_0|| (an orthogonalisation against no vectors), v_0 /= beta
+    HIPCHK(k::gr_orth_norm<T>(V, V, N, -1, N, gr, h->grpart, gr + k::kGrNorm, s));
+    HIPCHK(k::gr_scale<T>(V, N, gr + k::kGrNorm, s));
+    for (int j = 0; j < m; ++j) {
+      T* Vj = V + (int64_t)j * N;
+      T* Vn = V + (int64_t)(j + 1) * N;
+      const int p3 = prof_begin(h, 1, l, s);
+      HIPCHK(k::residual<T>(L, ot, A, h->dt, nullptr, Vj, res, s));
+      prof_end(h, p3, s);
+      p1 = prof_begin(h, 0, l, s);
+      HIPCHK(k::patch_apply<T>(L, o, res, Y, tr ? 1 : 0, s));
+      prof_end(h, p1, s);
+      p2 = prof_begin(h, 2, l, s);
+      HIPCHK(k::gather_update<T>(L, o, Y, Vn, (T)1, mode, s));
+      prof_end(h, p2, s);
+      double* hcol = gr + k::kGrH + (int64_t)j * (kMaxGr + 1);
+      HIPCHK(k::gr_dots<T>(V, N, j + 1, Vn, N, h->grpart, hcol, s));
+      HIPCHK(k::gr_orth_norm<T>(Vn, V, N, j, N, hcol, h->grpart, hcol + j + 1, s));
+      HIPCHK(k::gr_scale<T>(Vn, N, hcol + j + 1, s));
+    }
+    HIPCHK(k::gr_solve(gr, m, s));
+    HIPCHK(k::gr_update<T>(x, V, N, m, N, gr + k::kGrY, zero_start ? 1 : 0, s));
+    return IRK_OK;
+  }
   if (h->smoother == 1) {
     // Chebyshev relaxation (Sec. 5.1) on [cheb_lo, cheb_hi]: theta, delta, sigma and the
     // rho recurrence of the Chebyshev semi-iteration, coefficients formed in FP64
@@ -1009,9 +1055,18 @@ static irk_status setup_impl(const irk_mesh_level* lv, int nlevels, const irk_ta
         CHK(dalloc(h, &tmp, (D.N * es + 7) / 8));
         D.dch = tmp;
       }
+      if (h->smoother == 2) {
+        const int64_t nv = std::max(std::max(h->pre, h->post), 1) + 1;
+        CHK(dalloc(h, &tmp, (nv * D.N * es + 7) / 8));
+        D.grv = tmp;
+      }
       CHK(dalloc(h, &tmp, (D.inv_elems * es + 7) / 8));
       D.inv = tmp;
     }
+  }
+  if (h->smoother == 2) {
+    CHK(dalloc(h, &h->gr, (size_t)k::kGrSize));
+    CHK(dalloc(h, &h->grpart, (size_t)k::kGrBlocks * (kMaxGr + 1)));
   }
   // ---- patch factorisation on the GPU
   int* dfail;
@@ -1094,7 +1149,9 @@ irk_status irk_mg_setup(const irk_mesh_level* lv, int nlevels, const irk_tableau
     if (opt->weighting != 0 && opt->weighting != 1) return fail(IRK_EINVAL, "weighting must be 0 or 1");
     if (opt->precision != 0 && opt->precision != 1) return fail(IRK_EINVAL, "precision must be 0 or 1");
     if (opt->patch_form < 0 || opt->patch_form > 3) return fail(IRK_EINVAL, "patch_form must be 0, 1, 2 or 3");
-    if (opt->smoother != 0 && opt->smoother != 1) return fail(IRK_EINVAL, "smoother must be 0 or 1");
+    if (opt->smoother < 0 || opt->smoother > 2) return fail(IRK_EINVAL, "smoother must be 0, 1 or 2");
+    if (opt->smoother == 2 && (opt->pre > kMaxGr || opt->post > kMaxGr))
+      return fail(IRK_EINVAL, "GMRES relaxation takes at most " + std::to_string(kMaxGr) + " steps");
     if (opt->smoother == 1 && !(opt->cheb_lo > 0 && opt->cheb_hi > opt->cheb_lo && std::isfinite(opt->cheb_hi)))
       return fail(IRK_EINVAL, "Chebyshev interval must satisfy 0 < cheb_lo < cheb_hi < inf");
   }

@@ -1064,6 +1064,138 @@ __global__ __launch_bounds__(kBlock) void k_project_apply(double* __restrict__ x
     x[offV + e] -= mean[e % R];
 }
 
+// ------------------------------------------------------------- GMRES relaxation
+// One cycle of left-preconditioned GMRES on a level (Arnoldi with classical
+// Gram--Schmidt, Hessenberg least squares by Givens rotations): block partial sums in
+// a fixed order, one workgroup finishing each reduction, the small problem on one
+// thread; nothing returns to the host.
+// part[i * gridDim + block] = block's share of <V_i, w> (i < nv), accumulated in FP64
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_gr_dots(int64_t n, int nv, const T* __restrict__ V, int64_t ldv,
+                                                    const T* __restrict__ w, double* __restrict__ part) {
+  __shared__ double red[kBlock];
+  double acc[kMaxGr + 1];
+#pragma unroll
+  for (int i = 0; i <= kMaxGr; ++i) acc[i] = 0.0;
+  for (int64_t g = (int64_t)blockIdx.x * kBlock + threadIdx.x; g < n; g += (int64_t)gridDim.x * kBlock) {
+    const double wg = (double)w[g];
+#pragma unroll
+    for (int i = 0; i <= kMaxGr; ++i)
+      if (i < nv) acc[i] += (double)V[(int64_t)i * ldv + g] * wg;
+  }
+  for (int i = 0; i < nv; ++i) {
+    red[threadIdx.x] = acc[i];
+    __syncthreads();
+    for (int k = kBlock / 2; k > 0; k >>= 1) {
+      if ((int)threadIdx.x < k) red[threadIdx.x] += red[threadIdx.x + k];
+      __syncthreads();
+    }
+    if (threadIdx.x == 0) part[(int64_t)i * gridDim.x + blockIdx.x] = red[0];
+    __syncthreads();
+  }
+}
+
+// out[i] = sum over blocks of part[i * nb + b] (fixed order); sq: out[0] = sqrt(sum)
+__global__ __launch_bounds__(kBlock) void k_gr_finish(const double* __restrict__ part, int nb, int nv, int sq,
+                                                      double* __restrict__ out) {
+  __shared__ double red[kBlock];
+  for (int i = 0; i < nv; ++i) {
+    red[threadIdx.x] = (int)threadIdx.x < nb ? part[(int64_t)i * nb + threadIdx.x] : 0.0;
+    __syncthreads();
+    for (int k = kBlock / 2; k > 0; k >>= 1) {
+      if ((int)threadIdx.x < k) red[threadIdx.x] += red[threadIdx.x + k];
+      __syncthreads();
+    }
+    if (threadIdx.x == 0) out[i] = sq ? sqrt(red[0]) : red[0];
+    __syncthreads();
+  }
+}
+
+// w -= sum_{i <= j} h_i V_i (in order), part = block's share of ||w||^2
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_gr_orth(int64_t n, int j, const T* __restrict__ V, int64_t ldv,
+                                                    const double* __restrict__ h, T* __restrict__ w,
+                                                    double* __restrict__ part) {
+  __shared__ double red[kBlock];
+  double acc = 0.0;
+  for (int64_t g = (int64_t)blockIdx.x * kBlock + threadIdx.x; g < n; g += (int64_t)gridDim.x * kBlock) {
+    double v = (double)w[g];
+    for (int i = 0; i <= j; ++i) v -= h[i] * (double)V[(int64_t)i * ldv + g];
+    const T t = (T)v;
+    w[g] = t;
+    acc += (double)t * (double)t;
+  }
+  red[threadIdx.x] = acc;
+  __syncthreads();
+  for (int k = kBlock / 2; k > 0; k >>= 1) {
+    if ((int)threadIdx.x < k) red[threadIdx.x] += red[threadIdx.x + k];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) part[blockIdx.x] = red[0];
+}
+
+// v /= d (a zero norm leaves a zero vector)
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_gr_scale(int64_t n, const double* __restrict__ d, T* __restrict__ v) {
+  const int64_t g = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (g >= n) return;
+  const double dd = *d;
+  v[g] = dd > 0.0 ? (T)((double)v[g] / dd) : T(0);
+}
+
+// y minimising ||beta e_1 - H y|| for the first m_eff columns, m_eff the steps before the
+// first zero subdiagonal entry (an invariant Krylov space); y = 0 past m_eff
+__global__ void k_gr_solve(double* __restrict__ gr, int m) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  constexpr int ld = kMaxGr + 1;
+  const double* H = gr + kGrH;
+  const double beta = gr[kGrNorm];
+  double* y = gr + kGrY;
+  int me = m;
+  for (int j = 0; j < m; ++j)
+    if (!(H[j * ld + j + 1] != 0.0)) {
+      me = j + 1;
+      break;
+    }
+  double R[ld * kMaxGr], g[ld], c[kMaxGr], sn[kMaxGr];
+  for (int i = 0; i < ld * kMaxGr; ++i) R[i] = H[i];
+  for (int i = 0; i < ld; ++i) g[i] = 0.0;
+  g[0] = beta;
+  for (int j = 0; j < me; ++j) {
+    for (int i = 0; i < j; ++i) {  // earlier rotations on column j
+      const double a = R[j * ld + i], b = R[j * ld + i + 1];
+      R[j * ld + i] = c[i] * a + sn[i] * b;
+      R[j * ld + i + 1] = -sn[i] * a + c[i] * b;
+    }
+    const double a = R[j * ld + j], b = R[j * ld + j + 1];
+    const double rr = hypot(a, b);
+    c[j] = rr > 0.0 ? a / rr : 1.0;
+    sn[j] = rr > 0.0 ? b / rr : 0.0;
+    R[j * ld + j] = rr;
+    R[j * ld + j + 1] = 0.0;
+    const double g0 = g[j], g1 = g[j + 1];
+    g[j] = c[j] * g0 + sn[j] * g1;
+    g[j + 1] = -sn[j] * g0 + c[j] * g1;
+  }
+  for (int j = kMaxGr - 1; j >= 0; --j) y[j] = 0.0;
+  for (int j = me - 1; j >= 0; --j) {
+    double t = g[j];
+    for (int k = j + 1; k < me; ++k) t -= R[k * ld + j] * y[k];
+    y[j] = R[j * ld + j] != 0.0 ? t / R[j * ld + j] : 0.0;
+  }
+}
+
+// x = (assign ? 0 : x) + sum_j y_j V_j (in order)
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_gr_update(int64_t n, int m, const T* __restrict__ V, int64_t ldv,
+                                                      const double* __restrict__ y, int assign, T* __restrict__ x) {
+  const int64_t g = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (g >= n) return;
+  double v = assign ? 0.0 : (double)x[g];
+  for (int j = 0; j < m; ++j) v += y[j] * (double)V[(int64_t)j * ldv + g];
+  x[g] = (T)v;
+}
+
 // ------------------------------------------------------------------------- BLAS-1
 __global__ __launch_bounds__(kBlock) void k_dot_partial(const double* __restrict__ a,
                                                         const double* __restrict__ b, int64_t n,
@@ -1626,6 +1758,43 @@ hipError_t prolong_add(const DevLevel& F, const DevLevel& C, const DevOps<T>& fo
   return hipGetLastError();
 }
 
+template <typename T>
+hipError_t gr_dots(const T* V, int64_t ldv, int nv, const T* w, int64_t n, double* part, double* out,
+                   hipStream_t s) {
+  if (nv < 1 || nv > kMaxGr + 1) return hipErrorInvalidValue;
+  const int nb = (int)std::min<int64_t>(kGrBlocks, blocks_for(n));
+  k_gr_dots<T><<<dim3(nb), dim3(kBlock), 0, s>>>(n, nv, V, ldv, w, part);
+  k_gr_finish<<<dim3(1), dim3(kBlock), 0, s>>>(part, nb, nv, 0, out);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t gr_orth_norm(T* w, const T* V, int64_t ldv, int j, int64_t n, const double* h, double* part,
+                        double* nrm, hipStream_t s) {
+  const int nb = (int)std::min<int64_t>(kGrBlocks, blocks_for(n));
+  k_gr_orth<T><<<dim3(nb), dim3(kBlock), 0, s>>>(n, j, V, ldv, h, w, part);
+  k_gr_finish<<<dim3(1), dim3(kBlock), 0, s>>>(part, nb, 1, 1, nrm);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t gr_scale(T* v, int64_t n, const double* d, hipStream_t s) {
+  k_gr_scale<T><<<dim3(blocks_for(n)), dim3(kBlock), 0, s>>>(n, d, v);
+  return hipGetLastError();
+}
+
+hipError_t gr_solve(double* gr, int m, hipStream_t s) {
+  if (m < 1 || m > kMaxGr) return hipErrorInvalidValue;
+  k_gr_solve<<<dim3(1), dim3(64), 0, s>>>(gr, m);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t gr_update(T* x, const T* V, int64_t ldv, int m, int64_t n, const double* y, int assign, hipStream_t s) {
+  k_gr_update<T><<<dim3(blocks_for(n)), dim3(kBlock), 0, s>>>(n, m, V, ldv, y, assign, x);
+  return hipGetLastError();
+}
+
 hipError_t dense_inverse(double* J, int64_t N, double tol, double* colk, int64_t* swp, int* fail, hipStream_t s) {
   const unsigned gu = (unsigned)((N * N + kBlock - 1) / kBlock);
   for (int64_t k = 0; k < N; ++k) {
@@ -1820,6 +1989,11 @@ hipError_t mass_apply(const DevLevel& L, const double* st, double* out, hipStrea
   template hipError_t patch_apply<T>(const DevLevel&, const DevOps<T>&, const T*, T*, int,      \
                                      hipStream_t);                                              \
   template hipError_t pack_sym<T>(const DevLevel&, const int64_t*, const T*, hipStream_t);      \
+  template hipError_t gr_dots<T>(const T*, int64_t, int, const T*, int64_t, double*, double*, hipStream_t); \
+  template hipError_t gr_orth_norm<T>(T*, const T*, int64_t, int, int64_t, const double*, double*, double*, \
+                                      hipStream_t);                                                       \
+  template hipError_t gr_scale<T>(T*, int64_t, const double*, hipStream_t);                              \
+  template hipError_t gr_update<T>(T*, const T*, int64_t, int, int64_t, const double*, int, hipStream_t); \
   template hipError_t gather_cheb<T>(const DevLevel&, const DevOps<T>&, const T*, T, T, int, int, int, T*, \
                                      T*, hipStream_t);                                                  \
   template hipError_t gather_update<T>(const DevLevel&, const DevOps<T>&, const T*, T*, T, int, \

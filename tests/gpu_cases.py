@@ -61,12 +61,15 @@ def wind_of(case):
 @functools.lru_cache(maxsize=None)
 def oracle_of(case, dtype=np.float64, smoother="sweep"):
     """Oracle hierarchy; smoother "chebyshev" is the paper's relaxation (unweighted
-    additive operator, interval [2, 8])."""
+    additive operator, interval [2, 8]); "gmres" two GMRES steps per relaxation with the
+    weighted additive operator."""
     dim, nc, nl, fam, r, dt, nu, ws = CASES[case]
     A, b, c = tableau(fam, r)
     if smoother == "chebyshev":
         return Hierarchy(levels_of(case), A, dt, nu, wind=wind_of(case), dtype=dtype, weighted=False,
                          smoother="chebyshev", interval=(2.0, 8.0))
+    if smoother == "gmres":
+        return Hierarchy(levels_of(case), A, dt, nu, wind=wind_of(case), dtype=dtype, smoother="gmres")
     return Hierarchy(levels_of(case), A, dt, nu, wind=wind_of(case), dtype=dtype)
 
 
@@ -84,7 +87,7 @@ def gpu_of(case, precision=0, patch_form=2, smoother=0):
         wind = wind_of(case)
         wn = wind(irkmg.irk_mesh_p2_nodes(lv[-1])) if wind is not None else None
         say(f"[setup] case={case} precision={precision} patch_form={patch_form} smoother={smoother}")
-        extra = dict(smoother=1, weighting=0, interval=(2.0, 8.0)) if smoother == 1 else {}
+        extra = {1: dict(smoother=1, weighting=0, interval=(2.0, 8.0)), 2: dict(smoother=2)}.get(smoother, {})
         _GPU[key] = irkmg.IrkMG(lv, A, b, c, dt, nu, wind_nodal=wn, precision=precision, patch_form=patch_form,
                                 **extra)
         say(f"[setup] done case={case} N={_GPU[key].irk_mg_ndofs()} form={_GPU[key].irk_mg_patch_form()}")
