@@ -490,6 +490,68 @@ def run_batch(count, log_every=8):
     print(json.dumps(line), flush=True)
 
 
+def run_relax(n):
+    """The three relaxations side by side (Sec. 4.2: Chebyshev or GMRES acceleration of
+    the additive Vanka operator; the damped sweep): FGMRES(30) to 1e-8 on the 2D Oseen
+    problem (n x n, Gauss(2), nu = 0.01, dt = 5e-3, unit-speed wind) and on the 2D Stokes
+    problem of the headline line, FP64; iterations, time per solve and per V-cycle."""
+    import numpy as np
+    import torch
+
+    from paper_2202_07381_amd import irkmg
+    from paper_2202_07381_amd import workloads as wl
+
+    relaxations = {"sweep": dict(smoother=0), "chebyshev": dict(smoother=1, weighting=0, interval=(2.0, 8.0)),
+                   "gmres": dict(smoother=2)}
+    problems = {
+        f"oseen{n}": ("gauss", 2, 5e-3, 0.01, True),
+        "stokes256": ("radauIIA", 3, 1e-2, 1.0, False),
+    }
+    out = {}
+    for pname, (fam, r, dt, nu, convective) in problems.items():
+        nn = n if convective else 256
+        levels = wl.square_hierarchy(4, int(round(np.log2(nn // 4))) + 1)
+        A, b, c = irkmg.irk_tableau_builtin(fam, r)
+        nodes = irkmg.irk_mesh_p2_nodes(levels[-1])
+        wind = wl.wind_2d(3, nn)(nodes) if convective else None
+        f = wl.forcing_2d(3)
+        for rname, kw in relaxations.items():
+            t0 = time.time()
+            g = irkmg.IrkMG(levels, A, b, c, dt, nu, wind_nodal=wind, **kw)
+            torch.cuda.synchronize()
+            setup = time.time() - t0
+            N = g.irk_mg_ndofs()
+            sz = g.irk_mg_sizes()
+            F = torch.zeros(N, dtype=torch.float64, device="cuda")
+            g.irk_rhs(torch.tensor(np.stack([f(nodes)] * r).ravel(), device="cuda"),
+                      torch.zeros(sz["ns"], dtype=torch.float64, device="cuda"), F)
+            k = torch.zeros_like(F)
+            g.irk_fgmres_solve(F, k, rtol=1e-8, maxit=300)  # warm-up
+            k.zero_()
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            info = g.irk_fgmres_solve(F, k, rtol=1e-8, maxit=300)
+            torch.cuda.synchronize()
+            solve_ms = 1e3 * (time.perf_counter() - t1)
+            z = torch.zeros_like(F)
+            torch.cuda.synchronize()
+            t2 = time.perf_counter()
+            for _ in range(5):
+                g.irk_mg_vcycle(F, z)
+            torch.cuda.synchronize()
+            vc_ms = 1e3 * (time.perf_counter() - t2) / 5
+            out.setdefault(pname, {})[rname] = {
+                "converged": bool(info["converged"]), "iterations": info["iterations"],
+                "rel_residual": info["rel_residual"], "solve_ms": solve_ms, "vcycle_ms": vc_ms, "setup_s": setup}
+            log(f"relax {pname} {rname}: its {info['iterations']} solve {solve_ms:.1f} ms vcycle {vc_ms:.2f} ms")
+            g.close()
+    return {"metric": "FGMRES iterations and time to 1e-8 by relaxation (damped sweep, Chebyshev, GMRES)",
+            "unit": "iterations / ms", "n_gpus": 1, "dtype": "f64", "data": "synthetic",
+            "config": {"workload": f"2D Oseen {n}x{n} Gauss(2) nu=0.01 dt=5e-3 unit wind; 2D Stokes 256x256 "
+                                   "RadauIIA(3) dt=1e-2; 2/2 relaxation steps, FGMRES(30) to 1e-8"},
+            "results": out}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -498,8 +560,10 @@ def main():
     ap.add_argument("--n", type=int, default=256, help="finest mesh size (power-of-two multiple of 4)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp32", action="store_true")
-    ap.add_argument("--workload", default="stokes256", choices=["stokes256", "batch64", "t1"],
-                    help="stokes256: the headline line; batch64: the uneven batched workload")
+    ap.add_argument("--workload", default="stokes256", choices=["stokes256", "batch64", "t1", "relax"],
+                    help="stokes256: the headline line; batch64: the uneven batched workload; t1: the paper's "
+                         "2D Stokes table; relax: the three relaxations side by side")
+    ap.add_argument("--relax-n", type=int, default=512, help="relax: finest mesh size of the Oseen problem")
     ap.add_argument("--batch-count", type=int, default=64)
     ap.add_argument("--t1-level", type=int, default=5, help="t1: refinement level l of the crossed 8x8 mesh")
     ap.add_argument("--t1-stages", type=int, default=2, choices=[2, 3], help="t1: RadauIIA stages")
@@ -528,6 +592,9 @@ def main():
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     if args.workload == "batch64":
         run_batch(args.batch_count)
+        return
+    if args.workload == "relax":
+        print(json.dumps(run_relax(args.relax_n)), flush=True)
         return
     if args.workload == "t1":
         print(json.dumps(run_t1(args.t1_level, args.t1_stages, 1 if args.t1_fp32 else 0, args.t1_max_steps,
