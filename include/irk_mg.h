@@ -105,7 +105,7 @@ typedef struct irk_mg_opts {
                            symmetric, and each block inverse is kept by its
                            n_s/2 + 1 wrapped diagonals, r n_s (n_s/2 + 1)
                            stored values; used on levels whose patches have at
-                           most 64 unknowns per stage (form 1 on the others
+                           most 256 unknowns per stage (form 1 on the others
                            under 2; IRK_EINVAL from setup under 3)              */
   int smoother;      /* relaxation: 0 = `pre`/`post` damped additive sweeps
                         k += omega W S r; 1 = `pre`/`post` steps of the Chebyshev

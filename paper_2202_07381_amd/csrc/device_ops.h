@@ -480,49 +480,86 @@ __device__ __forceinline__ void patch_apply_eig_one(
   eig_out<T>(lane, n, ns, so, xs, sb, Y, transpose, D);
 }
 
-// Symmetric factored patch inverse.  For a symmetric spatial operator (Stokes: K
-// symmetric and the divergence coupling B, B^T) every eigen-block I (x) M_v + dt T_k (x)
-// S_v is symmetric (real eigenvalue) or complex symmetric (pair), and so is its inverse,
-// which is therefore stored by its wrapped diagonals s = 0 .. n_s/2 (layout with
-// sym_block_values): about half the values of the factored form.  One wavefront per
-// patch, lane i owns row i of every block (n_s <= 64); each stored entry is read once
-// from memory and used for both Z(i, i+s) and Z(i+s, i).  Transposed apply: real blocks
-// are unchanged, a pair's conjugate transpose is its conjugate.  Gather and eigenbasis
-// transforms as in the factored form.
-// Work of one stored word (16 bytes of lane i's row) of a symmetric block, whose
-// diagonals s0, s0-1, ..., s0-G+1 (descending) it holds.  Forward entries
-// Z(i, i+s) x_{i+s}, x read from the doubled copy xu (xu[i + s] = x_{(i+s) mod n_s}).
-// Transposed entries Z(i-s, i) x_{i-s}, 1 <= s <= nb, by a Horner scheme over the
-// descending diagonals: t <- rot(t) + Z(i, i+s) x_i with rot taking lane i-1's value
-// (lane n_s-1's for lane 0), so that after the diagonal s = 0 lane i holds
-// sum_s Z(i-s, i) x_{i-s}.  Real blocks use (ar, tr); pairs (ar, ai, tr, ti) with
-// x = (xu, xv) and cs = -1 for the conjugate.
-template <typename T>
-__device__ __forceinline__ void sym_word(const T* a, int type, int s0, int i, int nb, int src, const T* xu,
-                                         const T* xv, T xir, T xii, T cs, T& ar, T& ai, T& tr, T& ti) {
+// Value of lane l (uniform l) of v, for every lane.
+__device__ __forceinline__ double lane_value(double v, int l) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_readlane((int)b, l);
+  const int hi = __builtin_amdgcn_readlane((int)(b >> 32), l);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+__device__ __forceinline__ float lane_value(float v, int l) {
+  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), l));
+}
+
+// rot over the ring of the block's n_s rows, row i taking row i-1's value (row 0 takes
+// row n_s-1's).  Rows are held RS per lane, row q at slot q / 64 of lane q % 64.  One
+// slot: one cross-lane read from the fixed source lane src.  More slots: each slot
+// shifts by one lane (lane 0 reading lane 63 of the same slot), then lane 0 of slot k
+// takes the previous slot's lane 63 (uniform reads of the values before the shift),
+// and lane 0 of slot 0 row n_s-1 (slot kl, lane ll).
+template <typename T, int RS>
+__device__ __forceinline__ void sym_rot(T* t, int lane, int src, int kl, int ll) {
+  if constexpr (RS == 1) {
+    t[0] = __shfl(t[0], src, 64);
+  } else {
+    T edge[RS];
+#pragma unroll
+    for (int k = 0; k < RS; ++k) edge[k] = k == 0 ? T(0) : lane_value(t[k - 1], 63);
+    T last = T(0);
+#pragma unroll
+    for (int k = 0; k < RS; ++k)
+      if (k == kl) last = lane_value(t[k], ll);
+#pragma unroll
+    for (int k = 0; k < RS; ++k) {
+      const T r = __shfl(t[k], src, 64);
+      t[k] = lane == 0 ? (k == 0 ? last : edge[k]) : r;
+    }
+  }
+}
+
+// Work of one stored word (16 bytes per row) of a symmetric block for the rows iv[k] of
+// this lane, the word holding the diagonals s0, s0-1, ..., s0-G+1 (descending).  Forward
+// entries Z(i, i+s) x_{i+s}, x read from the doubled copy xu (xu[i + s] =
+// x_{(i+s) mod n_s}).  Transposed entries Z(i-s, i) x_{i-s}, 1 <= s <= nb, by a Horner
+// scheme over the descending diagonals: t <- rot(t) + Z(i, i+s) x_i (sym_rot), so that
+// after the diagonal s = 0 row i holds sum_s Z(i-s, i) x_{i-s}.  Real blocks use
+// (ar, tr); pairs (ar, ai, tr, ti) with x = (xu, xv) and cs = -1 for the conjugate.
+template <typename T, int RS>
+__device__ __forceinline__ void sym_word(const T (*a)[Vec16<T>::n], int type, int s0, const int* iv, int nb,
+                                         int lane, int src, int kl, int ll, const T* xu, const T* xv,
+                                         const T* xir, const T* xii, T cs, T* ar, T* ai, T* tr, T* ti) {
   constexpr int VEC = Vec16<T>::n;
   if (type == 1) {
 #pragma unroll
-    for (int k = 0; k < VEC; ++k) {
-      const int sd = s0 - k;
-      ar += a[k] * xu[i + sd];
-      tr = __shfl(tr, src, 64);
-      if (sd >= 1 && sd <= nb) tr += a[k] * xir;  // wave-uniform test
+    for (int q = 0; q < VEC; ++q) {
+      const int sd = s0 - q;
+#pragma unroll
+      for (int k = 0; k < RS; ++k) ar[k] += a[k][q] * xu[iv[k] + sd];
+      sym_rot<T, RS>(tr, lane, src, kl, ll);
+      if (sd >= 1 && sd <= nb)  // wave-uniform test
+#pragma unroll
+        for (int k = 0; k < RS; ++k) tr[k] += a[k][q] * xir[k];
     }
   } else {
 #pragma unroll
-    for (int k = 0; k < VEC / 2; ++k) {
-      const int sd = s0 - k;
-      const T dr = a[2 * k], di = cs * a[2 * k + 1];
-      const T zr = xu[i + sd], zi = xv[i + sd];
-      ar += dr * zr - di * zi;
-      ai += dr * zi + di * zr;
-      tr = __shfl(tr, src, 64);
-      ti = __shfl(ti, src, 64);
-      if (sd >= 1 && sd <= nb) {  // wave-uniform test
-        tr += dr * xir - di * xii;
-        ti += dr * xii + di * xir;
+    for (int q = 0; q < VEC / 2; ++q) {
+      const int sd = s0 - q;
+#pragma unroll
+      for (int k = 0; k < RS; ++k) {
+        const T dr = a[k][2 * q], di = cs * a[k][2 * q + 1];
+        const T zr = xu[iv[k] + sd], zi = xv[iv[k] + sd];
+        ar[k] += dr * zr - di * zi;
+        ai[k] += dr * zi + di * zr;
       }
+      sym_rot<T, RS>(tr, lane, src, kl, ll);
+      sym_rot<T, RS>(ti, lane, src, kl, ll);
+      if (sd >= 1 && sd <= nb)  // wave-uniform test
+#pragma unroll
+        for (int k = 0; k < RS; ++k) {
+          const T dr = a[k][2 * q], di = cs * a[k][2 * q + 1];
+          tr[k] += dr * xir[k] - di * xii[k];
+          ti[k] += dr * xii[k] + di * xir[k];
+        }
     }
   }
 }
@@ -532,15 +569,16 @@ __device__ __forceinline__ void sym_word(const T* a, int type, int s0, int i, in
 // S_v is symmetric (real eigenvalue) or complex symmetric (pair), and so is its inverse,
 // which is therefore stored by its wrapped diagonals s = 0 .. n_s/2 (layout with
 // sym_block_values): about half the values of the factored form.  One wavefront per
-// patch, lane i owns row i of every block (n_s <= 64); each stored entry is read once
-// from memory and used for both Z(i, i+s) and Z(i+s, i).  Transposed apply: real blocks
-// are unchanged, a pair's conjugate transpose is its conjugate.  Gather and eigenbasis
-// transforms as in the factored form (xt doubled, 2n values).
+// patch; the lane owns rows lane + 64 k, k < RS, of every block (n_s <= 64 RS); each
+// stored entry is read once from memory and used for both Z(i, i+s) and Z(i+s, i).
+// Transposed apply: real blocks are unchanged, a pair's conjugate transpose is its
+// conjugate.  Gather and eigenbasis transforms as in the factored form (xt doubled, 2n
+// values).
 //
 // The blocks of a patch follow each other, so its words form one sequence, word w of
 // row i at ((w n_s) + i) vec, read U words at a time; with PF the next U words are in
 // flight while the current ones are used (the first U before the gather).
-template <typename T, int U = 4, int NT = 1, int PF = 0>
+template <typename T, int U = 4, int NT = 1, int PF = 0, int RS = 1>
 __device__ __forceinline__ void patch_apply_sym_one(
     int p, int lane, T* xs, T* xt, const irk::StageBasis<T>& sb, const int32_t* __restrict__ p_nloc,
     const int64_t* __restrict__ p_inv_off, const int64_t* __restrict__ p_slot_off,
@@ -550,18 +588,24 @@ __device__ __forceinline__ void patch_apply_sym_one(
   const int n = p_nloc[p];
   const int ns = n / sb.r;
   const int64_t so = p_slot_off[p];
-  // lanes past n_s repeat lane 0's loads and arithmetic; no lane reads their results
-  const int i = lane < ns ? lane : 0;
-  const int src = i == 0 ? ns - 1 : i - 1;  // rot: lane i takes lane i-1 (mod n_s)
-  const T* __restrict__ Dp = inv + p_inv_off[p] + (int64_t)i * VEC;
+  // rows past n_s repeat row 0's loads and arithmetic; no row reads their results
+  int iv[RS];
+#pragma unroll
+  for (int k = 0; k < RS; ++k) iv[k] = lane + 64 * k < ns ? lane + 64 * k : 0;
+  // rot: one slot reads lane i-1 (lane n_s-1 for lane 0); more slots shift by one lane
+  const int src = RS == 1 ? (iv[0] == 0 ? ns - 1 : iv[0] - 1) : ((lane + 63) & 63);
+  const int kl = (ns - 1) / 64, ll = (ns - 1) % 64;  // slot and lane of row n_s-1
+  const T* __restrict__ Dp = inv + p_inv_off[p];
   const int64_t step = (int64_t)ns * VEC;
   int NG = 0;
   for (int b = 0; b < sb.nblk; ++b) NG += irk::sym_words(sb.type[b], ns, VEC);
-  T a[U][VEC];
+  T a[U][RS][VEC];
   if constexpr (PF) {
 #pragma unroll
     for (int u = 0; u < U; ++u)
-      if (u < NG) vload_s<T, NT>(Dp + u * step, a[u]);
+      if (u < NG)
+#pragma unroll
+        for (int k = 0; k < RS; ++k) vload_s<T, NT>(Dp + u * step + (int64_t)iv[k] * VEC, a[u][k]);
   }
   eig_in<T, true>(lane, n, ns, so, xs, xt, sb, gidx, res, W, transpose);
   const int nb = ns - irk::sym_diags(ns);  // diagonals also used transposed: 1 .. nb
@@ -572,28 +616,39 @@ __device__ __forceinline__ void patch_apply_sym_one(
   int top = ng * G - 1;
   const T* xu = xt + sb.st0[0] * 2 * ns;
   const T* xv = xu + 2 * ns;
-  T xir = xu[i], xii = type == 2 ? xv[i] : T(0);
-  T ar = T(0), ai = T(0), tr = T(0), ti = T(0);
+  T xir[RS], xii[RS], ar[RS], ai[RS], tr[RS], ti[RS];
+#pragma unroll
+  for (int k = 0; k < RS; ++k) {
+    xir[k] = xu[iv[k]];
+    xii[k] = type == 2 ? xv[iv[k]] : T(0);
+    ar[k] = ai[k] = tr[k] = ti[k] = T(0);
+  }
   for (int w0 = 0; w0 < NG; w0 += U) {
-    T nx[U][VEC];
+    T nx[U][RS][VEC];
     if constexpr (PF) {
 #pragma unroll
       for (int u = 0; u < U; ++u)
-        if (w0 + U + u < NG) vload_s<T, NT>(Dp + (w0 + U + u) * step, nx[u]);
+        if (w0 + U + u < NG)
+#pragma unroll
+          for (int k = 0; k < RS; ++k) vload_s<T, NT>(Dp + (w0 + U + u) * step + (int64_t)iv[k] * VEC, nx[u][k]);
     } else {
 #pragma unroll
       for (int u = 0; u < U; ++u)
-        if (w0 + u < NG) vload_s<T, NT>(Dp + (w0 + u) * step, a[u]);
+        if (w0 + u < NG)
+#pragma unroll
+          for (int k = 0; k < RS; ++k) vload_s<T, NT>(Dp + (w0 + u) * step + (int64_t)iv[k] * VEC, a[u][k]);
     }
 #pragma unroll
     for (int u = 0; u < U; ++u) {
       if (w0 + u >= NG) break;
-      sym_word<T>(a[u], type, top - wb * G, i, nb, src, xu, xv, xir, xii, cs, ar, ai, tr, ti);
+      sym_word<T, RS>(a[u], type, top - wb * G, iv, nb, lane, src, kl, ll, xu, xv, xir, xii, cs, ar, ai, tr, ti);
       if (++wb == ng) {  // block done: store its rows, move to the next block
-        if (lane < ns) {
-          xs[sb.st0[b] * ns + i] = ar + tr;
-          if (type == 2) xs[(sb.st0[b] + 1) * ns + i] = ai + ti;
-        }
+#pragma unroll
+        for (int k = 0; k < RS; ++k)
+          if (lane + 64 * k < ns) {
+            xs[sb.st0[b] * ns + iv[k]] = ar[k] + tr[k];
+            if (type == 2) xs[(sb.st0[b] + 1) * ns + iv[k]] = ai[k] + ti[k];
+          }
         if (++b < sb.nblk) {
           type = sb.type[b];
           ng = irk::sym_words(type, ns, VEC);
@@ -602,9 +657,12 @@ __device__ __forceinline__ void patch_apply_sym_one(
           top = ng * G - 1;
           xu = xt + sb.st0[b] * 2 * ns;
           xv = xu + 2 * ns;
-          xir = xu[i];
-          xii = type == 2 ? xv[i] : T(0);
-          ar = ai = tr = ti = T(0);
+#pragma unroll
+          for (int k = 0; k < RS; ++k) {
+            xir[k] = xu[iv[k]];
+            xii[k] = type == 2 ? xv[iv[k]] : T(0);
+            ar[k] = ai[k] = tr[k] = ti[k] = T(0);
+          }
         }
       }
     }
@@ -612,7 +670,9 @@ __device__ __forceinline__ void patch_apply_sym_one(
 #pragma unroll
       for (int u = 0; u < U; ++u)
 #pragma unroll
-        for (int v = 0; v < VEC; ++v) a[u][v] = nx[u][v];
+        for (int k = 0; k < RS; ++k)
+#pragma unroll
+          for (int v = 0; v < VEC; ++v) a[u][k][v] = nx[u][k][v];
     }
   }
   eig_out<T>(lane, n, ns, so, xs, sb, Y, transpose, D);

@@ -906,9 +906,9 @@ static irk_status setup_impl(const irk_mesh_level* lv, int nlevels, const irk_ta
       if (D.pform == 3) {
         int maxns = 0;
         for (int64_t p = 0; p < np; ++p) maxns = std::max(maxns, dim * (H.pn_ptr[p + 1] - H.pn_ptr[p]) + 1);
-        if (maxns > 64) {
+        if (maxns > 256) {
           if (h->patch_form_req == 3)
-            return fail(IRK_EINVAL, "the symmetric patch form needs patches of at most 64 unknowns per stage");
+            return fail(IRK_EINVAL, "the symmetric patch form needs patches of at most 256 unknowns per stage");
           D.pform = 1;
         }
       }

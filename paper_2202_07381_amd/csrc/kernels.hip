@@ -771,7 +771,7 @@ __global__ __launch_bounds__(WAVES * 64) __attribute__((amdgpu_waves_per_eu(WPE)
                                               p_slot_off, gidx, inv, res, W, Y, transpose, D);
 }
 
-template <typename T, int NMAX, int UNROLL, int PF, int WAVES, int NT = 1>
+template <typename T, int NMAX, int UNROLL, int PF, int WAVES, int NT = 1, int RS = 1>
 __global__ __launch_bounds__(WAVES * 64) void k_patch_apply_sym(
     int64_t npatch, irk::StageBasis<T> sb, const int32_t* __restrict__ sched,
     const int32_t* __restrict__ p_nloc, const int64_t* __restrict__ p_inv_off,
@@ -783,7 +783,7 @@ __global__ __launch_bounds__(WAVES * 64) void k_patch_apply_sym(
   const int wave = threadIdx.x >> 6;
   const int64_t idx = (int64_t)blockIdx.x * WAVES + wave;
   if (idx >= npatch) return;  // whole wavefront exits; no workgroup barrier below
-  dev::patch_apply_sym_one<T, UNROLL, NT, PF>(sched[idx], lane, xs[wave], xt[wave], sb, p_nloc, p_inv_off,
+  dev::patch_apply_sym_one<T, UNROLL, NT, PF, RS>(sched[idx], lane, xs[wave], xt[wave], sb, p_nloc, p_inv_off,
                                              p_slot_off, gidx, inv, res, W, Y, transpose, D);
 }
 
@@ -1662,22 +1662,31 @@ hipError_t patch_apply(const DevLevel& L, const DevOps<T>& ops, const T* res, T*
   const int rows_per_block = 64 * VEC;
   if (L.pform == 3) {
     const StageBasis<T>& sb = basis_of<T>(L);
-    if (L.max_nloc > 256 || L.max_nloc / L.r > 64) return hipErrorInvalidValue;
-#define IRK_PAS(NM, U, PF, WV, ...)                                                                      \
-  k_patch_apply_sym<T, NM, U, PF, WV, ##__VA_ARGS__><<<dim3(blocks_for(L.npatch, WV)), dim3(WV * 64), 0, s>>>(       \
+    const int max_ns = L.max_nloc / L.r;
+    if (L.max_nloc > 1024 || max_ns > 256) return hipErrorInvalidValue;
+#define IRK_PAS(NM, U, PF, WV, NT, RS)                                                                   \
+  k_patch_apply_sym<T, NM, U, PF, WV, NT, RS><<<dim3(blocks_for(L.npatch, WV)), dim3(WV * 64), 0, s>>>( \
       L.npatch, sb, L.sched, L.p_nloc, L.p_inv_off, L.p_slot_off, L.p_gidx, inv, res, W, Y, transpose, \
       L.dim)
-    // one wavefront per workgroup, two 16-byte words per lane in flight: measured best
-    // on both the bandwidth-bound fine levels and the latency-bound coarse ones
-    // one wavefront per workgroup, two 16-byte words per lane in flight; non-temporal
+    // one wavefront per workgroup, two 16-byte words per row in flight; non-temporal
     // loads where the factors stream from memory once per application, ordinary loads
-    // on the small levels, whose factors the last-level cache keeps between applications
-    const bool small = L.npatch <= kSmallPatches;
-    if (L.max_nloc <= 128) {
-      if (small) IRK_PAS(128, 2, 0, 1, 0);
-      else IRK_PAS(128, 2, 0, 1, 1);
-    } else if (small) IRK_PAS(256, 2, 0, 1, 0);
-    else IRK_PAS(256, 2, 0, 1, 1);
+    // on the small levels, whose factors the last-level cache keeps between
+    // applications; one row per lane up to 64 rows per block, else four (3D patches)
+    const int nt = L.npatch <= kSmallPatches ? 0 : 1;
+    if (max_ns <= 64) {
+      if (L.max_nloc <= 128) {
+        if (nt) IRK_PAS(128, 2, 0, 1, 1, 1);
+        else IRK_PAS(128, 2, 0, 1, 0, 1);
+      } else if (nt) IRK_PAS(256, 2, 0, 1, 1, 1);
+      else IRK_PAS(256, 2, 0, 1, 0, 1);
+    } else if (L.max_nloc <= 256) {
+      if (nt) IRK_PAS(256, 2, 0, 1, 1, 4);
+      else IRK_PAS(256, 2, 0, 1, 0, 4);
+    } else if (L.max_nloc <= 512) {
+      if (nt) IRK_PAS(512, 2, 0, 1, 1, 4);
+      else IRK_PAS(512, 2, 0, 1, 0, 4);
+    } else if (nt) IRK_PAS(1024, 2, 0, 1, 1, 4);
+    else IRK_PAS(1024, 2, 0, 1, 0, 4);
 #undef IRK_PAS
     return hipGetLastError();
   }
