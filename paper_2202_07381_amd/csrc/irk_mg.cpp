@@ -901,6 +901,8 @@ static irk_status setup_impl(const irk_mesh_level* lv, int nlevels, const irk_ta
       std::vector<int64_t> inv_off(np), slot_off(np);
       std::vector<int64_t> sym_off(np);
       int64_t io = 0, so = 0, sio = 0;
+      // 128-byte lines: patch outputs written and symmetric factors read line by line
+      const int64_t kLine = 128 / (h->precision == 0 ? 8 : 4);
       int maxn = 0, maxld = 0;
       D.pform = h->patch_form;
       if (D.pform == 3) {
@@ -928,11 +930,12 @@ static irk_status setup_impl(const irk_mesh_level* lv, int nlevels, const irk_ta
           io += (int64_t)lc * ns;
           sym_off[p] = sio;
           for (int b = 0; b < h->eig.nblk; ++b) sio += irk::sym_block_values(h->eig.type[b], ns, VEC);
+          sio = (sio + kLine - 1) / kLine * kLine;  // next patch on a whole cache line
         } else {
           ld[p] = (n + VEC - 1) / VEC * VEC;
           io += (int64_t)ld[p] * n;
         }
-        so += n;
+        so = (so + n + kLine - 1) / kLine * kLine;  // each patch's slots on whole cache lines
         maxn = std::max(maxn, n);
         maxld = std::max(maxld, ld[p]);
         for (int st = 0; st < r; ++st) {
@@ -941,6 +944,7 @@ static irk_status setup_impl(const irk_mesh_level* lv, int nlevels, const irk_ta
               gidx.push_back((int32_t)(((int64_t)H.pn_node[H.pn_ptr[p] + a] * dim + c) * r + st));
           gidx.push_back((int32_t)(D.offV + p * r + st));
         }
+        gidx.resize(so, -1);  // gidx is indexed by slot: padding entries, never read
       }
       D.inv_elems = D.pform == 3 ? sio : io;
       D.full_elems = io;
@@ -973,7 +977,8 @@ static irk_status setup_impl(const irk_mesh_level* lv, int nlevels, const irk_ta
         }
       }
       if (so > INT32_MAX || D.N > INT32_MAX) return fail(IRK_EINVAL, "problem too large for 32-bit patch indices");
-      for (int32_t g : gidx) gptr[g + 1]++;
+      for (int32_t g : gidx)
+        if (g >= 0) gptr[g + 1]++;
       for (int64_t g = 0; g < D.N; ++g) gptr[g + 1] += gptr[g];
       gslot.resize(so);
       std::vector<int32_t> fillp(gptr.begin(), gptr.end() - 1);
