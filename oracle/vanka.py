@@ -40,10 +40,17 @@ cycle with the j+1 steps taken; beta = 0 leaves k unchanged.  The result depends
 nonlinearly on F, so the V-cycle is a nonlinear preconditioner and the outer
 iteration must be flexible (Sec. 4.1).  The transposed relaxation uses J^T and S^T.
 
+Spectrum estimate for the Chebyshev interval (Sec. 5.1 takes [lambda_max/4, lambda_max],
+lambda_max the largest eigenvalue of S J): m Arnoldi steps on M = S J from a given
+start vector, classical Gram--Schmidt as in the GMRES relaxation, and the Ritz values,
+the eigenvalues of the leading m x m block of the Hessenberg matrix.
+
 Pinned by tests/test_oracle_vanka.py against: Fig. 1's patch (19 velocity nodes and
 one pressure node for an interior vertex); the DOF cover; single-patch exactness
 (R_v^T A_v^{-1} R_v J e = e for e supported on S_v); multiplicity bounds; the
-Chebyshev error polynomial in closed form on a diagonal operator; the GMRES relaxation
+Chebyshev error polynomial in closed form on a diagonal operator; the Ritz values
+against the eigenvalues of V^T M V for an orthonormal basis V of the Krylov space built
+from its power basis, and against the exact spectrum when m reaches the dimension; the GMRES relaxation
 against the minimal-residual step in closed form (m = 1), against a least-squares
 solve over the power basis of the Krylov space (m = 3), and against the exact solution
 when m reaches the dimension.
@@ -192,3 +199,26 @@ def gmres_relaxation(apply_J, apply_S, F, k, steps: int, dtype=np.float64):
     for j in range(m):
         k = k + dtype(y[j]) * V[j]
     return k
+
+
+def arnoldi_ritz(apply_J, apply_S, v0, steps: int):
+    """Hessenberg matrix H ((steps+1) x steps) of `steps` Arnoldi steps on M = S J from v0
+    (classical Gram--Schmidt) and the Ritz values, eigenvalues of H[:steps, :steps] sorted
+    by decreasing real part (module docstring).  Stops early at an invariant subspace."""
+    v = np.asarray(v0, dtype=np.float64)
+    V = [v / np.linalg.norm(v)]
+    H = np.zeros((steps + 1, steps))
+    m = steps
+    for j in range(steps):
+        w = apply_S(apply_J(V[j]))
+        h = np.array([V[i] @ w for i in range(j + 1)])
+        for i in range(j + 1):
+            w = w - h[i] * V[i]
+        H[:j + 1, j] = h
+        H[j + 1, j] = np.linalg.norm(w)
+        if H[j + 1, j] == 0.0:
+            m = j + 1
+            break
+        V.append(w / H[j + 1, j])
+    ritz = np.linalg.eigvals(H[:m, :m])
+    return H[:m + 1, :m], ritz[np.argsort(-ritz.real, kind="stable")]

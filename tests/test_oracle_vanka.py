@@ -167,3 +167,50 @@ def test_gmres_relaxation_full_dimension_is_exact():
     got = gmres_relaxation(lambda x: J @ x, lambda r: Jinv @ r, F, k0, 3)
     assert np.allclose(got, np.linalg.solve(J, F), rtol=1e-12, atol=1e-12)
     assert np.array_equal(gmres_relaxation(lambda x: J @ x, lambda r: Sm @ r, J @ k0, k0, 3), k0)
+
+
+# ------------------------------------------------- spectrum estimate (Chebyshev interval)
+def test_ritz_values_match_projected_operator():
+    """Ritz values from m Arnoldi steps on M = S J equal the eigenvalues of Q^T M Q for an
+    orthonormal basis Q of span{v0, M v0, ..., M^{m-1} v0} (QR of the power basis, an
+    independent construction); with m = dimension they are M's eigenvalues."""
+    from oracle.vanka import arnoldi_ritz
+
+    S, sm, _, v0 = _vanka_case()
+    J = S.J
+    M = lambda x: sm.apply_S(J @ x)
+    m = 6
+    K = [v0 / np.linalg.norm(v0)]
+    for _ in range(m - 1):
+        w = M(K[-1])
+        K.append(w / np.linalg.norm(w))
+    Q, _ = np.linalg.qr(np.stack(K, axis=1))
+    proj = np.linalg.eigvals(Q.T @ np.stack([M(Q[:, i]) for i in range(m)], axis=1))
+    H, ritz = arnoldi_ritz(lambda x: J @ x, sm.apply_S, v0, m)
+    assert H.shape == (m + 1, m)
+    proj = proj[np.argsort(-proj.real, kind="stable")]
+    assert np.allclose(ritz, proj, rtol=1e-8, atol=1e-8)
+    rng = np.random.default_rng(44)
+    n = 8
+    A = rng.standard_normal((n, n))
+    _, ritz = arnoldi_ritz(lambda x: A @ x, lambda r: r, rng.standard_normal(n), n)
+    ev = np.linalg.eigvals(A)
+    assert np.allclose(np.sort_complex(ritz), np.sort_complex(ev), atol=1e-9)
+
+
+def test_ritz_estimate_of_the_chebyshev_interval():
+    """On the 8x8 Stokes mesh (the setting of Sec. 5.1's [2, 8]) 20 Arnoldi steps put the
+    largest Ritz value of S J within 2% of the largest real eigenvalue part of the dense
+    S J, which lies in (7, 8)."""
+    from oracle.multigrid import Hierarchy
+    from oracle.vanka import arnoldi_ritz
+
+    A, b, c = tableau("radauIIA", 2)
+    H = Hierarchy(wl.square_hierarchy(4, 2), A, 1.0 / 32, 1.0, weighted=False, smoother="chebyshev")
+    J = H.systems[1].J
+    sm = H.smoothers[1]
+    dense = np.linalg.eigvals(np.column_stack([sm.apply_S(J.toarray()[:, i]) for i in range(J.shape[0])]))
+    _, ritz = arnoldi_ritz(lambda x: J @ x, sm.apply_S, np.random.default_rng(45).standard_normal(J.shape[0]), 20)
+    lam = dense.real.max()
+    assert 7.0 < lam < 8.0
+    assert abs(ritz[0].real - lam) < 0.02 * lam
