@@ -167,6 +167,28 @@ irk_status irk_mg_setup(const irk_mesh_level* levels, int nlevels, const irk_tab
  * irk_mg_opts), or -1 for NULL. */
 int irk_mg_patch_form(const irk_mg* h);
 
+/* Estimate of the spectrum of the relaxation's preconditioned operator W S J_l on level
+ * l >= 1 (S the additive Vanka operator, W the handle's weighting), from which Sec. 5.1's
+ * rule takes the Chebyshev interval [lambda_max / 4, lambda_max]: `steps` (1..64)
+ * Arnoldi steps with classical Gram--Schmidt from v0 (device, ABI layout of level l,
+ * not modified), then the Ritz values, eigenvalues of the leading Hessenberg block, in
+ * ritz_re / ritz_im (host, `steps` values each, decreasing real part, zero past
+ * *nritz).  H (host, (steps + 1) x steps column-major, may be NULL) receives the
+ * Hessenberg matrix.  An invariant Krylov space ends the estimate early (*nritz <
+ * steps; nritz may be NULL).  Allocates its Arnoldi basis for the call; synchronises
+ * `stream`.  IRK_ENOCONV if the small eigenvalue iteration fails. */
+irk_status irk_mg_ritz(irk_mg* h, int level, int steps, const double* v0, double* H, double* ritz_re,
+                       double* ritz_im, int* nritz, void* stream);
+
+/* Change the Chebyshev interval of a handle (smoother 1) after setup, for example to
+ * [lambda/4, lambda] from irk_mg_ritz.  IRK_EINVAL unless 0 < lo < hi < inf. */
+irk_status irk_mg_set_interval(irk_mg* h, double lo, double hi);
+
+/* Eigenvalues of the leading m x m block (1 <= m <= 1024) of an upper Hessenberg matrix
+ * H (host, column-major, leading dimension ldh >= m) by the shifted QR iteration,
+ * sorted by decreasing real part into wr / wi (host, m values).  Host-only. */
+irk_status irk_hessenberg_eigs(int m, const double* H, int ldh, double* wr, double* wi);
+
 /* Real block diagonalisation of a Butcher matrix, A = W T W^{-1}, as used by the
  * factored patch form: T is block diagonal with 1x1 blocks (real eigenvalues,
  * ascending) followed by 2x2 blocks [[a, b], [-b, a]] (pairs a +- ib, b > 0, ascending

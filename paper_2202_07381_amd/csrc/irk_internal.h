@@ -117,6 +117,11 @@ struct StageEig {
 // Returns false (with the reason in *why) when A has no well-conditioned real block
 // diagonalisation (repeated or defective eigenvalues, cond(W) > 1e6).
 bool stage_eigenbasis(const double* A, int r, StageEig& out, std::string* why);
+// Eigenvalues of the leading m x m block of an upper Hessenberg matrix (column-major,
+// leading dimension ldh) by the shifted QR iteration in complex arithmetic (Givens
+// rotations, Wilkinson shifts, deflation at negligible subdiagonal entries), sorted by
+// decreasing real part.  False if the iteration does not converge.
+bool hessenberg_eigs(int m, const double* H, int ldh, double* wr, double* wi);
 
 // Stored values per column of one eigen-block of a factored patch inverse: a real block
 // keeps its n_s entries, a pair keeps n_s complex entries (re, im interleaved); both

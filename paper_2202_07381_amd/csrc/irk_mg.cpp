@@ -477,6 +477,52 @@ irk_status level_sweep_T(irk_mg* h, int level, int transpose, const double* F, d
   return IRK_OK;
 }
 
+// Arnoldi on the relaxation's preconditioned operator W S J_l of level l (classical
+// Gram--Schmidt, the GMRES relaxation's kernels), Hessenberg copied to the host.
+template <typename T>
+irk_status ritz_T(irk_mg* h, int level, int steps, const double* v0, std::vector<double>& H, hipStream_t s) {
+  DevLevel& L = h->dev[level];
+  DevOps<T>& o = ops_of<T>(L);
+  const int64_t N = L.N;
+  const int ld = steps + 1;
+  T* V = nullptr;
+  double *dH = nullptr, *part = nullptr;
+  auto release = [&]() {
+    hipStreamSynchronize(s);
+    if (V) hipFree(V);
+    if (dH) hipFree(dH);
+    if (part) hipFree(part);
+  };
+  if (hipMalloc(&V, (size_t)(steps + 1) * N * sizeof(T)) != hipSuccess ||
+      hipMalloc(&dH, (size_t)ld * (steps + 1) * sizeof(double)) != hipSuccess ||
+      hipMalloc(&part, (size_t)k::kGrBlocks * (kMaxGr + 1) * sizeof(double)) != hipSuccess) {
+    release();
+    return fail(IRK_ENOMEM, "device allocation of the Arnoldi basis failed");
+  }
+  hipError_t e = hipMemsetAsync(dH, 0, (size_t)ld * (steps + 1) * sizeof(double), s);
+  double* nrm0 = dH + (size_t)ld * steps;  // spare column: the start vector's norm
+  if (e == hipSuccess) e = k::to_internal<T>(L, v0, V, s);
+  if (e == hipSuccess) e = k::gr_orth_norm<T>(V, V, N, -1, N, dH, part, nrm0, s);
+  if (e == hipSuccess) e = k::gr_scale<T>(V, N, nrm0, s);
+  for (int j = 0; j < steps && e == hipSuccess; ++j) {
+    T* Vj = V + (int64_t)j * N;
+    T* Vn = V + (int64_t)(j + 1) * N;
+    double* hcol = dH + (size_t)j * ld;
+    e = k::residual<T>(L, o, h->A, h->dt, nullptr, Vj, (T*)L.res, s);
+    if (e == hipSuccess) e = k::patch_apply<T>(L, o, (const T*)L.res, (T*)L.Y, 0, s);
+    if (e == hipSuccess) e = k::gather_update<T>(L, o, (const T*)L.Y, Vn, (T)1, 0, s);
+    for (int c0 = 0; c0 <= j && e == hipSuccess; c0 += kMaxGr + 1)
+      e = k::gr_dots<T>(V + (int64_t)c0 * N, N, std::min(kMaxGr + 1, j + 1 - c0), Vn, N, part, hcol + c0, s);
+    if (e == hipSuccess) e = k::gr_orth_norm<T>(Vn, V, N, j, N, hcol, part, hcol + j + 1, s);
+    if (e == hipSuccess) e = k::gr_scale<T>(Vn, N, hcol + j + 1, s);
+  }
+  H.assign((size_t)ld * steps, 0.0);
+  if (e == hipSuccess) e = hipMemcpyAsync(H.data(), dH, H.size() * sizeof(double), hipMemcpyDeviceToHost, s);
+  release();
+  if (e != hipSuccess) return fail(IRK_EHIP, std::string("Arnoldi estimate: ") + hipGetErrorString(e));
+  return IRK_OK;
+}
+
 }  // namespace
 
 int irk::ensure_krylov_ws(irk_mg* h, int restart) { return ensure_krylov(h, restart); }
@@ -1212,6 +1258,45 @@ irk_status irk_rhs_dirichlet(irk_mg* h, const double* g_n, const double* g_stage
   if (!h->A_invertible) return fail(IRK_EINVAL, "boundary stage derivatives need an invertible A");
   const DevLevel& L = h->dev[h->nlevels - 1];
   HIPCHK(k::rhs_dirichlet(L, h->Ainv_dt, g_n, g_stages, F, S(stream)));
+  return IRK_OK;
+}
+
+irk_status irk_hessenberg_eigs(int m, const double* H, int ldh, double* wr, double* wi) {
+  if (m < 1 || m > 1024 || ldh < m || !H || !wr || !wi) return fail(IRK_EINVAL, "need 1 <= m <= 1024, ldh >= m");
+  if (!irk::hessenberg_eigs(m, H, ldh, wr, wi)) return fail(IRK_ENOCONV, "Hessenberg QR iteration did not converge");
+  return IRK_OK;
+}
+
+irk_status irk_mg_ritz(irk_mg* h, int level, int steps, const double* v0, double* H, double* ritz_re,
+                       double* ritz_im, int* nritz, void* stream) {
+  CHK(check_level(h, level));
+  if (level < 1) return fail(IRK_EINVAL, "the coarsest level has no relaxation");
+  if (steps < 1 || steps > 64) return fail(IRK_EINVAL, "steps must be in 1..64");
+  if (!v0 || !ritz_re || !ritz_im) return fail(IRK_EINVAL, "null argument");
+  std::vector<double> Hh;
+  hipStream_t s = S(stream);
+  if (h->precision == 0) CHK(ritz_T<double>(h, level, steps, v0, Hh, s));
+  else CHK(ritz_T<float>(h, level, steps, v0, Hh, s));
+  const int ld = steps + 1;
+  int m = steps;  // an invariant Krylov space ends the estimate early
+  for (int j = 0; j < steps; ++j)
+    if (!(Hh[(size_t)j * ld + j + 1] != 0.0)) {
+      m = j + 1;
+      break;
+    }
+  if (H) std::memcpy(H, Hh.data(), Hh.size() * sizeof(double));
+  for (int j = 0; j < steps; ++j) ritz_re[j] = ritz_im[j] = 0.0;
+  if (!irk::hessenberg_eigs(m, Hh.data(), ld, ritz_re, ritz_im))
+    return fail(IRK_ENOCONV, "Hessenberg QR iteration did not converge");
+  if (nritz) *nritz = m;
+  return IRK_OK;
+}
+
+irk_status irk_mg_set_interval(irk_mg* h, double lo, double hi) {
+  CHK(check_handle(h));
+  if (!(lo > 0 && hi > lo && std::isfinite(hi))) return fail(IRK_EINVAL, "need 0 < lo < hi < inf");
+  h->cheb_lo = lo;
+  h->cheb_hi = hi;
   return IRK_OK;
 }
 

@@ -17,6 +17,7 @@
 #include <map>
 #include <numeric>
 #include <stdexcept>
+#include <vector>
 
 #include "irk_internal.h"
 
@@ -717,6 +718,80 @@ double inf_norm(int r, const double* M) {
   return m;
 }
 }  // namespace
+
+bool hessenberg_eigs(int m, const double* H, int ldh, double* wr, double* wi) {
+  using C = std::complex<double>;
+  if (m < 1) return true;
+  std::vector<C> a((size_t)m * m, C(0.0));  // row-major working copy
+  double nrm = 0.0;
+  for (int j = 0; j < m; ++j)
+    for (int i = 0; i <= std::min(j + 1, m - 1); ++i) {
+      a[(size_t)i * m + j] = H[(size_t)j * ldh + i];
+      nrm = std::max(nrm, std::abs(H[(size_t)j * ldh + i]));
+    }
+  auto A = [&](int i, int j) -> C& { return a[(size_t)i * m + j]; };
+  std::vector<C> ev(m);
+  const double eps = 4.0 * 2.220446049250313e-16;
+  int hi = m - 1, iter = 0;
+  while (hi >= 0) {
+    // the active block is [l, hi]: the subdiagonal entry above row l is negligible
+    int l = hi;
+    while (l > 0) {
+      double s = std::abs(A(l - 1, l - 1)) + std::abs(A(l, l));
+      if (s == 0.0) s = nrm;
+      if (std::abs(A(l, l - 1)) <= eps * s) {
+        A(l, l - 1) = 0.0;
+        break;
+      }
+      --l;
+    }
+    if (l == hi) {  // a 1 x 1 block: its entry is an eigenvalue
+      ev[hi] = A(hi, hi);
+      --hi;
+      iter = 0;
+      continue;
+    }
+    if (++iter > 100 * m) return false;
+    // shift: the eigenvalue of the trailing 2 x 2 closer to its last diagonal entry
+    // (Wilkinson), replaced by an ad hoc value every 11th iteration to break cycles
+    const C p = A(hi - 1, hi - 1), q = A(hi - 1, hi), r = A(hi, hi - 1), d = A(hi, hi);
+    const C half = 0.5 * (p + d), disc = std::sqrt(0.25 * (p - d) * (p - d) + q * r);
+    C mu = std::abs(half + disc - d) < std::abs(half - disc - d) ? half + disc : half - disc;
+    if (iter % 11 == 0) mu = d + 0.75 * std::abs(r);
+    // one QR step on the block: B - mu I = Q R by Givens rotations, B <- R Q + mu I
+    for (int k = l; k <= hi; ++k) A(k, k) -= mu;
+    std::vector<C> cs(hi - l), sn(hi - l);
+    for (int k = l; k < hi; ++k) {
+      const C x = A(k, k), y = A(k + 1, k);
+      const double rr = std::sqrt(std::norm(x) + std::norm(y));
+      const C c = rr > 0.0 ? x / rr : C(1.0), s = rr > 0.0 ? y / rr : C(0.0);
+      cs[k - l] = c;
+      sn[k - l] = s;
+      for (int j = k; j <= hi; ++j) {
+        const C t1 = A(k, j), t2 = A(k + 1, j);
+        A(k, j) = std::conj(c) * t1 + std::conj(s) * t2;
+        A(k + 1, j) = -s * t1 + c * t2;
+      }
+    }
+    for (int k = l; k < hi; ++k) {
+      const C c = cs[k - l], s = sn[k - l];
+      for (int i = l; i <= std::min(k + 1, hi); ++i) {
+        const C t1 = A(i, k), t2 = A(i, k + 1);
+        A(i, k) = t1 * c + t2 * s;
+        A(i, k + 1) = -t1 * std::conj(s) + t2 * std::conj(c);
+      }
+    }
+    for (int k = l; k <= hi; ++k) A(k, k) += mu;
+  }
+  std::vector<int> order(m);
+  std::iota(order.begin(), order.end(), 0);
+  std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return ev[x].real() > ev[y].real(); });
+  for (int k = 0; k < m; ++k) {
+    wr[k] = ev[order[k]].real();
+    wi[k] = ev[order[k]].imag();
+  }
+  return true;
+}
 
 bool stage_eigenbasis(const double* A, int r, StageEig& out, std::string* why) {
   auto fail = [&](const std::string& m) {

@@ -81,6 +81,9 @@ def _load() -> C.CDLL:
         "irk_mg_destroy": (None, [vp]),
         "irk_mg_patch_form": (i, [vp]),
         "irk_stage_basis": (i, [i, vp, vp, vp, vp]),
+        "irk_hessenberg_eigs": (i, [i, vp, i, vp, vp]),
+        "irk_mg_ritz": (i, [vp, i, i, vp, vp, vp, vp, vp, vp]),
+        "irk_mg_set_interval": (i, [vp, d, d]),
         "irk_mg_ndofs": (i64, [vp, i]),
         "irk_mg_sizes": (i, [vp, i, vp]),
         "irk_mg_p2_nodes": (i, [vp, i, vp, vp]),
@@ -160,6 +163,16 @@ def irk_stage_basis(A):
     return W, Wi, T
 
 
+def irk_hessenberg_eigs(H, m=None):
+    """Eigenvalues (complex array, decreasing real part) of the leading m x m block of an
+    upper Hessenberg matrix (irk_hessenberg_eigs; host only)."""
+    H = np.asfortranarray(H, dtype=np.float64)
+    m = H.shape[1] if m is None else int(m)
+    wr, wi = np.zeros(m), np.zeros(m)
+    _check(lib.irk_hessenberg_eigs(m, H.ctypes.data, H.shape[0], wr.ctypes.data, wi.ctypes.data))
+    return wr + 1j * wi
+
+
 def irk_mesh_p2_nodes(level) -> np.ndarray:
     s, keep = _mesh_struct(level)
     n = C.c_int64(0)
@@ -222,6 +235,21 @@ class IrkMG:
 
     def __del__(self):
         self.close()
+
+    # ----------------------------------------------------- relaxation spectrum
+    def irk_mg_ritz(self, level, steps, v0, stream=None):
+        """(H, Ritz values) of `steps` Arnoldi steps on W S J_level from v0 (device,
+        ABI layout of the level); the Ritz values past an early invariant space are dropped."""
+        n = self.irk_mg_ndofs(level)
+        H = np.zeros((steps + 1, steps), order="F")
+        wr, wi = np.zeros(steps), np.zeros(steps)
+        m = C.c_int(0)
+        _check(lib.irk_mg_ritz(self.h, level, steps, _dev(v0, n, "v0"), H.ctypes.data, wr.ctypes.data,
+                               wi.ctypes.data, C.byref(m), _stream(stream)))
+        return H, (wr + 1j * wi)[: m.value]
+
+    def irk_mg_set_interval(self, lo, hi):
+        _check(lib.irk_mg_set_interval(self.h, float(lo), float(hi)))
 
     # ---------------------------------------------------------------- sizes
     def irk_mg_patch_form(self) -> int:

@@ -161,3 +161,26 @@ def test_stage_basis_gauss4():
     ev = np.concatenate([[T[0, 0] + 1j * T[0, 1], T[0, 0] - 1j * T[0, 1]],
                          [T[2, 2] + 1j * T[2, 3], T[2, 2] - 1j * T[2, 3]]])
     assert np.abs(np.sort_complex(ev) - np.sort_complex(np.linalg.eigvals(A))).max() < 1e-12
+
+
+def test_hessenberg_eigenvalues_against_lapack():
+    """irk_hessenberg_eigs (shifted QR in complex arithmetic) against numpy's LAPACK
+    eigenvalues on random upper Hessenberg matrices (real and complex-pair spectra) and
+    on a block of plane rotations with a known spectrum; error paths."""
+    rng = np.random.default_rng(61)
+    for m in (1, 2, 5, 12, 30, 64):
+        H = np.triu(rng.standard_normal((m + 1, m)), -1)
+        ev = irkmg.irk_hessenberg_eigs(H, m)
+        ref = np.linalg.eigvals(H[:m, :m])
+        assert np.all(np.diff(ev.real) <= 1e-12)
+        for z in ref:  # every LAPACK eigenvalue has a close partner
+            assert np.min(np.abs(ev - z)) <= 1e-9 * max(1.0, np.abs(ref).max()), (m, z)
+    R = np.zeros((6, 6))
+    for k, (a, b) in enumerate([(1.0, 2.0), (-0.5, 0.25), (3.0, 1.0)]):
+        R[2 * k:2 * k + 2, 2 * k:2 * k + 2] = [[a, b], [-b, a]]
+    R[0, 5] = 0.7
+    ev = irkmg.irk_hessenberg_eigs(R)
+    want = np.array([3 + 1j, 3 - 1j, 1 + 2j, 1 - 2j, -0.5 + 0.25j, -0.5 - 0.25j])
+    assert all(np.min(np.abs(ev - z)) < 1e-12 for z in want)
+    with pytest.raises(irkmg.IrkError):
+        irkmg.irk_hessenberg_eigs(np.zeros((3, 3)), 0)

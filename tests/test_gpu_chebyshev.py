@@ -93,3 +93,61 @@ def test_chebyshev_adjoint_solve_matches_oracle(case):
                         project=S.project_pressure_mean)
         assert info["iterations"] == io.iterations
         assert relerr(to_host(lam), xo) < 1e-10
+
+
+@pytest.mark.parametrize("case", ["c1", "cross", "3d2"])
+def test_ritz_estimate_matches_oracle(case):
+    """Arnoldi on the relaxation operator S J of each level (Sec. 5.1's interval rule):
+    the Hessenberg matrix to 1e-11 of its largest entry and the Ritz values, as a set, to
+    1e-8 against the oracle's, from the same start vector."""
+    from oracle.vanka import arnoldi_ritz
+
+    g, H = gpu_of(case, smoother=1), oracle_of(case, smoother="chebyshev")
+    rng = np.random.default_rng(55)
+    for lev in range(1, g.nlevels):
+        J = H.systems[lev].J
+        steps = min(12, J.shape[0] - 1)
+        v0 = rng.standard_normal(J.shape[0])
+        say(f"[ritz] case={case} level={lev} steps={steps}")
+        Hg, rg = g.irk_mg_ritz(lev, steps, to_dev(v0))
+        Ho, ro = arnoldi_ritz(lambda x: J @ x, H.smoothers[lev].apply_S, v0, steps)
+        assert rg.size == ro.size == steps
+        assert np.abs(Hg - Ho).max() <= 1e-11 * np.abs(Ho).max()
+        # the same values (a conjugate pair's order within equal real parts may differ)
+        tol = 1e-8 * np.abs(ro).max()
+        assert all(np.min(np.abs(rg - z)) <= tol for z in ro)
+        assert all(np.min(np.abs(ro - z)) <= tol for z in rg)
+        assert abs(rg[0].real - ro[0].real) <= tol
+
+
+def test_interval_from_ritz_estimate():
+    """[lambda/4, lambda] from the finest level's largest Ritz value (the paper's rule)
+    set on the handle; the V-cycle then matches the oracle's with that interval."""
+    from oracle.multigrid import Hierarchy
+    from oracle.tableau import tableau
+    from gpu_cases import CASES, levels_of
+
+    case = "cross"
+    g = gpu_of(case, smoother=1)
+    dim, nc, nl, fam, r, dt, nu, ws = CASES[case]
+    lev = g.nlevels - 1
+    v0 = np.random.default_rng(56).standard_normal(g.irk_mg_ndofs(lev))
+    say("[ritz interval] estimate")
+    _, ritz = g.irk_mg_ritz(lev, 20, to_dev(v0))
+    lam = float(ritz[0].real)
+    say(f"[ritz interval] lambda_max estimate {lam:.4f}")
+    assert lam > 1.0
+    g.irk_mg_set_interval(lam / 4, lam)
+    try:
+        Ho = Hierarchy(levels_of(case), tableau(fam, r)[0], dt, nu, weighted=False, smoother="chebyshev",
+                       interval=(lam / 4, lam))
+        rv = np.random.default_rng(57).standard_normal(g.irk_mg_ndofs())
+        z = torch.zeros(rv.size, dtype=torch.float64, device="cuda")
+        say("[ritz interval] vcycle")
+        g.irk_mg_vcycle(to_dev(rv), z)
+        assert relerr(to_host(z), Ho.vcycle(rv)) < coarse_tol(Ho)
+    finally:
+        g.irk_mg_set_interval(2.0, 8.0)  # the cached handle keeps the paper's interval
+    from paper_2202_07381_amd import irkmg
+    with pytest.raises(irkmg.IrkError):
+        g.irk_mg_set_interval(3.0, 2.0)
