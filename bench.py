@@ -298,7 +298,7 @@ def p2p1_errors(level, vel, p, exact):
     return float(vel_err), float(p_err)
 
 
-def run_t1(ell, r, precision=0, max_steps=None, log_every=32, fixed_rtol=None):
+def run_t1(ell, r, precision=0, max_steps=None, log_every=32, fixed_rtol=None, auto_interval=False):
     """The paper's 2D Stokes experiment (Sec. 5.1, Table 1): exact solution
     u = (sin(pi x) cos(pi y), -cos(pi x) sin(pi y)) e^{-2 pi^2 t}, p = 0 (so f = 0 and the
     boundary data drive the flow), nu = 1, RadauIIA(r), FGMRES with the Chebyshev-relaxed
@@ -319,6 +319,17 @@ def run_t1(ell, r, precision=0, max_steps=None, log_every=32, fixed_rtol=None):
     g = irkmg.IrkMG(levels, A, b, c, dt, 1.0, weighting=0, precision=precision, smoother=1, interval=(2.0, 8.0))
     torch.cuda.synchronize()
     setup_s = time.time() - t0
+    interval = (2.0, 8.0)
+    if auto_interval:
+        # Sec. 5.1's rule [lambda/4, lambda], lambda the largest eigenvalue of S J, from 20
+        # Arnoldi steps on the finest level (the paper tuned its interval by hand)
+        top = len(levels) - 1
+        v0 = torch.tensor(np.random.default_rng(5).standard_normal(g.irk_mg_ndofs(top)), device="cuda")
+        _, ritz = g.irk_mg_ritz(top, 20, v0)
+        lam = float(ritz[0].real)
+        interval = (lam / 4, lam)
+        g.irk_mg_set_interval(*interval)
+        log(f"t1 interval from the Ritz estimate: [{interval[0]:.4f}, {interval[1]:.4f}]")
     nodes, free = g.irk_mg_p2_nodes()
     sz = g.irk_mg_sizes()
     N = g.irk_mg_ndofs()
@@ -379,7 +390,7 @@ def run_t1(ell, r, precision=0, max_steps=None, log_every=32, fixed_rtol=None):
         "n_gpus": 1, "steps": steps, "dtype": "f64" if precision == 0 else "f64 (FP32 patches)",
         "data": "synthetic (the paper's exact solution)",
         "config": {"workload": f"2D Stokes, crossed 8x8 refined l={ell} times, RadauIIA({r}), dt=0.5/2^{ell + 3}, "
-                               f"Chebyshev [2,8] 2/2, unweighted additive Vanka, "
+                               f"Chebyshev [{interval[0]:.4g},{interval[1]:.4g}] 2/2, unweighted additive Vanka, "
                                + (f"stop at {fixed_rtol:g} rel" if fixed_rtol is not None
                                   else "stop at 1e-2 N^-3 abs or 1e-8 rel"),
                    "l": ell, "stages": r, "unknowns": N, "dofs_per_stage": N // r, "time_steps_total": nsteps},
@@ -569,6 +580,8 @@ def main():
     ap.add_argument("--t1-stages", type=int, default=2, choices=[2, 3], help="t1: RadauIIA stages")
     ap.add_argument("--t1-max-steps", type=int, default=None, help="t1: stop after this many time steps")
     ap.add_argument("--t1-fp32", action="store_true", help="t1: FP32 patch factors")
+    ap.add_argument("--t1-auto-interval", action="store_true",
+                    help="t1: Chebyshev interval [lambda/4, lambda] from a Ritz estimate instead of [2, 8]")
     ap.add_argument("--t1-rtol", type=float, default=None,
                     help="t1: fixed relative tolerance instead of the paper's stopping rule")
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -598,7 +611,7 @@ def main():
         return
     if args.workload == "t1":
         print(json.dumps(run_t1(args.t1_level, args.t1_stages, 1 if args.t1_fp32 else 0, args.t1_max_steps,
-                                fixed_rtol=args.t1_rtol)), flush=True)
+                                fixed_rtol=args.t1_rtol, auto_interval=args.t1_auto_interval)), flush=True)
         return
     nlev = int(round(np.log2(args.n // 4))) + 1
     levels = wl.square_hierarchy(4, nlev)
