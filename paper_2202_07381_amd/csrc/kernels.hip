@@ -1144,7 +1144,10 @@ __global__ __launch_bounds__(kBlock) void k_gr_scale(int64_t n, const double* __
 }
 
 // y minimising ||beta e_1 - H y|| for the first m_eff columns, m_eff the steps before the
-// first zero subdiagonal entry (an invariant Krylov space); y = 0 past m_eff
+// first zero subdiagonal entry (an invariant Krylov space), and before a column whose
+// rotated diagonal falls below 1e-12 of the largest one so far (a numerically rank
+// deficient H, as when a basis vector lies in the pressure null space of J; a least
+// squares solve with a rank cut-off drops the same direction); y = 0 past m_eff
 __global__ void k_gr_solve(double* __restrict__ gr, int m) {
   if (threadIdx.x != 0 || blockIdx.x != 0) return;
   constexpr int ld = kMaxGr + 1;
@@ -1161,6 +1164,7 @@ __global__ void k_gr_solve(double* __restrict__ gr, int m) {
   for (int i = 0; i < ld * kMaxGr; ++i) R[i] = H[i];
   for (int i = 0; i < ld; ++i) g[i] = 0.0;
   g[0] = beta;
+  double rmax = 0.0;
   for (int j = 0; j < me; ++j) {
     for (int i = 0; i < j; ++i) {  // earlier rotations on column j
       const double a = R[j * ld + i], b = R[j * ld + i + 1];
@@ -1169,8 +1173,13 @@ __global__ void k_gr_solve(double* __restrict__ gr, int m) {
     }
     const double a = R[j * ld + j], b = R[j * ld + j + 1];
     const double rr = hypot(a, b);
-    c[j] = rr > 0.0 ? a / rr : 1.0;
-    sn[j] = rr > 0.0 ? b / rr : 0.0;
+    if (!(rr > 1e-12 * rmax)) {  // also catches a non-finite rr
+      me = j;
+      break;
+    }
+    rmax = fmax(rmax, rr);
+    c[j] = a / rr;
+    sn[j] = b / rr;
     R[j * ld + j] = rr;
     R[j * ld + j + 1] = 0.0;
     const double g0 = g[j], g1 = g[j + 1];
@@ -1181,7 +1190,7 @@ __global__ void k_gr_solve(double* __restrict__ gr, int m) {
   for (int j = me - 1; j >= 0; --j) {
     double t = g[j];
     for (int k = j + 1; k < me; ++k) t -= R[k * ld + j] * y[k];
-    y[j] = R[j * ld + j] != 0.0 ? t / R[j * ld + j] : 0.0;
+    y[j] = t / R[j * ld + j];
   }
 }
 
@@ -1313,11 +1322,13 @@ __global__ __launch_bounds__(kBlock) void k_scale_inv(double* __restrict__ y,
   if (i < n) y[i] = x[i] / (*s);
 }
 
+// y = a x + b y; with b = 0, y is not read (it may be fresh memory holding non-finite
+// bit patterns, which 0 * y would carry into the result)
 __global__ __launch_bounds__(kBlock) void k_axpby(double* __restrict__ y,
                                                   const double* __restrict__ x, int64_t n,
                                                   double a, double b) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) y[i] = a * x[i] + b * y[i];
+  if (i < n) y[i] = b == 0.0 ? a * x[i] : a * x[i] + b * y[i];
 }
 
 template <typename T>
@@ -1697,8 +1708,9 @@ hipError_t patch_apply(const DevLevel& L, const DevOps<T>& ops, const T* res, T*
   k_patch_apply_eig<T, RBV, NM, U, NT, WV, ##__VA_ARGS__><<<dim3(blocks_for(L.npatch, WV)), dim3(WV * 64), 0, s>>>( \
       L.npatch, sb, L.sched, L.p_nloc, L.p_ld, L.p_inv_off, L.p_slot_off, L.p_gidx, inv, res, W, Y,  \
       transpose, L.dim)
-    // 4 columns in flight per lane with non-temporal loads: at 62 VGPRs the 2D kernel
-    // runs 8 waves per SIMD; deeper unrolling lowered occupancy and measured slower
+    // 4 columns in flight per lane, non-temporal loads (ordinary ones on the small
+    // levels): at 62 VGPRs the 2D kernel runs 8 waves per SIMD; deeper unrolling
+    // lowered occupancy and measured slower
     const bool small = L.npatch <= kSmallPatches;
     if (small && L.max_nloc <= 128 && rbe <= 1) IRK_PAE(1, 128, 4, 0, 4);
     else if (L.max_nloc <= 128 && rbe <= 1) IRK_PAE(1, 128, 4, 1, 4);
