@@ -17,6 +17,8 @@ Modules
   fgmres     Flexible GMRES with right preconditioning (Sec. 4).
   timestep   IRK time stepping, errors, semi-discrete reference solution (Sec. 3.1, 5.1).
   adjoint    Transposed solves and gradients of a tracking loss (not in the paper).
+  navier_stokes  Navier--Stokes stage equations, their Jacobian, Newton with
+             Eisenstat--Walker forcing (Sec. 3.2).
 
 Pin status of every function is listed in each module header.
 """

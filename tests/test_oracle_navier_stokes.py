@@ -1,0 +1,203 @@
+"""Pins for oracle/navier_stokes.py: the Navier--Stokes stage equations and Newton (Sec. 3.2)."""
+import numpy as np
+import pytest
+
+from oracle.fem import TaylorHood
+from oracle.fgmres import fgmres
+from oracle.multigrid import Hierarchy
+from oracle.navier_stokes import EWParams, NavierStokesStages, ew_forcing
+from oracle.tableau import tableau
+from paper_2202_07381_amd import workloads as wl
+
+
+def _space(dim, n):
+    xyz, cells = wl.square_mesh(n) if dim == 2 else wl.cube_mesh(n)
+    return TaylorHood(xyz, cells)
+
+
+def _affine(th, seed):
+    """Nodal values of a random affine field x -> alpha + Bm x and (alpha, Bm)."""
+    rng = np.random.default_rng(seed)
+    alpha = rng.standard_normal(th.dim)
+    Bm = rng.standard_normal((th.dim, th.dim))
+    return alpha[None, :] + th.node_xyz @ Bm.T, alpha, Bm
+
+
+def _mass_rows(th, g_nodal):
+    """<g, phi_i> for a field g in P2 (nodal values), component-blocked free rows."""
+    Mf = th.scalar_mass_full()[th.free]
+    return np.concatenate([Mf @ g_nodal[:, c] for c in range(th.dim)])
+
+
+@pytest.mark.parametrize("dim,n", [(2, 4), (3, 2)])
+def test_convection_closed_form_affine(dim, n):
+    # (a . grad) b = Db (alpha_a + Ba x) is affine, so its P2 interpolant is exact and
+    # c(a, b; phi_i) = sum_j M_ij g(x_j); both operand orders (they differ: Ba Db != Db Ba).
+    th = _space(dim, n)
+    S = NavierStokesStages(th, np.eye(1), 0.1, 1.0)
+    a, al_a, Ba = _affine(th, 1)
+    b, al_b, Bb = _affine(th, 2)
+    ab = (a @ Bb.T)          # (a . grad) b = Bb a
+    ba = (b @ Ba.T)          # (b . grad) a = Ba b
+    for got, ref in ((S.convection_vector(a, b), _mass_rows(th, ab)),
+                     (S.convection_vector(b, a), _mass_rows(th, ba))):
+        assert np.abs(got - ref).max() <= 1e-13 * np.abs(ref).max()
+    assert np.abs(_mass_rows(th, ab) - _mass_rows(th, ba)).max() > 1e-3
+
+
+@pytest.mark.parametrize("dim,n", [(2, 4), (3, 2)])
+def test_reaction_closed_form_affine(dim, n):
+    # (z . grad) U = Bm z for U = alpha + Bm x: R(U) z = [sum_e Bm_ce M z_e]_c
+    th = _space(dim, n)
+    S = NavierStokesStages(th, np.eye(1), 0.1, 1.0)
+    U, _, Bm = _affine(th, 3)
+    z = np.random.default_rng(4).standard_normal(dim * th.nfree)
+    Mff = th.scalar_mass_full()[th.free][:, th.free]
+    zc = [z[c * th.nfree:(c + 1) * th.nfree] for c in range(dim)]
+    ref = np.concatenate([sum(Bm[c, e] * (Mff @ zc[e]) for e in range(dim)) for c in range(dim)])
+    got = S.reaction_matrix(U) @ z
+    assert np.abs(got - ref).max() <= 1e-13 * np.abs(ref).max()
+
+
+def test_reaction_equals_swapped_convection():
+    # R(U) z = c(z, U): two code paths (gradient of U at the points vs of the basis)
+    th = _space(2, 4)
+    S = NavierStokesStages(th, np.eye(1), 0.1, 1.0)
+    rng = np.random.default_rng(5)
+    U = rng.standard_normal((th.nnodes, 2))
+    z = rng.standard_normal(2 * th.nfree)
+    got = S.reaction_matrix(U) @ z
+    ref = S.convection_vector(S.free_nodal(z), U)
+    assert np.abs(got - ref).max() <= 1e-13 * np.abs(ref).max()
+
+
+def _ns(fam="radauIIA", r=3, dim=2, n=4, dt=0.1, nu=0.05):
+    th = _space(dim, n)
+    A, b, c = tableau(fam, r)
+    return NavierStokesStages(th, A, dt, nu), th, b, c
+
+
+@pytest.mark.parametrize("fam,r,dim,bnd", [("radauIIA", 3, 2, False), ("gauss", 2, 2, True),
+                                           ("lobattoIIIC", 2, 3, False)])
+def test_jacobian_equals_central_difference(fam, r, dim, bnd):
+    # G is quadratic in k, so (G(k + x) - G(k - x)) / 2 = J(k) x up to rounding
+    S, th, _, _ = _ns(fam, r, dim, 4 if dim == 2 else 2)
+    rng = np.random.default_rng(6)
+    k = rng.standard_normal(S.n)
+    x = rng.standard_normal(S.n)
+    u_n = rng.standard_normal(S.ns)
+    F = rng.standard_normal(S.n)
+    g = [rng.standard_normal((th.nnodes, dim)) for _ in range(r)] if bnd else None
+    fd = 0.5 * (S.residual(F, u_n, k + x, g) - S.residual(F, u_n, k - x, g))
+    Jx = S.jacobian(u_n, k, g) @ x
+    Jx_mf = S.jacobian_apply(u_n, k, x, g)
+    scale = np.abs(fd).max()
+    assert np.abs(Jx - fd).max() <= 1e-12 * scale
+    assert np.abs(Jx_mf - fd).max() <= 1e-12 * scale
+
+
+def test_ew_forcing():
+    p = EWParams()
+    assert ew_forcing(0, 1.0, 1.0, 0.0, p) == p.eta0
+    # a fast step: (0.01)^alpha is tiny, the safeguard gamma eta_prev^alpha = 0.3^1.618 = 0.143 > 0.1 holds
+    assert ew_forcing(1, 0.01, 1.0, 0.3, p) == pytest.approx(0.3 ** p.alpha)
+    # no safeguard when gamma eta_prev^alpha <= 0.1
+    assert ew_forcing(2, 1e-4, 1e-2, 0.05, p) == pytest.approx(0.01 ** p.alpha)
+    # a stalled step is capped at eta_max
+    assert ew_forcing(1, 2.0, 1.0, 0.3, p) == p.eta_max
+
+
+def _problem(S, th, seed=7, amp=20.0):
+    f = wl.forcing_2d(seed)
+    fam = lambda pts, t: amp * f(pts, t)  # noqa: E731
+    rng = np.random.default_rng(seed)
+    u_n = 0.5 * rng.standard_normal(th.nvel)  # free velocities of the state
+    return fam, u_n
+
+
+def test_newton_solution_satisfies_stage_equations():
+    S, th, b, c = _ns("radauIIA", 2, 2, 4, dt=0.1, nu=0.02)
+    forcing, u_n = _problem(S, th)
+    fn = [th.interpolate(forcing, ci * S.dt) for ci in c]
+    F = S.S.rhs(fn, u_n, np.zeros(th.nverts))
+    k, info = S.newton(F, u_n, np.zeros(S.n), rtol=1e-13)
+    assert info.converged and info.iterations <= 8
+    # the stage equations of Sec. 3.2, one stage at a time, with a double loop over a_ij
+    St = S.S
+    nf = th.nfree
+    for i in range(S.r):
+        Ui = u_n[:2 * nf].copy()
+        for j in range(S.r):
+            Ui += S.dt * S.A[i, j] * St.split(k, j)[0]
+        Un = S.free_nodal(Ui)
+        conv = S.convection_vector(Un, Un)
+        kui, _ = St.split(k, i)
+        vel = np.concatenate([St.Ms @ kui[cc * nf:(cc + 1) * nf] for cc in range(2)]) + conv
+        div = np.zeros(th.nverts)
+        for j in range(S.r):
+            ku, kp = St.split(k, j)
+            vel += S.dt * S.A[i, j] * (np.concatenate([St.Ks @ ku[cc * nf:(cc + 1) * nf] for cc in range(2)]) + St.B @ kp)
+            div += S.dt * S.A[i, j] * (St.B.T @ ku)
+        Mf = np.concatenate([St.Ms_free_all @ fn[i][:, cc] for cc in range(2)])
+        rhs_v = Mf - np.concatenate([St.Ks @ u_n[cc * nf:(cc + 1) * nf] for cc in range(2)])
+        assert np.abs(vel - rhs_v).max() <= 1e-10 * np.abs(rhs_v).max()
+        assert np.abs(div + St.B.T @ u_n[:2 * nf]).max() <= 1e-10 * np.abs(St.B.T @ u_n[:2 * nf]).max()
+
+
+def test_newton_converges_quadratically():
+    S, th, b, c = _ns("radauIIA", 3, 2, 4, dt=0.1, nu=0.01)
+    forcing, u_n = _problem(S, th, seed=8, amp=40.0)
+    fn = [th.interpolate(forcing, ci * S.dt) for ci in c]
+    F = S.S.rhs(fn, u_n, np.zeros(th.nverts))
+    k, info = S.newton(F, u_n, np.zeros(S.n), rtol=1e-14, maxit=30)
+    e = np.array(info.norms) / info.norms[0]
+    assert info.iterations >= 3  # a genuinely nonlinear problem
+    quad = [(e[i], e[i + 1]) for i in range(len(e) - 1) if e[i] < 1e-2 and e[i + 1] > 1e-13]
+    assert quad, e
+    for a, b_ in quad:
+        assert b_ <= 10.0 * a * a, e
+
+
+def test_newton_reduces_to_stokes_for_small_data():
+    # N is quadratic: k(eps F) = eps k_Stokes(F) + O(eps^2)
+    S, th, b, c = _ns("gauss", 2, 2, 4, dt=0.1, nu=0.1)
+    forcing, _ = _problem(S, th, seed=9, amp=1.0)
+    fn = [th.interpolate(forcing, ci * S.dt) for ci in c]
+    F = S.S.rhs(fn, np.zeros(th.nvel), np.zeros(th.nverts))
+    ks = S.direct_solver()(S.S.J, F, 0.0)[0]
+    errs = []
+    for eps in (1e-2, 1e-3):
+        k, info = S.newton(eps * F, np.zeros(th.nvel), np.zeros(S.n), rtol=1e-13)
+        errs.append(np.linalg.norm(k - eps * ks) / np.linalg.norm(eps * ks))
+    assert errs[1] < 0.2 * errs[0] and errs[1] < 1e-3
+
+
+def test_inexact_newton_with_kronecker_multigrid():
+    # Newton with FGMRES + the Oseen V-cycle at a frozen wind as preconditioner (a
+    # Kronecker operator) and Eisenstat--Walker forcing reaches the exact-Newton solution
+    A, b, c = tableau("radauIIA", 2)
+    levels = wl.square_hierarchy(2, 3)
+    th = TaylorHood(levels[-1].xyz, levels[-1].cells)
+    S = NavierStokesStages(th, A, 0.05, 0.02)
+    forcing, u_n = _problem(S, th, seed=10, amp=20.0)
+    fn = [th.interpolate(forcing, ci * S.dt) for ci in c]
+    F = S.S.rhs(fn, u_n, np.zeros(th.nverts))
+    k_ex, _ = S.newton(F, u_n, np.zeros(S.n), rtol=1e-12)
+    wind_nodal = S.free_nodal(u_n[:th.nvel])
+
+    def wind(pts, t):  # the frozen linearisation point u^n, at the finest nodes
+        return wind_nodal
+    H = Hierarchy(levels[-1:], A, S.dt, S.S.nu, wind=wind)  # one level: an exact Oseen solve
+    Hm = Hierarchy(levels, A, S.dt, S.S.nu)  # Stokes V-cycle
+
+    def mg_solve(H_):
+        def solve(Jm, rhs, eta):
+            x, inf = fgmres(lambda v: Jm @ v, H_.vcycle, rhs, np.zeros_like(rhs), eta, 200, 30,
+                            project=S.S.project_pressure_mean)
+            return x, inf.iterations
+        return solve
+    for H_ in (H, Hm):
+        k, info = S.newton(F, u_n, np.zeros(S.n), rtol=1e-10, linear_solve=mg_solve(H_))
+        assert info.converged
+        assert np.linalg.norm(S.S.project_pressure_mean(k) - S.S.project_pressure_mean(k_ex)) <= \
+            1e-7 * np.linalg.norm(k_ex)
