@@ -563,6 +563,90 @@ def run_relax(n):
             "results": out}
 
 
+def ns_element_flops(dim, r, ncells):
+    """Algorithmic FP64 flops (an FMA counts 2) of one Jacobian-mode launch of the
+    Navier--Stokes element kernel: per (cell, stage) the stage mix of the direction
+    (nloc dim r FMAs) and two trilinear terms, each nloc (dim+1) dim FMAs for the wind
+    coefficients and nloc^2 (nloc (dim+1) + dim) for the contraction."""
+    nl, nb = (6, 3) if dim == 2 else (10, 4)
+    fma = 2 * (nl * nb * dim + nl * nl * (nl * nb + dim)) + nl * dim * r
+    return 2.0 * fma * ncells * r
+
+
+def run_ns(n, nsteps, smoother):
+    """Navier--Stokes time stepping (Sec. 3.2): Newton with Eisenstat--Walker forcing,
+    FGMRES preconditioned by the V-cycle of the Oseen operator linearised at the initial
+    state (set up once, kept for every step), 2D n x n, RadauIIA(3), nu = 0.01 (Re = 100
+    for unit speed and length), dt = 1/400 (the paper's cylinder run), a unit-speed
+    divergence-free initial state and a smooth body force, all synthetic."""
+    import numpy as np
+    import torch
+
+    from paper_2202_07381_amd import irkmg
+    from paper_2202_07381_amd import workloads as wl
+
+    fam, r, dt, nu = "radauIIA", 3, 1.0 / 400, 0.01
+    levels = wl.square_hierarchy(4, int(round(np.log2(n // 4))) + 1)
+    A, b, c = irkmg.irk_tableau_builtin(fam, r)
+    nodes = irkmg.irk_mesh_p2_nodes(levels[-1])
+    u0 = wl.wind_2d(3, n)(nodes)
+    kw = {"sweep": dict(smoother=0), "chebyshev": dict(smoother=1, weighting=0, interval=(1.5, 8.0)),
+          "gmres": dict(smoother=2)}[smoother]
+    t0 = time.time()
+    g = irkmg.IrkMG(levels, A, b, c, dt, nu, wind_nodal=u0, **kw)
+    torch.cuda.synchronize()
+    setup_s = time.time() - t0
+    sz = g.irk_mg_sizes()
+    N = g.irk_mg_ndofs()
+    free = g.irk_mg_p2_nodes()[1]
+    state = torch.zeros(sz["ns"], dtype=torch.float64, device="cuda")
+    state[: 2 * sz["nfree"]] = torch.tensor(np.concatenate([u0[free, 0], u0[free, 1]]), device="cuda")
+    f = wl.forcing_2d(3)
+    fst = torch.tensor(np.stack([f(nodes)] * r).ravel(), device="cuda")
+    k = torch.zeros(N, dtype=torch.float64, device="cuda")
+    F = torch.zeros_like(k)
+    log(f"ns {n}x{n}: N={N} setup {setup_s:.1f} s")
+    steps = []
+    for it in range(nsteps):
+        if it == 1:
+            g.irk_mg_profile(2)  # kernel times from the second step on
+        g.irk_rhs(fst, state, F)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        info = g.irk_ns_newton_solve(F, state, k, rtol=1e-8)
+        torch.cuda.synchronize()
+        ms = 1e3 * (time.perf_counter() - t1)
+        g.irk_update(k, state)
+        steps.append({"newton": info["iterations"], "linear": info["linear_its"].tolist(), "ms": ms,
+                      "converged": info["converged"]})
+        log(f"ns step {it}: newton {info['iterations']} linear {info['linear_its'].tolist()} {ms:.1f} ms")
+    se, sg = g.irk_mg_kernel_stats("ns_element"), g.irk_mg_kernel_stats("ns_gather")
+    pa = g.irk_mg_kernel_stats("patch_apply")
+    g.irk_mg_profile(0)
+    e_ms = se["ms_total"] / max(1, se["launches"])
+    gat_ms = sg["ms_total"] / max(1, sg["launches"])
+    ncells = levels[-1].cells.shape[0]
+    flops = ns_element_flops(2, r, ncells)
+    g.close()
+    t = steps[1:] if len(steps) > 1 else steps
+    return {"metric": "Navier--Stokes IRK time step (Newton-Krylov-multigrid)", "unit": "ms / step",
+            "value": float(np.mean([s["ms"] for s in t])), "higher_is_better": False, "n_gpus": 1,
+            "dtype": "f64", "data": "synthetic",
+            "config": {"workload": f"2D Navier-Stokes {n}x{n} RadauIIA(3) nu=0.01 dt=1/400, relaxation {smoother}, "
+                                   "preconditioner linearised at the initial state, Newton to 1e-8"},
+            "setup_s": setup_s, "steps": steps,
+            "newton_per_step": float(np.mean([s["newton"] for s in t])),
+            "linear_per_step": float(np.mean([sum(s["linear"]) for s in t])),
+            "kernels": {"ns_element_us": 1e3 * e_ms, "ns_element_launches": se["launches"],
+                        "ns_gather_us": 1e3 * gat_ms, "ns_gather_bytes": sg["bytes_per_launch"],
+                        "patch_apply_us": 1e3 * pa["ms_total"] / max(1, pa["launches"])},
+            "roofline_ns_element": {"bound": "alu", "achieved": flops / (e_ms * 1e-3) / 1e12, "peak": 78.6,
+                                    "unit": "TFLOP/s", "frac": flops / (e_ms * 1e-3) / 1e12 / 78.6,
+                                    "flops_per_launch": flops},
+            "roofline_ns_gather": {"bound": "hbm", "achieved": sg["bytes_per_launch"] / (gat_ms * 1e-3) / 1e9,
+                                   "peak": 8000.0, "unit": "GB/s"}}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -571,9 +655,13 @@ def main():
     ap.add_argument("--n", type=int, default=256, help="finest mesh size (power-of-two multiple of 4)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp32", action="store_true")
-    ap.add_argument("--workload", default="stokes256", choices=["stokes256", "batch64", "t1", "relax"],
+    ap.add_argument("--workload", default="stokes256", choices=["stokes256", "batch64", "t1", "relax", "ns"],
                     help="stokes256: the headline line; batch64: the uneven batched workload; t1: the paper's "
-                         "2D Stokes table; relax: the three relaxations side by side")
+                         "2D Stokes table; relax: the three relaxations side by side; ns: Navier-Stokes "
+                         "time steps with Newton")
+    ap.add_argument("--ns-n", type=int, default=256, help="ns: finest mesh size")
+    ap.add_argument("--ns-steps", type=int, default=6, help="ns: time steps")
+    ap.add_argument("--ns-relax", default="sweep", choices=["sweep", "chebyshev", "gmres"], help="ns: relaxation")
     ap.add_argument("--relax-n", type=int, default=512, help="relax: finest mesh size of the Oseen problem")
     ap.add_argument("--batch-count", type=int, default=64)
     ap.add_argument("--t1-level", type=int, default=5, help="t1: refinement level l of the crossed 8x8 mesh")
@@ -608,6 +696,9 @@ def main():
         return
     if args.workload == "relax":
         print(json.dumps(run_relax(args.relax_n)), flush=True)
+        return
+    if args.workload == "ns":
+        print(json.dumps(run_ns(args.ns_n, args.ns_steps, args.ns_relax)), flush=True)
         return
     if args.workload == "t1":
         print(json.dumps(run_t1(args.t1_level, args.t1_stages, 1 if args.t1_fp32 else 0, args.t1_max_steps,

@@ -261,6 +261,71 @@ irk_status irk_rhs_dirichlet(irk_mg* h, const double* g_n, const double* g_stage
 /* state += dt * sum_j b_j k_j (the update of Sec. 3.1), state and k as above. */
 irk_status irk_update(irk_mg* h, const double* k, double* state, void* stream);
 
+/* Navier--Stokes stage equations and Newton's method (Sec. 3.2)
+ * --------------------------------------------------------------
+ * With inertia the velocity rows of stage i gain N(U_i), the discrete <U . grad U, v> at
+ * the stage value U_i = u^n + dt sum_j a_ij k_j^u (free nodes; at boundary nodes the
+ * stage data G_i of irk_rhs_dirichlet, or zero), so the stage system is nonlinear:
+ *   G(k) = (I (x) M^ + dt A (x) S^_Stokes) k - F_Stokes + [N(U_i); 0]_i = 0.
+ * These calls evaluate it on the finest level of a handle set up for the same mesh,
+ * tableau, dt and nu, with any wind w (NULL: Stokes): F is the right-hand side that
+ * irk_rhs (+ irk_rhs_dirichlet) builds on that handle, whose wind terms the calls cancel
+ * (they add c(U_i - w, U_i) = N(U_i) - C(w) U_i).  The Newton Jacobian, block (i, j) =
+ * delta_ij M^ + dt a_ij (S^ + N'(U_i)) with N'(U) z = c(z, U) + c(U, z), is not a
+ * Kronecker product; it is applied matrix-free (two kernels: element vectors per cell
+ * and stage, then a fixed-order sum per unknown) while the handle's V-cycle, built for
+ * its own Kronecker operator (wind w), preconditions FGMRES.  state: device, free
+ * velocities in the stage-block layout (the pressure part is not read); g_stages: device
+ * r x nnodes x dim stage boundary data or NULL.  All vectors in the ABI layout.
+ * Errors: IRK_EINVAL (null pointers, invalid options), IRK_ENAN (non-finite residual),
+ * IRK_EHIP, IRK_ENOMEM (the first call allocates the element data, about
+ * (nloc dim r + (dim+1) dim + nloc + 1) 8 ncells bytes). */
+
+/* R = F - J_w k - c(U - w, U), i.e. -G(k). */
+irk_status irk_ns_residual(irk_mg* h, const double* F, const double* state, const double* g_stages,
+                           const double* k, double* R, void* stream);
+/* y = G'(k) x, the Newton Jacobian at k applied to x. */
+irk_status irk_ns_jacobian_apply(irk_mg* h, const double* state, const double* g_stages, const double* k,
+                                 const double* x, double* y, void* stream);
+
+/* Newton (Sec. 3.2): k <- k + delta with G'(k) delta = -G(k) solved by FGMRES (the
+ * handle's V-cycle as preconditioner) from delta = 0 to the relative residual eta_l;
+ * the forcing terms follow Eisenstat and Walker's choice 2, eta_0 = eta0,
+ * eta_l = gamma (||G_l|| / ||G_{l-1}||)^alpha, raised to gamma eta_{l-1}^alpha when that
+ * exceeds the threshold, capped at eta_max (the paper names the criterion only; these
+ * constants are the defaults below), or eta_fixed when > 0.  Stops at
+ * ||G|| <= max(atol, rtol ||G(k0)||).  k: initial guess in (the previous step's stages,
+ * Sec. 3.2), solution out. */
+typedef struct irk_newton_opts {
+  double rtol, atol;    /* defaults 1e-8, 0                                         */
+  int maxit;            /* Newton steps, default 20                                 */
+  int linear_maxit;     /* FGMRES iterations per step, default 200                  */
+  int restart;          /* FGMRES restart length, default 30                        */
+  double eta0, eta_max; /* 0.3, 0.9 (both in (0, 1))                                */
+  double ew_gamma;      /* 1 (in (0, 1])                                            */
+  double ew_alpha;      /* (1 + sqrt 5) / 2 (in (1, 2])                             */
+  double ew_threshold;  /* 0.1                                                      */
+  double eta_fixed;     /* 0: Eisenstat--Walker; in (0, 1): this constant forcing    */
+} irk_newton_opts;
+/* history (host, may be NULL): ||G|| before each step and at exit; etas and linear_its
+ * (host, may be NULL): each step's forcing term and FGMRES iterations; all hold at most
+ * history_cap values. */
+typedef struct irk_newton_info {
+  int iterations, converged, linear_iterations;
+  double norm0, norm;   /* ||G(k0)|| and ||G|| at exit                              */
+  double* history;
+  double* etas;
+  int* linear_its;
+  int history_cap;
+  double ms_linear;     /* GPU time of the linear solves                            */
+  double ms_wall;       /* host wall time of the call (returns synchronised)        */
+} irk_newton_info;
+void irk_newton_default_opts(irk_newton_opts* opt);
+/* Returns IRK_OK, IRK_ENOCONV (maxit Newton steps without convergence; k holds the last
+ * iterate) or an error. */
+irk_status irk_ns_newton_solve(irk_mg* h, const double* F, const double* state, const double* g_stages,
+                               double* k, const irk_newton_opts* opt, irk_newton_info* info, void* stream);
+
 /* Adjoint building blocks (transposes of the maps above; used to differentiate a
  * sequence of IRK steps with respect to the forcing, the viscosity and the state).
  * irk_rhs_adjoint: the transpose of (f, state) -> F of irk_rhs: given lam (ABI layout),
@@ -353,7 +418,12 @@ void irk_batch_destroy(irk_batch* b);
  *   kernel 1  residual:      scalar P2 blocks (column index + M + L per entry), B and
  *                            B^T (index + dim values per entry), F and x read, r written;
  *   kernel 2  gather update: local corrections and their slot indices read, x read and
- *                            written, weights read.
+ *                            written, weights read;
+ *   kernel 3  Navier--Stokes element vectors (finest level, Jacobian mode): cell nodes
+ *                            and geometry, stage values and wind once per node, the
+ *                            direction once, element vectors written (FP64);
+ *   kernel 4  Navier--Stokes gather: incidence lists, the element entries of free
+ *                            nodes, y read and written.
  * Values are 8 bytes (FP64 mode) or 4 bytes (FP32 mode), indices 4 bytes. */
 typedef struct irk_kernel_stats {
   int64_t launches;

@@ -90,6 +90,12 @@ void build_topology(HostLevel& L, int dim, int64_t nv, int64_t nc, const double*
 void assemble_level(HostLevel& L, double nu, const std::vector<double>* wind_nodal,
                     bool with_mfa);
 void build_patches(HostLevel& L);
+// Element data of the Navier--Stokes terms: per cell the barycentric gradients
+// ((dim+1) x dim) and the measure; the reference tensor int phi_e phi_a d_lam_k phi_b /
+// |cell| reordered as [a][b][e][k]; int32 cell nodes; per free node the incidences
+// cell * nloc + a (cell order) of its node.
+void ns_cell_data(const HostLevel& L, std::vector<double>& geo, std::vector<double>& T,
+                  std::vector<int32_t>& cell_nodes, std::vector<int32_t>& inc_ptr, std::vector<int32_t>& inc);
 // Returns an empty string on success, else a description of the nesting failure.
 std::string build_transfer(const HostLevel& coarse, HostLevel& fine, const int64_t* parent);
 // Dense coarse operator (row-major N x N, internal layout) with the pressure of vertex 0
@@ -230,7 +236,7 @@ struct DevLevel {
   StageBasis<float> sb32;
 
   // algorithmic bytes per launch of patch apply, residual and gather update
-  double alg_bytes[3] = {0, 0, 0};
+  double alg_bytes[5] = {0, 0, 0, 0, 0};
 
   // work vectors (internal layout) in the working precision
   void *b = nullptr, *x = nullptr, *res = nullptr, *Y = nullptr;
@@ -279,6 +285,13 @@ struct Handle {
   std::vector<ProfEv> prof_pool;
   size_t prof_used = 0;
   hipEvent_t ev0 = nullptr, ev1 = nullptr, ev2 = nullptr, ev3 = nullptr;
+  // Navier--Stokes (Newton) data of the finest level, built at first use
+  std::vector<double> wind_fine;  // host copy of the finest-level wind (empty: none)
+  bool ns_ready = false;
+  bool ns_jac = false;  // FGMRES operator = the Newton Jacobian at ns_U
+  int32_t *ns_cells = nullptr, *ns_free = nullptr, *ns_inc_ptr = nullptr, *ns_inc = nullptr;
+  double *ns_geo = nullptr, *ns_T = nullptr, *ns_w = nullptr, *ns_U = nullptr, *ns_elem = nullptr;
+  double *ns_k = nullptr, *ns_F = nullptr, *ns_G = nullptr;  // Newton iterate, rhs, residual
 };
 
 // ------------------------------------------------------------------------ launchers
@@ -393,6 +406,31 @@ hipError_t update_adjoint(const DevLevel& L, const double* b, double dt, const d
 hipError_t nu_sensitivity(const DevLevel& L, const double* A, double dt, const double* lam, const double* kv,
                           const double* state, double* rowsum, double* partials, double* out, hipStream_t s);
 hipError_t mass_apply(const DevLevel& L, const double* st, double* out, hipStream_t s);
+
+// Navier--Stokes terms (Sec. 3.2), finest level.  dt a_ij (or a_ij) by value.
+struct NsCoef {
+  double a[kMaxStages * kMaxStages];
+};
+struct NsElemArgs {
+  int64_t nc = 0;
+  int r = 0;
+  int mode = 0;                       // 0: c(U - w, U); 1: c(U - w, z) + c(z, U)
+  const int32_t* cell_nodes = nullptr;  // nc x nloc node indices
+  const double* geo = nullptr;        // nc x ((dim+1) dim + 1): grad lam_k, then |cell|
+  const double* T = nullptr;          // [a][b][e][k] int phi_e phi_a d_lam_k phi_b / |cell|
+  const int32_t* free_of_node = nullptr;
+  const double* U = nullptr;          // stage values [node][d][i]
+  const double* w = nullptr;          // wind [node][d] (NULL: none)
+  const double* x = nullptr;          // mode 1: direction, internal layout
+  double a[kMaxStages * kMaxStages] = {0};  // mode 1: a_ij
+  double* elem = nullptr;             // out: [cell][a][d][i]
+};
+hipError_t ns_stage_values(int64_t nn, int dim, int r, int64_t nfree, const int32_t* free_of_node,
+                           const double* state, const double* x, const NsCoef& dtA, const double* g_st,
+                           double* U, hipStream_t s);
+hipError_t ns_element(int dim, const NsElemArgs& a, hipStream_t s);
+hipError_t ns_gather(int64_t nfree, int dim, int r, const int32_t* inc_ptr, const int32_t* inc,
+                     const double* elem, double scale, double* y, hipStream_t s);
 }  // namespace k
 
 }  // namespace irk

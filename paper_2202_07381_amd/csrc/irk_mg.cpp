@@ -6,6 +6,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <chrono>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -312,6 +313,76 @@ irk_status precondition(irk_mg* h, const double* v, double* z, bool tr, hipStrea
   return IRK_OK;
 }
 
+// ------------------------------------------------------- Navier--Stokes (Sec. 3.2)
+// Element data, the wind and the Newton work vectors of the finest level, on first use.
+irk_status ns_init(irk_mg* h, hipStream_t s) {
+  if (h->ns_ready) return IRK_OK;
+  HostLevel& H = h->host[h->nlevels - 1];
+  DevLevel& L = h->dev[h->nlevels - 1];
+  std::vector<double> geo, T;
+  std::vector<int32_t> cn, ip, inc;
+  ns_cell_data(H, geo, T, cn, ip, inc);
+  CHK(upload(h, &h->ns_geo, geo, s));
+  CHK(upload(h, &h->ns_T, T, s));
+  CHK(upload(h, &h->ns_cells, cn, s));
+  CHK(upload(h, &h->ns_inc_ptr, ip, s));
+  CHK(upload(h, &h->ns_inc, inc, s));
+  CHK(upload(h, &h->ns_free, H.free_of_node, s));
+  if (!h->wind_fine.empty()) CHK(upload(h, &h->ns_w, h->wind_fine, s));
+  const int d = h->dim, r = h->r, nl = d == 2 ? 6 : 10;
+  CHK(dalloc(h, &h->ns_U, (size_t)H.nn * d * r));
+  CHK(dalloc(h, &h->ns_elem, (size_t)H.nc * nl * d * r));
+  CHK(dalloc(h, &h->ns_k, (size_t)L.N));
+  CHK(dalloc(h, &h->ns_F, (size_t)L.N));
+  CHK(dalloc(h, &h->ns_G, (size_t)L.N));
+  HIPCHK(hipStreamSynchronize(s));
+  // algorithmic bytes of one Jacobian-mode launch: cell nodes and geometry, stage values
+  // and wind once per node, the direction once, element vectors written; the gather reads
+  // the incidences and element entries of free nodes and updates y
+  const double nc = (double)H.nc, nn = (double)H.nn, nf = (double)H.nfree;
+  L.alg_bytes[3] = nc * nl * 4 + nc * ((d + 1) * d + 1) * 8 + nn * 4 + nn * d * r * 8 +
+                   (h->ns_w ? nn * d * 8 : 0) + nf * d * r * 8 + nc * nl * d * r * 8;
+  L.alg_bytes[4] = nf * 4 + (double)inc.size() * 4 + (double)inc.size() * d * r * 8 + 2 * nf * d * r * 8;
+  h->ns_ready = true;
+  return IRK_OK;
+}
+
+// ns_U from the state (free velocities, stage-block layout), k (internal) and the stage
+// boundary data (r x nnodes x dim, or NULL: zero)
+irk_status ns_stage_values(irk_mg* h, const double* state, const double* k_int, const double* g_st, hipStream_t s) {
+  HostLevel& H = h->host[h->nlevels - 1];
+  k::NsCoef c;
+  for (int i = 0; i < h->r * h->r; ++i) c.a[i] = h->dt * h->A[i];
+  HIPCHK(k::ns_stage_values(H.nn, h->dim, h->r, H.nfree, h->ns_free, state, k_int, c, g_st, h->ns_U, s));
+  return IRK_OK;
+}
+
+// y += scale * (mode 0: c(U - w, U); mode 1: c(U - w, z) + c(z, U), z_i = sum_j a_ij x_j)
+irk_status ns_correction(irk_mg* h, int mode, const double* x, double* y, double scale, hipStream_t s) {
+  HostLevel& H = h->host[h->nlevels - 1];
+  const int lf = h->nlevels - 1;
+  k::NsElemArgs a;
+  a.nc = H.nc;
+  a.r = h->r;
+  a.mode = mode;
+  a.cell_nodes = h->ns_cells;
+  a.geo = h->ns_geo;
+  a.T = h->ns_T;
+  a.free_of_node = h->ns_free;
+  a.U = h->ns_U;
+  a.w = h->ns_w;
+  a.x = x;
+  for (int i = 0; i < h->r * h->r; ++i) a.a[i] = h->A[i];
+  a.elem = h->ns_elem;
+  const int p0 = prof_begin(h, 3, lf, s);
+  HIPCHK(k::ns_element(h->dim, a, s));
+  prof_end(h, p0, s);
+  const int p1 = prof_begin(h, 4, lf, s);
+  HIPCHK(k::ns_gather(H.nfree, h->dim, h->r, h->ns_inc_ptr, h->ns_inc, h->ns_elem, scale, y, s));
+  prof_end(h, p1, s);
+  return IRK_OK;
+}
+
 irk_status apply_J(irk_mg* h, const double* x, double* y, bool tr, const double* F, hipStream_t s) {
   DevLevel& L = h->dev[h->nlevels - 1];
   DevOps<double> o = L.d64;
@@ -320,6 +391,8 @@ irk_status apply_J(irk_mg* h, const double* x, double* y, bool tr, const double*
     o.u_L = o.u_Lt;
   }
   HIPCHK(k::residual<double>(L, o, tr ? h->At : h->A, h->dt, F, x, y, s));
+  // Newton mode: the operator is the Jacobian of the Navier--Stokes stage equations
+  if (h->ns_jac && !tr) CHK(ns_correction(h, 1, x, y, F ? -h->dt : h->dt, s));
   return IRK_OK;
 }
 
@@ -339,17 +412,13 @@ irk_status ensure_krylov(irk_mg* h, int restart) {
   return IRK_OK;
 }
 
-irk_status fgmres(irk_mg* h, const double* F_abi, double* k_abi, double rtol, int maxit, int restart,
-                  irk_solve_info* info, bool tr, hipStream_t s) {
-  if (!F_abi || !k_abi) return fail(IRK_EINVAL, "null vector");
-  if (!(rtol > 0) || maxit < 1 || restart < 1 || restart > 1000)
-    return fail(IRK_EINVAL, "rtol must be > 0, maxit >= 1, 1 <= restart <= 1000");
-  CHK(ensure_krylov(h, restart));
+// FGMRES on the finest level in the internal layout: solves J x = kF starting from the x
+// held in kx and leaves the solution in kx (and, when k_abi is given, in k_abi).  The
+// caller records ev0 and fills kF, kx; the Krylov workspace must hold `restart` vectors.
+irk_status fgmres_int(irk_mg* h, double* k_abi, double rtol, int maxit, int restart, irk_solve_info* info,
+                      bool tr, hipStream_t s) {
   DevLevel& L = h->dev[h->nlevels - 1];
   const int64_t N = L.N;
-  HIPCHK(hipEventRecord(h->ev0, s));
-  HIPCHK(k::to_internal<double>(L, F_abi, h->kF, s));
-  HIPCHK(k::to_internal<double>(L, k_abi, h->kx, s));
   double* H = nullptr;
   std::vector<double> Hm((size_t)(restart + 1) * restart), cs(restart), sn(restart), g(restart + 1),
       y(restart), hcol(restart + 2);
@@ -434,7 +503,7 @@ irk_status fgmres(irk_mg* h, const double* F_abi, double* k_abi, double rtol, in
   HIPCHK(k::dot(h->kr, h->kr, N, h->partials, h->scal, s, 1));
   double fin;
   CHK(host_scalar(h->scal, &fin));
-  HIPCHK(k::to_abi<double>(L, h->kx, k_abi, s));
+  if (k_abi) HIPCHK(k::to_abi<double>(L, h->kx, k_abi, s));
   HIPCHK(hipEventRecord(h->ev1, s));
   HIPCHK(hipEventSynchronize(h->ev1));
   float ms_t = 0;
@@ -452,6 +521,19 @@ irk_status fgmres(irk_mg* h, const double* F_abi, double* k_abi, double rtol, in
     return IRK_ENOCONV;
   }
   return IRK_OK;
+}
+
+irk_status fgmres(irk_mg* h, const double* F_abi, double* k_abi, double rtol, int maxit, int restart,
+                  irk_solve_info* info, bool tr, hipStream_t s) {
+  if (!F_abi || !k_abi) return fail(IRK_EINVAL, "null vector");
+  if (!(rtol > 0) || maxit < 1 || restart < 1 || restart > 1000)
+    return fail(IRK_EINVAL, "rtol must be > 0, maxit >= 1, 1 <= restart <= 1000");
+  CHK(ensure_krylov(h, restart));
+  DevLevel& L = h->dev[h->nlevels - 1];
+  HIPCHK(hipEventRecord(h->ev0, s));
+  HIPCHK(k::to_internal<double>(L, F_abi, h->kF, s));
+  HIPCHK(k::to_internal<double>(L, k_abi, h->kx, s));
+  return fgmres_int(h, k_abi, rtol, maxit, restart, info, tr, s);
 }
 
 irk_status check_handle(irk_mg* h) {
@@ -635,7 +717,7 @@ irk_status irk_mg_profile(irk_mg* h, int enable) {
 
 irk_status irk_mg_kernel_stats(irk_mg* h, int kernel, int level, irk_kernel_stats* out) {
   CHK(check_level(h, level));
-  if (!out || kernel < 0 || kernel > 2) return fail(IRK_EINVAL, "kernel must be 0, 1 or 2 and out non-NULL");
+  if (!out || kernel < 0 || kernel > 4) return fail(IRK_EINVAL, "kernel must be 0..4 and out non-NULL");
   out->launches = 0;
   out->ms_total = 0;
   out->bytes_per_launch = h->dev[level].alg_bytes[kernel];
@@ -868,6 +950,7 @@ static irk_status setup_impl(const irk_mesh_level* lv, int nlevels, const irk_ta
     }
     for (double w : winds[nlevels - 1])
       if (!std::isfinite(w)) return fail(IRK_EINVAL, "non-finite wind value");
+    h->wind_fine = winds[nlevels - 1];
   }
   for (int l = 0; l < nlevels; ++l) {
     assemble_level(h->host[l], nu, wind ? &winds[l] : nullptr, l == nlevels - 1);
@@ -1387,6 +1470,155 @@ irk_status irk_fgmres_solve(irk_mg* h, const double* F, double* k, double rtol, 
                             irk_solve_info* info, void* stream) {
   CHK(check_handle(h));
   return fgmres(h, F, k, rtol, maxit, restart, info, false, S(stream));
+}
+
+void irk_newton_default_opts(irk_newton_opts* o) {
+  if (!o) return;
+  o->rtol = 1e-8;
+  o->atol = 0.0;
+  o->maxit = 20;
+  o->linear_maxit = 200;
+  o->restart = 30;
+  o->eta0 = 0.3;
+  o->eta_max = 0.9;
+  o->ew_gamma = 1.0;
+  o->ew_alpha = 0.5 * (1.0 + std::sqrt(5.0));
+  o->ew_threshold = 0.1;
+  o->eta_fixed = 0.0;
+}
+
+// R = F - J k - c(U - w, U): minus the residual of the stage equations of Sec. 3.2 (F
+// from irk_rhs on this handle), into ns_G; state and g_st as in the public calls.
+static irk_status ns_residual_int(irk_mg* h, const double* state, const double* g_st, hipStream_t s) {
+  CHK(ns_stage_values(h, state, h->ns_k, g_st, s));
+  const bool jac = h->ns_jac;
+  h->ns_jac = false;
+  irk_status st = apply_J(h, h->ns_k, h->ns_G, false, h->ns_F, s);
+  h->ns_jac = jac;
+  CHK(st);
+  CHK(ns_correction(h, 0, nullptr, h->ns_G, -1.0, s));
+  return IRK_OK;
+}
+
+irk_status irk_ns_residual(irk_mg* h, const double* F, const double* state, const double* g_stages,
+                           const double* k, double* R, void* stream) {
+  CHK(check_handle(h));
+  if (!F || !state || !k || !R) return fail(IRK_EINVAL, "null vector");
+  hipStream_t s = S(stream);
+  CHK(ns_init(h, s));
+  DevLevel& L = h->dev[h->nlevels - 1];
+  HIPCHK(k::to_internal<double>(L, k, h->ns_k, s));
+  HIPCHK(k::to_internal<double>(L, F, h->ns_F, s));
+  CHK(ns_residual_int(h, state, g_stages, s));
+  HIPCHK(k::to_abi<double>(L, h->ns_G, R, s));
+  return IRK_OK;
+}
+
+irk_status irk_ns_jacobian_apply(irk_mg* h, const double* state, const double* g_stages, const double* k,
+                                 const double* x, double* y, void* stream) {
+  CHK(check_handle(h));
+  if (!state || !k || !x || !y) return fail(IRK_EINVAL, "null vector");
+  hipStream_t s = S(stream);
+  CHK(ns_init(h, s));
+  DevLevel& L = h->dev[h->nlevels - 1];
+  HIPCHK(k::to_internal<double>(L, k, h->ns_k, s));
+  CHK(ns_stage_values(h, state, h->ns_k, g_stages, s));
+  HIPCHK(k::to_internal<double>(L, x, h->ns_F, s));
+  h->ns_jac = true;
+  irk_status st = apply_J(h, h->ns_F, h->ns_G, false, nullptr, s);
+  h->ns_jac = false;
+  CHK(st);
+  HIPCHK(k::to_abi<double>(L, h->ns_G, y, s));
+  return IRK_OK;
+}
+
+irk_status irk_ns_newton_solve(irk_mg* h, const double* F, const double* state, const double* g_stages,
+                               double* k, const irk_newton_opts* opt, irk_newton_info* info, void* stream) {
+  CHK(check_handle(h));
+  if (!F || !state || !k) return fail(IRK_EINVAL, "null vector");
+  irk_newton_opts o;
+  irk_newton_default_opts(&o);
+  if (opt) o = *opt;
+  if (!(o.rtol >= 0) || !(o.atol >= 0) || o.maxit < 0 || o.linear_maxit < 1 || o.restart < 1 ||
+      o.restart > 1000 || !(o.eta0 > 0 && o.eta0 < 1) || !(o.eta_max > 0 && o.eta_max < 1) ||
+      !(o.ew_gamma > 0 && o.ew_gamma <= 1) || !(o.ew_alpha > 1 && o.ew_alpha <= 2) || !(o.ew_threshold >= 0) ||
+      !(o.eta_fixed >= 0 && o.eta_fixed < 1))
+    return fail(IRK_EINVAL, "invalid Newton options");
+  const auto t0 = std::chrono::steady_clock::now();
+  hipStream_t s = S(stream);
+  CHK(ns_init(h, s));
+  CHK(ensure_krylov(h, o.restart));
+  DevLevel& L = h->dev[h->nlevels - 1];
+  const int64_t N = L.N;
+  HIPCHK(k::to_internal<double>(L, F, h->ns_F, s));
+  HIPCHK(k::to_internal<double>(L, k, h->ns_k, s));
+  int it = 0, lin = 0, nhist = 0;
+  bool converged = false;
+  double norm0 = 0, norm = 0, norm_prev = 0, eta_prev = o.eta0;
+  float ms_lin = 0;
+  irk_status st = IRK_OK;
+  for (;;) {
+    CHK(ns_residual_int(h, state, g_stages, s));
+    HIPCHK(k::dot(h->ns_G, h->ns_G, N, h->partials, h->scal, s, 1));
+    HIPCHK(hipMemcpyAsync(&norm, h->scal, sizeof(double), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    if (info && info->history && nhist < info->history_cap) info->history[nhist] = norm;
+    ++nhist;
+    if (!std::isfinite(norm)) return fail(IRK_ENAN, "non-finite Navier--Stokes residual");
+    if (it == 0) norm0 = norm;
+    if (norm <= std::max(o.atol, o.rtol * norm0)) {
+      converged = true;
+      break;
+    }
+    if (it >= o.maxit) break;
+    // forcing term: Eisenstat--Walker choice 2 with its safeguard, or a fixed value
+    double eta;
+    if (o.eta_fixed > 0) {
+      eta = o.eta_fixed;
+    } else if (it == 0) {
+      eta = std::min(o.eta0, o.eta_max);
+    } else {
+      eta = o.ew_gamma * std::pow(norm / norm_prev, o.ew_alpha);
+      const double guard = o.ew_gamma * std::pow(eta_prev, o.ew_alpha);
+      if (guard > o.ew_threshold) eta = std::max(eta, guard);
+      eta = std::min(eta, o.eta_max);
+    }
+    if (info && it < info->history_cap) {
+      if (info->etas) info->etas[it] = eta;
+    }
+    // J delta = R from delta = 0, to ||R - J delta|| <= eta ||R||
+    HIPCHK(hipMemcpyAsync(h->kF, h->ns_G, (size_t)N * sizeof(double), hipMemcpyDeviceToDevice, s));
+    HIPCHK(k::fill(h->kx, N, 0.0, s));
+    irk_solve_info li{};
+    HIPCHK(hipEventRecord(h->ev0, s));
+    h->ns_jac = true;
+    st = fgmres_int(h, nullptr, eta, o.linear_maxit, o.restart, &li, false, s);
+    h->ns_jac = false;
+    if (st < 0) return st;
+    lin += li.iterations;
+    ms_lin += (float)li.ms_total;
+    if (info && info->linear_its && it < info->history_cap) info->linear_its[it] = li.iterations;
+    HIPCHK(k::axpby(h->ns_k, h->kx, N, 1.0, 1.0, s));
+    eta_prev = eta;
+    norm_prev = norm;
+    ++it;
+  }
+  HIPCHK(k::to_abi<double>(L, h->ns_k, k, s));
+  HIPCHK(hipStreamSynchronize(s));
+  if (info) {
+    info->iterations = it;
+    info->converged = converged ? 1 : 0;
+    info->linear_iterations = lin;
+    info->norm0 = norm0;
+    info->norm = norm;
+    info->ms_linear = ms_lin;
+    info->ms_wall = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+  }
+  if (!converged) {
+    g_err = "Newton reached maxit";
+    return IRK_ENOCONV;
+  }
+  return IRK_OK;
 }
 
 irk_status irk_adjoint_solve(irk_mg* h, const double* G, double* lam, double rtol, int maxit, int restart,

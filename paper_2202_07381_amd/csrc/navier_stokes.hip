@@ -1,0 +1,205 @@
+// Navier--Stokes terms of the stage equations and of their Newton Jacobian (Sec. 3.2)
+// on the finest level, for gfx950.
+//
+// With c(a, b; v) = int ((a . grad) b) . v, the stage equations of Sec. 3.2 add N(U_i) =
+// c(U_i, U_i; .) to the velocity rows of stage i, U_i = u^n + dt sum_j a_ij k_j^u, and
+// the Newton Jacobian adds dt a_ij (c(z, U_i; .) + c(U_i, z; .)) to block (i, j).  The
+// library's own operator is the Kronecker (Oseen) one with the prescribed wind w, so what
+// is computed here is the difference to it:
+//   residual:  c(U_i - w, U_i; .)                        (N(U_i) - C(w) U_i)
+//   Jacobian:  c(U_i - w, z_i; .) + c(z_i, U_i; .),  z_i = sum_j a_ij x_j
+// (C(w) is linear in w, so c(U_i, z) - c(w, z) = c(U_i - w, z)).
+//
+// Two launches, both deterministic (no atomics, so every solve repeats bit for bit):
+//   k_ns_element  one thread per (cell, stage): gathers the cell's nodal fields and
+//                 writes the element vector, vol * sum_{e,k} (a_e . grad lam_k)
+//                 T[a][b][e][k] b_b with T the reference tensor int phi_e phi_a d_k phi_b
+//                 / |cell| (exact: the integrand is a polynomial);
+//   k_ns_gather   one thread per free velocity unknown (internal layout): sums the element
+//                 vectors of the cells around its node in a fixed order, y += scale * sum.
+#include <hip/hip_runtime.h>
+
+#include "irk_internal.h"
+
+namespace irk {
+namespace k {
+namespace {
+
+template <int D>
+struct Elem {
+  static constexpr int NL = D == 2 ? 6 : 10;
+  static constexpr int NB = D + 1;
+};
+
+// out[a][d] += sum_b (sum_{e,k} (A_e . grad lam_k) T[a][b][e][k]) B[b][d]
+template <int D>
+__device__ __forceinline__ void conv_term(const double (&A)[Elem<D>::NL][D], const double (&B)[Elem<D>::NL][D],
+                                          const double (&glam)[D + 1][D], const double* __restrict__ T,
+                                          double (&out)[Elem<D>::NL][D]) {
+  constexpr int NL = Elem<D>::NL, NB = Elem<D>::NB;
+  double wg[NL][NB];
+#pragma unroll
+  for (int e = 0; e < NL; ++e)
+#pragma unroll
+    for (int k = 0; k < NB; ++k) {
+      double s = 0.0;
+#pragma unroll
+      for (int d = 0; d < D; ++d) s += A[e][d] * glam[k][d];
+      wg[e][k] = s;
+    }
+#pragma unroll
+  for (int a = 0; a < NL; ++a) {
+#pragma unroll 2
+    for (int b = 0; b < NL; ++b) {
+      const double* t = T + (a * NL + b) * NL * NB;
+      double s = 0.0;
+#pragma unroll
+      for (int e = 0; e < NL; ++e)
+#pragma unroll
+        for (int k = 0; k < NB; ++k) s += wg[e][k] * t[e * NB + k];
+#pragma unroll
+      for (int d = 0; d < D; ++d) out[a][d] += s * B[b][d];
+    }
+  }
+}
+
+template <int D>
+__global__ __launch_bounds__(256) void k_ns_element(NsElemArgs p) {
+  constexpr int NL = Elem<D>::NL, NB = Elem<D>::NB;
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int r = p.r;
+  if (t >= p.nc * r) return;
+  const int64_t c = t / r;  // consecutive threads: the stages of one cell
+  const int i = (int)(t - c * r);
+  const double* g = p.geo + c * (NB * D + 1);
+  double glam[NB][D];
+#pragma unroll
+  for (int k = 0; k < NB; ++k)
+#pragma unroll
+    for (int d = 0; d < D; ++d) glam[k][d] = g[k * D + d];
+  const double vol = g[NB * D];
+  int node[NL];
+#pragma unroll
+  for (int a = 0; a < NL; ++a) node[a] = p.cell_nodes[c * NL + a];
+  double out[NL][D];
+#pragma unroll
+  for (int a = 0; a < NL; ++a)
+#pragma unroll
+    for (int d = 0; d < D; ++d) out[a][d] = 0.0;
+  // V = U_i - w at the nodes
+  double V[NL][D];
+#pragma unroll
+  for (int a = 0; a < NL; ++a)
+#pragma unroll
+    for (int d = 0; d < D; ++d) {
+      const double u = p.U[((int64_t)node[a] * D + d) * r + i];
+      V[a][d] = p.w ? u - p.w[(int64_t)node[a] * D + d] : u;
+    }
+  if (p.mode == 0) {
+    double U[NL][D];
+#pragma unroll
+    for (int a = 0; a < NL; ++a)
+#pragma unroll
+      for (int d = 0; d < D; ++d) U[a][d] = p.U[((int64_t)node[a] * D + d) * r + i];
+    conv_term<D>(V, U, glam, p.T, out);
+  } else {
+    // z_i = sum_j a_ij x_j at the nodes; prescribed (boundary) nodes do not vary
+    double Z[NL][D];
+#pragma unroll
+    for (int a = 0; a < NL; ++a) {
+      const int f = p.free_of_node[node[a]];
+#pragma unroll
+      for (int d = 0; d < D; ++d) {
+        double s = 0.0;
+        if (f >= 0)
+          for (int j = 0; j < r; ++j) s += p.a[i * r + j] * p.x[((int64_t)f * D + d) * r + j];
+        Z[a][d] = s;
+      }
+    }
+    conv_term<D>(V, Z, glam, p.T, out);
+    double U[NL][D];
+#pragma unroll
+    for (int a = 0; a < NL; ++a)
+#pragma unroll
+      for (int d = 0; d < D; ++d) U[a][d] = p.U[((int64_t)node[a] * D + d) * r + i];
+    conv_term<D>(Z, U, glam, p.T, out);
+  }
+#pragma unroll
+  for (int a = 0; a < NL; ++a)
+#pragma unroll
+    for (int d = 0; d < D; ++d) p.elem[((c * NL + a) * D + d) * r + i] = vol * out[a][d];
+}
+
+// y[t] += scale * sum over the incidences (cell, local node) of free node f of the
+// element entries; t = (f * D + d) * r + i, inc[q] = cell * NL + a.
+__global__ __launch_bounds__(256) void k_ns_gather(int64_t n, int dr, const int32_t* __restrict__ inc_ptr,
+                                                   const int32_t* __restrict__ inc,
+                                                   const double* __restrict__ elem, double scale,
+                                                   double* __restrict__ y) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= n) return;
+  const int64_t f = t / dr;
+  const int rem = (int)(t - f * dr);
+  double s = 0.0;
+  for (int32_t q = inc_ptr[f]; q < inc_ptr[f + 1]; ++q) s += elem[(int64_t)inc[q] * dr + rem];
+  y[t] += scale * s;
+}
+
+// U[(node * D + d) * r + i]: free nodes u^n + dt sum_j a_ij k_j (state in the stage-block
+// layout, k internal), prescribed nodes the stage data (or zero).
+__global__ __launch_bounds__(256) void k_ns_stage_values(int64_t nn, int D, int r, int64_t nfree,
+                                                         const int32_t* __restrict__ free_of_node,
+                                                         const double* __restrict__ state,
+                                                         const double* __restrict__ x, NsCoef dtA,
+                                                         const double* __restrict__ g_st,
+                                                         double* __restrict__ U) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int dr = D * r;
+  if (t >= nn * dr) return;
+  const int64_t node = t / dr;
+  const int rem = (int)(t - node * dr);
+  const int d = rem / r, i = rem - d * r;
+  const int f = free_of_node[node];
+  double v;
+  if (f >= 0) {
+    v = state[(int64_t)d * nfree + f];
+    for (int j = 0; j < r; ++j) v += dtA.a[i * r + j] * x[((int64_t)f * D + d) * r + j];
+  } else {
+    v = g_st ? g_st[((int64_t)i * nn + node) * D + d] : 0.0;
+  }
+  U[t] = v;
+}
+
+inline unsigned blocks_for(int64_t n, int bs) { return (unsigned)((n + bs - 1) / bs); }
+
+}  // namespace
+
+hipError_t ns_stage_values(int64_t nn, int dim, int r, int64_t nfree, const int32_t* free_of_node,
+                           const double* state, const double* x, const NsCoef& dtA, const double* g_st,
+                           double* U, hipStream_t s) {
+  const int64_t n = nn * dim * r;
+  if (n == 0) return hipSuccess;
+  k_ns_stage_values<<<blocks_for(n, 256), 256, 0, s>>>(nn, dim, r, nfree, free_of_node, state, x, dtA, g_st, U);
+  return hipGetLastError();
+}
+
+hipError_t ns_element(int dim, const NsElemArgs& a, hipStream_t s) {
+  const int64_t n = a.nc * a.r;
+  if (n == 0) return hipSuccess;
+  if (dim == 2)
+    k_ns_element<2><<<blocks_for(n, 256), 256, 0, s>>>(a);
+  else
+    k_ns_element<3><<<blocks_for(n, 256), 256, 0, s>>>(a);
+  return hipGetLastError();
+}
+
+hipError_t ns_gather(int64_t nfree, int dim, int r, const int32_t* inc_ptr, const int32_t* inc,
+                     const double* elem, double scale, double* y, hipStream_t s) {
+  const int64_t n = nfree * dim * r;
+  if (n == 0) return hipSuccess;
+  k_ns_gather<<<blocks_for(n, 256), 256, 0, s>>>(n, dim * r, inc_ptr, inc, elem, scale, y);
+  return hipGetLastError();
+}
+
+}  // namespace k
+}  // namespace irk

@@ -65,7 +65,20 @@ class irk_kernel_stats(C.Structure):
     _fields_ = [("launches", C.c_int64), ("ms_total", C.c_double), ("bytes_per_launch", C.c_double)]
 
 
-KERNELS = {"patch_apply": 0, "residual": 1, "gather_update": 2}
+class irk_newton_opts(C.Structure):
+    _fields_ = [("rtol", C.c_double), ("atol", C.c_double), ("maxit", C.c_int), ("linear_maxit", C.c_int),
+                ("restart", C.c_int), ("eta0", C.c_double), ("eta_max", C.c_double), ("ew_gamma", C.c_double),
+                ("ew_alpha", C.c_double), ("ew_threshold", C.c_double), ("eta_fixed", C.c_double)]
+
+
+class irk_newton_info(C.Structure):
+    _fields_ = [("iterations", C.c_int), ("converged", C.c_int), ("linear_iterations", C.c_int),
+                ("norm0", C.c_double), ("norm", C.c_double), ("history", C.POINTER(C.c_double)),
+                ("etas", C.POINTER(C.c_double)), ("linear_its", C.POINTER(C.c_int)), ("history_cap", C.c_int),
+                ("ms_linear", C.c_double), ("ms_wall", C.c_double)]
+
+
+KERNELS = {"patch_apply": 0, "residual": 1, "gather_update": 2, "ns_element": 3, "ns_gather": 4}
 
 
 def _load() -> C.CDLL:
@@ -104,6 +117,10 @@ def _load() -> C.CDLL:
         "irk_update_adjoint": (i, [vp, vp, vp, vp]),
         "irk_nu_sensitivity": (i, [vp, vp, vp, vp, vp, vp]),
         "irk_mass_apply": (i, [vp, vp, vp, vp]),
+        "irk_ns_residual": (i, [vp, vp, vp, vp, vp, vp, vp]),
+        "irk_ns_jacobian_apply": (i, [vp, vp, vp, vp, vp, vp, vp]),
+        "irk_newton_default_opts": (None, [vp]),
+        "irk_ns_newton_solve": (i, [vp, vp, vp, vp, vp, vp, vp, vp]),
         "irk_batch_default_opts": (None, [vp]),
         "irk_batch_create": (i, [vp, i, vp, vp, vp]),
         "irk_batch_fgmres_solve": (i, [vp, vp, vp, d, i, i, vp, vp, vp]),
@@ -337,6 +354,47 @@ class IrkMG:
     def irk_mass_apply(self, state, out, stream=None):
         sz = self.irk_mg_sizes()
         _check(lib.irk_mass_apply(self.h, _dev(state, sz["ns"], "state"), _dev(out, sz["ns"], "out"), _stream(stream)))
+
+    # ------------------------------------------------ Navier--Stokes, Newton
+    def _ns_common(self, state, g_stages):
+        sz = self.irk_mg_sizes()
+        g = None if g_stages is None else _dev(g_stages, self.r * sz["nnodes"] * self.dim, "g_stages")
+        return _dev(state, sz["ns"], "state"), g
+
+    def irk_ns_residual(self, F, state, k, R, g_stages=None, stream=None):
+        n = self.irk_mg_ndofs()
+        st, g = self._ns_common(state, g_stages)
+        _check(lib.irk_ns_residual(self.h, _dev(F, n, "F"), st, g, _dev(k, n, "k"), _dev(R, n, "R"),
+                                   _stream(stream)))
+
+    def irk_ns_jacobian_apply(self, state, k, x, y, g_stages=None, stream=None):
+        n = self.irk_mg_ndofs()
+        st, g = self._ns_common(state, g_stages)
+        _check(lib.irk_ns_jacobian_apply(self.h, st, g, _dev(k, n, "k"), _dev(x, n, "x"), _dev(y, n, "y"),
+                                         _stream(stream)))
+
+    def irk_ns_newton_solve(self, F, state, k, g_stages=None, history_cap=64, stream=None, **opts):
+        """Newton on the Navier--Stokes stage equations; opts: fields of irk_newton_opts."""
+        n = self.irk_mg_ndofs()
+        st, g = self._ns_common(state, g_stages)
+        o = irk_newton_opts()
+        lib.irk_newton_default_opts(C.byref(o))
+        for key, val in opts.items():
+            if key not in dict(irk_newton_opts._fields_):
+                raise TypeError(f"unknown Newton option {key}")
+            setattr(o, key, val)
+        cap = max(1, history_cap)
+        hist, etas, lits = np.zeros(cap), np.zeros(cap), np.zeros(cap, dtype=np.int32)
+        info = irk_newton_info(0, 0, 0, 0.0, 0.0, hist.ctypes.data_as(C.POINTER(C.c_double)),
+                               etas.ctypes.data_as(C.POINTER(C.c_double)), lits.ctypes.data_as(C.POINTER(C.c_int)),
+                               cap, 0.0, 0.0)
+        status = _check(lib.irk_ns_newton_solve(self.h, _dev(F, n, "F"), st, g, _dev(k, n, "k"), C.byref(o),
+                                                C.byref(info), _stream(stream)), ok=(IRK_OK, IRK_ENOCONV))
+        its = info.iterations
+        return dict(status=status, iterations=its, converged=bool(info.converged),
+                    linear_iterations=info.linear_iterations, norm0=info.norm0, norm=info.norm,
+                    history=hist[: min(cap, its + 1)].copy(), etas=etas[: min(cap, its)].copy(),
+                    linear_its=lits[: min(cap, its)].copy(), ms_linear=info.ms_linear, ms_wall=info.ms_wall)
 
     # ---------------------------------------------------------- measurement
     def irk_mg_profile(self, mode):

@@ -1,0 +1,238 @@
+"""GPU parity of the Navier--Stokes stage equations and of Newton's method (Sec. 3.2)
+against the CPU oracle (oracle/navier_stokes.py), through the C ABI.
+
+Tolerances: residual and Jacobian action 1e-12 relative to the largest entry (the same
+FP64 sums in another order); Newton solutions 1e-8 relative (the GPU stops at
+||G|| <= 1e-11 ||G(k0)|| with inexact FGMRES steps, the oracle at 1e-13 with exact
+solves; the stage Jacobian's condition number at these sizes keeps the error of either
+below that bound); time stepping 1e-8 after three steps.  The Eisenstat--Walker
+forcing terms the library chose are recomputed from its residual history with the
+oracle's formula (1e-14)."""
+import ctypes as C
+
+import numpy as np
+import pytest
+
+from gpu_cases import CASES, gpu_of, levels_of, oracle_of, relerr, say, to_dev, to_host
+from oracle.fem import TaylorHood
+from oracle.navier_stokes import EWParams, NavierStokesStages, ew_forcing
+from paper_2202_07381_amd import workloads as wl
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+NS_CASES = ["c1", "oseen", "lob3", "3d2"]
+
+
+def _ns_oracle(case):
+    S = oracle_of(case).finest
+    return NavierStokesStages(S.th, S.A, S.dt, S.nu), S
+
+
+def _smooth_field(th, seed, amp):
+    """A smooth velocity field at every P2 node: (nnodes, dim)."""
+    f = wl.forcing_2d(seed) if th.dim == 2 else wl.forcing_3d(seed)
+    return amp * f(th.node_xyz, 0.0)
+
+
+def _inputs(case, seed, bnd=False, amp_u=1.0, amp_f=1.0):
+    """State (free velocities + pressure), stage forcing (r, nnodes, dim) and optional
+    stage boundary data, all host arrays."""
+    ns, S = _ns_oracle(case)
+    th = S.th
+    u_nod = _smooth_field(th, seed, amp_u)
+    state = np.concatenate([th.free_velocity(u_nod), np.zeros(th.nverts)])
+    fst = np.stack([_smooth_field(th, seed + 1, amp_f) * (1.0 + 0.1 * i) for i in range(S.r)])
+    gn = gst = None
+    if bnd:
+        gn = _smooth_field(th, seed + 2, 0.3)
+        gst = np.stack([gn * (1.0 + 0.05 * (i + 1)) for i in range(S.r)])
+    return ns, S, state, fst, gn, gst
+
+
+def _gpu_rhs(g, fst, state, gn=None, gst=None):
+    F = torch.zeros(g.irk_mg_ndofs(), dtype=torch.float64, device="cuda")
+    g.irk_rhs(to_dev(fst.reshape(-1)), to_dev(state), F)
+    if gst is not None:
+        g.irk_rhs_dirichlet(to_dev(gn.reshape(-1)), to_dev(gst.reshape(-1)), F)
+    return F
+
+
+def _oracle_rhs(S, fst, state, gn=None, gst=None):
+    th = S.th
+    nv = th.nvel
+    F = S.rhs(list(fst), state[:nv], state[nv:])
+    if gst is not None:
+        F = F + S.rhs_dirichlet(gn, list(gst))
+    return F
+
+
+def _stokes(ns):
+    return ns.S  # the oracle's Stokes stage system (no wind)
+
+
+@pytest.mark.parametrize("case,bnd", [("c1", False), ("oseen", False), ("oseen", True), ("lob3", True),
+                                      ("3d2", False)])
+def test_ns_residual_matches_oracle(case, bnd):
+    g = gpu_of(case)
+    ns, S, state, fst, gn, gst = _inputs(case, 11, bnd)
+    rng = np.random.default_rng(12)
+    k = 0.5 * rng.standard_normal(S.n)
+    say(f"[ns-residual] case={case} bnd={bnd}")
+    F = _gpu_rhs(g, fst, state, gn, gst)
+    R = torch.empty_like(F)
+    g.irk_ns_residual(F, to_dev(state), to_dev(k), R, g_stages=None if gst is None else to_dev(gst.reshape(-1)))
+    # -G(k) with the Stokes operator and right-hand side: the handle's wind cancels
+    ref = -ns.residual(_oracle_rhs(_stokes(ns), fst, state, gn, gst), state[:S.th.nvel], k, gst)
+    assert relerr(to_host(R), ref) < 1e-12
+    # deterministic: a second evaluation is bitwise equal
+    R2 = torch.empty_like(F)
+    g.irk_ns_residual(F, to_dev(state), to_dev(k), R2, g_stages=None if gst is None else to_dev(gst.reshape(-1)))
+    assert torch.equal(R, R2)
+
+
+@pytest.mark.parametrize("case,bnd", [("c1", False), ("oseen", True), ("lob3", False), ("3d2", True)])
+def test_ns_jacobian_matches_oracle(case, bnd):
+    g = gpu_of(case)
+    ns, S, state, fst, gn, gst = _inputs(case, 13, bnd)
+    rng = np.random.default_rng(14)
+    k = 0.5 * rng.standard_normal(S.n)
+    x = rng.standard_normal(S.n)
+    say(f"[ns-jacobian] case={case} bnd={bnd}")
+    y = torch.empty(S.n, dtype=torch.float64, device="cuda")
+    g.irk_ns_jacobian_apply(to_dev(state), to_dev(k), to_dev(x), y,
+                            g_stages=None if gst is None else to_dev(gst.reshape(-1)))
+    ref = ns.jacobian_apply(state[:S.th.nvel], k, x, gst)
+    assert relerr(to_host(y), ref) < 1e-12
+
+
+def _newton_pair(case, seed, amp_u, amp_f, bnd=False, **gopts):
+    g = gpu_of(case)
+    ns, S, state, fst, gn, gst = _inputs(case, seed, bnd, amp_u, amp_f)
+    F = _gpu_rhs(g, fst, state, gn, gst)
+    k = torch.zeros(S.n, dtype=torch.float64, device="cuda")
+    say(f"[ns-newton] case={case} seed={seed}")
+    info = g.irk_ns_newton_solve(F, to_dev(state), k, g_stages=None if gst is None else to_dev(gst.reshape(-1)),
+                                 **gopts)
+    Fo = _oracle_rhs(_stokes(ns), fst, state, gn, gst)
+    ko, oinfo = ns.newton(Fo, state[:S.th.nvel], np.zeros(S.n), gst, rtol=1e-13)
+    return g, ns, S, state, Fo, gst, to_host(k), ko, info, oinfo
+
+
+@pytest.mark.parametrize("case", NS_CASES)
+def test_ns_newton_matches_oracle(case):
+    amp = {"c1": 8.0, "oseen": 1.0, "lob3": 8.0, "3d2": 4.0}[case]
+    g, ns, S, state, Fo, gst, k, ko, info, oinfo = _newton_pair(case, 21, amp, amp, rtol=1e-11)
+    say(f"[ns-newton] its={info['iterations']} lin={info['linear_its'].tolist()} oracle its={oinfo.iterations}")
+    assert info["converged"] and oinfo.converged
+    assert info["iterations"] <= 12
+    pm = S.project_pressure_mean
+    assert relerr(pm(k), pm(ko)) < 1e-8
+    # the library's own residual history ends below its tolerance, and the oracle agrees
+    G = ns.residual(Fo, state[:S.th.nvel], k, gst)
+    assert np.linalg.norm(G) <= 1e-10 * info["norm0"]
+    assert info["history"][0] == pytest.approx(oinfo.norms[0], rel=1e-12)
+
+
+def test_ns_newton_with_boundary_data():
+    g, ns, S, state, Fo, gst, k, ko, info, oinfo = _newton_pair("oseen", 23, 1.0, 1.0, bnd=True, rtol=1e-11)
+    assert info["converged"]
+    pm = S.project_pressure_mean
+    assert relerr(pm(k), pm(ko)) < 1e-8
+
+
+def test_ns_newton_eisenstat_walker_terms():
+    g, ns, S, state, Fo, gst, k, ko, info, oinfo = _newton_pair("c1", 25, 12.0, 12.0, rtol=1e-11)
+    fst = _inputs("c1", 25, False, 12.0, 12.0)[3]
+    h, etas = info["history"], info["etas"]
+    p = EWParams()
+    assert len(etas) == info["iterations"] >= 2
+    for l in range(len(etas)):
+        ref = ew_forcing(l, h[l], h[l - 1] if l else h[0], etas[l - 1] if l else p.eta0, p)
+        assert etas[l] == pytest.approx(ref, rel=1e-14, abs=0)
+    # a fixed small forcing term (nearly exact steps) takes no more Newton steps
+    k2 = torch.zeros(S.n, dtype=torch.float64, device="cuda")
+    F = _gpu_rhs(g, fst, state)
+    fixed = g.irk_ns_newton_solve(F, to_dev(state), k2, rtol=1e-11, eta_fixed=1e-6)
+    assert fixed["converged"] and fixed["iterations"] <= info["iterations"]
+    assert relerr(S.project_pressure_mean(to_host(k2)), S.project_pressure_mean(ko)) < 1e-8
+
+
+def test_ns_newton_independent_of_preconditioner_wind():
+    # the same nonlinear problem on a Stokes handle and on an Oseen handle (wind w):
+    # different preconditioners, the same solution
+    from paper_2202_07381_amd import irkmg
+
+    dim, nc, nl, fam, r, dt, nu, ws = CASES["oseen"]
+    lv = levels_of("oseen")
+    A, b, c = irkmg.irk_tableau_builtin(fam, r)
+    say("[ns-wind] setting up a Stokes handle for the oseen mesh")
+    gs = irkmg.IrkMG(lv, A, b, c, dt, nu)
+    go = gpu_of("oseen")
+    ns, S, state, fst, gn, gst = _inputs("oseen", 27, False, 1.0, 1.0)
+    sols = []
+    for g in (gs, go):
+        F = _gpu_rhs(g, fst, state)
+        k = torch.zeros(S.n, dtype=torch.float64, device="cuda")
+        info = g.irk_ns_newton_solve(F, to_dev(state), k, rtol=1e-11)
+        assert info["converged"]
+        sols.append(S.project_pressure_mean(to_host(k)))
+    gs.close()
+    assert relerr(sols[0], sols[1]) < 1e-8
+
+
+def test_ns_time_stepping_matches_oracle():
+    # three steps from a smooth state, each from the previous step's stages (Sec. 3.2)
+    case = "c1"
+    g = gpu_of(case)
+    ns, S, state, fst, gn, gst = _inputs(case, 29, False, 6.0, 6.0)
+    th = S.th
+    b = g.b
+    st_g = to_dev(state)
+    st_o = state.copy()
+    kg = torch.zeros(S.n, dtype=torch.float64, device="cuda")
+    ko = np.zeros(S.n)
+    for n in range(3):
+        say(f"[ns-step] step={n}")
+        F = _gpu_rhs(g, fst, to_host(st_g))
+        info = g.irk_ns_newton_solve(F, st_g, kg, rtol=1e-12)
+        assert info["converged"]
+        g.irk_update(kg, st_g)
+        Fo = _oracle_rhs(_stokes(ns), fst, st_o)
+        ko, oinfo = ns.newton(Fo, st_o[:th.nvel], ko, rtol=1e-13)
+        for j in range(S.r):
+            ku, kp = S.split(ko, j)
+            st_o[:th.nvel] += S.dt * b[j] * ku
+            st_o[th.nvel:] += S.dt * b[j] * kp
+    sg = to_host(st_g)
+    assert relerr(sg[:th.nvel], st_o[:th.nvel]) < 1e-8
+
+
+def test_ns_errors_and_kernel_stats():
+    from paper_2202_07381_amd import irkmg
+
+    g = gpu_of("c1")
+    S = oracle_of("c1").finest
+    n = S.n
+    z = torch.zeros(n, dtype=torch.float64, device="cuda")
+    st = torch.zeros(S.ns, dtype=torch.float64, device="cuda")
+    say("[ns-errors] null vectors and options")
+    assert irkmg.lib.irk_ns_residual(g.h, None, st.data_ptr(), None, z.data_ptr(), z.data_ptr(), None) == \
+        irkmg.IRK_EINVAL
+    with pytest.raises(irkmg.IrkError) as e:
+        g.irk_ns_newton_solve(z, st, torch.zeros_like(z), eta_fixed=1.5)
+    assert e.value.status == irkmg.IRK_EINVAL
+    say("[ns-errors] non-finite iterate")
+    kbad = torch.zeros_like(z)
+    kbad[3] = float("nan")
+    with pytest.raises(irkmg.IrkError) as e:
+        g.irk_ns_newton_solve(z + 1.0, st, kbad)
+    assert e.value.status == irkmg.IRK_ENAN
+    say("[ns-errors] kernel stats")
+    g.irk_mg_profile(2)
+    y = torch.empty_like(z)
+    g.irk_ns_jacobian_apply(st, z, z + 1.0, y)
+    s3, s4 = g.irk_mg_kernel_stats("ns_element"), g.irk_mg_kernel_stats("ns_gather")
+    g.irk_mg_profile(0)
+    assert s3["launches"] == 1 and s4["launches"] == 1
+    assert s3["bytes_per_launch"] > 0 and s4["bytes_per_launch"] > 0
