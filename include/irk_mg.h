@@ -292,9 +292,11 @@ irk_status irk_ns_jacobian_apply(irk_mg* h, const double* state, const double* g
  * handle's V-cycle as preconditioner) from delta = 0 to the relative residual eta_l;
  * the forcing terms follow Eisenstat and Walker's choice 2, eta_0 = eta0,
  * eta_l = gamma (||G_l|| / ||G_{l-1}||)^alpha, raised to gamma eta_{l-1}^alpha when that
- * exceeds the threshold, capped at eta_max (the paper names the criterion only; these
- * constants are the defaults below), or eta_fixed when > 0.  Stops at
- * ||G|| <= max(atol, rtol ||G(k0)||).  k: initial guess in (the previous step's stages,
+ * exceeds the threshold, capped at eta_max, and kept at least 0.5 tau / ||G_l|| (a
+ * final-step safeguard against solving the last step far below what the stopping test
+ * needs) with tau = max(atol, rtol ||G(k0)||) (the paper names the criterion only;
+ * these constants are the defaults below); or eta_fixed when > 0.  Stops at
+ * ||G|| <= tau.  k: initial guess in (the previous step's stages,
  * Sec. 3.2), solution out. */
 typedef struct irk_newton_opts {
   double rtol, atol;    /* defaults 1e-8, 0                                         */

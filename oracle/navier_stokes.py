@@ -26,10 +26,13 @@ step's stages k^{n-1} (zero at the first step).  Inexact solves stop at
 ||G + J delta|| <= eta_l ||G|| with the Eisenstat--Walker forcing terms of Sec. 3.2.
 The paper names the criterion but not its variant or constants; the reading taken:
 Eisenstat and Walker's "choice 2", eta_l = gamma (||G_l|| / ||G_{l-1}||)^alpha, kept at
-least gamma eta_{l-1}^alpha when that exceeds a threshold (their safeguard against
-over-solving after a slow step), capped at eta_max, with eta_0 = 0.3, eta_max = 0.9,
-gamma = 1, alpha = (1 + sqrt 5)/2, threshold 0.1.  Newton stops when
-||G|| <= max(atol, rtol ||G(k^0)||).
+least gamma eta_{l-1}^alpha when that exceeds a threshold (their safeguard against a
+too-fast decrease of eta after a slow step), capped at eta_max, with eta_0 = 0.3,
+eta_max = 0.9, gamma = 1, alpha = (1 + sqrt 5)/2, threshold 0.1; and, since a forcing
+term far below what the Newton stopping test still needs only makes the last linear
+solve grind against rounding, never below 0.5 tau / ||G_l|| (the final-step safeguard of
+Kelley's textbook treatment of inexact Newton), tau = max(atol, rtol ||G(k^0)||), the
+tolerance at which Newton stops: ||G|| <= tau.
 
 Pinned by tests/test_oracle_navier_stokes.py against: closed forms of c(a, b) and of
 R(U) z for affine fields (their products are P1, so the integrals equal mass-matrix
@@ -60,15 +63,20 @@ class EWParams:
     threshold: float = 0.1
 
 
-def ew_forcing(it: int, norm: float, norm_prev: float, eta_prev: float, p: EWParams) -> float:
-    """Forcing term eta_it for the linear solve of Newton step `it` (it = 0: eta0)."""
+def ew_forcing(it: int, norm: float, norm_prev: float, eta_prev: float, p: EWParams, tau: float = 0.0) -> float:
+    """Forcing term eta_it for the linear solve of Newton step `it` (it = 0: eta0);
+    tau: the Newton stopping tolerance on ||G|| (0: no final-step safeguard)."""
     if it == 0:
-        return min(p.eta0, p.eta_max)
-    eta = p.gamma * (norm / norm_prev) ** p.alpha
-    guard = p.gamma * eta_prev ** p.alpha
-    if guard > p.threshold:
-        eta = max(eta, guard)
-    return min(eta, p.eta_max)
+        eta = min(p.eta0, p.eta_max)
+    else:
+        eta = p.gamma * (norm / norm_prev) ** p.alpha
+        guard = p.gamma * eta_prev ** p.alpha
+        if guard > p.threshold:
+            eta = max(eta, guard)
+        eta = min(eta, p.eta_max)
+    if tau > 0.0:
+        eta = min(p.eta_max, max(eta, 0.5 * tau / norm))
+    return eta
 
 
 @dataclass
@@ -226,7 +234,7 @@ class NavierStokesStages:
                 break
             if info.iterations >= maxit:
                 break
-            eta = ew_forcing(info.iterations, norm, norm_prev, eta_prev, ew)
+            eta = ew_forcing(info.iterations, norm, norm_prev, eta_prev, ew, max(atol, rtol * norm0))
             delta, lits = solve(self.jacobian(u_n, k, g_stages), -G, eta)
             k = k + delta
             info.etas.append(eta)

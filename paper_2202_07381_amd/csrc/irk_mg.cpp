@@ -1566,7 +1566,8 @@ irk_status irk_ns_newton_solve(irk_mg* h, const double* F, const double* state, 
     ++nhist;
     if (!std::isfinite(norm)) return fail(IRK_ENAN, "non-finite Navier--Stokes residual");
     if (it == 0) norm0 = norm;
-    if (norm <= std::max(o.atol, o.rtol * norm0)) {
+    const double tol = std::max(o.atol, o.rtol * norm0);
+    if (norm <= tol) {
       converged = true;
       break;
     }
@@ -1583,6 +1584,8 @@ irk_status irk_ns_newton_solve(irk_mg* h, const double* F, const double* state, 
       if (guard > o.ew_threshold) eta = std::max(eta, guard);
       eta = std::min(eta, o.eta_max);
     }
+    // final-step safeguard: no forcing term below half the stopping tolerance over ||G||
+    if (o.eta_fixed <= 0 && tol > 0) eta = std::min(o.eta_max, std::max(eta, 0.5 * tol / norm));
     if (info && it < info->history_cap) {
       if (info->etas) info->etas[it] = eta;
     }

@@ -148,7 +148,7 @@ def test_ns_newton_eisenstat_walker_terms():
     p = EWParams()
     assert len(etas) == info["iterations"] >= 2
     for l in range(len(etas)):
-        ref = ew_forcing(l, h[l], h[l - 1] if l else h[0], etas[l - 1] if l else p.eta0, p)
+        ref = ew_forcing(l, h[l], h[l - 1] if l else h[0], etas[l - 1] if l else p.eta0, p, tau=1e-11 * h[0])
         assert etas[l] == pytest.approx(ref, rel=1e-14, abs=0)
     # a fixed small forcing term (nearly exact steps) takes no more Newton steps
     k2 = torch.zeros(S.n, dtype=torch.float64, device="cuda")

@@ -105,6 +105,10 @@ def test_ew_forcing():
     assert ew_forcing(2, 1e-4, 1e-2, 0.05, p) == pytest.approx(0.01 ** p.alpha)
     # a stalled step is capped at eta_max
     assert ew_forcing(1, 2.0, 1.0, 0.3, p) == p.eta_max
+    # final-step safeguard: never below half the stopping tolerance over the residual
+    assert ew_forcing(2, 1e-4, 1e-2, 0.05, p, tau=1e-5) == pytest.approx(0.05)
+    assert ew_forcing(2, 1e-4, 1e-2, 0.05, p, tau=1e-9) == pytest.approx(0.01 ** p.alpha)
+    assert ew_forcing(2, 1e-4, 1e-2, 0.05, p, tau=1.0) == p.eta_max
 
 
 def _problem(S, th, seed=7, amp=20.0):
