@@ -573,39 +573,49 @@ def ns_element_flops(dim, r, ncells):
     return 2.0 * fma * ncells * r
 
 
-def run_ns(n, nsteps, smoother):
+def run_ns(n, nsteps, smoother, precond="oseen", dt=1.0 / 400, dim=2):
     """Navier--Stokes time stepping (Sec. 3.2): Newton with Eisenstat--Walker forcing,
     FGMRES preconditioned by the V-cycle of the Oseen operator linearised at the initial
-    state (set up once, kept for every step), 2D n x n, RadauIIA(3), nu = 0.01 (Re = 100
-    for unit speed and length), dt = 1/400 (the paper's cylinder run), a unit-speed
-    divergence-free initial state and a smooth body force, all synthetic."""
+    state (precond "oseen"; set up once, kept for every step) or of the Stokes operator
+    ("stokes"), 2D n x n, RadauIIA(3), nu = 0.01 (Re = 100 for unit speed and length),
+    dt = 1/400 (the paper's cylinder run), a unit-speed divergence-free initial state and a
+    smooth body force, all synthetic.  dim = 3: the n^3 cube (Kuhn tetrahedra), RadauIIA(2),
+    initial state and force from the 3D forcing modes."""
     import numpy as np
     import torch
 
     from paper_2202_07381_amd import irkmg
     from paper_2202_07381_amd import workloads as wl
 
-    fam, r, dt, nu = "radauIIA", 3, 1.0 / 400, 0.01
-    levels = wl.square_hierarchy(4, int(round(np.log2(n // 4))) + 1)
+    fam, r, nu = "radauIIA", 3 if dim == 2 else 2, 0.01
+    if dim == 2:
+        levels = wl.square_hierarchy(4, int(round(np.log2(n // 4))) + 1)
+    else:
+        levels = wl.cube_hierarchy(2, int(round(np.log2(n // 2))) + 1)
     A, b, c = irkmg.irk_tableau_builtin(fam, r)
     nodes = irkmg.irk_mesh_p2_nodes(levels[-1])
-    u0 = wl.wind_2d(3, n)(nodes)
+    if dim == 2:
+        u0 = wl.wind_2d(3, n)(nodes)
+    else:
+        u0 = wl.forcing_3d(4)(nodes, 0.0)
+        u0 /= np.abs(u0).max()
     kw = {"sweep": dict(smoother=0), "chebyshev": dict(smoother=1, weighting=0, interval=(1.5, 8.0)),
           "gmres": dict(smoother=2)}[smoother]
     t0 = time.time()
-    g = irkmg.IrkMG(levels, A, b, c, dt, nu, wind_nodal=u0, **kw)
+    g = irkmg.IrkMG(levels, A, b, c, dt, nu, wind_nodal=u0 if precond == "oseen" else None, **kw)
     torch.cuda.synchronize()
     setup_s = time.time() - t0
+    form = g.irk_mg_patch_form()
     sz = g.irk_mg_sizes()
     N = g.irk_mg_ndofs()
     free = g.irk_mg_p2_nodes()[1]
     state = torch.zeros(sz["ns"], dtype=torch.float64, device="cuda")
-    state[: 2 * sz["nfree"]] = torch.tensor(np.concatenate([u0[free, 0], u0[free, 1]]), device="cuda")
-    f = wl.forcing_2d(3)
+    state[: dim * sz["nfree"]] = torch.tensor(np.concatenate([u0[free, d] for d in range(dim)]), device="cuda")
+    f = wl.forcing_2d(3) if dim == 2 else wl.forcing_3d(3)
     fst = torch.tensor(np.stack([f(nodes)] * r).ravel(), device="cuda")
     k = torch.zeros(N, dtype=torch.float64, device="cuda")
     F = torch.zeros_like(k)
-    log(f"ns {n}x{n}: N={N} setup {setup_s:.1f} s")
+    log(f"ns {n}^{dim}: N={N} setup {setup_s:.1f} s")
     steps = []
     for it in range(nsteps):
         if it == 1:
@@ -620,20 +630,29 @@ def run_ns(n, nsteps, smoother):
         steps.append({"newton": info["iterations"], "linear": info["linear_its"].tolist(), "ms": ms,
                       "converged": info["converged"]})
         log(f"ns step {it}: newton {info['iterations']} linear {info['linear_its'].tolist()} {ms:.1f} ms")
-    se, sg = g.irk_mg_kernel_stats("ns_element"), g.irk_mg_kernel_stats("ns_gather")
     pa = g.irk_mg_kernel_stats("patch_apply")
+    # the element kernel and its gather in Jacobian mode alone (the residual mode does one
+    # of the two tensor contractions): 20 Jacobian actions at the last iterate
+    g.irk_mg_profile(2)
+    x = torch.ones_like(k)
+    y = torch.empty_like(k)
+    for _ in range(20):
+        g.irk_ns_jacobian_apply(state, k, x, y)
+    se, sg = g.irk_mg_kernel_stats("ns_element"), g.irk_mg_kernel_stats("ns_gather")
     g.irk_mg_profile(0)
     e_ms = se["ms_total"] / max(1, se["launches"])
     gat_ms = sg["ms_total"] / max(1, sg["launches"])
     ncells = levels[-1].cells.shape[0]
-    flops = ns_element_flops(2, r, ncells)
+    flops = ns_element_flops(dim, r, ncells)
     g.close()
     t = steps[1:] if len(steps) > 1 else steps
     return {"metric": "Navier--Stokes IRK time step (Newton-Krylov-multigrid)", "unit": "ms / step",
             "value": float(np.mean([s["ms"] for s in t])), "higher_is_better": False, "n_gpus": 1,
             "dtype": "f64", "data": "synthetic",
-            "config": {"workload": f"2D Navier-Stokes {n}x{n} RadauIIA(3) nu=0.01 dt=1/400, relaxation {smoother}, "
-                                   "preconditioner linearised at the initial state, Newton to 1e-8"},
+            "config": {"workload": f"{dim}D Navier-Stokes {n}^{dim} RadauIIA({r}) nu=0.01 dt={dt:g}, relaxation {smoother}, "
+                                   f"{precond} preconditioner (Oseen: linearised at the initial state), "
+                                   "Newton to 1e-8"},
+            "patch_form": form,
             "setup_s": setup_s, "steps": steps,
             "newton_per_step": float(np.mean([s["newton"] for s in t])),
             "linear_per_step": float(np.mean([sum(s["linear"]) for s in t])),
@@ -662,6 +681,10 @@ def main():
     ap.add_argument("--ns-n", type=int, default=256, help="ns: finest mesh size")
     ap.add_argument("--ns-steps", type=int, default=6, help="ns: time steps")
     ap.add_argument("--ns-relax", default="sweep", choices=["sweep", "chebyshev", "gmres"], help="ns: relaxation")
+    ap.add_argument("--ns-dim", type=int, default=2, choices=[2, 3], help="ns: 2 (square) or 3 (cube)")
+    ap.add_argument("--ns-dt", type=float, default=1.0 / 400, help="ns: time step (default the cylinder run's 1/400)")
+    ap.add_argument("--ns-precond", default="oseen", choices=["oseen", "stokes"],
+                    help="ns: operator of the V-cycle (Oseen at the initial state, or Stokes)")
     ap.add_argument("--relax-n", type=int, default=512, help="relax: finest mesh size of the Oseen problem")
     ap.add_argument("--batch-count", type=int, default=64)
     ap.add_argument("--t1-level", type=int, default=5, help="t1: refinement level l of the crossed 8x8 mesh")
@@ -698,7 +721,8 @@ def main():
         print(json.dumps(run_relax(args.relax_n)), flush=True)
         return
     if args.workload == "ns":
-        print(json.dumps(run_ns(args.ns_n, args.ns_steps, args.ns_relax)), flush=True)
+        print(json.dumps(run_ns(args.ns_n, args.ns_steps, args.ns_relax, args.ns_precond, args.ns_dt, args.ns_dim)),
+              flush=True)
         return
     if args.workload == "t1":
         print(json.dumps(run_t1(args.t1_level, args.t1_stages, 1 if args.t1_fp32 else 0, args.t1_max_steps,

@@ -11,7 +11,7 @@ operator, Runge--Kutta tableau or linear algebra.
 Meshes follow Sec. 4.1 of the paper (hierarchies from uniform refinement of a
 coarsest grid).  The 2D mesh splits every quad along the diagonal from its
 lower-right to its upper-left corner, the orientation drawn in Fig. 1; the 3D mesh
-is the Kuhn split of each cube into 6 tetrahedra ("the usual way", Sec. 5.4).
+is the Kuhn split of each cube into 6 tetrahedra (Sec. 5.4 cuts hexahedra into six).
 Both families are nested: the mesh at 2n is the red refinement of the mesh at n.
 """
 from __future__ import annotations

@@ -181,6 +181,20 @@ def test_ns_newton_independent_of_preconditioner_wind():
     assert relerr(sols[0], sols[1]) < 1e-8
 
 
+def test_ns_newton_with_fp32_preconditioner():
+    # FP32 patch factors and V-cycle inside the FP64 Newton-Krylov iteration: the same
+    # solution (the preconditioner does not enter the converged result)
+    g = gpu_of("c1", precision=1)
+    ns, S, state, fst, gn, gst = _inputs("c1", 31, False, 8.0, 8.0)
+    F = _gpu_rhs(g, fst, state)
+    k = torch.zeros(S.n, dtype=torch.float64, device="cuda")
+    say("[ns-fp32] newton with an FP32 V-cycle")
+    info = g.irk_ns_newton_solve(F, to_dev(state), k, rtol=1e-11)
+    assert info["converged"]
+    ko, _ = ns.newton(_oracle_rhs(_stokes(ns), fst, state), state[:S.th.nvel], np.zeros(S.n), rtol=1e-13)
+    assert relerr(S.project_pressure_mean(to_host(k)), S.project_pressure_mean(ko)) < 1e-8
+
+
 def test_ns_time_stepping_matches_oracle():
     # three steps from a smooth state, each from the previous step's stages (Sec. 3.2)
     case = "c1"
