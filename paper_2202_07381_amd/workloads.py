@@ -293,6 +293,48 @@ class StreamMMS:
         return -self.velocity(pts, t) - self.nu * self.laplacian(pts, t)
 
 
+@dataclass
+class StreamMMSInertial(StreamMMS):
+    """The same velocity and pressure (p = 0) as an exact solution of the Navier--Stokes
+    equations: f = u_t + (u . grad) u - nu Laplacian(u), with (u . grad) u written out
+    from the stream function (u = (psi_y, -psi_x))."""
+
+    amp: float = 1.0
+
+    def velocity(self, pts: np.ndarray, t: float) -> np.ndarray:
+        return self.amp * super().velocity(pts, t)
+
+    def laplacian(self, pts: np.ndarray, t: float) -> np.ndarray:
+        return self.amp * super().laplacian(pts, t)
+
+    def inertia(self, pts: np.ndarray, t: float) -> np.ndarray:
+        pts = np.asarray(pts, dtype=np.float64)
+        px, py, pxx, pyy, pxy = (np.zeros(pts.shape[0]) for _ in range(5))
+        for a, b, c in zip(self.a, self.b, self.c):
+            sx = self._s(a, pts[:, 0])
+            sy = self._s(b, pts[:, 1])
+            px += c * sx[1] * sy[0]
+            py += c * sx[0] * sy[1]
+            pxx += c * sx[2] * sy[0]
+            pyy += c * sx[0] * sy[2]
+            pxy += c * sx[1] * sy[1]
+        g = self.amp * np.exp(-t)
+        px, py, pxx, pyy, pxy = (g * v for v in (px, py, pxx, pyy, pxy))
+        out = np.zeros((pts.shape[0], 2))
+        out[:, 0] = py * pxy - px * pyy
+        out[:, 1] = -py * pxx + px * pxy
+        return out
+
+    def __call__(self, pts: np.ndarray, t: float = 0.0) -> np.ndarray:
+        return -self.velocity(pts, t) - self.nu * self.laplacian(pts, t) + self.inertia(pts, t)
+
+
+def mms_ns_2d(seed: int, nu: float, amp: float, nmodes: int = 4) -> StreamMMSInertial:
+    """Draws as mms_2d (fewer modes by default), velocity scaled by amp."""
+    m = mms_2d(seed, nu, nmodes)
+    return StreamMMSInertial(m.a, m.b, m.c, nu, amp)
+
+
 def mms_2d(seed: int, nu: float = 1.0, nmodes: int = 16) -> StreamMMS:
     """Draw order from PCG64(seed): a (nmodes ints in 1..4), b (same), then
     c ~ N(0,1), scaled by 1/(a^2+b^2)."""

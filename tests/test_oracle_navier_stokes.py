@@ -205,3 +205,37 @@ def test_inexact_newton_with_kronecker_multigrid():
         assert info.converged
         assert np.linalg.norm(S.S.project_pressure_mean(k) - S.S.project_pressure_mean(k_ex)) <= \
             1e-7 * np.linalg.norm(k_ex)
+
+
+def test_mms_inertia_matches_difference_quotients():
+    # the manufactured forcing's (u . grad) u against central differences of u
+    m = wl.mms_ns_2d(3, 0.1, 2.0)
+    x = np.random.default_rng(0).random((7, 2))
+    h = 1e-6
+    u = m.velocity(x, 0.3)
+    ux = (m.velocity(x + [h, 0], 0.3) - m.velocity(x - [h, 0], 0.3)) / (2 * h)
+    uy = (m.velocity(x + [0, h], 0.3) - m.velocity(x - [0, h], 0.3)) / (2 * h)
+    conv = u[:, :1] * ux + u[:, 1:] * uy
+    assert np.abs(conv - m.inertia(x, 0.3)).max() <= 1e-7 * np.abs(conv).max()
+
+
+def test_newton_time_stepping_temporal_order():
+    # RadauIIA(2) is of order 3 for the velocity of the index-2 DAE; on a fixed mesh the
+    # error against a run with 1/4 of the smallest step falls by about 2^3 per halving
+    th = _space(2, 4)
+    A, b, c = tableau("radauIIA", 2)
+    mms = wl.mms_ns_2d(3, 0.1, 2.0)
+    T = 1.0
+    u0 = th.free_velocity(th.interpolate(mms.velocity, 0.0))
+
+    def run(nsteps):
+        S = NavierStokesStages(th, A, T / nsteps, 0.1)
+        u, p, k = u0.copy(), np.zeros(th.nverts), np.zeros(S.n)
+        for n in range(nsteps):
+            u, p, k, info = S.step(b, c, mms, n * S.dt, u, p, k, rtol=1e-10, atol=1e-13)
+            assert info.converged
+        return u
+    ref = run(64)
+    errs = [np.linalg.norm(run(m) - ref) for m in (4, 8, 16)]
+    rates = np.log2(np.array(errs[:-1]) / np.array(errs[1:]))
+    assert np.all(rates > 2.6), (errs, rates)
