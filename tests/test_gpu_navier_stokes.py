@@ -181,6 +181,61 @@ def test_ns_newton_independent_of_preconditioner_wind():
     assert relerr(sols[0], sols[1]) < 1e-8
 
 
+@pytest.mark.parametrize("smoother", [1, 2])
+def test_ns_newton_with_chebyshev_and_gmres_relaxation(smoother):
+    # the relaxations of Sec. 5.1 (Chebyshev) and Sec. 4.2 (GMRES, a nonlinear
+    # preconditioner: FGMRES is flexible) inside the Newton steps: the same solution
+    g = gpu_of("oseen", smoother=smoother)
+    ns, S, state, fst, gn, gst = _inputs("oseen", 33, False, 1.0, 1.0)
+    F = _gpu_rhs(g, fst, state)
+    k = torch.zeros(S.n, dtype=torch.float64, device="cuda")
+    say(f"[ns-relax] smoother={smoother}")
+    info = g.irk_ns_newton_solve(F, to_dev(state), k, rtol=1e-11)
+    assert info["converged"]
+    ko, _ = ns.newton(_oracle_rhs(_stokes(ns), fst, state), state[:S.th.nvel], np.zeros(S.n), rtol=1e-13)
+    assert relerr(S.project_pressure_mean(to_host(k)), S.project_pressure_mean(ko)) < 1e-8
+
+
+def test_ns_one_stage_backward_euler():
+    # r = 1 (RadauIIA(1), backward Euler): residual, Jacobian and Newton
+    g = gpu_of("be")
+    ns, S, state, fst, gn, gst = _inputs("be", 35, False, 6.0, 6.0)
+    rng = np.random.default_rng(36)
+    k = 0.5 * rng.standard_normal(S.n)
+    x = rng.standard_normal(S.n)
+    say("[ns-be] residual, Jacobian, Newton")
+    F = _gpu_rhs(g, fst, state)
+    R = torch.empty_like(F)
+    g.irk_ns_residual(F, to_dev(state), to_dev(k), R)
+    assert relerr(to_host(R), -ns.residual(_oracle_rhs(_stokes(ns), fst, state), state[:S.th.nvel], k)) < 1e-12
+    y = torch.empty_like(F)
+    g.irk_ns_jacobian_apply(to_dev(state), to_dev(k), to_dev(x), y)
+    assert relerr(to_host(y), ns.jacobian_apply(state[:S.th.nvel], k, x)) < 1e-12
+    kk = torch.zeros_like(F)
+    info = g.irk_ns_newton_solve(F, to_dev(state), kk, rtol=1e-11)
+    assert info["converged"]
+    ko, _ = ns.newton(_oracle_rhs(_stokes(ns), fst, state), state[:S.th.nvel], np.zeros(S.n), rtol=1e-13)
+    assert relerr(S.project_pressure_mean(to_host(kk)), S.project_pressure_mean(ko)) < 1e-8
+
+
+def test_ns_newton_maxit_and_zero_residual():
+    # maxit = 0 reports ENOCONV with k untouched; a zero right-hand side at k = 0 with a
+    # zero state is converged before any step
+    from paper_2202_07381_amd import irkmg
+
+    g = gpu_of("c1")
+    ns, S, state, fst, gn, gst = _inputs("c1", 37, False, 4.0, 4.0)
+    F = _gpu_rhs(g, fst, state)
+    k = torch.zeros(S.n, dtype=torch.float64, device="cuda")
+    say("[ns-edge] maxit 0, zero data")
+    info = g.irk_ns_newton_solve(F, to_dev(state), k, maxit=0)
+    assert info["status"] == irkmg.IRK_ENOCONV and info["iterations"] == 0 and not info["converged"]
+    assert float(k.abs().max()) == 0.0
+    z = torch.zeros_like(F)
+    info = g.irk_ns_newton_solve(z, torch.zeros(S.ns, dtype=torch.float64, device="cuda"), k)
+    assert info["converged"] and info["iterations"] == 0 and info["norm0"] == 0.0
+
+
 def test_ns_newton_with_fp32_preconditioner():
     # FP32 patch factors and V-cycle inside the FP64 Newton-Krylov iteration: the same
     # solution (the preconditioner does not enter the converged result)
