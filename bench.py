@@ -566,10 +566,19 @@ def run_relax(n):
 def ns_element_flops(dim, r, ncells):
     """Algorithmic FP64 flops (an FMA counts 2) of one Jacobian-mode launch of the
     Navier--Stokes element kernel: per (cell, stage) the stage mix of the direction
-    (nloc dim r FMAs) and two trilinear terms, each nloc (dim+1) dim FMAs for the wind
-    coefficients and nloc^2 (nloc (dim+1) + dim) for the contraction."""
-    nl, nb = (6, 3) if dim == 2 else (10, 4)
-    fma = 2 * (nl * nb * dim + nl * nl * (nl * nb + dim)) + nl * dim * r
+    (nloc dim r FMAs), then
+      2D, seven quadrature points, each: the wind and z at the point (2 x 12), their
+      components along the three grad lam_k (2 x 6), the barycentric derivatives of z
+      and U (2 x 18: three nonzero basis derivatives per coordinate), the two
+      directional derivatives (2 x 6), the weighted test functions (6) and the
+      accumulation (12): 102;
+      3D, two tensor contractions, each nloc (dim+1) dim FMAs for the wind coefficients
+      and nloc^2 (nloc (dim+1) + dim) for the contraction."""
+    if dim == 2:
+        fma = 7 * 102 + 6 * 2 * r
+    else:
+        nl, nb = 10, 4
+        fma = 2 * (nl * nb * dim + nl * nl * (nl * nb + dim)) + nl * dim * r
     return 2.0 * fma * ncells * r
 
 
@@ -661,7 +670,9 @@ def run_ns(n, nsteps, smoother, precond="oseen", dt=1.0 / 400, dim=2):
                         "patch_apply_us": 1e3 * pa["ms_total"] / max(1, pa["launches"])},
             "roofline_ns_element": {"bound": "alu", "achieved": flops / (e_ms * 1e-3) / 1e12, "peak": 78.6,
                                     "unit": "TFLOP/s", "frac": flops / (e_ms * 1e-3) / 1e12 / 78.6,
-                                    "flops_per_launch": flops},
+                                    "flops_per_launch": flops,
+                                    "bytes_per_launch": se["bytes_per_launch"],
+                                    "hbm_GBps": se["bytes_per_launch"] / (e_ms * 1e-3) / 1e9},
             "roofline_ns_gather": {"bound": "hbm", "achieved": sg["bytes_per_launch"] / (gat_ms * 1e-3) / 1e9,
                                    "peak": 8000.0, "unit": "GB/s"}}
 
