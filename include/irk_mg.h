@@ -11,8 +11,10 @@
  *
  * preconditioning FGMRES (Sec. 4) with a geometric V-cycle whose relaxation is the
  * additive vertex-star Vanka sweep coupling all stages (Sec. 4.2) and whose transfers
- * are I_r (x) P and its transpose (Sec. 4.1).  All arithmetic runs in HIP kernels on a
- * gfx950 GPU; host code only builds the mesh topology and sparse structures.
+ * are I_r (x) P and its transpose (Sec. 4.1); and Newton's method on the nonlinear
+ * Navier--Stokes stage equations (Sec. 3.2) with these solves as its linear steps.  All
+ * arithmetic runs in HIP kernels on a gfx950 GPU; host code only builds the mesh
+ * topology and sparse structures and runs the Krylov and Newton loops' scalar logic.
  *
  * Conventions used by every entry point
  * -------------------------------------
