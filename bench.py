@@ -582,7 +582,7 @@ def ns_element_flops(dim, r, ncells):
     return 2.0 * fma * ncells * r
 
 
-def run_ns(n, nsteps, smoother, precond="oseen", dt=1.0 / 400, dim=2):
+def run_ns(n, nsteps, smoother, precond="oseen", dt=1.0 / 400, dim=2, nu=0.01, eta_fixed=0.0):
     """Navier--Stokes time stepping (Sec. 3.2): Newton with Eisenstat--Walker forcing,
     FGMRES preconditioned by the V-cycle of the Oseen operator linearised at the initial
     state (precond "oseen"; set up once, kept for every step) or of the Stokes operator
@@ -596,7 +596,7 @@ def run_ns(n, nsteps, smoother, precond="oseen", dt=1.0 / 400, dim=2):
     from paper_2202_07381_amd import irkmg
     from paper_2202_07381_amd import workloads as wl
 
-    fam, r, nu = "radauIIA", 3 if dim == 2 else 2, 0.01
+    fam, r = "radauIIA", 3 if dim == 2 else 2
     if dim == 2:
         levels = wl.square_hierarchy(4, int(round(np.log2(n // 4))) + 1)
     else:
@@ -632,7 +632,7 @@ def run_ns(n, nsteps, smoother, precond="oseen", dt=1.0 / 400, dim=2):
         g.irk_rhs(fst, state, F)
         torch.cuda.synchronize()
         t1 = time.perf_counter()
-        info = g.irk_ns_newton_solve(F, state, k, rtol=1e-8)
+        info = g.irk_ns_newton_solve(F, state, k, rtol=1e-8, eta_fixed=eta_fixed)
         torch.cuda.synchronize()
         ms = 1e3 * (time.perf_counter() - t1)
         g.irk_update(k, state)
@@ -658,7 +658,7 @@ def run_ns(n, nsteps, smoother, precond="oseen", dt=1.0 / 400, dim=2):
     return {"metric": "Navier--Stokes IRK time step (Newton-Krylov-multigrid)", "unit": "ms / step",
             "value": float(np.mean([s["ms"] for s in t])), "higher_is_better": False, "n_gpus": 1,
             "dtype": "f64", "data": "synthetic",
-            "config": {"workload": f"{dim}D Navier-Stokes {n}^{dim} RadauIIA({r}) nu=0.01 dt={dt:g}, relaxation {smoother}, "
+            "config": {"workload": f"{dim}D Navier-Stokes {n}^{dim} RadauIIA({r}) nu={nu:g} dt={dt:g}, relaxation {smoother}, "
                                    f"{precond} preconditioner (Oseen: linearised at the initial state), "
                                    "Newton to 1e-8"},
             "patch_form": form,
@@ -693,6 +693,10 @@ def main():
     ap.add_argument("--ns-steps", type=int, default=6, help="ns: time steps")
     ap.add_argument("--ns-relax", default="sweep", choices=["sweep", "chebyshev", "gmres"], help="ns: relaxation")
     ap.add_argument("--ns-dim", type=int, default=2, choices=[2, 3], help="ns: 2 (square) or 3 (cube)")
+    ap.add_argument("--ns-nu", type=float, default=0.01, help="ns: viscosity (1/Re for unit speed and length)")
+    ap.add_argument("--ns-eta-fixed", type=float, default=0.0,
+                    help="ns: constant forcing term instead of Eisenstat-Walker (e.g. 1e-8 to count iterations "
+                         "of tight linear solves)")
     ap.add_argument("--ns-dt", type=float, default=1.0 / 400, help="ns: time step (default the cylinder run's 1/400)")
     ap.add_argument("--ns-precond", default="oseen", choices=["oseen", "stokes"],
                     help="ns: operator of the V-cycle (Oseen at the initial state, or Stokes)")
@@ -732,8 +736,8 @@ def main():
         print(json.dumps(run_relax(args.relax_n)), flush=True)
         return
     if args.workload == "ns":
-        print(json.dumps(run_ns(args.ns_n, args.ns_steps, args.ns_relax, args.ns_precond, args.ns_dt, args.ns_dim)),
-              flush=True)
+        print(json.dumps(run_ns(args.ns_n, args.ns_steps, args.ns_relax, args.ns_precond, args.ns_dt, args.ns_dim,
+                                args.ns_nu, args.ns_eta_fixed)), flush=True)
         return
     if args.workload == "t1":
         print(json.dumps(run_t1(args.t1_level, args.t1_stages, 1 if args.t1_fp32 else 0, args.t1_max_steps,
