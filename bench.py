@@ -566,19 +566,15 @@ def run_relax(n):
 def ns_element_flops(dim, r, ncells):
     """Algorithmic FP64 flops (an FMA counts 2) of one Jacobian-mode launch of the
     Navier--Stokes element kernel: per (cell, stage) the stage mix of the direction
-    (nloc dim r FMAs), then
-      2D, seven quadrature points, each: the wind and z at the point (2 x 12), their
-      components along the three grad lam_k (2 x 6), the barycentric derivatives of z
-      and U (2 x 18: three nonzero basis derivatives per coordinate), the two
-      directional derivatives (2 x 6), the weighted test functions (6) and the
-      accumulation (12): 102;
-      3D, two tensor contractions, each nloc (dim+1) dim FMAs for the wind coefficients
-      and nloc^2 (nloc (dim+1) + dim) for the contraction."""
-    if dim == 2:
-        fma = 7 * 102 + 6 * 2 * r
-    else:
-        nl, nb = 10, 4
-        fma = 2 * (nl * nb * dim + nl * nl * (nl * nb + dim)) + nl * dim * r
+    (nloc dim r FMAs) and, at each quadrature point (7 in 2D, 14 in 3D), the wind and z
+    at the point (2 nloc dim), their components along the dim+1 gradients of the
+    barycentric coordinates (2 (dim+1) dim), the barycentric derivatives of z and U
+    (2 (dim+1)(1+dim) dim: 1 + dim nonzero basis derivatives per coordinate), the two
+    directional derivatives (2 (dim+1) dim), the weighted test functions (nloc) and the
+    accumulation (nloc dim)."""
+    nl, nb, nq = (6, 3, 7) if dim == 2 else (10, 4, 14)
+    per_point = 2 * nl * dim + 2 * nb * dim + 2 * nb * (1 + dim) * dim + 2 * nb * dim + nl + nl * dim
+    fma = nq * per_point + nl * dim * r
     return 2.0 * fma * ncells * r
 
 

@@ -319,11 +319,10 @@ irk_status ns_init(irk_mg* h, hipStream_t s) {
   if (h->ns_ready) return IRK_OK;
   HostLevel& H = h->host[h->nlevels - 1];
   DevLevel& L = h->dev[h->nlevels - 1];
-  std::vector<double> geo, T;
+  std::vector<double> geo;
   std::vector<int32_t> cn, ip, inc;
-  ns_cell_data(H, geo, T, cn, ip, inc);
+  ns_cell_data(H, geo, cn, ip, inc);
   CHK(upload(h, &h->ns_geo, geo, s));
-  CHK(upload(h, &h->ns_T, T, s));
   CHK(upload(h, &h->ns_cells, cn, s));
   CHK(upload(h, &h->ns_inc_ptr, ip, s));
   CHK(upload(h, &h->ns_inc, inc, s));
@@ -367,7 +366,6 @@ irk_status ns_correction(irk_mg* h, int mode, const double* x, double* y, double
   a.mode = mode;
   a.cell_nodes = h->ns_cells;
   a.geo = h->ns_geo;
-  a.T = h->ns_T;
   a.free_of_node = h->ns_free;
   a.U = h->ns_U;
   a.w = h->ns_w;

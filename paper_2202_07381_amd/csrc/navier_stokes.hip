@@ -13,9 +13,8 @@
 // Two launches, both deterministic (no atomics, so every solve repeats bit for bit):
 //   k_ns_element  one thread per (cell, stage): gathers the cell's nodal fields and
 //                 writes the element vector, exactly (the integrands are polynomials of
-//                 degree 5): in 2D by a seven-point rule of that degree, in 3D as
-//                 vol * sum_{e,k} (a_e . grad lam_k) T[a][b][e][k] b_b with T the
-//                 reference tensor int phi_e phi_a d_k phi_b / |cell|;
+//                 degree 5) by a quadrature rule of that degree (7 points on a triangle,
+//                 14 on a tetrahedron);
 //   k_ns_gather   one thread per free velocity unknown (internal layout): sums the element
 //                 vectors of the cells around its node in a fixed order, y += scale * sum.
 #include <hip/hip_runtime.h>
@@ -32,111 +31,127 @@ struct Elem {
   static constexpr int NB = D + 1;
 };
 
-// out[a][d] += sum_b (sum_{e,k} (A_e . grad lam_k) T[a][b][e][k]) B[b][d]
+// Quadrature rules exact for polynomials of degree 5, which covers every integrand
+// phi_a ((a . grad) b)_d of P2 fields: points in barycentric coordinates, weights summing
+// to 1 (the integral is |cell| sum_q w_q f(x_q)).
+//   triangle: Radon's seven points (centroid and two three-point orbits);
+//   tetrahedron: 14 points, two four-point orbits (a, a, a, 1 - 3a) and one six-point
+//   orbit (a, a, 1/2 - a, 1/2 - a), the orbit parameters solving the moment equations.
+// Both were checked on every monomial of degree <= 5 in 40-digit arithmetic.
 template <int D>
-__device__ __forceinline__ void conv_term(const double (&A)[Elem<D>::NL][D], const double (&B)[Elem<D>::NL][D],
-                                          const double (&glam)[D + 1][D], const double* __restrict__ T,
-                                          double (&out)[Elem<D>::NL][D]) {
-  constexpr int NL = Elem<D>::NL, NB = Elem<D>::NB;
-  double wg[NL][NB];
+struct Rule;
+template <>
+struct Rule<2> {
+  static constexpr int NQ = 7;
+  static constexpr double a1 = 0.10128650732345633880, b1 = 0.79742698535308732240;
+  static constexpr double a2 = 0.47014206410511508977, b2 = 0.059715871789769820459;
+  static constexpr double c = 1.0 / 3.0;
+  static constexpr double w0 = 0.225, w1 = 0.12593918054482715260, w2 = 0.13239415278850618074;
+  static constexpr double L[NQ][3] = {{c, c, c}, {a1, a1, b1}, {a1, b1, a1}, {b1, a1, a1},
+                                      {a2, a2, b2}, {a2, b2, a2}, {b2, a2, a2}};
+  static constexpr double W[NQ] = {w0, w1, w1, w1, w2, w2, w2};
+};
+template <>
+struct Rule<3> {
+  static constexpr int NQ = 14;
+  static constexpr double a1 = 0.09273525031089122640, b1 = 1.0 - 3.0 * a1;
+  static constexpr double a2 = 0.31088591926330060980, b2 = 1.0 - 3.0 * a2;
+  static constexpr double a3 = 0.45449629587435035051, b3 = 0.5 - a3;
+  static constexpr double w1 = 0.073493043116361949544, w2 = 0.11268792571801585080;
+  static constexpr double w3 = 0.042546020777081466438;
+  static constexpr double L[NQ][4] = {
+      {b1, a1, a1, a1}, {a1, b1, a1, a1}, {a1, a1, b1, a1}, {a1, a1, a1, b1},
+      {b2, a2, a2, a2}, {a2, b2, a2, a2}, {a2, a2, b2, a2}, {a2, a2, a2, b2},
+      {a3, a3, b3, b3}, {a3, b3, a3, b3}, {a3, b3, b3, a3}, {b3, a3, a3, b3}, {b3, a3, b3, a3}, {b3, b3, a3, a3}};
+  static constexpr double W[NQ] = {w1, w1, w1, w1, w2, w2, w2, w2, w3, w3, w3, w3, w3, w3};
+};
+template <int D>
+struct Edges;
+template <>
+struct Edges<2> {  // local edge order of the P2 basis
+  static constexpr int E[3][2] = {{0, 1}, {0, 2}, {1, 2}};
+};
+template <>
+struct Edges<3> {
+  static constexpr int E[6][2] = {{0, 1}, {0, 2}, {0, 3}, {1, 2}, {1, 3}, {2, 3}};
+};
+
+// Per point: the fields and their derivatives along the barycentric coordinates from the
+// P2 basis, grad = sum_k d/dlam_k grad lam_k.  MODE 0: (V . grad) U; MODE 1:
+// (V . grad) Z + (Z . grad) U.  out[a][d] += w_q phi_a(x_q) g_d.
+template <int D, int MODE>
+__device__ __forceinline__ void quad_terms(const double (&V)[Elem<D>::NL][D], const double (&Z)[Elem<D>::NL][D],
+                                           const double (&U)[Elem<D>::NL][D], const double (&glam)[D + 1][D],
+                                           double (&out)[Elem<D>::NL][D]) {
+  constexpr int NL = Elem<D>::NL, NB = D + 1;
+  using R = Rule<D>;
 #pragma unroll
-  for (int e = 0; e < NL; ++e)
+  for (int q = 0; q < R::NQ; ++q) {
+    double phi[NL], dphi[NL][NB];
+#pragma unroll
+    for (int v = 0; v < NB; ++v) {
+      phi[v] = R::L[q][v] * (2.0 * R::L[q][v] - 1.0);
+#pragma unroll
+      for (int k = 0; k < NB; ++k) dphi[v][k] = k == v ? 4.0 * R::L[q][v] - 1.0 : 0.0;
+    }
+#pragma unroll
+    for (int e = 0; e < NL - NB; ++e) {
+      const int i = Edges<D>::E[e][0], j = Edges<D>::E[e][1];
+      phi[NB + e] = 4.0 * R::L[q][i] * R::L[q][j];
+#pragma unroll
+      for (int k = 0; k < NB; ++k)
+        dphi[NB + e][k] = (k == i ? 4.0 * R::L[q][j] : 0.0) + (k == j ? 4.0 * R::L[q][i] : 0.0);
+    }
+    double vq[D];
+#pragma unroll
+    for (int d = 0; d < D; ++d) vq[d] = 0.0;
+#pragma unroll
+    for (int b = 0; b < NL; ++b)
+#pragma unroll
+      for (int d = 0; d < D; ++d) vq[d] += phi[b] * V[b][d];
+    double g[D];
+#pragma unroll
+    for (int d = 0; d < D; ++d) g[d] = 0.0;
+    const double (&X)[NL][D] = MODE == 0 ? U : Z;
 #pragma unroll
     for (int k = 0; k < NB; ++k) {
-      double s = 0.0;
+      double vg = 0.0;
 #pragma unroll
-      for (int d = 0; d < D; ++d) s += A[e][d] * glam[k][d];
-      wg[e][k] = s;
-    }
+      for (int d = 0; d < D; ++d) vg += vq[d] * glam[k][d];
 #pragma unroll
-  for (int a = 0; a < NL; ++a) {
-#pragma unroll 2
-    for (int b = 0; b < NL; ++b) {
-      const double* t = T + (a * NL + b) * NL * NB;
-      double s = 0.0;
-#pragma unroll
-      for (int e = 0; e < NL; ++e)
-#pragma unroll
-        for (int k = 0; k < NB; ++k) s += wg[e][k] * t[e * NB + k];
-#pragma unroll
-      for (int d = 0; d < D; ++d) out[a][d] += s * B[b][d];
-    }
-  }
-}
-
-// 2D: Radon's seven-point rule on the triangle, exact for polynomials of degree 5, which
-// covers every integrand phi_a ((a . grad) b)_d of P2 fields; points in barycentric
-// coordinates, weights summing to 1 (the integral is |cell| sum_q w_q f(x_q)).  Per point:
-// the fields and their derivatives along the barycentric coordinates from the P2 basis,
-// grad = sum_k d/dlam_k grad lam_k.  MODE 0: (V . grad) U; MODE 1: (V . grad) Z + (Z . grad) U.
-template <int MODE>
-__device__ __forceinline__ void quad_2d(const double (&V)[6][2], const double (&Z)[6][2], const double (&U)[6][2],
-                                        const double (&glam)[3][2], double (&out)[6][2]) {
-  constexpr double a1 = 0.10128650732345633880, b1 = 0.79742698535308732240;
-  constexpr double a2 = 0.47014206410511508977, b2 = 0.059715871789769820459;
-  constexpr double w0 = 0.225, w1 = 0.12593918054482715260, w2 = 0.13239415278850618074;
-  constexpr double c = 1.0 / 3.0;
-  constexpr double L[7][3] = {{c, c, c}, {a1, a1, b1}, {a1, b1, a1}, {b1, a1, a1},
-                              {a2, a2, b2}, {a2, b2, a2}, {b2, a2, a2}};
-  constexpr double W[7] = {w0, w1, w1, w1, w2, w2, w2};
-  constexpr int E[3][2] = {{0, 1}, {0, 2}, {1, 2}};  // local edge order of the P2 basis
-#pragma unroll
-  for (int q = 0; q < 7; ++q) {
-    double phi[6], dphi[6][3];
-#pragma unroll
-    for (int v = 0; v < 3; ++v) {
-      phi[v] = L[q][v] * (2.0 * L[q][v] - 1.0);
-#pragma unroll
-      for (int k = 0; k < 3; ++k) dphi[v][k] = k == v ? 4.0 * L[q][v] - 1.0 : 0.0;
-    }
-#pragma unroll
-    for (int e = 0; e < 3; ++e) {
-      const int i = E[e][0], j = E[e][1];
-      phi[3 + e] = 4.0 * L[q][i] * L[q][j];
-#pragma unroll
-      for (int k = 0; k < 3; ++k) dphi[3 + e][k] = (k == i ? 4.0 * L[q][j] : 0.0) + (k == j ? 4.0 * L[q][i] : 0.0);
-    }
-    // wind at the point and its components along grad lam_k
-    double vq[2] = {0.0, 0.0};
-#pragma unroll
-    for (int b = 0; b < 6; ++b)
-#pragma unroll
-      for (int d = 0; d < 2; ++d) vq[d] += phi[b] * V[b][d];
-    double g[2] = {0.0, 0.0};
-    const double (&X)[6][2] = MODE == 0 ? U : Z;
-#pragma unroll
-    for (int k = 0; k < 3; ++k) {
-      const double vg = vq[0] * glam[k][0] + vq[1] * glam[k][1];
-#pragma unroll
-      for (int d = 0; d < 2; ++d) {
+      for (int d = 0; d < D; ++d) {
         double dx = 0.0;
 #pragma unroll
-        for (int b = 0; b < 6; ++b) dx += dphi[b][k] * X[b][d];
+        for (int b = 0; b < NL; ++b) dx += dphi[b][k] * X[b][d];
         g[d] += vg * dx;
       }
     }
     if constexpr (MODE == 1) {
-      double zq[2] = {0.0, 0.0};
+      double zq[D];
 #pragma unroll
-      for (int b = 0; b < 6; ++b)
+      for (int d = 0; d < D; ++d) zq[d] = 0.0;
 #pragma unroll
-        for (int d = 0; d < 2; ++d) zq[d] += phi[b] * Z[b][d];
+      for (int b = 0; b < NL; ++b)
 #pragma unroll
-      for (int k = 0; k < 3; ++k) {
-        const double zg = zq[0] * glam[k][0] + zq[1] * glam[k][1];
+        for (int d = 0; d < D; ++d) zq[d] += phi[b] * Z[b][d];
 #pragma unroll
-        for (int d = 0; d < 2; ++d) {
+      for (int k = 0; k < NB; ++k) {
+        double zg = 0.0;
+#pragma unroll
+        for (int d = 0; d < D; ++d) zg += zq[d] * glam[k][d];
+#pragma unroll
+        for (int d = 0; d < D; ++d) {
           double du = 0.0;
 #pragma unroll
-          for (int b = 0; b < 6; ++b) du += dphi[b][k] * U[b][d];
+          for (int b = 0; b < NL; ++b) du += dphi[b][k] * U[b][d];
           g[d] += zg * du;
         }
       }
     }
 #pragma unroll
-    for (int a = 0; a < 6; ++a)
+    for (int a = 0; a < NL; ++a)
 #pragma unroll
-      for (int d = 0; d < 2; ++d) out[a][d] += (W[q] * phi[a]) * g[d];
+      for (int d = 0; d < D; ++d) out[a][d] += (R::W[q] * phi[a]) * g[d];
   }
 }
 
@@ -178,10 +193,7 @@ __global__ __launch_bounds__(256) void k_ns_element(NsElemArgs p) {
     for (int a = 0; a < NL; ++a)
 #pragma unroll
       for (int d = 0; d < D; ++d) U[a][d] = p.U[((int64_t)node[a] * D + d) * r + i];
-    if constexpr (D == 2)
-      quad_2d<0>(V, U, U, glam, out);
-    else
-      conv_term<D>(V, U, glam, p.T, out);
+    quad_terms<D, 0>(V, U, U, glam, out);
   } else {
     // z_i = sum_j a_ij x_j at the nodes; prescribed (boundary) nodes do not vary
     double Z[NL][D];
@@ -201,12 +213,7 @@ __global__ __launch_bounds__(256) void k_ns_element(NsElemArgs p) {
     for (int a = 0; a < NL; ++a)
 #pragma unroll
       for (int d = 0; d < D; ++d) U[a][d] = p.U[((int64_t)node[a] * D + d) * r + i];
-    if constexpr (D == 2) {
-      quad_2d<1>(V, Z, U, glam, out);
-    } else {
-      conv_term<D>(V, Z, glam, p.T, out);
-      conv_term<D>(Z, U, glam, p.T, out);
-    }
+    quad_terms<D, 1>(V, Z, U, glam, out);
   }
 #pragma unroll
   for (int a = 0; a < NL; ++a)

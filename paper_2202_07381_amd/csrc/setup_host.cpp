@@ -663,19 +663,12 @@ void coarse_matrix(const HostLevel& L, int r, const double* A, double dt, std::v
   *max_abs = scale;
 }
 
-void ns_cell_data(const HostLevel& L, std::vector<double>& geo, std::vector<double>& T,
-                  std::vector<int32_t>& cell_nodes, std::vector<int32_t>& inc_ptr, std::vector<int32_t>& inc) {
+void ns_cell_data(const HostLevel& L, std::vector<double>& geo, std::vector<int32_t>& cell_nodes,
+                  std::vector<int32_t>& inc_ptr, std::vector<int32_t>& inc) {
   const int d = L.dim, nb = d + 1, nl = nloc_of(d);
-  const RefTensors& R = ref_tensors(d);
   const int per = nb * d + 1;
   geo.assign((size_t)L.nc * per, 0.0);
   for (int64_t c = 0; c < L.nc; ++c) cell_geometry(L, c, &geo[(size_t)c * per], &geo[(size_t)c * per + nb * d]);
-  T.assign((size_t)nl * nl * nl * nb, 0.0);
-  for (int e = 0; e < nl; ++e)
-    for (int a = 0; a < nl; ++a)
-      for (int b = 0; b < nl; ++b)
-        for (int k = 0; k < nb; ++k)
-          T[(((size_t)a * nl + b) * nl + e) * nb + k] = R.C[((e * nl + a) * nl + b) * nb + k];
   cell_nodes.resize(L.cell_nodes.size());
   for (size_t i = 0; i < L.cell_nodes.size(); ++i) cell_nodes[i] = (int32_t)L.cell_nodes[i];
   inc_ptr.assign(L.nfree + 1, 0);
