@@ -423,8 +423,8 @@ void irk_batch_destroy(irk_batch* b);
  *                            B^T (index + dim values per entry), F and x read, r written;
  *   kernel 2  gather update: local corrections and their slot indices read, x read and
  *                            written, weights read;
- *   kernel 3  Navier--Stokes element vectors (finest level, Jacobian mode): cell nodes
- *                            and geometry, stage values and wind once per node, the
+ *   kernel 3  Navier--Stokes element vectors (finest level, Jacobian mode): cell nodes,
+ *                            their free indices and the geometry, stage values and wind once per node, the
  *                            direction once, element vectors written (FP64);
  *   kernel 4  Navier--Stokes gather: incidence lists, the element entries of free
  *                            nodes, y read and written.

@@ -91,10 +91,10 @@ void assemble_level(HostLevel& L, double nu, const std::vector<double>* wind_nod
                     bool with_mfa);
 void build_patches(HostLevel& L);
 // Element data of the Navier--Stokes terms: per cell the barycentric gradients
-// ((dim+1) x dim) and the measure; int32 cell nodes; per free node the incidences
-// cell * nloc + a (cell order) of its node.
+// ((dim+1) x dim) and the measure; int32 cell nodes and their free indices (-1 for
+// prescribed nodes); per free node the incidences cell * nloc + a (cell order) of its node.
 void ns_cell_data(const HostLevel& L, std::vector<double>& geo, std::vector<int32_t>& cell_nodes,
-                  std::vector<int32_t>& inc_ptr, std::vector<int32_t>& inc);
+                  std::vector<int32_t>& cell_free, std::vector<int32_t>& inc_ptr, std::vector<int32_t>& inc);
 // Returns an empty string on success, else a description of the nesting failure.
 std::string build_transfer(const HostLevel& coarse, HostLevel& fine, const int64_t* parent);
 // Dense coarse operator (row-major N x N, internal layout) with the pressure of vertex 0
@@ -288,7 +288,8 @@ struct Handle {
   std::vector<double> wind_fine;  // host copy of the finest-level wind (empty: none)
   bool ns_ready = false;
   bool ns_jac = false;  // FGMRES operator = the Newton Jacobian at ns_U
-  int32_t *ns_cells = nullptr, *ns_free = nullptr, *ns_inc_ptr = nullptr, *ns_inc = nullptr;
+  int32_t *ns_cells = nullptr, *ns_cell_free = nullptr, *ns_free = nullptr, *ns_inc_ptr = nullptr,
+          *ns_inc = nullptr;
   double *ns_geo = nullptr, *ns_w = nullptr, *ns_U = nullptr, *ns_elem = nullptr;
   double *ns_k = nullptr, *ns_F = nullptr, *ns_G = nullptr;  // Newton iterate, rhs, residual
 };
@@ -416,7 +417,7 @@ struct NsElemArgs {
   int mode = 0;                       // 0: c(U - w, U); 1: c(U - w, z) + c(z, U)
   const int32_t* cell_nodes = nullptr;  // nc x nloc node indices
   const double* geo = nullptr;        // nc x ((dim+1) dim + 1): grad lam_k, then |cell|
-  const int32_t* free_of_node = nullptr;
+  const int32_t* cell_free = nullptr;  // nc x nloc free indices of the cell nodes (-1: prescribed)
   const double* U = nullptr;          // stage values [node][d][i]
   const double* w = nullptr;          // wind [node][d] (NULL: none)
   const double* x = nullptr;          // mode 1: direction, internal layout

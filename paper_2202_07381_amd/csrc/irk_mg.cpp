@@ -320,10 +320,11 @@ irk_status ns_init(irk_mg* h, hipStream_t s) {
   HostLevel& H = h->host[h->nlevels - 1];
   DevLevel& L = h->dev[h->nlevels - 1];
   std::vector<double> geo;
-  std::vector<int32_t> cn, ip, inc;
-  ns_cell_data(H, geo, cn, ip, inc);
+  std::vector<int32_t> cn, cf, ip, inc;
+  ns_cell_data(H, geo, cn, cf, ip, inc);
   CHK(upload(h, &h->ns_geo, geo, s));
   CHK(upload(h, &h->ns_cells, cn, s));
+  CHK(upload(h, &h->ns_cell_free, cf, s));
   CHK(upload(h, &h->ns_inc_ptr, ip, s));
   CHK(upload(h, &h->ns_inc, inc, s));
   CHK(upload(h, &h->ns_free, H.free_of_node, s));
@@ -335,11 +336,12 @@ irk_status ns_init(irk_mg* h, hipStream_t s) {
   CHK(dalloc(h, &h->ns_F, (size_t)L.N));
   CHK(dalloc(h, &h->ns_G, (size_t)L.N));
   HIPCHK(hipStreamSynchronize(s));
-  // algorithmic bytes of one Jacobian-mode launch: cell nodes and geometry, stage values
-  // and wind once per node, the direction once, element vectors written; the gather reads
+  // algorithmic bytes of one Jacobian-mode launch: cell nodes, their free indices and the
+  // geometry, stage values and wind once per node, the direction once, element vectors
+  // written; the gather reads
   // the incidences and element entries of free nodes and updates y
   const double nc = (double)H.nc, nn = (double)H.nn, nf = (double)H.nfree;
-  L.alg_bytes[3] = nc * nl * 4 + nc * ((d + 1) * d + 1) * 8 + nn * 4 + nn * d * r * 8 +
+  L.alg_bytes[3] = 2 * nc * nl * 4 + nc * ((d + 1) * d + 1) * 8 + nn * d * r * 8 +
                    (h->ns_w ? nn * d * 8 : 0) + nf * d * r * 8 + nc * nl * d * r * 8;
   L.alg_bytes[4] = nf * 4 + (double)inc.size() * 4 + (double)inc.size() * d * r * 8 + 2 * nf * d * r * 8;
   h->ns_ready = true;
@@ -366,7 +368,7 @@ irk_status ns_correction(irk_mg* h, int mode, const double* x, double* y, double
   a.mode = mode;
   a.cell_nodes = h->ns_cells;
   a.geo = h->ns_geo;
-  a.free_of_node = h->ns_free;
+  a.cell_free = h->ns_cell_free;
   a.U = h->ns_U;
   a.w = h->ns_w;
   a.x = x;

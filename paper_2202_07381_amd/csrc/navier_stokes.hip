@@ -199,7 +199,7 @@ __global__ __launch_bounds__(256) void k_ns_element(NsElemArgs p) {
     double Z[NL][D];
 #pragma unroll
     for (int a = 0; a < NL; ++a) {
-      const int f = p.free_of_node[node[a]];
+      const int f = p.cell_free[c * NL + a];
 #pragma unroll
       for (int d = 0; d < D; ++d) {
         double s = 0.0;

@@ -664,13 +664,17 @@ void coarse_matrix(const HostLevel& L, int r, const double* A, double dt, std::v
 }
 
 void ns_cell_data(const HostLevel& L, std::vector<double>& geo, std::vector<int32_t>& cell_nodes,
-                  std::vector<int32_t>& inc_ptr, std::vector<int32_t>& inc) {
+                  std::vector<int32_t>& cell_free, std::vector<int32_t>& inc_ptr, std::vector<int32_t>& inc) {
   const int d = L.dim, nb = d + 1, nl = nloc_of(d);
   const int per = nb * d + 1;
   geo.assign((size_t)L.nc * per, 0.0);
   for (int64_t c = 0; c < L.nc; ++c) cell_geometry(L, c, &geo[(size_t)c * per], &geo[(size_t)c * per + nb * d]);
   cell_nodes.resize(L.cell_nodes.size());
-  for (size_t i = 0; i < L.cell_nodes.size(); ++i) cell_nodes[i] = (int32_t)L.cell_nodes[i];
+  cell_free.resize(L.cell_nodes.size());
+  for (size_t i = 0; i < L.cell_nodes.size(); ++i) {
+    cell_nodes[i] = (int32_t)L.cell_nodes[i];
+    cell_free[i] = L.free_of_node[L.cell_nodes[i]];
+  }
   inc_ptr.assign(L.nfree + 1, 0);
   inc.clear();
   for (int64_t f = 0; f < L.nfree; ++f) {
