@@ -34,6 +34,11 @@ solve grind against rounding, never below 0.5 tau / ||G_l|| (the final-step safe
 Kelley's textbook treatment of inexact Newton), tau = max(atol, rtol ||G(k^0)||), the
 tolerance at which Newton stops: ||G|| <= tau.
 
+Optional globalisation (not in the paper, off by default): a backtracking line search
+on ||G||, k <- k + lam delta with the first lam in 1, 1/2, 1/4, ... (at most ls_maxit
+halvings) for which ||G(k + lam delta)|| <= (1 - ls_alpha lam) ||G(k)|| (Armijo's
+sufficient decrease, ls_alpha = 1e-4); no such lam ends the iteration unconverged.
+
 Pinned by tests/test_oracle_navier_stokes.py against: closed forms of c(a, b) and of
 R(U) z for affine fields (their products are P1, so the integrals equal mass-matrix
 products of nodal values); the identity R(U) z = c(z, U) between the two code paths;
@@ -86,6 +91,7 @@ class NewtonInfo:
     norms: list = field(default_factory=list)   # ||G|| before each step and at exit
     etas: list = field(default_factory=list)    # forcing term of each step
     linear_its: list = field(default_factory=list)
+    lambdas: list = field(default_factory=list)  # step length of each step (line search)
 
 
 class NavierStokesStages:
@@ -215,9 +221,11 @@ class NavierStokesStages:
         return solve
 
     def newton(self, F: np.ndarray, u_n: np.ndarray, k0: np.ndarray, g_stages=None, rtol: float = 1e-8,
-               atol: float = 0.0, maxit: int = 20, ew: EWParams | None = None, linear_solve=None):
+               atol: float = 0.0, maxit: int = 20, ew: EWParams | None = None, linear_solve=None,
+               linesearch: bool = False, ls_alpha: float = 1e-4, ls_maxit: int = 12):
         """Newton's method on G(k) = 0 from k0.  linear_solve(Jmat, b, eta) -> (delta,
-        iterations) must satisfy ||b - J delta|| <= eta ||b||; default: exact solves."""
+        iterations) must satisfy ||b - J delta|| <= eta ||b||; default: exact solves.
+        linesearch: backtracking on ||G|| (module docstring)."""
         ew = ew or EWParams()
         solve = linear_solve or self.direct_solver()
         k = np.array(k0, dtype=np.float64)
@@ -236,13 +244,23 @@ class NavierStokesStages:
                 break
             eta = ew_forcing(info.iterations, norm, norm_prev, eta_prev, ew, max(atol, rtol * norm0))
             delta, lits = solve(self.jacobian(u_n, k, g_stages), -G, eta)
-            k = k + delta
+            lam = 1.0
+            for trial in range(ls_maxit + 1 if linesearch else 1):
+                kt = k + lam * delta
+                Gt = self.residual(F, u_n, kt, g_stages)
+                nt = float(np.linalg.norm(Gt))
+                if not linesearch or nt <= (1.0 - ls_alpha * lam) * norm:
+                    break
+                lam *= 0.5
+            else:
+                return k, info  # no sufficient decrease: unconverged, k the last iterate
+            k, G = kt, Gt
             info.etas.append(eta)
             info.linear_its.append(lits)
+            info.lambdas.append(lam)
             info.iterations += 1
             eta_prev, norm_prev = eta, norm
-            G = self.residual(F, u_n, k, g_stages)
-            norm = float(np.linalg.norm(G))
+            norm = nt
             info.norms.append(norm)
             if not np.isfinite(norm):
                 break

@@ -239,3 +239,27 @@ def test_newton_time_stepping_temporal_order():
     errs = [np.linalg.norm(run(m) - ref) for m in (4, 8, 16)]
     rates = np.log2(np.array(errs[:-1]) / np.array(errs[1:]))
     assert np.all(rates > 2.6), (errs, rates)
+
+
+def test_newton_line_search():
+    # a step too large for full Newton steps from k = 0: the backtracking line search
+    # converges (Armijo decrease every step, full steps once close), full steps do not
+    S, th, b, c = _ns("radauIIA", 3, 2, 4, dt=0.2, nu=0.02)
+    forcing, u_n = _problem(S, th, seed=8, amp=30.0)
+    fn = [th.interpolate(forcing, ci * S.dt) for ci in c]
+    F = S.S.rhs(fn, u_n, np.zeros(th.nverts))
+    _, full = S.newton(F, u_n, np.zeros(S.n), rtol=1e-12, maxit=30)
+    assert not full.converged
+    k, ls = S.newton(F, u_n, np.zeros(S.n), rtol=1e-12, maxit=30, linesearch=True)
+    assert ls.converged and ls.iterations <= 15
+    assert min(ls.lambdas) < 1.0 and ls.lambdas[-1] == 1.0
+    n = np.array(ls.norms)
+    lam = np.array(ls.lambdas)
+    assert np.all(n[1:] <= (1 - 1e-4 * lam) * n[:-1])
+    # on an easy problem every step is a full step: the same iterates as plain Newton
+    S2, th2, b2, c2 = _ns("radauIIA", 2, 2, 4, dt=0.1, nu=0.02)
+    forcing2, u2 = _problem(S2, th2)
+    F2 = S2.S.rhs([th2.interpolate(forcing2, ci * S2.dt) for ci in c2], u2, np.zeros(th2.nverts))
+    k1, i1 = S2.newton(F2, u2, np.zeros(S2.n), rtol=1e-13)
+    k2, i2 = S2.newton(F2, u2, np.zeros(S2.n), rtol=1e-13, linesearch=True)
+    assert i2.lambdas == [1.0] * i2.iterations and np.array_equal(k1, k2)
