@@ -310,10 +310,16 @@ typedef struct irk_newton_opts {
   double ew_alpha;      /* (1 + sqrt 5) / 2 (in (1, 2])                             */
   double ew_threshold;  /* 0.1                                                      */
   double eta_fixed;     /* 0: Eisenstat--Walker; in (0, 1): this constant forcing    */
+  int linesearch;       /* 1: backtracking line search on ||G|| (not in the paper;
+                           default 0, full Newton steps): k + lam delta with the first
+                           lam in 1, 1/2, ... (at most ls_maxit halvings) giving
+                           ||G(k + lam delta)|| <= (1 - ls_alpha lam) ||G(k)||          */
+  int ls_maxit;         /* 12 (0 .. 60)                                              */
+  double ls_alpha;      /* 1e-4 (in (0, 1))                                          */
 } irk_newton_opts;
-/* history (host, may be NULL): ||G|| before each step and at exit; etas and linear_its
- * (host, may be NULL): each step's forcing term and FGMRES iterations; all hold at most
- * history_cap values. */
+/* history (host, may be NULL): ||G|| before each step and at exit; etas, linear_its and
+ * lambdas (host, may be NULL): each step's forcing term, FGMRES iterations and step
+ * length; all hold at most history_cap values. */
 typedef struct irk_newton_info {
   int iterations, converged, linear_iterations;
   double norm0, norm;   /* ||G(k0)|| and ||G|| at exit                              */
@@ -323,10 +329,12 @@ typedef struct irk_newton_info {
   int history_cap;
   double ms_linear;     /* GPU time of the linear solves                            */
   double ms_wall;       /* host wall time of the call (returns synchronised)        */
+  double* lambdas;
 } irk_newton_info;
 void irk_newton_default_opts(irk_newton_opts* opt);
-/* Returns IRK_OK, IRK_ENOCONV (maxit Newton steps without convergence; k holds the last
- * iterate) or an error. */
+/* Returns IRK_OK, IRK_ENOCONV (maxit Newton steps without convergence, or no step length
+ * of the line search gave sufficient decrease; k holds the last accepted iterate) or an
+ * error. */
 irk_status irk_ns_newton_solve(irk_mg* h, const double* F, const double* state, const double* g_stages,
                                double* k, const irk_newton_opts* opt, irk_newton_info* info, void* stream);
 

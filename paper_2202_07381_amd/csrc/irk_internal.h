@@ -291,7 +291,7 @@ struct Handle {
   int32_t *ns_cells = nullptr, *ns_cell_free = nullptr, *ns_free = nullptr, *ns_inc_ptr = nullptr,
           *ns_inc = nullptr;
   double *ns_geo = nullptr, *ns_w = nullptr, *ns_U = nullptr, *ns_elem = nullptr;
-  double *ns_k = nullptr, *ns_F = nullptr, *ns_G = nullptr;  // Newton iterate, rhs, residual
+  double *ns_k = nullptr, *ns_kt = nullptr, *ns_F = nullptr, *ns_G = nullptr;  // iterate, trial, rhs, residual
 };
 
 // ------------------------------------------------------------------------ launchers

@@ -333,6 +333,7 @@ irk_status ns_init(irk_mg* h, hipStream_t s) {
   CHK(dalloc(h, &h->ns_U, (size_t)H.nn * d * r));
   CHK(dalloc(h, &h->ns_elem, (size_t)H.nc * nl * d * r));
   CHK(dalloc(h, &h->ns_k, (size_t)L.N));
+  CHK(dalloc(h, &h->ns_kt, (size_t)L.N));
   CHK(dalloc(h, &h->ns_F, (size_t)L.N));
   CHK(dalloc(h, &h->ns_G, (size_t)L.N));
   HIPCHK(hipStreamSynchronize(s));
@@ -1485,15 +1486,20 @@ void irk_newton_default_opts(irk_newton_opts* o) {
   o->ew_alpha = 0.5 * (1.0 + std::sqrt(5.0));
   o->ew_threshold = 0.1;
   o->eta_fixed = 0.0;
+  o->linesearch = 0;
+  o->ls_maxit = 12;
+  o->ls_alpha = 1e-4;
 }
 
 // R = F - J k - c(U - w, U): minus the residual of the stage equations of Sec. 3.2 (F
-// from irk_rhs on this handle), into ns_G; state and g_st as in the public calls.
-static irk_status ns_residual_int(irk_mg* h, const double* state, const double* g_st, hipStream_t s) {
-  CHK(ns_stage_values(h, state, h->ns_k, g_st, s));
+// from irk_rhs on this handle, in ns_F) at k (internal layout), into ns_G; state and g_st
+// as in the public calls.
+static irk_status ns_residual_int(irk_mg* h, const double* state, const double* g_st, const double* kk,
+                                  hipStream_t s) {
+  CHK(ns_stage_values(h, state, kk, g_st, s));
   const bool jac = h->ns_jac;
   h->ns_jac = false;
-  irk_status st = apply_J(h, h->ns_k, h->ns_G, false, h->ns_F, s);
+  irk_status st = apply_J(h, kk, h->ns_G, false, h->ns_F, s);
   h->ns_jac = jac;
   CHK(st);
   CHK(ns_correction(h, 0, nullptr, h->ns_G, -1.0, s));
@@ -1509,7 +1515,7 @@ irk_status irk_ns_residual(irk_mg* h, const double* F, const double* state, cons
   DevLevel& L = h->dev[h->nlevels - 1];
   HIPCHK(k::to_internal<double>(L, k, h->ns_k, s));
   HIPCHK(k::to_internal<double>(L, F, h->ns_F, s));
-  CHK(ns_residual_int(h, state, g_stages, s));
+  CHK(ns_residual_int(h, state, g_stages, h->ns_k, s));
   HIPCHK(k::to_abi<double>(L, h->ns_G, R, s));
   return IRK_OK;
 }
@@ -1542,7 +1548,8 @@ irk_status irk_ns_newton_solve(irk_mg* h, const double* F, const double* state, 
   if (!(o.rtol >= 0) || !(o.atol >= 0) || o.maxit < 0 || o.linear_maxit < 1 || o.restart < 1 ||
       o.restart > 1000 || !(o.eta0 > 0 && o.eta0 < 1) || !(o.eta_max > 0 && o.eta_max < 1) ||
       !(o.ew_gamma > 0 && o.ew_gamma <= 1) || !(o.ew_alpha > 1 && o.ew_alpha <= 2) || !(o.ew_threshold >= 0) ||
-      !(o.eta_fixed >= 0 && o.eta_fixed < 1))
+      !(o.eta_fixed >= 0 && o.eta_fixed < 1) || o.linesearch < 0 || o.linesearch > 1 || o.ls_maxit < 0 ||
+      o.ls_maxit > 60 || !(o.ls_alpha > 0 && o.ls_alpha < 1))
     return fail(IRK_EINVAL, "invalid Newton options");
   const auto t0 = std::chrono::steady_clock::now();
   hipStream_t s = S(stream);
@@ -1553,15 +1560,20 @@ irk_status irk_ns_newton_solve(irk_mg* h, const double* F, const double* state, 
   HIPCHK(k::to_internal<double>(L, F, h->ns_F, s));
   HIPCHK(k::to_internal<double>(L, k, h->ns_k, s));
   int it = 0, lin = 0, nhist = 0;
-  bool converged = false;
+  bool converged = false, ls_failed = false;
   double norm0 = 0, norm = 0, norm_prev = 0, eta_prev = o.eta0;
   float ms_lin = 0;
   irk_status st = IRK_OK;
-  for (;;) {
-    CHK(ns_residual_int(h, state, g_stages, s));
+  // ||G(kk)||, the residual left in ns_G
+  auto residual_norm = [&](const double* kk, double* out) -> irk_status {
+    CHK(ns_residual_int(h, state, g_stages, kk, s));
     HIPCHK(k::dot(h->ns_G, h->ns_G, N, h->partials, h->scal, s, 1));
-    HIPCHK(hipMemcpyAsync(&norm, h->scal, sizeof(double), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipMemcpyAsync(out, h->scal, sizeof(double), hipMemcpyDeviceToHost, s));
     HIPCHK(hipStreamSynchronize(s));
+    return IRK_OK;
+  };
+  CHK(residual_norm(h->ns_k, &norm));
+  for (;;) {
     if (info && info->history && nhist < info->history_cap) info->history[nhist] = norm;
     ++nhist;
     if (!std::isfinite(norm)) return fail(IRK_ENAN, "non-finite Navier--Stokes residual");
@@ -1601,9 +1613,29 @@ irk_status irk_ns_newton_solve(irk_mg* h, const double* F, const double* state, 
     lin += li.iterations;
     ms_lin += (float)li.ms_total;
     if (info && info->linear_its && it < info->history_cap) info->linear_its[it] = li.iterations;
-    HIPCHK(k::axpby(h->ns_k, h->kx, N, 1.0, 1.0, s));
+    // k + lam delta: lam = 1, or with the line search the first of 1, 1/2, ... giving
+    // ||G|| <= (1 - ls_alpha lam) ||G(k)|| (sufficient decrease)
+    double lam = 1.0, nt = 0.0;
+    bool ok = false;
+    for (int t = 0; t <= (o.linesearch ? o.ls_maxit : 0); ++t) {
+      HIPCHK(hipMemcpyAsync(h->ns_kt, h->ns_k, (size_t)N * sizeof(double), hipMemcpyDeviceToDevice, s));
+      HIPCHK(k::axpby(h->ns_kt, h->kx, N, lam, 1.0, s));
+      CHK(residual_norm(h->ns_kt, &nt));
+      if (!o.linesearch || (std::isfinite(nt) && nt <= (1.0 - o.ls_alpha * lam) * norm)) {
+        ok = true;
+        break;
+      }
+      lam *= 0.5;
+    }
+    if (!ok) {  // no sufficient decrease: k stays the last accepted iterate
+      ls_failed = true;
+      break;
+    }
+    std::swap(h->ns_k, h->ns_kt);
+    if (info && info->lambdas && it < info->history_cap) info->lambdas[it] = lam;
     eta_prev = eta;
     norm_prev = norm;
+    norm = nt;
     ++it;
   }
   HIPCHK(k::to_abi<double>(L, h->ns_k, k, s));
@@ -1618,7 +1650,7 @@ irk_status irk_ns_newton_solve(irk_mg* h, const double* F, const double* state, 
     info->ms_wall = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
   }
   if (!converged) {
-    g_err = "Newton reached maxit";
+    g_err = ls_failed ? "Newton line search found no sufficient decrease" : "Newton reached maxit";
     return IRK_ENOCONV;
   }
   return IRK_OK;

@@ -68,14 +68,15 @@ class irk_kernel_stats(C.Structure):
 class irk_newton_opts(C.Structure):
     _fields_ = [("rtol", C.c_double), ("atol", C.c_double), ("maxit", C.c_int), ("linear_maxit", C.c_int),
                 ("restart", C.c_int), ("eta0", C.c_double), ("eta_max", C.c_double), ("ew_gamma", C.c_double),
-                ("ew_alpha", C.c_double), ("ew_threshold", C.c_double), ("eta_fixed", C.c_double)]
+                ("ew_alpha", C.c_double), ("ew_threshold", C.c_double), ("eta_fixed", C.c_double),
+                ("linesearch", C.c_int), ("ls_maxit", C.c_int), ("ls_alpha", C.c_double)]
 
 
 class irk_newton_info(C.Structure):
     _fields_ = [("iterations", C.c_int), ("converged", C.c_int), ("linear_iterations", C.c_int),
                 ("norm0", C.c_double), ("norm", C.c_double), ("history", C.POINTER(C.c_double)),
                 ("etas", C.POINTER(C.c_double)), ("linear_its", C.POINTER(C.c_int)), ("history_cap", C.c_int),
-                ("ms_linear", C.c_double), ("ms_wall", C.c_double)]
+                ("ms_linear", C.c_double), ("ms_wall", C.c_double), ("lambdas", C.POINTER(C.c_double))]
 
 
 KERNELS = {"patch_apply": 0, "residual": 1, "gather_update": 2, "ns_element": 3, "ns_gather": 4}
@@ -384,17 +385,18 @@ class IrkMG:
                 raise TypeError(f"unknown Newton option {key}")
             setattr(o, key, val)
         cap = max(1, history_cap)
-        hist, etas, lits = np.zeros(cap), np.zeros(cap), np.zeros(cap, dtype=np.int32)
+        hist, etas, lits, lams = np.zeros(cap), np.zeros(cap), np.zeros(cap, dtype=np.int32), np.zeros(cap)
         info = irk_newton_info(0, 0, 0, 0.0, 0.0, hist.ctypes.data_as(C.POINTER(C.c_double)),
                                etas.ctypes.data_as(C.POINTER(C.c_double)), lits.ctypes.data_as(C.POINTER(C.c_int)),
-                               cap, 0.0, 0.0)
+                               cap, 0.0, 0.0, lams.ctypes.data_as(C.POINTER(C.c_double)))
         status = _check(lib.irk_ns_newton_solve(self.h, _dev(F, n, "F"), st, g, _dev(k, n, "k"), C.byref(o),
                                                 C.byref(info), _stream(stream)), ok=(IRK_OK, IRK_ENOCONV))
         its = info.iterations
         return dict(status=status, iterations=its, converged=bool(info.converged),
                     linear_iterations=info.linear_iterations, norm0=info.norm0, norm=info.norm,
                     history=hist[: min(cap, its + 1)].copy(), etas=etas[: min(cap, its)].copy(),
-                    linear_its=lits[: min(cap, its)].copy(), ms_linear=info.ms_linear, ms_wall=info.ms_wall)
+                    linear_its=lits[: min(cap, its)].copy(), lambdas=lams[: min(cap, its)].copy(),
+                    ms_linear=info.ms_linear, ms_wall=info.ms_wall)
 
     # ---------------------------------------------------------- measurement
     def irk_mg_profile(self, mode):

@@ -345,3 +345,42 @@ def test_ns_newton_time_stepping_temporal_order():
     rates = np.log2(np.array(errs[:-1]) / np.array(errs[1:]))
     say(f"[ns-order] errors {errs} rates {rates}")
     assert np.all(rates > 2.6), (errs, rates)
+
+
+def test_ns_newton_line_search():
+    # the oracle's line-search case (4^2, RadauIIA(3), dt = 0.2, nu = 0.02, a rough state
+    # and a strong force): full Newton steps diverge there; with the backtracking line
+    # search every accepted step meets the decrease condition and the iteration ends at
+    # the oracle's solution
+    from oracle.fem import TaylorHood as TH
+    from oracle.tableau import tableau as tab
+    from paper_2202_07381_amd import irkmg
+
+    lv = wl.square_hierarchy(2, 2)
+    A, b, c = irkmg.irk_tableau_builtin("radauIIA", 3)
+    dt, nu = 0.2, 0.02
+    say("[ns-ls] setup 4x4 RadauIIA(3) dt=0.2 nu=0.02")
+    g = irkmg.IrkMG(lv, A, b, c, dt, nu)
+    th = TH(lv[-1].xyz, lv[-1].cells)
+    Ao, _, co = tab("radauIIA", 3)
+    ns = NavierStokesStages(th, Ao, dt, nu)
+    f = wl.forcing_2d(8)
+    rng = np.random.default_rng(8)
+    u_n = 0.5 * rng.standard_normal(th.nvel)
+    state = np.concatenate([u_n, np.zeros(th.nverts)])
+    fst = np.stack([30.0 * f(th.node_xyz, ci * dt) for ci in co])
+    F = _gpu_rhs(g, fst, state)
+    k = torch.zeros(ns.n, dtype=torch.float64, device="cuda")
+    info = g.irk_ns_newton_solve(F, to_dev(state), k, rtol=1e-11, maxit=40, linesearch=1)
+    say(f"[ns-ls] its={info['iterations']} lambdas={info['lambdas'].tolist()}")
+    assert info["converged"]
+    h, lam = info["history"], info["lambdas"]
+    assert min(lam) < 1.0
+    assert np.all(h[1:] <= (1 - 1e-4 * lam) * h[:-1])
+    Fo = ns.S.rhs(list(fst), u_n, np.zeros(th.nverts))
+    ko, oinfo = ns.newton(Fo, u_n, np.zeros(ns.n), rtol=1e-13, maxit=40, linesearch=True)
+    assert oinfo.converged
+    pm = ns.S.project_pressure_mean
+    assert np.linalg.norm(ns.residual(Fo, u_n, to_host(k))) <= 1e-10 * h[0]
+    assert relerr(pm(to_host(k)), pm(ko)) < 1e-8
+    g.close()
