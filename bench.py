@@ -255,6 +255,11 @@ def stored_traffic():
 # Iterations per time step reported in Table 1 (2D Stokes, crossed 8x8 mesh refined l
 # times, dt = 0.5/2^(l+3), Chebyshev [2, 8] with 2/2 steps): {(r, l): its/step}.
 PAPER_T1_RADAU_ITS = {(2, 5): 8.70, (2, 6): 10.99, (2, 7): 14.22, (3, 5): 9.32, (3, 6): 12.40, (3, 7): 13.91}
+# Table 3 (the same runs with the time step fixed at 0.5/2^8): iterations per step by
+# (family, stages, level)
+PAPER_T3_ITS = {("radauIIA", 2, 5): 8.70, ("radauIIA", 2, 6): 12.18, ("radauIIA", 2, 7): 18.04,
+                ("radauIIA", 3, 5): 9.32, ("radauIIA", 3, 6): 14.22, ("radauIIA", 3, 7): 17.30,
+                ("lobattoIIIC", 3, 5): 9.61, ("lobattoIIIC", 3, 6): 14.60, ("lobattoIIIC", 3, 7): 17.47}
 
 
 def p2p1_errors(level, vel, p, exact):
@@ -298,11 +303,14 @@ def p2p1_errors(level, vel, p, exact):
     return float(vel_err), float(p_err)
 
 
-def run_t1(ell, r, precision=0, max_steps=None, log_every=32, fixed_rtol=None, auto_interval=False):
+def run_t1(ell, r, precision=0, max_steps=None, log_every=32, fixed_rtol=None, auto_interval=False,
+           family="radauIIA", dt_level=None):
     """The paper's 2D Stokes experiment (Sec. 5.1, Table 1): exact solution
     u = (sin(pi x) cos(pi y), -cos(pi x) sin(pi y)) e^{-2 pi^2 t}, p = 0 (so f = 0 and the
-    boundary data drive the flow), nu = 1, RadauIIA(r), FGMRES with the Chebyshev-relaxed
-    V-cycle, stopping at an absolute residual below 1e-2 N^-3 or a relative 1e-8."""
+    boundary data drive the flow), nu = 1, RadauIIA(r) (or LobattoIIIC(r)), FGMRES with the
+    Chebyshev-relaxed V-cycle, stopping at an absolute residual below 1e-2 N^-3 or a
+    relative 1e-8.  dt = 0.5/2^(dt_level+3) with dt_level = ell (Table 1) or fixed at 5
+    (Table 3: dt = 0.5/2^8 on every level)."""
     import math
 
     import numpy as np
@@ -312,8 +320,8 @@ def run_t1(ell, r, precision=0, max_steps=None, log_every=32, fixed_rtol=None, a
     from paper_2202_07381_amd import workloads as wl
 
     levels = wl.crossed_hierarchy(8, ell + 1)
-    A, b, c = irkmg.irk_tableau_builtin("radauIIA", r)
-    nsteps = 2 ** (ell + 3)
+    A, b, c = irkmg.irk_tableau_builtin(family, r)
+    nsteps = 2 ** ((ell if dt_level is None else dt_level) + 3)
     dt = 0.5 / nsteps
     t0 = time.time()
     g = irkmg.IrkMG(levels, A, b, c, dt, 1.0, weighting=0, precision=precision, smoother=1, interval=(2.0, 8.0))
@@ -389,13 +397,14 @@ def run_t1(ell, r, precision=0, max_steps=None, log_every=32, fixed_rtol=None, a
         "value": mean_its, "unit": "iterations per step", "higher_is_better": False,
         "n_gpus": 1, "steps": steps, "dtype": "f64" if precision == 0 else "f64 (FP32 patches)",
         "data": "synthetic (the paper's exact solution)",
-        "config": {"workload": f"2D Stokes, crossed 8x8 refined l={ell} times, RadauIIA({r}), dt=0.5/2^{ell + 3}, "
+        "config": {"workload": f"2D Stokes, crossed 8x8 refined l={ell} times, {family}({r}), dt=0.5/{nsteps}, "
                                f"Chebyshev [{interval[0]:.4g},{interval[1]:.4g}] 2/2, unweighted additive Vanka, "
                                + (f"stop at {fixed_rtol:g} rel" if fixed_rtol is not None
                                   else "stop at 1e-2 N^-3 abs or 1e-8 rel"),
                    "l": ell, "stages": r, "unknowns": N, "dofs_per_stage": N // r, "time_steps_total": nsteps},
         "iterations_per_step_mean": mean_its, "iterations_min_max": [min(its), max(its)],
-        "paper_iterations_per_step": PAPER_T1_RADAU_ITS.get((r, ell)),
+        "paper_iterations_per_step": (PAPER_T1_RADAU_ITS.get((r, ell)) if family == "radauIIA" and dt_level is None
+                                      else PAPER_T3_ITS.get((family, r, ell)) if dt_level == 5 else None),
         "time_s": elapsed, "setup_s": setup_s, "t_per_krylov_it_ms": 1e3 * elapsed / sum(its),
         "final_time": T, "velocity_rel_l2_error": vel_err, "pressure_l2_error": p_err,
     }
@@ -700,6 +709,9 @@ def main():
     ap.add_argument("--batch-count", type=int, default=64)
     ap.add_argument("--t1-level", type=int, default=5, help="t1: refinement level l of the crossed 8x8 mesh")
     ap.add_argument("--t1-stages", type=int, default=2, choices=[2, 3], help="t1: RadauIIA stages")
+    ap.add_argument("--t1-family", default="radauIIA", choices=["radauIIA", "lobattoIIIC"], help="t1: IRK family")
+    ap.add_argument("--t1-dt-level", type=int, default=None,
+                    help="t1: dt = 0.5/2^(this+3) instead of the level's own (5: the fixed step of Table 3)")
     ap.add_argument("--t1-max-steps", type=int, default=None, help="t1: stop after this many time steps")
     ap.add_argument("--t1-fp32", action="store_true", help="t1: FP32 patch factors")
     ap.add_argument("--t1-auto-interval", action="store_true",
@@ -737,6 +749,7 @@ def main():
         return
     if args.workload == "t1":
         print(json.dumps(run_t1(args.t1_level, args.t1_stages, 1 if args.t1_fp32 else 0, args.t1_max_steps,
+                                family=args.t1_family, dt_level=args.t1_dt_level,
                                 fixed_rtol=args.t1_rtol, auto_interval=args.t1_auto_interval)), flush=True)
         return
     nlev = int(round(np.log2(args.n // 4))) + 1
