@@ -709,7 +709,8 @@ def main():
     ap.add_argument("--batch-count", type=int, default=64)
     ap.add_argument("--t1-level", type=int, default=5, help="t1: refinement level l of the crossed 8x8 mesh")
     ap.add_argument("--t1-stages", type=int, default=2, choices=[2, 3], help="t1: RadauIIA stages")
-    ap.add_argument("--t1-family", default="radauIIA", choices=["radauIIA", "lobattoIIIC"], help="t1: IRK family")
+    ap.add_argument("--t1-family", default="radauIIA", choices=["radauIIA", "gauss", "lobattoIIIC"],
+                    help="t1: IRK family")
     ap.add_argument("--t1-dt-level", type=int, default=None,
                     help="t1: dt = 0.5/2^(this+3) instead of the level's own (5: the fixed step of Table 3)")
     ap.add_argument("--t1-max-steps", type=int, default=None, help="t1: stop after this many time steps")
