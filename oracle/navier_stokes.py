@@ -44,7 +44,10 @@ R(U) z for affine fields (their products are P1, so the integrals equal mass-mat
 products of nodal values); the identity R(U) z = c(z, U) between the two code paths;
 central differences of G, which are exact for a quadratic map, against the assembled
 Jacobian; the stage equations written out stage by stage with a double loop over a_ij
-at the Newton solution; and quadratic convergence of the exact-solve iteration.
+at the Newton solution; quadratic convergence of the exact-solve iteration; temporal
+order 3 of RadauIIA(2) stepping on a manufactured Navier--Stokes solution; and, for the
+line search, convergence where full steps diverge, the decrease condition at every
+accepted step, and bitwise equality with plain Newton when every step is full.
 """
 from __future__ import annotations
 
