@@ -281,7 +281,10 @@ irk_status irk_update(irk_mg* h, const double* k, double* state, void* stream);
  * r x nnodes x dim stage boundary data or NULL.  All vectors in the ABI layout.
  * Errors: IRK_EINVAL (null pointers, invalid options), IRK_ENAN (non-finite residual),
  * IRK_EHIP, IRK_ENOMEM (the first call allocates the element data, about
- * (nloc dim r + (dim+1) dim + nloc + 1) 8 ncells bytes). */
+ * (nloc dim r + (dim+1) dim + nloc + 1) 8 ncells bytes, the stage values, nnodes dim r
+ * doubles, and four vectors of ndofs doubles).  irk_ns_residual and irk_ns_jacobian_apply
+ * are stream-ordered; irk_ns_newton_solve reads norms on the host and returns
+ * synchronised. */
 
 /* R = F - J_w k - c(U - w, U), i.e. -G(k). */
 irk_status irk_ns_residual(irk_mg* h, const double* F, const double* state, const double* g_stages,
