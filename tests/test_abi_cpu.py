@@ -184,3 +184,37 @@ def test_hessenberg_eigenvalues_against_lapack():
     assert all(np.min(np.abs(ev - z)) < 1e-12 for z in want)
     with pytest.raises(irkmg.IrkError):
         irkmg.irk_hessenberg_eigs(np.zeros((3, 3)), 0)
+
+
+def test_struct_layouts_match_the_header(tmp_path):
+    # every ctypes structure of the binding has the size and field offsets that a C
+    # compiler gives the header's struct (a field added on one side only fails here)
+    import ctypes
+    import shutil
+    import subprocess
+
+    from paper_2202_07381_amd import irkmg
+
+    cc = shutil.which("gcc") or shutil.which("cc")
+    if cc is None:
+        pytest.skip("no C compiler")
+    structs = [irkmg.irk_mesh_level, irkmg.irk_tableau, irkmg.irk_mg_opts, irkmg.irk_solve_info,
+               irkmg.irk_batch_opts, irkmg.irk_kernel_stats, irkmg.irk_newton_opts, irkmg.irk_newton_info]
+    lines = ['#include <stdio.h>', '#include <stddef.h>', f'#include "{irkmg.HEADER}"', "int main(void) {"]
+    for st in structs:
+        name = st.__name__
+        lines.append(f'  printf("{name} %zu\\n", sizeof({name}));')
+        for field, _ in st._fields_:
+            lines.append(f'  printf("{name}.{field} %zu\\n", offsetof({name}, {field}));')
+    lines += ["  return 0;", "}"]
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines) + "\n")
+    exe = tmp_path / "layout"
+    subprocess.run([cc, str(src), "-o", str(exe)], check=True)
+    out = dict(line.split() for line in subprocess.run([str(exe)], check=True, capture_output=True,
+                                                        text=True).stdout.splitlines())
+    for st in structs:
+        name = st.__name__
+        assert int(out[name]) == ctypes.sizeof(st), name
+        for field, _ in st._fields_:
+            assert int(out[f"{name}.{field}"]) == getattr(st, field).offset, (name, field)
