@@ -8,13 +8,10 @@ solves; the stage Jacobian's condition number at these sizes keeps the error of 
 below that bound); time stepping 1e-8 after three steps.  The Eisenstat--Walker
 forcing terms the library chose are recomputed from its residual history with the
 oracle's formula (1e-14)."""
-import ctypes as C
-
 import numpy as np
 import pytest
 
 from gpu_cases import CASES, gpu_of, levels_of, oracle_of, relerr, say, to_dev, to_host
-from oracle.fem import TaylorHood
 from oracle.navier_stokes import EWParams, NavierStokesStages, ew_forcing
 from paper_2202_07381_amd import workloads as wl
 
