@@ -21,7 +21,6 @@ them and L quadratic), second-order-accurate differences in nu.
 from __future__ import annotations
 
 import numpy as np
-import scipy.sparse as sp
 
 from .stage import StageSystem
 

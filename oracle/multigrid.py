@@ -30,7 +30,6 @@ from __future__ import annotations
 
 import numpy as np
 import scipy.linalg as sla
-import scipy.sparse as sp
 
 from .fem import TaylorHood
 from .stage import StageSystem

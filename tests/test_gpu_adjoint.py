@@ -9,7 +9,7 @@ the forcing, so there the difference quotient is exact up to solver error / h)."
 import numpy as np
 import pytest
 
-from gpu_cases import forcing_rhs, gpu_of, levels_of, oracle_of, relerr, say, to_dev, to_host
+from gpu_cases import gpu_of, levels_of, oracle_of, relerr, say, to_dev, to_host
 
 pytestmark = pytest.mark.gpu
 torch = pytest.importorskip("torch")

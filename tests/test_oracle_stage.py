@@ -1,7 +1,6 @@
 """Pins for oracle/stage.py: the stage equations of Sec. 3.1 written stage by stage."""
 import numpy as np
 import pytest
-import scipy.sparse as sp
 
 from oracle.fem import TaylorHood
 from oracle.stage import StageSystem

@@ -1,7 +1,6 @@
 """Pins for oracle/transfer.py: polynomial reproduction and the Galerkin identity."""
 import numpy as np
 import pytest
-import scipy.sparse as sp
 
 from oracle.fem import TaylorHood
 from oracle.stage import StageSystem
