@@ -22,9 +22,14 @@ Mixed precision: with dtype=float32 the level operators, patch inverses and
 vectors of the V-cycle are float32 and the coarse solve stays float64, as in the
 FP32-patch variant of the HIP library.
 
-Pinned by tests/test_oracle_multigrid.py: coarse solve residual; two-grid and V-cycle
-contraction; FGMRES-MG solution equal to the dense direct solve; mesh-independent
-iteration counts.
+Pinned by tests/test_oracle_vcycle_propagator.py: V J equals the textbook error
+propagator G^post (I - P B_c P^T J) G^pre (G = I - omega W S J, B_c the coarser cycle),
+assembled from dense matrices, for two- and three-level cycles, unequal pre/post
+counts, Oseen operators and Chebyshev relaxation (whose factor is the closed-form
+Chebyshev polynomial of S J); one sweep against k + omega W S (F - J k); two-grid and
+V-cycle contraction (spectral radius about 0.3).  By tests/test_oracle_multigrid.py:
+coarse solve residual; FGMRES-MG solution equal to the dense direct solve;
+mesh-independent iteration counts.
 """
 from __future__ import annotations
 
