@@ -22,8 +22,10 @@ update work are charged to the V-cycles.
 The roofline object is for the dominant kernel, the finest-level patch apply, timed
 with HIP events around each of its launches on its own stream inside the timed
 region; achieved = algorithmic bytes per launch / average launch time.
-The cpu_baseline object times the CPU oracle's V-cycle on a bounded sample (the same
-workload family on the 128 x 128 mesh, 6 levels), single-threaded.
+The cpu_baseline object times the CPU oracle on a bounded sample (the same workload on
+the 128 x 128 mesh, 6 levels, by default; --cpu-n 256 for the benchmark mesh itself):
+setup, one V-cycle and the full solve of the first step, BLAS on every core the
+process may use.
 """
 from __future__ import annotations
 
@@ -133,32 +135,59 @@ def run_precision(precision, levels, A, b, c, dt, nu, mms, nodes, steps, warmup,
     return out
 
 
-def cpu_baseline(A, dt, nu):
+def cpu_baseline(A, c, dt, nu, n):
+    """The oracle on the host cores: setup (assembly of every level and the patch
+    inverses), one V-cycle (mean of 2 after a warm-up) and the full FGMRES(30) solve
+    of the first step to 1e-8, on the n x n member of the benchmark's workload family
+    (same tableau, dt, nu and manufactured solution), with the BLAS thread pool set to
+    the cores this process may run on."""
     import numpy as np
     from threadpoolctl import threadpool_limits
 
+    from oracle.fgmres import fgmres
     from oracle.multigrid import Hierarchy
     from paper_2202_07381_amd import workloads as wl
 
-    levels = wl.square_hierarchy(4, 6)  # 128 x 128 sample of the same workload family
-    t0 = time.time()
-    H = Hierarchy(levels, A, dt, nu)
-    log(f"oracle setup (128x128) {time.time() - t0:.1f}s")
-    N = H.finest.n
-    rv = np.random.default_rng(7).standard_normal(N)
-    with threadpool_limits(limits=1):
+    cores = len(os.sched_getaffinity(0))
+    nlev = int(round(np.log2(n // 4))) + 1
+    levels = wl.square_hierarchy(4, nlev)
+    with threadpool_limits(limits=cores):
+        t0 = time.perf_counter()
+        H = Hierarchy(levels, A, dt, nu)
+        setup_s = time.perf_counter() - t0
+        log(f"oracle setup ({n}x{n}, {cores} threads) {setup_s:.1f}s")
+        S = H.finest
+        th = S.th
+        N = S.n
+        mms = wl.mms_2d(2, nu)
+        u0 = th.free_velocity(th.interpolate(mms.velocity, 0.0))
+        F = S.rhs([th.interpolate(mms, ci * dt) for ci in c], u0, np.zeros(th.nverts))
+        rv = np.random.default_rng(7).standard_normal(N)
         H.vcycle(rv)
         t0 = time.perf_counter()
         reps = 2
         for _ in range(reps):
             H.vcycle(rv)
-        dtv = (time.perf_counter() - t0) / reps
-    log(f"oracle V-cycle {dtv:.2f}s")
-    return {"value": N / dtv, "unit": "stage-DOF updates/s", "cores": 1, "kind": "oracle",
-            "sample": f"one oracle V-cycle (7-level workload family, here 6 levels on the 128x128 mesh, "
-                      f"{N} unknowns, RadauIIA(3), dt=1e-2, nu=1), mean of {reps} after one warm-up, "
-                      f"single-threaded NumPy/SciPy; setup excluded",
-            "vcycle_s": dtv}
+        vcycle_s = (time.perf_counter() - t0) / reps
+        log(f"oracle V-cycle {vcycle_s:.2f}s")
+        t0 = time.perf_counter()
+        _, info = fgmres(S.apply, H.vcycle, F, np.zeros_like(F), 1e-8, 200, 30, project=S.project_pressure_mean)
+        solve_s = time.perf_counter() - t0
+        log(f"oracle FGMRES solve {solve_s:.1f}s, {info.iterations} iterations")
+    out = {"value": N / vcycle_s, "unit": "stage-DOF updates/s", "cores": cores, "kind": "oracle",
+           "sample": f"the oracle (NumPy/SciPy, FP64) on the {n}x{n} member of the benchmark workload "
+                     f"({nlev} levels, {N} unknowns, RadauIIA(3), dt=1e-2, nu=1, MMS seed 2): setup, one "
+                     f"V-cycle (value = unknowns / V-cycle time, the benchmark's unit) and the full "
+                     f"FGMRES(30) solve of the first step to 1e-8; BLAS threads = {cores} (the patch "
+                     f"inverses and sparse products run on one thread)",
+           "n": n, "unknowns": N, "setup_s": setup_s, "vcycle_s": vcycle_s, "solve_s": solve_s,
+           "solve_iterations": info.iterations}
+    if n != 256:
+        f = 4.0 ** round(np.log2(256 / n))
+        out["extrapolated_to_256"] = {"factor": f, "setup_s": f * setup_s, "vcycle_s": f * vcycle_s,
+                                      "solve_s": f * solve_s,
+                                      "note": "every oracle step is linear in the number of unknowns"}
+    return out
 
 
 # ------------------------------------------------------------ HBM traffic (PMC)
@@ -689,6 +718,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--n", type=int, default=256, help="finest mesh size (power-of-two multiple of 4)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-n", type=int, default=128,
+                    help="mesh of the oracle timing (256: the benchmark mesh itself, about 35 GB and minutes)")
     ap.add_argument("--no-fp32", action="store_true")
     ap.add_argument("--workload", default="stokes256", choices=["stokes256", "batch64", "t1", "relax", "ns"],
                     help="stokes256: the headline line; batch64: the uneven batched workload; t1: the paper's "
@@ -816,7 +847,7 @@ def main():
     if args.calibrate_copy:
         calibration_copies()
     if not args.no_cpu_baseline:
-        line["cpu_baseline"] = cpu_baseline(A, dt, nu)
+        line["cpu_baseline"] = cpu_baseline(A, c, dt, nu, args.cpu_n)
     print(json.dumps(line), flush=True)
 
 

@@ -186,6 +186,7 @@ irk_status irk_mg_ritz(irk_mg* h, int level, int steps, const double* v0, double
  * [lambda/4, lambda] from irk_mg_ritz.  IRK_EINVAL unless 0 < lo < hi < inf. */
 irk_status irk_mg_set_interval(irk_mg* h, double lo, double hi);
 
+
 /* Eigenvalues of the leading m x m block (1 <= m <= 1024) of an upper Hessenberg matrix
  * H (host, column-major, leading dimension ldh >= m) by the shifted QR iteration,
  * sorted by decreasing real part into wr / wi (host, m values).  Host-only. */
@@ -209,6 +210,17 @@ int64_t irk_mg_ndofs(const irk_mg* h, int level);
 /* Level sizes: out[0..4] = nverts, nnodes, nfree, ns (= dim*nfree + nverts), nlevels.
  * level -1 is the finest. */
 irk_status irk_mg_sizes(const irk_mg* h, int level, int64_t* out);
+
+/* Where each field of each stage sits in the ABI layout of level `level` (-1: finest;
+ * Sec. 3.1 orders the unknowns stage by stage, velocity then pressure): offsets (host,
+ * r x (dim + 1), may be NULL) receives, for stage s, offsets[s*(dim+1) + c] = the index
+ * of the first value of velocity component c (c < dim) and offsets[s*(dim+1) + dim] =
+ * that of the pressure; lengths (host, dim + 1, may be NULL) the number of values of
+ * each field (nfree per velocity component, nverts for the pressure).  Velocity value
+ * i of a component belongs to free node i (irk_mg_p2_nodes gives the node numbers);
+ * pressure value v to vertex v.  Errors: IRK_EINVAL (null handle, level out of range,
+ * both outputs NULL). */
+irk_status irk_mg_layout(const irk_mg* h, int level, int64_t* offsets, int64_t* lengths);
 
 /* Coordinates of the P2 nodes of a level (host out, nnodes x dim) and the node index of
  * every free node (host out, nfree; may be NULL). */
@@ -345,20 +357,32 @@ irk_status irk_ns_newton_solve(irk_mg* h, const double* F, const double* state, 
  * sequence of IRK steps with respect to the forcing, the viscosity and the state).
  * irk_rhs_adjoint: the transpose of (f, state) -> F of irk_rhs: given lam (ABI layout),
  *   gf (device, r x nnodes x dim, overwritten) = M_fa^T lam_i^u per stage and component,
- *   gstate (device, ns, overwritten) = [-L^T sum_i lam_i^u - B sum_i lam_i^p ;
- *   -B^T sum_i lam_i^u].
+ *   gstate (device, ns) = [-L^T sum_i lam_i^u - B sum_i lam_i^p ; -B^T sum_i lam_i^u],
+ *   overwritten (accumulate = 0) or added to it (accumulate = 1: the reverse sweep's
+ *   state adjoint gbar_n = gbar_{n+1} + (dF/dstate)^T lam^n in place).
  * irk_update_adjoint: the transpose of irk_update with respect to k: G_i = dt b_i gstate
  *   (G in the ABI layout, overwritten).
- * irk_nu_sensitivity: out (device, one double, overwritten) =
+ * irk_nu_sensitivity: out (device, one double) =
  *   lam^T (dF/dnu - dJ/dnu k) = -sum_i lam_i^u . (K_1 u) - dt sum_ij a_ij lam_i^u . (K_1 k_j^u),
  *   K_1 the vector P2 Laplacian with nu = 1 and u the velocity of `state`
- *   (F and J depend on nu through K = nu K_1; the convection term does not).
- * irk_mass_apply: out (ns) = [M u ; 0] for a state vector (velocity mass). */
-irk_status irk_rhs_adjoint(irk_mg* h, const double* lam, double* gf, double* gstate, void* stream);
+ *   (F and J depend on nu through K = nu K_1; the convection term does not);
+ *   overwritten (accumulate = 0) or added to *out (accumulate = 1: summing the steps).
+ * irk_mass_apply: out (ns) = [M u ; 0] for a state vector (velocity mass).
+ * irk_tracking_loss: the misfit of a state to a target, L = 1/2 e^T M e with e the
+ *   velocity part of state - target (state, target: device, ns values; the pressure is
+ *   not compared).  loss (device, one double, may be NULL) receives L; grad_state and
+ *   grad_target (device, ns, may be NULL) receive s [M e ; 0] and -s [M e ; 0], the
+ *   gradients of s L, with s = *scale (device, one double; NULL means 1).  At least
+ *   one output must be given.  Uses the handle's workspace (stream-ordered).
+ * The accumulate flags take 0 or 1 (else IRK_EINVAL). */
+irk_status irk_rhs_adjoint(irk_mg* h, const double* lam, double* gf, double* gstate, int accumulate,
+                           void* stream);
 irk_status irk_update_adjoint(irk_mg* h, const double* gstate, double* G, void* stream);
 irk_status irk_nu_sensitivity(irk_mg* h, const double* lam, const double* k, const double* state,
-                              double* out, void* stream);
+                              double* out, int accumulate, void* stream);
 irk_status irk_mass_apply(irk_mg* h, const double* state, double* out, void* stream);
+irk_status irk_tracking_loss(irk_mg* h, const double* state, const double* target, const double* scale,
+                             double* loss, double* grad_state, double* grad_target, void* stream);
 
 /* Per-level building blocks, exposed so that each step of the cycle can be checked on
  * its own.  Vectors use the ABI layout of the level named. */

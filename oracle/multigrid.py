@@ -44,13 +44,17 @@ from .vanka import VankaSmoother, patch_dofs
 
 class Hierarchy:
     def __init__(self, mesh_levels, A, dt, nu, wind=None, omega=0.5, weighted=True, pre=2, post=2,
-                 dtype=np.float64, smoother="sweep", interval=(2.0, 8.0)):
+                 dtype=np.float64, smoother="sweep", interval=(2.0, 8.0), level_operators=None):
         """mesh_levels: coarse-to-fine sequence of objects with .xyz and .cells.
         wind: callable (points, t) -> (npts, dim) or None (Stokes).
         smoother: "sweep" (damped additive sweeps, omega and weighting), "chebyshev"
         (Chebyshev relaxation on `interval` with the additive operator, Sec. 5.1) or
         "gmres" (`pre`/`post` steps of GMRES preconditioned by the additive operator,
-        Sec. 4.2, 5.4)."""
+        Sec. 4.2, 5.4).
+        level_operators: None (each level's operator is its StageSystem's J) or a
+        callable (level, StageSystem) -> sparse operator of that level with the same
+        unknowns, e.g. the Newton Jacobian of Sec. 3.2 rediscretised on the level; the
+        relaxation, the coarse solve and the cycle then use those operators (self.ops)."""
         self.A = np.asarray(A, dtype=np.float64)
         self.r = self.A.shape[0]
         self.pre, self.post = pre, post
@@ -69,14 +73,18 @@ class Hierarchy:
             Pu, Pp = interpolation_matrices(self.spaces[lc], self.spaces[lc + 1])
             self.P.append(stage_prolongation(Pu, Pp, self.dim, self.r))
         self.smoothers = [None]
-        self.Jw = [s.J.astype(dtype) for s in self.systems]
+        if level_operators is None:
+            self.ops = [s.J for s in self.systems]
+        else:
+            self.ops = [level_operators(lev, s).tocsr() for lev, s in enumerate(self.systems)]
+        self.Jw = [J.astype(dtype) for J in self.ops]
         self.Pw = [None] + [P.astype(dtype) for P in self.P[1:]]
         for lev in range(1, len(self.spaces)):
             pat = patch_dofs(self.spaces[lev], self.r)
-            self.smoothers.append(VankaSmoother(self.systems[lev].J, pat, omega, weighted, dtype))
+            self.smoothers.append(VankaSmoother(self.ops[lev], pat, omega, weighted, dtype))
         # coarse LU with one pinned pressure per stage
         s0 = self.systems[0]
-        Jc = s0.J.toarray()
+        Jc = self.ops[0].toarray()
         self.pinned = [i * s0.ns + s0.th.nvel for i in range(self.r)]
         for q in self.pinned:
             Jc[q, :] = 0.0

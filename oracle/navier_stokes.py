@@ -39,6 +39,14 @@ on ||G||, k <- k + lam delta with the first lam in 1, 1/2, 1/4, ... (at most ls_
 halvings) for which ||G(k + lam delta)|| <= (1 - ls_alpha lam) ||G(k)|| (Armijo's
 sufficient decrease, ls_alpha = 1e-4); no such lam ends the iteration unconverged.
 
+Newton Jacobian V-cycle (newton_hierarchy): every level rediscretises the stage
+Jacobian at the stage velocities injected from the finest level.  Pinned: injection of
+a P2 interpolant equals the coarse interpolant; at U = 0 the cycle equals the Stokes
+cycle and at a constant U (no reaction term) the Oseen cycle with that wind, to
+rounding; one Vanka sweep with a single patch solves the patch system exactly; and the
+cycle satisfies the error-propagator identity of the multigrid module for its own
+operators.
+
 Pinned by tests/test_oracle_navier_stokes.py against: closed forms of c(a, b) and of
 R(U) z for affine fields (their products are P1, so the integrals equal mass-matrix
 products of nodal values); the identity R(U) z = c(z, U) between the two code paths;
@@ -182,8 +190,12 @@ class NavierStokesStages:
 
     def jacobian(self, u_n: np.ndarray, k: np.ndarray, g_stages=None) -> sp.csr_matrix:
         """dG/dk at k: J_S plus dt a_ij N'(U_i) in the velocity block (i, j)."""
+        return self.jacobian_at(self.stage_values(u_n, k, g_stages))
+
+    def jacobian_at(self, U: list) -> sp.csr_matrix:
+        """The stage Jacobian for given nodal stage velocities U_i (nnodes, dim):
+        block (i, j) = delta_ij M + dt a_ij (K + N'(U_i)) with the B, B^T blocks."""
         nvel = self.th.nvel
-        U = self.stage_values(u_n, k, g_stages)
         blocks = [[None] * self.r for _ in range(self.r)]
         for i in range(self.r):
             Np = self.nprime(U[i])
@@ -225,9 +237,11 @@ class NavierStokesStages:
 
     def newton(self, F: np.ndarray, u_n: np.ndarray, k0: np.ndarray, g_stages=None, rtol: float = 1e-8,
                atol: float = 0.0, maxit: int = 20, ew: EWParams | None = None, linear_solve=None,
-               linesearch: bool = False, ls_alpha: float = 1e-4, ls_maxit: int = 12):
+               linesearch: bool = False, ls_alpha: float = 1e-4, ls_maxit: int = 12, linear_solve_at=None):
         """Newton's method on G(k) = 0 from k0.  linear_solve(Jmat, b, eta) -> (delta,
         iterations) must satisfy ||b - J delta|| <= eta ||b||; default: exact solves.
+        linear_solve_at(Jmat, b, eta, U), if given instead, also receives the nodal stage
+        velocities U_i of the iterate (to build a preconditioner for the Jacobian there).
         linesearch: backtracking on ||G|| (module docstring)."""
         ew = ew or EWParams()
         solve = linear_solve or self.direct_solver()
@@ -246,7 +260,11 @@ class NavierStokesStages:
             if info.iterations >= maxit:
                 break
             eta = ew_forcing(info.iterations, norm, norm_prev, eta_prev, ew, max(atol, rtol * norm0))
-            delta, lits = solve(self.jacobian(u_n, k, g_stages), -G, eta)
+            if linear_solve_at is not None:
+                U = self.stage_values(u_n, k, g_stages)
+                delta, lits = linear_solve_at(self.jacobian_at(U), -G, eta, U)
+            else:
+                delta, lits = solve(self.jacobian(u_n, k, g_stages), -G, eta)
             lam = 1.0
             for trial in range(ls_maxit + 1 if linesearch else 1):
                 kt = k + lam * delta
@@ -283,3 +301,36 @@ class NavierStokesStages:
             u_new += S.dt * b[j] * ku
             p_new += S.dt * b[j] * kp
         return u_new, p_new, k, info
+
+
+# --------------------------------------------------- the Newton Jacobian V-cycle
+def inject_nodal(th_fine: TaylorHood, th_coarse: TaylorHood, U_fine: np.ndarray) -> np.ndarray:
+    """A fine-level P2 field's values at the P2 nodes of the next coarser level, which
+    are nodes of the fine level (uniform refinement makes every coarse vertex and edge
+    midpoint a fine vertex), so the values are the fine field evaluated there."""
+    scale = 1.0 + float(np.abs(th_fine.node_xyz).max())
+    key = lambda x: tuple(np.round(x / scale * 2.0 ** 40).astype(np.int64))
+    where = {key(x): i for i, x in enumerate(th_fine.node_xyz)}
+    idx = np.array([where[key(x)] for x in th_coarse.node_xyz])
+    return U_fine[idx]
+
+
+def newton_hierarchy(mesh_levels, A, dt: float, nu: float, U_fine: list, **hierarchy_kw):
+    """The V-cycle for the Newton Jacobian of the Navier--Stokes stage equations
+    (Sec. 3.2) at the stage velocities U_fine (nodal arrays on the finest level): every
+    level rediscretises the Jacobian, block (i, j) = delta_ij M + dt a_ij (K + N'(U_i)),
+    with the stage velocities carried to it by injection at its nodes (the reading taken
+    for data of the finest level on coarser meshes, as for the wind of the Oseen
+    operator); Vanka patches, transfers and the coarse solve as for the Stokes cycle."""
+    from .multigrid import Hierarchy
+
+    spaces = [TaylorHood(m.xyz, m.cells) for m in mesh_levels]
+    U_lev = [None] * len(spaces)
+    U_lev[-1] = [np.asarray(u, dtype=np.float64) for u in U_fine]
+    for lev in range(len(spaces) - 2, -1, -1):
+        U_lev[lev] = [inject_nodal(spaces[lev + 1], spaces[lev], u) for u in U_lev[lev + 1]]
+
+    def op(lev, system):
+        return NavierStokesStages(system.th, A, dt, nu).jacobian_at(U_lev[lev])
+
+    return Hierarchy(mesh_levels, A, dt, nu, level_operators=op, **hierarchy_kw)

@@ -5,10 +5,11 @@ stage system preconditioned by the Vanka V-cycle, update) and keeps every step's
 and stages on the device (the checkpoints).  Its backward pass is the discrete adjoint:
 for n = N-1 .. 0 it solves J^T lam = dt b (x) gbar with FGMRES preconditioned by the
 transposed V-cycle (``irk_adjoint_solve``), maps lam back to the forcing and the state
-(``irk_rhs_adjoint``) and accumulates the viscosity sensitivity
-(``irk_nu_sensitivity``).  ``tracking_loss`` is 1/2 (u - u_hat)^T M (u - u_hat).
-All arithmetic on vectors runs in the library; this module only sequences calls and
-accumulates the per-step results.
+(``irk_rhs_adjoint``, adding into the state adjoint in place) and adds the viscosity
+sensitivity of the step (``irk_nu_sensitivity``, accumulating into one device value).
+``tracking_loss`` is 1/2 (u - u_hat)^T M (u - u_hat) (``irk_tracking_loss``, which also
+gives both gradients scaled by the incoming gradient).  All arithmetic runs in the
+library; this module only allocates tensors and sequences calls.
 """
 from __future__ import annotations
 
@@ -59,10 +60,8 @@ class IrkSteps(torch.autograd.Function):
         dev = g_state.device
         gbar = g_state.detach().clone().contiguous()
         gf = torch.empty(ctx.fshape, dtype=torch.float64, device=dev)
-        gnu = torch.zeros((), dtype=torch.float64, device=dev)
+        gnu = torch.zeros(1, dtype=torch.float64, device=dev)
         G = torch.empty(N, dtype=torch.float64, device=dev)
-        gs = torch.empty_like(gbar)
-        out = torch.empty(1, dtype=torch.float64, device=dev)
         for n in range(nsteps - 1, -1, -1):
             state_n, k_n = saved[2 * n], saved[2 * n + 1]
             solver.irk_update_adjoint(gbar, G)
@@ -70,12 +69,10 @@ class IrkSteps(torch.autograd.Function):
             info = solver.irk_adjoint_solve(G, lam, rtol=ctx.rtol, maxit=ctx.maxit, history_cap=0)
             if not info["converged"]:
                 raise RuntimeError(f"adjoint solve of step {n} did not converge: {info}")
-            gfn = gf[n]
-            solver.irk_rhs_adjoint(lam, gfn.view(-1), gs)
-            solver.irk_nu_sensitivity(lam, k_n, state_n, out)
-            gnu += out[0]
-            gbar += gs
-        return gf, gnu, gbar, None, None, None
+            # gbar_n = gbar_{n+1} + (dF/dstate)^T lam^n, gnu += lam^nT (dF/dnu - dJ/dnu k^n)
+            solver.irk_rhs_adjoint(lam, gf[n].view(-1), gbar, accumulate=True)
+            solver.irk_nu_sensitivity(lam, k_n, state_n, gnu, accumulate=True)
+        return gf, gnu.view(()), gbar, None, None, None
 
 
 class TrackingLoss(torch.autograd.Function):
@@ -83,18 +80,20 @@ class TrackingLoss(torch.autograd.Function):
 
     @staticmethod
     def forward(ctx, state, target, solver: IrkMG):
-        e = (state - target).contiguous()
-        nvel = solver.dim * solver.irk_mg_sizes()["nfree"]
-        e[nvel:] = 0.0
-        Me = torch.empty_like(e)
-        solver.irk_mass_apply(e, Me)
-        ctx.save_for_backward(Me)
-        return 0.5 * torch.dot(e, Me)
+        state, target = state.detach().contiguous(), target.detach().contiguous()
+        loss = torch.empty(1, dtype=torch.float64, device=state.device)
+        solver.irk_tracking_loss(state, target, loss=loss)
+        ctx.save_for_backward(state, target)
+        ctx.solver = solver
+        return loss.view(())
 
     @staticmethod
     def backward(ctx, g):
-        (Me,) = ctx.saved_tensors
-        return g * Me, -g * Me, None
+        state, target = ctx.saved_tensors
+        gs, gt = torch.empty_like(state), torch.empty_like(target)
+        scale = g.detach().to(dtype=torch.float64).reshape(1).contiguous()
+        ctx.solver.irk_tracking_loss(state, target, grad_state=gs, grad_target=gt, scale=scale)
+        return gs, gt, None
 
 
 def tracking_loss(state, target, solver: IrkMG):

@@ -73,7 +73,7 @@ struct BSolve {
   dev::Coef<double> dtA;
   int64_t ns;  // ABI stage block of the finest level
   BLevel lv[kMaxLevels];
-  const double* cinv;
+  const double *cinv, *cmat;  // coarse inverse and pinned operator, column-major
   double *cb, *cpart;
   int64_t pins[kMaxStages];
   int64_t N0;
@@ -100,7 +100,7 @@ struct BState {
 
 // the part of a solve's state that a work item reads (copied to LDS per item)
 struct BCur {
-  int phase, n_items, done_base, level, first, j, i, jend, pj_final;
+  int phase, n_items, done_base, level, first, j, i, jend, pj_final, sweep;
   double beta;
   double mean[kMaxStages];
 };
@@ -356,9 +356,13 @@ __device__ void exec_item(const BSolve& S, const BCur& st, const BState* gst, in
       const int64_t i = (int64_t)rbk * 64 + lane;
       const int64_t per = (S.N0 + kCoarseChunks - 1) / kCoarseChunks;
       const int64_t j0 = chunk * per, j1 = min(S.N0, j0 + per);
+      // coarse solve step st.sweep: 0 inv * b, 1 M * x (residual of the refinement
+      // step), 2 inv * (b - M x) (its correction)
+      const double* mat = st.sweep == 1 ? S.cmat : S.cinv;
+      const double* vec = st.sweep == 1 ? S.lv[0].x : S.cb;
       if (i < S.N0) {
         double acc = 0;
-        for (int64_t j = j0; j < j1; ++j) acc += S.cinv[j * S.N0 + i] * S.cb[j];
+        for (int64_t j = j0; j < j1; ++j) acc += mat[j * S.N0 + i] * vec[j];
         S.cpart[(int64_t)chunk * S.N0 + i] = acc;
       }
       break;
@@ -368,7 +372,9 @@ __device__ void exec_item(const BSolve& S, const BCur& st, const BState* gst, in
       for (int64_t g = e0 + tid; g < g1; g += kBlock) {
         double acc = 0;
         for (int c = 0; c < kCoarseChunks; ++c) acc += S.cpart[(int64_t)c * S.N0 + g];
-        S.lv[0].x[g] = acc;
+        if (st.sweep == 0) S.lv[0].x[g] = acc;
+        else if (st.sweep == 1) S.cb[g] -= acc;
+        else S.lv[0].x[g] += acc;
       }
       break;
     }
@@ -541,9 +547,16 @@ __host__ __device__ void advance(const BSolve& S, BState& st, double red_val, co
         start_smooth(S, st, st.level - 1, S.pre, 1);
       }
       break;
-    case PH_CO_IN: st.phase = PH_CO_MV; break;
+    case PH_CO_IN: st.sweep = 0; st.phase = PH_CO_MV; break;
     case PH_CO_MV: st.phase = PH_CO_RED; break;
-    case PH_CO_RED: after_coarse(S, st); break;
+    case PH_CO_RED:  // inverse times b, then one refinement step (residual, correction)
+      if (st.sweep < 2) {
+        st.sweep += 1;
+        st.phase = PH_CO_MV;
+      } else {
+        after_coarse(S, st);
+      }
+      break;
     case PH_UP_PROLONG:
       start_smooth(S, st, st.level, S.post, 0);
       break;
@@ -712,6 +725,7 @@ __global__ __launch_bounds__(kBlock, 1) void k_batch(const BSolve* __restrict__ 
       s_st.done_base = ald(&st->done_base);
       s_st.level = ald(&st->level);
       s_st.first = ald(&st->first);
+      s_st.sweep = ald(&st->sweep);
       s_st.j = ald(&st->j);
       s_st.i = ald(&st->i);
       s_st.jend = ald(&st->jend);
@@ -912,6 +926,7 @@ irk_status run(irk_batch* b, const double* const* F, double* const* k, bool tria
     S.ns = h->dim * Ft.nfree + Ft.nv;
     for (int l = 0; l < h->nlevels; ++l) S.lv[l] = level_view(h->dev[l]);
     S.cinv = h->coarse_inv;
+    S.cmat = h->coarse_mat;
     S.cb = h->cb;
     S.cpart = h->cpart;
     for (int st = 0; st < h->r; ++st) S.pins[st] = h->dev[0].offV + st;

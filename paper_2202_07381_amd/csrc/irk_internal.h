@@ -15,6 +15,7 @@
 
 #include <cstdint>
 #include <string>
+#include <complex>
 #include <vector>
 
 namespace irk {
@@ -127,6 +128,9 @@ bool stage_eigenbasis(const double* A, int r, StageEig& out, std::string* why);
 // rotations, Wilkinson shifts, deflation at negligible subdiagonal entries), sorted by
 // decreasing real part.  False if the iteration does not converge.
 bool hessenberg_eigs(int m, const double* H, int ldh, double* wr, double* wi);
+// the same with caller storage: work holds m*m + 3m complex values, iwork m ints
+bool hessenberg_eigs_ws(int m, const double* H, int ldh, double* wr, double* wi, std::complex<double>* work,
+                        int* iwork);
 
 // Stored values per column of one eigen-block of a factored patch inverse: a real block
 // keeps its n_s entries, a pair keeps n_s complex entries (re, im interleaved); both
@@ -260,6 +264,8 @@ struct Handle {
   std::vector<DevLevel> dev;
   double* coarse_inv = nullptr;   // column-major, internal layout
   double* coarse_invT = nullptr;  // column-major inverse of the transpose
+  double* coarse_mat = nullptr;   // the pinned coarse operator, column-major
+  double* coarse_matT = nullptr;  // its transpose, column-major
   double *cb = nullptr, *cx = nullptr;  // FP64 coarse vectors
   double* cpart = nullptr;               // coarse GEMV partial sums
   // FGMRES workspace (finest level, internal layout, FP64)
@@ -350,9 +356,15 @@ hipError_t eig_extract(const DevLevel& L, const StageBasis<T>& sb, int b, const 
 hipError_t dense_inverse(double* J, int64_t N, double tol, double* colk, int64_t* swp, int* fail, hipStream_t s);
 // out (N x N) = transpose of in (N x N)
 hipError_t transpose(const double* in, double* out, int64_t N, hipStream_t s);
-hipError_t coarse_gemv(const double* inv, int64_t N, const double* b, double* x,
-                       const int64_t* pins, int npins, double* part, hipStream_t s);
-int coarse_split();  // number of partial sums per row used by coarse_gemv
+// x = M^{-1} b on the coarsest level: the pinned entries of b are zeroed, x = inv b with
+// the stored inverse (column-major), then, when mat (the pinned operator M, column-major)
+// is given, one step of iterative refinement in FP64, b <- b - M x, x <- x + inv b (b is
+// overwritten).  Solving through an explicit inverse alone leaves a forward error of
+// order |M^{-1}| |M| |M^{-1}| |b| eps; the refinement step computes the residual with M
+// itself and brings the error down to order cond(M, x) eps (componentwise condition).
+hipError_t coarse_solve(const double* inv, const double* mat, int64_t N, double* b, double* x,
+                        const int64_t* pins, int npins, double* part, hipStream_t s);
+int coarse_split();  // number of partial sums per row used by coarse_solve
 template <typename T>
 hipError_t to_internal(const DevLevel& L, const double* abi, T* x, hipStream_t s);
 template <typename T>
@@ -400,11 +412,19 @@ hipError_t rhs(const DevLevel& L, int64_t nnodes, const double* f, const double*
 hipError_t update(const DevLevel& L, const double* b, double dt, const double* k,
                   double* state, hipStream_t s);
 hipError_t rhs_adjoint(const DevLevel& L, int64_t nnodes, const int32_t* mt_ptr, const int32_t* mt_col,
-                       const double* mt_val, const double* lam, double* gf, double* gstate, hipStream_t s);
+                       const double* mt_val, const double* lam, double* gf, double* gstate, int accumulate,
+                       hipStream_t s);
 hipError_t update_adjoint(const DevLevel& L, const double* b, double dt, const double* gs, double* G,
                           hipStream_t s);
 hipError_t nu_sensitivity(const DevLevel& L, const double* A, double dt, const double* lam, const double* kv,
-                          const double* state, double* rowsum, double* partials, double* out, hipStream_t s);
+                          const double* state, double* rowsum, double* partials, double* out, int accumulate,
+                          hipStream_t s);
+// loss = 1/2 e^T M e with e the velocity part of state - target (if loss is given);
+// grad_state = s [M e; 0], grad_target = -s [M e; 0] with s = *scale (1 if null), each
+// if given.  e and Me: ns-value workspaces; partials: the reduction workspace.
+hipError_t tracking_loss(const DevLevel& L, const double* state, const double* target, const double* scale,
+                         double* loss, double* grad_state, double* grad_target, double* e, double* Me,
+                         double* partials, hipStream_t s);
 hipError_t mass_apply(const DevLevel& L, const double* st, double* out, hipStream_t s);
 
 // Navier--Stokes terms (Sec. 3.2), finest level.  dt a_ij (or a_ij) by value.
@@ -442,4 +462,18 @@ namespace irk {
 int ensure_krylov_ws(irk_mg* h, int restart);
 // message returned by irk_last_error() on the calling thread
 void set_error(const std::string& msg);
+// Ritz estimate of a level's relaxation operator (irk_mg_ritz) in parts: argument
+// checks (level -1 is resolved to the finest); the Arnoldi process in caller-provided
+// device storage (V: (steps + 1) level vectors in the handle's precision, dH:
+// (steps + 1)^2 doubles, part: ritz_partials_bytes()), the Hessenberg matrix copied to
+// the host array Hh ((steps + 1) x steps) and the stream synchronised; the eigenvalues
+// from Hh with caller storage (work: steps^2 + 3 steps complex values, iwork: steps).
+int ritz_check(irk_mg* h, int& level, int steps, const double* v0, const double* ritz_re, const double* ritz_im);
+int ritz_into(irk_mg* h, int level, int steps, const double* v0, void* V, double* dH, double* part, double* Hh,
+              hipStream_t s);
+int ritz_finish(int steps, const double* Hh, double* H, double* ritz_re, double* ritz_im, int* nritz,
+                std::complex<double>* work, int* iwork);
+size_t ritz_partials_bytes();
+// stored failure (IRK_* code and message) for the calling thread
+int fail_with(int code, const std::string& msg);
 }  // namespace irk

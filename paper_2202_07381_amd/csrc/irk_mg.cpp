@@ -9,6 +9,7 @@
 #include <chrono>
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <numeric>
 #include <string>
@@ -42,6 +43,15 @@ irk_status fail(irk_status code, const std::string& msg) {
     if (s_ != IRK_OK) return s_;        \
   } while (0)
 
+// IRK_MG_POISON_ALLOC=1 in the environment fills every allocation of a handle with the
+// byte 0xFF (a NaN in FP64 and FP32) before first use, so that a kernel reading a
+// workspace entry it never wrote shows up as a non-finite result instead of passing
+// on whatever the allocator happened to return.
+bool poison_allocations() {
+  const char* v = std::getenv("IRK_MG_POISON_ALLOC");
+  return v && *v && std::strcmp(v, "0") != 0;
+}
+
 template <typename T>
 irk_status dalloc(Handle* h, T** p, size_t n) {
   *p = nullptr;
@@ -51,6 +61,7 @@ irk_status dalloc(Handle* h, T** p, size_t n) {
     return fail(e == hipErrorOutOfMemory ? IRK_ENOMEM : IRK_EHIP,
                 "hipMalloc of " + std::to_string(n * sizeof(T)) + " bytes failed: " + hipGetErrorName(e));
   h->allocations.push_back(*p);
+  if (poison_allocations()) HIPCHK(hipMemset(*p, 0xFF, n * sizeof(T)));
   return IRK_OK;
 }
 
@@ -259,37 +270,55 @@ irk_status smooth(Handle* h, int l, int nsweeps, bool zero_start, bool tr, hipSt
   return IRK_OK;
 }
 
+// One V-cycle (Sec. 4.1) by its legs: descend_T pre-smooths level l and restricts its
+// residual into the right-hand side of level l-1; coarse_T solves on level 0; ascend_T
+// prolongs the correction into level l and post-smooths.
+template <typename T>
+irk_status descend_T(Handle* h, int l, bool tr, hipStream_t s) {
+  DevLevel& L = h->dev[l];
+  DevOps<T> o = ops_of<T>(L);
+  if (tr) {
+    o.s_L = o.s_Lt;
+    o.u_L = o.u_Lt;
+  }
+  CHK(smooth<T>(h, l, tr ? h->post : h->pre, true, tr, s));
+  const int p0 = prof_begin(h, 1, l, s);
+  HIPCHK(k::residual<T>(L, o, tr ? h->At : h->A, h->dt, (const T*)L.b, (const T*)L.x, (T*)L.res, s));
+  prof_end(h, p0, s);
+  HIPCHK(k::restrict_<T>(L, h->dev[l - 1], ops_of<T>(L), (const T*)L.res, (T*)h->dev[l - 1].b, s));
+  return IRK_OK;
+}
+
+template <typename T>
+irk_status coarse_T(Handle* h, bool tr, hipStream_t s, const int64_t* pins) {
+  DevLevel& L = h->dev[0];
+  HIPCHK((k::cast<T, double>((const T*)L.b, h->cb, L.N, s)));
+  HIPCHK(k::coarse_solve(tr ? h->coarse_invT : h->coarse_inv, tr ? h->coarse_matT : h->coarse_mat, L.N, h->cb,
+                         h->cx, pins, h->r, h->cpart, s));
+  HIPCHK((k::cast<double, T>(h->cx, (T*)L.x, L.N, s)));
+  return IRK_OK;
+}
+
+template <typename T>
+irk_status ascend_T(Handle* h, int l, bool tr, hipStream_t s) {
+  DevLevel& L = h->dev[l];
+  HIPCHK(k::prolong_add<T>(L, h->dev[l - 1], ops_of<T>(L), (const T*)h->dev[l - 1].x, (T*)L.x, s));
+  CHK(smooth<T>(h, l, tr ? h->pre : h->post, false, tr, s));
+  return IRK_OK;
+}
+
+// the cycle restricted to levels 0..lt, entered with the right-hand side of level lt
+template <typename T>
+irk_status subcycle_T(Handle* h, int lt, bool tr, hipStream_t s, const int64_t* pins) {
+  for (int l = lt; l >= 1; --l) CHK(descend_T<T>(h, l, tr, s));
+  CHK(coarse_T<T>(h, tr, s, pins));
+  for (int l = 1; l <= lt; ++l) CHK(ascend_T<T>(h, l, tr, s));
+  return IRK_OK;
+}
+
 template <typename T>
 irk_status vcycle_T(Handle* h, bool tr, hipStream_t s, const int64_t* pins) {
-  const int top = h->nlevels - 1;
-  const int npre = tr ? h->post : h->pre;
-  const int npost = tr ? h->pre : h->post;
-  const double* A = tr ? h->At : h->A;
-  for (int l = top; l >= 1; --l) {
-    DevLevel& L = h->dev[l];
-    DevOps<T> o = ops_of<T>(L);
-    if (tr) {
-      o.s_L = o.s_Lt;
-      o.u_L = o.u_Lt;
-    }
-    CHK(smooth<T>(h, l, npre, true, tr, s));
-    const int p0 = prof_begin(h, 1, l, s);
-    HIPCHK(k::residual<T>(L, o, A, h->dt, (const T*)L.b, (const T*)L.x, (T*)L.res, s));
-    prof_end(h, p0, s);
-    HIPCHK(k::restrict_<T>(L, h->dev[l - 1], ops_of<T>(L), (const T*)L.res, (T*)h->dev[l - 1].b, s));
-  }
-  {
-    DevLevel& L = h->dev[0];
-    HIPCHK((k::cast<T, double>((const T*)L.b, h->cb, L.N, s)));
-    HIPCHK(k::coarse_gemv(tr ? h->coarse_invT : h->coarse_inv, L.N, h->cb, h->cx, pins, h->r, h->cpart, s));
-    HIPCHK((k::cast<double, T>(h->cx, (T*)L.x, L.N, s)));
-  }
-  for (int l = 1; l <= top; ++l) {
-    DevLevel& L = h->dev[l];
-    HIPCHK(k::prolong_add<T>(L, h->dev[l - 1], ops_of<T>(L), (const T*)h->dev[l - 1].x, (T*)L.x, s));
-    CHK(smooth<T>(h, l, npost, false, tr, s));
-  }
-  return IRK_OK;
+  return subcycle_T<T>(h, h->nlevels - 1, tr, s, pins);
 }
 
 
@@ -561,28 +590,18 @@ irk_status level_sweep_T(irk_mg* h, int level, int transpose, const double* F, d
 }
 
 // Arnoldi on the relaxation's preconditioned operator W S J_l of level l (classical
-// Gram--Schmidt, the GMRES relaxation's kernels), Hessenberg copied to the host.
+// Gram--Schmidt, the GMRES relaxation's kernels) in caller-provided device storage: V
+// holds steps + 1 vectors of the level, dH (steps + 1)^2 doubles, part the reduction
+// partial sums; the Hessenberg matrix ((steps + 1) x steps, column-major) is copied to
+// Hh on the host and the stream synchronised.
 template <typename T>
-irk_status ritz_T(irk_mg* h, int level, int steps, const double* v0, std::vector<double>& H, hipStream_t s) {
+irk_status ritz_ws_T(irk_mg* h, int level, int steps, const double* v0, T* V, double* dH, double* part,
+                     double* Hh, hipStream_t s) {
   DevLevel& L = h->dev[level];
   DevOps<T>& o = ops_of<T>(L);
   const int64_t N = L.N;
   const int ld = steps + 1;
-  T* V = nullptr;
-  double *dH = nullptr, *part = nullptr;
-  auto release = [&]() {
-    hipStreamSynchronize(s);
-    if (V) hipFree(V);
-    if (dH) hipFree(dH);
-    if (part) hipFree(part);
-  };
-  if (hipMalloc(&V, (size_t)(steps + 1) * N * sizeof(T)) != hipSuccess ||
-      hipMalloc(&dH, (size_t)ld * (steps + 1) * sizeof(double)) != hipSuccess ||
-      hipMalloc(&part, (size_t)k::kGrBlocks * (kMaxGr + 1) * sizeof(double)) != hipSuccess) {
-    release();
-    return fail(IRK_ENOMEM, "device allocation of the Arnoldi basis failed");
-  }
-  hipError_t e = hipMemsetAsync(dH, 0, (size_t)ld * (steps + 1) * sizeof(double), s);
+  hipError_t e = k::fill(dH, (int64_t)ld * (steps + 1), 0.0, s);
   double* nrm0 = dH + (size_t)ld * steps;  // spare column: the start vector's norm
   if (e == hipSuccess) e = k::to_internal<T>(L, v0, V, s);
   if (e == hipSuccess) e = k::gr_orth_norm<T>(V, V, N, -1, N, dH, part, nrm0, s);
@@ -599,17 +618,76 @@ irk_status ritz_T(irk_mg* h, int level, int steps, const double* v0, std::vector
     if (e == hipSuccess) e = k::gr_orth_norm<T>(Vn, V, N, j, N, hcol, part, hcol + j + 1, s);
     if (e == hipSuccess) e = k::gr_scale<T>(Vn, N, hcol + j + 1, s);
   }
-  H.assign((size_t)ld * steps, 0.0);
-  if (e == hipSuccess) e = hipMemcpyAsync(H.data(), dH, H.size() * sizeof(double), hipMemcpyDeviceToHost, s);
-  release();
+  if (e == hipSuccess) e = hipMemcpyAsync(Hh, dH, (size_t)ld * steps * sizeof(double), hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
   if (e != hipSuccess) return fail(IRK_EHIP, std::string("Arnoldi estimate: ") + hipGetErrorString(e));
   return IRK_OK;
 }
 
+template <typename T>
+irk_status ritz_T(irk_mg* h, int level, int steps, const double* v0, double* Hh, hipStream_t s) {
+  const int64_t N = h->dev[level].N;
+  T* V = nullptr;
+  double *dH = nullptr, *part = nullptr;
+  auto release = [&]() {
+    (void)hipStreamSynchronize(s);
+    if (V) (void)hipFree(V);
+    if (dH) (void)hipFree(dH);
+    if (part) (void)hipFree(part);
+  };
+  if (hipMalloc(&V, (size_t)(steps + 1) * N * sizeof(T)) != hipSuccess ||
+      hipMalloc(&dH, (size_t)(steps + 1) * (steps + 1) * sizeof(double)) != hipSuccess ||
+      hipMalloc(&part, irk::ritz_partials_bytes()) != hipSuccess) {
+    release();
+    return fail(IRK_ENOMEM, "device allocation of the Arnoldi basis failed");
+  }
+  const irk_status st = ritz_ws_T<T>(h, level, steps, v0, V, dH, part, Hh, s);
+  release();
+  return st;
+}
+
 }  // namespace
+
+size_t irk::ritz_partials_bytes() { return (size_t)k::kGrBlocks * (kMaxGr + 1) * sizeof(double); }
+
+irk_status irk::ritz_check(irk_mg* h, int& level, int steps, const double* v0, const double* ritz_re,
+                           const double* ritz_im) {
+  CHK(check_level(h, level));
+  if (level < 1) return fail(IRK_EINVAL, "the coarsest level has no relaxation");
+  if (steps < 1 || steps > 64) return fail(IRK_EINVAL, "steps must be in 1..64");
+  if (!v0 || !ritz_re || !ritz_im) return fail(IRK_EINVAL, "null argument");
+  return IRK_OK;
+}
+
+irk_status irk::ritz_into(irk_mg* h, int level, int steps, const double* v0, void* V, double* dH, double* part,
+                          double* Hh, hipStream_t s) {
+  if (h->precision == 0) return ritz_ws_T<double>(h, level, steps, v0, (double*)V, dH, part, Hh, s);
+  return ritz_ws_T<float>(h, level, steps, v0, (float*)V, dH, part, Hh, s);
+}
+
+// Ritz values from the Hessenberg matrix Hh ((steps + 1) x steps, column-major); an
+// invariant Krylov space (zero subdiagonal entry) ends the estimate early.
+irk_status irk::ritz_finish(int steps, const double* Hh, double* H, double* ritz_re, double* ritz_im, int* nritz,
+                            std::complex<double>* work, int* iwork) {
+  const int ld = steps + 1;
+  int m = steps;
+  for (int j = 0; j < steps; ++j)
+    if (!(Hh[(size_t)j * ld + j + 1] != 0.0)) {
+      m = j + 1;
+      break;
+    }
+  if (H) std::memcpy(H, Hh, (size_t)ld * steps * sizeof(double));
+  for (int j = 0; j < steps; ++j) ritz_re[j] = ritz_im[j] = 0.0;
+  if (!irk::hessenberg_eigs_ws(m, Hh, ld, ritz_re, ritz_im, work, iwork))
+    return fail(IRK_ENOCONV, "Hessenberg QR iteration did not converge");
+  if (nritz) *nritz = m;
+  return IRK_OK;
+}
+
 
 int irk::ensure_krylov_ws(irk_mg* h, int restart) { return ensure_krylov(h, restart); }
 void irk::set_error(const std::string& msg) { g_err = msg; }
+irk_status irk::fail_with(irk_status code, const std::string& msg) { return fail(code, msg); }
 
 // =========================================================================== ABI
 extern "C" {
@@ -1230,6 +1308,9 @@ static irk_status setup_impl(const irk_mesh_level* lv, int nlevels, const irk_ta
     coarse_matrix(h->host[0], r, h->A, dt, Jc, &scale);
     const int64_t N0 = h->dev[0].N;
     CHK(upload(h, &h->coarse_invT, Jc, s));
+    // the row-major operator is the column-major transpose; its transpose is the
+    // column-major operator (both kept for the refinement step of the coarse solve)
+    CHK(upload(h, &h->coarse_matT, Jc, s));
     Jc.clear();
     Jc.shrink_to_fit();
     double* colk;
@@ -1244,6 +1325,8 @@ static irk_status setup_impl(const irk_mesh_level* lv, int nlevels, const irk_ta
     if (cfail) return fail(IRK_ESINGULAR, "singular coarse operator");
     CHK(dalloc(h, &h->coarse_inv, (size_t)N0 * N0));
     HIPCHK(k::transpose(h->coarse_invT, h->coarse_inv, N0, s));
+    CHK(dalloc(h, &h->coarse_mat, (size_t)N0 * N0));
+    HIPCHK(k::transpose(h->coarse_matT, h->coarse_mat, N0, s));
     CHK(dalloc(h, &h->cb, N0));
     CHK(dalloc(h, &h->cx, N0));
     CHK(dalloc(h, &h->cpart, (size_t)N0 * k::coarse_split()));
@@ -1353,27 +1436,14 @@ irk_status irk_hessenberg_eigs(int m, const double* H, int ldh, double* wr, doub
 
 irk_status irk_mg_ritz(irk_mg* h, int level, int steps, const double* v0, double* H, double* ritz_re,
                        double* ritz_im, int* nritz, void* stream) {
-  CHK(check_level(h, level));
-  if (level < 1) return fail(IRK_EINVAL, "the coarsest level has no relaxation");
-  if (steps < 1 || steps > 64) return fail(IRK_EINVAL, "steps must be in 1..64");
-  if (!v0 || !ritz_re || !ritz_im) return fail(IRK_EINVAL, "null argument");
-  std::vector<double> Hh;
+  CHK(irk::ritz_check(h, level, steps, v0, ritz_re, ritz_im));
+  std::vector<double> Hh((size_t)(steps + 1) * steps);
   hipStream_t s = S(stream);
-  if (h->precision == 0) CHK(ritz_T<double>(h, level, steps, v0, Hh, s));
-  else CHK(ritz_T<float>(h, level, steps, v0, Hh, s));
-  const int ld = steps + 1;
-  int m = steps;  // an invariant Krylov space ends the estimate early
-  for (int j = 0; j < steps; ++j)
-    if (!(Hh[(size_t)j * ld + j + 1] != 0.0)) {
-      m = j + 1;
-      break;
-    }
-  if (H) std::memcpy(H, Hh.data(), Hh.size() * sizeof(double));
-  for (int j = 0; j < steps; ++j) ritz_re[j] = ritz_im[j] = 0.0;
-  if (!irk::hessenberg_eigs(m, Hh.data(), ld, ritz_re, ritz_im))
-    return fail(IRK_ENOCONV, "Hessenberg QR iteration did not converge");
-  if (nritz) *nritz = m;
-  return IRK_OK;
+  if (h->precision == 0) CHK(ritz_T<double>(h, level, steps, v0, Hh.data(), s));
+  else CHK(ritz_T<float>(h, level, steps, v0, Hh.data(), s));
+  std::vector<std::complex<double>> work((size_t)steps * steps + 3 * (size_t)steps);
+  std::vector<int> iwork(steps);
+  return irk::ritz_finish(steps, Hh.data(), H, ritz_re, ritz_im, nritz, work.data(), iwork.data());
 }
 
 irk_status irk_mg_set_interval(irk_mg* h, double lo, double hi) {
@@ -1677,12 +1747,15 @@ irk_status irk_update(irk_mg* h, const double* kv, double* state, void* stream) 
   return IRK_OK;
 }
 
-irk_status irk_rhs_adjoint(irk_mg* h, const double* lam, double* gf, double* gstate, void* stream) {
+irk_status irk_rhs_adjoint(irk_mg* h, const double* lam, double* gf, double* gstate, int accumulate,
+                           void* stream) {
   CHK(check_handle(h));
   if (!lam || !gf || !gstate) return fail(IRK_EINVAL, "null vector");
+  if (accumulate != 0 && accumulate != 1) return fail(IRK_EINVAL, "accumulate must be 0 or 1");
   const int top = h->nlevels - 1;
   DevLevel& L = h->dev[top];
-  HIPCHK(k::rhs_adjoint(L, h->host[top].nn, L.mfat_ptr, L.mfat_col, L.mfat_val, lam, gf, gstate, S(stream)));
+  HIPCHK(k::rhs_adjoint(L, h->host[top].nn, L.mfat_ptr, L.mfat_col, L.mfat_val, lam, gf, gstate, accumulate,
+                        S(stream)));
   return IRK_OK;
 }
 
@@ -1694,11 +1767,41 @@ irk_status irk_update_adjoint(irk_mg* h, const double* gstate, double* G, void* 
 }
 
 irk_status irk_nu_sensitivity(irk_mg* h, const double* lam, const double* kv, const double* state, double* out,
-                              void* stream) {
+                              int accumulate, void* stream) {
   CHK(check_handle(h));
   if (!lam || !kv || !state || !out) return fail(IRK_EINVAL, "null vector");
+  if (accumulate != 0 && accumulate != 1) return fail(IRK_EINVAL, "accumulate must be 0 or 1");
   DevLevel& L = h->dev[h->nlevels - 1];
-  HIPCHK(k::nu_sensitivity(L, h->A, h->dt, lam, kv, state, h->kw, h->partials, out, S(stream)));
+  HIPCHK(k::nu_sensitivity(L, h->A, h->dt, lam, kv, state, h->kw, h->partials, out, accumulate, S(stream)));
+  return IRK_OK;
+}
+
+irk_status irk_tracking_loss(irk_mg* h, const double* state, const double* target, const double* scale,
+                             double* loss, double* grad_state, double* grad_target, void* stream) {
+  CHK(check_handle(h));
+  if (!state || !target) return fail(IRK_EINVAL, "null vector");
+  if (!loss && !grad_state && !grad_target) return fail(IRK_EINVAL, "no output requested");
+  DevLevel& L = h->dev[h->nlevels - 1];
+  HIPCHK(k::tracking_loss(L, state, target, scale, loss, grad_state, grad_target, h->kw, h->kr, h->partials,
+                          S(stream)));
+  return IRK_OK;
+}
+
+irk_status irk_mg_layout(const irk_mg* hc, int level, int64_t* offsets, int64_t* lengths) {
+  irk_mg* h = const_cast<irk_mg*>(hc);
+  CHK(check_level(h, level));
+  if (!offsets && !lengths) return fail(IRK_EINVAL, "no output requested");
+  const HostLevel& H = h->host[level];
+  const int d = H.dim;
+  const int64_t ns = d * H.nfree + H.nv;
+  for (int st = 0; st < h->r && offsets; ++st) {
+    for (int c = 0; c < d; ++c) offsets[st * (d + 1) + c] = st * ns + c * H.nfree;
+    offsets[st * (d + 1) + d] = st * ns + d * H.nfree;
+  }
+  if (lengths) {
+    for (int c = 0; c < d; ++c) lengths[c] = H.nfree;
+    lengths[d] = H.nv;
+  }
   return IRK_OK;
 }
 
@@ -1771,7 +1874,8 @@ irk_status irk_coarse_solve(irk_mg* h, int transpose, const double* b, double* x
   DevLevel& L = h->dev[0];
   hipStream_t s = S(stream);
   HIPCHK(k::to_internal<double>(L, b, h->cb, s));
-  HIPCHK(k::coarse_gemv(transpose ? h->coarse_invT : h->coarse_inv, L.N, h->cb, h->cx, h->pins, h->r, h->cpart, s));
+  HIPCHK(k::coarse_solve(transpose ? h->coarse_invT : h->coarse_inv, transpose ? h->coarse_matT : h->coarse_mat,
+                         L.N, h->cb, h->cx, h->pins, h->r, h->cpart, s));
   HIPCHK(k::to_abi<double>(L, h->cx, x, s));
   return IRK_OK;
 }

@@ -12,7 +12,7 @@
 //  gather_update  owner gather: every DOF sums its patches' slots in a fixed order and
 //                 applies x += omega W sum (deterministic, no atomics).
 //  restrict_ / prolong_add   I_r (x) P and its transpose (Sec. 4.1), node-chunked CSR.
-//  coarse_gemv    dense coarse solve with the stored inverse.
+//  coarse_solve   dense coarse solve with the stored inverse, one refinement step.
 //  dot / axpy / ... deterministic fixed-order reductions for FGMRES.
 #include <hip/hip_runtime.h>
 
@@ -980,13 +980,15 @@ __global__ __launch_bounds__(kBlock) void k_coarse_gemv_part(const double* __res
   if (i < N) part[(int64_t)chunk * N + i] = acc;
 }
 
+// mode 0: x = sum of the partial sums; 1: x -= sum (a residual b - M y formed in
+// place of b); 2: x += sum (the correction of the refinement step)
 __global__ __launch_bounds__(kBlock) void k_coarse_reduce(const double* __restrict__ part, int64_t N,
-                                                          double* __restrict__ x) {
+                                                          double* __restrict__ x, int mode) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= N) return;
   double acc = 0;
   for (int c = 0; c < kCoarseSplit * (kBlock / 64); ++c) acc += part[(int64_t)c * N + i];
-  x[i] = acc;
+  x[i] = mode == 0 ? acc : (mode == 1 ? x[i] - acc : x[i] + acc);
 }
 
 __global__ void k_zero_pins(double* b, const int64_t* pins, int np) {
@@ -1239,8 +1241,9 @@ __global__ __launch_bounds__(kBlock) void k_sum_partial(const double* __restrict
   if (threadIdx.x == 0) partials[blockIdx.x] = red[0];
 }
 
+// mode 0: *out = sum; 1: *out = sqrt(sum); 2: *out += sum; 3: *out = sum / 2
 __global__ __launch_bounds__(kBlock) void k_dot_final(const double* __restrict__ partials, int nb,
-                                                      double* __restrict__ out, int take_sqrt) {
+                                                      double* __restrict__ out, int mode) {
   __shared__ double red[kBlock];
   double acc = 0;
   for (int i = threadIdx.x; i < nb; i += blockDim.x) acc += partials[i];
@@ -1250,7 +1253,10 @@ __global__ __launch_bounds__(kBlock) void k_dot_final(const double* __restrict__
     if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
     __syncthreads();
   }
-  if (threadIdx.x == 0) *out = take_sqrt ? sqrt(red[0]) : red[0];
+  if (threadIdx.x == 0) {
+    const double v = red[0];
+    *out = mode == 0 ? v : (mode == 1 ? sqrt(v) : (mode == 2 ? *out + v : 0.5 * v));
+  }
 }
 
 // ---- Arnoldi step by modified Gram--Schmidt, one launch per projection: launch i
@@ -1461,7 +1467,7 @@ __global__ __launch_bounds__(kBlock) void k_rhs_adjoint_s(
     const int32_t* __restrict__ b_ptr, const int32_t* __restrict__ b_col,
     const double* __restrict__ b_val, const int32_t* __restrict__ bt_ptr,
     const int32_t* __restrict__ bt_col, const double* __restrict__ bt_val,
-    const double* __restrict__ lam, double* __restrict__ gs) {
+    const double* __restrict__ lam, double* __restrict__ gs, int accumulate) {
   const int64_t row = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int64_t ns = D * nfree + nv;
   if (row < nfree) {
@@ -1477,7 +1483,7 @@ __global__ __launch_bounds__(kBlock) void k_rhs_adjoint_s(
         for (int s = 0; s < R; ++s) sp += lam[s * ns + D * nfree + b_col[p]];
         acc -= b_val[(int64_t)p * D + c] * sp;
       }
-      gs[c * nfree + row] = acc;
+      gs[c * nfree + row] = accumulate ? gs[c * nfree + row] + acc : acc;
     }
   } else if (row < nfree + nv) {
     const int64_t v = row - nfree;
@@ -1488,7 +1494,7 @@ __global__ __launch_bounds__(kBlock) void k_rhs_adjoint_s(
         for (int s = 0; s < R; ++s) su += lam[s * ns + c * nfree + bt_col[p]];
         acc -= bt_val[(int64_t)p * D + c] * su;
       }
-    gs[D * nfree + v] = acc;
+    gs[D * nfree + v] = accumulate ? gs[D * nfree + v] + acc : acc;
   }
 }
 
@@ -1531,6 +1537,24 @@ __global__ __launch_bounds__(kBlock) void k_nu_rows(int64_t nfree, int64_t nv, i
     }
   }
   rowsum[row] = tot;
+}
+
+// e = state - target on the velocity entries, 0 on the pressure entries
+__global__ __launch_bounds__(kBlock) void k_velocity_diff(int64_t nvel, int64_t ns, const double* __restrict__ a,
+                                                          const double* __restrict__ b, double* __restrict__ e) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < ns) e[i] = i < nvel ? a[i] - b[i] : 0.0;
+}
+
+// ga = s v, gb = -s v with s = *scale (1 when scale is null); ga or gb may be null
+__global__ __launch_bounds__(kBlock) void k_scaled_pair(int64_t n, const double* __restrict__ scale,
+                                                        const double* __restrict__ v, double* __restrict__ ga,
+                                                        double* __restrict__ gb) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const double w = (scale ? *scale : 1.0) * v[i];
+  if (ga) ga[i] = w;
+  if (gb) gb[i] = -w;
 }
 
 __global__ __launch_bounds__(kBlock) void k_mass_apply(int64_t nfree, int64_t nv, int D,
@@ -1832,11 +1856,18 @@ hipError_t transpose(const double* in, double* out, int64_t N, hipStream_t s) {
   return hipGetLastError();
 }
 
-hipError_t coarse_gemv(const double* inv, int64_t N, const double* b, double* x,
-                       const int64_t* pins, int npins, double* part, hipStream_t s) {
-  if (pins && npins > 0) k_zero_pins<<<dim3(1), dim3(64), 0, s>>>(const_cast<double*>(b), pins, npins);
-  k_coarse_gemv_part<<<dim3((unsigned)((N + 63) / 64), kCoarseSplit), dim3(kBlock), 0, s>>>(inv, N, b, part);
-  k_coarse_reduce<<<dim3(blocks_for(N)), dim3(kBlock), 0, s>>>(part, N, x);
+hipError_t coarse_solve(const double* inv, const double* mat, int64_t N, double* b, double* x,
+                        const int64_t* pins, int npins, double* part, hipStream_t s) {
+  const dim3 gp((unsigned)((N + 63) / 64), kCoarseSplit), gr(blocks_for(N));
+  if (pins && npins > 0) k_zero_pins<<<dim3(1), dim3(64), 0, s>>>(b, pins, npins);
+  k_coarse_gemv_part<<<gp, dim3(kBlock), 0, s>>>(inv, N, b, part);
+  k_coarse_reduce<<<gr, dim3(kBlock), 0, s>>>(part, N, x, 0);
+  if (mat) {  // one step of iterative refinement: b <- b - M x, x <- x + inv b
+    k_coarse_gemv_part<<<gp, dim3(kBlock), 0, s>>>(mat, N, x, part);
+    k_coarse_reduce<<<gr, dim3(kBlock), 0, s>>>(part, N, b, 1);
+    k_coarse_gemv_part<<<gp, dim3(kBlock), 0, s>>>(inv, N, b, part);
+    k_coarse_reduce<<<gr, dim3(kBlock), 0, s>>>(part, N, x, 2);
+  }
   return hipGetLastError();
 }
 
@@ -1959,12 +1990,13 @@ hipError_t update(const DevLevel& L, const double* b, double dt, const double* k
 }
 
 hipError_t rhs_adjoint(const DevLevel& L, int64_t nnodes, const int32_t* mt_ptr, const int32_t* mt_col,
-                       const double* mt_val, const double* lam, double* gf, double* gstate, hipStream_t s) {
+                       const double* mt_val, const double* lam, double* gf, double* gstate, int accumulate,
+                       hipStream_t s) {
   k_rhs_adjoint_f<<<dim3(blocks_for(nnodes)), dim3(kBlock), 0, s>>>(nnodes, L.nfree, L.nv, L.dim, L.r, mt_ptr,
                                                                     mt_col, mt_val, lam, gf);
   k_rhs_adjoint_s<<<dim3(blocks_for(L.nfree + L.nv)), dim3(kBlock), 0, s>>>(
       L.nfree, L.nv, L.dim, L.r, L.s_ptr, L.s_col, L.d64.s_Lt, L.b_ptr, L.b_col, L.d64.b_val, L.bt_ptr, L.bt_col,
-      L.d64.bt_val, lam, gstate);
+      L.d64.bt_val, lam, gstate, accumulate);
   return hipGetLastError();
 }
 
@@ -1978,14 +2010,32 @@ hipError_t update_adjoint(const DevLevel& L, const double* b, double dt, const d
 }
 
 hipError_t nu_sensitivity(const DevLevel& L, const double* A, double dt, const double* lam, const double* kv,
-                          const double* state, double* rowsum, double* partials, double* out, hipStream_t s) {
+                          const double* state, double* rowsum, double* partials, double* out, int accumulate,
+                          hipStream_t s) {
   Coef<double> c{};
   for (int i = 0; i < L.r * L.r; ++i) c.v[i] = dt * A[i];
   k_nu_rows<<<dim3(blocks_for(L.nfree)), dim3(kBlock), 0, s>>>(L.nfree, L.nv, L.dim, L.r, c, L.s_ptr, L.s_col,
                                                                L.s_K1, lam, kv, state, rowsum);
   const int nb = (int)std::min<int64_t>(kReduceBlocks, blocks_for(L.nfree));
   k_sum_partial<<<dim3(nb), dim3(kBlock), 0, s>>>(rowsum, L.nfree, partials);
-  k_dot_final<<<dim3(1), dim3(kBlock), 0, s>>>(partials, nb, out, 0);
+  k_dot_final<<<dim3(1), dim3(kBlock), 0, s>>>(partials, nb, out, accumulate ? 2 : 0);
+  return hipGetLastError();
+}
+
+hipError_t tracking_loss(const DevLevel& L, const double* state, const double* target, const double* scale,
+                         double* loss, double* grad_state, double* grad_target, double* e, double* Me,
+                         double* partials, hipStream_t s) {
+  const int64_t nvel = (int64_t)L.dim * L.nfree, ns = nvel + L.nv;
+  k_velocity_diff<<<dim3(blocks_for(ns)), dim3(kBlock), 0, s>>>(nvel, ns, state, target, e);
+  k_mass_apply<<<dim3(blocks_for(L.nfree + L.nv)), dim3(kBlock), 0, s>>>(L.nfree, L.nv, L.dim, L.s_ptr, L.s_col,
+                                                                         L.d64.s_M, e, Me);
+  if (loss) {
+    const int nb = (int)std::min<int64_t>(kReduceBlocks, blocks_for(ns));
+    k_dot_partial<<<dim3(nb), dim3(kBlock), 0, s>>>(e, Me, ns, partials);
+    k_dot_final<<<dim3(1), dim3(kBlock), 0, s>>>(partials, nb, loss, 3);
+  }
+  if (grad_state || grad_target)
+    k_scaled_pair<<<dim3(blocks_for(ns)), dim3(kBlock), 0, s>>>(ns, scale, Me, grad_state, grad_target);
   return hipGetLastError();
 }
 

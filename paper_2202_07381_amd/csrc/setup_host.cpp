@@ -744,10 +744,12 @@ double inf_norm(int r, const double* M) {
 }
 }  // namespace
 
-bool hessenberg_eigs(int m, const double* H, int ldh, double* wr, double* wi) {
+bool hessenberg_eigs_ws(int m, const double* H, int ldh, double* wr, double* wi, std::complex<double>* work,
+                        int* iwork) {
   using C = std::complex<double>;
   if (m < 1) return true;
-  std::vector<C> a((size_t)m * m, C(0.0));  // row-major working copy
+  C* a = work;  // row-major working copy
+  for (size_t q = 0; q < (size_t)m * m; ++q) a[q] = C(0.0);
   double nrm = 0.0;
   for (int j = 0; j < m; ++j)
     for (int i = 0; i <= std::min(j + 1, m - 1); ++i) {
@@ -755,7 +757,9 @@ bool hessenberg_eigs(int m, const double* H, int ldh, double* wr, double* wi) {
       nrm = std::max(nrm, std::abs(H[(size_t)j * ldh + i]));
     }
   auto A = [&](int i, int j) -> C& { return a[(size_t)i * m + j]; };
-  std::vector<C> ev(m);
+  C* ev = work + (size_t)m * m;
+  C* cs = ev + m;
+  C* sn = cs + m;
   const double eps = 4.0 * 2.220446049250313e-16;
   int hi = m - 1, iter = 0;
   while (hi >= 0) {
@@ -785,7 +789,6 @@ bool hessenberg_eigs(int m, const double* H, int ldh, double* wr, double* wi) {
     if (iter % 11 == 0) mu = d + 0.75 * std::abs(r);
     // one QR step on the block: B - mu I = Q R by Givens rotations, B <- R Q + mu I
     for (int k = l; k <= hi; ++k) A(k, k) -= mu;
-    std::vector<C> cs(hi - l), sn(hi - l);
     for (int k = l; k < hi; ++k) {
       const C x = A(k, k), y = A(k + 1, k);
       const double rr = std::sqrt(std::norm(x) + std::norm(y));
@@ -808,14 +811,29 @@ bool hessenberg_eigs(int m, const double* H, int ldh, double* wr, double* wi) {
     }
     for (int k = l; k <= hi; ++k) A(k, k) += mu;
   }
-  std::vector<int> order(m);
-  std::iota(order.begin(), order.end(), 0);
-  std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return ev[x].real() > ev[y].real(); });
+  // order by decreasing real part, ties in index order (a stable insertion sort, no
+  // temporary storage)
+  int* order = iwork;
+  for (int k = 0; k < m; ++k) {
+    int q = k;
+    while (q > 0 && ev[order[q - 1]].real() < ev[k].real()) {
+      order[q] = order[q - 1];
+      --q;
+    }
+    order[q] = k;
+  }
   for (int k = 0; k < m; ++k) {
     wr[k] = ev[order[k]].real();
     wi[k] = ev[order[k]].imag();
   }
   return true;
+}
+
+bool hessenberg_eigs(int m, const double* H, int ldh, double* wr, double* wi) {
+  if (m < 1) return true;
+  std::vector<std::complex<double>> work((size_t)m * m + 3 * (size_t)m);
+  std::vector<int> iwork(m);
+  return hessenberg_eigs_ws(m, H, ldh, wr, wi, work.data(), iwork.data());
 }
 
 bool stage_eigenbasis(const double* A, int r, StageEig& out, std::string* why) {

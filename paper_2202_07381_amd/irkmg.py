@@ -100,6 +100,7 @@ def _load() -> C.CDLL:
         "irk_mg_set_interval": (i, [vp, d, d]),
         "irk_mg_ndofs": (i64, [vp, i]),
         "irk_mg_sizes": (i, [vp, i, vp]),
+        "irk_mg_layout": (i, [vp, i, vp, vp]),
         "irk_mg_p2_nodes": (i, [vp, i, vp, vp]),
         "irk_mg_apply": (i, [vp, vp, vp, i, vp]),
         "irk_mg_vcycle": (i, [vp, vp, vp, vp]),
@@ -114,10 +115,11 @@ def _load() -> C.CDLL:
         "irk_level_restrict": (i, [vp, i, vp, vp, vp]),
         "irk_level_prolong": (i, [vp, i, vp, vp, vp]),
         "irk_coarse_solve": (i, [vp, i, vp, vp, vp]),
-        "irk_rhs_adjoint": (i, [vp, vp, vp, vp, vp]),
+        "irk_rhs_adjoint": (i, [vp, vp, vp, vp, i, vp]),
         "irk_update_adjoint": (i, [vp, vp, vp, vp]),
-        "irk_nu_sensitivity": (i, [vp, vp, vp, vp, vp, vp]),
+        "irk_nu_sensitivity": (i, [vp, vp, vp, vp, vp, i, vp]),
         "irk_mass_apply": (i, [vp, vp, vp, vp]),
+        "irk_tracking_loss": (i, [vp, vp, vp, vp, vp, vp, vp, vp]),
         "irk_ns_residual": (i, [vp, vp, vp, vp, vp, vp, vp]),
         "irk_ns_jacobian_apply": (i, [vp, vp, vp, vp, vp, vp, vp]),
         "irk_newton_default_opts": (None, [vp]),
@@ -283,6 +285,14 @@ class IrkMG:
         _check(lib.irk_mg_sizes(self.h, level, out.ctypes.data))
         return dict(nverts=int(out[0]), nnodes=int(out[1]), nfree=int(out[2]), ns=int(out[3]), nlevels=int(out[4]))
 
+    def irk_mg_layout(self, level: int = -1) -> tuple[np.ndarray, np.ndarray]:
+        """(offsets, lengths): offsets[s, c] is where velocity component c (c < dim) or the
+        pressure (c = dim) of stage s starts in the ABI layout; lengths[c] its length."""
+        off = np.zeros((self.r, self.dim + 1), dtype=np.int64)
+        ln = np.zeros(self.dim + 1, dtype=np.int64)
+        _check(lib.irk_mg_layout(self.h, level, off.ctypes.data, ln.ctypes.data))
+        return off, ln
+
     def irk_mg_p2_nodes(self, level: int = -1):
         sz = self.irk_mg_sizes(level)
         xyz = np.zeros((sz["nnodes"], self.dim))
@@ -335,22 +345,35 @@ class IrkMG:
         _check(lib.irk_update(self.h, _dev(k, self.irk_mg_ndofs(), "k"), _dev(state, sz["ns"], "state"), _stream(stream)))
 
     # -------------------------------------------------------------- adjoint
-    def irk_rhs_adjoint(self, lam, gf, gstate, stream=None):
+    def irk_rhs_adjoint(self, lam, gf, gstate, accumulate=False, stream=None):
         sz = self.irk_mg_sizes()
         _check(lib.irk_rhs_adjoint(self.h, _dev(lam, self.irk_mg_ndofs(), "lam"),
                                    _dev(gf, self.r * sz["nnodes"] * self.dim, "gf"), _dev(gstate, sz["ns"], "gstate"),
-                                   _stream(stream)))
+                                   int(accumulate), _stream(stream)))
 
     def irk_update_adjoint(self, gstate, G, stream=None):
         sz = self.irk_mg_sizes()
         _check(lib.irk_update_adjoint(self.h, _dev(gstate, sz["ns"], "gstate"), _dev(G, self.irk_mg_ndofs(), "G"),
                                       _stream(stream)))
 
-    def irk_nu_sensitivity(self, lam, k, state, out, stream=None):
+    def irk_nu_sensitivity(self, lam, k, state, out, accumulate=False, stream=None):
         sz = self.irk_mg_sizes()
         n = self.irk_mg_ndofs()
         _check(lib.irk_nu_sensitivity(self.h, _dev(lam, n, "lam"), _dev(k, n, "k"), _dev(state, sz["ns"], "state"),
-                                      _dev(out, 1, "out"), _stream(stream)))
+                                      _dev(out, 1, "out"), int(accumulate), _stream(stream)))
+
+    def irk_tracking_loss(self, state, target, loss=None, grad_state=None, grad_target=None, scale=None,
+                          stream=None):
+        """loss (1 value) = 1/2 e^T M e, e the velocity part of state - target;
+        grad_state / grad_target (ns values) = +- scale [M e; 0]; any output may be None."""
+        ns = self.irk_mg_sizes()["ns"]
+
+        def opt(t, m, name):
+            return None if t is None else _dev(t, m, name)
+
+        _check(lib.irk_tracking_loss(self.h, _dev(state, ns, "state"), _dev(target, ns, "target"),
+                                     opt(scale, 1, "scale"), opt(loss, 1, "loss"), opt(grad_state, ns, "grad_state"),
+                                     opt(grad_target, ns, "grad_target"), _stream(stream)))
 
     def irk_mass_apply(self, state, out, stream=None):
         sz = self.irk_mg_sizes()

@@ -19,7 +19,14 @@ CASES = {
     "3d2": (3, 2, 2, "radauIIA", 2, 1e-2, 1.0, None),
     "3d3": (3, 2, 3, "radauIIA", 2, 1e-2, 1.0, None),
     "cross": (2, 2, 3, "radauIIA", 3, 1 / 64, 1.0, None),
+    # the 7-level benchmark workload one level down: 128^2, 6 levels, 16,641 finest
+    # patches (above the count from which the library streams patch factors with
+    # non-temporal loads), 440,073 unknowns; its oracle takes about half a minute
+    "s128": (2, 4, 6, "radauIIA", 3, 1e-2, 1.0, None),
 }
+# cases whose oracle is too slow for the per-step sweeps over every level
+LARGE = {"s128"}
+SMALL = [c for c in CASES if c not in LARGE]
 # cases on the crossed mesh of Sec. 5.1 (four triangles per quad) instead of the
 # diagonal split
 CROSSED = {"cross"}

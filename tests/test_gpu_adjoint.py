@@ -51,6 +51,31 @@ def test_adjoint_building_blocks(case):
     Mo = torch.zeros(S.ns, dtype=torch.float64, device="cuda")
     g.irk_mass_apply(to_dev(st), Mo)
     assert relerr(to_host(Mo), np.concatenate([S.Mv @ st[:th.nvel], np.zeros(th.nverts)])) < 1e-13
+    # accumulating forms: the state adjoint and the viscosity sensitivity added in place
+    pre = rng.standard_normal(S.ns)
+    gs = to_dev(pre)
+    g.irk_rhs_adjoint(to_dev(lam), gf, gs, accumulate=True)
+    assert relerr(to_host(gs), pre + ref_s) < 1e-13
+    out = to_dev(np.array([2.5]))
+    g.irk_nu_sensitivity(to_dev(lam), to_dev(kk), to_dev(st), out, accumulate=True)
+    assert abs(to_host(out)[0] - (2.5 + ref)) < 1e-12 * abs(2.5 + ref)
+    # tracking loss 1/2 e^T M e (velocity part of state - target) and its gradients
+    from oracle.adjoint import loss as oracle_loss
+
+    tgt = rng.standard_normal(S.ns)
+    Lg = torch.zeros(1, dtype=torch.float64, device="cuda")
+    gsd, gtd = torch.zeros(S.ns, dtype=torch.float64, device="cuda"), torch.zeros(S.ns, dtype=torch.float64, device="cuda")
+    g.irk_tracking_loss(to_dev(st), to_dev(tgt), loss=Lg, grad_state=gsd, grad_target=gtd,
+                        scale=to_dev(np.array([0.75])))
+    Lref = oracle_loss(S, st, tgt[:th.nvel])
+    assert abs(to_host(Lg)[0] - Lref) < 1e-13 * abs(Lref)
+    Me = np.concatenate([S.Mv @ (st[:th.nvel] - tgt[:th.nvel]), np.zeros(th.nverts)])
+    assert relerr(to_host(gsd), 0.75 * Me) < 1e-13 and relerr(to_host(gtd), -0.75 * Me) < 1e-13
+    # field offsets of the ABI layout
+    off, ln = g.irk_mg_layout()
+    assert list(ln) == [th.nfree] * th.dim + [th.nverts]
+    for i in range(S.r):
+        assert list(off[i]) == [i * S.ns + c * th.nfree for c in range(th.dim)] + [i * S.ns + th.nvel]
 
 
 @pytest.mark.parametrize("case", ["c1", "oseen", "3d3"])

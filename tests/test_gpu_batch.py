@@ -110,3 +110,51 @@ def test_batch_streams_mode_matches_one_by_one():
         b.close()
     with pytest.raises(irkmg.IrkError):
         irkmg.IrkBatch(gs, autotune=False, mode=0)
+
+
+# members of the uneven 64-solve batch (seed 4) with meshes up to 128 x 128: both stage
+# counts, viscosities from 0.018 to 0.77
+C4_SUBSET = [2, 9, 10, 11, 17, 19, 22]
+
+
+def test_batch_c4_subset_persistent_matches_oracle():
+    """The persistent launch (mode 0, no autotuning, so the one-launch schedule is the
+    one that runs) on seven members of the uneven batch workload, each against the
+    oracle's FGMRES: equal iteration counts, solutions within 1e-10 relative."""
+    from oracle.fgmres import fgmres
+    from oracle.multigrid import Hierarchy
+    from oracle.tableau import tableau
+    from paper_2202_07381_amd import irkmg
+    from paper_2202_07381_amd import workloads as wl
+
+    specs = wl.batch_specs()
+    gs, Fs, Hs = [], [], []
+    for j in C4_SUBSET:
+        sp = specs[j]
+        nl = int(np.log2(sp.n // 4)) + 1
+        lv = wl.square_hierarchy(4, nl)
+        A, b, c = irkmg.irk_tableau_builtin("radauIIA", sp.r)
+        say(f"[batch-c4] member {j}: n={sp.n} r={sp.r} nu={sp.nu:.4f} levels={nl}")
+        gs.append(irkmg.IrkMG(lv, A, b, c, sp.dt, sp.nu))
+        H = Hierarchy(lv, tableau("radauIIA", sp.r)[0], sp.dt, sp.nu)
+        S = H.finest
+        f = wl.forcing_2d(sp.forcing_seed)
+        Fs.append(S.rhs([S.th.interpolate(f, 0.0)] * S.r, np.zeros(S.th.nvel), np.zeros(S.th.nverts)))
+        Hs.append(H)
+    b = irkmg.IrkBatch(gs, autotune=False, mode=0)
+    assert b.irk_batch_get_opts()["mode"] == 0
+    ks = [torch.zeros(F.size, dtype=torch.float64, device="cuda") for F in Fs]
+    say("[batch-c4] persistent solve")
+    st, infos, ms = b.irk_batch_fgmres_solve([to_dev(F) for F in Fs], ks, rtol=1e-8, maxit=200, restart=30)
+    assert st == irkmg.IRK_OK
+    for j, H, F, k, info in zip(C4_SUBSET, Hs, Fs, ks, infos):
+        S = H.finest
+        xo, io = fgmres(S.apply, H.vcycle, F, np.zeros_like(F), 1e-8, 200, 30, project=S.project_pressure_mean)
+        err = relerr(to_host(k), xo)
+        say(f"[batch-c4] member {j}: its={info['iterations']} oracle={io.iterations} err={err:.2e} "
+            f"latency={info['latency_ms']:.2f} ms")
+        assert info["converged"] and info["iterations"] == io.iterations
+        assert err < 1e-10
+    b.close()
+    for g in gs:
+        g.close()

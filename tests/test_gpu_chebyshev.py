@@ -2,13 +2,13 @@
 Vanka operator accelerated by Chebyshev polynomials of the first kind on [2, 8], 2 pre-
 and 2 post-steps) against the oracle, through the C ABI.  Tolerances as in
 test_gpu_parity.py: one relaxation step 1e-11 (patch inverses factored differently on
-the two sides), V-cycles max(1e-11, 4 cond(J_0) eps), FGMRES solutions after equal
+the two sides), V-cycles 1e-11 (as in test_gpu_parity.py), FGMRES solutions after equal
 iteration counts 1e-10."""
 import numpy as np
 import pytest
 
 from gpu_cases import forcing_rhs, gpu_of, oracle_of, relerr, say, to_dev, to_host
-from test_gpu_parity import coarse_tol
+from test_gpu_parity import VCYCLE_TOL
 
 pytestmark = pytest.mark.gpu
 torch = pytest.importorskip("torch")
@@ -40,10 +40,11 @@ def test_chebyshev_vcycle(case, form):
     z = torch.zeros(r.size, dtype=torch.float64, device="cuda")
     say(f"[cheb vcycle] case={case} form={form}")
     g.irk_mg_vcycle(to_dev(r), z)
-    assert relerr(to_host(z), H.vcycle(r)) < coarse_tol(H)
-    say(f"[cheb vcycle^T] case={case} form={form}")
+    err = relerr(to_host(z), H.vcycle(r))
     g.irk_mg_vcycle_transpose(to_dev(r), z)
-    assert relerr(to_host(z), H.vcycle_transpose(r)) < coarse_tol(H)
+    err_t = relerr(to_host(z), H.vcycle_transpose(r))
+    say(f"[cheb vcycle] case={case} form={form} err={err:.2e} err^T={err_t:.2e} tol={VCYCLE_TOL:.0e}")
+    assert err < VCYCLE_TOL and err_t < VCYCLE_TOL
 
 
 @pytest.mark.parametrize("case", CHEB_CASES)
@@ -145,7 +146,9 @@ def test_interval_from_ritz_estimate():
         z = torch.zeros(rv.size, dtype=torch.float64, device="cuda")
         say("[ritz interval] vcycle")
         g.irk_mg_vcycle(to_dev(rv), z)
-        assert relerr(to_host(z), Ho.vcycle(rv)) < coarse_tol(Ho)
+        err = relerr(to_host(z), Ho.vcycle(rv))
+        say(f"[ritz interval] vcycle err={err:.2e}")
+        assert err < VCYCLE_TOL
     finally:
         g.irk_mg_set_interval(2.0, 8.0)  # the cached handle keeps the paper's interval
     from paper_2202_07381_amd import irkmg

@@ -4,13 +4,13 @@ through the C ABI: one cycle of m left-preconditioned GMRES steps with the weigh
 additive operator, classical Gram--Schmidt, from the current iterate.  Tolerances: one
 relaxation step 1e-10 (the patch inverses are factored differently on the two sides and
 the step normalises and solves a small least-squares problem); V-cycles
-max(1e-10, 4 cond(J_0) eps) as for the other relaxations; FGMRES solutions after equal
+1e-11 as for the other relaxations; FGMRES solutions after equal
 iteration counts 1e-10."""
 import numpy as np
 import pytest
 
 from gpu_cases import forcing_rhs, gpu_of, levels_of, oracle_of, relerr, say, to_dev, to_host
-from test_gpu_parity import coarse_tol
+from test_gpu_parity import VCYCLE_TOL
 
 pytestmark = pytest.mark.gpu
 torch = pytest.importorskip("torch")
@@ -40,13 +40,14 @@ def test_gmres_vcycle(case, form):
     g, H = gpu_of(case, patch_form=form, smoother=2), oracle_of(case, smoother="gmres")
     r = np.random.default_rng(52).standard_normal(g.irk_mg_ndofs())
     z = torch.zeros(r.size, dtype=torch.float64, device="cuda")
-    tol = max(1e-10, coarse_tol(H))
+    tol = VCYCLE_TOL
     say(f"[gmres vcycle] case={case} form={form}")
     g.irk_mg_vcycle(to_dev(r), z)
-    assert relerr(to_host(z), H.vcycle(r)) < tol
-    say(f"[gmres vcycle^T] case={case} form={form}")
+    err = relerr(to_host(z), H.vcycle(r))
     g.irk_mg_vcycle_transpose(to_dev(r), z)
-    assert relerr(to_host(z), H.vcycle_transpose(r)) < tol
+    err_t = relerr(to_host(z), H.vcycle_transpose(r))
+    say(f"[gmres vcycle] case={case} form={form} err={err:.2e} err^T={err_t:.2e} tol={tol:.2e}")
+    assert err < tol and err_t < tol
 
 
 @pytest.mark.parametrize("case", GR_CASES)
@@ -85,7 +86,9 @@ def test_gmres_three_steps_and_adjoint():
     z = torch.zeros(S.n, dtype=torch.float64, device="cuda")
     say("[gmres 3/3] vcycle")
     g.irk_mg_vcycle(to_dev(rv), z)
-    assert relerr(to_host(z), H.vcycle(rv)) < max(1e-10, coarse_tol(H))
+    err = relerr(to_host(z), H.vcycle(rv))
+    say(f"[gmres 3/3] vcycle err={err:.2e}")
+    assert err < VCYCLE_TOL
     F = forcing_rhs("oseen")
     say("[gmres 3/3] fgmres")
     k = torch.zeros(S.n, dtype=torch.float64, device="cuda")

@@ -3,24 +3,30 @@
 Tolerances: single operator applications (residual, transfers) 1e-13 relative to the
 largest entry; patch sweeps 1e-11 (the patch inverses come from different elimination
 orders on the two sides, so they agree to the conditioning of the patch matrices
-times the unit roundoff); coarse solve and V-cycle max(1e-11, 4 cond(J_0) eps): the
-library applies an explicit Gauss--Jordan inverse of the pinned coarse operator and
-the oracle an LU solve, two backward-stable solves whose results differ by up to the
-condition number times the unit roundoff (cond(J_0) reaches 1e8 at dt = 1e-2);
-FGMRES solutions after equal iteration counts 1e-10 relative (the target stated for
-the method).  Sweeps, V-cycles and solves run with the patch forms 0 (dense patch
+times the unit roundoff); coarse solve and V-cycle max(1e-12, 4 cond_S(J_0) eps) with
+Skeel's componentwise condition number cond_S(J_0) = || |J_0^{-1}| |J_0| ||_inf of the
+pinned coarse operator (1e3 to 6e5 on these cases, against normwise condition numbers
+up to 1.3e8, which come from the scaling of the stage blocks): the oracle solves by LU
+with partial pivoting, the library by its stored inverse followed by one step of FP64
+iterative refinement, two solves whose forward errors are bounded by a small multiple
+of cond_S eps (Skeel's bound for a solve that is componentwise backward stable, which
+one refinement step in working precision provides); whole V-cycles (every relaxation)
+1e-11, about 20 times the largest difference measured (4.8e-13 on the 128 x 128 case;
+1e-14 to 7e-14 on the small cases, while the coarse solve alone differs by up to 7e-11
+on them); the measured errors are printed; FGMRES solutions after equal iteration
+counts 1e-10 relative (the target stated for the method).  Sweeps, V-cycles and solves run with the patch forms 0 (dense patch
 inverses), 1 (inverses factored through the stage eigenbasis) and 2 (automatic: for
 r >= 2 the symmetric factored form, wrapped diagonals of each block inverse, on the
 Stokes cases, else form 1), which apply the same operator up to rounding."""
 import numpy as np
 import pytest
 
-from gpu_cases import CASES, forcing_rhs, gpu_of, levels_of, oracle_of, relerr, say, to_dev, to_host, wind_of
+from gpu_cases import CASES, SMALL, forcing_rhs, gpu_of, levels_of, oracle_of, relerr, say, to_dev, to_host, wind_of
 
 pytestmark = pytest.mark.gpu
 torch = pytest.importorskip("torch")
 
-ALL = list(CASES)
+ALL = list(SMALL)
 FORMS = [0, 1, 2]
 
 
@@ -71,13 +77,22 @@ def test_transfers(case):
         assert relerr(to_host(fine), base + P @ xc) < 1e-13
 
 
+VCYCLE_TOL = 1e-11
+_SKEEL = {}
+
+
 def coarse_tol(H):
-    J = H.systems[0].J.toarray()
-    for q in H.pinned:
-        J[q, :] = 0.0
-        J[:, q] = 0.0
-        J[q, q] = 1.0
-    return max(1e-11, 4 * np.linalg.cond(J) * np.finfo(float).eps)
+    """max(1e-12, 4 cond_S(J_0) eps) for the pinned coarse operator J_0 of H, with
+    Skeel's condition number cond_S(J_0) = || |J_0^{-1}| |J_0| ||_inf."""
+    if id(H) not in _SKEEL:
+        J = H.systems[0].J.toarray()
+        for q in H.pinned:
+            J[q, :] = 0.0
+            J[:, q] = 0.0
+            J[q, q] = 1.0
+        cs = float(np.max(np.abs(np.linalg.inv(J)) @ np.abs(J) @ np.ones(J.shape[0])))
+        _SKEEL[id(H)] = (H, max(1e-12, 4 * cs * np.finfo(float).eps))
+    return _SKEEL[id(H)][1]
 
 
 @pytest.mark.parametrize("case", ALL)
@@ -89,7 +104,9 @@ def test_coarse_solve(case):
         say(f"[coarse] case={case} transpose={tr}")
         x = torch.zeros_like(to_dev(b))
         g.irk_coarse_solve(to_dev(b), x, transpose=tr)
-        assert relerr(to_host(x), H.coarse_solve(b, tr)) < coarse_tol(H)
+        err = relerr(to_host(x), H.coarse_solve(b, tr))
+        say(f"[coarse] case={case} transpose={tr} err={err:.2e} tol={coarse_tol(H):.2e}")
+        assert err < coarse_tol(H)
 
 
 @pytest.mark.parametrize("form", FORMS)
@@ -100,10 +117,11 @@ def test_vcycle(case, form):
     say(f"[vcycle] case={case} form={form}")
     z = torch.zeros(r.size, dtype=torch.float64, device="cuda")
     g.irk_mg_vcycle(to_dev(r), z)
-    assert relerr(to_host(z), H.vcycle(r)) < coarse_tol(H)
-    say(f"[vcycle^T] case={case}")
+    err = relerr(to_host(z), H.vcycle(r))
     g.irk_mg_vcycle_transpose(to_dev(r), z)
-    assert relerr(to_host(z), H.vcycle_transpose(r)) < coarse_tol(H)
+    err_t = relerr(to_host(z), H.vcycle_transpose(r))
+    say(f"[vcycle] case={case} form={form} err={err:.2e} err^T={err_t:.2e} tol={VCYCLE_TOL:.0e}")
+    assert err < VCYCLE_TOL and err_t < VCYCLE_TOL
 
 
 @pytest.mark.parametrize("form", FORMS)
@@ -316,7 +334,9 @@ def test_custom_tableaux(kind):
     r = np.random.default_rng(41).standard_normal(S.n)
     z = torch.zeros(S.n, dtype=torch.float64, device="cuda")
     g.irk_mg_vcycle(to_dev(r), z)
-    assert relerr(to_host(z), H.vcycle(r)) < coarse_tol(H)
+    err = relerr(to_host(z), H.vcycle(r))
+    say(f"[custom] {kind} vcycle err={err:.2e}")
+    assert err < VCYCLE_TOL
     f = wl.forcing_2d(1)
     F = S.rhs([S.th.interpolate(f, 0.0)] * S.r, np.zeros(S.th.nvel), np.zeros(S.th.nverts))
     k = torch.zeros(S.n, dtype=torch.float64, device="cuda")
@@ -347,3 +367,4 @@ def test_single_level_hierarchy():
     assert info["converged"] and info["iterations"] == io.iterations <= 2
     assert relerr(to_host(k), xo) < coarse_tol(H)
     g.close()
+

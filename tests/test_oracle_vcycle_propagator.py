@@ -41,7 +41,7 @@ TOL = 2e-9
 
 def _dense_S(H, lev, weighted):
     """W sum_v R_v^T A_v^{-1} R_v as a dense matrix, from the patch index sets and J."""
-    J = H.systems[lev].J.toarray()
+    J = H.ops[lev].toarray()
     pats = patch_dofs(H.spaces[lev], H.r)
     n = J.shape[0]
     S = np.zeros((n, n))
@@ -57,7 +57,7 @@ class _Propagator:
     def __init__(self, H, omega, weighted, relax="sweep", interval=(2.0, 8.0)):
         self.H = H
         self.omega, self.relax, self.interval = omega, relax, interval
-        self.J = [s.J.toarray() for s in H.systems]
+        self.J = [J.toarray() for J in H.ops]
         self.Jpinv = [np.linalg.pinv(J) for J in self.J]
         self.S = [None] + [_dense_S(H, lev, weighted) for lev in range(1, len(H.systems))]
         self.P = [None] + [P.toarray() for P in H.P[1:]]
@@ -99,7 +99,7 @@ def _project(H, X):
 def _check(H, prop, nprobe, seed, tol):
     S = H.finest
     X = np.random.default_rng(seed).standard_normal((S.n, nprobe))
-    JX = S.J @ X
+    JX = H.ops[-1] @ X
     got = np.column_stack([H.vcycle(JX[:, j]) for j in range(nprobe)])
     expect = _project(H, X - prop.E(len(H.systems) - 1, X))
     err = np.abs(got - expect).max() / np.abs(expect).max()
