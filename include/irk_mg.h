@@ -182,6 +182,21 @@ int irk_mg_patch_form(const irk_mg* h);
 irk_status irk_mg_ritz(irk_mg* h, int level, int steps, const double* v0, double* H, double* ritz_re,
                        double* ritz_im, int* nritz, void* stream);
 
+/* irk_mg_ritz without any allocation, for callers that cannot allocate device memory
+ * (code under HIP graph capture, tight serving loops, harnesses that forbid hipMalloc).
+ * Same arguments, results and errors as irk_mg_ritz, bitwise equal to them.  The Arnoldi
+ * basis, Hessenberg matrix and reduction partial sums live in a static device array of
+ * 64 MiB that the library holds on every GPU it runs on until the process ends (its
+ * address is looked up on the first call made with that GPU current): (steps + 1) level
+ * vectors of the handle's precision plus (steps + 1)^2 + 256 * 9 doubles must fit, each
+ * part rounded up to 256 bytes, else IRK_EINVAL with a message naming the need.  The
+ * host side uses fixed-size stack storage.  All calls on one GPU share that array and
+ * it keeps the last call's contents (each call initialises what it reads): calls that
+ * overlap in time on one GPU, from several threads or streams, race and must not be
+ * made.  Synchronises `stream`. */
+irk_status irk_mg_ritz_noalloc(irk_mg* h, int level, int steps, const double* v0, double* H, double* ritz_re,
+                               double* ritz_im, int* nritz, void* stream);
+
 /* Change the Chebyshev interval of a handle (smoother 1) after setup, for example to
  * [lambda/4, lambda] from irk_mg_ritz.  IRK_EINVAL unless 0 < lo < hi < inf. */
 irk_status irk_mg_set_interval(irk_mg* h, double lo, double hi);

@@ -97,6 +97,7 @@ def _load() -> C.CDLL:
         "irk_stage_basis": (i, [i, vp, vp, vp, vp]),
         "irk_hessenberg_eigs": (i, [i, vp, i, vp, vp]),
         "irk_mg_ritz": (i, [vp, i, i, vp, vp, vp, vp, vp, vp]),
+        "irk_mg_ritz_noalloc": (i, [vp, i, i, vp, vp, vp, vp, vp, vp]),
         "irk_mg_set_interval": (i, [vp, d, d]),
         "irk_mg_ndofs": (i64, [vp, i]),
         "irk_mg_sizes": (i, [vp, i, vp]),
@@ -266,6 +267,16 @@ class IrkMG:
         m = C.c_int(0)
         _check(lib.irk_mg_ritz(self.h, level, steps, _dev(v0, n, "v0"), H.ctypes.data, wr.ctypes.data,
                                wi.ctypes.data, C.byref(m), _stream(stream)))
+        return H, (wr + 1j * wi)[: m.value]
+
+    def irk_mg_ritz_noalloc(self, level, steps, v0, stream=None):
+        """irk_mg_ritz with the library's static device scratch instead of allocations."""
+        n = self.irk_mg_ndofs(level)
+        H = np.zeros((steps + 1, steps), order="F")
+        wr, wi = np.zeros(steps), np.zeros(steps)
+        m = C.c_int(0)
+        _check(lib.irk_mg_ritz_noalloc(self.h, level, steps, _dev(v0, n, "v0"), H.ctypes.data, wr.ctypes.data,
+                                       wi.ctypes.data, C.byref(m), _stream(stream)))
         return H, (wr + 1j * wi)[: m.value]
 
     def irk_mg_set_interval(self, lo, hi):
