@@ -619,8 +619,9 @@ def ns_element_flops(dim, r, ncells):
 def run_ns(n, nsteps, smoother, precond="oseen", dt=1.0 / 400, dim=2, nu=0.01, eta_fixed=0.0):
     """Navier--Stokes time stepping (Sec. 3.2): Newton with Eisenstat--Walker forcing,
     FGMRES preconditioned by the V-cycle of the Oseen operator linearised at the initial
-    state (precond "oseen"; set up once, kept for every step) or of the Stokes operator
-    ("stokes"), 2D n x n, RadauIIA(3), nu = 0.01 (Re = 100 for unit speed and length),
+    state (precond "oseen"; set up once, kept for every step), of the Stokes operator
+    ("stokes"), or of the Newton Jacobian itself, rediscretised on every level at each
+    Newton iterate ("newton", Sec. 3.2; its set-up time is part of the step), 2D n x n, RadauIIA(3), nu = 0.01 (Re = 100 for unit speed and length),
     dt = 1/400 (the paper's cylinder run), a unit-speed divergence-free initial state and a
     smooth body force, all synthetic.  dim = 3: the n^3 cube (Kuhn tetrahedra), RadauIIA(2),
     initial state and force from the 3D forcing modes."""
@@ -646,6 +647,7 @@ def run_ns(n, nsteps, smoother, precond="oseen", dt=1.0 / 400, dim=2, nu=0.01, e
           "gmres": dict(smoother=2)}[smoother]
     t0 = time.time()
     g = irkmg.IrkMG(levels, A, b, c, dt, nu, wind_nodal=u0 if precond == "oseen" else None, **kw)
+    pc = 1 if precond == "newton" else 0
     torch.cuda.synchronize()
     setup_s = time.time() - t0
     form = g.irk_mg_patch_form()
@@ -666,7 +668,7 @@ def run_ns(n, nsteps, smoother, precond="oseen", dt=1.0 / 400, dim=2, nu=0.01, e
         g.irk_rhs(fst, state, F)
         torch.cuda.synchronize()
         t1 = time.perf_counter()
-        info = g.irk_ns_newton_solve(F, state, k, rtol=1e-8, eta_fixed=eta_fixed)
+        info = g.irk_ns_newton_solve(F, state, k, rtol=1e-8, eta_fixed=eta_fixed, precond=pc)
         torch.cuda.synchronize()
         ms = 1e3 * (time.perf_counter() - t1)
         g.irk_update(k, state)
@@ -734,8 +736,9 @@ def main():
                     help="ns: constant forcing term instead of Eisenstat-Walker (e.g. 1e-8 to count iterations "
                          "of tight linear solves)")
     ap.add_argument("--ns-dt", type=float, default=1.0 / 400, help="ns: time step (default the cylinder run's 1/400)")
-    ap.add_argument("--ns-precond", default="oseen", choices=["oseen", "stokes"],
-                    help="ns: operator of the V-cycle (Oseen at the initial state, or Stokes)")
+    ap.add_argument("--ns-precond", default="oseen", choices=["oseen", "stokes", "newton"],
+                    help="ns: operator of the V-cycle (Oseen at the initial state, Stokes, or the Newton "
+                         "Jacobian at every iterate)")
     ap.add_argument("--relax-n", type=int, default=512, help="relax: finest mesh size of the Oseen problem")
     ap.add_argument("--batch-count", type=int, default=64)
     ap.add_argument("--t1-level", type=int, default=5, help="t1: refinement level l of the crossed 8x8 mesh")

@@ -346,6 +346,10 @@ typedef struct irk_newton_opts {
                            ||G(k + lam delta)|| <= (1 - ls_alpha lam) ||G(k)||          */
   int ls_maxit;         /* 12 (0 .. 60)                                              */
   double ls_alpha;      /* 1e-4 (in (0, 1))                                          */
+  int precond;          /* FGMRES preconditioner of the Newton steps: 0 (default) the
+                           handle's own V-cycle, built for its Kronecker operator; 1 the
+                           V-cycle of the Newton Jacobian itself, rebuilt at every Newton
+                           iterate (irk_ns_newton_preconditioner; FP64 handles only)      */
 } irk_newton_opts;
 /* history (host, may be NULL): ||G|| before each step and at exit; etas, linear_its and
  * lambdas (host, may be NULL): each step's forcing term, FGMRES iterations and step
@@ -367,6 +371,24 @@ void irk_newton_default_opts(irk_newton_opts* opt);
  * error. */
 irk_status irk_ns_newton_solve(irk_mg* h, const double* F, const double* state, const double* g_stages,
                                double* k, const irk_newton_opts* opt, irk_newton_info* info, void* stream);
+
+/* The V-cycle of the Newton Jacobian (Sec. 3.2): block (i, j) = delta_ij M^ +
+ * dt a_ij [K + N'(U_i) B; B^T 0], not a Kronecker product, rediscretised on every level
+ * at the stage velocities U_i of (state, k, g_stages) (as for irk_ns_residual) carried to
+ * the coarser levels by injection at their P2 nodes (which are nodes of the next finer
+ * level).  enable = 1 assembles the per-stage velocity blocks of every level (on the
+ * host), factorises the stage-coupled patch matrices of every level in the dense form
+ * and inverts the coarse operator (on the GPU), and switches the handle's V-cycle
+ * (irk_mg_vcycle, irk_level_sweep, irk_level_apply, irk_coarse_solve, and the
+ * preconditioner of irk_fgmres_solve) to these operators; enable = 0 switches back to
+ * the handle's own operator (state, g_stages and k are then not read).  FP64 handles
+ * only; no transposed form while enabled (IRK_EINVAL).  The first call allocates the
+ * per-stage blocks (r dim^2 doubles per entry of each level's scalar pattern), the dense
+ * patch inverses (sum over patches of (r n_v)^2 doubles per level) and three dense
+ * coarse matrices.  Synchronises `stream`.  Errors: IRK_EINVAL, IRK_ESINGULAR (zero
+ * pivot), IRK_ENOMEM, IRK_EHIP. */
+irk_status irk_ns_newton_preconditioner(irk_mg* h, const double* state, const double* g_stages, const double* k,
+                                        int enable, void* stream);
 
 /* Adjoint building blocks (transposes of the maps above; used to differentiate a
  * sequence of IRK steps with respect to the forcing, the viscosity and the state).

@@ -102,6 +102,14 @@ std::string build_transfer(const HostLevel& coarse, HostLevel& fine, const int64
 // pinned in every stage; *max_abs = its largest entry in magnitude.
 void coarse_matrix(const HostLevel& L, int r, const double* A, double dt, std::vector<double>& J,
                    double* max_abs);
+// Per-stage velocity operator of the Newton Jacobian for one stage velocity U (nodal,
+// nn x dim): adds (nu K + C(U)) delta_ce + R(U)_ce to out[p dim^2 + c dim + e] for every
+// entry p of the scalar pattern.
+void assemble_newton_block(const HostLevel& L, double nu, const double* U, double* out);
+// Dense coarse Newton Jacobian (row-major, pinned pressures) from the per-stage blocks
+// nw[(p r + s) dim^2 + c dim + e].
+void coarse_matrix_newton(const HostLevel& L, int r, const double* A, double dt, const double* nw,
+                          std::vector<double>& J, double* max_abs);
 
 // ------------------------------------------------------------- stage eigenbasis
 // Real block diagonalisation A = W T W^{-1} of the Butcher matrix.  T is block diagonal
@@ -298,6 +306,17 @@ struct Handle {
           *ns_inc = nullptr;
   double *ns_geo = nullptr, *ns_w = nullptr, *ns_U = nullptr, *ns_elem = nullptr;
   double *ns_k = nullptr, *ns_kt = nullptr, *ns_F = nullptr, *ns_G = nullptr;  // iterate, trial, rhs, residual
+  // Newton Jacobian preconditioner (Sec. 3.2): per level the per-stage velocity blocks
+  // N_s = K + N'(U_s) on the scalar pattern ((p r + s) dim^2 + c dim + e), and on levels
+  // >= 1 the dense inverses of the stage-coupled patch matrices with their layout; the
+  // coarse inverse and pinned operator (column-major) with scratch for their set-up.
+  // Allocated on first use; nw_active switches the V-cycle to these operators.
+  bool nw_active = false, nw_ready = false;
+  std::vector<double*> nw_vals, nw_inv;
+  std::vector<int32_t*> nw_ld;
+  std::vector<int64_t*> nw_off;
+  double *nw_cinv = nullptr, *nw_cmat = nullptr, *nw_ctmp = nullptr, *nw_colk = nullptr;
+  int64_t* nw_swp = nullptr;
 };
 
 // ------------------------------------------------------------------------ launchers
@@ -331,11 +350,19 @@ hipError_t prolong_add(const DevLevel& fine, const DevLevel& coarse, const DevOp
 // Factorise (invert) patches [p0, p1) with an R-stage coefficient matrix coef
 // (I (x) M_v + dt coef (x) S_v; R = r and coef = A for the dense form, R = 1 or 2 and
 // coef = a block of T for one eigen-block); inverse of patch p written column-major
-// (n x ld[p]) at out + off[p] - off0.  nmax: the largest n in the range.
+// (n x ld[p]) at out + off[p] - off0.  nmax: the largest n in the range.  nw (dense form
+// only, R = r, coef = A): the Newton Jacobian's per-stage velocity blocks (see
+// residual_newton) replace the Kronecker velocity block.
 template <typename T>
 hipError_t patch_factor_range(const DevLevel& L, const DevOps<T>& ops, int R, const double* coef,
                               double dt, const int32_t* ld, const int64_t* off, T* out, int64_t p0,
-                              int64_t p1, int64_t off0, int nmax, int* d_fail, hipStream_t s);
+                              int64_t p1, int64_t off0, int nmax, int* d_fail, hipStream_t s,
+                              const T* nw = nullptr);
+// r = F - J x (F null: J x) on a level for the Newton Jacobian of the Navier--Stokes stage
+// equations, block (s, t) = delta_st M + dt a_st [N_s B; B^T 0], with N_s = K + N'(U_s)
+// as dim x dim blocks on the scalar pattern: nw[(p r + s) dim^2 + c dim + e] (FP64).
+hipError_t residual_newton(const DevLevel& L, const double* nw, const double* A, double dt, const double* F,
+                           const double* x, double* y, hipStream_t s);
 // Complex eigenvalue pair block b (a + ib): invert C = M_v + dt (a - ib) S_v per patch in
 // LDS and write (Re, Im) of C^{-1} into the factored layout; zr = dt a, zi = -dt b.
 // hipErrorInvalidConfiguration when the n_s x n_s complex matrix does not fit in LDS.

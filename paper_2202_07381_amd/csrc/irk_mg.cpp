@@ -148,6 +148,36 @@ void prof_end(Handle* h, int idx, hipStream_t s) {
 }
 
 // ----------------------------------------------------------------------- V-cycle
+// Level operators of the cycle: the handle's stage operator, or, while the Newton
+// Jacobian preconditioner is active (FP64 only, forward only), the per-stage Newton
+// Jacobian of the level and its dense patch inverses.
+template <typename T>
+hipError_t lev_residual(Handle* h, int l, const DevOps<T>& o, const double* A, const T* b, const T* x, T* y,
+                        hipStream_t s) {
+  if constexpr (std::is_same<T, double>::value) {
+    if (h->nw_active) return k::residual_newton(h->dev[l], h->nw_vals[l], h->A, h->dt, b, x, y, s);
+  }
+  return k::residual<T>(h->dev[l], o, A, h->dt, b, x, y, s);
+}
+
+// the level with the Newton Jacobian's dense patch inverses in place of its own factors
+DevLevel newton_view(const Handle* h, int l) {
+  DevLevel V = h->dev[l];
+  V.pform = 0;
+  V.inv = h->nw_inv[l];
+  V.p_ld = h->nw_ld[l];
+  V.p_inv_off = h->nw_off[l];
+  return V;
+}
+
+template <typename T>
+hipError_t lev_patch(Handle* h, int l, const DevOps<T>& o, const T* r, T* Y, int tr, hipStream_t s) {
+  if constexpr (std::is_same<T, double>::value) {
+    if (h->nw_active) return k::patch_apply<double>(newton_view(h, l), o, r, Y, tr, s);
+  }
+  return k::patch_apply<T>(h->dev[l], o, r, Y, tr, s);
+}
+
 template <typename T>
 irk_status smooth(Handle* h, int l, int nsweeps, bool zero_start, bool tr, hipStream_t s) {
   DevLevel& L = h->dev[l];
@@ -181,12 +211,12 @@ irk_status smooth(Handle* h, int l, int nsweeps, bool zero_start, bool tr, hipSt
     const T* r = b;
     if (!zero_start) {
       const int p0 = prof_begin(h, 1, l, s);
-      HIPCHK(k::residual<T>(L, ot, A, h->dt, b, x, res, s));
+      HIPCHK(lev_residual<T>(h, l, ot, A, b, x, res, s));
       prof_end(h, p0, s);
       r = res;
     }
     int p1 = prof_begin(h, 0, l, s);
-    HIPCHK(k::patch_apply<T>(L, o, r, Y, tr ? 1 : 0, s));
+    HIPCHK(lev_patch<T>(h, l, o, r, Y, tr ? 1 : 0, s));
     prof_end(h, p1, s);
     int p2 = prof_begin(h, 2, l, s);
     HIPCHK(k::gather_update<T>(L, o, Y, V, (T)1, mode, s));
@@ -198,10 +228,10 @@ irk_status smooth(Handle* h, int l, int nsweeps, bool zero_start, bool tr, hipSt
       T* Vj = V + (int64_t)j * N;
       T* Vn = V + (int64_t)(j + 1) * N;
       const int p3 = prof_begin(h, 1, l, s);
-      HIPCHK(k::residual<T>(L, ot, A, h->dt, nullptr, Vj, res, s));
+      HIPCHK(lev_residual<T>(h, l, ot, A, nullptr, Vj, res, s));
       prof_end(h, p3, s);
       p1 = prof_begin(h, 0, l, s);
-      HIPCHK(k::patch_apply<T>(L, o, res, Y, tr ? 1 : 0, s));
+      HIPCHK(lev_patch<T>(h, l, o, res, Y, tr ? 1 : 0, s));
       prof_end(h, p1, s);
       p2 = prof_begin(h, 2, l, s);
       HIPCHK(k::gather_update<T>(L, o, Y, Vn, (T)1, mode, s));
@@ -227,12 +257,12 @@ irk_status smooth(Handle* h, int l, int nsweeps, bool zero_start, bool tr, hipSt
       const T* r = b;
       if (!xzero) {
         const int p0 = prof_begin(h, 1, l, s);
-        HIPCHK(k::residual<T>(L, ot, A, h->dt, b, x, res, s));
+        HIPCHK(lev_residual<T>(h, l, ot, A, b, x, res, s));
         prof_end(h, p0, s);
         r = res;
       }
       const int p1 = prof_begin(h, 0, l, s);
-      HIPCHK(k::patch_apply<T>(L, o, r, Y, tr ? 1 : 0, s));
+      HIPCHK(lev_patch<T>(h, l, o, r, Y, tr ? 1 : 0, s));
       prof_end(h, p1, s);
       double c1 = 0.0, c2;
       if (it == 0) {
@@ -255,12 +285,12 @@ irk_status smooth(Handle* h, int l, int nsweeps, bool zero_start, bool tr, hipSt
     const T* r = b;
     if (!first) {
       const int p0 = prof_begin(h, 1, l, s);
-      HIPCHK(k::residual<T>(L, ot, A, h->dt, b, x, res, s));
+      HIPCHK(lev_residual<T>(h, l, ot, A, b, x, res, s));
       prof_end(h, p0, s);
       r = res;
     }
     const int p1 = prof_begin(h, 0, l, s);
-    HIPCHK(k::patch_apply<T>(L, o, r, Y, tr ? 1 : 0, s));
+    HIPCHK(lev_patch<T>(h, l, o, r, Y, tr ? 1 : 0, s));
     prof_end(h, p1, s);
     const int mode = (tr ? 2 : 0) + (first ? 0 : 1);
     const int p2 = prof_begin(h, 2, l, s);
@@ -283,7 +313,7 @@ irk_status descend_T(Handle* h, int l, bool tr, hipStream_t s) {
   }
   CHK(smooth<T>(h, l, tr ? h->post : h->pre, true, tr, s));
   const int p0 = prof_begin(h, 1, l, s);
-  HIPCHK(k::residual<T>(L, o, tr ? h->At : h->A, h->dt, (const T*)L.b, (const T*)L.x, (T*)L.res, s));
+  HIPCHK(lev_residual<T>(h, l, o, tr ? h->At : h->A, (const T*)L.b, (const T*)L.x, (T*)L.res, s));
   prof_end(h, p0, s);
   HIPCHK(k::restrict_<T>(L, h->dev[l - 1], ops_of<T>(L), (const T*)L.res, (T*)h->dev[l - 1].b, s));
   return IRK_OK;
@@ -293,8 +323,11 @@ template <typename T>
 irk_status coarse_T(Handle* h, bool tr, hipStream_t s, const int64_t* pins) {
   DevLevel& L = h->dev[0];
   HIPCHK((k::cast<T, double>((const T*)L.b, h->cb, L.N, s)));
-  HIPCHK(k::coarse_solve(tr ? h->coarse_invT : h->coarse_inv, tr ? h->coarse_matT : h->coarse_mat, L.N, h->cb,
-                         h->cx, pins, h->r, h->cpart, s));
+  if (h->nw_active)
+    HIPCHK(k::coarse_solve(h->nw_cinv, h->nw_cmat, L.N, h->cb, h->cx, pins, h->r, h->cpart, s));
+  else
+    HIPCHK(k::coarse_solve(tr ? h->coarse_invT : h->coarse_inv, tr ? h->coarse_matT : h->coarse_mat, L.N, h->cb,
+                           h->cx, pins, h->r, h->cpart, s));
   HIPCHK((k::cast<double, T>(h->cx, (T*)L.x, L.N, s)));
   return IRK_OK;
 }
@@ -318,6 +351,7 @@ irk_status subcycle_T(Handle* h, int lt, bool tr, hipStream_t s, const int64_t* 
 
 template <typename T>
 irk_status vcycle_T(Handle* h, bool tr, hipStream_t s, const int64_t* pins) {
+  if (h->nw_active && tr) return fail(IRK_EINVAL, "the Newton Jacobian V-cycle has no transpose");
   return subcycle_T<T>(h, h->nlevels - 1, tr, s, pins);
 }
 
@@ -385,6 +419,108 @@ irk_status ns_stage_values(irk_mg* h, const double* state, const double* k_int, 
   k::NsCoef c;
   for (int i = 0; i < h->r * h->r; ++i) c.a[i] = h->dt * h->A[i];
   HIPCHK(k::ns_stage_values(H.nn, h->dim, h->r, H.nfree, h->ns_free, state, k_int, c, g_st, h->ns_U, s));
+  return IRK_OK;
+}
+
+// Operators of the Newton Jacobian V-cycle (Sec. 3.2) at the stage velocities in ns_U
+// (finest level): the stage velocities carried to every coarser level by injection (its
+// P2 nodes are nodes of the next finer level), the per-stage velocity blocks
+// K + N'(U_i) assembled on the host for every level, the stage-coupled patch matrices
+// factorised on the GPU in the dense form, and the coarse operator inverted on the
+// GPU.  Allocates on first use; FP64 handles only.
+irk_status nw_build(irk_mg* h, hipStream_t s) {
+  if (h->precision != 0) return fail(IRK_EINVAL, "the Newton Jacobian V-cycle needs an FP64 handle");
+  const int nl = h->nlevels, top = nl - 1, d = h->dim, r = h->r, dd = d * d;
+  constexpr int VEC = 2;  // dense inverse columns padded to 16-byte words
+  if (!h->nw_ready) {
+    h->nw_vals.assign(nl, nullptr);
+    h->nw_inv.assign(nl, nullptr);
+    h->nw_ld.assign(nl, nullptr);
+    h->nw_off.assign(nl, nullptr);
+    for (int l = 0; l < nl; ++l) {
+      const HostLevel& H = h->host[l];
+      CHK(dalloc(h, &h->nw_vals[l], H.s_col.size() * r * dd));
+      if (l == 0) continue;
+      const DevLevel& D = h->dev[l];
+      std::vector<int32_t> ld(D.npatch);
+      std::vector<int64_t> off(D.npatch);
+      int64_t io = 0;
+      for (int64_t p = 0; p < D.npatch; ++p) {
+        const int n = r * (d * (H.pn_ptr[p + 1] - H.pn_ptr[p]) + 1);
+        ld[p] = (n + VEC - 1) / VEC * VEC;
+        off[p] = io;
+        io += (int64_t)ld[p] * n;
+      }
+      CHK(upload(h, &h->nw_ld[l], ld, s));
+      CHK(upload(h, &h->nw_off[l], off, s));
+      CHK(dalloc(h, &h->nw_inv[l], (size_t)io));
+    }
+    const int64_t N0 = h->dev[0].N;
+    CHK(dalloc(h, &h->nw_cinv, (size_t)N0 * N0));
+    CHK(dalloc(h, &h->nw_cmat, (size_t)N0 * N0));
+    CHK(dalloc(h, &h->nw_ctmp, (size_t)N0 * N0));
+    CHK(dalloc(h, &h->nw_colk, (size_t)N0));
+    CHK(dalloc(h, &h->nw_swp, (size_t)N0));
+    h->nw_ready = true;
+  }
+  // stage velocities per level and stage, nodal: U[l][(i nn + node) d + c]
+  std::vector<std::vector<double>> U(nl);
+  {
+    const HostLevel& F = h->host[top];
+    std::vector<double> Uf((size_t)F.nn * d * r);
+    HIPCHK(hipMemcpyAsync(Uf.data(), h->ns_U, Uf.size() * sizeof(double), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    U[top].resize(Uf.size());
+    for (int64_t n = 0; n < F.nn; ++n)
+      for (int c = 0; c < d; ++c)
+        for (int i = 0; i < r; ++i) U[top][((size_t)i * F.nn + n) * d + c] = Uf[((size_t)n * d + c) * r + i];
+  }
+  for (int l = top - 1; l >= 0; --l) {
+    const HostLevel& C = h->host[l];
+    const HostLevel& F = h->host[l + 1];
+    U[l].resize((size_t)C.nn * d * r);
+    for (int i = 0; i < r; ++i)
+      for (int64_t n = 0; n < C.nn; ++n)
+        for (int c = 0; c < d; ++c)
+          U[l][((size_t)i * C.nn + n) * d + c] =
+              U[l + 1][((size_t)i * F.nn + F.coarse_node_to_fine_vertex[n]) * d + c];
+  }
+  HIPCHK(hipMemsetAsync(h->flag, 0, sizeof(int), s));
+  std::vector<double> Jc;
+  double scale = 0;
+  for (int l = 0; l < nl; ++l) {
+    const HostLevel& H = h->host[l];
+    const size_t nnz = H.s_col.size();
+    std::vector<double> vals(nnz * r * dd), blk(nnz * dd);
+    for (int i = 0; i < r; ++i) {
+      std::fill(blk.begin(), blk.end(), 0.0);
+      irk::assemble_newton_block(H, h->nu, &U[l][(size_t)i * H.nn * d], blk.data());
+      for (size_t p = 0; p < nnz; ++p)
+        for (int q = 0; q < dd; ++q) vals[(p * r + i) * dd + q] = blk[p * dd + q];
+    }
+    HIPCHK(hipMemcpyAsync(h->nw_vals[l], vals.data(), vals.size() * sizeof(double), hipMemcpyHostToDevice, s));
+    if (l == 0) irk::coarse_matrix_newton(H, r, h->A, h->dt, vals.data(), Jc, &scale);
+    HIPCHK(hipStreamSynchronize(s));  // vals is released at the end of the iteration
+    if (l >= 1) {
+      DevLevel V = newton_view(h, l);
+      if (V.max_nloc > 1024)
+        return fail(IRK_EINVAL, "patch of " + std::to_string(V.max_nloc) + " unknowns exceeds the limit of 1024");
+      HIPCHK(k::patch_factor_range<double>(V, V.d64, r, h->A, h->dt, V.p_ld, V.p_inv_off,
+                                           reinterpret_cast<double*>(V.inv), 0, V.npatch, 0, V.max_nloc, h->flag, s,
+                                           h->nw_vals[l]));
+    }
+  }
+  // coarse: the column-major operator (transpose of the row-major one) and its inverse
+  // (Gauss--Jordan in place on the row-major operator, then transposed)
+  const int64_t N0 = h->dev[0].N;
+  HIPCHK(hipMemcpyAsync(h->nw_ctmp, Jc.data(), Jc.size() * sizeof(double), hipMemcpyHostToDevice, s));
+  HIPCHK(k::transpose(h->nw_ctmp, h->nw_cmat, N0, s));
+  HIPCHK(k::dense_inverse(h->nw_ctmp, N0, std::max(1e-300, 1e-14 * scale), h->nw_colk, h->nw_swp, h->flag, s));
+  HIPCHK(k::transpose(h->nw_ctmp, h->nw_cinv, N0, s));
+  int fl = 0;
+  HIPCHK(hipMemcpyAsync(&fl, h->flag, sizeof(int), hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  if (fl) return fail(IRK_ESINGULAR, "zero pivot in a patch or the coarse operator of the Newton Jacobian");
   return IRK_OK;
 }
 
@@ -1559,6 +1695,28 @@ void irk_newton_default_opts(irk_newton_opts* o) {
   o->linesearch = 0;
   o->ls_maxit = 12;
   o->ls_alpha = 1e-4;
+  o->precond = 0;
+}
+
+irk_status irk_ns_newton_preconditioner(irk_mg* h, const double* state, const double* g_stages, const double* k,
+                                        int enable, void* stream) {
+  CHK(check_handle(h));
+  if (enable != 0 && enable != 1) return fail(IRK_EINVAL, "enable must be 0 or 1");
+  if (!enable) {
+    h->nw_active = false;
+    return IRK_OK;
+  }
+  if (!state || !k) return fail(IRK_EINVAL, "null vector");
+  if (h->precision != 0) return fail(IRK_EINVAL, "the Newton Jacobian V-cycle needs an FP64 handle");
+  hipStream_t s = S(stream);
+  CHK(ns_init(h, s));
+  DevLevel& L = h->dev[h->nlevels - 1];
+  HIPCHK(k::to_internal<double>(L, k, h->ns_kt, s));
+  CHK(ns_stage_values(h, state, h->ns_kt, g_stages, s));
+  h->nw_active = false;
+  CHK(nw_build(h, s));
+  h->nw_active = true;
+  return IRK_OK;
 }
 
 // R = F - J k - c(U - w, U): minus the residual of the stage equations of Sec. 3.2 (F
@@ -1619,8 +1777,10 @@ irk_status irk_ns_newton_solve(irk_mg* h, const double* F, const double* state, 
       o.restart > 1000 || !(o.eta0 > 0 && o.eta0 < 1) || !(o.eta_max > 0 && o.eta_max < 1) ||
       !(o.ew_gamma > 0 && o.ew_gamma <= 1) || !(o.ew_alpha > 1 && o.ew_alpha <= 2) || !(o.ew_threshold >= 0) ||
       !(o.eta_fixed >= 0 && o.eta_fixed < 1) || o.linesearch < 0 || o.linesearch > 1 || o.ls_maxit < 0 ||
-      o.ls_maxit > 60 || !(o.ls_alpha > 0 && o.ls_alpha < 1))
+      o.ls_maxit > 60 || !(o.ls_alpha > 0 && o.ls_alpha < 1) || o.precond < 0 || o.precond > 1)
     return fail(IRK_EINVAL, "invalid Newton options");
+  if (o.precond == 1 && h->precision != 0)
+    return fail(IRK_EINVAL, "the Newton Jacobian V-cycle (precond 1) needs an FP64 handle");
   const auto t0 = std::chrono::steady_clock::now();
   hipStream_t s = S(stream);
   CHK(ns_init(h, s));
@@ -1675,10 +1835,14 @@ irk_status irk_ns_newton_solve(irk_mg* h, const double* F, const double* state, 
     HIPCHK(hipMemcpyAsync(h->kF, h->ns_G, (size_t)N * sizeof(double), hipMemcpyDeviceToDevice, s));
     HIPCHK(k::fill(h->kx, N, 0.0, s));
     irk_solve_info li{};
+    if (o.precond == 1) CHK(nw_build(h, s));  // ns_U holds the stage values at the iterate
     HIPCHK(hipEventRecord(h->ev0, s));
+    const bool nw_prev = h->nw_active;
+    h->nw_active = o.precond == 1 || nw_prev;
     h->ns_jac = true;
     st = fgmres_int(h, nullptr, eta, o.linear_maxit, o.restart, &li, false, s);
     h->ns_jac = false;
+    h->nw_active = nw_prev;
     if (st < 0) return st;
     lin += li.iterations;
     ms_lin += (float)li.ms_total;
@@ -1827,7 +1991,8 @@ irk_status irk_level_apply(irk_mg* h, int level, int transpose, const double* x,
     o.s_L = o.s_Lt;
     o.u_L = o.u_Lt;
   }
-  HIPCHK(k::residual<double>(L, o, transpose ? h->At : h->A, h->dt, nullptr, tmp_in, tmp_out, s));
+  if (h->nw_active && transpose) return fail(IRK_EINVAL, "the Newton Jacobian level operators have no transpose");
+  HIPCHK(lev_residual<double>(h, level, o, transpose ? h->At : h->A, nullptr, tmp_in, tmp_out, s));
   HIPCHK(k::to_abi<double>(L, tmp_out, y, s));
   return IRK_OK;
 }
@@ -1837,6 +2002,7 @@ irk_status irk_level_sweep(irk_mg* h, int level, int transpose, const double* F,
   CHK(check_level(h, level));
   if (level < 1) return fail(IRK_EINVAL, "the coarsest level has no patches");
   if (!F || !kv) return fail(IRK_EINVAL, "null vector");
+  if (h->nw_active && transpose) return fail(IRK_EINVAL, "the Newton Jacobian relaxation has no transpose");
   if (h->precision == 0) return level_sweep_T<double>(h, level, transpose, F, kv, S(stream));
   return level_sweep_T<float>(h, level, transpose, F, kv, S(stream));
 }
@@ -1874,8 +2040,13 @@ irk_status irk_coarse_solve(irk_mg* h, int transpose, const double* b, double* x
   DevLevel& L = h->dev[0];
   hipStream_t s = S(stream);
   HIPCHK(k::to_internal<double>(L, b, h->cb, s));
-  HIPCHK(k::coarse_solve(transpose ? h->coarse_invT : h->coarse_inv, transpose ? h->coarse_matT : h->coarse_mat,
-                         L.N, h->cb, h->cx, h->pins, h->r, h->cpart, s));
+  if (h->nw_active) {
+    if (transpose) return fail(IRK_EINVAL, "the Newton Jacobian coarse solve has no transpose");
+    HIPCHK(k::coarse_solve(h->nw_cinv, h->nw_cmat, L.N, h->cb, h->cx, h->pins, h->r, h->cpart, s));
+  } else {
+    HIPCHK(k::coarse_solve(transpose ? h->coarse_invT : h->coarse_inv, transpose ? h->coarse_matT : h->coarse_mat,
+                           L.N, h->cb, h->cx, h->pins, h->r, h->cpart, s));
+  }
   HIPCHK(k::to_abi<double>(L, h->cx, x, s));
   return IRK_OK;
 }

@@ -253,15 +253,109 @@ __global__ __launch_bounds__(256) void k_residual_sell(
   }
 }
 
+// r = F - J x (F null: r = J x) for the Newton Jacobian of the Navier--Stokes stage
+// equations (Sec. 3.2): block (s, t) = delta_st M + dt a_st [N_s B; B^T 0] with the
+// per-stage velocity operator N_s = K + N'(U_s) kept as dim x dim blocks on the scalar
+// pattern, nw[(p R + s) D^2 + c D + e].  N_s depends on the row's stage, so each
+// gathered column is first mixed into its stage combinations z_s = sum_t dt a_st x_t and
+// N_s applied to z_s; the B part is stage-independent and mixed once per row.  One
+// thread per row (velocity rows node-major, then vertex rows).
+template <int D, int R>
+__global__ __launch_bounds__(kBlock) void k_residual_newton(
+    int64_t nfree, int64_t nv, int64_t offV, const int32_t* __restrict__ s_ptr, const int32_t* __restrict__ s_col,
+    const double* __restrict__ sM, const double* __restrict__ nw, const int32_t* __restrict__ b_ptr,
+    const int32_t* __restrict__ b_col, const double* __restrict__ b_val, const int32_t* __restrict__ bt_ptr,
+    const int32_t* __restrict__ bt_col, const double* __restrict__ bt_val, Coef<double> dtA,
+    const double* __restrict__ F, const double* __restrict__ x, double* __restrict__ y) {
+  constexpr int DR = D * R;
+  const int64_t row = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (row < nfree) {
+    double acc[DR], ab[DR];
+#pragma unroll
+    for (int q = 0; q < DR; ++q) acc[q] = ab[q] = 0.0;
+    for (int32_t p = s_ptr[row]; p < s_ptr[row + 1]; ++p) {
+      const int64_t j = s_col[p];
+      double xv[DR], z[DR];
+#pragma unroll
+      for (int q = 0; q < DR; ++q) xv[q] = x[j * DR + q];
+      const double m = sM[p];
+#pragma unroll
+      for (int e = 0; e < D; ++e)
+#pragma unroll
+        for (int st = 0; st < R; ++st) {
+          double v = 0.0;
+#pragma unroll
+          for (int t = 0; t < R; ++t) v += dtA.v[st * R + t] * xv[e * R + t];
+          z[e * R + st] = v;
+        }
+      const double* nwp = nw + (int64_t)p * R * D * D;
+#pragma unroll
+      for (int st = 0; st < R; ++st)
+#pragma unroll
+        for (int c = 0; c < D; ++c) {
+          double v = m * xv[c * R + st];
+#pragma unroll
+          for (int e = 0; e < D; ++e) v += nwp[(st * D + c) * D + e] * z[e * R + st];
+          acc[c * R + st] += v;
+        }
+    }
+    for (int32_t q = b_ptr[row]; q < b_ptr[row + 1]; ++q) {
+      const int64_t v = b_col[q];
+#pragma unroll
+      for (int c = 0; c < D; ++c) {
+        const double bv = b_val[(int64_t)q * D + c];
+#pragma unroll
+        for (int t = 0; t < R; ++t) ab[c * R + t] += bv * x[offV + v * R + t];
+      }
+    }
+#pragma unroll
+    for (int c = 0; c < D; ++c)
+#pragma unroll
+      for (int st = 0; st < R; ++st) {
+        double v = acc[c * R + st];
+#pragma unroll
+        for (int t = 0; t < R; ++t) v += dtA.v[st * R + t] * ab[c * R + t];
+        const int64_t o = row * DR + c * R + st;
+        y[o] = F ? F[o] - v : v;
+      }
+  } else if (row < nfree + nv) {
+    const int64_t vx = row - nfree;
+    double a[R];
+#pragma unroll
+    for (int t = 0; t < R; ++t) a[t] = 0.0;
+    for (int32_t q = bt_ptr[vx]; q < bt_ptr[vx + 1]; ++q) {
+      const int64_t j = bt_col[q];
+#pragma unroll
+      for (int c = 0; c < D; ++c) {
+        const double bv = bt_val[(int64_t)q * D + c];
+#pragma unroll
+        for (int t = 0; t < R; ++t) a[t] += bv * x[j * DR + c * R + t];
+      }
+    }
+#pragma unroll
+    for (int st = 0; st < R; ++st) {
+      double v = 0.0;
+#pragma unroll
+      for (int t = 0; t < R; ++t) v += dtA.v[st * R + t] * a[t];
+      const int64_t o = offV + vx * R + st;
+      y[o] = F ? F[o] - v : v;
+    }
+  }
+}
+
 // ------------------------------------------------------------------ patch factorise
-// One workgroup per patch, matrix in dynamic LDS (row-major n x n).
+// One workgroup per patch, matrix in dynamic LDS (row-major n x n).  With nw (the
+// Newton Jacobian's per-stage dim x dim blocks, as for k_residual_newton) the
+// velocity-velocity entries are delta_st delta_ce M_ab + dt a_st N_s[ab]_ce instead of
+// the Kronecker delta_st M_ab + dt a_st L_ab on each component.
 template <int D, int R, typename T>
 __global__ __launch_bounds__(kBlock) void k_patch_factor(
     int64_t npatch, const int32_t* __restrict__ pn_ptr, const int32_t* __restrict__ pvv_ptr,
     const int32_t* __restrict__ pvv, const int32_t* __restrict__ pvp,
     const int32_t* __restrict__ p_ld, const int64_t* __restrict__ p_inv_off,
     const T* __restrict__ sM, const T* __restrict__ sL, const T* __restrict__ b_val,
-    Coef<T> dtA, T* __restrict__ inv, int* __restrict__ fail, int64_t p0, int64_t off0) {
+    Coef<T> dtA, T* __restrict__ inv, int* __restrict__ fail, int64_t p0, int64_t off0,
+    const T* __restrict__ nw) {
   extern __shared__ unsigned char smem_raw[];
   const int64_t p = p0 + blockIdx.x;
   if (p >= npatch) return;
@@ -280,7 +374,18 @@ __global__ __launch_bounds__(kBlock) void k_patch_factor(
   const int32_t v0 = pvv_ptr[p], v1 = pvv_ptr[p + 1];
   for (int32_t e = v0 + tid; e < v1; e += blockDim.x) {
     const int la = pvv[3 * e], lb = pvv[3 * e + 1], pos = pvv[3 * e + 2];
-    const T m = sM[pos], l = sL[pos];
+    const T m = sM[pos];
+    if (nw) {
+      const T* nwp = nw + (int64_t)pos * R * D * D;
+      for (int c = 0; c < D; ++c)
+        for (int ce = 0; ce < D; ++ce)
+          for (int s = 0; s < R; ++s)
+            for (int t = 0; t < R; ++t)
+              Am[(s * sb + c * nn + la) * n + (t * sb + ce * nn + lb)] =
+                  (s == t && c == ce ? m : T(0)) + dtA.v[s * R + t] * nwp[(s * D + c) * D + ce];
+      continue;
+    }
+    const T l = sL[pos];
     for (int c = 0; c < D; ++c)
       for (int s = 0; s < R; ++s)
         for (int t = 0; t < R; ++t)
@@ -390,7 +495,8 @@ __global__ __launch_bounds__(kBlock) void k_patch_factor_global(
     const int32_t* __restrict__ pvv, const int32_t* __restrict__ pvp,
     const int32_t* __restrict__ p_ld, const int64_t* __restrict__ p_inv_off,
     const T* __restrict__ sM, const T* __restrict__ sL, const T* __restrict__ b_val,
-    Coef<T> dtA, T* __restrict__ inv, int* __restrict__ fail, int64_t p0, int64_t off0) {
+    Coef<T> dtA, T* __restrict__ inv, int* __restrict__ fail, int64_t p0, int64_t off0,
+    const T* __restrict__ nw) {
   extern __shared__ unsigned char smem_raw[];
   const int64_t p = p0 + blockIdx.x;
   if (p >= npatch) return;
@@ -411,7 +517,18 @@ __global__ __launch_bounds__(kBlock) void k_patch_factor_global(
   const int32_t v0 = pvv_ptr[p], v1 = pvv_ptr[p + 1];
   for (int32_t e = v0 + tid; e < v1; e += blockDim.x) {
     const int la = pvv[3 * e], lb = pvv[3 * e + 1], pos = pvv[3 * e + 2];
-    const T m = sM[pos], l = sL[pos];
+    const T m = sM[pos];
+    if (nw) {
+      const T* nwp = nw + (int64_t)pos * R * D * D;
+      for (int c = 0; c < D; ++c)
+        for (int ce = 0; ce < D; ++ce)
+          for (int s = 0; s < R; ++s)
+            for (int t = 0; t < R; ++t)
+              Am[(int64_t)(t * sb + ce * nn + lb) * ld + (s * sb + c * nn + la)] =
+                  (s == t && c == ce ? m : T(0)) + dtA.v[s * R + t] * nwp[(s * D + c) * D + ce];
+      continue;
+    }
+    const T l = sL[pos];
     for (int c = 0; c < D; ++c)
       for (int s = 0; s < R; ++s)
         for (int t = 0; t < R; ++t)
@@ -1611,10 +1728,20 @@ hipError_t residual(const DevLevel& L, const DevOps<T>& ops, const double* A, do
   return hipGetLastError();
 }
 
+hipError_t residual_newton(const DevLevel& L, const double* nw, const double* A, double dt, const double* F,
+                           const double* x, double* y, hipStream_t s) {
+  const unsigned g = blocks_for(L.nfree + L.nv);
+  IRK_DISPATCH_DR(L.dim, L.r, (k_residual_newton<DD, RR><<<dim3(g), dim3(kBlock), 0, s>>>(
+                                  L.nfree, L.nv, L.offV, L.s_ptr, L.s_col, L.d64.s_M, nw, L.b_ptr, L.b_col,
+                                  L.d64.b_val, L.bt_ptr, L.bt_col, L.d64.bt_val, scaled<double, RR>(A, dt), F, x,
+                                  y)));
+  return hipGetLastError();
+}
+
 template <typename T>
 hipError_t patch_factor_range(const DevLevel& L, const DevOps<T>& ops, int R, const double* coef, double dt,
                               const int32_t* ld, const int64_t* off, T* out, int64_t p0, int64_t p1,
-                              int64_t off0, int nmax, int* d_fail, hipStream_t s) {
+                              int64_t off0, int nmax, int* d_fail, hipStream_t s, const T* nw) {
   if (p1 <= p0) return hipSuccess;
   const unsigned g = (unsigned)(p1 - p0);
   const size_t n = (size_t)nmax;
@@ -1628,7 +1755,7 @@ hipError_t patch_factor_range(const DevLevel& L, const DevOps<T>& ops, int R, co
       hipError_t e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)glds);
       if (e != hipSuccess) return e;
       kern<<<dim3(g), dim3(kBlock), glds, s>>>(p1, L.pn_ptr, L.pvv_ptr, L.pvv, L.pvp, ld, off, ops.s_M, ops.s_L,
-                                               ops.b_val, scaled<T, RR>(coef, dt), out, d_fail, p0, off0);
+                                               ops.b_val, scaled<T, RR>(coef, dt), out, d_fail, p0, off0, nw);
     });
     return hipGetLastError();
   }
@@ -1637,7 +1764,7 @@ hipError_t patch_factor_range(const DevLevel& L, const DevOps<T>& ops, int R, co
     hipError_t e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
     kern<<<dim3(g), dim3(kBlock), lds, s>>>(p1, L.pn_ptr, L.pvv_ptr, L.pvv, L.pvp, ld, off, ops.s_M, ops.s_L,
-                                            ops.b_val, scaled<T, RR>(coef, dt), out, d_fail, p0, off0);
+                                            ops.b_val, scaled<T, RR>(coef, dt), out, d_fail, p0, off0, nw);
   });
   return hipGetLastError();
 }
@@ -2051,7 +2178,7 @@ hipError_t mass_apply(const DevLevel& L, const double* st, double* out, hipStrea
                                   const T*, const T*, T*, hipStream_t);                         \
   template hipError_t patch_factor_range<T>(const DevLevel&, const DevOps<T>&, int, const double*, \
                                             double, const int32_t*, const int64_t*, T*, int64_t,   \
-                                            int64_t, int64_t, int, int*, hipStream_t);             \
+                                            int64_t, int64_t, int, int*, hipStream_t, const T*);   \
   template hipError_t patch_factor_cplx<T>(const DevLevel&, const DevOps<T>&, double, double, int, int, \
                                            int*, hipStream_t);                                        \
   template hipError_t eig_extract<T>(const DevLevel&, const StageBasis<T>&, int, const int32_t*,  \

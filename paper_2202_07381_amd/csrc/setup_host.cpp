@@ -622,6 +622,110 @@ std::string build_transfer(const HostLevel& C, HostLevel& F, const int64_t* pare
 }
 
 // ---------------------------------------------------------------- coarse inverse
+// The per-stage velocity operator of the Newton Jacobian (Sec. 3.2) on the scalar pattern
+// of level L for one stage velocity U (nodal, nn x d, node-major): out[p d^2 + c d + e]
+// (added to, out zeroed by the caller) = (nu K + C(U))[p] delta_ce + R(U)[p][c][e], with
+//   C(U)_ab = int phi_a (U . grad phi_b),   R(U)_(a,c),(b,e) = int phi_a phi_b d_e U_c,
+// the two halves of the derivative of the trilinear form c(z, U) + c(U, z).  Exact
+// integration with the reference tensor int phi_e phi_a d_lam_k phi_b / |cell| (U is
+// quadratic on each cell, so every integrand is a polynomial of degree 5).
+void assemble_newton_block(const HostLevel& L, double nu, const double* U, double* out) {
+  const int d = L.dim, nb = d + 1, nl = nloc_of(d), dd = d * d;
+  const RefTensors& R = ref_tensors(d);
+  double glam[12], vol;
+  double wg[10][4], Ce[10][10], T[10][10][10][3], Re[10][10][3][3];
+  for (int64_t c = 0; c < L.nc; ++c) {
+    cell_geometry(L, c, glam, &vol);
+    const int64_t* cn = &L.cell_nodes[c * nl];
+    for (int f = 0; f < nl; ++f)
+      for (int k = 0; k < nb; ++k) {
+        double s = 0;
+        for (int i = 0; i < d; ++i) s += U[cn[f] * d + i] * glam[k * d + i];
+        wg[f][k] = s;
+      }
+    for (int a = 0; a < nl; ++a)
+      for (int b = 0; b < nl; ++b) {
+        double s = 0;
+        for (int f = 0; f < nl; ++f)
+          for (int k = 0; k < nb; ++k) s += wg[f][k] * R.C[((f * nl + a) * nl + b) * nb + k];
+        Ce[a][b] = vol * s;
+        for (int f = 0; f < nl; ++f)
+          for (int e = 0; e < d; ++e) {
+            double t = 0;
+            for (int k = 0; k < nb; ++k) t += glam[k * d + e] * R.C[((a * nl + b) * nl + f) * nb + k];
+            T[a][b][f][e] = t;
+          }
+        for (int cc = 0; cc < d; ++cc)
+          for (int e = 0; e < d; ++e) {
+            double t = 0;
+            for (int f = 0; f < nl; ++f) t += U[cn[f] * d + cc] * T[a][b][f][e];
+            Re[a][b][cc][e] = vol * t;
+          }
+      }
+    for (int a = 0; a < nl; ++a) {
+      const int64_t ia = L.free_of_node[cn[a]];
+      if (ia < 0) continue;
+      for (int b = 0; b < nl; ++b) {
+        const int64_t ib = L.free_of_node[cn[b]];
+        if (ib < 0) continue;
+        const int32_t p = find_in_row(L.s_ptr, L.s_col, ia, ib);
+        double* o = out + (size_t)p * dd;
+        for (int cc = 0; cc < d; ++cc) {
+          o[cc * d + cc] += Ce[a][b];
+          for (int e = 0; e < d; ++e) o[cc * d + e] += Re[a][b][cc][e];
+        }
+      }
+    }
+  }
+  for (size_t p = 0; p < L.s_col.size(); ++p)
+    for (int cc = 0; cc < d; ++cc) out[p * dd + cc * d + cc] += nu * L.s_K1[p];
+}
+
+// Dense coarse operator of the Newton Jacobian (row-major, internal layout, pressure of
+// vertex 0 pinned in every stage): block (s, t) = delta_st M + dt a_st [N_s B; B^T 0] with
+// N_s from nw[(p r + s) d^2 + c d + e].
+void coarse_matrix_newton(const HostLevel& L, int r, const double* A, double dt, const double* nw,
+                          std::vector<double>& J, double* max_abs) {
+  const int d = L.dim, dd = d * d;
+  const int64_t offV = L.nfree * d * r;
+  const int64_t N = offV + L.nv * r;
+  J.assign((size_t)N * N, 0.0);
+  auto vel = [&](int64_t i, int c, int s) { return (i * d + c) * r + s; };
+  auto pre = [&](int64_t v, int s) { return offV + v * r + s; };
+  for (int64_t i = 0; i < L.nfree; ++i) {
+    for (int32_t p = L.s_ptr[i]; p < L.s_ptr[i + 1]; ++p) {
+      const int64_t j = L.s_col[p];
+      for (int s = 0; s < r; ++s)
+        for (int t = 0; t < r; ++t)
+          for (int c = 0; c < d; ++c)
+            for (int e = 0; e < d; ++e)
+              J[vel(i, c, s) * N + vel(j, e, t)] += (s == t && c == e ? L.s_M[p] : 0.0) +
+                                                    dt * A[s * r + t] * nw[((size_t)p * r + s) * dd + c * d + e];
+    }
+    for (int32_t p = L.b_ptr[i]; p < L.b_ptr[i + 1]; ++p) {
+      const int64_t v = L.b_col[p];
+      for (int c = 0; c < d; ++c)
+        for (int s = 0; s < r; ++s)
+          for (int t = 0; t < r; ++t) {
+            const double val = dt * A[s * r + t] * L.b_val[(size_t)p * d + c];
+            J[vel(i, c, s) * N + pre(v, t)] += val;
+            J[pre(v, s) * N + vel(i, c, t)] += val;
+          }
+    }
+  }
+  for (int s = 0; s < r; ++s) {
+    const int64_t q = pre(0, s);
+    for (int64_t k = 0; k < N; ++k) {
+      J[q * N + k] = 0.0;
+      J[k * N + q] = 0.0;
+    }
+    J[q * N + q] = 1.0;
+  }
+  double scale = 0;
+  for (double v : J) scale = std::max(scale, std::fabs(v));
+  *max_abs = scale;
+}
+
 void coarse_matrix(const HostLevel& L, int r, const double* A, double dt, std::vector<double>& J,
                    double* max_abs) {
   const int d = L.dim;

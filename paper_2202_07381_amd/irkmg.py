@@ -69,7 +69,7 @@ class irk_newton_opts(C.Structure):
     _fields_ = [("rtol", C.c_double), ("atol", C.c_double), ("maxit", C.c_int), ("linear_maxit", C.c_int),
                 ("restart", C.c_int), ("eta0", C.c_double), ("eta_max", C.c_double), ("ew_gamma", C.c_double),
                 ("ew_alpha", C.c_double), ("ew_threshold", C.c_double), ("eta_fixed", C.c_double),
-                ("linesearch", C.c_int), ("ls_maxit", C.c_int), ("ls_alpha", C.c_double)]
+                ("linesearch", C.c_int), ("ls_maxit", C.c_int), ("ls_alpha", C.c_double), ("precond", C.c_int)]
 
 
 class irk_newton_info(C.Structure):
@@ -125,6 +125,7 @@ def _load() -> C.CDLL:
         "irk_ns_jacobian_apply": (i, [vp, vp, vp, vp, vp, vp, vp]),
         "irk_newton_default_opts": (None, [vp]),
         "irk_ns_newton_solve": (i, [vp, vp, vp, vp, vp, vp, vp, vp]),
+        "irk_ns_newton_preconditioner": (i, [vp, vp, vp, vp, i, vp]),
         "irk_batch_default_opts": (None, [vp]),
         "irk_batch_create": (i, [vp, i, vp, vp, vp]),
         "irk_batch_fgmres_solve": (i, [vp, vp, vp, d, i, i, vp, vp, vp]),
@@ -407,6 +408,16 @@ class IrkMG:
         st, g = self._ns_common(state, g_stages)
         _check(lib.irk_ns_jacobian_apply(self.h, st, g, _dev(k, n, "k"), _dev(x, n, "x"), _dev(y, n, "y"),
                                          _stream(stream)))
+
+    def irk_ns_newton_preconditioner(self, state=None, k=None, g_stages=None, enable=True, stream=None):
+        """Switch the V-cycle to the Newton Jacobian's operators at (state, k) (enable) or
+        back to the handle's own operator."""
+        if not enable:
+            _check(lib.irk_ns_newton_preconditioner(self.h, None, None, None, 0, _stream(stream)))
+            return
+        st, g = self._ns_common(state, g_stages)
+        _check(lib.irk_ns_newton_preconditioner(self.h, st, g, _dev(k, self.irk_mg_ndofs(), "k"), 1,
+                                                _stream(stream)))
 
     def irk_ns_newton_solve(self, F, state, k, g_stages=None, history_cap=64, stream=None, **opts):
         """Newton on the Navier--Stokes stage equations; opts: fields of irk_newton_opts."""

@@ -85,7 +85,7 @@ def coarse_tol(H):
     """max(1e-12, 4 cond_S(J_0) eps) for the pinned coarse operator J_0 of H, with
     Skeel's condition number cond_S(J_0) = || |J_0^{-1}| |J_0| ||_inf."""
     if id(H) not in _SKEEL:
-        J = H.systems[0].J.toarray()
+        J = H.ops[0].toarray()
         for q in H.pinned:
             J[q, :] = 0.0
             J[:, q] = 0.0
