@@ -17,6 +17,7 @@
 #include <map>
 #include <numeric>
 #include <stdexcept>
+#include <thread>
 #include <vector>
 
 #include "irk_internal.h"
@@ -629,56 +630,65 @@ std::string build_transfer(const HostLevel& C, HostLevel& F, const int64_t* pare
 // the two halves of the derivative of the trilinear form c(z, U) + c(U, z).  Exact
 // integration with the reference tensor int phi_e phi_a d_lam_k phi_b / |cell| (U is
 // quadratic on each cell, so every integrand is a polynomial of degree 5).
+// Assembled by rows: each free node sums the contributions of the cells around it to its
+// own row, in the order of its cell list, so threads over disjoint row ranges write
+// disjoint entries and the result does not depend on the thread count.
 void assemble_newton_block(const HostLevel& L, double nu, const double* U, double* out) {
   const int d = L.dim, nb = d + 1, nl = nloc_of(d), dd = d * d;
   const RefTensors& R = ref_tensors(d);
-  double glam[12], vol;
-  double wg[10][4], Ce[10][10], T[10][10][10][3], Re[10][10][3][3];
-  for (int64_t c = 0; c < L.nc; ++c) {
-    cell_geometry(L, c, glam, &vol);
-    const int64_t* cn = &L.cell_nodes[c * nl];
-    for (int f = 0; f < nl; ++f)
-      for (int k = 0; k < nb; ++k) {
-        double s = 0;
-        for (int i = 0; i < d; ++i) s += U[cn[f] * d + i] * glam[k * d + i];
-        wg[f][k] = s;
-      }
-    for (int a = 0; a < nl; ++a)
-      for (int b = 0; b < nl; ++b) {
-        double s = 0;
+  auto rows = [&](int64_t i0, int64_t i1) {
+    double glam[12], vol, wg[10][4], Tg[10][3];
+    for (int64_t ia = i0; ia < i1; ++ia) {
+      const int64_t na = L.node_of_free[ia];
+      for (int32_t q = L.node_cell_ptr[na]; q < L.node_cell_ptr[na + 1]; ++q) {
+        const int64_t c = L.node_cell[q];
+        const int64_t* cn = &L.cell_nodes[c * nl];
+        int a = 0;
+        while (cn[a] != na) ++a;
+        cell_geometry(L, c, glam, &vol);
         for (int f = 0; f < nl; ++f)
-          for (int k = 0; k < nb; ++k) s += wg[f][k] * R.C[((f * nl + a) * nl + b) * nb + k];
-        Ce[a][b] = vol * s;
-        for (int f = 0; f < nl; ++f)
-          for (int e = 0; e < d; ++e) {
-            double t = 0;
-            for (int k = 0; k < nb; ++k) t += glam[k * d + e] * R.C[((a * nl + b) * nl + f) * nb + k];
-            T[a][b][f][e] = t;
+          for (int k = 0; k < nb; ++k) {
+            double sum = 0;
+            for (int i = 0; i < d; ++i) sum += U[cn[f] * d + i] * glam[k * d + i];
+            wg[f][k] = sum;
           }
-        for (int cc = 0; cc < d; ++cc)
-          for (int e = 0; e < d; ++e) {
-            double t = 0;
-            for (int f = 0; f < nl; ++f) t += U[cn[f] * d + cc] * T[a][b][f][e];
-            Re[a][b][cc][e] = vol * t;
+        for (int b = 0; b < nl; ++b) {
+          const int64_t ib = L.free_of_node[cn[b]];
+          if (ib < 0) continue;
+          double ce = 0;
+          for (int f = 0; f < nl; ++f)
+            for (int k = 0; k < nb; ++k) ce += wg[f][k] * R.C[((f * nl + a) * nl + b) * nb + k];
+          for (int f = 0; f < nl; ++f)
+            for (int e = 0; e < d; ++e) {
+              double t = 0;
+              for (int k = 0; k < nb; ++k) t += glam[k * d + e] * R.C[((a * nl + b) * nl + f) * nb + k];
+              Tg[f][e] = t;
+            }
+          double* o = out + (size_t)find_in_row(L.s_ptr, L.s_col, ia, ib) * dd;
+          for (int cc = 0; cc < d; ++cc) {
+            o[cc * d + cc] += vol * ce;
+            for (int e = 0; e < d; ++e) {
+              double t = 0;
+              for (int f = 0; f < nl; ++f) t += U[cn[f] * d + cc] * Tg[f][e];
+              o[cc * d + e] += vol * t;
+            }
           }
-      }
-    for (int a = 0; a < nl; ++a) {
-      const int64_t ia = L.free_of_node[cn[a]];
-      if (ia < 0) continue;
-      for (int b = 0; b < nl; ++b) {
-        const int64_t ib = L.free_of_node[cn[b]];
-        if (ib < 0) continue;
-        const int32_t p = find_in_row(L.s_ptr, L.s_col, ia, ib);
-        double* o = out + (size_t)p * dd;
-        for (int cc = 0; cc < d; ++cc) {
-          o[cc * d + cc] += Ce[a][b];
-          for (int e = 0; e < d; ++e) o[cc * d + e] += Re[a][b][cc][e];
         }
       }
+      for (int32_t p = L.s_ptr[ia]; p < L.s_ptr[ia + 1]; ++p)
+        for (int cc = 0; cc < d; ++cc) out[(size_t)p * dd + cc * d + cc] += nu * L.s_K1[p];
     }
+  };
+  const int64_t n = L.nfree;
+  const int nt = (int)std::max<int64_t>(1, std::min<int64_t>({16, (int64_t)std::thread::hardware_concurrency(),
+                                                              n / 4096}));
+  if (nt == 1) {
+    rows(0, n);
+    return;
   }
-  for (size_t p = 0; p < L.s_col.size(); ++p)
-    for (int cc = 0; cc < d; ++cc) out[p * dd + cc * d + cc] += nu * L.s_K1[p];
+  std::vector<std::thread> pool;
+  for (int t = 0; t < nt; ++t) pool.emplace_back(rows, n * t / nt, n * (t + 1) / nt);
+  for (auto& th : pool) th.join();
 }
 
 // Dense coarse operator of the Newton Jacobian (row-major, internal layout, pressure of
