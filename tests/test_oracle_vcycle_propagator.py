@@ -42,7 +42,8 @@ TOL = 2e-9
 def _dense_S(H, lev, weighted):
     """W sum_v R_v^T A_v^{-1} R_v as a dense matrix, from the patch index sets and J."""
     J = H.ops[lev].toarray()
-    pats = patch_dofs(H.spaces[lev], H.r)
+    sp_ = H.spaces[lev]
+    pats = sp_.patches(H.r) if hasattr(sp_, "patches") else patch_dofs(sp_, H.r)
     n = J.shape[0]
     S = np.zeros((n, n))
     for p in pats:
