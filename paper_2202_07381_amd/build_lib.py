@@ -15,7 +15,10 @@ CSRC = os.path.join(HERE, "csrc")
 ROOT = os.path.dirname(HERE)
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libirkmg.so")
-SOURCES = ["kernels.hip", "batch.hip", "navier_stokes.hip", "noalloc.hip", "irk_mg.cpp", "setup_host.cpp"]
+SOURCES = [
+    "kernels.hip", "batch.hip", "navier_stokes.hip", "noalloc.hip", "mhd.hip",
+    "irk_mg.cpp", "setup_host.cpp", "mhd.cpp", "mhd_host.cpp",
+]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 COMMON = [

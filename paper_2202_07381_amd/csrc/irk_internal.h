@@ -503,4 +503,20 @@ int ritz_finish(int steps, const double* Hh, double* H, double* ritz_re, double*
 size_t ritz_partials_bytes();
 // stored failure (IRK_* code and message) for the calling thread
 int fail_with(int code, const std::string& msg);
+
+// Element helpers of the P2 assembly, for the other model assemblies: barycentric
+// gradients ((dim+1) x dim) and measure of cell c; barycentric coordinates of x in
+// cell c; CSR position of column c in a sorted row (-1 if absent); CSR from sorted
+// rows; CSR transpose (columns sorted); int_T phi_a lam_i / |T| for the P2 basis
+// ((nloc x (dim+1)), row-major); int_T d_k phi_a d_l phi_b / |T| indexed
+// [((a nloc + b)(dim+1) + k)(dim+1) + l], derivatives in barycentric coordinates.
+void fe_cell_geometry(const HostLevel& L, int64_t c, double* glam, double* vol);
+void fe_barycentric(const HostLevel& L, int64_t c, const double* x, double* lam);
+int32_t fe_find_in_row(const std::vector<int32_t>& ptr, const std::vector<int32_t>& col, int64_t row, int64_t c);
+void fe_csr_from_rows(std::vector<std::vector<int32_t>>& rows, std::vector<int32_t>& ptr, std::vector<int32_t>& col);
+void fe_transpose_csr(int64_t nrows, int64_t ncols, const std::vector<int32_t>& ptr, const std::vector<int32_t>& col,
+                      const std::vector<double>& val, std::vector<int32_t>& tptr, std::vector<int32_t>& tcol,
+                      std::vector<double>& tval);
+void fe_p2_lam_moments(int dim, double* out);
+const double* fe_p2_grad_grad(int dim);
 }  // namespace irk

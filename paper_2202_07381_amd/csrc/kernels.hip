@@ -21,6 +21,7 @@
 
 #include "device_ops.h"
 #include "irk_internal.h"
+#include "mhd_internal.h"
 
 namespace irk {
 namespace k {
@@ -1769,6 +1770,47 @@ hipError_t patch_factor_range(const DevLevel& L, const DevOps<T>& ops, int R, co
   return hipGetLastError();
 }
 
+// Generic Kronecker operators (one value per spatial unknown and stage): the kernels
+// above with D = 1, where the patch's last unknown takes the place of the pressure
+// slot and every coupling, that one included, comes from the triples.
+template <typename T>
+hipError_t patch_factor_scalar(const DevLevel& L, const DevOps<T>& ops, int R, const double* A, double dt,
+                               T* out, int nmax, int* d_fail, hipStream_t s) {
+  if (L.npatch <= 0) return hipSuccess;
+  const unsigned g = (unsigned)L.npatch;
+  const size_t n = (size_t)nmax;
+  const size_t lds = n * n * sizeof(T) + n * sizeof(T) + n * sizeof(int) + 64;
+#define IRK_PFS(KERN, LDS)                                                                                   \
+  do {                                                                                                       \
+    hipError_t e = hipFuncSetAttribute((const void*)KERN, hipFuncAttributeMaxDynamicSharedMemorySize, (int)(LDS)); \
+    if (e != hipSuccess) return e;                                                                           \
+    KERN<<<dim3(g), dim3(kBlock), LDS, s>>>(L.npatch, L.pn_ptr, L.pvv_ptr, L.pvv, L.pvp, L.p_ld, L.p_inv_off,  \
+                                           ops.s_M, ops.s_L, nullptr, cf, out, d_fail, 0, 0, nullptr);        \
+  } while (0)
+#define IRK_PFS_R(RR)                                                                                        \
+  {                                                                                                          \
+    const Coef<T> cf = scaled<T, RR>(A, dt);                                                                 \
+    if (lds <= 160 * 1024) {                                                                                 \
+      IRK_PFS((k_patch_factor<1, RR, T>), lds);                                                              \
+    } else {                                                                                                 \
+      if (n > (size_t)kGjRows * kBlock) return hipErrorInvalidConfiguration;                                 \
+      const size_t glds = (size_t)kGjBw * n * sizeof(T) + n * sizeof(T) + (size_t)kGjBw * kGjJt * sizeof(T) + \
+                          n * sizeof(int) + 64;                                                              \
+      IRK_PFS((k_patch_factor_global<1, RR, T>), glds);                                                      \
+    }                                                                                                        \
+  }
+  switch (R) {
+    case 1: IRK_PFS_R(1) break;
+    case 2: IRK_PFS_R(2) break;
+    case 3: IRK_PFS_R(3) break;
+    case 4: IRK_PFS_R(4) break;
+    default: return hipErrorInvalidValue;
+  }
+#undef IRK_PFS_R
+#undef IRK_PFS
+  return hipGetLastError();
+}
+
 template <typename T>
 hipError_t patch_factor_cplx(const DevLevel& L, const DevOps<T>& ops, double zr, double zi, int b, int nmax,
                              int* d_fail, hipStream_t s) {
@@ -2179,6 +2221,8 @@ hipError_t mass_apply(const DevLevel& L, const double* st, double* out, hipStrea
   template hipError_t patch_factor_range<T>(const DevLevel&, const DevOps<T>&, int, const double*, \
                                             double, const int32_t*, const int64_t*, T*, int64_t,   \
                                             int64_t, int64_t, int, int*, hipStream_t, const T*);   \
+  template hipError_t patch_factor_scalar<T>(const DevLevel&, const DevOps<T>&, int, const double*, double, T*, \
+                                             int, int*, hipStream_t);                                        \
   template hipError_t patch_factor_cplx<T>(const DevLevel&, const DevOps<T>&, double, double, int, int, \
                                            int*, hipStream_t);                                        \
   template hipError_t eig_extract<T>(const DevLevel&, const StageBasis<T>&, int, const int32_t*,  \

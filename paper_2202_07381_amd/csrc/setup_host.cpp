@@ -1135,4 +1135,25 @@ std::vector<double> sell_values(const Sell& S, const std::vector<double>& v, int
       for (int c = 0; c < k; ++c) out[e * k + c] = v[S.src[e] * k + c];
   return out;
 }
+
+// ---------------------------------------------- element helpers for other assemblies
+void fe_cell_geometry(const HostLevel& L, int64_t c, double* glam, double* vol) { cell_geometry(L, c, glam, vol); }
+void fe_barycentric(const HostLevel& L, int64_t c, const double* x, double* lam) { barycentric(L, c, x, lam); }
+int32_t fe_find_in_row(const std::vector<int32_t>& ptr, const std::vector<int32_t>& col, int64_t row, int64_t c) {
+  return find_in_row(ptr, col, row, c);
+}
+void fe_csr_from_rows(std::vector<std::vector<int32_t>>& rows, std::vector<int32_t>& ptr, std::vector<int32_t>& col) {
+  csr_from_rows(rows, ptr, col);
+}
+void fe_transpose_csr(int64_t nrows, int64_t ncols, const std::vector<int32_t>& ptr, const std::vector<int32_t>& col,
+                      const std::vector<double>& val, std::vector<int32_t>& tptr, std::vector<int32_t>& tcol,
+                      std::vector<double>& tval) {
+  transpose_csr(nrows, ncols, ptr, col, val, 1, tptr, tcol, tval);
+}
+void fe_p2_lam_moments(int dim, double* out) {
+  const int nl = nloc_of(dim), nb = dim + 1;
+  for (int a = 0; a < nl; ++a)
+    for (int i = 0; i < nb; ++i) out[a * nb + i] = integrate(mul(basis(dim, a), lam_pow(i, 1, 1.0)), dim);
+}
+const double* fe_p2_grad_grad(int dim) { return ref_tensors(dim).S.data(); }
 }  // namespace irk

@@ -1,4 +1,4 @@
-"""Thin ctypes binding of libirkmg (include/irk_mg.h).
+"""Thin ctypes binding of libirkmg (include/irk_mg.h, include/irk_mhd.h).
 
 Argument marshalling only: every step of the method runs in the HIP library.  Names
 follow the C ABI.  Device vectors are torch float64 CUDA tensors; the current torch
@@ -24,6 +24,7 @@ import torch  # noqa: F401,E402
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libirkmg.so")
 HEADER = os.path.join(os.path.dirname(_HERE), "include", "irk_mg.h")
+MHD_HEADER = os.path.join(os.path.dirname(_HERE), "include", "irk_mhd.h")
 
 IRK_OK, IRK_EINVAL, IRK_ENOMEM, IRK_EHIP, IRK_ESINGULAR, IRK_ENAN, IRK_ENOCONV = 0, -1, -2, -3, -4, -5, 1
 FAMILIES = {"radauIIA": 0, "gauss": 1, "lobattoIIIC": 2}
@@ -70,6 +71,10 @@ class irk_newton_opts(C.Structure):
                 ("restart", C.c_int), ("eta0", C.c_double), ("eta_max", C.c_double), ("ew_gamma", C.c_double),
                 ("ew_alpha", C.c_double), ("ew_threshold", C.c_double), ("eta_fixed", C.c_double),
                 ("linesearch", C.c_int), ("ls_maxit", C.c_int), ("ls_alpha", C.c_double), ("precond", C.c_int)]
+
+
+class irk_mhd_opts(C.Structure):
+    _fields_ = [("pre", C.c_int), ("post", C.c_int), ("omega", C.c_double), ("weighting", C.c_int)]
 
 
 class irk_newton_info(C.Structure):
@@ -134,6 +139,19 @@ def _load() -> C.CDLL:
         "irk_mg_profile": (i, [vp, i]),
         "irk_mg_kernel_stats": (i, [vp, i, i, vp]),
         "irk_last_error": (C.c_char_p, []),
+        "irk_mhd_default_opts": (None, [vp]),
+        "irk_mhd_setup": (i, [vp, i, vp, d, d, d, vp, vp, vp, vp, vp]),
+        "irk_mhd_destroy": (None, [vp]),
+        "irk_mhd_host_operators": (i, [vp, i, i, d, d, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp]),
+        "irk_mhd_ndofs": (i64, [vp, i]),
+        "irk_mhd_layout": (i, [vp, i, vp]),
+        "irk_mhd_apply": (i, [vp, i, vp, vp, vp]),
+        "irk_mhd_sweep": (i, [vp, i, vp, vp, vp]),
+        "irk_mhd_restrict": (i, [vp, i, vp, vp, vp]),
+        "irk_mhd_prolong": (i, [vp, i, vp, vp, vp]),
+        "irk_mhd_coarse_solve": (i, [vp, vp, vp, vp]),
+        "irk_mhd_vcycle": (i, [vp, vp, vp, vp]),
+        "irk_mhd_fgmres_solve": (i, [vp, vp, vp, d, i, i, vp, vp]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -146,8 +164,8 @@ lib = _load()
 
 
 def header_functions() -> list[str]:
-    """Names of the functions the public header declares."""
-    txt = open(HEADER).read()
+    """Names of the functions the public headers declare."""
+    txt = open(HEADER).read() + open(MHD_HEADER).read()
     return sorted(set(re.findall(r"^\s*(?:irk_status|void|int64_t|int|const char\*)\s+(irk_\w+)\s*\(", txt, re.M)))
 
 
@@ -515,3 +533,108 @@ class IrkBatch:
         out = [dict(iterations=i.iterations, converged=bool(i.converged), rel_residual=i.rel_residual,
                     latency_ms=float(l)) for i, l in zip(infos, lat)]
         return st, out, float(infos[0].ms_total)
+
+
+def irk_mhd_host_operators(levels, level, Re, Rem, w, b0):
+    """(M, S, P) of one level as scipy CSR matrices, assembled by the library on the host
+    (irk_mhd_host_operators; P is None on level 0)."""
+    import scipy.sparse as sp
+
+    structs, keep = [], []
+    for lv in levels:
+        s, k = _mesh_struct(lv)
+        structs.append(s)
+        keep += k
+    arr = (irk_mesh_level * len(structs))(*structs)
+    w = np.ascontiguousarray(w, dtype=np.float64)
+    b0 = np.ascontiguousarray(b0, dtype=np.float64)
+    sizes = np.zeros(4, dtype=np.int64)
+    args = (arr, len(structs), level, Re, Rem, w.ctypes.data, b0.ctypes.data, sizes.ctypes.data)
+    _check(lib.irk_mhd_host_operators(*args, None, None, None, None, None, None, None))
+    ns, nnz, nnzp, nsc = (int(v) for v in sizes)
+    ptr, col = np.zeros(ns + 1, np.int32), np.zeros(nnz, np.int32)
+    mv, sv = np.zeros(nnz), np.zeros(nnz)
+    pp, pc, pv = np.zeros(ns + 1, np.int32), np.zeros(max(nnzp, 1), np.int32), np.zeros(max(nnzp, 1))
+    _check(lib.irk_mhd_host_operators(*args, ptr.ctypes.data, col.ctypes.data, mv.ctypes.data, sv.ctypes.data,
+                                      pp.ctypes.data, pc.ctypes.data, pv.ctypes.data))
+    M = sp.csr_matrix((mv, col, ptr), shape=(ns, ns))
+    S = sp.csr_matrix((sv, col, ptr), shape=(ns, ns))
+    P = sp.csr_matrix((pv[:nnzp], pc[:nnzp], pp), shape=(ns, nsc)) if nsc > 0 else None
+    return M, S, P
+
+
+class IrkMHD:
+    """Handle of the linearised 2D MHD stage solver (irk_mhd_setup ... irk_mhd_destroy).
+    w: finest P2 nodes x 2 (the velocity of the linearisation); b0: Nedelec degrees of
+    freedom of B0 on every finest edge."""
+
+    def __init__(self, levels, A, dt: float, Re: float, Rem: float, w, b0, pre=2, post=2, omega=0.5, weighting=1,
+                 stream=None):
+        structs, keep = [], []
+        for lv in levels:
+            s, k = _mesh_struct(lv)
+            structs.append(s)
+            keep += k
+        arr = (irk_mesh_level * len(structs))(*structs)
+        self.A = np.ascontiguousarray(A, dtype=np.float64)
+        self.r = self.A.shape[0]
+        zero = np.zeros(self.r)
+        tab = irk_tableau(self.r, self.A.ctypes.data, zero.ctypes.data, zero.ctypes.data)
+        opts = irk_mhd_opts(pre, post, omega, weighting)
+        w = np.ascontiguousarray(w, dtype=np.float64)
+        b0 = np.ascontiguousarray(b0, dtype=np.float64)
+        h = C.c_void_p()
+        _check(lib.irk_mhd_setup(arr, len(structs), C.byref(tab), dt, Re, Rem, w.ctypes.data, b0.ctypes.data,
+                                 C.byref(opts), _stream(stream), C.byref(h)))
+        self.h = h
+        self.nlevels = len(structs)
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib.irk_mhd_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        self.close()
+
+    def irk_mhd_ndofs(self, level: int = -1) -> int:
+        return int(lib.irk_mhd_ndofs(self.h, level))
+
+    def irk_mhd_layout(self, level: int = -1) -> dict:
+        out = np.zeros(7, dtype=np.int64)
+        _check(lib.irk_mhd_layout(self.h, level, out.ctypes.data))
+        return dict(zip(("u_x", "u_y", "B", "p", "gamma", "ns", "r"), (int(v) for v in out)))
+
+    def irk_mhd_apply(self, level, x, y, stream=None):
+        n = self.irk_mhd_ndofs(level)
+        _check(lib.irk_mhd_apply(self.h, level, _dev(x, n, "x"), _dev(y, n, "y"), _stream(stream)))
+
+    def irk_mhd_sweep(self, level, F, k, stream=None):
+        n = self.irk_mhd_ndofs(level)
+        _check(lib.irk_mhd_sweep(self.h, level, _dev(F, n, "F"), _dev(k, n, "k"), _stream(stream)))
+
+    def irk_mhd_restrict(self, level, xf, xc, stream=None):
+        _check(lib.irk_mhd_restrict(self.h, level, _dev(xf, self.irk_mhd_ndofs(level), "xf"),
+                                    _dev(xc, self.irk_mhd_ndofs(level - 1), "xc"), _stream(stream)))
+
+    def irk_mhd_prolong(self, level, xc, xf, stream=None):
+        _check(lib.irk_mhd_prolong(self.h, level, _dev(xc, self.irk_mhd_ndofs(level - 1), "xc"),
+                                   _dev(xf, self.irk_mhd_ndofs(level), "xf"), _stream(stream)))
+
+    def irk_mhd_coarse_solve(self, b, x, stream=None):
+        n = self.irk_mhd_ndofs(0)
+        _check(lib.irk_mhd_coarse_solve(self.h, _dev(b, n, "b"), _dev(x, n, "x"), _stream(stream)))
+
+    def irk_mhd_vcycle(self, r, z, stream=None):
+        n = self.irk_mhd_ndofs()
+        _check(lib.irk_mhd_vcycle(self.h, _dev(r, n, "r"), _dev(z, n, "z"), _stream(stream)))
+
+    def irk_mhd_fgmres_solve(self, F, k, rtol=1e-8, maxit=1000, restart=30, history_cap=1024, stream=None):
+        n = self.irk_mhd_ndofs()
+        hist = np.zeros(max(1, history_cap))
+        info = irk_solve_info(0, 0, 0.0, hist.ctypes.data_as(C.POINTER(C.c_double)), history_cap, 0.0, 0.0)
+        st = _check(lib.irk_mhd_fgmres_solve(self.h, _dev(F, n, "F"), _dev(k, n, "k"), rtol, maxit, restart,
+                                             C.byref(info), _stream(stream)), ok=(IRK_OK, IRK_ENOCONV))
+        its = info.iterations
+        return dict(status=st, iterations=its, converged=bool(info.converged), rel_residual=info.rel_residual,
+                    history=hist[: min(history_cap, its + 1)].copy(), ms_vcycle=info.ms_vcycle, ms_total=info.ms_total)

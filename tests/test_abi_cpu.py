@@ -199,8 +199,9 @@ def test_struct_layouts_match_the_header(tmp_path):
     if cc is None:
         pytest.skip("no C compiler")
     structs = [irkmg.irk_mesh_level, irkmg.irk_tableau, irkmg.irk_mg_opts, irkmg.irk_solve_info,
-               irkmg.irk_batch_opts, irkmg.irk_kernel_stats, irkmg.irk_newton_opts, irkmg.irk_newton_info]
-    lines = ['#include <stdio.h>', '#include <stddef.h>', f'#include "{irkmg.HEADER}"', "int main(void) {"]
+               irkmg.irk_batch_opts, irkmg.irk_kernel_stats, irkmg.irk_newton_opts, irkmg.irk_newton_info,
+               irkmg.irk_mhd_opts]
+    lines = ['#include <stdio.h>', '#include <stddef.h>', f'#include "{irkmg.MHD_HEADER}"', "int main(void) {"]
     for st in structs:
         name = st.__name__
         lines.append(f'  printf("{name} %zu\\n", sizeof({name}));')
