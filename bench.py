@@ -135,6 +135,76 @@ def run_precision(precision, levels, A, b, c, dt, nu, mms, nodes, steps, warmup,
     return out
 
 
+def run_mhd(base=5, nlevels=7, Re=5000.0, nv=5):
+    """The linearised 2D MHD stage system (Sec. 3.3) of the island-coalescence workload
+    (Sec. 5.3): LobattoIIIC(2), Re = Rem, dt = 0.025 at the paper's level l = 4 (halved
+    per level), the crossed base x base mesh refined nlevels - 1 times (5 -> 320: the
+    paper's l = 4 finest mesh size, 2.66M unknowns per stage), state w = 0 and the
+    perturbed island field.  Times the V-cycle, one FGMRES(30) solve to 1e-8 of
+    J k = J x (x seeded N(0, 1)) from zero, and the finest level's kernels."""
+    import numpy as np
+    import torch
+
+    from paper_2202_07381_amd import irkmg
+    from paper_2202_07381_amd import workloads as wl
+
+    lv = wl.crossed_hierarchy(base, nlevels)
+    nfine = base * 2 ** (nlevels - 1)
+    ell = int(round(np.log2(nfine / 20)))
+    dt = 0.025 * 2.0 ** (4 - ell)
+    w0, b0 = wl.island_coalescence(lv[-1].xyz, lv[-1].cells)
+    A, _, _ = irkmg.irk_tableau_builtin("lobattoIIIC", 2)
+    t0 = time.time()
+    g = irkmg.IrkMHD(lv, A, dt, Re, Re, w0, b0)
+    torch.cuda.synchronize()
+    setup_s = time.time() - t0
+    n = g.irk_mhd_ndofs()
+    log(f"mhd setup {setup_s:.1f}s N={n}")
+    gen = torch.Generator(device="cuda").manual_seed(5)
+    xt = torch.randn(n, dtype=torch.float64, device="cuda", generator=gen)
+    F = torch.zeros_like(xt)
+    g.irk_mhd_apply(-1, xt, F)
+    z = torch.zeros_like(xt)
+    for _ in range(2):
+        g.irk_mhd_vcycle(xt, z)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(nv):
+        g.irk_mhd_vcycle(xt, z)
+    e1.record()
+    torch.cuda.synchronize()
+    vms = e0.elapsed_time(e1) / nv
+    k = torch.zeros_like(F)
+    info = g.irk_mhd_fgmres_solve(F, k, rtol=1e-8, maxit=300, restart=30, history_cap=0)
+    torch.cuda.synchronize()
+    g.irk_mhd_profile(1)
+    for _ in range(nv):
+        g.irk_mhd_vcycle(xt, z)
+    torch.cuda.synchronize()
+    kern = {}
+    for kname in ("patch_apply", "residual", "gather_update"):
+        st = g.irk_mhd_kernel_stats(kname, -1)
+        avg = st["ms_total"] / max(1, st["launches"])
+        gbs = st["bytes_per_launch"] / max(1e-12, avg * 1e-3) / 1e9
+        kern[kname] = {"launches": st["launches"], "avg_ms": avg, "bytes_per_launch": st["bytes_per_launch"],
+                       "GB/s": gbs, "frac": gbs / HBM_PEAK_GBS}
+    g.irk_mhd_profile(0)
+    lay = g.irk_mhd_layout()
+    g.close()
+    log(f"mhd V-cycle {vms:.2f} ms, FGMRES {info['iterations']} its {info['ms_total']:.1f} ms")
+    return {
+        "workload": f"linearised 2D MHD (island coalescence, w=0, perturbed B0), crossed {base}x{base} refined "
+                    f"{nlevels - 1}x to {nfine}x{nfine}, P2/Nedelec/P1/P1, LobattoIIIC(2), dt={dt}, Re=Rem={Re:g}, "
+                    f"{nlevels}-level V-cycle 2/2 additive Vanka omega=0.5, FGMRES(30) to 1e-8",
+        "unknowns": n, "unknowns_per_stage": lay["ns"], "setup_s": setup_s,
+        "vcycle_ms": vms, "vcycle_updates_per_s": n / (vms * 1e-3),
+        "fgmres": {"iterations": info["iterations"], "ms": info["ms_total"], "rel_residual": info["rel_residual"],
+                   "converged": info["converged"]},
+        "kernels_finest_level": kern,
+    }
+
+
 def cpu_baseline(A, c, dt, nu, n):
     """The oracle on the host cores: setup (assembly of every level and the patch
     inverses), one V-cycle (mean of 2 after a warm-up) and the full FGMRES(30) solve
@@ -723,7 +793,8 @@ def main():
     ap.add_argument("--cpu-n", type=int, default=128,
                     help="mesh of the oracle timing (256: the benchmark mesh itself, about 35 GB and minutes)")
     ap.add_argument("--no-fp32", action="store_true")
-    ap.add_argument("--workload", default="stokes256", choices=["stokes256", "batch64", "t1", "relax", "ns"],
+    ap.add_argument("--no-mhd", action="store_true", help="skip the linearised MHD measurement")
+    ap.add_argument("--workload", default="stokes256", choices=["stokes256", "batch64", "t1", "relax", "ns", "mhd"],
                     help="stokes256: the headline line; batch64: the uneven batched workload; t1: the paper's "
                          "2D Stokes table; relax: the three relaxations side by side; ns: Navier-Stokes "
                          "time steps with Newton")
@@ -781,6 +852,9 @@ def main():
     if args.workload == "ns":
         print(json.dumps(run_ns(args.ns_n, args.ns_steps, args.ns_relax, args.ns_precond, args.ns_dt, args.ns_dim,
                                 args.ns_nu, args.ns_eta_fixed)), flush=True)
+        return
+    if args.workload == "mhd":
+        print(json.dumps(run_mhd()), flush=True)
         return
     if args.workload == "t1":
         print(json.dumps(run_t1(args.t1_level, args.t1_stages, 1 if args.t1_fp32 else 0, args.t1_max_steps,
@@ -847,6 +921,8 @@ def main():
             "state_rel_diff_vs_fp64": diff,
             "patch_apply_GB/s": s32["bytes_per_launch"] / (ms32 * 1e-3) / 1e9,
         }
+    if not args.no_mhd:
+        line["mhd"] = run_mhd()
     if args.calibrate_copy:
         calibration_copies()
     if not args.no_cpu_baseline:

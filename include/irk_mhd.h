@@ -113,6 +113,20 @@ irk_status irk_mhd_vcycle(irk_mhd* h, const double* r, double* z, void* stream);
 irk_status irk_mhd_fgmres_solve(irk_mhd* h, const double* F, double* k, double rtol, int maxit, int restart,
                                 irk_solve_info* info, void* stream);
 
+/* Per-kernel timing with HIP events on the calls' stream: enable = 1 records the
+ * finest level's launches, 2 every level's, 0 stops; enabling clears what was recorded.
+ * irk_mhd_kernel_stats reports, for kernel 0 (patch apply), 1 (Kronecker residual) or
+ * 2 (gather update) on one level, the launches recorded, their total time and the
+ * algorithmic bytes of one launch (8-byte values, 4-byte indices):
+ *   patch apply    every stored inverse (sum over patches of (r n_s)^2 values), the
+ *                  residual once, the patch outputs;
+ *   residual       one column index and the M and S values per operator entry, x and F
+ *                  read once, the result written;
+ *   gather update  the patch outputs with their slot indices, x read and written, the
+ *                  weights. */
+irk_status irk_mhd_profile(irk_mhd* h, int enable);
+irk_status irk_mhd_kernel_stats(irk_mhd* h, int kernel, int level, irk_kernel_stats* out);
+
 #ifdef __cplusplus
 }
 #endif

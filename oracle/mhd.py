@@ -214,11 +214,10 @@ class MHDSpace:
         MB = np.einsum("q,cqfk,cqgk,c->cgf", w, nval, nval, detj, optimize=True)
         M = M + self._assemble(MB, brow, brow, shape)
         # pressure: -(p, div v) and -(q, div u)
-        Dv = th.divergence()  # component-blocked free velocity x vertices
-        Sp = sp.lil_matrix(shape)
-        Sp[: self.nu_, self.off_p:self.off_g] = Dv
-        Sp[self.off_p:self.off_g, : self.nu_] = Dv.T
-        S = S + Sp.tocsr()
+        Dv = sp.coo_matrix(th.divergence())  # component-blocked free velocity x vertices
+        rows = np.concatenate([Dv.row, Dv.col + self.off_p])
+        cols = np.concatenate([Dv.col + self.off_p, Dv.row])
+        S = S + sp.coo_matrix((np.concatenate([Dv.data, Dv.data]), (rows, cols)), shape=shape).tocsr()
         # multiplier: -(grad gamma, c) and -(B, grad s)
         Eg = -np.einsum("q,cqgk,cjk,c->cgj", w, nval, self.glam, detj, optimize=True)  # (nc, 3 edges, 3 vertices)
         S = S + self._assemble(Eg, brow, grow, shape)

@@ -35,6 +35,13 @@ struct MhdDev {
   DevLevel pv;
   DevOps<double> ops;
   double *b = nullptr, *x = nullptr, *res = nullptr, *Y = nullptr;
+  // algorithmic bytes per launch: patch apply, residual, gather update
+  double alg_bytes[3] = {0, 0, 0};
+};
+
+struct ProfEv {
+  hipEvent_t a = nullptr, b = nullptr;
+  int kernel = 0, level = 0;
 };
 
 }  // namespace
@@ -52,6 +59,9 @@ struct irk_mhd {
   double *partials = nullptr, *scal = nullptr, *hbuf = nullptr;
   int* flag = nullptr;
   hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
+  int prof = 0;  // 0 off, 1 finest level, 2 every level
+  std::vector<ProfEv> prof_pool;
+  size_t prof_used = 0;
   std::vector<void*> allocations;
 };
 
@@ -97,21 +107,48 @@ irk_status upload(irk_mhd* h, T** p, const std::vector<Src>& v, hipStream_t s) {
   return IRK_OK;
 }
 
+// ------------------------------------------------------------------- measurement
+int prof_begin(irk_mhd* h, int kernel, int level, hipStream_t s) {
+  if (!h->prof || (h->prof == 1 && level != h->nlevels - 1)) return -1;
+  if (h->prof_used == h->prof_pool.size()) {
+    ProfEv e;
+    if (hipEventCreate(&e.a) != hipSuccess || hipEventCreate(&e.b) != hipSuccess) return -1;
+    h->prof_pool.push_back(e);
+  }
+  ProfEv& e = h->prof_pool[h->prof_used];
+  e.kernel = kernel;
+  e.level = level;
+  if (hipEventRecord(e.a, s) != hipSuccess) return -1;
+  return (int)h->prof_used++;
+}
+
+void prof_end(irk_mhd* h, int idx, hipStream_t s) {
+  if (idx >= 0) (void)hipEventRecord(h->prof_pool[idx].b, s);
+}
+
 // ------------------------------------------------------------------ level operations
-irk_status residual(irk_mhd* h, const MhdDev& D, const double* F, const double* x, double* y, hipStream_t s) {
+irk_status residual(irk_mhd* h, int l, const double* F, const double* x, double* y, hipStream_t s) {
+  const MhdDev& D = h->dev[l];
+  const int pe = prof_begin(h, 1, l, s);
   HIPCHK(k::kron_residual(D.ns, D.nsl, D.sl_off, D.sl_w, D.sl_col, D.sl_m, D.sl_s, h->r, h->A, h->dt, F, x, y, s));
+  prof_end(h, pe, s);
   return IRK_OK;
 }
 
 // one damped additive sweep x += omega W S (b - J x); from x = 0 (zero) the residual is b
-irk_status sweep(irk_mhd* h, MhdDev& D, const double* b, double* x, bool zero, hipStream_t s) {
+irk_status sweep(irk_mhd* h, int l, const double* b, double* x, bool zero, hipStream_t s) {
+  MhdDev& D = h->dev[l];
   const double* res = b;
   if (!zero) {
-    CHK(residual(h, D, b, x, D.res, s));
+    CHK(residual(h, l, b, x, D.res, s));
     res = D.res;
   }
+  int pe = prof_begin(h, 0, l, s);
   HIPCHK(k::patch_apply<double>(D.pv, D.ops, res, D.Y, 0, s));
+  prof_end(h, pe, s);
+  pe = prof_begin(h, 2, l, s);
   HIPCHK(k::gather_update<double>(D.pv, D.ops, D.Y, x, h->omega, zero ? 0 : 1, s));
+  prof_end(h, pe, s);
   return IRK_OK;
 }
 
@@ -129,14 +166,14 @@ irk_status cycle(irk_mhd* h, int l, const double* b, double* x, hipStream_t s) {
     return coarse(h, D.b, x, s);
   }
   bool zero = true;
-  for (int i = 0; i < h->pre; ++i, zero = false) CHK(sweep(h, D, b, x, zero, s));
+  for (int i = 0; i < h->pre; ++i, zero = false) CHK(sweep(h, l, b, x, zero, s));
   if (zero) HIPCHK(k::fill(x, D.N, 0.0, s));
-  CHK(residual(h, D, b, x, D.res, s));
+  CHK(residual(h, l, b, x, D.res, s));
   MhdDev& C = h->dev[l - 1];
   HIPCHK(k::kron_csr(C.ns, D.Pt_ptr, D.Pt_col, D.Pt_val, h->r, D.res, C.b, 0, s));
   CHK(cycle(h, l - 1, C.b, C.x, s));
   HIPCHK(k::kron_csr(D.ns, D.P_ptr, D.P_col, D.P_val, h->r, C.x, x, 1, s));
-  for (int i = 0; i < h->post; ++i) CHK(sweep(h, D, b, x, false, s));
+  for (int i = 0; i < h->post; ++i) CHK(sweep(h, l, b, x, false, s));
   return IRK_OK;
 }
 
@@ -170,7 +207,8 @@ irk_status ensure_krylov(irk_mhd* h, int restart) {
 }
 
 irk_status fgmres(irk_mhd* h, double rtol, int maxit, int restart, irk_solve_info* info, hipStream_t s) {
-  MhdDev& L = h->dev[h->nlevels - 1];
+  const int fl = h->nlevels - 1;
+  MhdDev& L = h->dev[fl];
   const int64_t N = L.N;
   std::vector<double> Hm((size_t)(restart + 1) * restart), cs(restart), sn(restart), g(restart + 1), y(restart),
       hcol(restart + 2);
@@ -179,7 +217,7 @@ irk_status fgmres(irk_mhd* h, double rtol, int maxit, int restart, irk_solve_inf
     HIPCHK(hipStreamSynchronize(s));
     return IRK_OK;
   };
-  CHK(residual(h, L, h->kF, h->kx, h->kr, s));
+  CHK(residual(h, fl, h->kF, h->kx, h->kr, s));
   HIPCHK(k::dot(h->kr, h->kr, N, h->partials, h->scal, s, 1));
   double beta0;
   CHK(host_scalar(&beta0));
@@ -193,7 +231,7 @@ irk_status fgmres(irk_mhd* h, double rtol, int maxit, int restart, irk_solve_inf
   bool converged = beta0 == 0.0;
   float ms_v = 0.f;
   while (!converged && its < maxit) {
-    CHK(residual(h, L, h->kF, h->kx, h->kr, s));
+    CHK(residual(h, fl, h->kF, h->kx, h->kr, s));
     HIPCHK(k::dot(h->kr, h->kr, N, h->partials, h->scal, s, 1));
     double beta;
     CHK(host_scalar(&beta));
@@ -213,7 +251,7 @@ irk_status fgmres(irk_mhd* h, double rtol, int maxit, int restart, irk_solve_inf
       HIPCHK(hipEventRecord(h->ev[2], s));
       CHK(precondition(h, vj, zj, s));
       HIPCHK(hipEventRecord(h->ev[3], s));
-      CHK(residual(h, L, nullptr, zj, vn, s));
+      CHK(residual(h, fl, nullptr, zj, vn, s));
       HIPCHK(k::mgs_arnoldi(vn, h->kv, N, j, h->partials, h->hbuf, s));
       HIPCHK(hipMemcpyAsync(hcol.data(), h->hbuf, (j + 2) * sizeof(double), hipMemcpyDeviceToHost, s));
       HIPCHK(hipStreamSynchronize(s));
@@ -250,7 +288,7 @@ irk_status fgmres(irk_mhd* h, double rtol, int maxit, int restart, irk_solve_inf
     if (std::fabs(g[jend]) <= rtol * beta0) converged = true;
   }
   HIPCHK(k::project_pressure(L.pv, h->kx, h->partials, s));
-  CHK(residual(h, L, h->kF, h->kx, h->kr, s));
+  CHK(residual(h, fl, h->kF, h->kx, h->kr, s));
   HIPCHK(k::dot(h->kr, h->kr, N, h->partials, h->scal, s, 1));
   double fin;
   CHK(host_scalar(&fin));
@@ -295,6 +333,8 @@ irk_status build_device_level(irk_mhd* h, MhdHost& H, int l, hipStream_t s) {
   V.nv = H.nv;
   V.offV = H.off_p * r;
   for (double** b : {&D.b, &D.x, &D.res}) CHK(dalloc(h, b, (size_t)D.N));
+  // residual: column index and two values per operator entry, x, F read and y written
+  D.alg_bytes[1] = (double)H.col.size() * (4 + 2 * 8) + 3.0 * 8 * (double)D.N;
   if (l == 0) return IRK_OK;
   // transfers
   {
@@ -362,6 +402,17 @@ irk_status build_device_level(irk_mhd* h, MhdHost& H, int l, hipStream_t s) {
     CHK(upload(h, &V.g_off, G.off, s));
     CHK(upload(h, &V.g_w, G.w, s));
     CHK(upload(h, &V.g_slot, G.col, s));
+  }
+  {
+    // patch apply: every stored inverse once, the residual once, the patch outputs;
+    // gather update: the slots with their indices, x read and written, the weights
+    double sum_n = 0, sum_n2 = 0;
+    for (int64_t p = 0; p < np; ++p) {
+      sum_n += nloc[p];
+      sum_n2 += (double)nloc[p] * nloc[p];
+    }
+    D.alg_bytes[0] = 8.0 * (sum_n2 + (double)D.N + sum_n);
+    D.alg_bytes[2] = sum_n * (8 + 4) + 3.0 * 8 * (double)D.N;
   }
   std::vector<int32_t> sched(np);
   std::iota(sched.begin(), sched.end(), 0);
@@ -616,8 +667,39 @@ irk_status irk_mhd_host_operators(const irk_mesh_level* lv, int nlevels, int lev
   return IRK_OK;
 }
 
+irk_status irk_mhd_profile(irk_mhd* h, int enable) {
+  CHK(check(h));
+  if (enable < 0 || enable > 2) return fail(IRK_EINVAL, "profile mode must be 0..2");
+  h->prof = enable;
+  h->prof_used = 0;
+  return IRK_OK;
+}
+
+irk_status irk_mhd_kernel_stats(irk_mhd* h, int kernel, int level, irk_kernel_stats* out) {
+  CHK(check(h));
+  CHK(level_of(h, level, false));
+  if (!out || kernel < 0 || kernel > 2) return fail(IRK_EINVAL, "kernel must be 0..2 and out non-NULL");
+  out->launches = 0;
+  out->ms_total = 0;
+  out->bytes_per_launch = h->dev[level].alg_bytes[kernel];
+  for (size_t i = 0; i < h->prof_used; ++i) {
+    ProfEv& e = h->prof_pool[i];
+    if (e.kernel != kernel || e.level != level) continue;
+    HIPCHK(hipEventSynchronize(e.b));
+    float ms = 0;
+    HIPCHK(hipEventElapsedTime(&ms, e.a, e.b));
+    out->launches++;
+    out->ms_total += ms;
+  }
+  return IRK_OK;
+}
+
 void irk_mhd_destroy(irk_mhd* h) {
   if (!h) return;
+  for (auto& e : h->prof_pool) {
+    if (e.a) (void)hipEventDestroy(e.a);
+    if (e.b) (void)hipEventDestroy(e.b);
+  }
   for (void* p : h->allocations) (void)hipFree(p);
   for (auto& e : h->ev)
     if (e) (void)hipEventDestroy(e);
@@ -648,7 +730,7 @@ irk_status irk_mhd_apply(irk_mhd* h, int level, const double* x, double* y, void
   MhdDev& D = h->dev[level];
   hipStream_t s = S(stream);
   HIPCHK(k::stage_to_internal(D.ns, h->r, x, D.b, s));
-  CHK(residual(h, D, nullptr, D.b, D.res, s));
+  CHK(residual(h, level, nullptr, D.b, D.res, s));
   HIPCHK(k::stage_to_abi(D.ns, h->r, D.res, y, s));
   return IRK_OK;
 }
@@ -661,7 +743,7 @@ irk_status irk_mhd_sweep(irk_mhd* h, int level, const double* F, double* kk, voi
   hipStream_t s = S(stream);
   HIPCHK(k::stage_to_internal(D.ns, h->r, F, D.b, s));
   HIPCHK(k::stage_to_internal(D.ns, h->r, kk, D.x, s));
-  CHK(sweep(h, D, D.b, D.x, false, s));
+  CHK(sweep(h, level, D.b, D.x, false, s));
   HIPCHK(k::stage_to_abi(D.ns, h->r, D.x, kk, s));
   return IRK_OK;
 }

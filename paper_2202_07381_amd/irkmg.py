@@ -152,6 +152,8 @@ def _load() -> C.CDLL:
         "irk_mhd_coarse_solve": (i, [vp, vp, vp, vp]),
         "irk_mhd_vcycle": (i, [vp, vp, vp, vp]),
         "irk_mhd_fgmres_solve": (i, [vp, vp, vp, d, i, i, vp, vp]),
+        "irk_mhd_profile": (i, [vp, i]),
+        "irk_mhd_kernel_stats": (i, [vp, i, i, vp]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -269,7 +271,8 @@ class IrkMG:
         self.dim = levels[0].dim
 
     def close(self):
-        if getattr(self, "h", None):
+        # at interpreter exit the module globals may already be gone
+        if getattr(self, "h", None) and lib is not None:
             lib.irk_mg_destroy(self.h)
             self.h = None
 
@@ -507,7 +510,8 @@ class IrkBatch:
         self.h = h
 
     def close(self):
-        if getattr(self, "h", None):
+        # at interpreter exit the module globals may already be gone
+        if getattr(self, "h", None) and lib is not None:
             lib.irk_batch_destroy(self.h)
             self.h = None
 
@@ -590,7 +594,8 @@ class IrkMHD:
         self.nlevels = len(structs)
 
     def close(self):
-        if getattr(self, "h", None):
+        # at interpreter exit the module globals may already be gone
+        if getattr(self, "h", None) and lib is not None:
             lib.irk_mhd_destroy(self.h)
             self.h = None
 
@@ -638,3 +643,12 @@ class IrkMHD:
         its = info.iterations
         return dict(status=st, iterations=its, converged=bool(info.converged), rel_residual=info.rel_residual,
                     history=hist[: min(history_cap, its + 1)].copy(), ms_vcycle=info.ms_vcycle, ms_total=info.ms_total)
+
+    def irk_mhd_profile(self, mode):
+        _check(lib.irk_mhd_profile(self.h, int(mode)))
+
+    def irk_mhd_kernel_stats(self, kernel: str, level: int = -1) -> dict:
+        kid = {"patch_apply": 0, "residual": 1, "gather_update": 2}[kernel]
+        st = irk_kernel_stats()
+        _check(lib.irk_mhd_kernel_stats(self.h, kid, level, C.byref(st)))
+        return dict(launches=st.launches, ms_total=st.ms_total, bytes_per_launch=st.bytes_per_launch)

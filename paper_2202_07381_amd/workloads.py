@@ -145,6 +145,45 @@ def crossed_hierarchy(n_coarse: int, nlevels: int) -> list[MeshLevel]:
     return levels
 
 
+def mesh_edges(cells: np.ndarray, nverts: int) -> np.ndarray:
+    """(nedges, 2) vertex pairs (smaller, larger) of a simplicial mesh, sorted: the edge
+    numbering of the library and the checker."""
+    nb = cells.shape[1]
+    pairs = np.concatenate([cells[:, [a, b]] for a in range(nb) for b in range(a + 1, nb)])
+    key = np.sort(pairs, axis=1)
+    code = np.unique(key[:, 0] * nverts + key[:, 1])
+    return np.stack([code // nverts, code % nverts], axis=1)
+
+
+def island_field(x: np.ndarray, k: float = 0.2, perturb: bool = True) -> np.ndarray:
+    """The island-coalescence magnetic field of Sec. 5.3 (the equilibrium and, with
+    perturb, the perturbation of its initial condition) at points x of the unit square,
+    in the coordinates X = 2x - 1 of the paper's square (-1, 1)^2: (n, 2)."""
+    X, Y = 2.0 * x[:, 0] - 1.0, 2.0 * x[:, 1] - 1.0
+    den = np.cosh(2 * np.pi * Y) + k * np.cos(2 * np.pi * X)
+    b = np.stack([np.sinh(2 * np.pi * Y), k * np.sin(2 * np.pi * X)], axis=1) / den[:, None]
+    if perturb:
+        b += (-0.01 / np.pi) * np.stack([-np.cos(np.pi * X) * np.sin(np.pi * Y / 2) / 2,
+                                         np.cos(np.pi * Y / 2) * np.sin(np.pi * X)], axis=1)
+    return b
+
+
+def island_coalescence(xyz: np.ndarray, cells: np.ndarray, k: float = 0.2, perturb: bool = True,
+                       npts: int = 8) -> tuple[np.ndarray, np.ndarray]:
+    """Linearisation state of the 2D MHD workload on one mesh: the velocity w = 0 at the
+    P2 nodes (vertices, then edges), (nverts + nedges, 2), and the line integrals of the
+    island field along every edge from its smaller to its larger vertex (Gauss--Legendre
+    with npts points), (nedges,)."""
+    nv = xyz.shape[0]
+    edges = mesh_edges(cells, nv)
+    a, b = xyz[edges[:, 0]], xyz[edges[:, 1]]
+    g, wg = np.polynomial.legendre.leggauss(npts)
+    b0 = np.zeros(edges.shape[0])
+    for t, wt in zip(0.5 * (g + 1.0), 0.5 * wg):
+        b0 += wt * np.einsum("ek,ek->e", island_field(a + t * (b - a), k, perturb), b - a)
+    return np.zeros((nv + edges.shape[0], 2)), b0
+
+
 # ----------------------------------------------------------------------------- 3D
 _KUHN_PERMS = list(itertools.permutations(range(3)))
 

@@ -34,12 +34,10 @@ def _levels(case):
 
 
 def _state(case):
-    from oracle.fem import TaylorHood
-    from oracle.mhd import MHDSpace, island_state
+    from paper_2202_07381_amd import workloads as wl
 
     lv = _levels(case)
-    sf = MHDSpace(TaylorHood(lv[-1].xyz, lv[-1].cells))
-    w0, b0 = island_state(sf)
+    w0, b0 = wl.island_coalescence(lv[-1].xyz, lv[-1].cells)
     if CASES[case]["seed"] is not None:
         w0 = 0.3 * np.random.default_rng(CASES[case]["seed"]).standard_normal(w0.shape)
     return w0, b0

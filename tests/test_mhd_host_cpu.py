@@ -15,8 +15,7 @@ from paper_2202_07381_amd import workloads as wl
 
 
 def _state(lv, seed):
-    sf = MHDSpace(TaylorHood(lv[-1].xyz, lv[-1].cells))
-    w0, b0 = island_state(sf)
+    w0, b0 = wl.island_coalescence(lv[-1].xyz, lv[-1].cells)
     if seed is not None:
         w0 = 0.3 * np.random.default_rng(seed).standard_normal(w0.shape)
     return w0, b0
@@ -40,6 +39,16 @@ def test_host_operators_match_oracle(nc, nl, Re, Rem, seed):
         Po = H.P[level][:ns, :nsc]
         assert P.shape == Po.shape and P.nnz == Po.nnz
         assert abs(P - Po).max() <= 1e-14
+
+
+@pytest.mark.parametrize("hier", ["square", "crossed"])
+def test_island_input_is_the_oracle_island_state(hier):
+    """The shared input generator gives the oracle's island-coalescence state."""
+    lv = (wl.square_hierarchy(3, 2) if hier == "square" else wl.crossed_hierarchy(2, 2))[-1]
+    w_o, b_o = island_state(MHDSpace(TaylorHood(lv.xyz, lv.cells)))
+    w, b = wl.island_coalescence(lv.xyz, lv.cells)
+    assert w.shape == w_o.shape and not w.any()
+    assert np.abs(b - b_o).max() <= 1e-15 * np.abs(b_o).max()
 
 
 def test_host_operators_reject_invalid_meshes():
