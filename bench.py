@@ -304,16 +304,17 @@ def _pmc_rows(d, counter):
 PATCH_KERNELS = ("k_patch_apply_sym<double, 128", "k_patch_apply_eig<double, 1, 128")
 
 
-def summarize_pmc(fetch_dir, write_dir):
-    """Per-launch HBM bytes of the finest-level patch apply from two rocprofv3 --pmc
-    runs (FETCH_SIZE, WRITE_SIZE; KiB per dispatch), each scaled by what the same
-    counter reads for the calibration copies (CALIB_ELEMS doubles in and out)."""
+def summarize_pmc(fetch_dir, write_dir, tags=PATCH_KERNELS):
+    """Per-launch HBM bytes of the finest-level patch apply (the first kernel whose name
+    contains one of tags) from two rocprofv3 --pmc runs (FETCH_SIZE, WRITE_SIZE; KiB per
+    dispatch), each scaled by what the same counter reads for the calibration copies
+    (CALIB_ELEMS doubles in and out)."""
     res = {}
     for name, d, counter in (("fetch", fetch_dir, "FETCH_SIZE"), ("write", write_dir, "WRITE_SIZE")):
         rows = _pmc_rows(d, counter)
         cal = [v for (k, g), vals in rows.items() if "neg_kernel" in k for v in vals]
         pa = {}
-        for tag in PATCH_KERNELS:  # the form the bench workload uses (symmetric for Stokes)
+        for tag in tags:  # the form the workload uses (symmetric for Stokes)
             pa = {(k, g): vals for (k, g), vals in rows.items() if tag in k}
             if pa:
                 res["kernel"] = tag
@@ -826,11 +827,14 @@ def main():
                     help="t1: fixed relative tolerance instead of the paper's stopping rule")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run plain copies of known size (for scaling PMC byte counters)")
+    ap.add_argument("--pmc-kernel", action="append", default=None,
+                    help="with --summarize-pmc: kernel name fragment(s) to summarise (default: the patch apply "
+                         "of the headline workload)")
     ap.add_argument("--summarize-pmc", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
                     help="print the traffic record from two rocprofv3 --pmc output directories and exit")
     args = ap.parse_args()
     if args.summarize_pmc:
-        summarize_pmc(*args.summarize_pmc)
+        summarize_pmc(*args.summarize_pmc, tags=tuple(args.pmc_kernel) if args.pmc_kernel else PATCH_KERNELS)
         return
     if args.gpus != 1:
         print("bench.py measures one GPU: the library has no multi-GPU path "
@@ -855,6 +859,8 @@ def main():
         return
     if args.workload == "mhd":
         print(json.dumps(run_mhd()), flush=True)
+        if args.calibrate_copy:
+            calibration_copies()
         return
     if args.workload == "t1":
         print(json.dumps(run_t1(args.t1_level, args.t1_stages, 1 if args.t1_fp32 else 0, args.t1_max_steps,

@@ -138,3 +138,26 @@ def test_mhd_vcycle_equals_textbook_propagator():
     w0, b0 = island_state(sf)
     H = MHDHierarchy(lv, A, 0.025, 50.0, 50.0, w0 + 0.3, b0)
     _check(H, _Propagator(H, 0.5, True), 16, 21, TOL)
+
+
+def test_single_patch_exactness():
+    """One patch solve of the stage-coupled system recovers any vector supported on the
+    patch (Sec. 4.2): R_v^T A_v^{-1} R_v J e = e, for an interior, an edge and a corner
+    vertex of the linearised MHD operator."""
+    A, _, _ = tableau("lobattoIIIC", 2)
+    lv = wl.square_hierarchy(2, 2)
+    sf = MHDSpace(TaylorHood(lv[-1].xyz, lv[-1].cells))
+    w0, b0 = island_state(sf)
+    H = MHDHierarchy(lv, A, 0.025, 50.0, 20.0, w0 + 0.3, b0)
+    J = H.ops[-1]
+    pats = sf.patches(2)
+    rng = np.random.default_rng(4)
+    n = 4
+    for v in (2 * (n + 1) + 2, 2, 0):
+        idx = pats[v]
+        e = np.zeros(J.shape[0])
+        e[idx] = rng.standard_normal(idx.size)
+        Av = J[idx][:, idx].toarray()
+        got = np.zeros_like(e)
+        got[idx] = np.linalg.solve(Av, (J @ e)[idx])
+        assert np.abs(got - e).max() <= 16 * np.linalg.cond(Av) * np.finfo(float).eps * np.abs(e).max()
