@@ -25,7 +25,9 @@ inline unsigned blocks_for(int64_t n, int block = kBlock) {
 }
 
 // one lane per row; slices of 64 rows stored column-major, so the k-th entries of a
-// wavefront's rows are one coalesced access (padding entries: column 0, values 0)
+// wavefront's rows are one coalesced access (padding entries: column 0, values 0).  The
+// entries are taken four at a time, all their loads issued before the first product, so
+// that a lane has four gathers of x in flight; the products are summed in entry order.
 template <int R>
 __global__ __launch_bounds__(kBlock) void k_kron_residual(int64_t nrows, int64_t nsl, const int32_t* __restrict__ sl_off,
                                                           const int32_t* __restrict__ sl_w,
@@ -43,7 +45,31 @@ __global__ __launch_bounds__(kBlock) void k_kron_residual(int64_t nrows, int64_t
   double am[R], as[R];
 #pragma unroll
   for (int s = 0; s < R; ++s) am[s] = as[s] = 0.0;
-  for (int k = 0; k < w; ++k) {
+  constexpr int U = 4;
+  int k = 0;
+  for (; k + U <= w; k += U) {
+    int64_t c[U];
+    double m[U], sv[U], xv[U][R];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int64_t e = e0 + (int64_t)(k + u) * 64;
+      c[u] = sl_col[e];
+      m[u] = sl_m[e];
+      sv[u] = sl_s[e];
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+#pragma unroll
+      for (int s = 0; s < R; ++s) xv[u][s] = x[c[u] * R + s];
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+#pragma unroll
+      for (int s = 0; s < R; ++s) {
+        am[s] += m[u] * xv[u][s];
+        as[s] += sv[u] * xv[u][s];
+      }
+  }
+  for (; k < w; ++k) {
     const int64_t e = e0 + (int64_t)k * 64;
     const int64_t c = sl_col[e];
     const double m = sl_m[e], sv = sl_s[e];
