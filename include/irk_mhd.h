@@ -57,13 +57,21 @@ typedef struct irk_mhd irk_mhd; /* opaque handle */
 
 /* Relaxation options: `pre` / `post` damped additive sweeps k += omega W S (F - J k)
  * per level (Sec. 4.2), W = I (weighting 0) or each unknown's correction divided by
- * the number of patches containing it (weighting 1).  Defaults: 2, 2, 0.5, 1. */
+ * the number of patches containing it (weighting 1).  patch_form: how the exact inverse
+ * of each stage-coupled patch matrix I (x) M_v + dt A (x) S_v is stored (the operator
+ * applied is the same): 0 dense, (r n_s)^2 values; 1 factored through A = W T W^{-1}
+ * (irk_stage_basis), r n_s^2 values, IRK_EINVAL from setup if A has no
+ * well-conditioned real block diagonalisation; 2 automatic (1 when r >= 2 and the
+ * decomposition exists, else 0).  Defaults: 2, 2, 0.5, 1, 2. */
 typedef struct irk_mhd_opts {
   int pre, post;
   double omega;
   int weighting;
+  int patch_form;
 } irk_mhd_opts;
 void irk_mhd_default_opts(irk_mhd_opts* opt);
+/* The patch form the handle uses (0 or 1), -1 for NULL. */
+int irk_mhd_patch_form(const irk_mhd* h);
 
 /* Build the hierarchy, assemble every level's M and S, factorise every patch on the
  * GPU and the coarsest operator (dense, FP64).

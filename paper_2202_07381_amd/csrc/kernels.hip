@@ -1775,17 +1775,18 @@ hipError_t patch_factor_range(const DevLevel& L, const DevOps<T>& ops, int R, co
 // slot and every coupling, that one included, comes from the triples.
 template <typename T>
 hipError_t patch_factor_scalar(const DevLevel& L, const DevOps<T>& ops, int R, const double* A, double dt,
-                               T* out, int nmax, int* d_fail, hipStream_t s) {
-  if (L.npatch <= 0) return hipSuccess;
-  const unsigned g = (unsigned)L.npatch;
+                               const int32_t* ld, const int64_t* off, T* out, int64_t p0, int64_t p1, int64_t off0,
+                               int nmax, int* d_fail, hipStream_t s) {
+  if (p1 <= p0) return hipSuccess;
+  const unsigned g = (unsigned)(p1 - p0);
   const size_t n = (size_t)nmax;
   const size_t lds = n * n * sizeof(T) + n * sizeof(T) + n * sizeof(int) + 64;
 #define IRK_PFS(KERN, LDS)                                                                                   \
   do {                                                                                                       \
     hipError_t e = hipFuncSetAttribute((const void*)KERN, hipFuncAttributeMaxDynamicSharedMemorySize, (int)(LDS)); \
     if (e != hipSuccess) return e;                                                                           \
-    KERN<<<dim3(g), dim3(kBlock), LDS, s>>>(L.npatch, L.pn_ptr, L.pvv_ptr, L.pvv, L.pvp, L.p_ld, L.p_inv_off,  \
-                                           ops.s_M, ops.s_L, nullptr, cf, out, d_fail, 0, 0, nullptr);        \
+    KERN<<<dim3(g), dim3(kBlock), LDS, s>>>(p1, L.pn_ptr, L.pvv_ptr, L.pvv, L.pvp, ld, off, ops.s_M, ops.s_L,  \
+                                           nullptr, cf, out, d_fail, p0, off0, nullptr);                      \
   } while (0)
 #define IRK_PFS_R(RR)                                                                                        \
   {                                                                                                          \
@@ -2221,7 +2222,8 @@ hipError_t mass_apply(const DevLevel& L, const double* st, double* out, hipStrea
   template hipError_t patch_factor_range<T>(const DevLevel&, const DevOps<T>&, int, const double*, \
                                             double, const int32_t*, const int64_t*, T*, int64_t,   \
                                             int64_t, int64_t, int, int*, hipStream_t, const T*);   \
-  template hipError_t patch_factor_scalar<T>(const DevLevel&, const DevOps<T>&, int, const double*, double, T*, \
+  template hipError_t patch_factor_scalar<T>(const DevLevel&, const DevOps<T>&, int, const double*, double,   \
+                                             const int32_t*, const int64_t*, T*, int64_t, int64_t, int64_t,  \
                                              int, int*, hipStream_t);                                        \
   template hipError_t patch_factor_cplx<T>(const DevLevel&, const DevOps<T>&, double, double, int, int, \
                                            int*, hipStream_t);                                        \

@@ -51,6 +51,8 @@ struct irk_mhd {
   double dt = 0, A[kMaxStages * kMaxStages] = {0};
   int pre = 2, post = 2, weighting = 1;
   double omega = 0.5;
+  int pform = 0;     // patch storage: 0 dense, 1 factored through the stage eigenbasis
+  StageEig eig;      // A = W T W^{-1} when pform = 1
   std::vector<MhdDev> dev;
   double *cinv = nullptr, *cmat = nullptr, *cpart = nullptr;
   int64_t* pins = nullptr;
@@ -309,6 +311,64 @@ irk_status fgmres(irk_mhd* h, double rtol, int maxit, int restart, irk_solve_inf
 }
 
 // ----------------------------------------------------------------------------- setup
+// Factored form: for each block of the stage eigenbasis (one real eigenvalue or one
+// complex pair), the 1- or 2-stage block matrix I (x) M_v + dt T_b (x) S_v of a chunk of
+// patches is inverted densely into a temporary buffer, and its first block column is
+// copied into the factored layout; chunks keep the temporary under 2 GiB.
+irk_status factor_blocks(irk_mhd* h, const DevLevel& V, const DevOps<double>& ops, const std::vector<int32_t>& nloc,
+                         int max_ns, hipStream_t s) {
+  const StageEig& E = h->eig;
+  const int r = h->r, VEC = 2;
+  const int64_t np = V.npatch;
+  const int64_t budget = ((int64_t)2 << 30) / (int64_t)sizeof(double);
+  for (int b = 0; b < E.nblk; ++b) {
+    const int m = E.type[b];
+    std::vector<int32_t> tld(np);
+    std::vector<int64_t> toff(np + 1, 0);
+    for (int64_t p = 0; p < np; ++p) {
+      const int n = m * (nloc[p] / r);
+      tld[p] = (n + VEC - 1) / VEC * VEC;
+      toff[p + 1] = toff[p] + (int64_t)tld[p] * n;
+    }
+    int64_t chunk_max = 0;
+    for (int64_t p0 = 0; p0 < np;) {
+      int64_t p1 = p0 + 1;
+      while (p1 < np && toff[p1 + 1] - toff[p0] <= budget) ++p1;
+      chunk_max = std::max(chunk_max, toff[p1] - toff[p0]);
+      p0 = p1;
+    }
+    int32_t* d_tld = nullptr;
+    int64_t* d_toff = nullptr;
+    double* tmp = nullptr;
+    auto release = [&]() {
+      (void)hipStreamSynchronize(s);
+      if (d_tld) (void)hipFree(d_tld);
+      if (d_toff) (void)hipFree(d_toff);
+      if (tmp) (void)hipFree(tmp);
+    };
+    if (hipMalloc(&d_tld, np * sizeof(int32_t)) != hipSuccess ||
+        hipMalloc(&d_toff, (np + 1) * sizeof(int64_t)) != hipSuccess ||
+        hipMalloc(&tmp, (size_t)chunk_max * sizeof(double)) != hipSuccess) {
+      release();
+      return fail(IRK_ENOMEM, "device allocation of the factorisation workspace failed");
+    }
+    hipError_t e = hipMemcpyAsync(d_tld, tld.data(), np * sizeof(int32_t), hipMemcpyHostToDevice, s);
+    if (e == hipSuccess)
+      e = hipMemcpyAsync(d_toff, toff.data(), (np + 1) * sizeof(int64_t), hipMemcpyHostToDevice, s);
+    for (int64_t p0 = 0; e == hipSuccess && p0 < np;) {
+      int64_t p1 = p0 + 1;
+      while (p1 < np && toff[p1 + 1] - toff[p0] <= budget) ++p1;
+      e = k::patch_factor_scalar<double>(V, ops, m, E.Tb[b], h->dt, d_tld, d_toff, tmp, p0, p1, toff[p0],
+                                         m * max_ns, h->flag, s);
+      if (e == hipSuccess) e = k::eig_extract<double>(V, V.sb64, b, d_tld, d_toff, toff[p0], tmp, p0, p1, s);
+      p0 = p1;
+    }
+    release();
+    if (e != hipSuccess) return fail(IRK_EHIP, std::string("patch factorisation: ") + hipGetErrorString(e));
+  }
+  return IRK_OK;
+}
+
 irk_status build_device_level(irk_mhd* h, MhdHost& H, int l, hipStream_t s) {
   MhdDev& D = h->dev[l];
   const int r = h->r;
@@ -357,13 +417,22 @@ irk_status build_device_level(irk_mhd* h, MhdHost& H, int l, hipStream_t s) {
   std::vector<int64_t> inv_off(np), slot_off(np);
   int64_t io = 0, so = 0;
   int maxn = 0;
+  const int pform = h->pform;
   for (int64_t p = 0; p < np; ++p) {
     const int nsp = H.pptr[p + 1] - H.pptr[p];
     const int n = r * nsp;
     nloc[p] = n;
-    ld[p] = (n + VEC - 1) / VEC * VEC;
     inv_off[p] = io;
-    io += (int64_t)ld[p] * n;
+    if (pform == 1) {
+      // n_s columns, each the concatenation of the eigen-blocks' rows
+      int lc = 0;
+      for (int b = 0; b < h->eig.nblk; ++b) lc += irk::eig_block_rows(h->eig.type[b], nsp, VEC);
+      ld[p] = lc;
+      io += (int64_t)lc * nsp;
+    } else {
+      ld[p] = (n + VEC - 1) / VEC * VEC;
+      io += (int64_t)ld[p] * n;
+    }
     slot_off[p] = so;
     so = (so + n + kLine - 1) / kLine * kLine;
     maxn = std::max(maxn, n);
@@ -406,10 +475,11 @@ irk_status build_device_level(irk_mhd* h, MhdHost& H, int l, hipStream_t s) {
   {
     // patch apply: every stored inverse once, the residual once, the patch outputs;
     // gather update: the slots with their indices, x read and written, the weights
+    // (stored values: (r n_s)^2 dense, r n_s^2 factored)
     double sum_n = 0, sum_n2 = 0;
     for (int64_t p = 0; p < np; ++p) {
       sum_n += nloc[p];
-      sum_n2 += (double)nloc[p] * nloc[p];
+      sum_n2 += pform == 1 ? (double)nloc[p] * nloc[p] / r : (double)nloc[p] * nloc[p];
     }
     D.alg_bytes[0] = 8.0 * (sum_n2 + (double)D.N + sum_n);
     D.alg_bytes[2] = sum_n * (8 + 4) + 3.0 * 8 * (double)D.N;
@@ -418,7 +488,20 @@ irk_status build_device_level(irk_mhd* h, MhdHost& H, int l, hipStream_t s) {
   std::iota(sched.begin(), sched.end(), 0);
   std::stable_sort(sched.begin(), sched.end(), [&](int32_t a, int32_t b) { return nloc[a] > nloc[b]; });
   V.npatch = np;
-  V.pform = 0;
+  V.pform = pform;
+  if (pform == 1) {
+    const StageEig& E = h->eig;
+    V.sb64.r = r;
+    V.sb64.nblk = E.nblk;
+    for (int b = 0; b < E.nblk; ++b) {
+      V.sb64.type[b] = E.type[b];
+      V.sb64.st0[b] = E.st0[b];
+    }
+    for (int i = 0; i < r * r; ++i) {
+      V.sb64.W[i] = E.W[i];
+      V.sb64.Winv[i] = E.Winv[i];
+    }
+  }
   V.max_nloc = maxn;
   V.max_ld = *std::max_element(ld.begin(), ld.end());
   V.inv_elems = io;
@@ -444,7 +527,12 @@ irk_status build_device_level(irk_mhd* h, MhdHost& H, int l, hipStream_t s) {
   CHK(dalloc(h, &D.Y, (size_t)so + 1));
   HIPCHK(hipMemsetAsync(D.Y, 0, (so + 1) * sizeof(double), s));
   HIPCHK(hipMemsetAsync(h->flag, 0, sizeof(int), s));
-  HIPCHK(k::patch_factor_scalar<double>(V, D.ops, r, h->A, h->dt, inv, maxn, h->flag, s));
+  if (pform == 0) {
+    HIPCHK(k::patch_factor_scalar<double>(V, D.ops, r, h->A, h->dt, V.p_ld, V.p_inv_off, inv, 0, np, 0, maxn,
+                                          h->flag, s));
+  } else {
+    CHK(factor_blocks(h, V, D.ops, nloc, maxn / r, s));
+  }
   int fl = 0;
   HIPCHK(hipMemcpyAsync(&fl, h->flag, sizeof(int), hipMemcpyDeviceToHost, s));
   HIPCHK(hipStreamSynchronize(s));
@@ -577,6 +665,7 @@ void irk_mhd_default_opts(irk_mhd_opts* opt) {
   opt->post = 2;
   opt->omega = 0.5;
   opt->weighting = 1;
+  opt->patch_form = 2;
 }
 
 irk_status irk_mhd_setup(const irk_mesh_level* lv, int nlevels, const irk_tableau* tab, double dt, double Re,
@@ -597,6 +686,7 @@ irk_status irk_mhd_setup(const irk_mesh_level* lv, int nlevels, const irk_tablea
   if (o.pre < 0 || o.post < 0 || o.pre > 64 || o.post > 64) return fail(IRK_EINVAL, "sweep counts must be in 0..64");
   if (!(o.omega > 0) || !std::isfinite(o.omega)) return fail(IRK_EINVAL, "omega must be positive");
   if (o.weighting != 0 && o.weighting != 1) return fail(IRK_EINVAL, "weighting must be 0 or 1");
+  if (o.patch_form < 0 || o.patch_form > 2) return fail(IRK_EINVAL, "patch_form must be 0, 1 or 2");
   CHK(check_meshes(lv, nlevels));
   irk_mhd* h = new (std::nothrow) irk_mhd();
   if (!h) return fail(IRK_ENOMEM, "handle allocation failed");
@@ -608,6 +698,15 @@ irk_status irk_mhd_setup(const irk_mesh_level* lv, int nlevels, const irk_tablea
   h->post = o.post;
   h->omega = o.omega;
   h->weighting = o.weighting;
+  {
+    std::string why;
+    const bool ok = o.patch_form != 0 && stage_eigenbasis(h->A, h->r, h->eig, &why);
+    if (o.patch_form == 1 && !ok) {
+      delete h;
+      return fail(IRK_EINVAL, "factored patch form unavailable: " + why);
+    }
+    h->pform = ok && (o.patch_form == 1 || h->r >= 2) ? 1 : 0;
+  }
   irk_status st;
   try {
     st = setup_impl(lv, nlevels, tab, dt, Re, Rem, w, b0, S(stream), h);
@@ -705,6 +804,8 @@ void irk_mhd_destroy(irk_mhd* h) {
     if (e) (void)hipEventDestroy(e);
   delete h;
 }
+
+int irk_mhd_patch_form(const irk_mhd* h) { return h ? h->pform : -1; }
 
 int64_t irk_mhd_ndofs(const irk_mhd* h, int level) {
   if (!h) return -1;

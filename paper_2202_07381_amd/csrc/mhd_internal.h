@@ -61,13 +61,15 @@ hipError_t kron_csr(int64_t nrows, const int32_t* ptr, const int32_t* col, const
 // between the ABI layout (stage blocks of ns) and the internal layout (stage innermost)
 hipError_t stage_to_internal(int64_t ns, int R, const double* abi, double* x, hipStream_t s);
 hipError_t stage_to_abi(int64_t ns, int R, const double* x, double* abi, hipStream_t s);
-// Dense inverses of the stage-coupled patch matrices of a generic Kronecker operator:
+// Dense inverses of I_R (x) M_v + dt A (x) S_v for the patches [p0, p1) of a generic
+// Kronecker operator (A: R x R, the stage matrix or one block of its eigenbasis form):
 // patch p has n_s = pn_ptr[p+1] - pn_ptr[p] + 1 spatial unknowns, its entries come from
-// the triples pvv (M and S values at their CSR positions); L.p_ld / L.p_inv_off give
-// the storage (column-major n x ld, n = R n_s).
+// the triples pvv (M and S values at their CSR positions); patch p's inverse is stored
+// column-major (R n_s x ld[p]) at out + off[p] - off0; nmax bounds R n_s.
 template <typename T>
 hipError_t patch_factor_scalar(const DevLevel& L, const DevOps<T>& ops, int R, const double* A, double dt,
-                               T* out, int nmax, int* d_fail, hipStream_t s);
+                               const int32_t* ld, const int64_t* off, T* out, int64_t p0, int64_t p1, int64_t off0,
+                               int nmax, int* d_fail, hipStream_t s);
 }  // namespace k
 
 }  // namespace irk

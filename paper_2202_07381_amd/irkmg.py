@@ -74,7 +74,8 @@ class irk_newton_opts(C.Structure):
 
 
 class irk_mhd_opts(C.Structure):
-    _fields_ = [("pre", C.c_int), ("post", C.c_int), ("omega", C.c_double), ("weighting", C.c_int)]
+    _fields_ = [("pre", C.c_int), ("post", C.c_int), ("omega", C.c_double), ("weighting", C.c_int),
+                ("patch_form", C.c_int)]
 
 
 class irk_newton_info(C.Structure):
@@ -144,6 +145,7 @@ def _load() -> C.CDLL:
         "irk_mhd_destroy": (None, [vp]),
         "irk_mhd_host_operators": (i, [vp, i, i, d, d, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp]),
         "irk_mhd_ndofs": (i64, [vp, i]),
+        "irk_mhd_patch_form": (i, [vp]),
         "irk_mhd_layout": (i, [vp, i, vp]),
         "irk_mhd_apply": (i, [vp, i, vp, vp, vp]),
         "irk_mhd_sweep": (i, [vp, i, vp, vp, vp]),
@@ -573,7 +575,7 @@ class IrkMHD:
     freedom of B0 on every finest edge."""
 
     def __init__(self, levels, A, dt: float, Re: float, Rem: float, w, b0, pre=2, post=2, omega=0.5, weighting=1,
-                 stream=None):
+                 patch_form=2, stream=None):
         structs, keep = [], []
         for lv in levels:
             s, k = _mesh_struct(lv)
@@ -584,7 +586,7 @@ class IrkMHD:
         self.r = self.A.shape[0]
         zero = np.zeros(self.r)
         tab = irk_tableau(self.r, self.A.ctypes.data, zero.ctypes.data, zero.ctypes.data)
-        opts = irk_mhd_opts(pre, post, omega, weighting)
+        opts = irk_mhd_opts(pre, post, omega, weighting, patch_form)
         w = np.ascontiguousarray(w, dtype=np.float64)
         b0 = np.ascontiguousarray(b0, dtype=np.float64)
         h = C.c_void_p()
@@ -604,6 +606,9 @@ class IrkMHD:
 
     def irk_mhd_ndofs(self, level: int = -1) -> int:
         return int(lib.irk_mhd_ndofs(self.h, level))
+
+    def irk_mhd_patch_form(self) -> int:
+        return int(lib.irk_mhd_patch_form(self.h))
 
     def irk_mhd_layout(self, level: int = -1) -> dict:
         out = np.zeros(7, dtype=np.int64)

@@ -9,7 +9,10 @@ mesh family of the paper's island-coalescence runs) at Re = Rem = 5000.
 Tolerances as for the fluid solver: single operator applications 1e-13 relative to the
 largest entry; patch sweeps 1e-11; the coarse solve max(1e-12, 4 cond_S(J_0) eps)
 (Skeel's componentwise condition number of the pinned coarse operator); V-cycles 1e-11;
-FGMRES solutions after equal iteration counts 1e-10."""
+FGMRES solutions after equal iteration counts 1e-10.  Sweeps, V-cycles and solves run
+with both patch forms: dense inverses (0) and the automatic choice (2), which for r >= 2
+stores each inverse factored through the stage eigenbasis (the same operator up to
+rounding)."""
 import numpy as np
 import pytest
 
@@ -24,6 +27,7 @@ CASES = {
     "mx": dict(mesh="crossed", nc=2, nl=3, fam="lobattoIIIC", r=2, dt=0.025, Re=5000.0, Rem=5000.0, seed=None),
 }
 _G, _H = {}, {}
+FORMS = [0, 2]
 
 
 def _levels(case):
@@ -55,17 +59,17 @@ def oracle_of(case):
     return _H[case]
 
 
-def gpu_of(case):
-    if case not in _G:
+def gpu_of(case, form=2):
+    if (case, form) not in _G:
         from oracle.tableau import tableau
         from paper_2202_07381_amd import irkmg
 
         c = CASES[case]
         A, _, _ = tableau(c["fam"], c["r"])
         w0, b0 = _state(case)
-        say(f"[mhd-setup] case={case}")
-        _G[case] = irkmg.IrkMHD(_levels(case), A, c["dt"], c["Re"], c["Rem"], w0, b0)
-    return _G[case]
+        say(f"[mhd-setup] case={case} form={form}")
+        _G[(case, form)] = irkmg.IrkMHD(_levels(case), A, c["dt"], c["Re"], c["Rem"], w0, b0, patch_form=form)
+    return _G[(case, form)]
 
 
 def _skeel_tol(H):
@@ -129,39 +133,43 @@ def test_coarse_solve(case):
     assert err < tol
 
 
+@pytest.mark.parametrize("form", FORMS)
 @pytest.mark.parametrize("case", list(CASES))
-def test_sweep_each_level(case):
-    g, H = gpu_of(case), oracle_of(case)
+def test_sweep_each_level(case, form):
+    g, H = gpu_of(case, form), oracle_of(case)
+    assert g.irk_mhd_patch_form() == (1 if form == 2 else 0)
     rng = np.random.default_rng(24)
     for lev in range(1, g.nlevels):
         J = H.systems[lev].J
         F, k0 = rng.standard_normal(J.shape[0]), rng.standard_normal(J.shape[0])
-        say(f"[mhd-sweep] case={case} level={lev}")
+        say(f"[mhd-sweep] case={case} form={form} level={lev}")
         k = to_dev(k0)
         g.irk_mhd_sweep(lev, to_dev(F), k)
         ref = H.smoothers[lev].sweep(F, k0, J)
         err = relerr(to_host(k), ref)
-        say(f"[mhd-sweep] case={case} level={lev} err={err:.2e}")
+        say(f"[mhd-sweep] case={case} form={form} level={lev} err={err:.2e}")
         assert err < 1e-11
 
 
+@pytest.mark.parametrize("form", FORMS)
 @pytest.mark.parametrize("case", list(CASES))
-def test_vcycle(case):
-    g, H = gpu_of(case), oracle_of(case)
+def test_vcycle(case, form):
+    g, H = gpu_of(case, form), oracle_of(case)
     r = np.random.default_rng(25).standard_normal(g.irk_mhd_ndofs())
     say(f"[mhd-vcycle] case={case}")
     z = torch.zeros(r.size, dtype=torch.float64, device="cuda")
     g.irk_mhd_vcycle(to_dev(r), z)
     err = relerr(to_host(z), H.vcycle(r))
-    say(f"[mhd-vcycle] case={case} err={err:.2e}")
+    say(f"[mhd-vcycle] case={case} form={form} err={err:.2e}")
     assert err < 1e-11
 
 
+@pytest.mark.parametrize("form", FORMS)
 @pytest.mark.parametrize("case", list(CASES))
-def test_fgmres_matches_oracle(case):
+def test_fgmres_matches_oracle(case, form):
     from oracle.fgmres import fgmres
 
-    g, H = gpu_of(case), oracle_of(case)
+    g, H = gpu_of(case, form), oracle_of(case)
     S = H.systems[-1]
     F = S.J @ np.random.default_rng(26).standard_normal(S.n)
     for rtol, maxit in ((1e-8, 200), (1e-30, 4)):
@@ -170,7 +178,8 @@ def test_fgmres_matches_oracle(case):
         info = g.irk_mhd_fgmres_solve(to_dev(F), k, rtol=rtol, maxit=maxit, restart=30)
         xo, io = fgmres(S.apply, H.vcycle, F, np.zeros_like(F), rtol, maxit, 30, project=S.project_pressure_mean)
         err = relerr(to_host(k), xo)
-        say(f"[mhd-fgmres] case={case} its={info['iterations']} oracle_its={io.iterations} err={err:.2e}")
+        say(f"[mhd-fgmres] case={case} form={form} its={info['iterations']} oracle_its={io.iterations} "
+            f"err={err:.2e}")
         assert info["iterations"] == io.iterations
         assert err < 1e-10
         if rtol > 1e-20:
