@@ -55,19 +55,24 @@ extern "C" {
 
 typedef struct irk_mhd irk_mhd; /* opaque handle */
 
-/* Relaxation options: `pre` / `post` damped additive sweeps k += omega W S (F - J k)
- * per level (Sec. 4.2), W = I (weighting 0) or each unknown's correction divided by
- * the number of patches containing it (weighting 1).  patch_form: how the exact inverse
+/* Relaxation options: smoother 0, `pre` / `post` damped additive sweeps
+ * k += omega W S (F - J k) per level (Sec. 4.2), W = I (weighting 0) or each unknown's
+ * correction divided by the number of patches containing it (weighting 1); smoother 1,
+ * `pre` / `post` steps of the Chebyshev semi-iteration (Sec. 5.1) accelerating W S for
+ * the spectrum interval [cheb_lo, cheb_hi] of W S J (omega unused; the paper's MHD runs
+ * use 3 / 3 steps on [2, 10] with the unweighted operator).  patch_form: how the exact inverse
  * of each stage-coupled patch matrix I (x) M_v + dt A (x) S_v is stored (the operator
  * applied is the same): 0 dense, (r n_s)^2 values; 1 factored through A = W T W^{-1}
  * (irk_stage_basis), r n_s^2 values, IRK_EINVAL from setup if A has no
  * well-conditioned real block diagonalisation; 2 automatic (1 when r >= 2 and the
- * decomposition exists, else 0).  Defaults: 2, 2, 0.5, 1, 2. */
+ * decomposition exists, else 0).  Defaults: 2, 2, 0.5, 1, 2, smoother 0, interval [2, 10]. */
 typedef struct irk_mhd_opts {
   int pre, post;
   double omega;
   int weighting;
   int patch_form;
+  int smoother;
+  double cheb_lo, cheb_hi;
 } irk_mhd_opts;
 void irk_mhd_default_opts(irk_mhd_opts* opt);
 /* The patch form the handle uses (0 or 1), -1 for NULL. */
@@ -103,7 +108,8 @@ irk_status irk_mhd_layout(const irk_mhd* h, int level, int64_t* out);
 /* y = J_l x on level l. */
 irk_status irk_mhd_apply(irk_mhd* h, int level, const double* x, double* y, void* stream);
 /* One damped additive Vanka sweep on level l >= 1: k <- k + omega W sum_v R_v^T
- * A_v^{-1} R_v (F - J_l k), A_v = R_v J_l R_v^T (Sec. 4.2). */
+ * A_v^{-1} R_v (F - J_l k), A_v = R_v J_l R_v^T (Sec. 4.2); with smoother 1 one
+ * Chebyshev step from k, k <- k + W S (F - J_l k) / theta. */
 irk_status irk_mhd_sweep(irk_mhd* h, int level, const double* F, double* k, void* stream);
 /* xc = (I_r (x) P_l)^T xf, level l >= 1 to l-1; xf += (I_r (x) P_l) xc (Sec. 4.1). */
 irk_status irk_mhd_restrict(irk_mhd* h, int level, const double* xf, double* xc, void* stream);

@@ -325,15 +325,18 @@ class _MHDLevel:
 
 class MHDHierarchy(Hierarchy):
     """The V-cycle of Sec. 4.1 for the linearised MHD stage system: rediscretisation on
-    every level, the Vanka patches of Fig. 1 (right), damped additive sweeps, I_r (x) P
-    transfers and a dense coarse solve with the pressure of vertex 0 pinned per stage;
-    the cycle itself is multigrid.Hierarchy's."""
+    every level, the Vanka patches of Fig. 1 (right), damped additive sweeps (smoother
+    "sweep") or Chebyshev relaxation on `interval` (smoother "chebyshev", Sec. 5.1; the
+    paper's MHD runs take 3 / 3 steps on [2, 10]), I_r (x) P transfers and a dense coarse
+    solve with the pressure of vertex 0 pinned per stage; the cycle itself is
+    multigrid.Hierarchy's."""
 
-    def __init__(self, mesh_levels, A, dt, Re, Rem, w_fine, b0_fine, omega=0.5, weighted=True, pre=2, post=2):
+    def __init__(self, mesh_levels, A, dt, Re, Rem, w_fine, b0_fine, omega=0.5, weighted=True, pre=2, post=2,
+                 smoother="sweep", interval=(2.0, 10.0)):
         self.A = np.asarray(A, dtype=np.float64)
         self.r = r = self.A.shape[0]
         self.pre, self.post = pre, post
-        self.smoother, self.interval = "sweep", (2.0, 8.0)
+        self.smoother, self.interval = smoother, tuple(interval)
         self.dtype = np.float64
         ths = [TaylorHood(m.xyz, m.cells) for m in mesh_levels]
         self.spaces = [MHDSpace(t) for t in ths]

@@ -35,6 +35,7 @@ struct MhdDev {
   DevLevel pv;
   DevOps<double> ops;
   double *b = nullptr, *x = nullptr, *res = nullptr, *Y = nullptr;
+  double* dch = nullptr;  // Chebyshev direction
   // algorithmic bytes per launch: patch apply, residual, gather update
   double alg_bytes[3] = {0, 0, 0};
 };
@@ -51,6 +52,8 @@ struct irk_mhd {
   double dt = 0, A[kMaxStages * kMaxStages] = {0};
   int pre = 2, post = 2, weighting = 1;
   double omega = 0.5;
+  int smoother = 0;  // 0 damped additive sweeps, 1 Chebyshev (Sec. 5.1)
+  double cheb_lo = 2.0, cheb_hi = 10.0;
   int pform = 0;     // patch storage: 0 dense, 1 factored through the stage eigenbasis
   StageEig eig;      // A = W T W^{-1} when pform = 1
   std::vector<MhdDev> dev;
@@ -154,6 +157,49 @@ irk_status sweep(irk_mhd* h, int l, const double* b, double* x, bool zero, hipSt
   return IRK_OK;
 }
 
+// n relaxation steps on level l from x (from zero when zero): damped sweeps, or the
+// Chebyshev semi-iteration on [cheb_lo, cheb_hi] for the spectrum of W S J (theta, delta,
+// sigma and the rho recurrence, coefficients in FP64)
+irk_status relax(irk_mhd* h, int l, const double* b, double* x, int n, bool zero, hipStream_t s) {
+  MhdDev& D = h->dev[l];
+  if (n == 0) {
+    if (zero) HIPCHK(k::fill(x, D.N, 0.0, s));
+    return IRK_OK;
+  }
+  if (h->smoother == 0) {
+    for (int i = 0; i < n; ++i) CHK(sweep(h, l, b, x, zero && i == 0, s));
+    return IRK_OK;
+  }
+  const double theta = 0.5 * (h->cheb_hi + h->cheb_lo), delta = 0.5 * (h->cheb_hi - h->cheb_lo);
+  const double sigma = theta / delta;
+  double rho = 0.0;
+  for (int it = 0; it < n; ++it) {
+    const bool xzero = zero && it == 0;
+    const double* r = b;
+    if (!xzero) {
+      CHK(residual(h, l, b, x, D.res, s));
+      r = D.res;
+    }
+    int pe = prof_begin(h, 0, l, s);
+    HIPCHK(k::patch_apply<double>(D.pv, D.ops, r, D.Y, 0, s));
+    prof_end(h, pe, s);
+    double c1 = 0.0, c2;
+    if (it == 0) {
+      rho = 1.0 / sigma;
+      c2 = 1.0 / theta;
+    } else {
+      const double rn = 1.0 / (2.0 * sigma - rho);
+      c1 = rn * rho;
+      c2 = 2.0 * rn / delta;
+      rho = rn;
+    }
+    pe = prof_begin(h, 2, l, s);
+    HIPCHK(k::gather_cheb<double>(D.pv, D.ops, D.Y, c1, c2, it == 0 ? 1 : 0, xzero ? 1 : 0, 0, D.dch, x, s));
+    prof_end(h, pe, s);
+  }
+  return IRK_OK;
+}
+
 irk_status coarse(irk_mhd* h, double* b, double* x, hipStream_t s) {
   HIPCHK(k::coarse_solve(h->cinv, h->cmat, h->dev[0].N, b, x, h->pins, h->r, h->cpart, s));
   return IRK_OK;
@@ -167,15 +213,13 @@ irk_status cycle(irk_mhd* h, int l, const double* b, double* x, hipStream_t s) {
     if (b != D.b) HIPCHK(hipMemcpyAsync(D.b, b, D.N * sizeof(double), hipMemcpyDeviceToDevice, s));
     return coarse(h, D.b, x, s);
   }
-  bool zero = true;
-  for (int i = 0; i < h->pre; ++i, zero = false) CHK(sweep(h, l, b, x, zero, s));
-  if (zero) HIPCHK(k::fill(x, D.N, 0.0, s));
+  CHK(relax(h, l, b, x, h->pre, true, s));
   CHK(residual(h, l, b, x, D.res, s));
   MhdDev& C = h->dev[l - 1];
   HIPCHK(k::kron_csr(C.ns, D.Pt_ptr, D.Pt_col, D.Pt_val, h->r, D.res, C.b, 0, s));
   CHK(cycle(h, l - 1, C.b, C.x, s));
   HIPCHK(k::kron_csr(D.ns, D.P_ptr, D.P_col, D.P_val, h->r, C.x, x, 1, s));
-  for (int i = 0; i < h->post; ++i) CHK(sweep(h, l, b, x, false, s));
+  CHK(relax(h, l, b, x, h->post, false, s));
   return IRK_OK;
 }
 
@@ -393,6 +437,7 @@ irk_status build_device_level(irk_mhd* h, MhdHost& H, int l, hipStream_t s) {
   V.nv = H.nv;
   V.offV = H.off_p * r;
   for (double** b : {&D.b, &D.x, &D.res}) CHK(dalloc(h, b, (size_t)D.N));
+  if (h->smoother == 1 && l > 0) CHK(dalloc(h, &D.dch, (size_t)D.N));
   // residual: column index and two values per operator entry, x, F read and y written
   D.alg_bytes[1] = (double)H.col.size() * (4 + 2 * 8) + 3.0 * 8 * (double)D.N;
   if (l == 0) return IRK_OK;
@@ -666,6 +711,9 @@ void irk_mhd_default_opts(irk_mhd_opts* opt) {
   opt->omega = 0.5;
   opt->weighting = 1;
   opt->patch_form = 2;
+  opt->smoother = 0;
+  opt->cheb_lo = 2.0;
+  opt->cheb_hi = 10.0;
 }
 
 irk_status irk_mhd_setup(const irk_mesh_level* lv, int nlevels, const irk_tableau* tab, double dt, double Re,
@@ -687,6 +735,9 @@ irk_status irk_mhd_setup(const irk_mesh_level* lv, int nlevels, const irk_tablea
   if (!(o.omega > 0) || !std::isfinite(o.omega)) return fail(IRK_EINVAL, "omega must be positive");
   if (o.weighting != 0 && o.weighting != 1) return fail(IRK_EINVAL, "weighting must be 0 or 1");
   if (o.patch_form < 0 || o.patch_form > 2) return fail(IRK_EINVAL, "patch_form must be 0, 1 or 2");
+  if (o.smoother != 0 && o.smoother != 1) return fail(IRK_EINVAL, "smoother must be 0 or 1");
+  if (o.smoother == 1 && !(o.cheb_lo > 0 && o.cheb_hi > o.cheb_lo && std::isfinite(o.cheb_hi)))
+    return fail(IRK_EINVAL, "Chebyshev interval must satisfy 0 < cheb_lo < cheb_hi < inf");
   CHK(check_meshes(lv, nlevels));
   irk_mhd* h = new (std::nothrow) irk_mhd();
   if (!h) return fail(IRK_ENOMEM, "handle allocation failed");
@@ -698,6 +749,9 @@ irk_status irk_mhd_setup(const irk_mesh_level* lv, int nlevels, const irk_tablea
   h->post = o.post;
   h->omega = o.omega;
   h->weighting = o.weighting;
+  h->smoother = o.smoother;
+  h->cheb_lo = o.cheb_lo;
+  h->cheb_hi = o.cheb_hi;
   {
     std::string why;
     const bool ok = o.patch_form != 0 && stage_eigenbasis(h->A, h->r, h->eig, &why);
@@ -844,7 +898,7 @@ irk_status irk_mhd_sweep(irk_mhd* h, int level, const double* F, double* kk, voi
   hipStream_t s = S(stream);
   HIPCHK(k::stage_to_internal(D.ns, h->r, F, D.b, s));
   HIPCHK(k::stage_to_internal(D.ns, h->r, kk, D.x, s));
-  CHK(sweep(h, level, D.b, D.x, false, s));
+  CHK(relax(h, level, D.b, D.x, 1, false, s));
   HIPCHK(k::stage_to_abi(D.ns, h->r, D.x, kk, s));
   return IRK_OK;
 }

@@ -75,7 +75,7 @@ class irk_newton_opts(C.Structure):
 
 class irk_mhd_opts(C.Structure):
     _fields_ = [("pre", C.c_int), ("post", C.c_int), ("omega", C.c_double), ("weighting", C.c_int),
-                ("patch_form", C.c_int)]
+                ("patch_form", C.c_int), ("smoother", C.c_int), ("cheb_lo", C.c_double), ("cheb_hi", C.c_double)]
 
 
 class irk_newton_info(C.Structure):
@@ -575,7 +575,7 @@ class IrkMHD:
     freedom of B0 on every finest edge."""
 
     def __init__(self, levels, A, dt: float, Re: float, Rem: float, w, b0, pre=2, post=2, omega=0.5, weighting=1,
-                 patch_form=2, stream=None):
+                 patch_form=2, smoother=0, interval=(2.0, 10.0), stream=None):
         structs, keep = [], []
         for lv in levels:
             s, k = _mesh_struct(lv)
@@ -586,7 +586,7 @@ class IrkMHD:
         self.r = self.A.shape[0]
         zero = np.zeros(self.r)
         tab = irk_tableau(self.r, self.A.ctypes.data, zero.ctypes.data, zero.ctypes.data)
-        opts = irk_mhd_opts(pre, post, omega, weighting, patch_form)
+        opts = irk_mhd_opts(pre, post, omega, weighting, patch_form, smoother, interval[0], interval[1])
         w = np.ascontiguousarray(w, dtype=np.float64)
         b0 = np.ascontiguousarray(b0, dtype=np.float64)
         h = C.c_void_p()

@@ -5,7 +5,9 @@ Cases: a diagonal-split hierarchy 2 -> 8 with LobattoIIIC(2), a random linearisa
 velocity and the island-coalescence field; a diagonal-split 2 -> 16 hierarchy with
 RadauIIA(3) (stage-coupled patches of up to 156 unknowns: the factorisation takes the
 blocked global-memory path); a crossed 2 -> 8 hierarchy (vertices of valence 8 and 4, the
-mesh family of the paper's island-coalescence runs) at Re = Rem = 5000.
+mesh family of the paper's island-coalescence runs) at Re = Rem = 5000, with the damped
+sweep and with the paper's MHD relaxation (3 / 3 Chebyshev steps on [2, 10], Sec. 5.1,
+5.3; a level sweep is then one Chebyshev step).
 Tolerances as for the fluid solver: single operator applications 1e-13 relative to the
 largest entry; patch sweeps 1e-11; the coarse solve max(1e-12, 4 cond_S(J_0) eps)
 (Skeel's componentwise condition number of the pinned coarse operator); V-cycles 1e-11;
@@ -25,6 +27,9 @@ CASES = {
     "m2": dict(mesh="square", nc=2, nl=3, fam="lobattoIIIC", r=2, dt=0.025, Re=100.0, Rem=50.0, seed=3),
     "m3": dict(mesh="square", nc=2, nl=4, fam="radauIIA", r=3, dt=0.01, Re=1000.0, Rem=1000.0, seed=None),
     "mx": dict(mesh="crossed", nc=2, nl=3, fam="lobattoIIIC", r=2, dt=0.025, Re=5000.0, Rem=5000.0, seed=None),
+    # the paper's MHD relaxation: 3 / 3 Chebyshev steps on [2, 10], unweighted operator
+    "mc": dict(mesh="crossed", nc=2, nl=3, fam="lobattoIIIC", r=2, dt=0.025, Re=5000.0, Rem=5000.0, seed=None,
+               cheb=True),
 }
 _G, _H = {}, {}
 FORMS = [0, 2]
@@ -55,7 +60,11 @@ def oracle_of(case):
         c = CASES[case]
         A, _, _ = tableau(c["fam"], c["r"])
         w0, b0 = _state(case)
-        _H[case] = MHDHierarchy(_levels(case), A, c["dt"], c["Re"], c["Rem"], w0, b0)
+        if c.get("cheb"):
+            _H[case] = MHDHierarchy(_levels(case), A, c["dt"], c["Re"], c["Rem"], w0, b0, weighted=False, pre=3,
+                                    post=3, smoother="chebyshev", interval=(2.0, 10.0))
+        else:
+            _H[case] = MHDHierarchy(_levels(case), A, c["dt"], c["Re"], c["Rem"], w0, b0)
     return _H[case]
 
 
@@ -68,7 +77,9 @@ def gpu_of(case, form=2):
         A, _, _ = tableau(c["fam"], c["r"])
         w0, b0 = _state(case)
         say(f"[mhd-setup] case={case} form={form}")
-        _G[(case, form)] = irkmg.IrkMHD(_levels(case), A, c["dt"], c["Re"], c["Rem"], w0, b0, patch_form=form)
+        relax = dict(pre=3, post=3, weighting=0, smoother=1, interval=(2.0, 10.0)) if c.get("cheb") else {}
+        _G[(case, form)] = irkmg.IrkMHD(_levels(case), A, c["dt"], c["Re"], c["Rem"], w0, b0, patch_form=form,
+                                        **relax)
     return _G[(case, form)]
 
 
@@ -145,7 +156,10 @@ def test_sweep_each_level(case, form):
         say(f"[mhd-sweep] case={case} form={form} level={lev}")
         k = to_dev(k0)
         g.irk_mhd_sweep(lev, to_dev(F), k)
-        ref = H.smoothers[lev].sweep(F, k0, J)
+        if CASES[case].get("cheb"):
+            ref = H.smoothers[lev].chebyshev(F, k0, J, 1, 2.0, 10.0)
+        else:
+            ref = H.smoothers[lev].sweep(F, k0, J)
         err = relerr(to_host(k), ref)
         say(f"[mhd-sweep] case={case} form={form} level={lev} err={err:.2e}")
         assert err < 1e-11
