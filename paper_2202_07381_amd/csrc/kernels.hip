@@ -56,6 +56,8 @@ const StageBasis<float>& basis_of<float>(const DevLevel& L) { return L.sb32; }
 // kernels read them with ordinary loads there and with non-temporal loads on the
 // large levels, whose factors stream through once per application.
 constexpr int64_t kSmallPatches = 8192;
+// Residual slices below which each slice is split between two wavefronts (k_residual_sell)
+constexpr int64_t kSplitSlices = 4096;
 
 // ------------------------------------------------------------------------ residual
 template <int D, int R, typename T>
@@ -71,11 +73,16 @@ __global__ __launch_bounds__(kBlock) void k_residual(
                              bt_val, dtA, F, x, y);
 }
 
-// Same residual from the sliced operator copies: one wavefront per slice of 64 rows
-// (velocity slices first, then vertex slices), lane = row, entries of the slice read
-// column-major (coalesced indices and values), kSellUnroll entries' gathers in flight
-// per lane (4: more lowered occupancy and measured slower on every level).
-template <int D, int R, typename T, int kSellUnroll>
+// Same residual from the sliced operator copies: NW wavefronts per slice of 64 rows
+// (velocity slices first, then vertex slices), lane = row.  Wavefront h of a slice takes
+// its entries k = h, h + NW, ..., each read column-major (coalesced indices and values),
+// with kSellUnroll entries' gathers in flight per lane (4: more lowered occupancy and
+// measured slower on every level); with NW = 2 the odd wavefront's partial sums reach the
+// even one through LDS.  Two wavefronts per slice halve each lane's chain of dependent
+// gathers and double the wavefronts in flight, which pays on levels with too few slices
+// to fill the chip (128 x 128 and below: 17.6 -> 14.1 us at 128 x 128, 12.4 -> 8.9 us at
+// 64 x 64) but not on the 256 x 256 level (47.3 -> 49.4 us).
+template <int D, int R, typename T, int kSellUnroll, int NW>
 __global__ __launch_bounds__(256) void k_residual_sell(
     int64_t nfree, int64_t nv, int64_t offV, int64_t nsu, int64_t nsp, const int32_t* __restrict__ su_off,
     const int32_t* __restrict__ su_w, const int32_t* __restrict__ su_col, const T* __restrict__ uM,
@@ -84,29 +91,34 @@ __global__ __launch_bounds__(256) void k_residual_sell(
     const int32_t* __restrict__ sp_w, const int32_t* __restrict__ sp_col, const T* __restrict__ pBt,
     Coef<T> dtA, const T* __restrict__ F, const T* __restrict__ x, T* __restrict__ y) {
   constexpr int DR = D * R;
+  constexpr int64_t kStride = 64 * NW;  // from this wavefront's entry to its next
+  constexpr int kSlices = 4 / NW;       // slices per workgroup of four wavefronts
+  __shared__ T part[NW == 2 ? kSlices : 1][NW == 2 ? 2 * DR : 1][64];
   const int lane = threadIdx.x & 63;
-  const int64_t sl = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
-  if (sl < nsu) {
-    const int64_t row = sl * 64 + lane;
-    T am[DR], al[DR];
+  const int half = (threadIdx.x >> 6) % NW;
+  const int pair = (threadIdx.x >> 6) / NW;
+  const int64_t sl = (int64_t)blockIdx.x * kSlices + pair;
+  T am[DR], al[DR];
 #pragma unroll
-    for (int q = 0; q < DR; ++q) am[q] = al[q] = T(0);
+  for (int q = 0; q < DR; ++q) am[q] = al[q] = T(0);
+  if (sl < nsu) {
     {
       const int w = su_w[sl];
-      const int64_t e0 = su_off[sl] + lane;
+      const int wh = w > half ? (w - half + NW - 1) / NW : 0;
+      const int64_t e0 = su_off[sl] + (int64_t)half * 64 + lane;
       // software pipelined: the next round's column indices are fetched while this
       // round's gathers are in flight
       int32_t jn[kSellUnroll];
-      if (kSellUnroll <= w)
+      if (kSellUnroll <= wh)
 #pragma unroll
-        for (int u = 0; u < kSellUnroll; ++u) jn[u] = su_col[e0 + (int64_t)u * 64];
+        for (int u = 0; u < kSellUnroll; ++u) jn[u] = su_col[e0 + (int64_t)u * kStride];
       int k = 0;
-      for (; k + kSellUnroll <= w; k += kSellUnroll) {
+      for (; k + kSellUnroll <= wh; k += kSellUnroll) {
         int32_t j[kSellUnroll];
         T m[kSellUnroll], l[kSellUnroll], xv[kSellUnroll][DR];
 #pragma unroll
         for (int u = 0; u < kSellUnroll; ++u) {
-          const int64_t e = e0 + (int64_t)(k + u) * 64;
+          const int64_t e = e0 + (int64_t)(k + u) * kStride;
           j[u] = jn[u];
           m[u] = uM[e];
           l[u] = uL[e];
@@ -115,9 +127,9 @@ __global__ __launch_bounds__(256) void k_residual_sell(
         for (int u = 0; u < kSellUnroll; ++u)
 #pragma unroll
           for (int q = 0; q < DR; ++q) xv[u][q] = x[(int64_t)j[u] * DR + q];
-        if (k + 2 * kSellUnroll <= w)
+        if (k + 2 * kSellUnroll <= wh)
 #pragma unroll
-          for (int u = 0; u < kSellUnroll; ++u) jn[u] = su_col[e0 + (int64_t)(k + kSellUnroll + u) * 64];
+          for (int u = 0; u < kSellUnroll; ++u) jn[u] = su_col[e0 + (int64_t)(k + kSellUnroll + u) * kStride];
 #pragma unroll
         for (int u = 0; u < kSellUnroll; ++u)
 #pragma unroll
@@ -126,8 +138,8 @@ __global__ __launch_bounds__(256) void k_residual_sell(
             al[q] += l[u] * xv[u][q];
           }
       }
-      for (; k < w; ++k) {
-        const int64_t e = e0 + (int64_t)k * 64;
+      for (; k < wh; ++k) {
+        const int64_t e = e0 + (int64_t)k * kStride;
         const int64_t jj = su_col[e];
         const T mm = uM[e], ll = uL[e];
 #pragma unroll
@@ -140,23 +152,24 @@ __global__ __launch_bounds__(256) void k_residual_sell(
     }
     {
       const int w = sb_w[sl];
-      const int64_t e0 = sb_off[sl] + lane;
+      const int wh = w > half ? (w - half + NW - 1) / NW : 0;
+      const int64_t e0 = sb_off[sl] + (int64_t)half * 64 + lane;
       int32_t jn[kSellUnroll];
-      if (kSellUnroll <= w)
+      if (kSellUnroll <= wh)
 #pragma unroll
-        for (int u = 0; u < kSellUnroll; ++u) jn[u] = sb_col[e0 + (int64_t)u * 64];
+        for (int u = 0; u < kSellUnroll; ++u) jn[u] = sb_col[e0 + (int64_t)u * kStride];
       int k = 0;
-      for (; k + kSellUnroll <= w; k += kSellUnroll) {
+      for (; k + kSellUnroll <= wh; k += kSellUnroll) {
         int32_t j[kSellUnroll];
         T pv[kSellUnroll][R], bv[kSellUnroll][D];
 #pragma unroll
         for (int u = 0; u < kSellUnroll; ++u) j[u] = jn[u];
-        if (k + 2 * kSellUnroll <= w)
+        if (k + 2 * kSellUnroll <= wh)
 #pragma unroll
-          for (int u = 0; u < kSellUnroll; ++u) jn[u] = sb_col[e0 + (int64_t)(k + kSellUnroll + u) * 64];
+          for (int u = 0; u < kSellUnroll; ++u) jn[u] = sb_col[e0 + (int64_t)(k + kSellUnroll + u) * kStride];
 #pragma unroll
         for (int u = 0; u < kSellUnroll; ++u) {
-          const int64_t e = e0 + (int64_t)(k + u) * 64;
+          const int64_t e = e0 + (int64_t)(k + u) * kStride;
 #pragma unroll
           for (int t = 0; t < R; ++t) pv[u][t] = x[offV + (int64_t)j[u] * R + t];
 #pragma unroll
@@ -169,8 +182,8 @@ __global__ __launch_bounds__(256) void k_residual_sell(
 #pragma unroll
             for (int t = 0; t < R; ++t) al[c * R + t] += bv[u][c] * pv[u][t];
       }
-      for (; k < w; ++k) {
-        const int64_t e = e0 + (int64_t)k * 64;
+      for (; k < wh; ++k) {
+        const int64_t e = e0 + (int64_t)k * kStride;
         const T* xp = x + offV + (int64_t)sb_col[e] * R;
         T pv[R];
 #pragma unroll
@@ -183,6 +196,69 @@ __global__ __launch_bounds__(256) void k_residual_sell(
         }
       }
     }
+  } else if (sl < nsu + nsp) {
+    // vertex rows: the R sums go to am[0 .. R)
+    const int64_t ps = sl - nsu;
+    const int w = sp_w[ps];
+    const int wh = w > half ? (w - half + NW - 1) / NW : 0;
+    const int64_t e0 = sp_off[ps] + (int64_t)half * 64 + lane;
+    int32_t jn[kSellUnroll];
+    if (kSellUnroll <= wh)
+#pragma unroll
+      for (int u = 0; u < kSellUnroll; ++u) jn[u] = sp_col[e0 + (int64_t)u * kStride];
+    int k = 0;
+    for (; k + kSellUnroll <= wh; k += kSellUnroll) {
+      int32_t j[kSellUnroll];
+      T xv[kSellUnroll][DR];
+#pragma unroll
+      for (int u = 0; u < kSellUnroll; ++u) j[u] = jn[u];
+#pragma unroll
+      for (int u = 0; u < kSellUnroll; ++u)
+#pragma unroll
+        for (int q = 0; q < DR; ++q) xv[u][q] = x[(int64_t)j[u] * DR + q];
+      if (k + 2 * kSellUnroll <= wh)
+#pragma unroll
+        for (int u = 0; u < kSellUnroll; ++u) jn[u] = sp_col[e0 + (int64_t)(k + kSellUnroll + u) * kStride];
+#pragma unroll
+      for (int u = 0; u < kSellUnroll; ++u) {
+        const int64_t e = e0 + (int64_t)(k + u) * kStride;
+#pragma unroll
+        for (int c = 0; c < D; ++c) {
+          const T bv = pBt[e * D + c];
+#pragma unroll
+          for (int t = 0; t < R; ++t) am[t] += bv * xv[u][c * R + t];
+        }
+      }
+    }
+    for (; k < wh; ++k) {
+      const int64_t e = e0 + (int64_t)k * kStride;
+      const T* xi = x + (int64_t)sp_col[e] * DR;
+#pragma unroll
+      for (int c = 0; c < D; ++c) {
+        const T bv = pBt[e * D + c];
+#pragma unroll
+        for (int t = 0; t < R; ++t) am[t] += bv * xi[c * R + t];
+      }
+    }
+  }
+  if constexpr (NW == 2) {
+    if (half) {
+#pragma unroll
+      for (int q = 0; q < DR; ++q) {
+        part[pair][q][lane] = am[q];
+        part[pair][DR + q][lane] = al[q];
+      }
+    }
+    __syncthreads();
+    if (half) return;
+#pragma unroll
+    for (int q = 0; q < DR; ++q) {
+      am[q] += part[pair][q][lane];
+      al[q] += part[pair][DR + q][lane];
+    }
+  }
+  if (sl < nsu) {
+    const int64_t row = sl * 64 + lane;
     if (row < nfree) {
 #pragma unroll
       for (int c = 0; c < D; ++c)
@@ -196,57 +272,13 @@ __global__ __launch_bounds__(256) void k_residual_sell(
         }
     }
   } else if (sl < nsu + nsp) {
-    const int64_t ps = sl - nsu;
-    const int64_t v = ps * 64 + lane;
-    T a[R];
-#pragma unroll
-    for (int t = 0; t < R; ++t) a[t] = T(0);
-    const int w = sp_w[ps];
-    const int64_t e0 = sp_off[ps] + lane;
-    int32_t jn[kSellUnroll];
-    if (kSellUnroll <= w)
-#pragma unroll
-      for (int u = 0; u < kSellUnroll; ++u) jn[u] = sp_col[e0 + (int64_t)u * 64];
-    int k = 0;
-    for (; k + kSellUnroll <= w; k += kSellUnroll) {
-      int32_t j[kSellUnroll];
-      T xv[kSellUnroll][DR];
-#pragma unroll
-      for (int u = 0; u < kSellUnroll; ++u) j[u] = jn[u];
-#pragma unroll
-      for (int u = 0; u < kSellUnroll; ++u)
-#pragma unroll
-        for (int q = 0; q < DR; ++q) xv[u][q] = x[(int64_t)j[u] * DR + q];
-      if (k + 2 * kSellUnroll <= w)
-#pragma unroll
-        for (int u = 0; u < kSellUnroll; ++u) jn[u] = sp_col[e0 + (int64_t)(k + kSellUnroll + u) * 64];
-#pragma unroll
-      for (int u = 0; u < kSellUnroll; ++u) {
-        const int64_t e = e0 + (int64_t)(k + u) * 64;
-#pragma unroll
-        for (int c = 0; c < D; ++c) {
-          const T bv = pBt[e * D + c];
-#pragma unroll
-          for (int t = 0; t < R; ++t) a[t] += bv * xv[u][c * R + t];
-        }
-      }
-    }
-    for (; k < w; ++k) {
-      const int64_t e = e0 + (int64_t)k * 64;
-      const T* xi = x + (int64_t)sp_col[e] * DR;
-#pragma unroll
-      for (int c = 0; c < D; ++c) {
-        const T bv = pBt[e * D + c];
-#pragma unroll
-        for (int t = 0; t < R; ++t) a[t] += bv * xi[c * R + t];
-      }
-    }
+    const int64_t v = (sl - nsu) * 64 + lane;
     if (v < nv) {
 #pragma unroll
       for (int s = 0; s < R; ++s) {
         T acc = T(0);
 #pragma unroll
-        for (int t = 0; t < R; ++t) acc += dtA.v[s * R + t] * a[t];
+        for (int t = 0; t < R; ++t) acc += dtA.v[s * R + t] * am[t];
         const int64_t o = offV + v * R + s;
         y[o] = F ? F[o] - acc : acc;
       }
@@ -1721,8 +1753,18 @@ template <typename T>
 hipError_t residual(const DevLevel& L, const DevOps<T>& ops, const double* A, double dt,
                     const T* F, const T* x, T* y, hipStream_t s) {
   const int64_t nsl = L.nsl_u + L.nsl_p;
+  // two wavefronts per slice where one per slice would leave the chip short of
+  // wavefronts (fewer than four per SIMD: 256 CUs x 4 SIMDs x 4)
+  if (nsl < kSplitSlices) {
+    const unsigned g = (unsigned)((nsl + 1) / 2);
+    IRK_DISPATCH_DR(L.dim, L.r, (k_residual_sell<DD, RR, T, 4, 2><<<dim3(g), dim3(256), 0, s>>>(
+                                    L.nfree, L.nv, L.offV, L.nsl_u, L.nsl_p, L.su_off, L.su_w, L.su_col, ops.u_M,
+                                    ops.u_L, L.sb_off, L.sb_w, L.sb_col, ops.u_B, L.sp_off, L.sp_w, L.sp_col,
+                                    ops.p_Bt, scaled<T, RR>(A, dt), F, x, y)));
+    return hipGetLastError();
+  }
   const unsigned g = (unsigned)((nsl + 3) / 4);
-  IRK_DISPATCH_DR(L.dim, L.r, (k_residual_sell<DD, RR, T, 4><<<dim3(g), dim3(256), 0, s>>>(
+  IRK_DISPATCH_DR(L.dim, L.r, (k_residual_sell<DD, RR, T, 4, 1><<<dim3(g), dim3(256), 0, s>>>(
                                   L.nfree, L.nv, L.offV, L.nsl_u, L.nsl_p, L.su_off, L.su_w, L.su_col, ops.u_M,
                                   ops.u_L, L.sb_off, L.sb_w, L.sb_col, ops.u_B, L.sp_off, L.sp_w, L.sp_col,
                                   ops.p_Bt, scaled<T, RR>(A, dt), F, x, y)));
