@@ -41,6 +41,15 @@ from .stage import StageSystem
 from .transfer import interpolation_matrices, stage_prolongation
 from .vanka import VankaSmoother, patch_dofs
 
+# Optional callable(str) told when each stage of a hierarchy's construction finishes (for
+# callers that must show progress during a long setup); it does not affect the results.
+PROGRESS = None
+
+
+def _progress(msg):
+    if PROGRESS is not None:
+        PROGRESS(msg)
+
 
 class Hierarchy:
     def __init__(self, mesh_levels, A, dt, nu, wind=None, omega=0.5, weighted=True, pre=2, post=2,
@@ -67,6 +76,7 @@ class Hierarchy:
         for th in self.spaces:
             wn = th.interpolate(wind) if wind is not None else None
             self.systems.append(StageSystem(th, self.A, dt, nu, wn))
+            _progress(f"oracle: level with {th.ncells} cells assembled")
         self.dim = self.spaces[0].dim
         self.P = [None]
         for lc in range(len(self.spaces) - 1):
@@ -82,6 +92,7 @@ class Hierarchy:
         for lev in range(1, len(self.spaces)):
             pat = patch_dofs(self.spaces[lev], self.r)
             self.smoothers.append(VankaSmoother(self.ops[lev], pat, omega, weighted, dtype))
+            _progress(f"oracle: patch inverses of level {lev} computed")
         # coarse LU with one pinned pressure per stage
         s0 = self.systems[0]
         Jc = self.ops[0].toarray()

@@ -23,9 +23,12 @@ CASES = {
     # patches (above the count from which the library streams patch factors with
     # non-temporal loads), 440,073 unknowns; its oracle takes about half a minute
     "s128": (2, 4, 6, "radauIIA", 3, 1e-2, 1.0, None),
+    # the benchmark workload itself: 256^2, 7 levels, 1,764,873 unknowns; its oracle needs
+    # about 35 GB and a few minutes (test_gpu_parity_256.py, run on request)
+    "s256": (2, 4, 7, "radauIIA", 3, 1e-2, 1.0, None),
 }
 # cases whose oracle is too slow for the per-step sweeps over every level
-LARGE = {"s128"}
+LARGE = {"s128", "s256"}
 SMALL = [c for c in CASES if c not in LARGE]
 # cases on the crossed mesh of Sec. 5.1 (four triangles per quad) instead of the
 # diagonal split
