@@ -571,6 +571,7 @@ irk_status ensure_krylov(irk_mg* h, int restart) {
     h->allocations.erase(std::remove(h->allocations.begin(), h->allocations.end(), (void*)h->kv), h->allocations.end());
     h->allocations.erase(std::remove(h->allocations.begin(), h->allocations.end(), (void*)h->kz), h->allocations.end());
     h->kv = h->kz = nullptr;
+    h->krylov_cap = 0;  // no usable basis until the new one is in place
   }
   CHK(dalloc(h, &h->kv, (size_t)(restart + 1) * N));
   CHK(dalloc(h, &h->kz, (size_t)restart * N));

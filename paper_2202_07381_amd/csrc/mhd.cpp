@@ -233,6 +233,7 @@ irk_status precondition(irk_mhd* h, const double* v, double* z, hipStream_t s) {
 irk_status ensure_krylov(irk_mhd* h, int restart) {
   if (restart <= h->restart_cap) return IRK_OK;
   const int64_t N = h->dev[h->nlevels - 1].N;
+  h->restart_cap = 0;  // no usable basis until the new one is in place
   for (double** p : {&h->kv, &h->kz}) {
     if (*p) {
       h->allocations.erase(std::find(h->allocations.begin(), h->allocations.end(), (void*)*p));
