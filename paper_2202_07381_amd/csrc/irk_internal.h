@@ -503,6 +503,9 @@ int ritz_finish(int steps, const double* Hh, double* H, double* ritz_re, double*
 size_t ritz_partials_bytes();
 // stored failure (IRK_* code and message) for the calling thread
 int fail_with(int code, const std::string& msg);
+// IRK_MG_POISON_ALLOC set (and not "0"): every allocation of a handle is filled with the
+// byte 0xFF (NaN) before first use
+bool poison_requested();
 
 // Element helpers of the P2 assembly, for the other model assemblies: barycentric
 // gradients ((dim+1) x dim) and measure of cell c; barycentric coordinates of x in

@@ -825,6 +825,7 @@ irk_status irk::ritz_finish(int steps, const double* Hh, double* H, double* ritz
 int irk::ensure_krylov_ws(irk_mg* h, int restart) { return ensure_krylov(h, restart); }
 void irk::set_error(const std::string& msg) { g_err = msg; }
 irk_status irk::fail_with(irk_status code, const std::string& msg) { return fail(code, msg); }
+bool irk::poison_requested() { return poison_allocations(); }
 
 // =========================================================================== ABI
 extern "C" {

@@ -99,6 +99,7 @@ irk_status dalloc(irk_mhd* h, T** p, size_t n) {
     return fail(e == hipErrorOutOfMemory ? IRK_ENOMEM : IRK_EHIP,
                 "hipMalloc of " + std::to_string(n * sizeof(T)) + " bytes failed");
   h->allocations.push_back(*p);
+  if (poison_requested()) HIPCHK(hipMemset(*p, 0xFF, n * sizeof(T)));
   return IRK_OK;
 }
 

@@ -83,3 +83,34 @@ def test_solve_on_poisoned_memory(poisoned, case, smoother, precision):
     g.irk_mg_vcycle(to_dev(F), z)
     assert np.all(np.isfinite(to_host(z)))
     g.close()
+
+
+@pytest.mark.parametrize("case", ["mx", "mc"])
+def test_mhd_solve_on_poisoned_memory(poisoned, case):
+    """The linearised MHD solver (damped sweeps and Chebyshev relaxation) on poisoned
+    memory: FGMRES equal to the oracle's, equal iterations, 1e-10."""
+    from oracle.fgmres import fgmres
+    from test_gpu_mhd import CASES as MHD, _levels, _state, oracle_of as mhd_oracle
+    from oracle.tableau import tableau
+    from paper_2202_07381_amd import irkmg
+
+    c = MHD[case]
+    A, _, _ = tableau(c["fam"], c["r"])
+    w0, b0 = _state(case)
+    relax = dict(pre=3, post=3, weighting=0, smoother=1, interval=(2.0, 10.0)) if c.get("cheb") else {}
+    say(f"[poison] mhd case={case}")
+    g = irkmg.IrkMHD(_levels(case), A, c["dt"], c["Re"], c["Rem"], w0, b0, **relax)
+    H = mhd_oracle(case)
+    S = H.systems[-1]
+    F = S.J @ np.random.default_rng(27).standard_normal(S.n)
+    k = torch.zeros(F.size, dtype=torch.float64, device="cuda")
+    info = g.irk_mhd_fgmres_solve(to_dev(F), k, rtol=1e-8, maxit=200, restart=30)
+    xo, io = fgmres(S.apply, H.vcycle, F, np.zeros_like(F), 1e-8, 200, 30, project=S.project_pressure_mean)
+    x = to_host(k)
+    assert np.all(np.isfinite(x))
+    assert info["iterations"] == io.iterations
+    assert relerr(x, xo) < 1e-10
+    z = torch.zeros(F.size, dtype=torch.float64, device="cuda")
+    g.irk_mhd_vcycle(to_dev(F), z)
+    assert relerr(to_host(z), H.vcycle(F)) < 1e-11
+    g.close()
