@@ -317,6 +317,13 @@ struct Handle {
   std::vector<int64_t*> nw_off;
   double *nw_cinv = nullptr, *nw_cmat = nullptr, *nw_ctmp = nullptr, *nw_colk = nullptr;
   int64_t* nw_swp = nullptr;
+  // their assembly on the GPU: per level the element data of ns_cell_data, the stiffness
+  // values on the scalar pattern, the stage velocities at the P2 nodes ((node dim + c) r
+  // + s; the finest level's are ns_U) and, below the finest level, the fine vertex of each
+  // P2 node; the reference tensor int phi_e phi_a d_k phi_b / |T|
+  std::vector<double*> nwa_geo, nwa_K1, nwa_U;
+  std::vector<int32_t*> nwa_cn, nwa_cf, nwa_inc_ptr, nwa_inc, nwa_c2f;
+  double* nwa_C = nullptr;
 };
 
 // ------------------------------------------------------------------------ launchers
@@ -477,6 +484,17 @@ hipError_t ns_stage_values(int64_t nn, int dim, int r, int64_t nfree, const int3
 hipError_t ns_element(int dim, const NsElemArgs& a, hipStream_t s);
 hipError_t ns_gather(int64_t nfree, int dim, int r, const int32_t* inc_ptr, const int32_t* inc,
                      const double* elem, double scale, double* y, hipStream_t s);
+// Per-stage velocity blocks of the Newton Jacobian on one level (assemble_newton_block on
+// the device, every stage at once): nw[(p r + s) dim^2 + c dim + e] = (nu K + C(U_s))
+// delta_ce + R(U_s)_ce for every entry p of the scalar pattern; geo / cn / cf / inc_ptr /
+// inc from ns_cell_data, K1 the stiffness values, Cref fe_p2_conv_tensor, U the stage
+// velocities ((node dim + c) r + s).  One thread per (free row, stage), which owns its
+// row's entries; the row's cells are summed in incidence order.
+hipError_t newton_blocks(int dim, int r, int64_t nfree, const int32_t* s_ptr, const int32_t* s_col, const double* K1,
+                         double nu, const double* geo, const int32_t* cn, const int32_t* cf, const int32_t* inc_ptr,
+                         const int32_t* inc, const double* Cref, const double* U, double* nw, hipStream_t s);
+// Uc[n w + q] = Uf[c2f[n] w + q] for n < nc, q < w (injection at the coarse P2 nodes)
+hipError_t inject_nodal(int64_t nc, int w, const int32_t* c2f, const double* Uf, double* Uc, hipStream_t s);
 }  // namespace k
 
 }  // namespace irk
@@ -522,4 +540,6 @@ void fe_transpose_csr(int64_t nrows, int64_t ncols, const std::vector<int32_t>& 
                       std::vector<double>& tval);
 void fe_p2_lam_moments(int dim, double* out);
 const double* fe_p2_grad_grad(int dim);
+// int_T phi_e phi_a d_k phi_b / |T| indexed [((e nloc + a) nloc + b)(dim+1) + k]
+const double* fe_p2_conv_tensor(int dim);
 }  // namespace irk

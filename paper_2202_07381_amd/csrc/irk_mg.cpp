@@ -461,46 +461,50 @@ irk_status nw_build(irk_mg* h, hipStream_t s) {
     CHK(dalloc(h, &h->nw_ctmp, (size_t)N0 * N0));
     CHK(dalloc(h, &h->nw_colk, (size_t)N0));
     CHK(dalloc(h, &h->nw_swp, (size_t)N0));
+    // element data for the assembly of the blocks on the device
+    for (auto* v : {&h->nwa_geo, &h->nwa_K1, &h->nwa_U}) v->assign(nl, nullptr);
+    for (auto* v : {&h->nwa_cn, &h->nwa_cf, &h->nwa_inc_ptr, &h->nwa_inc, &h->nwa_c2f}) v->assign(nl, nullptr);
+    for (int l = 0; l < nl; ++l) {
+      const HostLevel& H = h->host[l];
+      std::vector<double> geo;
+      std::vector<int32_t> cn, cf, ip, inc;
+      irk::ns_cell_data(H, geo, cn, cf, ip, inc);
+      CHK(upload(h, &h->nwa_geo[l], geo, s));
+      CHK(upload(h, &h->nwa_cn[l], cn, s));
+      CHK(upload(h, &h->nwa_cf[l], cf, s));
+      CHK(upload(h, &h->nwa_inc_ptr[l], ip, s));
+      CHK(upload(h, &h->nwa_inc[l], inc, s));
+      CHK(upload(h, &h->nwa_K1[l], H.s_K1, s));
+      if (l < top) {
+        CHK(dalloc(h, &h->nwa_U[l], (size_t)H.nn * d * r));
+        CHK(upload(h, &h->nwa_c2f[l], h->host[l + 1].coarse_node_to_fine_vertex, s));
+      }
+    }
+    const int nloc = d == 2 ? 6 : 10;
+    const double* C = irk::fe_p2_conv_tensor(d);
+    CHK(upload(h, &h->nwa_C, std::vector<double>(C, C + nloc * nloc * nloc * (d + 1)), s));
     h->nw_ready = true;
   }
-  // stage velocities per level and stage, nodal: U[l][(i nn + node) d + c]
-  std::vector<std::vector<double>> U(nl);
-  {
-    const HostLevel& F = h->host[top];
-    std::vector<double> Uf((size_t)F.nn * d * r);
-    HIPCHK(hipMemcpyAsync(Uf.data(), h->ns_U, Uf.size() * sizeof(double), hipMemcpyDeviceToHost, s));
-    HIPCHK(hipStreamSynchronize(s));
-    U[top].resize(Uf.size());
-    for (int64_t n = 0; n < F.nn; ++n)
-      for (int c = 0; c < d; ++c)
-        for (int i = 0; i < r; ++i) U[top][((size_t)i * F.nn + n) * d + c] = Uf[((size_t)n * d + c) * r + i];
-  }
-  for (int l = top - 1; l >= 0; --l) {
-    const HostLevel& C = h->host[l];
-    const HostLevel& F = h->host[l + 1];
-    U[l].resize((size_t)C.nn * d * r);
-    for (int i = 0; i < r; ++i)
-      for (int64_t n = 0; n < C.nn; ++n)
-        for (int c = 0; c < d; ++c)
-          U[l][((size_t)i * C.nn + n) * d + c] =
-              U[l + 1][((size_t)i * F.nn + F.coarse_node_to_fine_vertex[n]) * d + c];
-  }
+  // stage velocities on every level: the finest level's at its P2 nodes (ns_U), injected
+  // at the coarser levels' P2 nodes, which are vertices of the next finer level
+  h->nwa_U[top] = h->ns_U;
+  for (int l = top - 1; l >= 0; --l)
+    HIPCHK(k::inject_nodal(h->host[l].nn, d * r, h->nwa_c2f[l], h->nwa_U[l + 1], h->nwa_U[l], s));
   HIPCHK(hipMemsetAsync(h->flag, 0, sizeof(int), s));
   std::vector<double> Jc;
   double scale = 0;
   for (int l = 0; l < nl; ++l) {
     const HostLevel& H = h->host[l];
-    const size_t nnz = H.s_col.size();
-    std::vector<double> vals(nnz * r * dd), blk(nnz * dd);
-    for (int i = 0; i < r; ++i) {
-      std::fill(blk.begin(), blk.end(), 0.0);
-      irk::assemble_newton_block(H, h->nu, &U[l][(size_t)i * H.nn * d], blk.data());
-      for (size_t p = 0; p < nnz; ++p)
-        for (int q = 0; q < dd; ++q) vals[(p * r + i) * dd + q] = blk[p * dd + q];
+    HIPCHK(k::newton_blocks(d, r, H.nfree, h->dev[l].s_ptr, h->dev[l].s_col, h->nwa_K1[l], h->nu, h->nwa_geo[l],
+                            h->nwa_cn[l], h->nwa_cf[l], h->nwa_inc_ptr[l], h->nwa_inc[l], h->nwa_C, h->nwa_U[l],
+                            h->nw_vals[l], s));
+    if (l == 0) {
+      // the dense coarse operator is built on the host from the coarsest level's blocks
+      std::vector<double> vals(H.s_col.size() * r * dd);
+      HIPCHK(hipMemcpyAsync(vals.data(), h->nw_vals[0], vals.size() * sizeof(double), hipMemcpyDeviceToHost, s));
+      HIPCHK(hipStreamSynchronize(s));
+      irk::coarse_matrix_newton(H, r, h->A, h->dt, vals.data(), Jc, &scale);
     }
-    HIPCHK(hipMemcpyAsync(h->nw_vals[l], vals.data(), vals.size() * sizeof(double), hipMemcpyHostToDevice, s));
-    if (l == 0) irk::coarse_matrix_newton(H, r, h->A, h->dt, vals.data(), Jc, &scale);
-    HIPCHK(hipStreamSynchronize(s));  // vals is released at the end of the iteration
     if (l >= 1) {
       DevLevel V = newton_view(h, l);
       if (V.max_nloc > 1024)

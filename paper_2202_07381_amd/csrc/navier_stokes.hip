@@ -263,6 +263,104 @@ __global__ __launch_bounds__(256) void k_ns_stage_values(int64_t nn, int D, int 
 
 inline unsigned blocks_for(int64_t n, int bs) { return (unsigned)((n + bs - 1) / bs); }
 
+// The Newton Jacobian's per-stage velocity blocks, one thread per (free row, stage): the
+// thread owns its row's pattern entries, visits the cells around the row's node in
+// incidence order and adds, for each free column node b of the cell, the convection
+// int phi_a (U . grad phi_b) on the diagonal component blocks and the reaction
+// int phi_a phi_b d_e U_c on block (c, e), by the exact reference tensor; the stiffness
+// nu K on the diagonal blocks last.
+template <int D>
+__global__ __launch_bounds__(256) void k_newton_blocks(int r, int64_t nfree, const int32_t* __restrict__ s_ptr,
+                                                       const int32_t* __restrict__ s_col,
+                                                       const double* __restrict__ K1, double nu,
+                                                       const double* __restrict__ geo,
+                                                       const int32_t* __restrict__ cn,
+                                                       const int32_t* __restrict__ cf,
+                                                       const int32_t* __restrict__ inc_ptr,
+                                                       const int32_t* __restrict__ inc,
+                                                       const double* __restrict__ Cref,
+                                                       const double* __restrict__ U, double* __restrict__ nw) {
+  constexpr int NL = Elem<D>::NL, NB = D + 1, DD = D * D, PER = NB * D + 1;
+  const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (t >= nfree * r) return;
+  const int64_t ia = t / r;
+  const int i = (int)(t - ia * r);
+  const int32_t p0 = s_ptr[ia], p1 = s_ptr[ia + 1];
+  for (int32_t p = p0; p < p1; ++p)
+#pragma unroll
+    for (int q = 0; q < DD; ++q) nw[((int64_t)p * r + i) * DD + q] = 0.0;
+  for (int32_t q = inc_ptr[ia]; q < inc_ptr[ia + 1]; ++q) {
+    const int32_t e = inc[q];
+    const int64_t c = e / NL;
+    const int a = e - (int)c * NL;
+    const double* g = geo + c * PER;
+    const double vol = g[NB * D];
+    double Uf[NL][D], wg[NL][NB];
+#pragma unroll
+    for (int f = 0; f < NL; ++f) {
+      const int64_t node = cn[c * NL + f];
+#pragma unroll
+      for (int cc = 0; cc < D; ++cc) Uf[f][cc] = U[(node * D + cc) * r + i];
+#pragma unroll
+      for (int k = 0; k < NB; ++k) {
+        double sum = 0.0;
+#pragma unroll
+        for (int cc = 0; cc < D; ++cc) sum += Uf[f][cc] * g[k * D + cc];
+        wg[f][k] = sum;
+      }
+    }
+    for (int b = 0; b < NL; ++b) {
+      const int32_t ib = cf[c * NL + b];
+      if (ib < 0) continue;
+      double ce = 0.0;
+#pragma unroll
+      for (int f = 0; f < NL; ++f)
+#pragma unroll
+        for (int k = 0; k < NB; ++k) ce += wg[f][k] * Cref[((f * NL + a) * NL + b) * NB + k];
+      double Tg[NL][D];
+#pragma unroll
+      for (int f = 0; f < NL; ++f)
+#pragma unroll
+        for (int ee = 0; ee < D; ++ee) {
+          double sum = 0.0;
+#pragma unroll
+          for (int k = 0; k < NB; ++k) sum += g[k * D + ee] * Cref[((a * NL + b) * NL + f) * NB + k];
+          Tg[f][ee] = sum;
+        }
+      int32_t lo = p0, hi = p1;  // the column ib in the row's sorted pattern
+      while (lo < hi) {
+        const int32_t mid = (lo + hi) >> 1;
+        if (s_col[mid] < ib) lo = mid + 1;
+        else hi = mid;
+      }
+      double* o = nw + ((int64_t)lo * r + i) * DD;
+#pragma unroll
+      for (int cc = 0; cc < D; ++cc) {
+        o[cc * D + cc] += vol * ce;
+#pragma unroll
+        for (int ee = 0; ee < D; ++ee) {
+          double tt = 0.0;
+#pragma unroll
+          for (int f = 0; f < NL; ++f) tt += Uf[f][cc] * Tg[f][ee];
+          o[cc * D + ee] += vol * tt;
+        }
+      }
+    }
+  }
+  for (int32_t p = p0; p < p1; ++p)
+#pragma unroll
+    for (int cc = 0; cc < D; ++cc) nw[((int64_t)p * r + i) * DD + cc * D + cc] += nu * K1[p];
+}
+
+__global__ __launch_bounds__(256) void k_inject_nodal(int64_t n, int w, const int32_t* __restrict__ c2f,
+                                                      const double* __restrict__ Uf, double* __restrict__ Uc) {
+  const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (t >= n) return;
+  const int64_t node = t / w;
+  const int q = (int)(t - node * w);
+  Uc[t] = Uf[(int64_t)c2f[node] * w + q];
+}
+
 }  // namespace
 
 hipError_t ns_stage_values(int64_t nn, int dim, int r, int64_t nfree, const int32_t* free_of_node,
@@ -281,6 +379,27 @@ hipError_t ns_element(int dim, const NsElemArgs& a, hipStream_t s) {
     k_ns_element<2><<<blocks_for(n, 256), 256, 0, s>>>(a);
   else
     k_ns_element<3><<<blocks_for(n, 256), 256, 0, s>>>(a);
+  return hipGetLastError();
+}
+
+hipError_t newton_blocks(int dim, int r, int64_t nfree, const int32_t* s_ptr, const int32_t* s_col, const double* K1,
+                         double nu, const double* geo, const int32_t* cn, const int32_t* cf, const int32_t* inc_ptr,
+                         const int32_t* inc, const double* Cref, const double* U, double* nw, hipStream_t s) {
+  const int64_t n = nfree * r;
+  if (n == 0) return hipSuccess;
+  if (dim == 2)
+    k_newton_blocks<2><<<blocks_for(n, 256), 256, 0, s>>>(r, nfree, s_ptr, s_col, K1, nu, geo, cn, cf, inc_ptr, inc,
+                                                         Cref, U, nw);
+  else
+    k_newton_blocks<3><<<blocks_for(n, 256), 256, 0, s>>>(r, nfree, s_ptr, s_col, K1, nu, geo, cn, cf, inc_ptr, inc,
+                                                         Cref, U, nw);
+  return hipGetLastError();
+}
+
+hipError_t inject_nodal(int64_t nc, int w, const int32_t* c2f, const double* Uf, double* Uc, hipStream_t s) {
+  const int64_t n = nc * w;
+  if (n == 0) return hipSuccess;
+  k_inject_nodal<<<blocks_for(n, 256), 256, 0, s>>>(n, w, c2f, Uf, Uc);
   return hipGetLastError();
 }
 

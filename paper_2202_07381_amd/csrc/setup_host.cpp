@@ -1156,4 +1156,5 @@ void fe_p2_lam_moments(int dim, double* out) {
     for (int i = 0; i < nb; ++i) out[a * nb + i] = integrate(mul(basis(dim, a), lam_pow(i, 1, 1.0)), dim);
 }
 const double* fe_p2_grad_grad(int dim) { return ref_tensors(dim).S.data(); }
+const double* fe_p2_conv_tensor(int dim) { return ref_tensors(dim).C.data(); }
 }  // namespace irk
