@@ -381,25 +381,16 @@ __global__ __launch_bounds__(kBlock) void k_residual_newton(
 // Newton Jacobian's per-stage dim x dim blocks, as for k_residual_newton) the
 // velocity-velocity entries are delta_st delta_ce M_ab + dt a_st N_s[ab]_ce instead of
 // the Kronecker delta_st M_ab + dt a_st L_ab on each component.
+// The patch matrix, row-major with stride n, zeroed and filled by the workgroup (ends
+// with a barrier).  With nw (the Newton Jacobian's per-stage dim x dim blocks, as for
+// k_residual_newton) the velocity-velocity entries are delta_st delta_ce M_ab + dt a_st
+// N_s[ab]_ce instead of the Kronecker delta_st M_ab + dt a_st L_ab on each component.
 template <int D, int R, typename T>
-__global__ __launch_bounds__(kBlock) void k_patch_factor(
-    int64_t npatch, const int32_t* __restrict__ pn_ptr, const int32_t* __restrict__ pvv_ptr,
-    const int32_t* __restrict__ pvv, const int32_t* __restrict__ pvp,
-    const int32_t* __restrict__ p_ld, const int64_t* __restrict__ p_inv_off,
-    const T* __restrict__ sM, const T* __restrict__ sL, const T* __restrict__ b_val,
-    Coef<T> dtA, T* __restrict__ inv, int* __restrict__ fail, int64_t p0, int64_t off0,
-    const T* __restrict__ nw) {
-  extern __shared__ unsigned char smem_raw[];
-  const int64_t p = p0 + blockIdx.x;
-  if (p >= npatch) return;
-  const int nn = pn_ptr[p + 1] - pn_ptr[p];
+__device__ void assemble_patch(int64_t p, int nn, int n, const int32_t* __restrict__ pn_ptr,
+                               const int32_t* __restrict__ pvv_ptr, const int32_t* __restrict__ pvv,
+                               const int32_t* __restrict__ pvp, const T* __restrict__ sM, const T* __restrict__ sL,
+                               const T* __restrict__ b_val, const Coef<T>& dtA, const T* __restrict__ nw, T* Am) {
   const int sb = D * nn + 1;  // per-stage block size
-  const int n = R * sb;
-  T* Am = reinterpret_cast<T*>(smem_raw);
-  T* colk = Am + (size_t)n * n;
-  int* perm = reinterpret_cast<int*>(colk + n);
-  __shared__ int s_piv;
-  __shared__ T s_best;
   const int tid = threadIdx.x;
   for (int e = tid; e < n * n; e += blockDim.x) Am[e] = T(0);
   __syncthreads();
@@ -441,6 +432,29 @@ __global__ __launch_bounds__(kBlock) void k_patch_factor(
     }
   }
   __syncthreads();
+}
+
+// One workgroup per patch, matrix in dynamic LDS (row-major n x n).
+template <int D, int R, typename T>
+__global__ __launch_bounds__(kBlock) void k_patch_factor(
+    int64_t npatch, const int32_t* __restrict__ pn_ptr, const int32_t* __restrict__ pvv_ptr,
+    const int32_t* __restrict__ pvv, const int32_t* __restrict__ pvp,
+    const int32_t* __restrict__ p_ld, const int64_t* __restrict__ p_inv_off,
+    const T* __restrict__ sM, const T* __restrict__ sL, const T* __restrict__ b_val,
+    Coef<T> dtA, T* __restrict__ inv, int* __restrict__ fail, int64_t p0, int64_t off0,
+    const T* __restrict__ nw) {
+  extern __shared__ unsigned char smem_raw[];
+  const int64_t p = p0 + blockIdx.x;
+  if (p >= npatch) return;
+  const int nn = pn_ptr[p + 1] - pn_ptr[p];
+  const int n = R * (D * nn + 1);
+  T* Am = reinterpret_cast<T*>(smem_raw);
+  T* colk = Am + (size_t)n * n;
+  int* perm = reinterpret_cast<int*>(colk + n);
+  __shared__ int s_piv;
+  __shared__ T s_best;
+  const int tid = threadIdx.x;
+  assemble_patch<D, R, T>(p, nn, n, pn_ptr, pvv_ptr, pvv, pvp, sM, sL, b_val, dtA, nw, Am);
   // in-place Gauss--Jordan with partial pivoting (ties -> smallest row index)
   for (int kk = 0; kk < n; ++kk) {
     if (tid < 64) {
@@ -509,6 +523,232 @@ __global__ __launch_bounds__(kBlock) void k_patch_factor(
     const int j = e / ld, i = e - j * ld;
     out[e] = i < n ? Am[i * n + j] : T(0);
   }
+}
+
+// Register-tiled Gauss--Jordan for mid-sized patches (64 < n <= 32 TM, TM <= 4): the
+// matrix is assembled in LDS, then each of 1024 threads keeps a TM x TM tile of it in
+// registers (wavefront w holds column tiles 2w and 2w + 1; lane l the row tile l mod 32
+// of column tile 2w + l / 32).  Pivoting is implicit, the exchange form of Gauss--Jordan
+// without row swaps: at step k the unused row p with the largest |a_pk| (smallest index
+// on ties) becomes the pivot row of column k, so every register keeps its matrix
+// position.  Row p is kept unscaled, multiplied by a_pk (its multiplier in step k is 0
+// and its column-k entry becomes 1); the updates are linear in the row, so it stays so
+// scaled, and it is divided by a_pk once, when the inverse is written.  The wavefront
+// owning the next column publishes that column, its pivot and the reciprocal to LDS
+// during the update, and one barrier separates the steps; the pivot row reaches the
+// other lanes of its wavefront by reads of one lane.  At the end entry
+// (i, j) of the exchanged matrix is entry (step at which row i was the pivot, pivot row
+// of step j) of the inverse.
+constexpr int kRtThreads = 1024;
+// A thread's tile, entry (a, c) at a * TM + c: one vector value of at most 1024 bits, so
+// that selecting a column by a wavefront-uniform index stays in registers (indexed
+// register moves).
+template <typename T, int TM>
+struct RtTile {
+  static_assert(TM * TM <= 16, "tile of at most 16 entries");
+  typedef T type __attribute__((ext_vector_type(16)));
+};
+
+// Cross-lane moves for the register-tiled kernel: DPP lane permutations within rows of 16
+// lanes (quad_perm [1,0,3,2] and [2,3,0,1], row_half_mirror, row_mirror) and reads of
+// one lane (uniform lane index).
+template <int CTRL>
+__device__ __forceinline__ double dpp_mov(double v) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_mov_dpp((int)b, CTRL, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_mov_dpp((int)(b >> 32), CTRL, 0xF, 0xF, false);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+}
+template <int CTRL>
+__device__ __forceinline__ float dpp_mov(float v) {
+  return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), CTRL, 0xF, 0xF, false));
+}
+__device__ __forceinline__ double lane_read(double v, int l) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_readlane((int)b, l);
+  const int hi = __builtin_amdgcn_readlane((int)(b >> 32), l);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+}
+__device__ __forceinline__ float lane_read(float v, int l) {
+  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), l));
+}
+
+// Column q of the register tiles of k_patch_factor_rt and its pivot (largest |a_iq| over
+// the rows not yet used, smallest index on ties), by the wavefront that owns the
+// column: the column into colbuf with the pivot row's entry 0, the pivot row into *piv
+// (-1 for a zero or missing pivot) and its reciprocal into *ipv.  The largest magnitude
+// comes from a butterfly of lane permutations over each row of 16 lanes and the two
+// rows of the column's half, the pivot from the first lane holding it (lanes hold
+// increasing rows).
+template <typename T, int TM>
+__device__ __forceinline__ void rt_publish(const typename RtTile<T, TM>::type& t, unsigned used, int q, int n,
+                                           int w, int lane, T* colbuf, int* piv, T* ipv) {
+  constexpr int NP = 32 * TM;
+  const int cq = q / TM;
+  if ((cq >> 1) != w) return;  // uniform across the wavefront
+  const int cc = q - cq * TM, i0 = (lane & 31) * TM, hq = cq & 1;
+  const bool mine = (lane >> 5) == hq;
+  T best = T(-1), bv = T(0);
+  int bi = NP;
+  if (mine) {
+#pragma unroll
+    for (int a = 0; a < TM; ++a) {
+      const T v = t[a * TM + cc];
+      if (i0 + a < n) {
+        colbuf[i0 + a] = v;
+        const T mag = fabs(v);
+        if (!((used >> a) & 1u) && mag > best) {
+          best = mag;
+          bv = v;
+          bi = i0 + a;
+        }
+      }
+    }
+  }
+  T mx = best;
+  mx = fmax(mx, dpp_mov<0xB1>(mx));
+  mx = fmax(mx, dpp_mov<0x4E>(mx));
+  mx = fmax(mx, dpp_mov<0x141>(mx));
+  mx = fmax(mx, dpp_mov<0x140>(mx));
+  const T gm = fmax(lane_read(mx, hq << 5), lane_read(mx, (hq << 5) + 16));
+  const unsigned long long hit = __ballot(mine && best == gm);
+  const int L = hit ? __ffsll((long long)hit) - 1 : 0;
+  const int pb = __builtin_amdgcn_readlane(bi, L);
+  const T pvv = hit ? lane_read(bv, L) : T(0);
+  if (lane == 0) {
+    const bool ok = pvv != T(0) && pb >= 0 && pb < n;
+    *piv = ok ? pb : -1;
+    *ipv = ok ? T(1) / pvv : T(0);
+    if (ok) colbuf[pb] = T(0);  // after the column's writes (one wavefront, in order)
+  }
+}
+
+template <int D, int R, typename T, int TM>
+__global__ __launch_bounds__(kRtThreads) void k_patch_factor_rt(
+    int64_t npatch, const int32_t* __restrict__ pn_ptr, const int32_t* __restrict__ pvv_ptr,
+    const int32_t* __restrict__ pvv, const int32_t* __restrict__ pvp,
+    const int32_t* __restrict__ p_ld, const int64_t* __restrict__ p_inv_off,
+    const T* __restrict__ sM, const T* __restrict__ sL, const T* __restrict__ b_val,
+    Coef<T> dtA, T* __restrict__ inv, int* __restrict__ fail, int64_t p0, int64_t off0,
+    const T* __restrict__ nw) {
+  constexpr int NP = 32 * TM;
+  extern __shared__ unsigned char smem_raw[];
+  __shared__ T colbuf[2][NP];
+  __shared__ T s_ip[2];            // reciprocal of the pivot
+  __shared__ int s_piv[2];         // pivot row (-1: zero pivot)
+  __shared__ int s_pivrow[NP];     // pivot row of each step
+  __shared__ int s_rowstep[NP];    // step at which each row was the pivot
+  __shared__ T s_rowip[NP];        // reciprocal of each row's pivot
+  const int64_t p = p0 + blockIdx.x;
+  if (p >= npatch) return;
+  const int nn = pn_ptr[p + 1] - pn_ptr[p];
+  const int n = R * (D * nn + 1);
+  T* Am = reinterpret_cast<T*>(smem_raw);
+  const int tid = threadIdx.x;
+  for (int e = tid; e < 2 * NP; e += kRtThreads) colbuf[e / NP][e % NP] = T(0);
+  assemble_patch<D, R, T>(p, nn, n, pn_ptr, pvv_ptr, pvv, pvp, sM, sL, b_val, dtA, nw, Am);
+  const int w = tid >> 6, lane = tid & 63, half = lane >> 5, ri = lane & 31;
+  const int i0 = ri * TM, j0 = (2 * w + half) * TM;
+  typename RtTile<T, TM>::type t;
+#pragma unroll
+  for (int a = 0; a < TM; ++a)
+#pragma unroll
+    for (int c = 0; c < TM; ++c)
+      t[a * TM + c] = (i0 + a < n && j0 + c < n) ? Am[(i0 + a) * n + j0 + c] : T(0);
+  unsigned used = 0;  // bit a: row i0 + a has been a pivot row
+  rt_publish<T, TM>(t, used, 0, n, w, lane, colbuf[0], &s_piv[0], &s_ip[0]);
+  __syncthreads();
+  for (int kk = 0; kk < n; ++kk) {
+    const int buf = kk & 1;
+    const int pv = __builtin_amdgcn_readfirstlane(s_piv[buf]);
+    const T ip = s_ip[buf];
+    T m[TM];
+#pragma unroll
+    for (int a = 0; a < TM; ++a) m[a] = colbuf[buf][i0 + a];
+    if (pv < 0) {
+      if (tid == 0) atomicMax(fail, 1);
+      return;  // uniform across the workgroup
+    }
+    const int pr = pv / TM, pa = pv - pr * TM;
+    // the pivot row of this lane's columns, from lane pr of this half
+    T rrow[TM];
+#pragma unroll
+    for (int c = 0; c < TM; ++c) {
+      const T e = t[pa * TM + c];
+      const T v0 = lane_read(e, pr), v1 = lane_read(e, pr + 32);
+      rrow[c] = (half ? v1 : v0) * ip;
+    }
+    if (ri == pr) used |= 1u << pa;
+    const int ck = kk / TM;
+    if ((ck >> 1) == w) {
+      // the wavefront holding column kk: the column becomes -a_ik / pivot, and 1 in the
+      // (unscaled) pivot row
+      const bool own = half == (ck & 1);
+      const int cc = kk - ck * TM;
+#pragma unroll
+      for (int c = 0; c < TM; ++c)
+        if (own && c == cc) rrow[c] = ip;
+#pragma unroll
+      for (int a = 0; a < TM; ++a)
+#pragma unroll
+        for (int c = 0; c < TM; ++c)
+          t[a * TM + c] = ((own && c == cc) ? (i0 + a == pv ? T(1) : T(0)) : t[a * TM + c]) - m[a] * rrow[c];
+    } else {
+#pragma unroll
+      for (int a = 0; a < TM; ++a)
+#pragma unroll
+        for (int c = 0; c < TM; ++c) t[a * TM + c] = t[a * TM + c] - m[a] * rrow[c];
+    }
+    if (tid == 0) {
+      s_pivrow[kk] = pv;
+      s_rowstep[pv] = kk;
+      s_rowip[pv] = ip;
+    }
+    if (kk + 1 < n) rt_publish<T, TM>(t, used, kk + 1, n, w, lane, colbuf[buf ^ 1], &s_piv[buf ^ 1], &s_ip[buf ^ 1]);
+    __syncthreads();
+  }
+  // the inverse, column-major, staged in LDS and written out with whole columns
+#pragma unroll
+  for (int a = 0; a < TM; ++a)
+#pragma unroll
+    for (int c = 0; c < TM; ++c)
+      if (i0 + a < n && j0 + c < n)
+        Am[s_pivrow[j0 + c] * n + s_rowstep[i0 + a]] = t[a * TM + c] * s_rowip[i0 + a];
+  __syncthreads();
+  const int ld = p_ld[p];
+  T* out = inv + (p_inv_off[p] - off0);
+  for (int e = tid; e < n * ld; e += kRtThreads) {
+    const int j = e / ld, i = e - j * ld;
+    out[e] = i < n ? Am[j * n + i] : T(0);
+  }
+}
+
+// The LDS-resident factorisation of patches of up to n unknowns: the register-tiled
+// kernel for 64 < n <= 128, else the kernel with the whole matrix in LDS.
+template <int D, int RR, typename T>
+hipError_t launch_patch_factor_lds(unsigned g, size_t n, size_t lds, hipStream_t s, int64_t npatch,
+                                   const int32_t* pn_ptr, const int32_t* pvv_ptr, const int32_t* pvv,
+                                   const int32_t* pvp, const int32_t* ld, const int64_t* off, const T* sM,
+                                   const T* sL, const T* b_val, Coef<T> cf, T* out, int* d_fail, int64_t p0,
+                                   int64_t off0, const T* nw) {
+  auto go = [&](auto kern, unsigned block, size_t bytes) -> hipError_t {
+    hipError_t e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+    if (e != hipSuccess) return e;
+    kern<<<dim3(g), dim3(block), bytes, s>>>(npatch, pn_ptr, pvv_ptr, pvv, pvp, ld, off, sM, sL, b_val, cf, out,
+                                             d_fail, p0, off0, nw);
+    return hipGetLastError();
+  };
+  if constexpr (D < 3) {
+    // static LDS of the register-tiled kernel: two columns, the row reciprocals, two
+    // permutations
+    const size_t rt = n * n * sizeof(T);
+    auto fits = [&](int tm) {
+      return rt + (size_t)96 * tm * sizeof(T) + (size_t)64 * tm * sizeof(int) + 64 <= 160 * 1024;
+    };
+    if (n > 64 && n <= 96 && fits(3)) return go(k_patch_factor_rt<D, RR, T, 3>, kRtThreads, rt);
+    if (n > 96 && n <= 128 && fits(4)) return go(k_patch_factor_rt<D, RR, T, 4>, kRtThreads, rt);
+  }
+  return go(k_patch_factor<D, RR, T>, kBlock, lds);
 }
 
 // Patches too large for LDS: the matrix is assembled straight into its column-major
@@ -1803,11 +2043,10 @@ hipError_t patch_factor_range(const DevLevel& L, const DevOps<T>& ops, int R, co
     return hipGetLastError();
   }
   IRK_DISPATCH_DR(L.dim, R, {
-    auto kern = k_patch_factor<DD, RR, T>;
-    hipError_t e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    hipError_t e = launch_patch_factor_lds<DD, RR, T>(g, n, lds, s, p1, L.pn_ptr, L.pvv_ptr, L.pvv, L.pvp, ld, off,
+                                                      ops.s_M, ops.s_L, ops.b_val, scaled<T, RR>(coef, dt), out,
+                                                      d_fail, p0, off0, nw);
     if (e != hipSuccess) return e;
-    kern<<<dim3(g), dim3(kBlock), lds, s>>>(p1, L.pn_ptr, L.pvv_ptr, L.pvv, L.pvp, ld, off, ops.s_M, ops.s_L,
-                                            ops.b_val, scaled<T, RR>(coef, dt), out, d_fail, p0, off0, nw);
   });
   return hipGetLastError();
 }
@@ -1834,7 +2073,10 @@ hipError_t patch_factor_scalar(const DevLevel& L, const DevOps<T>& ops, int R, c
   {                                                                                                          \
     const Coef<T> cf = scaled<T, RR>(A, dt);                                                                 \
     if (lds <= 160 * 1024) {                                                                                 \
-      IRK_PFS((k_patch_factor<1, RR, T>), lds);                                                              \
+      hipError_t e = launch_patch_factor_lds<1, RR, T>(g, n, lds, s, p1, L.pn_ptr, L.pvv_ptr, L.pvv, L.pvp, ld, \
+                                                       off, ops.s_M, ops.s_L, nullptr, cf, out, d_fail, p0,   \
+                                                       off0, nullptr);                                        \
+      if (e != hipSuccess) return e;                                                                         \
     } else {                                                                                                 \
       if (n > (size_t)kGjRows * kBlock) return hipErrorInvalidConfiguration;                                 \
       const size_t glds = (size_t)kGjBw * n * sizeof(T) + n * sizeof(T) + (size_t)kGjBw * kGjJt * sizeof(T) + \
