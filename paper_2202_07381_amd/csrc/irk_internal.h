@@ -297,7 +297,9 @@ struct Handle {
   int prof_mode = 3;
   std::vector<ProfEv> prof_pool;
   size_t prof_used = 0;
-  hipEvent_t ev0 = nullptr, ev1 = nullptr, ev2 = nullptr, ev3 = nullptr;
+  hipEvent_t ev0 = nullptr, ev1 = nullptr, ev2 = nullptr, ev3 = nullptr, ev4 = nullptr, ev5 = nullptr,
+             evh = nullptr;
+  double* hpin = nullptr;  // pinned host: FGMRES Hessenberg column and update coefficients
   // Navier--Stokes (Newton) data of the finest level, built at first use
   std::vector<double> wind_fine;  // host copy of the finest-level wind (empty: none)
   bool ns_ready = false;
@@ -436,6 +438,9 @@ hipError_t axpy_dev(double* y, const double* x, int64_t n, const double* dev_sca
 // y = x / (*dev_scalar)
 hipError_t scale_inv_dev(double* y, const double* x, int64_t n, const double* dev_scalar,
                          hipStream_t s);
+// x += sum_i c_i Z_i (Z: m vectors of n, c on the device), accumulated per entry in the
+// order i = 0, 1, ..., m - 1
+hipError_t update_sum(double* x, const double* Z, int64_t n, const double* c, int m, hipStream_t s);
 hipError_t axpby(double* y, const double* x, int64_t n, double alpha, double beta,
                  hipStream_t s);  // y = alpha x + beta y
 hipError_t fill(double* y, int64_t n, double v, hipStream_t s);

@@ -583,6 +583,10 @@ irk_status ensure_krylov(irk_mg* h, int restart) {
   return IRK_OK;
 }
 
+// Start the next FGMRES iteration's V-cycle before the host has read the Hessenberg column
+// when the predicted residual estimate stays above this many tolerances.
+constexpr double kSpecMargin = 20.0;
+
 // FGMRES on the finest level in the internal layout: solves J x = kF starting from the x
 // held in kx and leaves the solution in kx (and, when k_abi is given, in k_abi).  The
 // caller records ev0 and fills kF, kx; the Krylov workspace must hold `restart` vectors.
@@ -592,7 +596,9 @@ irk_status fgmres_int(irk_mg* h, double* k_abi, double rtol, int maxit, int rest
   const int64_t N = L.N;
   double* H = nullptr;
   std::vector<double> Hm((size_t)(restart + 1) * restart), cs(restart), sn(restart), g(restart + 1),
-      y(restart), hcol(restart + 2);
+      y(restart);
+  double* hcol = h->hpin;          // pinned: restart + 2 values
+  double* ycoef = h->hpin + 1032;  // pinned: restart values
   auto host_scalar = [&](double* dev, double* out) -> irk_status {
     HIPCHK(hipMemcpyAsync(out, dev, sizeof(double), hipMemcpyDeviceToHost, s));
     HIPCHK(hipStreamSynchronize(s));
@@ -626,22 +632,47 @@ irk_status fgmres_int(irk_mg* h, double* k_abi, double rtol, int maxit, int rest
     std::fill(g.begin(), g.end(), 0.0);
     g[0] = beta;
     int jend = 0;
+    bool z_ready = false;  // z_j was started by the previous iteration
+    double res_prev = -1.0, res_cur = beta;
     for (int j = 0; j < restart; ++j) {
       double* vj = h->kv + (size_t)j * N;
       double* zj = h->kz + (size_t)j * N;
       double* vn = h->kv + (size_t)(j + 1) * N;
-      HIPCHK(hipEventRecord(h->ev2, s));
-      CHK(precondition(h, vj, zj, tr, s));
-      HIPCHK(hipEventRecord(h->ev3, s));
+      hipEvent_t ea = (j & 1) ? h->ev4 : h->ev2, eb = (j & 1) ? h->ev5 : h->ev3;
+      if (!z_ready) {
+        HIPCHK(hipEventRecord(ea, s));
+        CHK(precondition(h, vj, zj, tr, s));
+        HIPCHK(hipEventRecord(eb, s));
+      }
       CHK(apply_J(h, zj, vn, tr, nullptr, s));
       HIPCHK(k::mgs_arnoldi(vn, h->kv, N, j, h->partials, h->hbuf, s));
-      HIPCHK(hipMemcpyAsync(hcol.data(), h->hbuf, (j + 2) * sizeof(double), hipMemcpyDeviceToHost, s));
-      HIPCHK(hipStreamSynchronize(s));
+      HIPCHK(hipMemcpyAsync(hcol, h->hbuf, (j + 2) * sizeof(double), hipMemcpyDeviceToHost, s));
+      HIPCHK(hipEventRecord(h->evh, s));
+      // The next V-cycle needs only v_{j+1}, which is on the device: start it before the host
+      // reads column j when the residual estimates (the last contraction applied once more)
+      // put the end of this cycle more than kSpecMargin tolerances away.  A wrong guess costs
+      // one unused V-cycle; the iterates are the same either way.
+      bool spec = false;
+      if (j + 1 < restart && its + 1 < maxit && res_prev > 0.0) {
+        const double rho = std::min(1.0, res_cur / res_prev);
+        spec = res_cur * rho > kSpecMargin * rtol * beta0;
+      }
+      if (spec) {
+        hipEvent_t na = (j & 1) ? h->ev2 : h->ev4, nb = (j & 1) ? h->ev3 : h->ev5;
+        HIPCHK(hipEventRecord(na, s));
+        CHK(precondition(h, vn, h->kz + (size_t)(j + 1) * N, tr, s));
+        HIPCHK(hipEventRecord(nb, s));
+      }
+      HIPCHK(hipEventSynchronize(h->evh));
       float ms = 0;
-      HIPCHK(hipEventElapsedTime(&ms, h->ev2, h->ev3));
+      HIPCHK(hipEventElapsedTime(&ms, ea, eb));
       ms_v += ms;
+      z_ready = spec;
       for (int i = 0; i <= j + 1; ++i) {
-        if (!std::isfinite(hcol[i])) return fail(IRK_ENAN, "non-finite value in the Arnoldi process");
+        if (!std::isfinite(hcol[i])) {
+          if (spec) (void)hipStreamSynchronize(s);
+          return fail(IRK_ENAN, "non-finite value in the Arnoldi process");
+        }
         Hm[i * restart + j] = hcol[i];
       }
       for (int i = 0; i < j; ++i) {
@@ -659,6 +690,8 @@ irk_status fgmres_int(irk_mg* h, double* k_abi, double rtol, int maxit, int rest
       ++its;
       jend = j + 1;
       push_hist(std::fabs(g[j + 1]));
+      res_prev = res_cur;
+      res_cur = std::fabs(g[j + 1]);
       if (std::fabs(g[j + 1]) <= rtol * beta0 || its >= maxit) break;
     }
     for (int i = jend - 1; i >= 0; --i) {
@@ -666,7 +699,12 @@ irk_status fgmres_int(irk_mg* h, double* k_abi, double rtol, int maxit, int rest
       for (int m = i + 1; m < jend; ++m) acc -= Hm[i * restart + m] * y[m];
       y[i] = acc / Hm[i * restart + i];
     }
-    for (int i = 0; i < jend; ++i) HIPCHK(k::axpby(h->kx, h->kz + (size_t)i * N, N, y[i], 1.0, s));
+    // x += Z y in one pass (the coefficients through the pinned buffer, which the host next
+    // writes after later synchronisations; the device column buffer is free until the next
+    // cycle's Arnoldi step)
+    std::copy(y.begin(), y.begin() + jend, ycoef);
+    HIPCHK(hipMemcpyAsync(h->hbuf, ycoef, (size_t)jend * sizeof(double), hipMemcpyHostToDevice, s));
+    HIPCHK(k::update_sum(h->kx, h->kz, N, h->hbuf, jend, s));
     if (std::fabs(g[jend]) <= rtol * beta0) converged = true;
   }
   HIPCHK(k::project_pressure(L, h->kx, h->partials, s));
@@ -961,8 +999,9 @@ void irk_mg_destroy(irk_mg* h) {
     if (e.b) (void)hipEventDestroy(e.b);
   }
   for (void* p : h->allocations) (void)hipFree(p);
-  for (hipEvent_t e : {h->ev0, h->ev1, h->ev2, h->ev3})
+  for (hipEvent_t e : {h->ev0, h->ev1, h->ev2, h->ev3, h->ev4, h->ev5, h->evh})
     if (e) (void)hipEventDestroy(e);
+  if (h->hpin) (void)hipHostFree(h->hpin);
   delete h;
 }
 
@@ -1485,7 +1524,8 @@ static irk_status setup_impl(const irk_mesh_level* lv, int nlevels, const irk_ta
   CHK(dalloc(h, &h->scal, 16));
   CHK(dalloc(h, &h->partials, 1024));
   CHK(dalloc(h, &h->hbuf, 1024 + 2));
-  for (hipEvent_t* e : {&h->ev0, &h->ev1, &h->ev2, &h->ev3}) HIPCHK(hipEventCreate(e));
+  for (hipEvent_t* e : {&h->ev0, &h->ev1, &h->ev2, &h->ev3, &h->ev4, &h->ev5, &h->evh}) HIPCHK(hipEventCreate(e));
+  HIPCHK(hipHostMalloc((void**)&h->hpin, 2 * 1032 * sizeof(double), hipHostMallocDefault));
   HIPCHK(hipStreamSynchronize(s));
   return IRK_OK;
 }

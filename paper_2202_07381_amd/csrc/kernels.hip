@@ -1603,9 +1603,20 @@ __global__ __launch_bounds__(kBlock) void k_dot_partial(const double* __restrict
                                                         double* __restrict__ partials) {
   __shared__ double red[kBlock];
   double acc = 0;
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
-       i += (int64_t)gridDim.x * blockDim.x)
-    acc += a[i] * b[i];
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  constexpr int U = 4;  // loads of four grid-stride elements together, sums in order
+  for (; i + (U - 1) * stride < n; i += U * stride) {
+    double av[U], bv[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      av[u] = a[i + u * stride];
+      bv[u] = b[i + u * stride];
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) acc += av[u] * bv[u];
+  }
+  for (; i < n; i += stride) acc += a[i] * b[i];
   red[threadIdx.x] = acc;
   __syncthreads();
   for (int w = kBlock / 2; w > 0; w >>= 1) {
@@ -1669,14 +1680,35 @@ __device__ double block_reduce_partials(const double* __restrict__ partials, int
 }
 
 __global__ __launch_bounds__(kBlock) void k_mgs_step(double* __restrict__ w, const double* __restrict__ vi,
-                                                     const double* vnext, int64_t n, const double* __restrict__ pin,
-                                                     int nb, double* __restrict__ pout, double* __restrict__ hout) {
+                                                     const double* __restrict__ vnext, int64_t n,
+                                                     const double* __restrict__ pin, int nb,
+                                                     double* __restrict__ pout, double* __restrict__ hout) {
   __shared__ double red[kBlock];
   const double h = block_reduce_partials(pin, nb, red);
   if (blockIdx.x == 0 && threadIdx.x == 0) *hout = h;
   const double a = -1.0 * h;
   double acc = 0;
-  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  // four grid-stride elements' loads issued together, then the same sums in the same order
+  constexpr int U = 4;
+  for (; e + (U - 1) * stride < n; e += U * stride) {
+    double wv[U], vv[U], nv[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      wv[u] = w[e + u * stride];
+      vv[u] = vi[e + u * stride];
+      nv[u] = vnext ? vnext[e + u * stride] : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      double y = wv[u];
+      y += a * vv[u];
+      w[e + u * stride] = y;
+      acc += y * (vnext ? nv[u] : y);
+    }
+  }
+  for (; e < n; e += stride) {
     double y = w[e];
     y += a * vi[e];
     w[e] = y;
@@ -1697,8 +1729,17 @@ __global__ __launch_bounds__(kBlock) void k_mgs_normalize(double* __restrict__ w
   __shared__ double red[kBlock];
   const double nrm = sqrt(block_reduce_partials(pin, nb, red));
   if (blockIdx.x == 0 && threadIdx.x == 0) *hout = nrm;
-  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x)
-    w[e] = w[e] / nrm;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  constexpr int U = 4;  // loads of four grid-stride elements together
+  for (; e + (U - 1) * stride < n; e += U * stride) {
+    double wv[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) wv[u] = w[e + u * stride];
+#pragma unroll
+    for (int u = 0; u < U; ++u) w[e + u * stride] = wv[u] / nrm;
+  }
+  for (; e < n; e += stride) w[e] = w[e] / nrm;
 }
 
 __global__ __launch_bounds__(kBlock) void k_axpy_dev(double* __restrict__ y,
@@ -1725,6 +1766,15 @@ __global__ __launch_bounds__(kBlock) void k_axpby(double* __restrict__ y,
                                                   double a, double b) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) y[i] = b == 0.0 ? a * x[i] : a * x[i] + b * y[i];
+}
+
+__global__ __launch_bounds__(kBlock) void k_update_sum(double* __restrict__ x, const double* __restrict__ Z,
+                                                       int64_t n, const double* __restrict__ c, int m) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  double acc = x[i];
+  for (int k = 0; k < m; ++k) acc = fma(c[k], Z[(size_t)k * n + i], acc);
+  x[i] = acc;
 }
 
 template <typename T>
@@ -2392,6 +2442,12 @@ hipError_t axpy_dev(double* y, const double* x, int64_t n, const double* dev_sca
 hipError_t scale_inv_dev(double* y, const double* x, int64_t n, const double* dev_scalar,
                          hipStream_t s) {
   k_scale_inv<<<dim3(blocks_for(n)), dim3(kBlock), 0, s>>>(y, x, n, dev_scalar);
+  return hipGetLastError();
+}
+
+hipError_t update_sum(double* x, const double* Z, int64_t n, const double* c, int m, hipStream_t s) {
+  if (m <= 0) return hipSuccess;
+  k_update_sum<<<dim3(blocks_for(n)), dim3(kBlock), 0, s>>>(x, Z, n, c, m);
   return hipGetLastError();
 }
 
