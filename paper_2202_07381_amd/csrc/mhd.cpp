@@ -63,7 +63,10 @@ struct irk_mhd {
   double *kv = nullptr, *kz = nullptr, *kF = nullptr, *kx = nullptr, *kr = nullptr;
   double *partials = nullptr, *scal = nullptr, *hbuf = nullptr;
   int* flag = nullptr;
-  hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
+  // 0, 1: the solve; 2, 3 and 4, 5: V-cycles of alternate FGMRES iterations; 6: the
+  // Hessenberg column's copy
+  hipEvent_t ev[7] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
+  double* hpin = nullptr;  // pinned host: Hessenberg column and update coefficients
   int prof = 0;  // 0 off, 1 finest level, 2 every level
   std::vector<ProfEv> prof_pool;
   size_t prof_used = 0;
@@ -254,12 +257,17 @@ irk_status ensure_krylov(irk_mhd* h, int restart) {
   return IRK_OK;
 }
 
+// Start the next FGMRES iteration's V-cycle before the host has read the Hessenberg column
+// when the predicted residual estimate stays above this many tolerances.
+constexpr double kSpecMargin = 20.0;
+
 irk_status fgmres(irk_mhd* h, double rtol, int maxit, int restart, irk_solve_info* info, hipStream_t s) {
   const int fl = h->nlevels - 1;
   MhdDev& L = h->dev[fl];
   const int64_t N = L.N;
-  std::vector<double> Hm((size_t)(restart + 1) * restart), cs(restart), sn(restart), g(restart + 1), y(restart),
-      hcol(restart + 2);
+  std::vector<double> Hm((size_t)(restart + 1) * restart), cs(restart), sn(restart), g(restart + 1), y(restart);
+  double* hcol = h->hpin;          // pinned: restart + 2 values
+  double* ycoef = h->hpin + 1032;  // pinned: restart values
   auto host_scalar = [&](double* out) -> irk_status {
     HIPCHK(hipMemcpyAsync(out, h->scal, sizeof(double), hipMemcpyDeviceToHost, s));
     HIPCHK(hipStreamSynchronize(s));
@@ -292,22 +300,45 @@ irk_status fgmres(irk_mhd* h, double rtol, int maxit, int restart, irk_solve_inf
     std::fill(g.begin(), g.end(), 0.0);
     g[0] = beta;
     int jend = 0;
+    bool z_ready = false;  // z_j was started by the previous iteration
+    double res_prev = -1.0, res_cur = beta;
     for (int j = 0; j < restart; ++j) {
       double* vj = h->kv + (size_t)j * N;
       double* zj = h->kz + (size_t)j * N;
       double* vn = h->kv + (size_t)(j + 1) * N;
-      HIPCHK(hipEventRecord(h->ev[2], s));
-      CHK(precondition(h, vj, zj, s));
-      HIPCHK(hipEventRecord(h->ev[3], s));
+      hipEvent_t ea = h->ev[(j & 1) ? 4 : 2], eb = h->ev[(j & 1) ? 5 : 3];
+      if (!z_ready) {
+        HIPCHK(hipEventRecord(ea, s));
+        CHK(precondition(h, vj, zj, s));
+        HIPCHK(hipEventRecord(eb, s));
+      }
       CHK(residual(h, fl, nullptr, zj, vn, s));
       HIPCHK(k::mgs_arnoldi(vn, h->kv, N, j, h->partials, h->hbuf, s));
-      HIPCHK(hipMemcpyAsync(hcol.data(), h->hbuf, (j + 2) * sizeof(double), hipMemcpyDeviceToHost, s));
-      HIPCHK(hipStreamSynchronize(s));
+      HIPCHK(hipMemcpyAsync(hcol, h->hbuf, (j + 2) * sizeof(double), hipMemcpyDeviceToHost, s));
+      HIPCHK(hipEventRecord(h->ev[6], s));
+      // the next V-cycle needs only v_{j+1}: started before the host reads column j when
+      // the last contraction, applied once more, leaves the estimate above kSpecMargin
+      // tolerances (the iterates are the same either way)
+      bool spec = false;
+      if (j + 1 < restart && its + 1 < maxit && res_prev > 0.0) {
+        const double rho = std::min(1.0, res_cur / res_prev);
+        spec = res_cur * rho > kSpecMargin * rtol * beta0;
+      }
+      if (spec) {
+        HIPCHK(hipEventRecord(h->ev[(j & 1) ? 2 : 4], s));
+        CHK(precondition(h, vn, h->kz + (size_t)(j + 1) * N, s));
+        HIPCHK(hipEventRecord(h->ev[(j & 1) ? 3 : 5], s));
+      }
+      HIPCHK(hipEventSynchronize(h->ev[6]));
       float ms = 0;
-      HIPCHK(hipEventElapsedTime(&ms, h->ev[2], h->ev[3]));
+      HIPCHK(hipEventElapsedTime(&ms, ea, eb));
       ms_v += ms;
+      z_ready = spec;
       for (int i = 0; i <= j + 1; ++i) {
-        if (!std::isfinite(hcol[i])) return fail(IRK_ENAN, "non-finite value in the Arnoldi process");
+        if (!std::isfinite(hcol[i])) {
+          if (spec) (void)hipStreamSynchronize(s);
+          return fail(IRK_ENAN, "non-finite value in the Arnoldi process");
+        }
         Hm[i * restart + j] = hcol[i];
       }
       for (int i = 0; i < j; ++i) {
@@ -325,6 +356,8 @@ irk_status fgmres(irk_mhd* h, double rtol, int maxit, int restart, irk_solve_inf
       ++its;
       jend = j + 1;
       push_hist(std::fabs(g[j + 1]));
+      res_prev = res_cur;
+      res_cur = std::fabs(g[j + 1]);
       if (std::fabs(g[j + 1]) <= rtol * beta0 || its >= maxit) break;
     }
     for (int i = jend - 1; i >= 0; --i) {
@@ -332,7 +365,11 @@ irk_status fgmres(irk_mhd* h, double rtol, int maxit, int restart, irk_solve_inf
       for (int m = i + 1; m < jend; ++m) acc -= Hm[i * restart + m] * y[m];
       y[i] = acc / Hm[i * restart + i];
     }
-    for (int i = 0; i < jend; ++i) HIPCHK(k::axpby(h->kx, h->kz + (size_t)i * N, N, y[i], 1.0, s));
+    // x += Z y in one pass (coefficients through the pinned buffer into the device column
+    // buffer, free until the next cycle's Arnoldi step)
+    std::copy(y.begin(), y.begin() + jend, ycoef);
+    HIPCHK(hipMemcpyAsync(h->hbuf, ycoef, (size_t)jend * sizeof(double), hipMemcpyHostToDevice, s));
+    HIPCHK(k::update_sum(h->kx, h->kz, N, h->hbuf, jend, s));
     if (std::fabs(g[jend]) <= rtol * beta0) converged = true;
   }
   HIPCHK(k::project_pressure(L.pv, h->kx, h->partials, s));
@@ -652,6 +689,7 @@ irk_status setup_impl(const irk_mesh_level* lv, int nlevels, const irk_tableau* 
   CHK(dalloc(h, &h->partials, 1024));
   CHK(dalloc(h, &h->scal, 4));
   for (auto& e : h->ev) HIPCHK(hipEventCreate(&e));
+  HIPCHK(hipHostMalloc((void**)&h->hpin, 2 * 1032 * sizeof(double), hipHostMallocDefault));
   h->dev.resize(nlevels);
   for (int l = 0; l < nlevels; ++l) {
     MhdHost& H = host[l];
@@ -858,6 +896,7 @@ void irk_mhd_destroy(irk_mhd* h) {
   for (void* p : h->allocations) (void)hipFree(p);
   for (auto& e : h->ev)
     if (e) (void)hipEventDestroy(e);
+  if (h->hpin) (void)hipHostFree(h->hpin);
   delete h;
 }
 
