@@ -381,19 +381,23 @@ __global__ __launch_bounds__(kBlock) void k_residual_newton(
 // Newton Jacobian's per-stage dim x dim blocks, as for k_residual_newton) the
 // velocity-velocity entries are delta_st delta_ce M_ab + dt a_st N_s[ab]_ce instead of
 // the Kronecker delta_st M_ab + dt a_st L_ab on each component.
-// The patch matrix, row-major with stride n, zeroed and filled by the workgroup (ends
-// with a barrier).  With nw (the Newton Jacobian's per-stage dim x dim blocks, as for
+// Rows [r0, r1) of the patch matrix, row-major with stride n from row r0, zeroed and filled
+// by the workgroup (ends with a barrier).  With nw (the Newton Jacobian's per-stage dim x dim blocks, as for
 // k_residual_newton) the velocity-velocity entries are delta_st delta_ce M_ab + dt a_st
 // N_s[ab]_ce instead of the Kronecker delta_st M_ab + dt a_st L_ab on each component.
 template <int D, int R, typename T>
 __device__ void assemble_patch(int64_t p, int nn, int n, const int32_t* __restrict__ pn_ptr,
                                const int32_t* __restrict__ pvv_ptr, const int32_t* __restrict__ pvv,
                                const int32_t* __restrict__ pvp, const T* __restrict__ sM, const T* __restrict__ sL,
-                               const T* __restrict__ b_val, const Coef<T>& dtA, const T* __restrict__ nw, T* Am) {
+                               const T* __restrict__ b_val, const Coef<T>& dtA, const T* __restrict__ nw, int r0,
+                               int r1, T* Am) {
   const int sb = D * nn + 1;  // per-stage block size
   const int tid = threadIdx.x;
-  for (int e = tid; e < n * n; e += blockDim.x) Am[e] = T(0);
+  for (int e = tid; e < (r1 - r0) * n; e += blockDim.x) Am[e] = T(0);
   __syncthreads();
+  auto put = [&](int row, int col, T v) {
+    if (row >= r0 && row < r1) Am[(row - r0) * n + col] = v;
+  };
   // velocity-velocity: delta_st M_ab + dt a_st L_ab on every component
   const int32_t v0 = pvv_ptr[p], v1 = pvv_ptr[p + 1];
   for (int32_t e = v0 + tid; e < v1; e += blockDim.x) {
@@ -401,33 +405,37 @@ __device__ void assemble_patch(int64_t p, int nn, int n, const int32_t* __restri
     const T m = sM[pos];
     if (nw) {
       const T* nwp = nw + (int64_t)pos * R * D * D;
+#pragma unroll 1
       for (int c = 0; c < D; ++c)
+#pragma unroll 1
         for (int ce = 0; ce < D; ++ce)
           for (int s = 0; s < R; ++s)
             for (int t = 0; t < R; ++t)
-              Am[(s * sb + c * nn + la) * n + (t * sb + ce * nn + lb)] =
-                  (s == t && c == ce ? m : T(0)) + dtA.v[s * R + t] * nwp[(s * D + c) * D + ce];
+              put(s * sb + c * nn + la, t * sb + ce * nn + lb,
+                  (s == t && c == ce ? m : T(0)) + dtA.v[s * R + t] * nwp[(s * D + c) * D + ce]);
       continue;
     }
     const T l = sL[pos];
+#pragma unroll 1
     for (int c = 0; c < D; ++c)
+#pragma unroll 1
       for (int s = 0; s < R; ++s)
         for (int t = 0; t < R; ++t)
-          Am[(s * sb + c * nn + la) * n + (t * sb + c * nn + lb)] =
-              (s == t ? m : T(0)) + dtA.v[s * R + t] * l;
+          put(s * sb + c * nn + la, t * sb + c * nn + lb, (s == t ? m : T(0)) + dtA.v[s * R + t] * l);
   }
   // velocity-pressure couplings with the patch vertex: dt a_st B and dt a_st B^T
   const int32_t n0 = pn_ptr[p];
   for (int la = tid; la < nn; la += blockDim.x) {
     const int pos = pvp[n0 + la];
     if (pos < 0) continue;
+#pragma unroll 1
     for (int c = 0; c < D; ++c) {
       const T bv = b_val[(int64_t)pos * D + c];
       for (int s = 0; s < R; ++s)
         for (int t = 0; t < R; ++t) {
           const T val = dtA.v[s * R + t] * bv;
-          Am[(s * sb + c * nn + la) * n + (t * sb + D * nn)] = val;
-          Am[(s * sb + D * nn) * n + (t * sb + c * nn + la)] = val;
+          put(s * sb + c * nn + la, t * sb + D * nn, val);
+          put(s * sb + D * nn, t * sb + c * nn + la, val);
         }
     }
   }
@@ -454,7 +462,7 @@ __global__ __launch_bounds__(kBlock) void k_patch_factor(
   __shared__ int s_piv;
   __shared__ T s_best;
   const int tid = threadIdx.x;
-  assemble_patch<D, R, T>(p, nn, n, pn_ptr, pvv_ptr, pvv, pvp, sM, sL, b_val, dtA, nw, Am);
+  assemble_patch<D, R, T>(p, nn, n, pn_ptr, pvv_ptr, pvv, pvp, sM, sL, b_val, dtA, nw, 0, n, Am);
   // in-place Gauss--Jordan with partial pivoting (ties -> smallest row index)
   for (int kk = 0; kk < n; ++kk) {
     if (tid < 64) {
@@ -540,6 +548,8 @@ __global__ __launch_bounds__(kBlock) void k_patch_factor(
 // (i, j) of the exchanged matrix is entry (step at which row i was the pivot, pivot row
 // of step j) of the inverse.
 constexpr int kRtThreads = 1024;
+// Rows per LDS pass of the register-tiled kernel: half of n, rounded up to whole tiles.
+__host__ __device__ constexpr int rt_half_rows(int n, int tm) { return ((n + 1) / 2 + tm - 1) / tm * tm; }
 // A thread's tile, entry (a, c) at a * TM + c: one vector value of at most 1024 bits, so
 // that selecting a column by a wavefront-uniform index stays in registers (indexed
 // register moves).
@@ -624,7 +634,7 @@ __device__ __forceinline__ void rt_publish(const typename RtTile<T, TM>::type& t
 }
 
 template <int D, int R, typename T, int TM>
-__global__ __launch_bounds__(kRtThreads) void k_patch_factor_rt(
+__global__ __launch_bounds__(kRtThreads, 8) void k_patch_factor_rt(
     int64_t npatch, const int32_t* __restrict__ pn_ptr, const int32_t* __restrict__ pvv_ptr,
     const int32_t* __restrict__ pvv, const int32_t* __restrict__ pvp,
     const int32_t* __restrict__ p_ld, const int64_t* __restrict__ p_inv_off,
@@ -646,15 +656,28 @@ __global__ __launch_bounds__(kRtThreads) void k_patch_factor_rt(
   T* Am = reinterpret_cast<T*>(smem_raw);
   const int tid = threadIdx.x;
   for (int e = tid; e < 2 * NP; e += kRtThreads) colbuf[e / NP][e % NP] = T(0);
-  assemble_patch<D, R, T>(p, nn, n, pn_ptr, pvv_ptr, pvv, pvp, sM, sL, b_val, dtA, nw, Am);
   const int w = tid >> 6, lane = tid & 63, half = lane >> 5, ri = lane & 31;
   const int i0 = ri * TM, j0 = (2 * w + half) * TM;
+  // the matrix passes through LDS in two halves of rows (hr rows, a multiple of TM, each),
+  // so that two patches' workgroups fit on a CU
+  const int hr = rt_half_rows(n, TM);
   typename RtTile<T, TM>::type t;
+  for (int r0 = 0; r0 < n; r0 += hr) {
+    const int r1 = min(n, r0 + hr);
+    assemble_patch<D, R, T>(p, nn, n, pn_ptr, pvv_ptr, pvv, pvp, sM, sL, b_val, dtA, nw, r0, r1, Am);
+    if (i0 >= r0 && i0 < r1) {
 #pragma unroll
-  for (int a = 0; a < TM; ++a)
+      for (int a = 0; a < TM; ++a)
 #pragma unroll
-    for (int c = 0; c < TM; ++c)
-      t[a * TM + c] = (i0 + a < n && j0 + c < n) ? Am[(i0 + a) * n + j0 + c] : T(0);
+        for (int c = 0; c < TM; ++c)
+          t[a * TM + c] = (i0 + a < n && j0 + c < n) ? Am[(i0 + a - r0) * n + j0 + c] : T(0);
+    }
+    __syncthreads();
+  }
+  if (i0 >= n) {
+#pragma unroll
+    for (int e = 0; e < TM * TM; ++e) t[e] = T(0);
+  }
   unsigned used = 0;  // bit a: row i0 + a has been a pivot row
   rt_publish<T, TM>(t, used, 0, n, w, lane, colbuf[0], &s_piv[0], &s_ip[0]);
   __syncthreads();
@@ -707,19 +730,26 @@ __global__ __launch_bounds__(kRtThreads) void k_patch_factor_rt(
     if (kk + 1 < n) rt_publish<T, TM>(t, used, kk + 1, n, w, lane, colbuf[buf ^ 1], &s_piv[buf ^ 1], &s_ip[buf ^ 1]);
     __syncthreads();
   }
-  // the inverse, column-major, staged in LDS and written out with whole columns
-#pragma unroll
-  for (int a = 0; a < TM; ++a)
-#pragma unroll
-    for (int c = 0; c < TM; ++c)
-      if (i0 + a < n && j0 + c < n)
-        Am[s_pivrow[j0 + c] * n + s_rowstep[i0 + a]] = t[a * TM + c] * s_rowip[i0 + a];
-  __syncthreads();
+  // the inverse, column-major, staged in LDS by halves of its columns and written out with
+  // whole columns
   const int ld = p_ld[p];
   T* out = inv + (p_inv_off[p] - off0);
-  for (int e = tid; e < n * ld; e += kRtThreads) {
-    const int j = e / ld, i = e - j * ld;
-    out[e] = i < n ? Am[j * n + i] : T(0);
+  for (int c0 = 0; c0 < n; c0 += hr) {
+    const int c1 = min(n, c0 + hr);
+#pragma unroll
+    for (int a = 0; a < TM; ++a)
+#pragma unroll
+      for (int c = 0; c < TM; ++c)
+        if (i0 + a < n && j0 + c < n) {
+          const int b = s_pivrow[j0 + c];
+          if (b >= c0 && b < c1) Am[(b - c0) * n + s_rowstep[i0 + a]] = t[a * TM + c] * s_rowip[i0 + a];
+        }
+    __syncthreads();
+    for (int e = tid; e < (c1 - c0) * ld; e += kRtThreads) {
+      const int j = e / ld, i = e - j * ld;
+      out[(int64_t)c0 * ld + e] = i < n ? Am[j * n + i] : T(0);
+    }
+    __syncthreads();
   }
 }
 
@@ -741,12 +771,13 @@ hipError_t launch_patch_factor_lds(unsigned g, size_t n, size_t lds, hipStream_t
   if constexpr (D < 3) {
     // static LDS of the register-tiled kernel: two columns, the row reciprocals, two
     // permutations
-    const size_t rt = n * n * sizeof(T);
+    // dynamic LDS: half of the rows (two workgroups per CU share its 160 KB)
+    auto rt = [&](int tm) { return (size_t)rt_half_rows((int)n, tm) * n * sizeof(T); };
     auto fits = [&](int tm) {
-      return rt + (size_t)96 * tm * sizeof(T) + (size_t)64 * tm * sizeof(int) + 64 <= 160 * 1024;
+      return rt(tm) + (size_t)96 * tm * sizeof(T) + (size_t)64 * tm * sizeof(int) + 64 <= 80 * 1024;
     };
-    if (n > 64 && n <= 96 && fits(3)) return go(k_patch_factor_rt<D, RR, T, 3>, kRtThreads, rt);
-    if (n > 96 && n <= 128 && fits(4)) return go(k_patch_factor_rt<D, RR, T, 4>, kRtThreads, rt);
+    if (n > 64 && n <= 96 && fits(3)) return go(k_patch_factor_rt<D, RR, T, 3>, kRtThreads, rt(3));
+    if (n > 96 && n <= 128 && fits(4)) return go(k_patch_factor_rt<D, RR, T, 4>, kRtThreads, rt(4));
   }
   return go(k_patch_factor<D, RR, T>, kBlock, lds);
 }
