@@ -544,7 +544,7 @@ __global__ __launch_bounds__(kBlock) void k_patch_factor(
 // scaled, and it is divided by a_pk once, when the inverse is written.  The wavefront
 // owning the next column publishes that column, its pivot and the reciprocal to LDS
 // during the update, and one barrier separates the steps; the pivot row reaches the
-// other lanes of its wavefront by reads of one lane.  At the end entry
+// other lanes of its wavefront by a lane permutation.  At the end entry
 // (i, j) of the exchanged matrix is entry (step at which row i was the pivot, pivot row
 // of step j) of the inverse.
 constexpr int kRtThreads = 1024;
@@ -695,12 +695,9 @@ __global__ __launch_bounds__(kRtThreads, 8) void k_patch_factor_rt(
     const int pr = pv / TM, pa = pv - pr * TM;
     // the pivot row of this lane's columns, from lane pr of this half
     T rrow[TM];
+    const int src = (half << 5) + pr;
 #pragma unroll
-    for (int c = 0; c < TM; ++c) {
-      const T e = t[pa * TM + c];
-      const T v0 = lane_read(e, pr), v1 = lane_read(e, pr + 32);
-      rrow[c] = (half ? v1 : v0) * ip;
-    }
+    for (int c = 0; c < TM; ++c) rrow[c] = __shfl(t[pa * TM + c], src, 64) * ip;
     if (ri == pr) used |= 1u << pa;
     const int ck = kk / TM;
     if ((ck >> 1) == w) {
