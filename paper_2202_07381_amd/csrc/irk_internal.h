@@ -315,6 +315,8 @@ struct Handle {
   // Allocated on first use; nw_active switches the V-cycle to these operators.
   bool nw_active = false, nw_ready = false;
   std::vector<double*> nw_vals, nw_inv;
+  std::vector<double*> nw_sl;     // the blocks in the sliced order of each level (residual)
+  std::vector<int32_t*> nw_src;   // CSR position of each sliced entry of the velocity operator
   std::vector<int32_t*> nw_ld;
   std::vector<int64_t*> nw_off;
   double *nw_cinv = nullptr, *nw_cmat = nullptr, *nw_ctmp = nullptr, *nw_colk = nullptr;
@@ -369,9 +371,15 @@ hipError_t patch_factor_range(const DevLevel& L, const DevOps<T>& ops, int R, co
                               const T* nw = nullptr);
 // r = F - J x (F null: J x) on a level for the Newton Jacobian of the Navier--Stokes stage
 // equations, block (s, t) = delta_st M + dt a_st [N_s B; B^T 0], with N_s = K + N'(U_s)
-// as dim x dim blocks on the scalar pattern: nw[(p r + s) dim^2 + c dim + e] (FP64).
-hipError_t residual_newton(const DevLevel& L, const double* nw, const double* A, double dt, const double* F,
+// as dim x dim blocks on the scalar pattern, nw[(p r + s) dim^2 + c dim + e] at CSR
+// position p, given in the sliced order of the level's velocity operator (sell_blocks
+// with k = r dim^2) (FP64).
+hipError_t residual_newton(const DevLevel& L, const double* nws, const double* A, double dt, const double* F,
                            const double* x, double* y, hipStream_t s);
+// out = the values v (k per CSR entry) in the sliced order, value q of sliced entry e at
+// ((e / 64) k + q) 64 + e mod 64; src[e] is the CSR position of sliced entry e (-1: padding,
+// value 0); ne sliced entries (a multiple of 64)
+hipError_t sell_blocks(int64_t ne, int k, const int32_t* src, const double* v, double* out, hipStream_t s);
 // Complex eigenvalue pair block b (a + ib): invert C = M_v + dt (a - ib) S_v per patch in
 // LDS and write (Re, Im) of C^{-1} into the factored layout; zr = dt a, zi = -dt b.
 // hipErrorInvalidConfiguration when the n_s x n_s complex matrix does not fit in LDS.

@@ -155,7 +155,7 @@ template <typename T>
 hipError_t lev_residual(Handle* h, int l, const DevOps<T>& o, const double* A, const T* b, const T* x, T* y,
                         hipStream_t s) {
   if constexpr (std::is_same<T, double>::value) {
-    if (h->nw_active) return k::residual_newton(h->dev[l], h->nw_vals[l], h->A, h->dt, b, x, y, s);
+    if (h->nw_active) return k::residual_newton(h->dev[l], h->nw_sl[l], h->A, h->dt, b, x, y, s);
   }
   return k::residual<T>(h->dev[l], o, A, h->dt, b, x, y, s);
 }
@@ -425,7 +425,8 @@ irk_status ns_stage_values(irk_mg* h, const double* state, const double* k_int, 
 // Operators of the Newton Jacobian V-cycle (Sec. 3.2) at the stage velocities in ns_U
 // (finest level): the stage velocities carried to every coarser level by injection (its
 // P2 nodes are nodes of the next finer level), the per-stage velocity blocks
-// K + N'(U_i) assembled on the host for every level, the stage-coupled patch matrices
+// K + N'(U_i) assembled on the GPU for every level (and copied to the sliced order of the
+// residual), the stage-coupled patch matrices
 // factorised on the GPU in the dense form, and the coarse operator inverted on the
 // GPU.  Allocates on first use; FP64 handles only.
 irk_status nw_build(irk_mg* h, hipStream_t s) {
@@ -434,12 +435,18 @@ irk_status nw_build(irk_mg* h, hipStream_t s) {
   constexpr int VEC = 2;  // dense inverse columns padded to 16-byte words
   if (!h->nw_ready) {
     h->nw_vals.assign(nl, nullptr);
+    h->nw_sl.assign(nl, nullptr);
+    h->nw_src.assign(nl, nullptr);
     h->nw_inv.assign(nl, nullptr);
     h->nw_ld.assign(nl, nullptr);
     h->nw_off.assign(nl, nullptr);
     for (int l = 0; l < nl; ++l) {
       const HostLevel& H = h->host[l];
       CHK(dalloc(h, &h->nw_vals[l], H.s_col.size() * r * dd));
+      std::vector<int32_t> src(H.sell_s.src.size());
+      for (size_t e = 0; e < src.size(); ++e) src[e] = (int32_t)H.sell_s.src[e];
+      CHK(upload(h, &h->nw_src[l], src, s));
+      CHK(dalloc(h, &h->nw_sl[l], src.size() * r * dd));
       if (l == 0) continue;
       const DevLevel& D = h->dev[l];
       std::vector<int32_t> ld(D.npatch);
@@ -498,6 +505,7 @@ irk_status nw_build(irk_mg* h, hipStream_t s) {
     HIPCHK(k::newton_blocks(d, r, H.nfree, h->dev[l].s_ptr, h->dev[l].s_col, h->nwa_K1[l], h->nu, h->nwa_geo[l],
                             h->nwa_cn[l], h->nwa_cf[l], h->nwa_inc_ptr[l], h->nwa_inc[l], h->nwa_C, h->nwa_U[l],
                             h->nw_vals[l], s));
+    HIPCHK(k::sell_blocks((int64_t)H.sell_s.src.size(), r * dd, h->nw_src[l], h->nw_vals[l], h->nw_sl[l], s));
     if (l == 0) {
       // the dense coarse operator is built on the host from the coarsest level's blocks
       std::vector<double> vals(H.s_col.size() * r * dd);

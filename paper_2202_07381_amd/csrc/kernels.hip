@@ -289,91 +289,128 @@ __global__ __launch_bounds__(256) void k_residual_sell(
 // r = F - J x (F null: r = J x) for the Newton Jacobian of the Navier--Stokes stage
 // equations (Sec. 3.2): block (s, t) = delta_st M + dt a_st [N_s B; B^T 0] with the
 // per-stage velocity operator N_s = K + N'(U_s) kept as dim x dim blocks on the scalar
-// pattern, nw[(p R + s) D^2 + c D + e].  N_s depends on the row's stage, so each
-// gathered column is first mixed into its stage combinations z_s = sum_t dt a_st x_t and
-// N_s applied to z_s; the B part is stage-independent and mixed once per row.  One
-// thread per row (velocity rows node-major, then vertex rows).
+// pattern.  N_s depends on the row's stage, so each gathered column is first mixed into
+// its stage combinations z_s = sum_t dt a_st x_t and N_s applied to z_s; the B part is
+// stage-independent and mixed once per row.  The sliced layout of k_residual_sell (a
+// wavefront per slice of 64 rows, lane = row, velocity slices then vertex slices), with
+// the blocks copied to the sliced order by k_sell_blocks: value q of sliced entry e at
+// ((e / 64) R D^2 + q) 64 + e mod 64, so that every value is one coalesced load.  Each
+// row sums its entries in CSR order (padding entries add zeros).
 template <int D, int R>
-__global__ __launch_bounds__(kBlock) void k_residual_newton(
-    int64_t nfree, int64_t nv, int64_t offV, const int32_t* __restrict__ s_ptr, const int32_t* __restrict__ s_col,
-    const double* __restrict__ sM, const double* __restrict__ nw, const int32_t* __restrict__ b_ptr,
-    const int32_t* __restrict__ b_col, const double* __restrict__ b_val, const int32_t* __restrict__ bt_ptr,
-    const int32_t* __restrict__ bt_col, const double* __restrict__ bt_val, Coef<double> dtA,
-    const double* __restrict__ F, const double* __restrict__ x, double* __restrict__ y) {
-  constexpr int DR = D * R;
-  const int64_t row = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (row < nfree) {
+__global__ __launch_bounds__(256) void k_residual_newton_sell(
+    int64_t nfree, int64_t nv, int64_t offV, int64_t nsu, int64_t nsp, const int32_t* __restrict__ su_off,
+    const int32_t* __restrict__ su_w, const int32_t* __restrict__ su_col, const double* __restrict__ uM,
+    const double* __restrict__ nws, const int32_t* __restrict__ sb_off, const int32_t* __restrict__ sb_w,
+    const int32_t* __restrict__ sb_col, const double* __restrict__ uB, const int32_t* __restrict__ sp_off,
+    const int32_t* __restrict__ sp_w, const int32_t* __restrict__ sp_col, const double* __restrict__ pBt,
+    Coef<double> dtA, const double* __restrict__ F, const double* __restrict__ x, double* __restrict__ y) {
+  constexpr int DR = D * R, RDD = R * D * D;
+  const int lane = threadIdx.x & 63;
+  const int64_t sl = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (sl < nsu) {
     double acc[DR], ab[DR];
 #pragma unroll
     for (int q = 0; q < DR; ++q) acc[q] = ab[q] = 0.0;
-    for (int32_t p = s_ptr[row]; p < s_ptr[row + 1]; ++p) {
-      const int64_t j = s_col[p];
-      double xv[DR], z[DR];
+    {
+      const int w = su_w[sl];
+      const int64_t e0 = su_off[sl] + lane;
+      for (int k = 0; k < w; ++k) {
+        const int64_t e = e0 + (int64_t)k * 64;
+        const int64_t j = su_col[e];
+        double xv[DR], z[DR];
 #pragma unroll
-      for (int q = 0; q < DR; ++q) xv[q] = x[j * DR + q];
-      const double m = sM[p];
+        for (int q = 0; q < DR; ++q) xv[q] = x[j * DR + q];
+        const double m = uM[e];
 #pragma unroll
-      for (int e = 0; e < D; ++e)
+        for (int ee = 0; ee < D; ++ee)
 #pragma unroll
-        for (int st = 0; st < R; ++st) {
-          double v = 0.0;
+          for (int st = 0; st < R; ++st) {
+            double v = 0.0;
 #pragma unroll
-          for (int t = 0; t < R; ++t) v += dtA.v[st * R + t] * xv[e * R + t];
-          z[e * R + st] = v;
-        }
-      const double* nwp = nw + (int64_t)p * R * D * D;
+            for (int t = 0; t < R; ++t) v += dtA.v[st * R + t] * xv[ee * R + t];
+            z[ee * R + st] = v;
+          }
+        const double* nwp = nws + (e >> 6) * RDD * 64 + lane;
 #pragma unroll
-      for (int st = 0; st < R; ++st)
+        for (int st = 0; st < R; ++st)
+#pragma unroll
+          for (int c = 0; c < D; ++c) {
+            double v = m * xv[c * R + st];
+#pragma unroll
+            for (int ee = 0; ee < D; ++ee) v += nwp[(int64_t)((st * D + c) * D + ee) * 64] * z[ee * R + st];
+            acc[c * R + st] += v;
+          }
+      }
+    }
+    {
+      const int w = sb_w[sl];
+      const int64_t e0 = sb_off[sl] + lane;
+      for (int k = 0; k < w; ++k) {
+        const int64_t e = e0 + (int64_t)k * 64;
+        const int64_t v = sb_col[e];
 #pragma unroll
         for (int c = 0; c < D; ++c) {
-          double v = m * xv[c * R + st];
+          const double bv = uB[e * D + c];
 #pragma unroll
-          for (int e = 0; e < D; ++e) v += nwp[(st * D + c) * D + e] * z[e * R + st];
-          acc[c * R + st] += v;
+          for (int t = 0; t < R; ++t) ab[c * R + t] += bv * x[offV + v * R + t];
+        }
+      }
+    }
+    const int64_t row = sl * 64 + lane;
+    if (row < nfree) {
+#pragma unroll
+      for (int c = 0; c < D; ++c)
+#pragma unroll
+        for (int st = 0; st < R; ++st) {
+          double v = acc[c * R + st];
+#pragma unroll
+          for (int t = 0; t < R; ++t) v += dtA.v[st * R + t] * ab[c * R + t];
+          const int64_t o = row * DR + c * R + st;
+          y[o] = F ? F[o] - v : v;
         }
     }
-    for (int32_t q = b_ptr[row]; q < b_ptr[row + 1]; ++q) {
-      const int64_t v = b_col[q];
-#pragma unroll
-      for (int c = 0; c < D; ++c) {
-        const double bv = b_val[(int64_t)q * D + c];
-#pragma unroll
-        for (int t = 0; t < R; ++t) ab[c * R + t] += bv * x[offV + v * R + t];
-      }
-    }
-#pragma unroll
-    for (int c = 0; c < D; ++c)
-#pragma unroll
-      for (int st = 0; st < R; ++st) {
-        double v = acc[c * R + st];
-#pragma unroll
-        for (int t = 0; t < R; ++t) v += dtA.v[st * R + t] * ab[c * R + t];
-        const int64_t o = row * DR + c * R + st;
-        y[o] = F ? F[o] - v : v;
-      }
-  } else if (row < nfree + nv) {
-    const int64_t vx = row - nfree;
+  } else if (sl < nsu + nsp) {
+    const int64_t ps = sl - nsu;
     double a[R];
 #pragma unroll
     for (int t = 0; t < R; ++t) a[t] = 0.0;
-    for (int32_t q = bt_ptr[vx]; q < bt_ptr[vx + 1]; ++q) {
-      const int64_t j = bt_col[q];
+    const int w = sp_w[ps];
+    const int64_t e0 = sp_off[ps] + lane;
+    for (int k = 0; k < w; ++k) {
+      const int64_t e = e0 + (int64_t)k * 64;
+      const int64_t j = sp_col[e];
 #pragma unroll
       for (int c = 0; c < D; ++c) {
-        const double bv = bt_val[(int64_t)q * D + c];
+        const double bv = pBt[e * D + c];
 #pragma unroll
         for (int t = 0; t < R; ++t) a[t] += bv * x[j * DR + c * R + t];
       }
     }
+    const int64_t vx = ps * 64 + lane;
+    if (vx < nv) {
 #pragma unroll
-    for (int st = 0; st < R; ++st) {
-      double v = 0.0;
+      for (int st = 0; st < R; ++st) {
+        double v = 0.0;
 #pragma unroll
-      for (int t = 0; t < R; ++t) v += dtA.v[st * R + t] * a[t];
-      const int64_t o = offV + vx * R + st;
-      y[o] = F ? F[o] - v : v;
+        for (int t = 0; t < R; ++t) v += dtA.v[st * R + t] * a[t];
+        const int64_t o = offV + vx * R + st;
+        y[o] = F ? F[o] - v : v;
+      }
     }
   }
+}
+
+// Values of a CSR value array (k per entry) in the sliced order of k_residual_newton_sell:
+// out[((e / 64) k + q) 64 + e mod 64] = v[src[e] k + q], zero for padding (src < 0).
+__global__ __launch_bounds__(kBlock) void k_sell_blocks(int64_t ne, int k, const int32_t* __restrict__ src,
+                                                        const double* __restrict__ v, double* __restrict__ out) {
+  const int64_t o = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (o >= ne * k) return;
+  const int64_t rest = o >> 6, blk = rest / k;
+  const int q = (int)(rest - blk * k);
+  const int64_t e = blk * 64 + (o & 63);
+  const int32_t p = src[e];
+  out[o] = p >= 0 ? v[(int64_t)p * k + q] : 0.0;
 }
 
 // ------------------------------------------------------------------ patch factorise
@@ -2089,13 +2126,19 @@ hipError_t residual(const DevLevel& L, const DevOps<T>& ops, const double* A, do
   return hipGetLastError();
 }
 
-hipError_t residual_newton(const DevLevel& L, const double* nw, const double* A, double dt, const double* F,
+hipError_t residual_newton(const DevLevel& L, const double* nws, const double* A, double dt, const double* F,
                            const double* x, double* y, hipStream_t s) {
-  const unsigned g = blocks_for(L.nfree + L.nv);
-  IRK_DISPATCH_DR(L.dim, L.r, (k_residual_newton<DD, RR><<<dim3(g), dim3(kBlock), 0, s>>>(
-                                  L.nfree, L.nv, L.offV, L.s_ptr, L.s_col, L.d64.s_M, nw, L.b_ptr, L.b_col,
-                                  L.d64.b_val, L.bt_ptr, L.bt_col, L.d64.bt_val, scaled<double, RR>(A, dt), F, x,
-                                  y)));
+  const unsigned g = (unsigned)std::max<int64_t>(1, (L.nsl_u + L.nsl_p + 3) / 4);
+  IRK_DISPATCH_DR(L.dim, L.r, (k_residual_newton_sell<DD, RR><<<dim3(g), dim3(256), 0, s>>>(
+                                  L.nfree, L.nv, L.offV, L.nsl_u, L.nsl_p, L.su_off, L.su_w, L.su_col, L.d64.u_M,
+                                  nws, L.sb_off, L.sb_w, L.sb_col, L.d64.u_B, L.sp_off, L.sp_w, L.sp_col,
+                                  L.d64.p_Bt, scaled<double, RR>(A, dt), F, x, y)));
+  return hipGetLastError();
+}
+
+hipError_t sell_blocks(int64_t ne, int k, const int32_t* src, const double* v, double* out, hipStream_t s) {
+  if (ne <= 0) return hipSuccess;
+  k_sell_blocks<<<dim3(blocks_for(ne * k)), dim3(kBlock), 0, s>>>(ne, k, src, v, out);
   return hipGetLastError();
 }
 
