@@ -2,7 +2,7 @@
 7 levels, 1,764,873 unknowns, the first step of the seeded manufactured solution), in the
 patch form the benchmark uses (automatic: symmetric factored).  The oracle hierarchy needs
 about 35 GB of host memory (the test is skipped on hosts with less than 64 GB) and about
-a minute and a half of setup; the whole test takes about two minutes on the GPU machine
+a minute and a half of setup; the whole test takes about two minutes on one MI355X
 (measured: V-cycle 1.5e-13, FGMRES 13 iterations on both sides with solution error
 4.3e-12, FP32-patch residual 3.0e-9 and error 1.1e-11 against the oracle's FP64 solution).
 Bars as at 128 x 128: the
