@@ -827,6 +827,57 @@ constexpr int kGjBw = 16;     // panel width
 constexpr int kGjJt = 64;     // columns per update tile
 constexpr int kGjRows = 4;    // rows per thread (n <= 1024)
 
+// Rank-bw update of k_patch_factor_global on the matrix cores (FP64): the columns outside
+// the panel [kb, kb + bw) receive A[:, j] <- (A[:, j], pivot rows zeroed) + P A_old[pivot rows,
+// j], P the panel's transform (P[c n + i], LDS), in tiles of 16 rows x 16 columns, one
+// wavefront per tile, the tile accumulated by four v_mfma_f64_16x16x4 steps over the bw <= 16
+// panel columns.  The product is formed transposed (A_old[pivot rows, j]^T P^T) so that
+// the accumulator's lanes run along rows: lane l, element v of a tile holds row
+// i0 + l mod 16 of column j0 + l / 16 + 4 v, and 16 lanes read and write 16 consecutive
+// entries of one column.  Operand layouts of the instruction: lane l holds A(l mod 16,
+// l / 16), B(l / 16, l mod 16).  Ak stages the pivot rows of kGjJt columns at a time.
+__device__ __forceinline__ void gj_update_mfma(double* __restrict__ Am, int ld, int n, int kb, int bw,
+                                               const double* P, double* Ak) {
+  typedef double d4 __attribute__((ext_vector_type(4)));
+  const int tid = threadIdx.x, wv = tid >> 6, ln = tid & 63;
+  const int lr = ln & 15, lk = ln >> 4;
+  const int nrt = (n + 15) / 16;
+  for (int j0 = 0; j0 < n; j0 += kGjJt) {
+    const int jt = min(kGjJt, n - j0);
+    for (int e = tid; e < kGjBw * kGjJt; e += blockDim.x) {
+      const int c = e / kGjJt, jj = e - c * kGjJt;
+      Ak[e] = (c < bw && jj < jt) ? Am[(int64_t)(j0 + jj) * ld + kb + c] : 0.0;
+    }
+    __syncthreads();
+    const int nct = (jt + 15) / 16;
+    for (int tI = wv; tI < nrt * nct; tI += blockDim.x / 64) {
+      const int rt = tI / nct, ct = tI - rt * nct;
+      const int i = rt * 16 + lr;  // this lane's row
+      const bool rok = i < n, rpan = i >= kb && i < kb + bw;
+      d4 acc;
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int jj = ct * 16 + lk + 4 * v, j = j0 + jj;
+        const bool cok = jj < jt && !(j >= kb && j < kb + bw);
+        acc[v] = (cok && rok && !rpan) ? Am[(int64_t)j * ld + i] : 0.0;
+      }
+#pragma unroll
+      for (int kq = 0; kq < kGjBw / 4; ++kq) {
+        const int c = kq * 4 + lk;
+        const double a = Ak[c * kGjJt + ct * 16 + lr];  // A(lr, lk): pivot row c, column ct*16 + lr
+        const double b = (c < bw && rok) ? P[c * n + i] : 0.0;  // B(lk, lr): P(i, c)
+        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc, 0, 0, 0);
+      }
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int jj = ct * 16 + lk + 4 * v, j = j0 + jj;
+        if (jj < jt && !(j >= kb && j < kb + bw) && rok) Am[(int64_t)j * ld + i] = acc[v];
+      }
+    }
+    __syncthreads();
+  }
+}
+
 template <int D, int R, typename T>
 __global__ __launch_bounds__(kBlock) void k_patch_factor_global(
     int64_t npatch, const int32_t* __restrict__ pn_ptr, const int32_t* __restrict__ pvv_ptr,
@@ -959,6 +1010,9 @@ __global__ __launch_bounds__(kBlock) void k_patch_factor_global(
       __syncthreads();
     }
     // rank-bw update of the other columns
+    if constexpr (std::is_same<T, double>::value) {
+      gj_update_mfma(Am, ld, n, kb, bw, P, Ak);
+    } else {
     T pr[kGjRows][kGjBw];
 #pragma unroll
     for (int rr = 0; rr < kGjRows; ++rr) {
@@ -988,6 +1042,7 @@ __global__ __launch_bounds__(kBlock) void k_patch_factor_global(
         }
       }
       __syncthreads();
+    }
     }
     for (int e = tid; e < bw * n; e += blockDim.x) {
       const int c = e / n, i = e - c * n;
