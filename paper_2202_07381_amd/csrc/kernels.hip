@@ -295,8 +295,10 @@ __global__ __launch_bounds__(256) void k_residual_sell(
 // wavefront per slice of 64 rows, lane = row, velocity slices then vertex slices), with
 // the blocks copied to the sliced order by k_sell_blocks: value q of sliced entry e at
 // ((e / 64) R D^2 + q) 64 + e mod 64, so that every value is one coalesced load.  Each
-// row sums its entries in CSR order (padding entries add zeros).
-template <int D, int R>
+// row sums its entries in CSR order (padding entries add zeros); with NW = 2 (levels of
+// fewer than kSplitSlices slices, latency-bound) two wavefronts take alternate entries of
+// a slice and add their sums through LDS.
+template <int D, int R, int NW>
 __global__ __launch_bounds__(256) void k_residual_newton_sell(
     int64_t nfree, int64_t nv, int64_t offV, int64_t nsu, int64_t nsp, const int32_t* __restrict__ su_off,
     const int32_t* __restrict__ su_w, const int32_t* __restrict__ su_col, const double* __restrict__ uM,
@@ -305,16 +307,21 @@ __global__ __launch_bounds__(256) void k_residual_newton_sell(
     const int32_t* __restrict__ sp_w, const int32_t* __restrict__ sp_col, const double* __restrict__ pBt,
     Coef<double> dtA, const double* __restrict__ F, const double* __restrict__ x, double* __restrict__ y) {
   constexpr int DR = D * R, RDD = R * D * D;
+  constexpr int kSlices = 4 / NW;  // slices per workgroup of four wavefronts
+  __shared__ double part[NW == 2 ? kSlices : 1][NW == 2 ? 2 * DR : 1][64];
   const int lane = threadIdx.x & 63;
-  const int64_t sl = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
-  if (sl < nsu) {
-    double acc[DR], ab[DR];
+  const int half = (threadIdx.x >> 6) % NW;
+  const int pair = (threadIdx.x >> 6) / NW;
+  const int64_t sl = (int64_t)blockIdx.x * kSlices + pair;
+  // wavefront `half` of the slice takes entries k = half, half + NW, ...
+  double acc[DR], ab[DR];
 #pragma unroll
-    for (int q = 0; q < DR; ++q) acc[q] = ab[q] = 0.0;
+  for (int q = 0; q < DR; ++q) acc[q] = ab[q] = 0.0;
+  if (sl < nsu) {
     {
       const int w = su_w[sl];
       const int64_t e0 = su_off[sl] + lane;
-      for (int k = 0; k < w; ++k) {
+      for (int k = half; k < w; k += NW) {
         const int64_t e = e0 + (int64_t)k * 64;
         const int64_t j = su_col[e];
         double xv[DR], z[DR];
@@ -345,7 +352,7 @@ __global__ __launch_bounds__(256) void k_residual_newton_sell(
     {
       const int w = sb_w[sl];
       const int64_t e0 = sb_off[sl] + lane;
-      for (int k = 0; k < w; ++k) {
+      for (int k = half; k < w; k += NW) {
         const int64_t e = e0 + (int64_t)k * 64;
         const int64_t v = sb_col[e];
 #pragma unroll
@@ -356,6 +363,39 @@ __global__ __launch_bounds__(256) void k_residual_newton_sell(
         }
       }
     }
+  } else if (sl < nsu + nsp) {
+    // vertex rows: the R sums go to acc[0 .. R)
+    const int64_t ps = sl - nsu;
+    const int w = sp_w[ps];
+    const int64_t e0 = sp_off[ps] + lane;
+    for (int k = half; k < w; k += NW) {
+      const int64_t e = e0 + (int64_t)k * 64;
+      const int64_t j = sp_col[e];
+#pragma unroll
+      for (int c = 0; c < D; ++c) {
+        const double bv = pBt[e * D + c];
+#pragma unroll
+        for (int t = 0; t < R; ++t) acc[t] += bv * x[j * DR + c * R + t];
+      }
+    }
+  }
+  if constexpr (NW == 2) {
+    if (half) {
+#pragma unroll
+      for (int q = 0; q < DR; ++q) {
+        part[pair][q][lane] = acc[q];
+        part[pair][DR + q][lane] = ab[q];
+      }
+    }
+    __syncthreads();
+    if (half) return;
+#pragma unroll
+    for (int q = 0; q < DR; ++q) {
+      acc[q] += part[pair][q][lane];
+      ab[q] += part[pair][DR + q][lane];
+    }
+  }
+  if (sl < nsu) {
     const int64_t row = sl * 64 + lane;
     if (row < nfree) {
 #pragma unroll
@@ -370,29 +410,13 @@ __global__ __launch_bounds__(256) void k_residual_newton_sell(
         }
     }
   } else if (sl < nsu + nsp) {
-    const int64_t ps = sl - nsu;
-    double a[R];
-#pragma unroll
-    for (int t = 0; t < R; ++t) a[t] = 0.0;
-    const int w = sp_w[ps];
-    const int64_t e0 = sp_off[ps] + lane;
-    for (int k = 0; k < w; ++k) {
-      const int64_t e = e0 + (int64_t)k * 64;
-      const int64_t j = sp_col[e];
-#pragma unroll
-      for (int c = 0; c < D; ++c) {
-        const double bv = pBt[e * D + c];
-#pragma unroll
-        for (int t = 0; t < R; ++t) a[t] += bv * x[j * DR + c * R + t];
-      }
-    }
-    const int64_t vx = ps * 64 + lane;
+    const int64_t vx = (sl - nsu) * 64 + lane;
     if (vx < nv) {
 #pragma unroll
       for (int st = 0; st < R; ++st) {
         double v = 0.0;
 #pragma unroll
-        for (int t = 0; t < R; ++t) v += dtA.v[st * R + t] * a[t];
+        for (int t = 0; t < R; ++t) v += dtA.v[st * R + t] * acc[t];
         const int64_t o = offV + vx * R + st;
         y[o] = F ? F[o] - v : v;
       }
@@ -2183,8 +2207,18 @@ hipError_t residual(const DevLevel& L, const DevOps<T>& ops, const double* A, do
 
 hipError_t residual_newton(const DevLevel& L, const double* nws, const double* A, double dt, const double* F,
                            const double* x, double* y, hipStream_t s) {
-  const unsigned g = (unsigned)std::max<int64_t>(1, (L.nsl_u + L.nsl_p + 3) / 4);
-  IRK_DISPATCH_DR(L.dim, L.r, (k_residual_newton_sell<DD, RR><<<dim3(g), dim3(256), 0, s>>>(
+  const int64_t nsl = L.nsl_u + L.nsl_p;
+  if (nsl < kSplitSlices) {
+    // latency-bound levels: two wavefronts per slice
+    const unsigned g = (unsigned)std::max<int64_t>(1, (nsl + 1) / 2);
+    IRK_DISPATCH_DR(L.dim, L.r, (k_residual_newton_sell<DD, RR, 2><<<dim3(g), dim3(256), 0, s>>>(
+                                    L.nfree, L.nv, L.offV, L.nsl_u, L.nsl_p, L.su_off, L.su_w, L.su_col,
+                                    L.d64.u_M, nws, L.sb_off, L.sb_w, L.sb_col, L.d64.u_B, L.sp_off, L.sp_w,
+                                    L.sp_col, L.d64.p_Bt, scaled<double, RR>(A, dt), F, x, y)));
+    return hipGetLastError();
+  }
+  const unsigned g = (unsigned)std::max<int64_t>(1, (nsl + 3) / 4);
+  IRK_DISPATCH_DR(L.dim, L.r, (k_residual_newton_sell<DD, RR, 1><<<dim3(g), dim3(256), 0, s>>>(
                                   L.nfree, L.nv, L.offV, L.nsl_u, L.nsl_p, L.su_off, L.su_w, L.su_col, L.d64.u_M,
                                   nws, L.sb_off, L.sb_w, L.sb_col, L.d64.u_B, L.sp_off, L.sp_w, L.sp_col,
                                   L.d64.p_Bt, scaled<double, RR>(A, dt), F, x, y)));
