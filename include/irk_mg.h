@@ -376,14 +376,16 @@ irk_status irk_ns_newton_solve(irk_mg* h, const double* F, const double* state, 
  * dt a_ij [K + N'(U_i) B; B^T 0], not a Kronecker product, rediscretised on every level
  * at the stage velocities U_i of (state, k, g_stages) (as for irk_ns_residual) carried to
  * the coarser levels by injection at their P2 nodes (which are nodes of the next finer
- * level).  enable = 1 assembles the per-stage velocity blocks of every level (on the
- * host), factorises the stage-coupled patch matrices of every level in the dense form
- * and inverts the coarse operator (on the GPU), and switches the handle's V-cycle
+ * level).  enable = 1 assembles the per-stage velocity blocks of every level,
+ * factorises the stage-coupled patch matrices of every level in the dense form and
+ * inverts the coarse operator (all on the GPU; the coarsest level's blocks pass through
+ * the host for its dense operator), and switches the handle's V-cycle
  * (irk_mg_vcycle, irk_level_sweep, irk_level_apply, irk_coarse_solve, and the
  * preconditioner of irk_fgmres_solve) to these operators; enable = 0 switches back to
  * the handle's own operator (state, g_stages and k are then not read).  FP64 handles
  * only; no transposed form while enabled (IRK_EINVAL).  The first call allocates the
- * per-stage blocks (r dim^2 doubles per entry of each level's scalar pattern), the dense
+ * per-stage blocks (r dim^2 doubles per entry of each level's scalar pattern, and again
+ * in the sliced order of the residual kernel), the element data of every level, the dense
  * patch inverses (sum over patches of (r n_v)^2 doubles per level) and three dense
  * coarse matrices.  Synchronises `stream`.  Errors: IRK_EINVAL, IRK_ESINGULAR (zero
  * pivot), IRK_ENOMEM, IRK_EHIP. */
