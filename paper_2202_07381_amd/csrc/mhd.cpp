@@ -11,6 +11,7 @@
 #include <cstring>
 #include <numeric>
 #include <string>
+#include <type_traits>
 #include <vector>
 
 #include "mhd_internal.h"
@@ -110,9 +111,16 @@ template <typename T, typename Src>
 irk_status upload(irk_mhd* h, T** p, const std::vector<Src>& v, hipStream_t s) {
   CHK(dalloc(h, p, v.size()));
   if (v.empty()) return IRK_OK;
-  std::vector<T> tmp(v.begin(), v.end());
-  HIPCHK(hipMemcpyAsync(*p, tmp.data(), tmp.size() * sizeof(T), hipMemcpyHostToDevice, s));
-  HIPCHK(hipStreamSynchronize(s));
+  // same element type: copied from the source itself (no staging copy); the wait keeps
+  // the source (or the converted copy) alive until the transfer has read it
+  if constexpr (std::is_same<T, Src>::value) {
+    HIPCHK(hipMemcpyAsync(*p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice, s));
+    HIPCHK(hipStreamSynchronize(s));
+  } else {
+    std::vector<T> tmp(v.begin(), v.end());
+    HIPCHK(hipMemcpyAsync(*p, tmp.data(), tmp.size() * sizeof(T), hipMemcpyHostToDevice, s));
+    HIPCHK(hipStreamSynchronize(s));
+  }
   return IRK_OK;
 }
 

@@ -13,8 +13,12 @@
 // reduces exactly to the moments int lam_i lam_j / |T| = (1 + delta_ij) / 12,
 // int lam_i / |T| = 1/3 and int phi_a lam_i / |T| (phi_a a P2 basis function).
 #include <algorithm>
+#include <climits>
 #include <cmath>
+#include <cstdint>
+#include <exception>
 #include <stdexcept>
+#include <thread>
 #include <utility>
 
 #include "mhd_internal.h"
@@ -86,6 +90,58 @@ void cell_dofs(const MhdHost& H, int64_t c, CellDofs& d) {
   }
 }
 
+// body(lo, hi) over contiguous ranges of [0, n) on up to 16 host threads, at least `grain`
+// items each; the ranges partition [0, n) in order.  An exception thrown by a range is
+// rethrown on the calling thread after every range has finished.
+template <typename F>
+void parallel_ranges(int64_t n, F&& body, int64_t grain = 4096) {
+  const int nt = (int)std::max<int64_t>(1, std::min<int64_t>({16, (int64_t)std::thread::hardware_concurrency(),
+                                                              n / grain}));
+  if (nt == 1) {
+    body((int64_t)0, n);
+    return;
+  }
+  std::vector<std::exception_ptr> err(nt);
+  std::vector<std::thread> pool;
+  for (int t = 0; t < nt; ++t)
+    pool.emplace_back([&body, &err, n, nt, t] {
+      try {
+        body(n * t / nt, n * (t + 1) / nt);
+      } catch (...) {
+        err[t] = std::current_exception();
+      }
+    });
+  for (auto& th : pool) th.join();
+  for (auto& e : err)
+    if (e) std::rethrow_exception(e);
+}
+
+// Cells grouped so that no two cells of a group share a vertex (greedy, in cell order):
+// every row a cell's element matrix touches belongs to one of its vertices or edges, so
+// the cells of one group scatter into disjoint rows and can be assembled concurrently.
+// group g holds cells[gptr[g] .. gptr[g+1]), ascending.
+void vertex_disjoint_groups(const HostLevel& L, std::vector<int64_t>& gptr, std::vector<int64_t>& cells) {
+  std::vector<uint64_t> used(L.nv, 0);
+  std::vector<int8_t> colour(L.nc);
+  int ng = 0;
+  for (int64_t c = 0; c < L.nc; ++c) {
+    const int64_t* v = &L.cells[c * 3];
+    const uint64_t taken = used[v[0]] | used[v[1]] | used[v[2]];
+    if (taken == ~0ull) throw std::runtime_error("MHD assembly: more than 64 cells around a vertex");
+    int g = 0;
+    while (taken >> g & 1) ++g;
+    colour[c] = (int8_t)g;
+    ng = std::max(ng, g + 1);
+    for (int j = 0; j < 3; ++j) used[v[j]] |= 1ull << g;
+  }
+  gptr.assign(ng + 1, 0);
+  for (int64_t c = 0; c < L.nc; ++c) ++gptr[colour[c] + 1];
+  for (int g = 0; g < ng; ++g) gptr[g + 1] += gptr[g];
+  cells.resize(L.nc);
+  std::vector<int64_t> fill(gptr.begin(), gptr.end() - 1);
+  for (int64_t c = 0; c < L.nc; ++c) cells[fill[colour[c]]++] = c;
+}
+
 }  // namespace
 
 void mhd_index(MhdHost& H) {
@@ -117,43 +173,40 @@ void mhd_index(MhdHost& H) {
 void mhd_assemble(MhdHost& H, double Re, double Rem, const double* w, const double* b0) {
   const HostLevel& L = H.L;
   const int64_t nf = H.nfree;
-  // ---- pattern: the couplings of the weak form within each cell
+  // ---- pattern: the couplings of the weak form within each cell; a row's columns are
+  // the unknowns its cells couple it to, so each row is gathered from the cells around
+  // its node (rows independent, built concurrently)
   {
     std::vector<std::vector<int32_t>> rows(H.ns);
-    CellDofs d;
-    auto add = [&](int64_t r, int64_t c) {
-      if (r >= 0 && c >= 0) rows[r].push_back((int32_t)c);
-    };
-    for (int64_t c = 0; c < L.nc; ++c) {
-      cell_dofs(H, c, d);
-      for (int k = 0; k < 2; ++k)
-        for (int a = 0; a < 6; ++a) {
-          const int64_t r = d.u[k][a];
-          if (r < 0) continue;
-          for (int k2 = 0; k2 < 2; ++k2)
-            for (int b = 0; b < 6; ++b) add(r, d.u[k2][b]);
-          for (int e = 0; e < 3; ++e) add(r, d.e[e]);
-          for (int j = 0; j < 3; ++j) add(r, d.p[j]);
+    parallel_ranges(H.ns, [&](int64_t r0, int64_t r1) {
+      CellDofs d;
+      for (int64_t r = r0; r < r1; ++r) {
+        std::vector<int32_t>& row = rows[r];
+        int kind;  // 0 velocity, 1 field, 2 pressure, 3 multiplier
+        int64_t node;
+        if (r < 2 * nf) kind = 0, node = L.node_of_free[r < nf ? r : r - nf];
+        else if (r < H.off_p) kind = 1, node = L.nv + H.efree[r - H.off_B];
+        else if (r < H.off_g) kind = 2, node = r - H.off_p;
+        else kind = 3, node = H.vint[r - H.off_g];
+        auto add = [&](int64_t c) {
+          if (c >= 0) row.push_back((int32_t)c);
+        };
+        for (int32_t q = L.node_cell_ptr[node]; q < L.node_cell_ptr[node + 1]; ++q) {
+          cell_dofs(H, L.node_cell[q], d);
+          if (kind <= 2)
+            for (int k2 = 0; k2 < 2; ++k2)
+              for (int b = 0; b < 6; ++b) add(d.u[k2][b]);
+          if (kind != 2)
+            for (int f = 0; f < 3; ++f) add(d.e[f]);
+          for (int j = 0; j < 3; ++j) {
+            if (kind == 0) add(d.p[j]);
+            if (kind == 1) add(d.g[j]);
+          }
         }
-      for (int e = 0; e < 3; ++e) {
-        const int64_t r = d.e[e];
-        if (r < 0) continue;
-        for (int k2 = 0; k2 < 2; ++k2)
-          for (int b = 0; b < 6; ++b) add(r, d.u[k2][b]);
-        for (int f = 0; f < 3; ++f) add(r, d.e[f]);
-        for (int j = 0; j < 3; ++j) add(r, d.g[j]);
+        std::sort(row.begin(), row.end());
+        row.erase(std::unique(row.begin(), row.end()), row.end());
       }
-      for (int j = 0; j < 3; ++j) {
-        for (int k2 = 0; k2 < 2; ++k2)
-          for (int b = 0; b < 6; ++b) add(d.p[j], d.u[k2][b]);
-        if (d.g[j] >= 0)
-          for (int f = 0; f < 3; ++f) add(d.g[j], d.e[f]);
-      }
-    }
-    for (auto& r : rows) {
-      std::sort(r.begin(), r.end());
-      r.erase(std::unique(r.begin(), r.end()), r.end());
-    }
+    });
     fe_csr_from_rows(rows, H.ptr, H.col);
   }
   H.mval.assign(H.col.size(), 0.0);
@@ -168,33 +221,36 @@ void mhd_assemble(MhdHost& H, double Re, double Rem, const double* w, const doub
   {
     std::vector<double> nw(L.s_col.size() * 4, 0.0);
     assemble_newton_block(L, 0.0, w, nw.data());
-    for (int64_t i = 0; i < nf; ++i)
-      for (int32_t p = L.s_ptr[i]; p < L.s_ptr[i + 1]; ++p) {
-        const int64_t j = L.s_col[p];
-        for (int c = 0; c < 2; ++c) {
-          const size_t q = at(c * nf + i, c * nf + j);
-          H.mval[q] += L.s_M[p];
-          H.sval[q] += L.s_K1[p] / Re;
-          for (int e = 0; e < 2; ++e) H.sval[at(c * nf + i, e * nf + j)] += nw[(size_t)p * 4 + c * 2 + e];
+    // rows of the free node i (both components): written by i's range only
+    parallel_ranges(nf, [&](int64_t i0, int64_t i1) {
+      for (int64_t i = i0; i < i1; ++i) {
+        for (int32_t p = L.s_ptr[i]; p < L.s_ptr[i + 1]; ++p) {
+          const int64_t j = L.s_col[p];
+          for (int c = 0; c < 2; ++c) {
+            const size_t q = at(c * nf + i, c * nf + j);
+            H.mval[q] += L.s_M[p];
+            H.sval[q] += L.s_K1[p] / Re;
+            for (int e = 0; e < 2; ++e) H.sval[at(c * nf + i, e * nf + j)] += nw[(size_t)p * 4 + c * 2 + e];
+          }
         }
+        for (int32_t p = L.b_ptr[i]; p < L.b_ptr[i + 1]; ++p)
+          for (int c = 0; c < 2; ++c) H.sval[at(c * nf + i, H.off_p + L.b_col[p])] += L.b_val[(size_t)p * 2 + c];
       }
-    for (int64_t i = 0; i < nf; ++i)
-      for (int32_t p = L.b_ptr[i]; p < L.b_ptr[i + 1]; ++p) {
-        const int64_t v = L.b_col[p];
-        for (int c = 0; c < 2; ++c) {
-          const double b = L.b_val[(size_t)p * 2 + c];
-          H.sval[at(c * nf + i, H.off_p + v)] += b;
-          H.sval[at(H.off_p + v, c * nf + i)] += b;
-        }
-      }
+    });
+    // pressure rows from the transposed divergence (B^T: vertex -> free nodes)
+    parallel_ranges(H.nv, [&](int64_t v0, int64_t v1) {
+      for (int64_t v = v0; v < v1; ++v)
+        for (int32_t p = L.bt_ptr[v]; p < L.bt_ptr[v + 1]; ++p)
+          for (int c = 0; c < 2; ++c) H.sval[at(H.off_p + v, c * nf + L.bt_col[p])] += L.bt_val[(size_t)p * 2 + c];
+    });
   }
   // ---- cell terms
   double T1[6][3];
   fe_p2_lam_moments(2, &T1[0][0]);
   const double* RS = fe_p2_grad_grad(2);
-  CellNed N;
-  CellDofs d;
-  for (int64_t c = 0; c < L.nc; ++c) {
+  auto cell_terms = [&](int64_t c) {
+    CellNed N;
+    CellDofs d;
     cell_nedelec(L, c, N);
     cell_dofs(H, c, d);
     const double vol = N.vol;
@@ -280,44 +336,87 @@ void mhd_assemble(MhdHost& H, double Re, double Rem, const double* w, const doub
         H.sval[at(d.g[j], d.e[g])] -= vol * s;
       }
     }
-  }
+  };
+  // cells of one vertex-disjoint group write disjoint rows
+  std::vector<int64_t> gptr, gcells;
+  vertex_disjoint_groups(L, gptr, gcells);
+  for (size_t g = 0; g + 1 < gptr.size(); ++g)
+    parallel_ranges(gptr[g + 1] - gptr[g], [&](int64_t i0, int64_t i1) {
+      for (int64_t i = i0; i < i1; ++i) cell_terms(gcells[gptr[g] + i]);
+    });
 }
 
 void mhd_patches(MhdHost& H) {
   const HostLevel& L = H.L;
+  // Vertices are independent: ranges of them are handled concurrently in two passes, the
+  // first listing each patch's unknowns and counting its coupling entries, the second
+  // writing the triples straight to their final place (no list grows while threads run).
+  const int64_t nchunks = std::max<int64_t>(1, std::min<int64_t>(256, H.nv / 1024));
+  std::vector<std::vector<int32_t>> cdof(nchunks);
   H.pptr.assign(H.nv + 1, 0);
-  H.pdof.clear();
   H.pvv_ptr.assign(H.nv + 1, 0);
-  H.pvv.clear();
-  std::vector<int32_t> dl;
-  CellDofs d;
-  for (int64_t v = 0; v < H.nv; ++v) {
-    dl.clear();
-    for (int32_t p = L.node_cell_ptr[v]; p < L.node_cell_ptr[v + 1]; ++p) {
-      cell_dofs(H, L.node_cell[p], d);
-      for (int k = 0; k < 2; ++k)
-        for (int a = 0; a < 6; ++a)
-          if (d.u[k][a] >= 0) dl.push_back((int32_t)d.u[k][a]);
-      for (int e = 0; e < 3; ++e)
-        if (d.e[e] >= 0) dl.push_back((int32_t)d.e[e]);
-    }
-    dl.push_back((int32_t)(H.off_p + v));
-    if (H.gidx[v] >= 0) dl.push_back((int32_t)(H.off_g + H.gidx[v]));
-    std::sort(dl.begin(), dl.end());
-    dl.erase(std::unique(dl.begin(), dl.end()), dl.end());
-    for (size_t la = 0; la < dl.size(); ++la)
-      for (int32_t p = H.ptr[dl[la]]; p < H.ptr[dl[la] + 1]; ++p) {
-        auto it = std::lower_bound(dl.begin(), dl.end(), H.col[p]);
-        if (it != dl.end() && *it == H.col[p]) {
-          H.pvv.push_back((int32_t)la);
-          H.pvv.push_back((int32_t)(it - dl.begin()));
-          H.pvv.push_back(p);
+  // the triples (a, b, CSR position) coupling the sorted unknowns dl of one patch, in the
+  // order of the rows of dl and, within a row, of its columns
+  auto couplings = [&](const int32_t* dl, int32_t n, int32_t* out) {
+    int32_t cnt = 0;
+    for (int32_t la = 0; la < n; ++la) {
+      int32_t p = H.ptr[dl[la]];
+      const int32_t pe = H.ptr[dl[la] + 1];
+      int32_t lb = 0;
+      while (p < pe && lb < n) {  // both sorted: one merge
+        const int32_t c = H.col[p];
+        if (c < dl[lb]) ++p;
+        else if (c > dl[lb]) ++lb;
+        else {
+          if (out) {
+            out[cnt * 3] = la;
+            out[cnt * 3 + 1] = lb;
+            out[cnt * 3 + 2] = p;
+          }
+          ++cnt, ++p, ++lb;
         }
       }
-    H.pdof.insert(H.pdof.end(), dl.begin(), dl.end());
-    H.pptr[v + 1] = (int32_t)H.pdof.size();
-    H.pvv_ptr[v + 1] = (int32_t)(H.pvv.size() / 3);
+    }
+    return cnt;
+  };
+  auto chunk_lo = [&](int64_t k) { return H.nv * k / nchunks; };
+  parallel_ranges(nchunks, [&](int64_t k0, int64_t k1) {
+    std::vector<int32_t> dl;
+    CellDofs d;
+    for (int64_t k = k0; k < k1; ++k)
+      for (int64_t v = chunk_lo(k); v < chunk_lo(k + 1); ++v) {
+        dl.clear();
+        for (int32_t p = L.node_cell_ptr[v]; p < L.node_cell_ptr[v + 1]; ++p) {
+          cell_dofs(H, L.node_cell[p], d);
+          for (int c = 0; c < 2; ++c)
+            for (int a = 0; a < 6; ++a)
+              if (d.u[c][a] >= 0) dl.push_back((int32_t)d.u[c][a]);
+          for (int e = 0; e < 3; ++e)
+            if (d.e[e] >= 0) dl.push_back((int32_t)d.e[e]);
+        }
+        dl.push_back((int32_t)(H.off_p + v));
+        if (H.gidx[v] >= 0) dl.push_back((int32_t)(H.off_g + H.gidx[v]));
+        std::sort(dl.begin(), dl.end());
+        dl.erase(std::unique(dl.begin(), dl.end()), dl.end());
+        cdof[k].insert(cdof[k].end(), dl.begin(), dl.end());
+        H.pptr[v + 1] = (int32_t)dl.size();
+        H.pvv_ptr[v + 1] = couplings(dl.data(), (int32_t)dl.size(), nullptr);
+      }
+  }, 1);
+  for (int64_t v = 0; v < H.nv; ++v) {
+    H.pptr[v + 1] += H.pptr[v];
+    if ((int64_t)H.pvv_ptr[v] + H.pvv_ptr[v + 1] > INT32_MAX)
+      throw std::runtime_error("MHD patches: more than 2^31 coupling entries on one level");
+    H.pvv_ptr[v + 1] += H.pvv_ptr[v];
   }
+  H.pdof.clear();
+  H.pdof.reserve(H.pptr[H.nv]);
+  for (const auto& c : cdof) H.pdof.insert(H.pdof.end(), c.begin(), c.end());
+  H.pvv.assign((size_t)H.pvv_ptr[H.nv] * 3, 0);
+  parallel_ranges(H.nv, [&](int64_t v0, int64_t v1) {
+    for (int64_t v = v0; v < v1; ++v)
+      couplings(&H.pdof[H.pptr[v]], H.pptr[v + 1] - H.pptr[v], &H.pvv[(size_t)H.pvv_ptr[v] * 3]);
+  });
 }
 
 std::string mhd_transfer(const MhdHost& C, MhdHost& F, const int64_t* parent) {
