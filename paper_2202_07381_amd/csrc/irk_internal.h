@@ -13,9 +13,12 @@
 
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cstdint>
+#include <exception>
 #include <string>
 #include <complex>
+#include <thread>
 #include <vector>
 
 namespace irk {
@@ -91,6 +94,53 @@ void build_topology(HostLevel& L, int dim, int64_t nv, int64_t nc, const double*
 void assemble_level(HostLevel& L, double nu, const std::vector<double>* wind_nodal,
                     bool with_mfa);
 void build_patches(HostLevel& L);
+
+// body(lo, hi) over contiguous ranges of [0, n) on up to 16 host threads, at least `grain`
+// items each; the ranges partition [0, n) in order.  An exception thrown by a range is
+// rethrown on the calling thread after every range has finished.
+template <typename F>
+void parallel_ranges(int64_t n, F&& body, int64_t grain = 4096) {
+  const int nt = (int)std::max<int64_t>(1, std::min<int64_t>({16, (int64_t)std::thread::hardware_concurrency(),
+                                                              n / grain}));
+  if (nt == 1) {
+    body((int64_t)0, n);
+    return;
+  }
+  std::vector<std::exception_ptr> err(nt);
+  std::vector<std::thread> pool;
+  for (int t = 0; t < nt; ++t)
+    pool.emplace_back([&body, &err, n, nt, t] {
+      try {
+        body(n * t / nt, n * (t + 1) / nt);
+      } catch (...) {
+        err[t] = std::current_exception();
+      }
+    });
+  for (auto& th : pool) th.join();
+  for (auto& e : err)
+    if (e) std::rethrow_exception(e);
+}
+// Cells grouped so that no two cells of a group share a vertex (greedy, in cell order).
+// Every row that a cell's element matrices touch belongs to one of its vertices or edges,
+// so the cells of one group scatter into disjoint rows and can be assembled concurrently.
+// Group g holds cells[gptr[g] .. gptr[g+1]), ascending.  A mesh needing more than 64
+// groups (more than 64 cells around some vertex) gets one group of every cell, which
+// callers then assemble on one thread.
+void vertex_disjoint_groups(const HostLevel& L, std::vector<int64_t>& gptr, std::vector<int64_t>& cells);
+// Scatter cell_body(c) over every cell, group by group (vertex_disjoint_groups).
+template <typename F>
+void for_cells_by_groups(const HostLevel& L, F&& cell_body) {
+  std::vector<int64_t> gptr, cells;
+  vertex_disjoint_groups(L, gptr, cells);
+  if (gptr.size() == 2 && L.nc > 1) {  // one group: cells may share vertices
+    for (int64_t c = 0; c < L.nc; ++c) cell_body(c);
+    return;
+  }
+  for (size_t g = 0; g + 1 < gptr.size(); ++g)
+    parallel_ranges(gptr[g + 1] - gptr[g], [&](int64_t i0, int64_t i1) {
+      for (int64_t i = i0; i < i1; ++i) cell_body(cells[gptr[g] + i]);
+    }, 256);
+}
 // Element data of the Navier--Stokes terms: per cell the barycentric gradients
 // ((dim+1) x dim) and the measure; int32 cell nodes and their free indices (-1 for
 // prescribed nodes); per free node the incidences cell * nloc + a (cell order) of its node.

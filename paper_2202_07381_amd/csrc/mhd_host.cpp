@@ -16,9 +16,7 @@
 #include <climits>
 #include <cmath>
 #include <cstdint>
-#include <exception>
 #include <stdexcept>
-#include <thread>
 #include <utility>
 
 #include "mhd_internal.h"
@@ -88,58 +86,6 @@ void cell_dofs(const MhdHost& H, int64_t c, CellDofs& d) {
     d.p[j] = H.off_p + v;
     d.g[j] = H.gidx[v] < 0 ? -1 : H.off_g + H.gidx[v];
   }
-}
-
-// body(lo, hi) over contiguous ranges of [0, n) on up to 16 host threads, at least `grain`
-// items each; the ranges partition [0, n) in order.  An exception thrown by a range is
-// rethrown on the calling thread after every range has finished.
-template <typename F>
-void parallel_ranges(int64_t n, F&& body, int64_t grain = 4096) {
-  const int nt = (int)std::max<int64_t>(1, std::min<int64_t>({16, (int64_t)std::thread::hardware_concurrency(),
-                                                              n / grain}));
-  if (nt == 1) {
-    body((int64_t)0, n);
-    return;
-  }
-  std::vector<std::exception_ptr> err(nt);
-  std::vector<std::thread> pool;
-  for (int t = 0; t < nt; ++t)
-    pool.emplace_back([&body, &err, n, nt, t] {
-      try {
-        body(n * t / nt, n * (t + 1) / nt);
-      } catch (...) {
-        err[t] = std::current_exception();
-      }
-    });
-  for (auto& th : pool) th.join();
-  for (auto& e : err)
-    if (e) std::rethrow_exception(e);
-}
-
-// Cells grouped so that no two cells of a group share a vertex (greedy, in cell order):
-// every row a cell's element matrix touches belongs to one of its vertices or edges, so
-// the cells of one group scatter into disjoint rows and can be assembled concurrently.
-// group g holds cells[gptr[g] .. gptr[g+1]), ascending.
-void vertex_disjoint_groups(const HostLevel& L, std::vector<int64_t>& gptr, std::vector<int64_t>& cells) {
-  std::vector<uint64_t> used(L.nv, 0);
-  std::vector<int8_t> colour(L.nc);
-  int ng = 0;
-  for (int64_t c = 0; c < L.nc; ++c) {
-    const int64_t* v = &L.cells[c * 3];
-    const uint64_t taken = used[v[0]] | used[v[1]] | used[v[2]];
-    if (taken == ~0ull) throw std::runtime_error("MHD assembly: more than 64 cells around a vertex");
-    int g = 0;
-    while (taken >> g & 1) ++g;
-    colour[c] = (int8_t)g;
-    ng = std::max(ng, g + 1);
-    for (int j = 0; j < 3; ++j) used[v[j]] |= 1ull << g;
-  }
-  gptr.assign(ng + 1, 0);
-  for (int64_t c = 0; c < L.nc; ++c) ++gptr[colour[c] + 1];
-  for (int g = 0; g < ng; ++g) gptr[g + 1] += gptr[g];
-  cells.resize(L.nc);
-  std::vector<int64_t> fill(gptr.begin(), gptr.end() - 1);
-  for (int64_t c = 0; c < L.nc; ++c) cells[fill[colour[c]]++] = c;
 }
 
 }  // namespace
@@ -338,12 +284,7 @@ void mhd_assemble(MhdHost& H, double Re, double Rem, const double* w, const doub
     }
   };
   // cells of one vertex-disjoint group write disjoint rows
-  std::vector<int64_t> gptr, gcells;
-  vertex_disjoint_groups(L, gptr, gcells);
-  for (size_t g = 0; g + 1 < gptr.size(); ++g)
-    parallel_ranges(gptr[g + 1] - gptr[g], [&](int64_t i0, int64_t i1) {
-      for (int64_t i = i0; i < i1; ++i) cell_terms(gcells[gptr[g] + i]);
-    });
+  for_cells_by_groups(L, cell_terms);
 }
 
 void mhd_patches(MhdHost& H) {

@@ -15,6 +15,7 @@
 #include <cmath>
 #include <cstring>
 #include <map>
+#include <mutex>
 #include <numeric>
 #include <stdexcept>
 #include <thread>
@@ -350,26 +351,28 @@ void assemble_level(HostLevel& L, double nu, const std::vector<double>* wind, bo
   // patterns from node -> cell adjacency
   std::vector<std::vector<int32_t>> srows(L.nfree), brows(L.nfree), mrows;
   if (with_mfa) mrows.resize(L.nfree);
-  for (int64_t i = 0; i < L.nfree; ++i) {
-    const int64_t n = L.node_of_free[i];
-    for (int32_t p = L.node_cell_ptr[n]; p < L.node_cell_ptr[n + 1]; ++p) {
-      const int64_t c = L.node_cell[p];
-      for (int a = 0; a < nl; ++a) {
-        int64_t m = L.cell_nodes[c * nl + a];
-        if (L.free_of_node[m] >= 0) srows[i].push_back(L.free_of_node[m]);
-        if (with_mfa) mrows[i].push_back((int32_t)m);
+  parallel_ranges(L.nfree, [&](int64_t i0, int64_t i1) {  // rows independent
+    for (int64_t i = i0; i < i1; ++i) {
+      const int64_t n = L.node_of_free[i];
+      for (int32_t p = L.node_cell_ptr[n]; p < L.node_cell_ptr[n + 1]; ++p) {
+        const int64_t c = L.node_cell[p];
+        for (int a = 0; a < nl; ++a) {
+          int64_t m = L.cell_nodes[c * nl + a];
+          if (L.free_of_node[m] >= 0) srows[i].push_back(L.free_of_node[m]);
+          if (with_mfa) mrows[i].push_back((int32_t)m);
+        }
+        for (int q = 0; q < nb; ++q) brows[i].push_back((int32_t)L.cells[c * nb + q]);
       }
-      for (int q = 0; q < nb; ++q) brows[i].push_back((int32_t)L.cells[c * nb + q]);
+      for (auto* v : {&srows[i], &brows[i]}) {
+        std::sort(v->begin(), v->end());
+        v->erase(std::unique(v->begin(), v->end()), v->end());
+      }
+      if (with_mfa) {
+        std::sort(mrows[i].begin(), mrows[i].end());
+        mrows[i].erase(std::unique(mrows[i].begin(), mrows[i].end()), mrows[i].end());
+      }
     }
-    for (auto* v : {&srows[i], &brows[i]}) {
-      std::sort(v->begin(), v->end());
-      v->erase(std::unique(v->begin(), v->end()), v->end());
-    }
-    if (with_mfa) {
-      std::sort(mrows[i].begin(), mrows[i].end());
-      mrows[i].erase(std::unique(mrows[i].begin(), mrows[i].end()), mrows[i].end());
-    }
-  }
+  });
   csr_from_rows(srows, L.s_ptr, L.s_col);
   csr_from_rows(brows, L.b_ptr, L.b_col);
   const size_t snnz = L.s_col.size();
@@ -390,9 +393,13 @@ void assemble_level(HostLevel& L, double nu, const std::vector<double>* wind, bo
     L.fb_m.assign(L.fb_col.size(), 0.0);
     L.fb_l.assign(L.fb_col.size(), 0.0);
   }
-  double glam[12], vol;
-  double G[4][4], Me[10][10], Ke[10][10], Ce[10][10], Be[10][4][3];
-  for (int64_t c = 0; c < L.nc; ++c) {
+  // element matrices scattered by vertex-disjoint groups of cells (disjoint rows); the
+  // boundary triples of each range are appended under a lock and sorted on every field
+  // below, so their order does not depend on the threads
+  std::mutex trip_lock;
+  auto cell_body = [&](int64_t c, std::vector<std::array<double, 5>>& trips) {
+    double glam[12], vol;
+    double G[4][4], Me[10][10], Ke[10][10], Ce[10][10], Be[10][4][3];
     cell_geometry(L, c, glam, &vol);
     for (int k = 0; k < nb; ++k)
       for (int l = 0; l < nb; ++l) {
@@ -443,7 +450,7 @@ void assemble_level(HostLevel& L, double nu, const std::vector<double>* wind, bo
           for (int q = 0; q < nb; ++q) {
             std::array<double, 5> t{(double)L.cells[c * nb + q], (double)na, 0, 0, 0};
             for (int i = 0; i < d; ++i) t[2 + i] = Be[a][q][i];
-            bnd_trip.push_back(t);
+            trips.push_back(t);
           }
         continue;
       }
@@ -470,21 +477,34 @@ void assemble_level(HostLevel& L, double nu, const std::vector<double>* wind, bo
         for (int i = 0; i < d; ++i) L.b_val[(size_t)p * d + i] += Be[a][q][i];
       }
     }
+  };
+  std::vector<int64_t> gptr, gcells;
+  vertex_disjoint_groups(L, gptr, gcells);
+  const bool one_group = gptr.size() == 2 && L.nc > 1;  // cells may share vertices
+  for (size_t g = 0; g + 1 < gptr.size(); ++g) {
+    auto range = [&](int64_t i0, int64_t i1) {
+      std::vector<std::array<double, 5>> trips;
+      for (int64_t i = i0; i < i1; ++i) cell_body(gcells[gptr[g] + i], trips);
+      std::lock_guard<std::mutex> lk(trip_lock);
+      bnd_trip.insert(bnd_trip.end(), trips.begin(), trips.end());
+    };
+    if (one_group) range(0, L.nc);
+    else parallel_ranges(gptr[g + 1] - gptr[g], range, 256);
   }
   for (size_t p = 0; p < snnz; ++p) L.s_L[p] = nu * L.s_K1[p] + conv[p];
   // L^T on the same symmetric pattern
   L.s_Lt.assign(snnz, 0.0);
-  for (int64_t i = 0; i < L.nfree; ++i)
-    for (int32_t p = L.s_ptr[i]; p < L.s_ptr[i + 1]; ++p) {
-      int32_t q = find_in_row(L.s_ptr, L.s_col, L.s_col[p], i);
-      L.s_Lt[p] = L.s_L[q];
-    }
+  parallel_ranges(L.nfree, [&](int64_t i0, int64_t i1) {
+    for (int64_t i = i0; i < i1; ++i)
+      for (int32_t p = L.s_ptr[i]; p < L.s_ptr[i + 1]; ++p) {
+        int32_t q = find_in_row(L.s_ptr, L.s_col, L.s_col[p], i);
+        L.s_Lt[p] = L.s_L[q];
+      }
+  });
   transpose_csr(L.nfree, L.nv, L.b_ptr, L.b_col, L.b_val, d, L.bt_ptr, L.bt_col, L.bt_val);
   if (with_mfa) {
     // vertex rows x boundary nodes of B^T (the divergence of prescribed velocities)
-    std::sort(bnd_trip.begin(), bnd_trip.end(), [](const std::array<double, 5>& x, const std::array<double, 5>& y) {
-      return x[0] < y[0] || (x[0] == y[0] && x[1] < y[1]);
-    });
+    std::sort(bnd_trip.begin(), bnd_trip.end());  // by (vertex, node), then the values
     L.vb_ptr.assign(L.nv + 1, 0);
     L.vb_col.clear();
     L.vb_val.clear();
@@ -503,42 +523,107 @@ void assemble_level(HostLevel& L, double nu, const std::vector<double>* wind, bo
   }
 }
 
+void vertex_disjoint_groups(const HostLevel& L, std::vector<int64_t>& gptr, std::vector<int64_t>& cells) {
+  const int nb = L.dim + 1;
+  std::vector<uint64_t> used(L.nv, 0);
+  std::vector<int8_t> colour(L.nc);
+  int ng = 0;
+  for (int64_t c = 0; c < L.nc; ++c) {
+    const int64_t* v = &L.cells[c * nb];
+    uint64_t taken = 0;
+    for (int j = 0; j < nb; ++j) taken |= used[v[j]];
+    if (taken == ~0ull) {  // more than 64 groups: one group, assembled on one thread
+      gptr = {0, L.nc};
+      cells.resize(L.nc);
+      std::iota(cells.begin(), cells.end(), (int64_t)0);
+      return;
+    }
+    int g = 0;
+    while (taken >> g & 1) ++g;
+    colour[c] = (int8_t)g;
+    ng = std::max(ng, g + 1);
+    for (int j = 0; j < nb; ++j) used[v[j]] |= 1ull << g;
+  }
+  gptr.assign(ng + 1, 0);
+  for (int64_t c = 0; c < L.nc; ++c) ++gptr[colour[c] + 1];
+  for (int g = 0; g < ng; ++g) gptr[g + 1] += gptr[g];
+  cells.resize(L.nc);
+  std::vector<int64_t> fill(gptr.begin(), gptr.end() - 1);
+  for (int64_t c = 0; c < L.nc; ++c) cells[fill[colour[c]]++] = c;
+}
+
 // --------------------------------------------------------------------------- patches
 void build_patches(HostLevel& L) {
   const int nl = nloc_of(L.dim);
+  // Vertices are independent: ranges of them are handled concurrently in two passes, the
+  // first listing each patch's free nodes and counting its coupling entries, the second
+  // writing the triples and B positions straight to their final place.
+  const int64_t nchunks = std::max<int64_t>(1, std::min<int64_t>(256, L.nv / 1024));
+  std::vector<std::vector<int32_t>> cnode(nchunks);
   L.pn_ptr.assign(L.nv + 1, 0);
-  L.pn_node.clear();
   L.pvv_ptr.assign(L.nv + 1, 0);
-  L.pvv.clear();
-  L.pvp.clear();
-  std::vector<int32_t> nodes;
-  for (int64_t v = 0; v < L.nv; ++v) {
-    nodes.clear();
-    for (int32_t p = L.node_cell_ptr[v]; p < L.node_cell_ptr[v + 1]; ++p) {
-      const int64_t c = L.node_cell[p];
-      for (int a = 0; a < nl; ++a) {
-        int32_t f = L.free_of_node[L.cell_nodes[c * nl + a]];
-        if (f >= 0) nodes.push_back(f);
-      }
-    }
-    std::sort(nodes.begin(), nodes.end());
-    nodes.erase(std::unique(nodes.begin(), nodes.end()), nodes.end());
-    for (size_t la = 0; la < nodes.size(); ++la) {
-      const int32_t i = nodes[la];
-      for (int32_t p = L.s_ptr[i]; p < L.s_ptr[i + 1]; ++p) {
-        auto it = std::lower_bound(nodes.begin(), nodes.end(), L.s_col[p]);
-        if (it != nodes.end() && *it == L.s_col[p]) {
-          L.pvv.push_back((int32_t)la);
-          L.pvv.push_back((int32_t)(it - nodes.begin()));
-          L.pvv.push_back(p);
+  // the triples (a, b, CSR position) coupling the sorted free nodes of one patch, rows of
+  // the list in order and, within a row, its columns in order (one merge of two sorted lists)
+  auto couplings = [&](const int32_t* nodes, int32_t n, int32_t* out) {
+    int32_t cnt = 0;
+    for (int32_t la = 0; la < n; ++la) {
+      int32_t p = L.s_ptr[nodes[la]];
+      const int32_t pe = L.s_ptr[nodes[la] + 1];
+      int32_t lb = 0;
+      while (p < pe && lb < n) {
+        const int32_t c = L.s_col[p];
+        if (c < nodes[lb]) ++p;
+        else if (c > nodes[lb]) ++lb;
+        else {
+          if (out) {
+            out[cnt * 3] = la;
+            out[cnt * 3 + 1] = lb;
+            out[cnt * 3 + 2] = p;
+          }
+          ++cnt, ++p, ++lb;
         }
       }
-      L.pvp.push_back(find_in_row(L.b_ptr, L.b_col, i, v));
     }
-    L.pn_node.insert(L.pn_node.end(), nodes.begin(), nodes.end());
-    L.pn_ptr[v + 1] = (int32_t)L.pn_node.size();
-    L.pvv_ptr[v + 1] = (int32_t)(L.pvv.size() / 3);
+    return cnt;
+  };
+  auto chunk_lo = [&](int64_t k) { return L.nv * k / nchunks; };
+  parallel_ranges(nchunks, [&](int64_t k0, int64_t k1) {
+    std::vector<int32_t> nodes;
+    for (int64_t k = k0; k < k1; ++k)
+      for (int64_t v = chunk_lo(k); v < chunk_lo(k + 1); ++v) {
+        nodes.clear();
+        for (int32_t p = L.node_cell_ptr[v]; p < L.node_cell_ptr[v + 1]; ++p) {
+          const int64_t c = L.node_cell[p];
+          for (int a = 0; a < nl; ++a) {
+            int32_t f = L.free_of_node[L.cell_nodes[c * nl + a]];
+            if (f >= 0) nodes.push_back(f);
+          }
+        }
+        std::sort(nodes.begin(), nodes.end());
+        nodes.erase(std::unique(nodes.begin(), nodes.end()), nodes.end());
+        cnode[k].insert(cnode[k].end(), nodes.begin(), nodes.end());
+        L.pn_ptr[v + 1] = (int32_t)nodes.size();
+        L.pvv_ptr[v + 1] = couplings(nodes.data(), (int32_t)nodes.size(), nullptr);
+      }
+  }, 1);
+  for (int64_t v = 0; v < L.nv; ++v) {
+    L.pn_ptr[v + 1] += L.pn_ptr[v];
+    if ((int64_t)L.pvv_ptr[v] + L.pvv_ptr[v + 1] > INT32_MAX)
+      throw std::runtime_error("patches: more than 2^31 coupling entries on one level");
+    L.pvv_ptr[v + 1] += L.pvv_ptr[v];
   }
+  L.pn_node.clear();
+  L.pn_node.reserve(L.pn_ptr[L.nv]);
+  for (const auto& c : cnode) L.pn_node.insert(L.pn_node.end(), c.begin(), c.end());
+  L.pvv.assign((size_t)L.pvv_ptr[L.nv] * 3, 0);
+  L.pvp.assign(L.pn_node.size(), 0);
+  parallel_ranges(L.nv, [&](int64_t v0, int64_t v1) {
+    for (int64_t v = v0; v < v1; ++v) {
+      const int32_t q0 = L.pn_ptr[v], n = L.pn_ptr[v + 1] - q0;
+      couplings(&L.pn_node[q0], n, &L.pvv[(size_t)L.pvv_ptr[v] * 3]);
+      for (int32_t la = 0; la < n; ++la) L.pvp[q0 + la] = find_in_row(L.b_ptr, L.b_col, L.pn_node[q0 + la], v);
+    }
+  }, 1024);
 }
 
 // ------------------------------------------------------------------------- transfers
