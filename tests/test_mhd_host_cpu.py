@@ -68,3 +68,37 @@ def test_host_operators_reject_invalid_meshes():
     if cube is not None:
         with pytest.raises(irkmg.IrkError):
             irkmg.irk_mhd_host_operators(cube, 0, 1.0, 1.0, w0, b0)
+
+
+def test_host_operators_threaded_assembly():
+    """On a 64 x 64 level the host assembly runs on threads (pattern rows, vertex-disjoint
+    cell groups, patch lists): the result matches the oracle to rounding and is bitwise
+    the same on a second call."""
+    lv = wl.square_hierarchy(4, 5)
+    w0, b0 = _state(lv, 5)
+    M, S, P = irkmg.irk_mhd_host_operators(lv, 4, 300.0, 200.0, w0, b0)
+    Mo, So = MHDSpace(TaylorHood(lv[-1].xyz, lv[-1].cells)).operators(300.0, 200.0, w0, b0)
+    assert abs(M - Mo).max() <= 1e-13 * abs(Mo).max()
+    assert abs(S - So).max() <= 1e-13 * abs(So).max()
+    M2, S2, P2 = irkmg.irk_mhd_host_operators(lv, 4, 300.0, 200.0, w0, b0)
+    for x, y in ((M, M2), (S, S2), (P, P2)):
+        assert (x.indptr == y.indptr).all() and (x.indices == y.indices).all() and (x.data == y.data).all()
+
+
+def test_host_operators_vertex_of_high_valence():
+    """A fan of 70 triangles around one vertex (more cells around a vertex than the
+    assembly's 64 cell groups can separate): the cells are assembled in order on one
+    thread and the operators still match the oracle."""
+    m = 70
+    t = 2 * np.pi * np.arange(m) / m
+    xyz = np.concatenate([[[0.0, 0.0]], np.stack([np.cos(t), np.sin(t)], 1)])
+    cells = np.array([[0, 1 + i, 1 + (i + 1) % m] for i in range(m)], dtype=np.int64)
+    lv = [wl.MeshLevel(2, xyz, cells, None)]
+    th = TaylorHood(xyz, cells)
+    rng = np.random.default_rng(8)
+    w0 = 0.2 * rng.standard_normal((xyz.shape[0] + th.nedges, 2))
+    b0 = rng.standard_normal(th.nedges)
+    M, S, _ = irkmg.irk_mhd_host_operators(lv, 0, 40.0, 30.0, w0, b0)
+    Mo, So = MHDSpace(th).operators(40.0, 30.0, w0, b0)
+    assert abs(M - Mo).max() <= 1e-13 * abs(Mo).max()
+    assert abs(S - So).max() <= 1e-13 * abs(So).max()
